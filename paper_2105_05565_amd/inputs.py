@@ -1,0 +1,115 @@
+"""Seeded synthetic ridge problems shaped like the paper's workloads.
+
+This module only generates inputs (X, y, lambda); it contains none of the
+solver's arithmetic. Both the HIP library's callers and the CPU oracle's
+tests consume what it returns.
+
+Recipes (numpy PCG64, ``data_seed`` fixed per workload):
+
+* dense:   X_ij ~ N(0, 1), optionally times a per-column scale exp(s * xi_j)
+           with xi_j ~ N(0, 1) (log-normal column norms), optionally with a
+           fraction of columns replaced by 0.9 * (a random partner column)
+           + sqrt(1 - 0.81) * fresh noise (correlated pairs);
+* csr:     exactly ``nnz`` distinct positions drawn uniformly over the n x d
+           grid (row and column counts then follow Poisson-like laws),
+           values N(0, 1);
+* targets: y = X w* + noise_scale * N(0, 1) with w* ~ N(0, 1).
+
+The paper's own datasets (Boston, California Housing, RCV1, YearPredictionMSD)
+are not used; these synthetic matrices stand in for them.
+"""
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.sparse as sp
+
+DATA_SEED_BASE = 2105055650
+
+
+@dataclass
+class Problem:
+    name: str
+    X: object            # numpy array (n x d) or scipy.sparse.csr_matrix
+    y: np.ndarray        # FP64 [n]
+    lam: float
+    w_star: np.ndarray   # the generating weights (not the ridge solution)
+
+
+def dense_matrix(n, d, rng, dtype=np.float64, col_log_sigma=0.0, corr_frac=0.0, corr_rho=0.9):
+    X = rng.standard_normal((n, d), dtype=np.float64 if dtype == np.float64 else np.float32)
+    if corr_frac > 0.0:
+        ncorr = int(round(corr_frac * d))
+        cols = rng.choice(d, size=ncorr, replace=False)
+        for j in cols:
+            p = int(rng.integers(0, d - 1))
+            p = p + 1 if p >= j else p
+            g = rng.standard_normal(n).astype(X.dtype)
+            X[:, j] = corr_rho * X[:, p] + np.sqrt(1.0 - corr_rho ** 2) * g
+    if col_log_sigma > 0.0:
+        scale = np.exp(col_log_sigma * rng.standard_normal(d))
+        X *= scale.astype(X.dtype)[None, :]
+    return np.ascontiguousarray(X.astype(dtype, copy=False))
+
+
+def csr_matrix(n, d, nnz, rng, dtype=np.float32):
+    lin = rng.choice(n * d, size=nnz, replace=False)
+    lin.sort()
+    rows = lin // d
+    cols = (lin % d).astype(np.int32)
+    vals = rng.standard_normal(nnz).astype(dtype)
+    indptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(indptr, rows + 1, 1)
+    indptr = np.cumsum(indptr)
+    X = sp.csr_matrix((vals, cols, indptr), shape=(n, d))
+    X.has_sorted_indices = True
+    return X
+
+
+def targets(X, rng, noise=0.01):
+    d = X.shape[1]
+    w_star = rng.standard_normal(d)
+    Xw = np.asarray(X @ w_star.astype(np.float64) if sp.issparse(X)
+                    else X.astype(np.float64, copy=False) @ w_star).ravel()
+    y = Xw + noise * rng.standard_normal(X.shape[0])
+    return y, w_star
+
+
+def make_dense(n, d, lam, seed, dtype=np.float64, col_log_sigma=0.0, corr_frac=0.0, name=None):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    X = dense_matrix(n, d, rng, dtype, col_log_sigma, corr_frac)
+    y, w_star = targets(X, rng)
+    return Problem(name or f"dense_{n}x{d}", X, y, lam, w_star)
+
+
+def make_csr(n, d, density, lam, seed, dtype=np.float32, name=None):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nnz = int(round(density * n * d))
+    X = csr_matrix(n, d, nnz, rng, dtype)
+    y, w_star = targets(X, rng)
+    return Problem(name or f"csr_{n}x{d}", X, y, lam, w_star)
+
+
+# The five workloads, with reduced shape-alike variants for fast tests.
+def dense_primal(scale=1.0, seed=DATA_SEED_BASE + 0):
+    """X 2000 x 500 FP64 N(0,1), lambda = 1e-2 (subsample sketch, tau = 50)."""
+    n, d = int(2000 * scale), int(500 * scale)
+    return make_dense(n, d, 1e-2, seed, np.float64, name=f"dense_primal_{n}x{d}")
+
+
+def sparse_csr(scale=1.0, seed=DATA_SEED_BASE + 1):
+    """CSR X 100000 x 20000 FP32, density 0.1%, lambda = 1e-3 (count / SubCount, tau = 500)."""
+    n, d = int(100000 * scale), int(20000 * scale)
+    return make_csr(n, d, 1e-3, 1e-3, seed, np.float32, name=f"csr_{n}x{d}")
+
+
+def dense_mixed(scale=1.0, seed=DATA_SEED_BASE + 2):
+    """X 50000 x 8192 FP32, N(0,1) times log-normal(0,1) column scales, lambda = 1e-1."""
+    n, d = int(50000 * scale), int(8192 * scale)
+    return make_dense(n, d, 1e-1, seed, np.float32, col_log_sigma=1.0, name=f"dense_mixed_{n}x{d}")
+
+
+def dense_learned(scale=1.0, seed=DATA_SEED_BASE + 4):
+    """X 200000 x 4096 FP32, log-normal(0,2) column norms, 5% correlated columns, lambda = 1e-2."""
+    n, d = int(200000 * scale), int(4096 * scale)
+    return make_dense(n, d, 1e-2, seed, np.float32, col_log_sigma=2.0, corr_frac=0.05,
+                      name=f"dense_learned_{n}x{d}")
