@@ -1,0 +1,164 @@
+/*
+ * rs.h -- C ABI of the MI355X sketch-and-project ridge solver (librs.so).
+ *
+ * Method: sketch-and-project with momentum for ridge regression
+ * (RidgeSketch, arXiv 2105.05565, Alg. 2). The library solves
+ *
+ *     A x = b,  A = Z Z^T + lambda I                              (eq:Axb)
+ *
+ * in the primal form (Z = X^T, b = X^T y, x = w; eq:linear) or the dual form
+ * (Z = X, b = y, x = alpha, w = X^T alpha; eq:duallinear). Each iteration k
+ * draws a sketch S_k (subsample, Def. 4.2; count, Sec. 4.2; SubCount,
+ * Def. 4.3), forms AS_k = Z (Z^T S_k) + lambda S_k, solves the tau x tau
+ * system (S_k^T A S_k) delta = S_k^T r^k (eq:sketched_system) and applies
+ *
+ *     x^{k+1} = (1 + beta_k) x^k - beta_k x^{k-1} - gamma_k S_k delta
+ *     r^{k+1} = (1 + beta_k) r^k - beta_k r^{k-1} - gamma_k AS_k delta
+ *
+ * (eq:res_update_mom), with residual r = A x - b (Sec. 3) and
+ * x^{-1} = x^0 = 0. All device work runs on the stream the caller passes.
+ *
+ * Conventions for every entry point:
+ *  - Return value: RS_OK (0) on success, a negative rs_status on error, or
+ *    the positive warning RS_NOT_CONVERGED. No exception crosses the ABI.
+ *    After an error, rs_last_error(handle) describes it (thread-local text
+ *    for rs_create failures, readable through rs_last_error(NULL)).
+ *  - Pointers marked "host" are CPU memory, "device" are HIP device memory
+ *    of the current device; rs_matrix.mem says which one X and y are.
+ *  - The library copies X and y at rs_create; the caller keeps ownership of
+ *    every buffer it passes and may free them once the call returns.
+ *  - Handles are not thread-safe: one thread at a time per handle.
+ */
+#ifndef RS_H
+#define RS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rs_status;
+
+enum {
+  RS_OK = 0,
+  RS_NOT_CONVERGED = 1,   /* warning: max_iter reached before tol */
+  RS_EINVAL = -1,         /* bad argument: shape, tau > m, lambda <= 0, NaN, ... */
+  RS_ENOMEM = -2,         /* device allocation failed */
+  RS_EDEVICE = -3,        /* a HIP call failed */
+  RS_ESINGULAR = -4,      /* non-positive Cholesky pivot on a nonzero sketch column */
+  RS_EUNSUPPORTED = -5    /* option combination not built */
+};
+
+/* Matrix X (n x d). Dense layouts are row-major (ld = d) or column-major
+ * (ld = n); CSR uses row_ptr[n + 1] (int64) and col_idx[nnz] (int32, sorted
+ * within each row, no duplicates). */
+enum { RS_DENSE_ROWMAJOR = 0, RS_DENSE_COLMAJOR = 1, RS_CSR = 2 };
+enum { RS_F64 = 0, RS_F32 = 1 };
+enum { RS_HOST = 0, RS_DEVICE = 1 };
+
+typedef struct rs_matrix {
+  int64_t n, d;
+  int32_t layout;           /* RS_DENSE_ROWMAJOR | RS_DENSE_COLMAJOR | RS_CSR */
+  int32_t dtype;            /* RS_F64 | RS_F32 (values of X) */
+  const void* vals;         /* n*d values (dense) or nnz values (CSR) */
+  const int64_t* row_ptr;   /* CSR only */
+  const int32_t* col_idx;   /* CSR only */
+  int64_t nnz;              /* CSR only */
+  int32_t mem;              /* RS_HOST | RS_DEVICE: where vals/row_ptr/col_idx/y live */
+} rs_matrix;
+
+/* Form of the linear system (Sec. 2.1): AUTO picks primal when d <= n. */
+enum { RS_FORM_AUTO = 0, RS_FORM_PRIMAL = 1, RS_FORM_DUAL = 2 };
+/* Sketch distribution D (Sec. 4). */
+enum { RS_SKETCH_SUBSAMPLE = 0, RS_SKETCH_COUNT = 1, RS_SKETCH_SUBCOUNT = 2 };
+/* Momentum schedule (Sec. 6, Sec. 9.1):
+ *  NONE      gamma = 1, beta = 0 (Alg. 1)
+ *  CONSTANT  gamma = opts.gamma, beta = opts.beta (0.5 in the paper's comparison)
+ *  HEURISTIC gamma = 1, beta_k = min(beta_max, 1 - (2 - eta) / ((k+1)(1 - eta) + 1))
+ *            (eq:parametersheurististic) */
+enum { RS_MOMENTUM_NONE = 0, RS_MOMENTUM_CONSTANT = 1, RS_MOMENTUM_HEURISTIC = 2 };
+/* Arithmetic of the AS products: FP64 throughout, or BF16 products with FP32
+ * accumulation and an FP64 Cholesky plus a periodic FP64 residual refresh. */
+enum { RS_PREC_FP64 = 0, RS_PREC_MIXED_BF16 = 1 };
+
+typedef struct rs_options {
+  int32_t form;             /* RS_FORM_* */
+  int32_t sketch;           /* RS_SKETCH_* */
+  int32_t tau;              /* sketch size, 1 <= tau <= m */
+  int32_t subcount_k;       /* SubCount sum size k; 0 = the paper's rule (k = 10 if 10 tau <= m,
+                               else floor(m / tau)); s = k tau must be <= m */
+  int32_t momentum;         /* RS_MOMENTUM_* */
+  int32_t precision;        /* RS_PREC_* */
+  double gamma, beta;       /* CONSTANT schedule */
+  double eta, beta_max;     /* HEURISTIC schedule (defaults 0.995, 0.5) */
+  double tol;               /* stop when ||r^k|| / ||r^0|| <= tol (default 1e-6) */
+  int64_t max_iter;         /* iteration cap (default 100000) */
+  uint64_t seed;            /* Philox key word 0 */
+  uint64_t problem_id;      /* Philox key word 1 */
+  int32_t refresh_every;    /* mixed precision: FP64 recomputation of r every R iterations (default 20) */
+  int32_t lookahead;        /* sketches drawn and factorised ahead per batch; 0 = library choice */
+  void* stream;             /* hipStream_t for all work; NULL = the default stream */
+} rs_options;
+
+typedef struct rs_report {
+  int64_t iters;            /* iterations performed */
+  double rel_res;           /* ||r^iters|| / ||r^0|| of the tracked residual */
+  double seconds;           /* wall time of the solve on the stream */
+} rs_report;
+
+typedef struct rs_handle rs_handle;
+
+/* Fill *o with defaults: AUTO form, subsample, tau = 0 (must be set), heuristic
+ * momentum, eta 0.995, beta_max 0.5, tol 1e-6, max_iter 100000, seed 1. */
+rs_status rs_options_default(rs_options* o);
+
+/* Build a solver for X, y (y: n values, FP64, in the memory X.mem names) and
+ * lambda > 0. Uploads X into library-owned device layouts, forms b, sets
+ * x^0 = x^{-1} = 0, r^0 = r^{-1} = -b. Errors: RS_EINVAL (shapes, tau, lambda,
+ * non-finite y), RS_ENOMEM, RS_EDEVICE, RS_EUNSUPPORTED. */
+rs_status rs_create(const rs_matrix* X, const double* y, double lambda,
+                    const rs_options* o, rs_handle** out);
+
+/* Advance up to `iters` iterations (fewer if ||r^k|| / ||r^0|| <= tol is met
+ * first), then synchronise the stream. *rel_res_out (host, may be NULL)
+ * receives ||r^k|| / ||r^0|| at the final k. */
+rs_status rs_step(rs_handle* h, int64_t iters, double* rel_res_out);
+
+/* Iterate until tol or max_iter. x_out (host, may be NULL) receives the
+ * ridge weights w (d values; dual form maps alpha through X^T). rep (host,
+ * may be NULL) gets the report. Returns RS_NOT_CONVERGED if max_iter hit. */
+rs_status rs_solve(rs_handle* h, double* w_out, rs_report* rep);
+
+/* Current iteration count k. */
+int64_t rs_iteration(const rs_handle* h);
+/* m, the size of the system (d in primal form, n in dual form). */
+int64_t rs_system_size(const rs_handle* h);
+
+/* Copy the state to host buffers of m doubles each (any may be NULL):
+ * x^k, x^{k-1}, r^k = A x^k - b (tracked), r^{k-1}. */
+rs_status rs_get_state(const rs_handle* h, double* x, double* x_prev, double* r, double* r_prev);
+
+/* Ridge weights from the current iterate (host, d doubles). */
+rs_status rs_get_weights(rs_handle* h, double* w_out);
+
+/* The sketch S_{k-1} used by the last iteration, as (rows, cols, signs)
+ * triplets of its nonzeros (host buffers of capacity m). *nnz_out receives
+ * the count. Bucket-major order: all nonzeros of column 0 first. */
+rs_status rs_get_last_sketch(const rs_handle* h, int32_t* rows, int32_t* cols, int8_t* signs,
+                             int64_t* nnz_out);
+
+/* Relative residual history ||r^k|| / ||r^0||, k = 0..count-1 (host). */
+rs_status rs_get_history(const rs_handle* h, double* out, int64_t count);
+
+rs_status rs_destroy(rs_handle* h);
+
+const char* rs_status_string(rs_status s);
+/* Text of the last error on this handle (or of the last failed rs_create on
+ * this thread when h is NULL). Valid until the next call on the handle. */
+const char* rs_last_error(const rs_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RS_H */

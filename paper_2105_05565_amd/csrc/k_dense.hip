@@ -1,0 +1,201 @@
+// Dense products for the subsample sketch and setup helpers (CDNA4, wave64).
+//
+// For S = I_C, A S = Z (Z^T I_C) + lambda I_C = Z Z[C,:]^T + lambda I_C: an m x tau
+// contraction over K whose second operand is the gathered rows C of Z. Several
+// lookahead sketches share the first operand, so one launch contracts Z against
+// [Z[C_0,:]; Z[C_1,:]; ...] (N = slots * tau columns) on FP64 MFMA (16x16x4).
+#include "dev_common.h"
+#include "rs_internal.h"
+
+namespace rs {
+namespace {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+constexpr int kTM = 64, kTN = 64, kTK = 16;
+
+__global__ __launch_bounds__(256) void k_as_dense_f64(const double* __restrict__ Z, int64_t ldz,
+                                                      int64_t m, int64_t K,
+                                                      const int32_t* __restrict__ members,
+                                                      int32_t tau, int32_t nslots, double lam,
+                                                      double* __restrict__ AS,
+                                                      const int32_t* __restrict__ done) {
+  __shared__ double As[kTM][kTK + 1];
+  __shared__ double Bs[kTN][kTK + 1];
+  __shared__ int64_t brow[kTN];
+  if (*done) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * kTM;
+  const int64_t n0 = (int64_t)blockIdx.y * kTN;
+  const int64_t ntot = (int64_t)nslots * tau;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  if (tid < kTN) {
+    const int64_t n = n0 + tid;
+    brow[tid] = n < ntot ? (int64_t)members[n] : -1;  // members is [slot][tau]
+  }
+  __syncthreads();
+
+  d4v acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
+
+  const int lr = tid >> 2, lk = (tid & 3) * 4;
+  const int64_t arow = row0 + lr;
+  const int64_t brw = brow[lr];
+  for (int64_t kk = 0; kk < K; kk += kTK) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t kidx = kk + lk + q;
+      As[lr][lk + q] = (arow < m && kidx < K) ? Z[arow * ldz + kidx] : 0.0;
+      Bs[lr][lk + q] = (brw >= 0 && kidx < K) ? Z[brw * ldz + kidx] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < kTK; k4 += 4) {
+      double a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = As[wr + i * 16 + (lane & 15)][k4 + (lane >> 4)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Bs[wc + j * 16 + (lane & 15)][k4 + (lane >> 4)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  // D layout of the 16x16x4 FP64 MFMA: lane l, element v -> row 4 v + l / 16, column l % 16.
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = row0 + wr + i * 16 + v * 4 + (lane >> 4);
+        const int col = wc + j * 16 + (lane & 15);
+        const int64_t n = n0 + col;
+        if (row < m && n < ntot) {
+          const int64_t slot = n / tau, c = n % tau;
+          double val = acc[i][j][v];
+          if (row == brow[col]) val += lam;
+          AS[(slot * m + row) * tau + c] = val;
+        }
+      }
+}
+
+__global__ void k_transpose_to_f64(const void* __restrict__ src, int32_t is_f32, int64_t rows,
+                                   int64_t cols, int64_t lds, double* __restrict__ dst, int64_t ldd) {
+  __shared__ double tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 32 x 8
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int64_t r = r0 + yy, c = c0 + tx;
+    double v = 0.0;
+    if (r < rows && c < cols)
+      v = is_f32 ? (double)((const float*)src)[r * lds + c] : ((const double*)src)[r * lds + c];
+    tile[yy][tx] = v;
+  }
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int64_t c = c0 + yy, r = r0 + tx;  // dst[c][r] = src[r][c]
+    if (c < cols && r < rows) dst[c * ldd + r] = tile[tx][yy];
+  }
+}
+
+__global__ void k_copy_to_f64(const void* __restrict__ src, int32_t is_f32, int64_t rows,
+                              int64_t cols, int64_t lds, double* __restrict__ dst, int64_t ldd) {
+  const int64_t r = blockIdx.y;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cols;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    dst[r * ldd + c] =
+        is_f32 ? (double)((const float*)src)[r * lds + c] : ((const double*)src)[r * lds + c];
+  }
+  (void)rows;
+}
+
+// out[j] = sum_k Z[j][k] v[k]: one wave per row, fixed-order reduction.
+__global__ void k_gemv_rows(const double* __restrict__ Z, int64_t ldz, int64_t m, int64_t K,
+                            const double* __restrict__ v, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= m) return;
+  double s = 0.0;
+  for (int64_t k = lane; k < K; k += 64) s += Z[row * ldz + k] * v[k];
+  s = wave_sum(s);
+  if (lane == 0) out[row] = s;
+}
+
+// out[k] = sum_j Z[j][k] v[j]: one thread per column k, rows in order.
+__global__ void k_gemv_cols(const double* __restrict__ Z, int64_t ldz, int64_t m, int64_t K,
+                            const double* __restrict__ v, double* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  double s = 0.0;
+  for (int64_t j = 0; j < m; ++j) s += Z[j * ldz + k] * v[j];
+  out[k] = s;
+}
+
+__global__ void k_vec_to_f64(const void* __restrict__ src, int32_t is_f32, int64_t n,
+                             double* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = is_f32 ? (double)((const float*)src)[i] : ((const double*)src)[i];
+}
+
+}  // namespace
+
+hipError_t launch_as_dense_f64(const double* Z, int64_t ldz, int64_t m, int64_t K,
+                               const int32_t* members, int32_t tau, int32_t nslots, double lam,
+                               double* AS, const int32_t* done, hipStream_t s) {
+  const int64_t ntot = (int64_t)nslots * tau;
+  dim3 grid((unsigned)((m + kTM - 1) / kTM), (unsigned)((ntot + kTN - 1) / kTN));
+  hipLaunchKernelGGL(k_as_dense_f64, grid, dim3(256), 0, s, Z, ldz, m, K, members, tau, nslots,
+                     lam, AS, done);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_to_f64(const void* src, int32_t src_is_f32, int64_t rows, int64_t cols,
+                                   int64_t lds, double* dst, int64_t ldd, hipStream_t s) {
+  dim3 grid((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32));
+  hipLaunchKernelGGL(k_transpose_to_f64, grid, dim3(256), 0, s, src, src_is_f32, rows, cols, lds,
+                     dst, ldd);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_to_f64(const void* src, int32_t src_is_f32, int64_t rows, int64_t cols,
+                              int64_t lds, double* dst, int64_t ldd, hipStream_t s) {
+  if (rows == 0) return hipSuccess;
+  unsigned gx = (unsigned)((cols + 255) / 256);
+  if (gx > 64) gx = 64;
+  dim3 grid(gx, (unsigned)rows);
+  hipLaunchKernelGGL(k_copy_to_f64, grid, dim3(256), 0, s, src, src_is_f32, rows, cols, lds, dst,
+                     ldd);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemv_rows(const double* Z, int64_t ldz, int64_t m, int64_t K, const double* v,
+                            double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_gemv_rows, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, Z, ldz, m, K, v,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemv_cols(const double* Z, int64_t ldz, int64_t m, int64_t K, const double* v,
+                            double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_gemv_cols, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, Z, ldz, m, K,
+                     v, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_vec_to_f64(const void* src, int32_t src_is_f32, int64_t n, double* dst,
+                             hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_vec_to_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src,
+                     src_is_f32, n, dst);
+  return hipGetLastError();
+}
+
+}  // namespace rs

@@ -1,0 +1,588 @@
+// Host runtime behind the C ABI declared in include/rs.h.
+//
+// Solve loop (Alg. 2, eq:res_update_mom). Sketches S_k, the products AS_k and the
+// factorised inverses G_k^{-1} do not depend on the iterate (S_k is an independent
+// draw, Sec. 3), so they are produced for a batch of `lookahead` iterations at a
+// time, spreading the tau x tau factorisations over the compute units. The serial
+// part per iteration is two launches: delta_k = G_k^{-1} S_k^T r^k and the fused
+// momentum update. A device flag set by the stop test turns the remaining queued
+// work into no-ops, so no host synchronisation is needed inside a batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rs_internal.h"
+
+using namespace rs;
+
+struct rs_handle {
+  rs_options opt{};
+  int form = RS_FORM_PRIMAL;
+  int64_t n = 0, d = 0, m = 0, K = 0;
+  double lam = 0.0;
+  bool sparse = false;
+  int kind = kSubsample;
+  int tau = 0, sub_k = 0;
+  int64_t nsel = 0;
+  hipStream_t stream = nullptr;
+
+  // Z (m x K): dense row-major, or CSR of Z and of Z^T.
+  double* Z = nullptr;
+  int64_t ldz = 0;
+  int64_t* zr_ptr = nullptr;
+  int32_t* zr_col = nullptr;
+  double* zr_val = nullptr;
+  int64_t* zt_ptr = nullptr;
+  int32_t* zt_col = nullptr;
+  double* zt_val = nullptr;
+
+  double* b = nullptr;
+  double* xbuf[2] = {nullptr, nullptr};
+  double* rbuf[2] = {nullptr, nullptr};
+
+  // lookahead batch
+  int B = 1;
+  int64_t ldg = 0;
+  int32_t* hmap = nullptr;
+  int32_t* members = nullptr;
+  int32_t* offs = nullptr;
+  uint64_t* keys = nullptr;
+  double* AS = nullptr;
+  double* G = nullptr;
+  double* W = nullptr;
+  int32_t* status = nullptr;
+  double* delta = nullptr;
+  double* partials = nullptr;
+  int npart = 0;
+  double* hist = nullptr;
+  int64_t hist_len = 0;
+  DevFlags* flags = nullptr;
+  int32_t* err = nullptr;
+
+  int64_t k = 0;          // iterations performed
+  int64_t batch_k0 = -1;  // iteration of slot 0 of the most recent batch
+  int batch_n = 0;
+  bool done = false;
+  std::string last_error;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct Fail {
+  rs_status code;
+  std::string msg;
+};
+
+void check_hip(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw Fail{RS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+template <class T>
+T* dalloc(rs_handle* h, size_t count) {
+  if (count == 0) count = 1;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, sizeof(T) * count);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Fail{RS_ENOMEM, "hipMalloc of " + std::to_string(sizeof(T) * count) + " bytes failed"};
+  }
+  h->allocs.push_back(p);
+  return static_cast<T*>(p);
+}
+
+void dfree_all(rs_handle* h) {
+  for (void* p : h->allocs) (void)hipFree(p);
+  h->allocs.clear();
+}
+
+// Momentum schedule (Sec. 6, Sec. 9.1), evaluated in a fixed operation order.
+#pragma clang fp contract(off)
+void schedule(const rs_options& o, int64_t k, double* gamma, double* beta) {
+  switch (o.momentum) {
+    case RS_MOMENTUM_NONE:
+      *gamma = 1.0;
+      *beta = 0.0;
+      return;
+    case RS_MOMENTUM_CONSTANT:
+      *gamma = o.gamma;
+      *beta = o.beta;
+      return;
+    default: {
+      const double eta = o.eta;
+      double denom = (double)(k + 1) * (1.0 - eta);
+      denom = denom + 1.0;
+      const double bt = 1.0 - (2.0 - eta) / denom;
+      *gamma = 1.0;
+      *beta = std::min(o.beta_max, bt);
+      return;
+    }
+  }
+}
+
+int subcount_rule(int64_t m, int tau) {
+  if (10ll * tau <= m) return 10;
+  return (int)(m / tau);
+}
+
+template <class T>
+T* to_device(rs_handle* h, const void* src, size_t count, int mem) {
+  T* d = dalloc<T>(h, count);
+  if (count) check_hip(hipMemcpyAsync(d, src, sizeof(T) * count,
+                                      mem == RS_DEVICE ? hipMemcpyDeviceToDevice
+                                                       : hipMemcpyHostToDevice,
+                                      h->stream),
+                       "upload");
+  return d;
+}
+
+void run_batch(rs_handle* h, int64_t k0, int nb) {
+  hipStream_t s = h->stream;
+  const int32_t* done = &h->flags->done;
+  SketchArgs a{};
+  a.kind = h->kind;
+  a.m = h->m;
+  a.tau = h->tau;
+  a.sub_k = h->sub_k;
+  a.nsel = h->nsel;
+  a.seed = h->opt.seed;
+  a.pid = h->opt.problem_id;
+  a.k0 = k0;
+  a.nslots = nb;
+  a.hmap = h->hmap;
+  a.members = h->members;
+  a.offs = h->offs;
+  a.keys = h->keys;
+  a.err = h->err;
+  a.done = done;
+  check_hip(launch_sketch(a, s), "sketch");
+  if (h->sparse) {
+    check_hip(launch_as_sparse_f64(h->zr_ptr, h->zr_col, h->zr_val, h->zt_ptr, h->zt_col, h->zt_val,
+                                   h->m, h->tau, nb, h->kind, h->lam, h->hmap, h->members, h->offs,
+                                   h->nsel, h->AS, h->G, h->ldg, done, s),
+              "AS (sparse)");
+  } else {
+    check_hip(launch_as_dense_f64(h->Z, h->ldz, h->m, h->K, h->members, h->tau, nb, h->lam, h->AS,
+                                  done, s),
+              "AS (dense)");
+  }
+  check_hip(launch_chol_inverse(h->G, h->W, h->ldg, h->tau, nb, h->kind, h->AS, h->m, h->members,
+                                h->offs, h->status, done, s),
+            "cholesky");
+  for (int i = 0; i < nb; ++i) {
+    const int64_t k = k0 + i;
+    double gamma, beta;
+    schedule(h->opt, k, &gamma, &beta);
+    const int cur = (int)(k & 1), nxt = 1 - cur;
+    const int32_t* hm = h->hmap + (int64_t)i * h->m;
+    check_hip(launch_delta(h->rbuf[cur], hm, h->members + (int64_t)i * h->nsel,
+                           h->offs + (int64_t)i * (h->tau + 1), h->tau,
+                           h->G + (int64_t)i * h->ldg * h->ldg, h->ldg, h->partials, h->npart,
+                           h->flags, h->hist, k, h->opt.tol, h->delta, s),
+              "delta");
+    check_hip(launch_update(h->AS + (int64_t)i * h->m * h->tau, h->tau, h->delta, hm, h->m,
+                            h->xbuf[cur], h->xbuf[nxt], h->rbuf[cur], h->rbuf[nxt], gamma, beta,
+                            h->partials, h->npart, h->flags, s),
+              "update");
+  }
+  h->batch_k0 = k0;
+  h->batch_n = nb;
+}
+
+// Advance up to `iters` iterations, one lookahead batch at a time. After each batch
+// the stop flag, the factorisation status and the error word are read back.
+void advance(rs_handle* h, int64_t iters) {
+  int64_t k_enq = h->k;
+  int64_t left = std::min(iters, h->opt.max_iter - h->k);
+  std::vector<int32_t> st(h->B);
+  while (left > 0 && !h->done) {
+    const int nb = (int)std::min<int64_t>(h->B, left);
+    run_batch(h, k_enq, nb);
+    k_enq += nb;
+    left -= nb;
+    if (left == 0)
+      check_hip(launch_finalize(h->partials, h->npart, h->flags, h->hist, k_enq, h->opt.tol, h->stream),
+                "finalize");
+    DevFlags f{};
+    int32_t err = 0;
+    check_hip(hipMemcpyAsync(&f, h->flags, sizeof(DevFlags), hipMemcpyDeviceToHost, h->stream), "flags");
+    check_hip(hipMemcpyAsync(st.data(), h->status, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, h->stream),
+              "status");
+    check_hip(hipMemcpyAsync(&err, h->err, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream), "err");
+    check_hip(hipStreamSynchronize(h->stream), "sync");
+    if (err) throw Fail{RS_EDEVICE, "internal sketch limit hit (code " + std::to_string(err) + ")"};
+    const int64_t k_end = f.done ? f.k_done : k_enq;
+    for (int i = 0; i < nb; ++i)
+      if (st[i] != 0 && h->batch_k0 + i < k_end)
+        throw Fail{RS_ESINGULAR, "non-positive pivot in the Cholesky factorisation of S^T A S"};
+    h->k = k_end;
+    if (f.done) h->done = true;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+rs_status rs_options_default(rs_options* o) {
+  if (!o) return RS_EINVAL;
+  std::memset(o, 0, sizeof(*o));
+  o->form = RS_FORM_AUTO;
+  o->sketch = RS_SKETCH_SUBSAMPLE;
+  o->tau = 0;
+  o->subcount_k = 0;
+  o->momentum = RS_MOMENTUM_HEURISTIC;
+  o->precision = RS_PREC_FP64;
+  o->gamma = 1.0;
+  o->beta = 0.5;
+  o->eta = 0.995;
+  o->beta_max = 0.5;
+  o->tol = 1e-6;
+  o->max_iter = 100000;
+  o->seed = 1;
+  o->problem_id = 0;
+  o->refresh_every = 20;
+  o->lookahead = 0;
+  o->stream = nullptr;
+  return RS_OK;
+}
+
+const char* rs_status_string(rs_status s) {
+  switch (s) {
+    case RS_OK: return "ok";
+    case RS_NOT_CONVERGED: return "not converged (max_iter reached)";
+    case RS_EINVAL: return "invalid argument";
+    case RS_ENOMEM: return "out of device memory";
+    case RS_EDEVICE: return "device error";
+    case RS_ESINGULAR: return "sketched system not positive definite";
+    case RS_EUNSUPPORTED: return "unsupported option";
+    default: return "unknown status";
+  }
+}
+
+const char* rs_last_error(const rs_handle* h) {
+  return h ? h->last_error.c_str() : g_create_error.c_str();
+}
+
+rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs_options* o,
+                    rs_handle** out) {
+  g_create_error.clear();
+  if (!X || !y || !o || !out) {
+    g_create_error = "null argument";
+    return RS_EINVAL;
+  }
+  *out = nullptr;
+  rs_handle* h = new rs_handle();
+  try {
+    h->opt = *o;
+    h->stream = static_cast<hipStream_t>(o->stream);
+    const int64_t n = X->n, d = X->d;
+    if (n <= 0 || d <= 0) throw Fail{RS_EINVAL, "X must have n, d >= 1"};
+    if (!(lambda > 0.0) || !std::isfinite(lambda)) throw Fail{RS_EINVAL, "lambda must be positive and finite"};
+    if (X->dtype != RS_F64 && X->dtype != RS_F32) throw Fail{RS_EINVAL, "dtype must be RS_F64 or RS_F32"};
+    if (X->mem != RS_HOST && X->mem != RS_DEVICE) throw Fail{RS_EINVAL, "mem must be RS_HOST or RS_DEVICE"};
+    if (X->layout != RS_DENSE_ROWMAJOR && X->layout != RS_DENSE_COLMAJOR && X->layout != RS_CSR)
+      throw Fail{RS_EINVAL, "unknown layout"};
+    if (!X->vals) throw Fail{RS_EINVAL, "X.vals is null"};
+    if (X->layout == RS_CSR && (!X->row_ptr || !X->col_idx || X->nnz < 0))
+      throw Fail{RS_EINVAL, "CSR needs row_ptr, col_idx and nnz >= 0"};
+    if (n > INT32_MAX || d > INT32_MAX) throw Fail{RS_EINVAL, "n and d must fit in int32"};
+    if (o->precision != RS_PREC_FP64) throw Fail{RS_EUNSUPPORTED, "only RS_PREC_FP64 is built"};
+    if (o->momentum < RS_MOMENTUM_NONE || o->momentum > RS_MOMENTUM_HEURISTIC)
+      throw Fail{RS_EINVAL, "unknown momentum"};
+    if (!(o->tol >= 0.0)) throw Fail{RS_EINVAL, "tol must be >= 0"};
+    if (o->max_iter < 0 || o->max_iter > 100000000) throw Fail{RS_EINVAL, "max_iter out of range"};
+    h->form = o->form == RS_FORM_AUTO ? (d <= n ? RS_FORM_PRIMAL : RS_FORM_DUAL) : o->form;
+    if (h->form != RS_FORM_PRIMAL && h->form != RS_FORM_DUAL) throw Fail{RS_EINVAL, "unknown form"};
+    h->n = n;
+    h->d = d;
+    h->m = h->form == RS_FORM_PRIMAL ? d : n;
+    h->K = h->form == RS_FORM_PRIMAL ? n : d;
+    h->lam = lambda;
+    h->sparse = X->layout == RS_CSR;
+    h->tau = o->tau;
+    if (h->tau < 1 || h->tau > h->m) throw Fail{RS_EINVAL, "tau must satisfy 1 <= tau <= m"};
+    switch (o->sketch) {
+      case RS_SKETCH_SUBSAMPLE:
+        h->kind = kSubsample;
+        h->nsel = h->tau;
+        break;
+      case RS_SKETCH_COUNT:
+        h->kind = kCount;
+        h->nsel = h->m;
+        if (h->tau > 2048) throw Fail{RS_EUNSUPPORTED, "count sketch supports tau <= 2048"};
+        break;
+      case RS_SKETCH_SUBCOUNT:
+        h->kind = kSubcount;
+        h->sub_k = o->subcount_k > 0 ? o->subcount_k : subcount_rule(h->m, h->tau);
+        h->nsel = (int64_t)h->sub_k * h->tau;
+        if (h->sub_k < 1 || h->nsel > h->m) throw Fail{RS_EINVAL, "SubCount needs 1 <= k and k * tau <= m"};
+        if (h->nsel > 8192) throw Fail{RS_EUNSUPPORTED, "SubCount supports s = k * tau <= 8192"};
+        if (h->tau > 2048) throw Fail{RS_EUNSUPPORTED, "SubCount supports tau <= 2048"};
+        break;
+      default:
+        throw Fail{RS_EINVAL, "unknown sketch"};
+    }
+    if (h->kind != kSubsample && !h->sparse)
+      throw Fail{RS_EUNSUPPORTED, "count and SubCount sketches need CSR data"};
+    if (h->kind == kSubsample && h->sparse)
+      throw Fail{RS_EUNSUPPORTED, "the subsample sketch needs dense data"};
+
+    // y: validate on the host
+    std::vector<double> yh(n);
+    if (X->mem == RS_DEVICE)
+      check_hip(hipMemcpy(yh.data(), y, sizeof(double) * n, hipMemcpyDeviceToHost), "y download");
+    else
+      std::memcpy(yh.data(), y, sizeof(double) * n);
+    for (double v : yh)
+      if (!std::isfinite(v)) throw Fail{RS_EINVAL, "y has a non-finite entry"};
+
+    hipStream_t s = h->stream;
+    const bool f32 = X->dtype == RS_F32;
+    const size_t esz = f32 ? 4 : 8;
+    double* yd = to_device<double>(h, yh.data(), n, RS_HOST);
+    h->b = dalloc<double>(h, h->m);
+
+    if (!h->sparse) {
+      const size_t total = (size_t)n * d;
+      void* xv = dalloc<char>(h, total * esz);
+      check_hip(hipMemcpyAsync(xv, X->vals, total * esz,
+                               X->mem == RS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s),
+                "X upload");
+      h->ldz = h->K;
+      h->Z = dalloc<double>(h, (size_t)h->m * h->ldz);
+      // Z = X^T (primal) or X (dual), row-major m x K
+      const bool rowmajor = X->layout == RS_DENSE_ROWMAJOR;
+      const bool need_transpose = (h->form == RS_FORM_PRIMAL) == rowmajor;
+      if (need_transpose) {
+        // source viewed row-major: rowmajor -> n x d, colmajor -> d x n
+        const int64_t rows = rowmajor ? n : d, cols = rowmajor ? d : n;
+        check_hip(launch_transpose_to_f64(xv, f32, rows, cols, cols, h->Z, h->ldz, s), "transpose");
+      } else {
+        const int64_t rows = rowmajor ? n : d, cols = rowmajor ? d : n;
+        check_hip(launch_copy_to_f64(xv, f32, rows, cols, cols, h->Z, h->ldz, s), "copy");
+      }
+      if (h->form == RS_FORM_PRIMAL)
+        check_hip(launch_gemv_rows(h->Z, h->ldz, h->m, h->K, yd, h->b, s), "b = X^T y");
+      else
+        check_hip(hipMemcpyAsync(h->b, yd, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "b = y");
+    } else {
+      const int64_t nnz = X->nnz;
+      if (nnz > INT32_MAX) throw Fail{RS_EINVAL, "nnz must fit in int32"};
+      int64_t* xptr = to_device<int64_t>(h, X->row_ptr, n + 1, X->mem);
+      int32_t* xcol = to_device<int32_t>(h, X->col_idx, nnz, X->mem);
+      void* xval = dalloc<char>(h, (size_t)nnz * esz);
+      if (nnz)
+        check_hip(hipMemcpyAsync(xval, X->vals, nnz * esz,
+                                 X->mem == RS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s),
+                  "X upload");
+      // host-side structural check of row_ptr
+      std::vector<int64_t> ph(n + 1);
+      check_hip(hipMemcpyAsync(ph.data(), xptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s),
+                "row_ptr");
+      check_hip(hipStreamSynchronize(s), "sync");
+      if (ph[0] != 0 || ph[n] != nnz) throw Fail{RS_EINVAL, "row_ptr must start at 0 and end at nnz"};
+      for (int64_t i = 0; i < n; ++i)
+        if (ph[i + 1] < ph[i]) throw Fail{RS_EINVAL, "row_ptr must be non-decreasing"};
+      std::vector<int32_t> ch(nnz);
+      if (nnz)
+        check_hip(hipMemcpy(ch.data(), xcol, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost), "col_idx");
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t p = ph[i]; p < ph[i + 1]; ++p)
+          if (ch[p] < 0 || ch[p] >= d || (p > ph[i] && ch[p] <= ch[p - 1]))
+            throw Fail{RS_EINVAL, "col_idx must be in [0, d) and strictly increasing within a row"};
+      double* xval64 = dalloc<double>(h, nnz);
+      check_hip(launch_vec_to_f64(xval, f32, nnz, xval64, s), "values");
+      int64_t* tptr = dalloc<int64_t>(h, d + 1);
+      int32_t* tcol = dalloc<int32_t>(h, nnz);
+      double* tval = dalloc<double>(h, nnz);
+      check_hip(csr_transpose(xptr, xcol, xval, f32, n, d, nnz, tptr, tcol, tval, s), "transpose");
+      if (h->form == RS_FORM_PRIMAL) {
+        h->zr_ptr = tptr; h->zr_col = tcol; h->zr_val = tval;  // Z = X^T
+        h->zt_ptr = xptr; h->zt_col = xcol; h->zt_val = xval64;
+        check_hip(launch_spmv_csr(h->zr_ptr, h->zr_col, h->zr_val, h->m, yd, h->b, s), "b = X^T y");
+      } else {
+        h->zr_ptr = xptr; h->zr_col = xcol; h->zr_val = xval64;  // Z = X
+        h->zt_ptr = tptr; h->zt_col = tcol; h->zt_val = tval;
+        check_hip(hipMemcpyAsync(h->b, yd, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "b = y");
+      }
+    }
+
+    // batch buffers
+    h->ldg = ((int64_t)h->tau + 31) / 32 * 32;
+    const size_t per_slot = sizeof(double) * ((size_t)h->m * h->tau + 2 * (size_t)h->ldg * h->ldg) +
+                            sizeof(int32_t) * ((size_t)h->m + h->nsel + h->tau + 1) +
+                            sizeof(uint64_t) * (size_t)h->m;
+    int B = o->lookahead > 0 ? o->lookahead : 64;
+    const size_t budget = (size_t)24 << 30;
+    while (B > 1 && (size_t)B * per_slot > budget) B >>= 1;
+    h->B = B;
+    h->hmap = dalloc<int32_t>(h, (size_t)B * h->m);
+    h->members = dalloc<int32_t>(h, (size_t)B * h->nsel);
+    h->offs = dalloc<int32_t>(h, (size_t)B * (h->tau + 1));
+    h->keys = dalloc<uint64_t>(h, (size_t)B * h->m);
+    h->AS = dalloc<double>(h, (size_t)B * h->m * h->tau);
+    h->G = dalloc<double>(h, (size_t)B * h->ldg * h->ldg);
+    h->W = dalloc<double>(h, (size_t)B * h->ldg * h->ldg);
+    h->status = dalloc<int32_t>(h, B);
+    h->delta = dalloc<double>(h, h->ldg);
+    h->npart = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (h->m + 255) / 256));
+    h->partials = dalloc<double>(h, h->npart);
+    h->hist_len = h->opt.max_iter + 1;
+    h->hist = dalloc<double>(h, h->hist_len);
+    h->flags = dalloc<DevFlags>(h, 1);
+    h->err = dalloc<int32_t>(h, 1);
+    for (int i = 0; i < 2; ++i) {
+      h->xbuf[i] = dalloc<double>(h, h->m);
+      h->rbuf[i] = dalloc<double>(h, h->m);
+    }
+    check_hip(hipMemsetAsync(h->status, 0, sizeof(int32_t) * B, s), "memset");
+    check_hip(hipMemsetAsync(h->err, 0, sizeof(int32_t), s), "memset");
+    check_hip(launch_init_state(h->b, h->xbuf[0], h->xbuf[1], h->rbuf[0], h->rbuf[1], h->m,
+                                h->partials, h->npart, h->flags, h->hist, s),
+              "init");
+    DevFlags f{};
+    check_hip(hipMemcpyAsync(&f, h->flags, sizeof(DevFlags), hipMemcpyDeviceToHost, s), "flags");
+    check_hip(hipStreamSynchronize(s), "sync");
+    h->done = f.done != 0;
+    *out = h;
+    return RS_OK;
+  } catch (const Fail& f) {
+    g_create_error = f.msg;
+    dfree_all(h);
+    delete h;
+    return f.code;
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    dfree_all(h);
+    delete h;
+    return RS_EDEVICE;
+  }
+}
+
+rs_status rs_step(rs_handle* h, int64_t iters, double* rel_res_out) {
+  if (!h || iters < 0) return RS_EINVAL;
+  try {
+    if (iters > 0) advance(h, iters);
+    if (rel_res_out) {
+      double v = 1.0;
+      check_hip(hipMemcpy(&v, h->hist + h->k, sizeof(double), hipMemcpyDeviceToHost), "hist");
+      *rel_res_out = v;
+    }
+    return RS_OK;
+  } catch (const Fail& f) {
+    h->last_error = f.msg;
+    return f.code;
+  }
+}
+
+int64_t rs_iteration(const rs_handle* h) { return h ? h->k : -1; }
+int64_t rs_system_size(const rs_handle* h) { return h ? h->m : -1; }
+
+rs_status rs_get_weights(rs_handle* h, double* w_out) {
+  if (!h || !w_out) return RS_EINVAL;
+  try {
+    const double* x = h->xbuf[h->k & 1];
+    if (h->form == RS_FORM_PRIMAL) {
+      check_hip(hipMemcpyAsync(w_out, x, sizeof(double) * h->d, hipMemcpyDeviceToHost, h->stream), "w");
+    } else {
+      double* wd = nullptr;
+      check_hip(hipMalloc(&wd, sizeof(double) * h->d), "alloc");
+      hipError_t e = h->sparse ? launch_spmv_csr(h->zt_ptr, h->zt_col, h->zt_val, h->d, x, wd, h->stream)
+                               : launch_gemv_cols(h->Z, h->ldz, h->m, h->K, x, wd, h->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(w_out, wd, sizeof(double) * h->d, hipMemcpyDeviceToHost, h->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+      (void)hipFree(wd);
+      check_hip(e, "w = X^T alpha");
+    }
+    check_hip(hipStreamSynchronize(h->stream), "sync");
+    return RS_OK;
+  } catch (const Fail& f) {
+    h->last_error = f.msg;
+    return f.code;
+  }
+}
+
+rs_status rs_solve(rs_handle* h, double* w_out, rs_report* rep) {
+  if (!h) return RS_EINVAL;
+  try {
+    const auto t0 = std::chrono::steady_clock::now();
+    advance(h, h->opt.max_iter - h->k);
+    const auto t1 = std::chrono::steady_clock::now();
+    double rel = 1.0;
+    check_hip(hipMemcpy(&rel, h->hist + h->k, sizeof(double), hipMemcpyDeviceToHost), "hist");
+    if (rep) {
+      rep->iters = h->k;
+      rep->rel_res = rel;
+      rep->seconds = std::chrono::duration<double>(t1 - t0).count();
+    }
+    if (w_out) {
+      rs_status st = rs_get_weights(h, w_out);
+      if (st != RS_OK) return st;
+    }
+    return h->done ? RS_OK : RS_NOT_CONVERGED;
+  } catch (const Fail& f) {
+    h->last_error = f.msg;
+    return f.code;
+  }
+}
+
+rs_status rs_get_state(const rs_handle* h, double* x, double* x_prev, double* r, double* r_prev) {
+  if (!h) return RS_EINVAL;
+  const int cur = (int)(h->k & 1), prv = 1 - cur;
+  const double* src[4] = {h->xbuf[cur], h->xbuf[prv], h->rbuf[cur], h->rbuf[prv]};
+  double* dst[4] = {x, x_prev, r, r_prev};
+  for (int i = 0; i < 4; ++i)
+    if (dst[i] && hipMemcpy(dst[i], src[i], sizeof(double) * h->m, hipMemcpyDeviceToHost) != hipSuccess)
+      return RS_EDEVICE;
+  return RS_OK;
+}
+
+rs_status rs_get_last_sketch(const rs_handle* h, int32_t* rows, int32_t* cols, int8_t* signs,
+                             int64_t* nnz_out) {
+  if (!h || !rows || !cols || !signs || !nnz_out) return RS_EINVAL;
+  const int64_t it = h->k - 1;
+  if (it < 0 || h->batch_k0 < 0 || it < h->batch_k0 || it >= h->batch_k0 + h->batch_n) return RS_EINVAL;
+  const int64_t slot = it - h->batch_k0;
+  std::vector<int32_t> mem(h->nsel), off(h->tau + 1), hm(h->m);
+  if (hipMemcpy(mem.data(), h->members + slot * h->nsel, sizeof(int32_t) * h->nsel, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(off.data(), h->offs + slot * (h->tau + 1), sizeof(int32_t) * (h->tau + 1), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(hm.data(), h->hmap + slot * h->m, sizeof(int32_t) * h->m, hipMemcpyDeviceToHost) != hipSuccess)
+    return RS_EDEVICE;
+  int64_t c = 0;
+  for (int b = 0; b < h->tau; ++b)
+    for (int p = off[b]; p < off[b + 1]; ++p) {
+      const int32_t j = mem[p];
+      rows[c] = j;
+      cols[c] = b;
+      signs[c] = (hm[j] & 1) ? -1 : 1;
+      ++c;
+    }
+  *nnz_out = c;
+  return RS_OK;
+}
+
+rs_status rs_get_history(const rs_handle* h, double* out, int64_t count) {
+  if (!h || !out || count < 0 || count > h->k + 1) return RS_EINVAL;
+  if (count && hipMemcpy(out, h->hist, sizeof(double) * count, hipMemcpyDeviceToHost) != hipSuccess)
+    return RS_EDEVICE;
+  return RS_OK;
+}
+
+rs_status rs_destroy(rs_handle* h) {
+  if (!h) return RS_EINVAL;
+  if (h->stream) (void)hipStreamSynchronize(h->stream); else (void)hipDeviceSynchronize();
+  dfree_all(h);
+  delete h;
+  return RS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,319 @@
+"""Python binding of librs.so (include/rs.h): argument marshalling only.
+
+Every step of the solver runs inside the HIP library. This module converts
+numpy arrays (host memory) or torch CUDA tensors (device memory) into the
+plain pointers and sizes the C ABI takes, and raises ``RsError`` on a negative
+status. It fails loudly when the library is missing: there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librs.so")
+
+RS_OK, RS_NOT_CONVERGED = 0, 1
+RS_EINVAL, RS_ENOMEM, RS_EDEVICE, RS_ESINGULAR, RS_EUNSUPPORTED = -1, -2, -3, -4, -5
+RS_DENSE_ROWMAJOR, RS_DENSE_COLMAJOR, RS_CSR = 0, 1, 2
+RS_F64, RS_F32 = 0, 1
+RS_HOST, RS_DEVICE = 0, 1
+RS_FORM_AUTO, RS_FORM_PRIMAL, RS_FORM_DUAL = 0, 1, 2
+RS_SKETCH_SUBSAMPLE, RS_SKETCH_COUNT, RS_SKETCH_SUBCOUNT = 0, 1, 2
+RS_MOMENTUM_NONE, RS_MOMENTUM_CONSTANT, RS_MOMENTUM_HEURISTIC = 0, 1, 2
+RS_PREC_FP64, RS_PREC_MIXED_BF16 = 0, 1
+
+FORMS = {"auto": RS_FORM_AUTO, "primal": RS_FORM_PRIMAL, "dual": RS_FORM_DUAL}
+SKETCHES = {"subsample": RS_SKETCH_SUBSAMPLE, "count": RS_SKETCH_COUNT, "subcount": RS_SKETCH_SUBCOUNT}
+MOMENTA = {"none": RS_MOMENTUM_NONE, "constant": RS_MOMENTUM_CONSTANT, "heuristic": RS_MOMENTUM_HEURISTIC}
+PRECISIONS = {"fp64": RS_PREC_FP64, "mixed": RS_PREC_MIXED_BF16}
+
+
+class rs_matrix(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int64), ("layout", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("vals", ctypes.c_void_p), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("nnz", ctypes.c_int64), ("mem", ctypes.c_int32)]
+
+
+class rs_options(ctypes.Structure):
+    _fields_ = [("form", ctypes.c_int32), ("sketch", ctypes.c_int32), ("tau", ctypes.c_int32),
+                ("subcount_k", ctypes.c_int32), ("momentum", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("gamma", ctypes.c_double), ("beta", ctypes.c_double),
+                ("eta", ctypes.c_double), ("beta_max", ctypes.c_double), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int64), ("seed", ctypes.c_uint64), ("problem_id", ctypes.c_uint64),
+                ("refresh_every", ctypes.c_int32), ("lookahead", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
+class rs_report(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int64), ("rel_res", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+class RsError(RuntimeError):
+    def __init__(self, status, where, detail=""):
+        self.status = status
+        super().__init__(f"{where}: status {status} ({status_string(status)}) {detail}".rstrip())
+
+
+_lib = None
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+
+# name -> (restype, argtypes): every entry point declared in include/rs.h
+SIGNATURES = {
+    "rs_options_default": (ctypes.c_int32, [ctypes.POINTER(rs_options)]),
+    "rs_create": (ctypes.c_int32, [ctypes.POINTER(rs_matrix), _P, ctypes.c_double,
+                                   ctypes.POINTER(rs_options), ctypes.POINTER(_P)]),
+    "rs_step": (ctypes.c_int32, [_P, ctypes.c_int64, _D]),
+    "rs_solve": (ctypes.c_int32, [_P, _P, ctypes.POINTER(rs_report)]),
+    "rs_iteration": (ctypes.c_int64, [_P]),
+    "rs_system_size": (ctypes.c_int64, [_P]),
+    "rs_get_state": (ctypes.c_int32, [_P, _P, _P, _P, _P]),
+    "rs_get_weights": (ctypes.c_int32, [_P, _P]),
+    "rs_get_last_sketch": (ctypes.c_int32, [_P, _P, _P, _P, ctypes.POINTER(ctypes.c_int64)]),
+    "rs_get_history": (ctypes.c_int32, [_P, _P, ctypes.c_int64]),
+    "rs_destroy": (ctypes.c_int32, [_P]),
+    "rs_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
+    "rs_last_error": (ctypes.c_char_p, [_P]),
+}
+
+
+def load(path=LIB_PATH):
+    """Load librs.so; raises if it is not built. No CPU fallback exists.
+
+    PyTorch wheels carry their own HIP runtime (same SONAME as the system one).
+    torch is imported first when it is installed, so that librs.so binds to that
+    runtime by SONAME and device pointers and streams from torch are valid for it:
+    one process must hold a single HIP runtime.
+    """
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with `python -m paper_2105_05565_amd.build`")
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        lib = ctypes.CDLL(path, mode=os.RTLD_NOW | os.RTLD_GLOBAL)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def status_string(s):
+    return load().rs_status_string(int(s)).decode()
+
+
+def last_error(h=None):
+    return load().rs_last_error(h).decode()
+
+
+def _check(status, where, h=None):
+    if status < 0:
+        raise RsError(status, where, last_error(h))
+    return status
+
+
+def _ptr(a):
+    """Pointer of a numpy array (host) or torch tensor (device); keeps no reference."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _is_device(a):
+    return not isinstance(a, np.ndarray) and getattr(a, "is_cuda", False)
+
+
+# ---------------------------------------------------------------- thin wrappers (same names)
+def rs_options_default():
+    o = rs_options()
+    _check(load().rs_options_default(ctypes.byref(o)), "rs_options_default")
+    return o
+
+
+def rs_create(X, y, lam, opts):
+    h = _P()
+    _check(load().rs_create(ctypes.byref(X), _ptr(y), float(lam), ctypes.byref(opts), ctypes.byref(h)),
+           "rs_create")
+    return h
+
+
+def rs_step(h, iters):
+    rel = ctypes.c_double(0.0)
+    _check(load().rs_step(h, int(iters), ctypes.byref(rel)), "rs_step", h)
+    return rel.value
+
+
+def rs_solve(h, w_out=None):
+    rep = rs_report()
+    st = _check(load().rs_solve(h, _ptr(w_out), ctypes.byref(rep)), "rs_solve", h)
+    return st, rep
+
+
+def rs_iteration(h):
+    return load().rs_iteration(h)
+
+
+def rs_system_size(h):
+    return load().rs_system_size(h)
+
+
+def rs_get_state(h, x=None, x_prev=None, r=None, r_prev=None):
+    _check(load().rs_get_state(h, _ptr(x), _ptr(x_prev), _ptr(r), _ptr(r_prev)), "rs_get_state", h)
+
+
+def rs_get_weights(h, w_out):
+    _check(load().rs_get_weights(h, _ptr(w_out)), "rs_get_weights", h)
+
+
+def rs_get_last_sketch(h, rows, cols, signs):
+    nnz = ctypes.c_int64(0)
+    _check(load().rs_get_last_sketch(h, _ptr(rows), _ptr(cols), _ptr(signs), ctypes.byref(nnz)),
+           "rs_get_last_sketch", h)
+    return nnz.value
+
+
+def rs_get_history(h, out, count):
+    _check(load().rs_get_history(h, _ptr(out), int(count)), "rs_get_history", h)
+
+
+def rs_destroy(h):
+    if h:
+        load().rs_destroy(h)
+
+
+# ---------------------------------------------------------------- convenience wrapper
+def make_matrix(X):
+    """rs_matrix for a numpy array, a scipy CSR matrix, or torch CUDA tensors.
+
+    Returns (rs_matrix, keepalive) -- keep `keepalive` until rs_create returns.
+    """
+    import scipy.sparse as sp
+    keep = []
+    M = rs_matrix()
+    if isinstance(X, tuple):  # (indptr, indices, data, shape) as torch CUDA tensors
+        indptr, indices, data, shape = X
+        M.n, M.d = shape
+        M.layout = RS_CSR
+        M.dtype = RS_F32 if str(data.dtype).endswith("float32") else RS_F64
+        M.vals, M.row_ptr, M.col_idx = data.data_ptr(), indptr.data_ptr(), indices.data_ptr()
+        M.nnz = int(data.numel())
+        M.mem = RS_DEVICE
+        keep += [indptr, indices, data]
+        return M, keep
+    if sp.issparse(X):
+        X = sp.csr_matrix(X)
+        X.sort_indices()
+        indptr = np.ascontiguousarray(X.indptr, dtype=np.int64)
+        indices = np.ascontiguousarray(X.indices, dtype=np.int32)
+        data = np.ascontiguousarray(X.data)
+        if data.dtype not in (np.float32, np.float64):
+            data = data.astype(np.float64)
+        M.n, M.d = X.shape
+        M.layout = RS_CSR
+        M.dtype = RS_F32 if data.dtype == np.float32 else RS_F64
+        M.vals, M.row_ptr, M.col_idx = data.ctypes.data, indptr.ctypes.data, indices.ctypes.data
+        M.nnz = int(data.shape[0])
+        M.mem = RS_HOST
+        keep += [indptr, indices, data]
+        return M, keep
+    if isinstance(X, np.ndarray):
+        A = X if X.dtype in (np.float32, np.float64) else X.astype(np.float64)
+        if A.flags.c_contiguous:
+            M.layout = RS_DENSE_ROWMAJOR
+        elif A.flags.f_contiguous:
+            M.layout = RS_DENSE_COLMAJOR
+        else:
+            A = np.ascontiguousarray(A)
+            M.layout = RS_DENSE_ROWMAJOR
+        M.n, M.d = A.shape
+        M.dtype = RS_F32 if A.dtype == np.float32 else RS_F64
+        M.vals = A.ctypes.data
+        M.mem = RS_HOST
+        keep.append(A)
+        return M, keep
+    # torch tensor on the GPU, row-major contiguous
+    A = X.contiguous()
+    M.n, M.d = A.shape
+    M.layout = RS_DENSE_ROWMAJOR
+    M.dtype = RS_F32 if str(A.dtype).endswith("float32") else RS_F64
+    M.vals = A.data_ptr()
+    M.mem = RS_DEVICE if _is_device(A) else RS_HOST
+    keep.append(A)
+    return M, keep
+
+
+class Solver:
+    """Owns one rs_handle. `X` and `y` may live on the host (numpy) or the GPU (torch)."""
+
+    def __init__(self, X, y, lam, *, tau, sketch="subsample", form="auto", momentum="heuristic",
+                 precision="fp64", subcount_k=0, tol=1e-6, max_iter=100000, seed=1, problem_id=0,
+                 eta=0.995, beta_max=0.5, gamma=1.0, beta=0.5, lookahead=0, refresh_every=20,
+                 stream=None):
+        o = rs_options_default()
+        o.form, o.sketch, o.tau = FORMS[form], SKETCHES[sketch], int(tau)
+        o.subcount_k, o.momentum, o.precision = int(subcount_k), MOMENTA[momentum], PRECISIONS[precision]
+        o.gamma, o.beta, o.eta, o.beta_max, o.tol = gamma, beta, eta, beta_max, tol
+        o.max_iter, o.seed, o.problem_id = int(max_iter), int(seed), int(problem_id)
+        o.refresh_every, o.lookahead = int(refresh_every), int(lookahead)
+        o.stream = stream
+        M, keep = make_matrix(X)
+        if M.mem == RS_DEVICE:
+            yv = y.double().contiguous()
+        else:
+            yv = np.ascontiguousarray(np.asarray(y, dtype=np.float64))
+        keep.append(yv)
+        self.h = rs_create(M, yv, lam, o)
+        self.m = rs_system_size(self.h)
+        self.d = int(M.d)
+
+    def step(self, iters):
+        return rs_step(self.h, iters)
+
+    def solve(self):
+        w = np.zeros(self.d)
+        st, rep = rs_solve(self.h, w)
+        return w, st, rep
+
+    @property
+    def k(self):
+        return rs_iteration(self.h)
+
+    def state(self):
+        x, xp, r, rp = (np.zeros(self.m) for _ in range(4))
+        rs_get_state(self.h, x, xp, r, rp)
+        return x, xp, r, rp
+
+    def weights(self):
+        w = np.zeros(self.d)
+        rs_get_weights(self.h, w)
+        return w
+
+    def last_sketch(self):
+        rows = np.zeros(self.m, dtype=np.int32)
+        cols = np.zeros(self.m, dtype=np.int32)
+        signs = np.zeros(self.m, dtype=np.int8)
+        n = rs_get_last_sketch(self.h, rows, cols, signs)
+        return rows[:n].astype(np.int64), cols[:n].astype(np.int64), signs[:n].astype(np.float64)
+
+    def history(self):
+        out = np.zeros(self.k + 1)
+        rs_get_history(self.h, out, self.k + 1)
+        return out
+
+    def close(self):
+        if self.h:
+            rs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

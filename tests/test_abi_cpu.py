@@ -1,0 +1,101 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared entry
+point, and rejects bad arguments before touching a device (no GPU needed)."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2105_05565_amd import rs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rs.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(rs.LIB_PATH), reason="librs.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rs_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ["rs_create", "rs_step", "rs_solve", "rs_destroy", "rs_get_state", "rs_status_string"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(rs.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(declared_functions()) == set(rs.SIGNATURES), "binding and header disagree"
+
+
+def test_status_strings_and_defaults():
+    assert rs.status_string(rs.RS_OK) == "ok"
+    assert "invalid" in rs.status_string(rs.RS_EINVAL)
+    o = rs.rs_options_default()
+    assert o.tol == 1e-6 and o.eta == 0.995 and o.beta_max == 0.5 and o.momentum == rs.RS_MOMENTUM_HEURISTIC
+
+
+def _create(X, y, lam, **kw):
+    o = rs.rs_options_default()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    M, keep = rs.make_matrix(X)
+    yv = np.ascontiguousarray(y, dtype=np.float64)
+    h = rs.rs_create(M, yv, lam, o)
+    rs.rs_destroy(h)
+
+
+@pytest.mark.parametrize("kw,lam", [
+    (dict(tau=0), 1.0),                      # tau < 1
+    (dict(tau=9), 1.0),                      # tau > m = 8
+    (dict(tau=3), 0.0),                      # lambda <= 0
+    (dict(tau=3), -1.0),
+    (dict(tau=3), math.inf),
+    (dict(tau=3, max_iter=-1), 1.0),
+    (dict(tau=3, tol=-1.0), 1.0),
+    (dict(tau=3, momentum=7), 1.0),
+    (dict(tau=3, form=9), 1.0),
+    (dict(tau=3, sketch=9), 1.0),
+])
+def test_rejects_bad_arguments_without_device(kw, lam):
+    X = np.ones((20, 8))
+    with pytest.raises(rs.RsError) as e:
+        _create(X, np.ones(20), lam, **kw)
+    assert e.value.status == rs.RS_EINVAL
+
+
+def test_rejects_nonfinite_targets():
+    y = np.ones(20)
+    y[3] = np.nan
+    with pytest.raises(rs.RsError) as e:
+        _create(np.ones((20, 8)), y, 1.0, tau=3)
+    assert e.value.status == rs.RS_EINVAL
+    assert "non-finite" in rs.last_error()
+
+
+def test_rejects_unsupported_combinations():
+    import scipy.sparse as sp
+    with pytest.raises(rs.RsError) as e:
+        _create(np.ones((20, 8)), np.ones(20), 1.0, tau=3, sketch=rs.RS_SKETCH_COUNT)
+    assert e.value.status == rs.RS_EUNSUPPORTED
+    X = sp.random(20, 8, density=0.3, format="csr", random_state=0)
+    with pytest.raises(rs.RsError) as e:
+        _create(X, np.ones(20), 1.0, tau=3, sketch=rs.RS_SKETCH_SUBCOUNT, subcount_k=3)  # 9 > m
+    assert e.value.status == rs.RS_EINVAL
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    saved = rs._lib
+    try:
+        rs._lib = None
+        with pytest.raises(RuntimeError):
+            rs.load(str(tmp_path / "nope.so"))
+    finally:
+        rs._lib = saved
