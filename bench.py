@@ -1,0 +1,237 @@
+#!/usr/bin/env python3
+"""Benchmark: time to relative residual 1e-6 of sketch-and-project on one MI355X.
+
+A step is one full solve (x^0 = 0 until ||r^k|| / ||r^0|| <= 1e-6) of the sparse
+workload: CSR X 100000 x 20000 with 0.1% uniform nonzeros (FP32 values N(0,1)),
+y = X w* + 0.01 noise, lambda = 1e-3, primal form, count sketch tau = 500,
+heuristic momentum, FP64 arithmetic. Every step uses a new sketch seed
+(seed = step index + 1); the data and its device layouts stay resident in HBM.
+
+Prints one JSON line with the metric, a roofline entry for the kernel that
+dominates the solve (algorithmic bytes per launch over its HIP-event duration),
+a per-kernel breakdown and the CPU oracle's time on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
+FP64_PEAK_TFS = 78.6        # MI355X FP64 (vector and matrix)
+BF16_PEAK_TFS = 2500.0      # MI355X dense BF16 MFMA
+
+WORKLOADS = {
+    "sparse_count": dict(kind="csr", sketch="count", tau=500, sub_k=0,
+                         name="csr_100000x20000_density0.001_count_tau500_primal"),
+    "sparse_subcount": dict(kind="csr", sketch="subcount", tau=500, sub_k=4,
+                            name="csr_100000x20000_density0.001_subcount_s2000_tau500_primal"),
+    "dense_primal": dict(kind="dense", sketch="subsample", tau=50, sub_k=0,
+                         name="dense_2000x500_subsample_tau50_primal"),
+}
+
+
+def kernel_source_sha(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2105_05565_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(cls, wl, n, d, nnz, m, K, tau, nsel):
+    """Minimum HBM bytes one sketch (iteration) needs in each kernel class (FP64 layouts)."""
+    if cls == "as":
+        if wl["kind"] == "csr":
+            # CSR of Z and of Z^T (FP32 value + int32 column each) read once, row pointers,
+            # bucket map, AS written once (FP64), G = S^T A S written once (FP64)
+            return 2 * nnz * 8 + (m + 1) * 8 + (K + 1) * 8 + m * 4 + m * tau * 8 + tau * tau * 8
+        # dense subsample: Z read once (m x K) + gathered rows (tau x K) + AS written
+        return m * K * 8 + tau * K * 8 + m * tau * 8
+    if cls == "update":
+        # AS read, bucket map, x^k, x^{k-1}, r^k, r^{k-1} read, two vectors written, delta
+        return m * tau * 8 + m * 4 + 4 * m * 8 + 2 * m * 8 + tau * 8
+    if cls == "delta":
+        return tau * tau * 8 + nsel * (4 + 4 + 8) + tau * 4 + tau * 8
+    if cls == "sketch":
+        return m * (8 + 4) + nsel * 4 + (tau + 1) * 4
+    if cls == "chol":
+        return 3 * tau * tau * 8
+    if cls == "iters":
+        return (algorithmic_bytes("delta", wl, n, d, nnz, m, K, tau, nsel)
+                + algorithmic_bytes("update", wl, n, d, nnz, m, K, tau, nsel))
+    return 0
+
+
+def make_problem(wl):
+    from paper_2105_05565_amd import inputs
+    if wl["kind"] == "csr":
+        return inputs.sparse_csr()
+    return inputs.dense_primal()
+
+
+def cpu_baseline(p, wl, gpu_iters_median, sample_s):
+    """The oracle, single-threaded, on the first iterations of the seed-1 solve."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.problem import ridge_system
+    from oracle.solver import Options, init_state, step
+    with threadpool_limits(limits=1):
+        system = ridge_system(p.X, p.y, p.lam, "primal")
+        st = init_state(system)
+        opts = Options(sketch=wl["sketch"], tau=wl["tau"], sum_size=wl["sub_k"], momentum="heuristic",
+                       seed=1, tol=1e-6)
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < sample_s and st.history[-1] > 1e-6:
+            step(system, st, opts)
+        el = time.perf_counter() - t0
+    per_iter = el / st.k
+    return {"value": per_iter * gpu_iters_median, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": (f"first {st.k} iterations of the seed-1 solve on the full workload "
+                       f"({el:.1f} s, {per_iter:.3f} s/iteration, 1 thread), extrapolated to the "
+                       f"GPU's median iteration count {gpu_iters_median:.0f}; sketches are bit-identical"),
+            "s_per_iter": per_iter}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="sparse_count", choices=sorted(WORKLOADS))
+    ap.add_argument("--lookahead", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-s", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver is single-GPU.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2105_05565_amd import rs
+
+    wl = WORKLOADS[args.workload]
+    torch.cuda.set_device(0)
+    print(f"[bench] generating {wl['name']}", file=sys.stderr, flush=True)
+    p = make_problem(wl)
+    n, d = p.X.shape
+    if wl["kind"] == "csr":
+        X = (torch.from_numpy(p.X.indptr.astype(np.int64)).cuda(),
+             torch.from_numpy(p.X.indices.astype(np.int32)).cuda(),
+             torch.from_numpy(p.X.data).cuda(), (n, d))
+        nnz = int(p.X.nnz)
+    else:
+        X = torch.from_numpy(p.X).cuda()
+        nnz = n * d
+    y = torch.from_numpy(p.y).cuda()
+    stream = torch.cuda.current_stream().cuda_stream
+    torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    S = rs.Solver(X, y, p.lam, tau=wl["tau"], sketch=wl["sketch"], form="primal", momentum="heuristic",
+                  subcount_k=wl["sub_k"], tol=1e-6, max_iter=200000, seed=1,
+                  lookahead=args.lookahead, profile=1, stream=stream)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    m, K = d, n
+    nsel = {"count": m, "subcount": wl["tau"] * max(wl["sub_k"], 1), "subsample": wl["tau"]}[wl["sketch"]]
+
+    for w in range(args.warmup):
+        S.reset(10000 + w)
+        S.solve()
+        print(f"[bench] warmup {w} done: {S.k} iterations", file=sys.stderr, flush=True)
+    S.profile(clear=True)
+
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    times, iters = [], []
+    for i in range(args.steps):
+        ti = time.perf_counter()
+        S.reset(i + 1)
+        _, st, rep = S.solve()
+        times.append(time.perf_counter() - ti)
+        iters.append(rep.iters)
+        if st != rs.RS_OK:
+            print(f"[bench] step {i} did not converge: {rep.rel_res:.3e}", file=sys.stderr, flush=True)
+        print(f"[bench] step {i}: {rep.iters} iterations, {times[-1]*1e3:.1f} ms", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    prof = S.profile()
+    S.close()
+
+    # one more solve, untimed, with every launch bracketed by events (per-launch breakdown)
+    S2 = rs.Solver(X, y, p.lam, tau=wl["tau"], sketch=wl["sketch"], form="primal", momentum="heuristic",
+                   subcount_k=wl["sub_k"], tol=1e-6, max_iter=200000, seed=1,
+                   lookahead=args.lookahead, profile=2, stream=stream)
+    S2.solve()
+    prof2 = S2.profile()
+    S2.close()
+
+    T = total / args.steps
+    tot_iters = sum(iters)
+    kernels = {}
+    for cls, v in prof.items():
+        if v["launches"] == 0:
+            continue
+        b = algorithmic_bytes(cls, wl, n, d, nnz, m, K, wl["tau"], nsel) * v["slots"] / v["launches"]
+        avg_ms = v["ms"] / v["launches"]
+        kernels[cls] = {"total_ms": round(v["ms"], 3), "launches": v["launches"],
+                        "slots_per_launch": round(v["slots"] / v["launches"], 2),
+                        "avg_ms": round(avg_ms, 5), "alg_bytes_per_launch": int(b),
+                        "gbs": round(b / (avg_ms * 1e-3) / 1e9, 1) if avg_ms > 0 else None,
+                        "share_of_timed": round(v["ms"] / (total * 1e3), 4)}
+    dom = max(kernels, key=lambda c: kernels[c]["total_ms"])
+    kd = kernels[dom]
+    achieved = kd["gbs"]
+    roofline = {"kernel": {"as": "k_as_sparse_bucket" if wl["kind"] == "csr" else "k_as_dense_f64",
+                           "update": "k_update", "chol": "k_chol_inverse", "delta": "k_delta",
+                           "iters": "k_delta+k_update sequence",
+                           "sketch": "k_sketch_count" if wl["sketch"] == "count" else "k_sketch_select"}[dom],
+                "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None, "traffic": None,
+                "alg_bytes_per_launch": kd["alg_bytes_per_launch"], "avg_launch_ms": kd["avg_ms"]}
+    traffic_file = os.path.join(ROOT, "profiles", f"traffic_{roofline['kernel']}_{args.workload}.json")
+    if os.path.exists(traffic_file):
+        tf = json.load(open(traffic_file))
+        src = {"k_as_sparse_bucket": ["k_sparse.hip"], "k_update": ["k_update.hip"],
+               "k_as_dense_f64": ["k_dense.hip"]}.get(roofline["kernel"], [])
+        if src and tf.get("source_sha") == kernel_source_sha(src):
+            roofline["traffic"] = tf["hbm_bytes_per_launch_scaled"] * kd["slots_per_launch"] / tf["slots_per_launch"]
+
+    out = {
+        "metric": "time-to-rel-residual 1e-6", "value": round(T, 6), "unit": "s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(T * 1e3, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl["name"], "n": n, "d": d, "nnz": nnz, "form": "primal",
+                   "sketch": wl["sketch"], "tau": wl["tau"], "subcount_k": wl["sub_k"],
+                   "lambda": p.lam, "momentum": "heuristic", "tol": 1e-6, "precision": "fp64"},
+        "iters_per_s": round(tot_iters / total, 1),
+        "iters_median": statistics.median(iters),
+        "time_s_quartiles": [round(q, 6) for q in statistics.quantiles(times, n=4)] if len(times) > 1 else times,
+        "setup_s": round(setup_s, 4),
+        "roofline": roofline,
+        "kernels": kernels,
+        "kernels_per_launch_untimed": {c: {"avg_ms": round(v["ms"] / v["launches"], 5),
+                                           "launches": v["launches"]}
+                                       for c, v in prof2.items() if v["launches"]},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        cb = cpu_baseline(p, wl, statistics.median(iters), args.cpu_sample_s)
+        cb.pop("s_per_iter")
+        out["cpu_baseline"] = cb
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -98,6 +98,7 @@ typedef struct rs_options {
   uint64_t problem_id;      /* Philox key word 1 */
   int32_t refresh_every;    /* mixed precision: FP64 recomputation of r every R iterations (default 20) */
   int32_t lookahead;        /* sketches drawn and factorised ahead per batch; 0 = library choice */
+  int32_t profile;          /* 0: off; 1: batch-level HIP-event timing; 2: every launch (rs_get_profile) */
   void* stream;             /* hipStream_t for all work; NULL = the default stream */
 } rs_options;
 
@@ -106,6 +107,20 @@ typedef struct rs_report {
   double rel_res;           /* ||r^iters|| / ||r^0|| of the tracked residual */
   double seconds;           /* wall time of the solve on the stream */
 } rs_report;
+
+/* Per-kernel timing collected with HIP events on the solver's stream (indices
+ * RS_PROF_*). rs_options.profile = 1 times each batch-level launch (sketch, AS,
+ * Cholesky) and the whole per-iteration sequence of a batch (RS_PROF_ITERS);
+ * profile = 2 also times every per-iteration launch (delta, update), which adds
+ * event packets between them. `launches` counts timed launches (or sequences),
+ * `slots` the sketches (iterations) they processed. */
+enum { RS_PROF_SKETCH = 0, RS_PROF_AS = 1, RS_PROF_CHOL = 2, RS_PROF_DELTA = 3, RS_PROF_UPDATE = 4,
+       RS_PROF_REFRESH = 5, RS_PROF_ITERS = 6, RS_PROF_COUNT = 8 };
+typedef struct rs_profile {
+  double ms[RS_PROF_COUNT];
+  int64_t launches[RS_PROF_COUNT];
+  int64_t slots[RS_PROF_COUNT];
+} rs_profile;
 
 typedef struct rs_handle rs_handle;
 
@@ -129,6 +144,14 @@ rs_status rs_step(rs_handle* h, int64_t iters, double* rel_res_out);
  * ridge weights w (d values; dual form maps alpha through X^T). rep (host,
  * may be NULL) gets the report. Returns RS_NOT_CONVERGED if max_iter hit. */
 rs_status rs_solve(rs_handle* h, double* w_out, rs_report* rep);
+
+/* Restart from x^0 = x^{-1} = 0, r^0 = r^{-1} = -b with a new sketch seed,
+ * keeping the device layouts built by rs_create (k returns to 0). */
+rs_status rs_reset(rs_handle* h, uint64_t seed);
+
+/* Accumulated per-kernel timings since rs_create or the last call with
+ * clear != 0 (which zeroes them after copying). Needs rs_options.profile. */
+rs_status rs_get_profile(rs_handle* h, rs_profile* out, int32_t clear);
 
 /* Current iteration count k. */
 int64_t rs_iteration(const rs_handle* h);

@@ -8,86 +8,114 @@
 //
 // A column of S that is zero (an empty count bucket) makes the matching row and
 // column of G zero and rho_b = 0; the diagonal entry is set to 1 so that delta_b = 0,
-// which equals the pseudo-inverse solution. Padding to a multiple of 32 is the
+// which equals the pseudo-inverse solution. Padding to a multiple of 64 is the
 // identity as well.
 //
-// Blocked algorithm on 32 x 32 tiles staged in LDS (256 threads, each owning a
-// 1 x 4 strip of a tile):
-//   1. right-looking Cholesky: factor diagonal tile, panel solve, trailing update;
-//   2. W = L^{-1}: inverted diagonal tiles, W_ij = -W_ii sum_{k=j}^{i-1} L_ik W_kj;
-//   3. G^{-1} = W^T W, written to both triangles.
+// Blocked algorithm on 64 x 64 tiles (4 waves, FP64 MFMA 16x16x4 for tile products,
+// operands staged in LDS), with U = L^{-T} (upper triangular) kept instead of L^{-1}
+// so that every tile product reads its operands row-major:
+//   1. right-looking Cholesky: factor the diagonal tile and invert it in LDS,
+//      panel L_ik = G_ik U_kk, trailing update G_ij -= L_ik L_jk^T;
+//   2. U_ji = -(sum_{k=j}^{i-1} U_jk L_ik^T) U_ii for i > j  (U = (L^{-1})^T);
+//   3. G^{-1} = U U^T, tile (i, j) = sum_{k >= max(i,j)} U_ik U_jk^T, both triangles.
 #include "dev_common.h"
 #include "rs_internal.h"
 
 namespace rs {
 namespace {
 
-constexpr int NB = 32;
+constexpr int NB = 64;
+constexpr int LDT = NB + 1;  // LDS row stride (odd: fewer bank conflicts)
 constexpr int kThreads = 256;
 
-struct CholLds {
-  double a[NB][NB + 1];
-  double b[NB][NB + 1];
-  double d[NB][NB + 1];
-  int bad;
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+struct Acc {
+  d4v v[2][2];
 };
 
-__device__ __forceinline__ void load_tile(double (*dst)[NB + 1], const double* src, int64_t ld,
-                                          bool trans) {
+__device__ __forceinline__ void acc_zero(Acc& c) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) c.v[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
+}
+
+// dst[r][c] = src[r * ld + c]  (trans: src[c * ld + r]) for a 64 x 64 tile.
+__device__ __forceinline__ void load_tile(double* dst, const double* src, int64_t ld, bool trans) {
   for (int e = threadIdx.x; e < NB * NB; e += kThreads) {
-    const int r = e >> 5, c = e & 31;
-    dst[r][c] = trans ? src[(int64_t)c * ld + r] : src[(int64_t)r * ld + c];
+    const int r = e >> 6, c = e & 63;
+    dst[r * LDT + c] = trans ? src[(int64_t)c * ld + r] : src[(int64_t)r * ld + c];
   }
 }
 
-// acc (this thread's 1 x 4 strip) += A * B with A, B in LDS.
-__device__ __forceinline__ void tile_fma(double acc[4], double (*A)[NB + 1], double (*B)[NB + 1]) {
-  const int r = threadIdx.x >> 3, c4 = (threadIdx.x & 7) * 4;
-#pragma unroll 8
-  for (int k = 0; k < NB; ++k) {
-    const double av = A[r][k];
+// C += A * B^T with A = a[r][k], B = b[c][k] (both 64 x 64 in LDS), K = 64.
+// Wave w owns rows 32 (w / 2) .. +32 and columns 32 (w % 2) .. +32 of C.
+__device__ __forceinline__ void tile_mma(Acc& c, const double* a, const double* b) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int l16 = lane & 15, lk = lane >> 4;
+#pragma unroll 4
+  for (int k4 = 0; k4 < NB; k4 += 4) {
+    double av[2], bv[2];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] += av * B[k][c4 + q];
+    for (int i = 0; i < 2; ++i) av[i] = a[(wr + i * 16 + l16) * LDT + k4 + lk];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) bv[j] = b[(wc + j * 16 + l16) * LDT + k4 + lk];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        c.v[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], c.v[i][j], 0, 0, 0);
   }
 }
 
-__device__ __forceinline__ void store_strip(double* dst, int64_t ld, const double acc[4]) {
-  const int r = threadIdx.x >> 3, c4 = (threadIdx.x & 7) * 4;
+// Visit the accumulator elements: f(row, col, value) with (row, col) inside the tile.
+// 16x16x4 FP64 MFMA result layout: lane l, element v -> row 4 v + l / 16, column l % 16.
+template <class F>
+__device__ __forceinline__ void acc_for_each(const Acc& c, F f) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) dst[(int64_t)r * ld + c4 + q] = acc[q];
-}
-
-__device__ __forceinline__ void add_strip(double* dst, int64_t ld, const double acc[4], double alpha) {
-  const int r = threadIdx.x >> 3, c4 = (threadIdx.x & 7) * 4;
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-  for (int q = 0; q < 4; ++q) dst[(int64_t)r * ld + c4 + q] += alpha * acc[q];
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        f(wr + i * 16 + 4 * v + (lane >> 4), wc + j * 16 + (lane & 15), c.v[i][j][v]);
 }
 
 __global__ __launch_bounds__(kThreads) void k_chol_inverse(double* __restrict__ Gall,
-                                                           double* __restrict__ Wall, int64_t ldg,
+                                                           double* __restrict__ Uall, int64_t ldg,
                                                            int32_t tau, int32_t kind,
-                                                           const double* __restrict__ ASall, int64_t m,
+                                                           const double* __restrict__ ASall,
+                                                           int64_t ldas, int64_t m,
                                                            const int32_t* __restrict__ members_all,
                                                            const int32_t* __restrict__ offs_all,
                                                            int32_t* __restrict__ status,
                                                            const int32_t* __restrict__ done) {
-  __shared__ CholLds S;
+  extern __shared__ __align__(16) double lds[];
+  double* ta = lds;                  // [64][65]
+  double* tb = lds + NB * LDT;       // [64][65]
+  double* td = lds + 2 * NB * LDT;   // [64][65]
+  double* col = lds + 3 * NB * LDT;  // [64]
+  __shared__ int bad;
   if (*done) return;
   const int tid = threadIdx.x;
   const int64_t slot = blockIdx.x;
   double* G = Gall + slot * ldg * ldg;
-  double* W = Wall + slot * ldg * ldg;
+  double* U = Uall + slot * ldg * ldg;
   const int32_t* offs = offs_all + slot * (tau + 1);
   const int nt = (int)(ldg / NB);
-  if (tid == 0) S.bad = 0;
+  if (tid == 0) bad = 0;
 
   // Phase 0: assemble G (subsample: rows C of AS), padding and empty buckets.
   if (kind == kSubsample) {
     const int32_t* members = members_all + slot * tau;
-    const double* AS = ASall + slot * m * tau;
+    const double* AS = ASall + slot * m * ldas;
     for (int64_t e = tid; e < (int64_t)tau * tau; e += kThreads) {
       const int64_t c = e / tau, cc = e % tau;
-      G[c * ldg + cc] = AS[(int64_t)members[c] * tau + cc];
+      G[c * ldg + cc] = AS[(int64_t)members[c] * ldas + cc];
     }
   }
   for (int64_t e = tid; e < ldg * ldg; e += kThreads) {
@@ -101,139 +129,137 @@ __global__ __launch_bounds__(kThreads) void k_chol_inverse(double* __restrict__ 
   }
   __syncthreads();
 
-  // Phase 1: Cholesky, lower triangle in place.
+  // Phase 1: Cholesky (lower triangle of G in place) and U_kk = L_kk^{-T}.
   for (int kt = 0; kt < nt; ++kt) {
     double* Gkk = G + (int64_t)kt * NB * ldg + kt * NB;
-    load_tile(S.d, Gkk, ldg, false);
+    load_tile(td, Gkk, ldg, false);
     __syncthreads();
     for (int c = 0; c < NB; ++c) {
-      if (tid == 0) {
-        double piv = S.d[c][c];
+      if (tid < NB) {
+        double piv = td[c * LDT + c];
         if (!(piv > 0.0) || !(piv < INFINITY)) {
-          S.bad = 1;
+          if (tid == c) bad = 1;
           piv = 1.0;
         }
-        S.d[c][c] = sqrt(piv);
+        const double sq = sqrt(piv);
+        col[tid] = (tid == c) ? sq : (tid > c ? td[tid * LDT + c] / sq : 0.0);
       }
-      __syncthreads();
-      if (tid > c && tid < NB) S.d[tid][c] /= S.d[c][c];
       __syncthreads();
       for (int e = tid; e < NB * NB; e += kThreads) {
-        const int r = e >> 5, cc = e & 31;
-        if (cc > c && r >= cc) S.d[r][cc] -= S.d[r][c] * S.d[cc][c];
+        const int r = e >> 6, cc = e & 63;
+        if (cc == c && r >= c) td[r * LDT + c] = col[r];
+        else if (cc > c && r >= cc) td[r * LDT + cc] -= col[r] * col[cc];
       }
       __syncthreads();
     }
-    // zero the strict upper part; invert the diagonal tile into S.a (one column per thread)
-    for (int e = tid; e < NB * NB; e += kThreads) {
-      const int r = e >> 5, c = e & 31;
-      if (c > r) S.d[r][c] = 0.0;
-    }
-    __syncthreads();
+    // X = L_kk^{-1} row by row (row i needs rows < i): thread j owns column j, ta[i][j] = X[i][j]
     if (tid < NB) {
       const int j = tid;
       for (int i = 0; i < NB; ++i) {
         double s = (i == j) ? 1.0 : 0.0;
-        for (int t = j; t < i; ++t) s -= S.d[i][t] * S.a[t][j];
-        S.a[i][j] = (i >= j) ? s / S.d[i][i] : 0.0;
+        for (int t = j; t < i; ++t) s -= td[i * LDT + t] * ta[t * LDT + j];
+        ta[i * LDT + j] = (i >= j) ? s / td[i * LDT + i] : 0.0;
       }
     }
     __syncthreads();
+    // write L_kk (upper part zero) and U_kk = X^T; tb[c][k] = U_kk[k][c] = X[c][k] for the panel
+    double* Ukk = U + (int64_t)kt * NB * ldg + kt * NB;
     for (int e = tid; e < NB * NB; e += kThreads) {
-      const int r = e >> 5, c = e & 31;
-      Gkk[(int64_t)r * ldg + c] = S.d[r][c];
-      W[((int64_t)kt * NB + r) * ldg + kt * NB + c] = S.a[r][c];
+      const int r = e >> 6, c = e & 63;
+      Gkk[(int64_t)r * ldg + c] = (c <= r) ? td[r * LDT + c] : 0.0;
+      Ukk[(int64_t)r * ldg + c] = ta[c * LDT + r];
+      tb[r * LDT + c] = ta[r * LDT + c];
     }
     __syncthreads();
-    // panel: L_ik = G_ik * (L_kk^{-1})^T
-    for (int e = tid; e < NB * NB; e += kThreads) {
-      const int r = e >> 5, c = e & 31;
-      S.b[r][c] = S.a[c][r];
-    }
-    __syncthreads();
+    // panel: L_ik = G_ik U_kk
     for (int it = kt + 1; it < nt; ++it) {
       double* Gik = G + (int64_t)it * NB * ldg + kt * NB;
-      load_tile(S.a, Gik, ldg, false);
+      load_tile(ta, Gik, ldg, false);
       __syncthreads();
-      double acc[4] = {0.0, 0.0, 0.0, 0.0};
-      tile_fma(acc, S.a, S.b);
+      Acc c;
+      acc_zero(c);
+      tile_mma(c, ta, tb);
       __syncthreads();
-      store_strip(Gik, ldg, acc);
+      acc_for_each(c, [&](int r, int cc, double v) { Gik[(int64_t)r * ldg + cc] = v; });
       __syncthreads();
     }
     // trailing update: G_ij -= L_ik L_jk^T for kt < jt <= it
     for (int jt = kt + 1; jt < nt; ++jt) {
-      load_tile(S.b, G + (int64_t)jt * NB * ldg + kt * NB, ldg, true);
+      load_tile(tb, G + (int64_t)jt * NB * ldg + kt * NB, ldg, false);  // tb[c][k] = L_jk[c][k]
       for (int it = jt; it < nt; ++it) {
-        load_tile(S.a, G + (int64_t)it * NB * ldg + kt * NB, ldg, false);
+        load_tile(ta, G + (int64_t)it * NB * ldg + kt * NB, ldg, false);
         __syncthreads();
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        tile_fma(acc, S.a, S.b);
-        add_strip(G + (int64_t)it * NB * ldg + jt * NB, ldg, acc, -1.0);
+        Acc c;
+        acc_zero(c);
+        tile_mma(c, ta, tb);
+        double* Gij = G + (int64_t)it * NB * ldg + jt * NB;
+        acc_for_each(c, [&](int r, int cc, double v) { Gij[(int64_t)r * ldg + cc] -= v; });
         __syncthreads();
       }
     }
   }
 
-  // Phase 2: W = L^{-1} below the diagonal tiles (diagonal tiles were stored above).
+  // Phase 2: U_ji = -(sum_{k=j}^{i-1} U_jk L_ik^T) U_ii for i > j.
   for (int jt = 0; jt < nt; ++jt) {
     for (int it = jt + 1; it < nt; ++it) {
-      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      Acc c;
+      acc_zero(c);
       for (int kt = jt; kt < it; ++kt) {
-        load_tile(S.a, G + (int64_t)it * NB * ldg + kt * NB, ldg, false);  // L_ik
-        load_tile(S.b, W + (int64_t)kt * NB * ldg + jt * NB, ldg, false);  // W_kj
+        load_tile(ta, U + (int64_t)jt * NB * ldg + kt * NB, ldg, false);  // ta = U_jk
+        load_tile(tb, G + (int64_t)it * NB * ldg + kt * NB, ldg, false);  // tb[c][k] = L_ik[c][k]
         __syncthreads();
-        tile_fma(acc, S.a, S.b);
+        tile_mma(c, ta, tb);
         __syncthreads();
       }
-      {
-        const int r = tid >> 3, c4 = (tid & 7) * 4;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) S.d[r][c4 + q] = acc[q];
-      }
-      load_tile(S.a, W + (int64_t)it * NB * ldg + it * NB, ldg, false);  // W_ii
+      acc_for_each(c, [&](int r, int cc, double v) { ta[r * LDT + cc] = v; });
+      load_tile(tb, U + (int64_t)it * NB * ldg + it * NB, ldg, true);  // tb[c][k] = U_ii[k][c]
       __syncthreads();
-      double out[4] = {0.0, 0.0, 0.0, 0.0};
-      tile_fma(out, S.a, S.d);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) out[q] = -out[q];
-      store_strip(W + (int64_t)it * NB * ldg + jt * NB, ldg, out);
+      Acc o;
+      acc_zero(o);
+      tile_mma(o, ta, tb);
+      double* Uji = U + (int64_t)jt * NB * ldg + it * NB;
+      acc_for_each(o, [&](int r, int cc, double v) { Uji[(int64_t)r * ldg + cc] = -v; });
       __syncthreads();
     }
   }
 
-  // Phase 3: G^{-1} = W^T W (both triangles of G).
+  // Phase 3: G^{-1} = U U^T, tile (i, j) = sum_{k >= i} U_ik U_jk^T for i >= j.
   for (int it = 0; it < nt; ++it) {
     for (int jt = 0; jt <= it; ++jt) {
-      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      Acc c;
+      acc_zero(c);
       for (int kt = it; kt < nt; ++kt) {
-        load_tile(S.a, W + (int64_t)kt * NB * ldg + it * NB, ldg, true);   // W_ki^T
-        load_tile(S.b, W + (int64_t)kt * NB * ldg + jt * NB, ldg, false);  // W_kj
+        load_tile(ta, U + (int64_t)it * NB * ldg + kt * NB, ldg, false);  // ta = U_ik
+        load_tile(tb, U + (int64_t)jt * NB * ldg + kt * NB, ldg, false);  // tb[c][k] = U_jk[c][k]
         __syncthreads();
-        tile_fma(acc, S.a, S.b);
+        tile_mma(c, ta, tb);
         __syncthreads();
       }
-      const int r = tid >> 3, c4 = (tid & 7) * 4;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        G[((int64_t)it * NB + r) * ldg + jt * NB + c4 + q] = acc[q];
-        if (jt != it) G[((int64_t)jt * NB + c4 + q) * ldg + it * NB + r] = acc[q];
-      }
+      double* Gij = G + (int64_t)it * NB * ldg + jt * NB;
+      double* Gji = G + (int64_t)jt * NB * ldg + it * NB;
+      acc_for_each(c, [&](int r, int cc, double v) {
+        Gij[(int64_t)r * ldg + cc] = v;
+        if (jt != it) Gji[(int64_t)cc * ldg + r] = v;
+      });
       __syncthreads();
     }
   }
-  if (tid == 0) status[slot] = S.bad;
+  if (tid == 0) status[slot] = bad;
 }
 
 }  // namespace
 
 hipError_t launch_chol_inverse(double* G, double* W, int64_t ldg, int32_t tau, int32_t nslots,
-                               int32_t kind, const double* AS, int64_t m, const int32_t* members,
-                               const int32_t* offs, int32_t* status, const int32_t* done,
-                               hipStream_t s) {
+                               int32_t kind, const double* AS, int64_t ldas, int64_t m,
+                               const int32_t* members, const int32_t* offs, int32_t* status,
+                               const int32_t* done, hipStream_t s) {
   if (ldg % NB != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_chol_inverse, dim3(nslots), dim3(kThreads), 0, s, G, W, ldg, tau, kind, AS,
-                     m, members, offs, status, done);
+  const size_t bytes = sizeof(double) * (3 * NB * LDT + NB);
+  hipError_t e = hipFuncSetAttribute((const void*)k_chol_inverse,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_chol_inverse, dim3(nslots), dim3(kThreads), bytes, s, G, W, ldg, tau, kind, AS,
+                     ldas, m, members, offs, status, done);
   return hipGetLastError();
 }
 

@@ -17,7 +17,8 @@ constexpr int kTM = 64, kTN = 64, kTK = 16;
 __global__ __launch_bounds__(256) void k_as_dense_f64(const double* __restrict__ Z, int64_t ldz,
                                                       int64_t m, int64_t K,
                                                       const int32_t* __restrict__ members,
-                                                      int32_t tau, int32_t nslots, double lam,
+                                                      int32_t tau, int64_t ldas, int32_t nslots,
+                                                      double lam,
                                                       double* __restrict__ AS,
                                                       const int32_t* __restrict__ done) {
   __shared__ double As[kTM][kTK + 1];
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(256) void k_as_dense_f64(const double* __restrict__
           const int64_t slot = n / tau, c = n % tau;
           double val = acc[i][j][v];
           if (row == brow[col]) val += lam;
-          AS[(slot * m + row) * tau + c] = val;
+          AS[(slot * m + row) * ldas + c] = val;
         }
       }
 }
@@ -108,13 +109,11 @@ __global__ void k_transpose_to_f64(const void* __restrict__ src, int32_t is_f32,
 
 __global__ void k_copy_to_f64(const void* __restrict__ src, int32_t is_f32, int64_t rows,
                               int64_t cols, int64_t lds, double* __restrict__ dst, int64_t ldd) {
-  const int64_t r = blockIdx.y;
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cols;
-       c += (int64_t)gridDim.x * blockDim.x) {
-    dst[r * ldd + c] =
-        is_f32 ? (double)((const float*)src)[r * lds + c] : ((const double*)src)[r * lds + c];
-  }
-  (void)rows;
+  for (int64_t r = blockIdx.y; r < rows; r += gridDim.y)
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cols;
+         c += (int64_t)gridDim.x * blockDim.x)
+      dst[r * ldd + c] =
+          is_f32 ? (double)((const float*)src)[r * lds + c] : ((const double*)src)[r * lds + c];
 }
 
 // out[j] = sum_k Z[j][k] v[k]: one wave per row, fixed-order reduction.
@@ -148,12 +147,12 @@ __global__ void k_vec_to_f64(const void* __restrict__ src, int32_t is_f32, int64
 }  // namespace
 
 hipError_t launch_as_dense_f64(const double* Z, int64_t ldz, int64_t m, int64_t K,
-                               const int32_t* members, int32_t tau, int32_t nslots, double lam,
-                               double* AS, const int32_t* done, hipStream_t s) {
+                               const int32_t* members, int32_t tau, int64_t ldas, int32_t nslots,
+                               double lam, double* AS, const int32_t* done, hipStream_t s) {
   const int64_t ntot = (int64_t)nslots * tau;
   dim3 grid((unsigned)((m + kTM - 1) / kTM), (unsigned)((ntot + kTN - 1) / kTN));
-  hipLaunchKernelGGL(k_as_dense_f64, grid, dim3(256), 0, s, Z, ldz, m, K, members, tau, nslots,
-                     lam, AS, done);
+  hipLaunchKernelGGL(k_as_dense_f64, grid, dim3(256), 0, s, Z, ldz, m, K, members, tau, ldas,
+                     nslots, lam, AS, done);
   return hipGetLastError();
 }
 
@@ -170,7 +169,7 @@ hipError_t launch_copy_to_f64(const void* src, int32_t src_is_f32, int64_t rows,
   if (rows == 0) return hipSuccess;
   unsigned gx = (unsigned)((cols + 255) / 256);
   if (gx > 64) gx = 64;
-  dim3 grid(gx, (unsigned)rows);
+  dim3 grid(gx, (unsigned)(rows < 65535 ? rows : 65535));
   hipLaunchKernelGGL(k_copy_to_f64, grid, dim3(256), 0, s, src, src_is_f32, rows, cols, lds, dst,
                      ldd);
   return hipGetLastError();

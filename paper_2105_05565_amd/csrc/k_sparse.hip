@@ -6,13 +6,22 @@
 //   T[i, :]  = sum_{j' in row i of Z^T} s_j' Z_j'i e_{h(j')}          (T = Z^T S),
 //
 // where h(j) is the bucket (column of S) holding coordinate j and s_j its sign.
-// Each row of AS is built by one wavefront as a signed scatter-add of CSR entries
-// into tau bucket accumulators staged in LDS. Buckets are processed by one
-// workgroup each, so the sketched matrix G = S^T A S, whose row b is
-// sum_{j in bucket b} s_j AS[j, :], is accumulated in registers alongside the rows
-// (no global atomics; fixed reduction order). For SubCount the coordinates outside
-// the sketch still need their rows of AS; a second kernel builds those rows.
+// Per sketch, one streaming pass stores T entry by entry, aligned with CSR(Z^T), as
+// (bucket, signed value). Each row of AS is then built by one wavefront as a signed
+// scatter-add of Z_ji T[i, :] into tau bucket accumulators staged in LDS; the wave
+// splits into 16-lane groups that each walk one row of T (coalesced segments).
+// Buckets are processed by one workgroup each, so G = S^T A S,
+// whose row b is sum_{j in bucket b} s_j AS[j, :], is accumulated alongside the
+// rows in LDS (no global atomics; fixed reduction order across waves). For SubCount
+// the coordinates outside the sketch still need their rows of AS; a second kernel
+// builds those rows.
+//
+// CSR values are held in the input precision (FP32 inputs stay FP32: exactly
+// representable, and their pairwise products are exact in FP64); every product and
+// sum is formed in FP64.
 #include <hipcub/hipcub.hpp>
+
+#include <algorithm>
 
 #include "dev_common.h"
 #include "rs_internal.h"
@@ -20,49 +29,108 @@
 namespace rs {
 namespace {
 
-constexpr int kWaves = 4;
-constexpr int kMaxTauChunks = 32;  // tau <= 2048
+constexpr int kWaves = 8;
 
-// One wavefront: acc[0 .. tau) <- row j of AS (acc is this wave's LDS slice).
-__device__ __forceinline__ void scatter_row(int64_t j, const int64_t* __restrict__ zr_ptr,
-                                            const int32_t* __restrict__ zr_col,
-                                            const double* __restrict__ zr_val,
-                                            const int64_t* __restrict__ zt_ptr,
-                                            const int32_t* __restrict__ zt_col,
-                                            const double* __restrict__ zt_val,
-                                            const int32_t* __restrict__ hmap, int32_t tau,
-                                            double lam, double* acc, int lane) {
-  for (int c = lane; c < tau; c += 64) acc[c] = 0.0;
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  const int64_t p0 = zr_ptr[j], p1 = zr_ptr[j + 1];
-  for (int64_t p = p0 + lane; p < p1; p += 64) {
-    const int64_t i = zr_col[p];
-    const double zv = zr_val[p];
-    const int64_t q0 = zt_ptr[i], q1 = zt_ptr[i + 1];
-    for (int64_t q = q0; q < q1; ++q) {
-      const int code = hmap[zt_col[q]];
-      if (code >= 0) {
-        double v = zv * zt_val[q];
-        if (code & 1) v = -v;
-        atomicAdd(&acc[code >> 1], v);
-      }
-    }
+// Entry of T = Z^T S aligned with CSR(Z^T): bucket code of the column (-1: outside the
+// sketch) and the signed value s_j' Z_j'i.
+template <typename V>
+struct TEntry;
+template <>
+struct __align__(8) TEntry<float> {
+  int32_t code;
+  float val;
+};
+template <>
+struct __align__(16) TEntry<double> {
+  int64_t code;
+  double val;
+};
+
+// T[slot][q] for every entry q of CSR(Z^T): one pass per sketch, coalesced apart from
+// the bucket-map lookup.
+template <typename V>
+__global__ void k_build_t(const int32_t* __restrict__ zt_col, const V* __restrict__ zt_val,
+                          int64_t nnz, const int32_t* __restrict__ hmap_all, int64_t m,
+                          TEntry<V>* __restrict__ T, const int32_t* __restrict__ done) {
+  if (*done) return;
+  const int64_t slot = blockIdx.y;
+  const int32_t* hmap = hmap_all + slot * m;
+  TEntry<V>* t = T + slot * nnz;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnz;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int code = hmap[zt_col[q]];
+    const V v = zt_val[q];
+    TEntry<V> e;
+    e.code = code < 0 ? -1 : (code >> 1);
+    e.val = (code & 1) ? -v : v;
+    t[q] = e;
   }
-  const int cj = hmap[j];
-  if (lane == 0 && cj >= 0) atomicAdd(&acc[cj >> 1], (cj & 1) ? -lam : lam);
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+struct RowLds {  // per-wave staging of one chunk (<= 64 entries) of row j of Z
+  int64_t q0[64];
+  int32_t len[64];
+  double zv[64];
+};
+
+// One wavefront: acc[0 .. tau) <- row j of AS. The wave splits into four 16-lane
+// groups; group g walks entries p = g, g + 4, ... of the current chunk of row j and
+// its lanes stride over the matching row of Z^T (coalesced 16-entry segments).
+template <typename V>
+__device__ __forceinline__ void scatter_row(int64_t j, const int64_t* __restrict__ zr_ptr,
+                                            const int32_t* __restrict__ zr_col,
+                                            const V* __restrict__ zr_val,
+                                            const int64_t* __restrict__ zt_ptr,
+                                            const TEntry<V>* __restrict__ T, int code_j, int32_t tau,
+                                            double lam, double* acc, RowLds* rl, int lane) {
+  for (int c = lane; c < tau; c += 64) acc[c] = 0.0;
+  const int grp = lane >> 4, sub = lane & 15;
+  const int64_t p0 = zr_ptr[j], p1 = zr_ptr[j + 1];
+  for (int64_t pb = p0; pb < p1; pb += 64) {
+    const int64_t p = pb + lane;
+    const int cnt = (int)min<int64_t>(64, p1 - pb);
+    if (p < p1) {
+      const int64_t i = zr_col[p];
+      const int64_t q0 = zt_ptr[i];
+      rl->q0[lane] = q0;
+      rl->len[lane] = (int)(zt_ptr[i + 1] - q0);
+      rl->zv[lane] = (double)zr_val[p];
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    for (int e = grp; e < cnt; e += 4) {
+      const int64_t q0 = rl->q0[e];
+      const int len = rl->len[e];
+      const double zv = rl->zv[e];
+      for (int t = sub; t < len; t += 32) {
+        const TEntry<V> a = T[q0 + t];
+        const bool two = t + 16 < len;
+        TEntry<V> b;
+        if (two) b = T[q0 + t + 16];
+        if (a.code >= 0) atomicAdd(&acc[a.code], zv * (double)a.val);
+        if (two && b.code >= 0) atomicAdd(&acc[b.code], zv * (double)b.val);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  }
+  if (lane == 0 && code_j >= 0) atomicAdd(&acc[code_j >> 1], (code_j & 1) ? -lam : lam);
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+}
+
+// One workgroup per bucket b of a sketch: its member rows of AS and row b of G.
+// NCH = number of 64-column chunks of tau held per lane for the G partial sums.
+template <typename V, int NCH>
 __global__ __launch_bounds__(kWaves * 64) void k_as_sparse_bucket(
     const int64_t* __restrict__ zr_ptr, const int32_t* __restrict__ zr_col,
-    const double* __restrict__ zr_val, const int64_t* __restrict__ zt_ptr,
-    const int32_t* __restrict__ zt_col, const double* __restrict__ zt_val, int64_t m, int32_t tau,
+    const V* __restrict__ zr_val, const int64_t* __restrict__ zt_ptr,
+    const TEntry<V>* __restrict__ T_all, int64_t nnz, int64_t m, int32_t tau, int64_t ldas,
     double lam, const int32_t* __restrict__ hmap_all, const int32_t* __restrict__ members_all,
     const int32_t* __restrict__ offs_all, int64_t nsel, double* __restrict__ AS,
     double* __restrict__ G, int64_t ldg, const int32_t* __restrict__ done) {
-  extern __shared__ __align__(16) double lds[];  // [kWaves][tau]
+  extern __shared__ __align__(16) double lds[];  // acc [kWaves][tau]
+  __shared__ RowLds rls[kWaves];
   if (*done) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int b = blockIdx.x;
@@ -70,19 +138,21 @@ __global__ __launch_bounds__(kWaves * 64) void k_as_sparse_bucket(
   const int32_t* hmap = hmap_all + slot * m;
   const int32_t* members = members_all + slot * nsel;
   const int32_t* offs = offs_all + slot * (tau + 1);
+  const TEntry<V>* T = T_all + slot * nnz;
   double* acc = lds + wave * tau;
-  double gp[kMaxTauChunks];
+  double gp[NCH];
 #pragma unroll
-  for (int t = 0; t < kMaxTauChunks; ++t) gp[t] = 0.0;
+  for (int t = 0; t < NCH; ++t) gp[t] = 0.0;
 
   const int p0 = offs[b], p1 = offs[b + 1];
   for (int p = p0 + wave; p < p1; p += kWaves) {
     const int64_t j = members[p];
-    scatter_row(j, zr_ptr, zr_col, zr_val, zt_ptr, zt_col, zt_val, hmap, tau, lam, acc, lane);
-    const double sj = (hmap[j] & 1) ? -1.0 : 1.0;
-    double* out = AS + (slot * m + j) * tau;
+    const int cj = hmap[j];
+    scatter_row<V>(j, zr_ptr, zr_col, zr_val, zt_ptr, T, cj, tau, lam, acc, &rls[wave], lane);
+    const double sj = (cj & 1) ? -1.0 : 1.0;
+    double* out = AS + (slot * m + j) * ldas;
 #pragma unroll
-    for (int t = 0; t < kMaxTauChunks; ++t) {
+    for (int t = 0; t < NCH; ++t) {
       const int c = lane + 64 * t;
       if (c < tau) {
         const double v = acc[c];
@@ -91,10 +161,11 @@ __global__ __launch_bounds__(kWaves * 64) void k_as_sparse_bucket(
       }
     }
     __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   }
   __syncthreads();
 #pragma unroll
-  for (int t = 0; t < kMaxTauChunks; ++t) {
+  for (int t = 0; t < NCH; ++t) {
     const int c = lane + 64 * t;
     if (c < tau) acc[c] = gp[t];
   }
@@ -102,40 +173,46 @@ __global__ __launch_bounds__(kWaves * 64) void k_as_sparse_bucket(
   double* grow = G + (slot * ldg + b) * ldg;
   for (int c = tid; c < tau; c += kWaves * 64) {
     double v = 0.0;
+#pragma unroll
     for (int w = 0; w < kWaves; ++w) v += lds[w * tau + c];
     grow[c] = v;
   }
 }
 
 // Rows of AS for coordinates outside the sketch (SubCount); one wavefront per row.
+template <typename V>
 __global__ __launch_bounds__(kWaves * 64) void k_as_sparse_rows(
     const int64_t* __restrict__ zr_ptr, const int32_t* __restrict__ zr_col,
-    const double* __restrict__ zr_val, const int64_t* __restrict__ zt_ptr,
-    const int32_t* __restrict__ zt_col, const double* __restrict__ zt_val, int64_t m, int32_t tau,
+    const V* __restrict__ zr_val, const int64_t* __restrict__ zt_ptr,
+    const TEntry<V>* __restrict__ T_all, int64_t nnz, int64_t m, int32_t tau, int64_t ldas,
     double lam, const int32_t* __restrict__ hmap_all, double* __restrict__ AS,
     const int32_t* __restrict__ done) {
   extern __shared__ __align__(16) double lds[];
+  __shared__ RowLds rls[kWaves];
   if (*done) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t slot = blockIdx.y;
   const int64_t j = (int64_t)blockIdx.x * kWaves + wave;
   if (j >= m) return;
   const int32_t* hmap = hmap_all + slot * m;
-  if (hmap[j] >= 0) return;  // member rows come from the bucket kernel
+  const int cj = hmap[j];
+  if (cj >= 0) return;  // member rows come from the bucket kernel
   double* acc = lds + wave * tau;
-  scatter_row(j, zr_ptr, zr_col, zr_val, zt_ptr, zt_col, zt_val, hmap, tau, lam, acc, lane);
-  double* out = AS + (slot * m + j) * tau;
+  scatter_row<V>(j, zr_ptr, zr_col, zr_val, zt_ptr, T_all + slot * nnz, cj, tau, lam, acc,
+                 &rls[wave], lane);
+  double* out = AS + (slot * m + j) * ldas;
   for (int c = lane; c < tau; c += 64) out[c] = acc[c];
 }
 
+template <typename V>
 __global__ void k_spmv_csr(const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                           const double* __restrict__ val, int64_t rows, const double* __restrict__ v,
+                           const V* __restrict__ val, int64_t rows, const double* __restrict__ v,
                            double* __restrict__ out) {
   const int lane = threadIdx.x & 63;
   const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (r >= rows) return;
   double s = 0.0;
-  for (int64_t p = ptr[r] + lane; p < ptr[r + 1]; p += 64) s += val[p] * v[col[p]];
+  for (int64_t p = ptr[r] + lane; p < ptr[r + 1]; p += 64) s += (double)val[p] * v[col[p]];
   s = wave_sum(s);
   if (lane == 0) out[r] = s;
 }
@@ -153,14 +230,15 @@ __global__ void k_iota(int32_t* __restrict__ v, int64_t n) {
   if (i < n) v[i] = (int32_t)i;
 }
 
+template <typename V>
 __global__ void k_gather_transposed(const int32_t* __restrict__ perm, const int32_t* __restrict__ row_of,
-                                    const void* __restrict__ val, int32_t is_f32, int64_t nnz,
-                                    int32_t* __restrict__ tcol, double* __restrict__ tval) {
+                                    const V* __restrict__ val, int64_t nnz, int32_t* __restrict__ tcol,
+                                    V* __restrict__ tval) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nnz) return;
   const int32_t p = perm[i];
   tcol[i] = row_of[p];
-  tval[i] = is_f32 ? (double)((const float*)val)[p] : ((const double*)val)[p];
+  tval[i] = val[p];
 }
 
 // tptr[c] = number of sorted keys < c (binary search on the sorted column keys).
@@ -176,47 +254,55 @@ __global__ void k_row_ptr_from_sorted(const int32_t* __restrict__ keys, int64_t 
   tptr[c] = lo;
 }
 
-}  // namespace
-
-hipError_t launch_as_sparse_f64(const int64_t* zr_ptr, const int32_t* zr_col, const double* zr_val,
-                                const int64_t* zt_ptr, const int32_t* zt_col, const double* zt_val,
-                                int64_t m, int32_t tau, int32_t nslots, int32_t kind, double lam,
-                                const int32_t* hmap, const int32_t* members, const int32_t* offs,
-                                int64_t nsel, double* AS, double* G, int64_t ldg,
-                                const int32_t* done, hipStream_t s) {
-  if (tau > 64 * kMaxTauChunks) return hipErrorInvalidValue;
+template <typename V, int NCH>
+hipError_t bucket_launch(const int64_t* zr_ptr, const int32_t* zr_col, const V* zr_val,
+                         const int64_t* zt_ptr, const TEntry<V>* T, int64_t nnz, int64_t m,
+                         int32_t tau, int64_t ldas, int32_t nslots, double lam, const int32_t* hmap,
+                         const int32_t* members, const int32_t* offs, int64_t nsel, double* AS,
+                         double* G, int64_t ldg, const int32_t* done, hipStream_t s) {
   const size_t bytes = sizeof(double) * kWaves * (size_t)tau;
-  hipError_t e = hipFuncSetAttribute((const void*)k_as_sparse_bucket,
+  hipError_t e = hipFuncSetAttribute((const void*)k_as_sparse_bucket<V, NCH>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_as_sparse_bucket, dim3(tau, nslots), dim3(kWaves * 64), bytes, s, zr_ptr,
-                     zr_col, zr_val, zt_ptr, zt_col, zt_val, m, tau, lam, hmap, members, offs, nsel,
-                     AS, G, ldg, done);
-  e = hipGetLastError();
+  hipLaunchKernelGGL((k_as_sparse_bucket<V, NCH>), dim3(tau, nslots), dim3(kWaves * 64), bytes, s,
+                     zr_ptr, zr_col, zr_val, zt_ptr, T, nnz, m, tau, ldas, lam, hmap, members, offs,
+                     nsel, AS, G, ldg, done);
+  return hipGetLastError();
+}
+
+template <typename V>
+hipError_t as_sparse(const int64_t* zr_ptr, const int32_t* zr_col, const V* zr_val,
+                     const int64_t* zt_ptr, const int32_t* zt_col, const V* zt_val, int64_t nnz,
+                     int64_t m, int32_t tau, int64_t ldas, int32_t nslots, int32_t kind, double lam,
+                     const int32_t* hmap, const int32_t* members, const int32_t* offs, int64_t nsel,
+                     void* tbuf, double* AS, double* G, int64_t ldg, const int32_t* done,
+                     hipStream_t s) {
+  const TEntry<V>* T = static_cast<const TEntry<V>*>(tbuf);
+  hipError_t e = hipSuccess;
+  if (tau <= 512)
+    e = bucket_launch<V, 8>(zr_ptr, zr_col, zr_val, zt_ptr, T, nnz, m, tau, ldas, nslots, lam, hmap,
+                            members, offs, nsel, AS, G, ldg, done, s);
+  else if (tau <= 1024)
+    e = bucket_launch<V, 16>(zr_ptr, zr_col, zr_val, zt_ptr, T, nnz, m, tau, ldas, nslots, lam, hmap,
+                             members, offs, nsel, AS, G, ldg, done, s);
+  else
+    e = bucket_launch<V, 32>(zr_ptr, zr_col, zr_val, zt_ptr, T, nnz, m, tau, ldas, nslots, lam, hmap,
+                             members, offs, nsel, AS, G, ldg, done, s);
   if (e != hipSuccess || kind != kSubcount) return e;
-  e = hipFuncSetAttribute((const void*)k_as_sparse_rows,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  const size_t rbytes = sizeof(double) * kWaves * (size_t)tau;
+  e = hipFuncSetAttribute((const void*)k_as_sparse_rows<V>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)rbytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_as_sparse_rows, dim3((unsigned)((m + kWaves - 1) / kWaves), nslots),
-                     dim3(kWaves * 64), bytes, s, zr_ptr, zr_col, zr_val, zt_ptr, zt_col, zt_val, m,
-                     tau, lam, hmap, AS, done);
+  hipLaunchKernelGGL(k_as_sparse_rows<V>, dim3((unsigned)((m + kWaves - 1) / kWaves), nslots),
+                     dim3(kWaves * 64), rbytes, s, zr_ptr, zr_col, zr_val, zt_ptr, T, nnz, m, tau,
+                     ldas, lam, hmap, AS, done);
   return hipGetLastError();
 }
 
-hipError_t launch_spmv_csr(const int64_t* ptr, const int32_t* col, const double* val, int64_t rows,
-                           const double* v, double* out, hipStream_t s) {
-  if (rows == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_spmv_csr, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, ptr, col, val,
-                     rows, v, out);
-  return hipGetLastError();
-}
-
-hipError_t csr_transpose(const int64_t* ptr, const int32_t* col, const void* val, int32_t val_is_f32,
-                         int64_t rows, int64_t cols, int64_t nnz, int64_t* tptr, int32_t* tcol,
-                         double* tval, hipStream_t s) {
-  if (nnz == 0) {
-    return hipMemsetAsync(tptr, 0, sizeof(int64_t) * (cols + 1), s);
-  }
+template <typename V>
+hipError_t transpose_impl(const int64_t* ptr, const int32_t* col, const V* val, int64_t rows,
+                          int64_t cols, int64_t nnz, int64_t* tptr, int32_t* tcol, V* tval,
+                          hipStream_t s) {
   int32_t *row_of = nullptr, *keys_out = nullptr, *idx_in = nullptr, *idx_out = nullptr;
   void* tmp = nullptr;
   size_t tmp_bytes = 0;
@@ -238,8 +324,8 @@ hipError_t csr_transpose(const int64_t* ptr, const int32_t* col, const void* val
                                            0, end_bit, s);
   }
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_gather_transposed, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s,
-                       idx_out, row_of, val, val_is_f32, nnz, tcol, tval);
+    hipLaunchKernelGGL(k_gather_transposed<V>, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s,
+                       idx_out, row_of, val, nnz, tcol, tval);
     hipLaunchKernelGGL(k_row_ptr_from_sorted, dim3((unsigned)((cols + 1 + 255) / 256)), dim3(256),
                        0, s, keys_out, nnz, cols, tptr);
     e = hipGetLastError();
@@ -251,6 +337,65 @@ hipError_t csr_transpose(const int64_t* ptr, const int32_t* col, const void* val
   (void)hipFree(idx_out);
   (void)hipFree(tmp);
   return e;
+}
+
+}  // namespace
+
+size_t sparse_t_bytes(int32_t vals_f32, int64_t nnz) {
+  return (size_t)nnz * (vals_f32 ? sizeof(TEntry<float>) : sizeof(TEntry<double>));
+}
+
+hipError_t launch_build_t(const int32_t* zt_col, const void* zt_val, int32_t vals_f32, int64_t nnz,
+                          const int32_t* hmap, int64_t m, int32_t nslots, void* tbuf,
+                          const int32_t* done, hipStream_t s) {
+  if (nnz == 0) return hipSuccess;
+  const unsigned gx = (unsigned)std::min<int64_t>(4096, (nnz + 255) / 256);
+  if (vals_f32)
+    hipLaunchKernelGGL(k_build_t<float>, dim3(gx, nslots), dim3(256), 0, s, zt_col,
+                       (const float*)zt_val, nnz, hmap, m, (TEntry<float>*)tbuf, done);
+  else
+    hipLaunchKernelGGL(k_build_t<double>, dim3(gx, nslots), dim3(256), 0, s, zt_col,
+                       (const double*)zt_val, nnz, hmap, m, (TEntry<double>*)tbuf, done);
+  return hipGetLastError();
+}
+
+hipError_t launch_as_sparse(const int64_t* zr_ptr, const int32_t* zr_col, const void* zr_val,
+                            const int64_t* zt_ptr, const int32_t* zt_col, const void* zt_val,
+                            int32_t vals_f32, int64_t nnz, int64_t m, int32_t tau, int64_t ldas,
+                            int32_t nslots, int32_t kind, double lam, const int32_t* hmap,
+                            const int32_t* members, const int32_t* offs, int64_t nsel, void* tbuf,
+                            double* AS, double* G, int64_t ldg, const int32_t* done, hipStream_t s) {
+  if (tau > 2048) return hipErrorInvalidValue;
+  if (vals_f32)
+    return as_sparse<float>(zr_ptr, zr_col, (const float*)zr_val, zt_ptr, zt_col, (const float*)zt_val,
+                            nnz, m, tau, ldas, nslots, kind, lam, hmap, members, offs, nsel, tbuf, AS, G,
+                            ldg, done, s);
+  return as_sparse<double>(zr_ptr, zr_col, (const double*)zr_val, zt_ptr, zt_col,
+                           (const double*)zt_val, nnz, m, tau, ldas, nslots, kind, lam, hmap, members,
+                           offs, nsel, tbuf, AS, G, ldg, done, s);
+}
+
+hipError_t launch_spmv_csr(const int64_t* ptr, const int32_t* col, const void* val, int32_t vals_f32,
+                           int64_t rows, const double* v, double* out, hipStream_t s) {
+  if (rows == 0) return hipSuccess;
+  if (vals_f32)
+    hipLaunchKernelGGL(k_spmv_csr<float>, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, ptr,
+                       col, (const float*)val, rows, v, out);
+  else
+    hipLaunchKernelGGL(k_spmv_csr<double>, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, ptr,
+                       col, (const double*)val, rows, v, out);
+  return hipGetLastError();
+}
+
+hipError_t csr_transpose(const int64_t* ptr, const int32_t* col, const void* val, int32_t vals_f32,
+                         int64_t rows, int64_t cols, int64_t nnz, int64_t* tptr, int32_t* tcol,
+                         void* tval, hipStream_t s) {
+  if (nnz == 0) return hipMemsetAsync(tptr, 0, sizeof(int64_t) * (cols + 1), s);
+  if (vals_f32)
+    return transpose_impl<float>(ptr, col, (const float*)val, rows, cols, nnz, tptr, tcol,
+                                 (float*)tval, s);
+  return transpose_impl<double>(ptr, col, (const double*)val, rows, cols, nnz, tptr, tcol,
+                                (double*)tval, s);
 }
 
 }  // namespace rs

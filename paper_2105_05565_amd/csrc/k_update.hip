@@ -1,12 +1,16 @@
 // Per-iteration kernels of sketch-and-project with momentum (Alg. 2).
 //
 //   k_delta : ||r^k|| from the previous update's partial sums (fixed order), the stop
-//             test ||r^k|| / ||r^0|| <= tol, rho = S_k^T r^k (bucket sums) and
-//             delta_k = G_k^{-1} rho (rows of the precomputed inverse);
+//             test ||r^k|| / ||r^0|| <= tol, and delta_k = G_k^{-1} rho_k (rows of the
+//             precomputed inverse; rho_k = S_k^T r^k was produced beforehand);
 //   k_update: x^{k+1} = (1 + beta) x^k - beta x^{k-1} - gamma S_k delta and
 //             r^{k+1} = (1 + beta) r^k - beta r^{k-1} - gamma AS_k delta
 //             (eq:res_update_mom), written over the x^{k-1} / r^{k-1} buffers, plus
-//             per-workgroup partial sums of ||r^{k+1}||^2.
+//             per-workgroup partial sums of ||r^{k+1}||^2. When the next sketch S_{k+1}
+//             is already drawn, rows are visited bucket-major for S_{k+1} and the next
+//             sketched residual rho_{k+1} = S_{k+1}^T r^{k+1} is summed on the way;
+//   k_rho   : rho = S^T r on its own, with the same summation order, for iterations
+//             whose predecessor did not produce it.
 // Once the stop test fires, a device flag turns every later kernel into a no-op, so
 // the state stays at the iteration that met the tolerance.
 #include "dev_common.h"
@@ -16,7 +20,10 @@ namespace rs {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kDeltaRows = 64;  // rows of G^{-1} per k_delta workgroup
+constexpr int kDeltaRows = 4;       // rows of G^{-1} per k_delta workgroup (one per wave)
+constexpr int kBucketWaves = 16;    // waves per bucket in the bucket-major update
+constexpr int kUpdateThreads = 64 * kBucketWaves;
+constexpr int kRowsPerWave = 4;     // rows per wave in the row-range update
 
 __device__ __forceinline__ double reduce_partials(const double* __restrict__ partials, int npart,
                                                   double* scratch) {
@@ -62,10 +69,37 @@ __global__ __launch_bounds__(kThreads) void k_norm0(const double* __restrict__ p
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_delta(const double* __restrict__ r,
-                                                    const int32_t* __restrict__ hmap,
-                                                    const int32_t* __restrict__ members,
-                                                    const int32_t* __restrict__ offs, int32_t tau,
+// rho[b] = sum_{p in bucket b} s_{members[p]} r[members[p]]: wave w of the bucket's
+// workgroup sums p = offs[b] + w, + 16, ... in order; waves are combined in order
+// (the bucket-major update uses the same order).
+__global__ __launch_bounds__(kBucketWaves * 64) void k_rho(const double* __restrict__ r,
+                                                           const int32_t* __restrict__ hmap,
+                                                           const int32_t* __restrict__ members,
+                                                           const int32_t* __restrict__ offs,
+                                                           double* __restrict__ rho,
+                                                           const DevFlags* __restrict__ flags) {
+  __shared__ double part[kBucketWaves];
+  if (flags->done) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int b = blockIdx.x;
+  double s = 0.0;
+  if (lane == 0) {
+    for (int p = offs[b] + wave; p < offs[b + 1]; p += kBucketWaves) {
+      const int j = members[p];
+      const double v = r[j];
+      s += (hmap[j] & 1) ? -v : v;
+    }
+    part[wave] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kBucketWaves; ++w) t += part[w];
+    rho[b] = t;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_delta(const double* __restrict__ rho_in, int32_t tau,
                                                     const double* __restrict__ Ginv, int64_t ldg,
                                                     const double* __restrict__ partials,
                                                     int32_t npart, DevFlags* __restrict__ flags,
@@ -75,6 +109,7 @@ __global__ __launch_bounds__(kThreads) void k_delta(const double* __restrict__ r
   __shared__ double scratch[16];
   if (flags->done) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int c = tid; c < tau; c += kThreads) rho[c] = rho_in[c];
   double rel = 1.0;  // ||r^0|| / ||r^0||
   if (k > 0) {
     const double s = reduce_partials(partials, npart, scratch);
@@ -88,15 +123,6 @@ __global__ __launch_bounds__(kThreads) void k_delta(const double* __restrict__ r
     }
     return;
   }
-  for (int bk = tid; bk < tau; bk += kThreads) {
-    double s = 0.0;
-    for (int p = offs[bk]; p < offs[bk + 1]; ++p) {
-      const int j = members[p];
-      const double v = r[j];
-      s += (hmap[j] & 1) ? -v : v;
-    }
-    rho[bk] = s;
-  }
   __syncthreads();
   const int row_end = min(tau, (int)(blockIdx.x + 1) * kDeltaRows);
   for (int c = blockIdx.x * kDeltaRows + wave; c < row_end; c += kThreads / 64) {
@@ -108,44 +134,108 @@ __global__ __launch_bounds__(kThreads) void k_delta(const double* __restrict__ r
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_update(const double* __restrict__ AS, int32_t tau,
-                                                     const double* __restrict__ delta,
-                                                     const int32_t* __restrict__ hmap, int64_t m,
-                                                     const double* __restrict__ x,
-                                                     double* __restrict__ x_prev_out,
-                                                     const double* __restrict__ r,
-                                                     double* __restrict__ r_prev_out, double gamma,
-                                                     double beta, double* __restrict__ partials,
-                                                     int32_t npart,
-                                                     const DevFlags* __restrict__ flags) {
-  extern __shared__ __align__(16) double dl[];  // [tau]
+// One row of the update, computed by one wave; returns r^{k+1}_j in every lane.
+__device__ __forceinline__ double update_row(int64_t j, const double* __restrict__ AS, int64_t ldas,
+                                             const double* dl, const int32_t* __restrict__ hmap,
+                                             const double* __restrict__ x, double* __restrict__ xo,
+                                             const double* __restrict__ r, double* __restrict__ ro,
+                                             double gamma, double beta, int lane) {
+  int code = -1;
+  double rj = 0.0, roj = 0.0, xj = 0.0, xoj = 0.0;
+  if (lane == 0) {  // issued ahead of the row so their latency overlaps the dot product
+    code = hmap[j];
+    rj = r[j];
+    roj = ro[j];
+    xj = x[j];
+    xoj = xo[j];
+  }
+  const double2* row = reinterpret_cast<const double2*>(AS + j * ldas);
+  const int half = (int)(ldas >> 1);
+  double s = 0.0;
+  for (int c2 = lane; c2 < half; c2 += 64) {
+    const double2 a = row[c2];
+    s += a.x * dl[2 * c2] + a.y * dl[2 * c2 + 1];
+  }
+  s = wave_sum(s);
+  double rn = 0.0;
+  if (lane == 0) {
+    double sd = 0.0;
+    if (code >= 0) sd = (code & 1) ? -dl[code >> 1] : dl[code >> 1];
+    const double onepb = 1.0 + beta;
+    rn = onepb * rj - beta * roj - gamma * s;
+    const double xn = onepb * xj - beta * xoj - gamma * sd;
+    ro[j] = rn;
+    xo[j] = xn;
+  }
+  return rn;
+}
+
+struct UpdateArgs {
+  const double* AS;
+  int64_t ldas;
+  int32_t tau;
+  const double* delta;
+  const int32_t* hmap;
+  int64_t m;
+  const double* x;
+  double* xo;
+  const double* r;
+  double* ro;
+  double gamma, beta;
+  double* partials;
+  // next sketch (bucket-major visit and rho_{k+1}); hmap_n == nullptr: none
+  const int32_t* hmap_n;
+  const int32_t* members_n;
+  const int32_t* offs_n;
+  int32_t skip_all_rows;  // 1 when every coordinate is a member of the next sketch
+  double* rho_n;
+  int32_t nbucket_blocks;  // workgroups in the bucket-major part
+  const DevFlags* flags;
+};
+
+__global__ __launch_bounds__(kUpdateThreads) void k_update(UpdateArgs a) {
+  extern __shared__ __align__(16) double dl[];  // [ldas]
   __shared__ double scratch[16];
-  if (flags->done) return;
+  __shared__ double part[kBucketWaves];
+  if (a.flags->done) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int c = tid; c < tau; c += kThreads) dl[c] = delta[c];
+  for (int c = tid; c < (int)a.ldas; c += blockDim.x) dl[c] = (c < a.tau) ? a.delta[c] : 0.0;
   __syncthreads();
-  const int64_t per = (m + npart - 1) / npart;
-  const int64_t j0 = min(m, (int64_t)blockIdx.x * per), j1 = min(m, j0 + per);
-  const double onepb = 1.0 + beta;
   double ss = 0.0;
-  for (int64_t j = j0 + wave; j < j1; j += kThreads / 64) {
-    const double* row = AS + j * tau;
-    double s = 0.0;
-    for (int c = lane; c < tau; c += 64) s += row[c] * dl[c];
-    s = wave_sum(s);
-    if (lane == 0) {
-      const int code = hmap[j];
-      double sd = 0.0;
-      if (code >= 0) sd = (code & 1) ? -dl[code >> 1] : dl[code >> 1];
-      const double rn = onepb * r[j] - beta * r_prev_out[j] - gamma * s;
-      const double xn = onepb * x[j] - beta * x_prev_out[j] - gamma * sd;
-      r_prev_out[j] = rn;
-      x_prev_out[j] = xn;
-      ss += rn * rn;
+  if ((int)blockIdx.x < a.nbucket_blocks) {
+    // bucket b of the next sketch: 8 waves share its members, in a fixed order
+    const int b = blockIdx.x;
+    double rs = 0.0;
+    for (int p = a.offs_n[b] + wave; p < a.offs_n[b + 1]; p += kBucketWaves) {
+      const int64_t j = a.members_n[p];
+      const double rn = update_row(j, a.AS, a.ldas, dl, a.hmap, a.x, a.xo, a.r, a.ro, a.gamma, a.beta,
+                                   lane);
+      if (lane == 0) {
+        ss += rn * rn;
+        rs += (a.hmap_n[j] & 1) ? -rn : rn;
+      }
+    }
+    if (lane == 0) part[wave] = rs;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int w = 0; w < kBucketWaves; ++w) t += part[w];
+      a.rho_n[b] = t;
+    }
+  } else if (!a.skip_all_rows) {
+    // rows outside the next sketch (all rows when there is none), in index order
+    const int64_t blk = (int64_t)blockIdx.x - a.nbucket_blocks;
+    const int64_t rows_per_block = (int64_t)(blockDim.x >> 6) * kRowsPerWave;
+    const int64_t j0 = blk * rows_per_block, j1 = min(a.m, j0 + rows_per_block);
+    for (int64_t j = j0 + wave; j < j1; j += (blockDim.x >> 6)) {
+      if (a.hmap_n && a.hmap_n[j] >= 0) continue;
+      const double rn = update_row(j, a.AS, a.ldas, dl, a.hmap, a.x, a.xo, a.r, a.ro, a.gamma, a.beta,
+                                   lane);
+      if (lane == 0) ss += rn * rn;
     }
   }
   ss = block_sum(ss, scratch);
-  if (tid == 0) partials[blockIdx.x] = ss;
+  if (tid == 0) a.partials[blockIdx.x] = ss;
 }
 
 __global__ __launch_bounds__(kThreads) void k_finalize(const double* __restrict__ partials,
@@ -167,6 +257,11 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const double* __restrict_
 
 }  // namespace
 
+int32_t update_partials(int64_t m, int32_t tau) {
+  const int64_t rows_per_block = (int64_t)(kUpdateThreads / 64) * kRowsPerWave;
+  return (int32_t)(tau + (m + rows_per_block - 1) / rows_per_block);
+}
+
 hipError_t launch_init_state(const double* b, double* x0, double* x1, double* r0, double* r1,
                              int64_t m, double* partials, int32_t npart, DevFlags* flags,
                              double* hist, hipStream_t s) {
@@ -176,22 +271,57 @@ hipError_t launch_init_state(const double* b, double* x0, double* x1, double* r0
   return hipGetLastError();
 }
 
-hipError_t launch_delta(const double* r, const int32_t* hmap, const int32_t* members,
-                        const int32_t* offs, int32_t tau, const double* Ginv, int64_t ldg,
-                        const double* partials, int32_t npart, DevFlags* flags, double* hist,
-                        int64_t k, double tol, double* delta, hipStream_t s) {
-  const unsigned grid = (unsigned)((tau + kDeltaRows - 1) / kDeltaRows);
-  hipLaunchKernelGGL(k_delta, dim3(grid), dim3(kThreads), sizeof(double) * tau, s, r, hmap, members,
-                     offs, tau, Ginv, ldg, partials, npart, flags, hist, k, tol, delta);
+hipError_t launch_rho(const double* r, const int32_t* hmap, const int32_t* members,
+                      const int32_t* offs, int32_t tau, double* rho, const DevFlags* flags,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_rho, dim3(tau), dim3(kBucketWaves * 64), 0, s, r, hmap, members, offs, rho,
+                     flags);
   return hipGetLastError();
 }
 
-hipError_t launch_update(const double* AS, int32_t tau, const double* delta, const int32_t* hmap,
-                         int64_t m, const double* x, double* x_prev_out, const double* r,
-                         double* r_prev_out, double gamma, double beta, double* partials,
-                         int32_t npart, const DevFlags* flags, hipStream_t s) {
-  hipLaunchKernelGGL(k_update, dim3(npart), dim3(kThreads), sizeof(double) * tau, s, AS, tau, delta,
-                     hmap, m, x, x_prev_out, r, r_prev_out, gamma, beta, partials, npart, flags);
+hipError_t launch_delta(const double* rho, int32_t tau, const double* Ginv, int64_t ldg,
+                        const double* partials, int32_t npart, DevFlags* flags, double* hist,
+                        int64_t k, double tol, double* delta, hipStream_t s) {
+  const unsigned grid = (unsigned)((tau + kDeltaRows - 1) / kDeltaRows);
+  hipLaunchKernelGGL(k_delta, dim3(grid), dim3(kThreads), sizeof(double) * tau, s, rho, tau, Ginv,
+                     ldg, partials, npart, flags, hist, k, tol, delta);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(const double* AS, int64_t ldas, int32_t tau, const double* delta,
+                         const int32_t* hmap, int64_t m, const double* x, double* x_prev_out,
+                         const double* r, double* r_prev_out, double gamma, double beta,
+                         double* partials, int32_t npart, const int32_t* hmap_next,
+                         const int32_t* members_next, const int32_t* offs_next,
+                         int32_t next_covers_all, double* rho_next, const DevFlags* flags,
+                         hipStream_t s) {
+  UpdateArgs a;
+  a.AS = AS;
+  a.ldas = ldas;
+  a.tau = tau;
+  a.delta = delta;
+  a.hmap = hmap;
+  a.m = m;
+  a.x = x;
+  a.xo = x_prev_out;
+  a.r = r;
+  a.ro = r_prev_out;
+  a.gamma = gamma;
+  a.beta = beta;
+  a.partials = partials;
+  a.hmap_n = hmap_next;
+  a.members_n = members_next;
+  a.offs_n = offs_next;
+  a.skip_all_rows = (hmap_next && next_covers_all) ? 1 : 0;
+  a.rho_n = rho_next;
+  a.nbucket_blocks = hmap_next ? tau : 0;
+  a.flags = flags;
+  const int64_t rows_per_block = (int64_t)(kUpdateThreads / 64) * kRowsPerWave;
+  const int32_t nrow_blocks = (int32_t)((m + rows_per_block - 1) / rows_per_block);
+  const int32_t grid = tau + nrow_blocks;
+  if (grid != npart) return hipErrorInvalidValue;
+  // without a next sketch the bucket part is empty: its partial slots are written as zero
+  hipLaunchKernelGGL(k_update, dim3(grid), dim3(kUpdateThreads), sizeof(double) * ldas, s, a);
   return hipGetLastError();
 }
 

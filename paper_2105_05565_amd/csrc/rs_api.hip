@@ -36,10 +36,13 @@ struct rs_handle {
   int64_t ldz = 0;
   int64_t* zr_ptr = nullptr;
   int32_t* zr_col = nullptr;
-  double* zr_val = nullptr;
+  void* zr_val = nullptr;
   int64_t* zt_ptr = nullptr;
   int32_t* zt_col = nullptr;
-  double* zt_val = nullptr;
+  void* zt_val = nullptr;
+  int32_t vals_f32 = 0;  // CSR values kept in the input precision
+  int64_t nnz = 0;
+  void* tbuf = nullptr;  // per-sketch T = Z^T S entries (sparse path)
 
   double* b = nullptr;
   double* xbuf[2] = {nullptr, nullptr};
@@ -48,6 +51,8 @@ struct rs_handle {
   // lookahead batch
   int B = 1;
   int64_t ldg = 0;
+  int64_t ldas = 0;  // row stride of AS (tau rounded up to 8)
+  double* rho = nullptr;
   int32_t* hmap = nullptr;
   int32_t* members = nullptr;
   int32_t* offs = nullptr;
@@ -63,6 +68,13 @@ struct rs_handle {
   int64_t hist_len = 0;
   DevFlags* flags = nullptr;
   int32_t* err = nullptr;
+
+  // profiling (rs_options.profile)
+  std::vector<hipEvent_t> ev;  // pool: 2 events per timed launch of one batch
+  std::vector<int> ev_cls;     // kernel class of each pair
+  std::vector<int> ev_slots;   // sketches processed by each pair
+  int ev_used = 0;
+  rs_profile prof{};
 
   int64_t k = 0;          // iterations performed
   int64_t batch_k0 = -1;  // iteration of slot 0 of the most recent batch
@@ -101,6 +113,8 @@ T* dalloc(rs_handle* h, size_t count) {
 void dfree_all(rs_handle* h) {
   for (void* p : h->allocs) (void)hipFree(p);
   h->allocs.clear();
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  h->ev.clear();
 }
 
 // Momentum schedule (Sec. 6, Sec. 9.1), evaluated in a fixed operation order.
@@ -143,6 +157,32 @@ T* to_device(rs_handle* h, const void* src, size_t count, int mem) {
   return d;
 }
 
+// Event pair around one launch when profiling: returns the pair index or -1.
+int prof_begin(rs_handle* h, int cls, int slots, int level = 1) {
+  if (h->opt.profile < level) return -1;
+  const int i = h->ev_used++;
+  h->ev_cls[i] = cls;
+  h->ev_slots[i] = slots;
+  check_hip(hipEventRecord(h->ev[2 * i], h->stream), "event");
+  return i;
+}
+
+void prof_end(rs_handle* h, int i) {
+  if (i >= 0) check_hip(hipEventRecord(h->ev[2 * i + 1], h->stream), "event");
+}
+
+// After a synchronisation: fold the recorded pairs into h->prof.
+void prof_collect(rs_handle* h) {
+  for (int i = 0; i < h->ev_used; ++i) {
+    float ms = 0.0f;
+    check_hip(hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]), "elapsed");
+    h->prof.ms[h->ev_cls[i]] += ms;
+    h->prof.launches[h->ev_cls[i]] += 1;
+    h->prof.slots[h->ev_cls[i]] += h->ev_slots[i];
+  }
+  h->ev_used = 0;
+}
+
 void run_batch(rs_handle* h, int64_t k0, int nb) {
   hipStream_t s = h->stream;
   const int32_t* done = &h->flags->done;
@@ -162,36 +202,59 @@ void run_batch(rs_handle* h, int64_t k0, int nb) {
   a.keys = h->keys;
   a.err = h->err;
   a.done = done;
+  int pe = prof_begin(h, RS_PROF_SKETCH, nb);
   check_hip(launch_sketch(a, s), "sketch");
+  if (h->sparse)
+    check_hip(launch_build_t(h->zt_col, h->zt_val, h->vals_f32, h->nnz, h->hmap, h->m, nb, h->tbuf,
+                             done, s),
+              "T map");
+  prof_end(h, pe);
+  pe = prof_begin(h, RS_PROF_AS, nb);
   if (h->sparse) {
-    check_hip(launch_as_sparse_f64(h->zr_ptr, h->zr_col, h->zr_val, h->zt_ptr, h->zt_col, h->zt_val,
-                                   h->m, h->tau, nb, h->kind, h->lam, h->hmap, h->members, h->offs,
-                                   h->nsel, h->AS, h->G, h->ldg, done, s),
+    check_hip(launch_as_sparse(h->zr_ptr, h->zr_col, h->zr_val, h->zt_ptr, h->zt_col, h->zt_val,
+                               h->vals_f32, h->nnz, h->m, h->tau, h->ldas, nb, h->kind, h->lam,
+                               h->hmap, h->members, h->offs, h->nsel, h->tbuf, h->AS, h->G, h->ldg,
+                               done, s),
               "AS (sparse)");
   } else {
-    check_hip(launch_as_dense_f64(h->Z, h->ldz, h->m, h->K, h->members, h->tau, nb, h->lam, h->AS,
-                                  done, s),
+    check_hip(launch_as_dense_f64(h->Z, h->ldz, h->m, h->K, h->members, h->tau, h->ldas, nb, h->lam,
+                                  h->AS, done, s),
               "AS (dense)");
   }
-  check_hip(launch_chol_inverse(h->G, h->W, h->ldg, h->tau, nb, h->kind, h->AS, h->m, h->members,
-                                h->offs, h->status, done, s),
+  prof_end(h, pe);
+  pe = prof_begin(h, RS_PROF_CHOL, nb);
+  check_hip(launch_chol_inverse(h->G, h->W, h->ldg, h->tau, nb, h->kind, h->AS, h->ldas, h->m,
+                                h->members, h->offs, h->status, done, s),
             "cholesky");
+  prof_end(h, pe);
+  // rho_{k0} = S_{k0}^T r^{k0}; later iterations get rho from the preceding update
+  check_hip(launch_rho(h->rbuf[k0 & 1], h->hmap, h->members, h->offs, h->tau, h->rho, h->flags, s),
+            "rho");
+  const int pe_iters = prof_begin(h, RS_PROF_ITERS, nb);
   for (int i = 0; i < nb; ++i) {
     const int64_t k = k0 + i;
     double gamma, beta;
     schedule(h->opt, k, &gamma, &beta);
     const int cur = (int)(k & 1), nxt = 1 - cur;
     const int32_t* hm = h->hmap + (int64_t)i * h->m;
-    check_hip(launch_delta(h->rbuf[cur], hm, h->members + (int64_t)i * h->nsel,
-                           h->offs + (int64_t)i * (h->tau + 1), h->tau,
-                           h->G + (int64_t)i * h->ldg * h->ldg, h->ldg, h->partials, h->npart,
-                           h->flags, h->hist, k, h->opt.tol, h->delta, s),
+    pe = prof_begin(h, RS_PROF_DELTA, 1, 2);
+    check_hip(launch_delta(h->rho, h->tau, h->G + (int64_t)i * h->ldg * h->ldg, h->ldg, h->partials,
+                           h->npart, h->flags, h->hist, k, h->opt.tol, h->delta, s),
               "delta");
-    check_hip(launch_update(h->AS + (int64_t)i * h->m * h->tau, h->tau, h->delta, hm, h->m,
+    prof_end(h, pe);
+    pe = prof_begin(h, RS_PROF_UPDATE, 1, 2);
+    const bool has_next = i + 1 < nb;
+    check_hip(launch_update(h->AS + (int64_t)i * h->m * h->ldas, h->ldas, h->tau, h->delta, hm, h->m,
                             h->xbuf[cur], h->xbuf[nxt], h->rbuf[cur], h->rbuf[nxt], gamma, beta,
-                            h->partials, h->npart, h->flags, s),
+                            h->partials, h->npart,
+                            has_next ? h->hmap + (int64_t)(i + 1) * h->m : nullptr,
+                            has_next ? h->members + (int64_t)(i + 1) * h->nsel : nullptr,
+                            has_next ? h->offs + (int64_t)(i + 1) * (h->tau + 1) : nullptr,
+                            h->kind == kCount ? 1 : 0, h->rho, h->flags, s),
               "update");
+    prof_end(h, pe);
   }
+  prof_end(h, pe_iters);
   h->batch_k0 = k0;
   h->batch_n = nb;
 }
@@ -202,8 +265,18 @@ void advance(rs_handle* h, int64_t iters) {
   int64_t k_enq = h->k;
   int64_t left = std::min(iters, h->opt.max_iter - h->k);
   std::vector<int32_t> st(h->B);
+  // last two known points (k, ||r^k|| / ||r^0||) of the residual history
+  int64_t k_a = -1, k_b = -1;
+  double rel_a = 0.0, rel_b = 0.0;
   while (left > 0 && !h->done) {
-    const int nb = (int)std::min<int64_t>(h->B, left);
+    int nb = (int)std::min<int64_t>(h->B, left);
+    // Near the tolerance, size the batch from the observed contraction so that few
+    // sketches are formed past the stopping iteration.
+    if (k_a >= 0 && k_b > k_a && rel_b < rel_a && rel_b > 0.0 && h->opt.tol > 0.0) {
+      const double rate = std::log(rel_b / rel_a) / (double)(k_b - k_a);
+      const double need = std::log(h->opt.tol / rel_b) / rate - (double)(h->k - k_b);
+      if (need < nb) nb = (int)std::max<double>(16.0, std::min<double>(nb, need * 1.1 + 8.0));
+    }
     run_batch(h, k_enq, nb);
     k_enq += nb;
     left -= nb;
@@ -217,11 +290,20 @@ void advance(rs_handle* h, int64_t iters) {
               "status");
     check_hip(hipMemcpyAsync(&err, h->err, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream), "err");
     check_hip(hipStreamSynchronize(h->stream), "sync");
+    prof_collect(h);
     if (err) throw Fail{RS_EDEVICE, "internal sketch limit hit (code " + std::to_string(err) + ")"};
     const int64_t k_end = f.done ? f.k_done : k_enq;
     for (int i = 0; i < nb; ++i)
       if (st[i] != 0 && h->batch_k0 + i < k_end)
         throw Fail{RS_ESINGULAR, "non-positive pivot in the Cholesky factorisation of S^T A S"};
+    if (!f.done && left > 0 && k_end > 0) {
+      double rel = 0.0;  // ||r^{k_end - 1}||, written by the batch's last delta launch
+      check_hip(hipMemcpy(&rel, h->hist + (k_end - 1), sizeof(double), hipMemcpyDeviceToHost), "hist");
+      k_a = k_b;
+      rel_a = rel_b;
+      k_b = k_end - 1;
+      rel_b = rel;
+    }
     h->k = k_end;
     if (f.done) h->done = true;
   }
@@ -398,42 +480,49 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
         for (int64_t p = ph[i]; p < ph[i + 1]; ++p)
           if (ch[p] < 0 || ch[p] >= d || (p > ph[i] && ch[p] <= ch[p - 1]))
             throw Fail{RS_EINVAL, "col_idx must be in [0, d) and strictly increasing within a row"};
-      double* xval64 = dalloc<double>(h, nnz);
-      check_hip(launch_vec_to_f64(xval, f32, nnz, xval64, s), "values");
+      h->vals_f32 = f32 ? 1 : 0;
+      h->nnz = nnz;
       int64_t* tptr = dalloc<int64_t>(h, d + 1);
       int32_t* tcol = dalloc<int32_t>(h, nnz);
-      double* tval = dalloc<double>(h, nnz);
-      check_hip(csr_transpose(xptr, xcol, xval, f32, n, d, nnz, tptr, tcol, tval, s), "transpose");
+      void* tval = dalloc<char>(h, (size_t)nnz * esz);
+      check_hip(csr_transpose(xptr, xcol, xval, h->vals_f32, n, d, nnz, tptr, tcol, tval, s), "transpose");
       if (h->form == RS_FORM_PRIMAL) {
         h->zr_ptr = tptr; h->zr_col = tcol; h->zr_val = tval;  // Z = X^T
-        h->zt_ptr = xptr; h->zt_col = xcol; h->zt_val = xval64;
-        check_hip(launch_spmv_csr(h->zr_ptr, h->zr_col, h->zr_val, h->m, yd, h->b, s), "b = X^T y");
+        h->zt_ptr = xptr; h->zt_col = xcol; h->zt_val = xval;
+        check_hip(launch_spmv_csr(h->zr_ptr, h->zr_col, h->zr_val, h->vals_f32, h->m, yd, h->b, s),
+                  "b = X^T y");
       } else {
-        h->zr_ptr = xptr; h->zr_col = xcol; h->zr_val = xval64;  // Z = X
+        h->zr_ptr = xptr; h->zr_col = xcol; h->zr_val = xval;  // Z = X
         h->zt_ptr = tptr; h->zt_col = tcol; h->zt_val = tval;
         check_hip(hipMemcpyAsync(h->b, yd, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "b = y");
       }
     }
 
     // batch buffers
-    h->ldg = ((int64_t)h->tau + 31) / 32 * 32;
-    const size_t per_slot = sizeof(double) * ((size_t)h->m * h->tau + 2 * (size_t)h->ldg * h->ldg) +
+    h->ldg = ((int64_t)h->tau + 63) / 64 * 64;
+    h->ldas = ((int64_t)h->tau + 7) / 8 * 8;
+    const size_t per_slot = (h->sparse ? sparse_t_bytes(h->vals_f32, h->nnz) : 0) +
+                            sizeof(double) * ((size_t)h->m * h->ldas + 2 * (size_t)h->ldg * h->ldg) +
                             sizeof(int32_t) * ((size_t)h->m + h->nsel + h->tau + 1) +
                             sizeof(uint64_t) * (size_t)h->m;
-    int B = o->lookahead > 0 ? o->lookahead : 64;
-    const size_t budget = (size_t)24 << 30;
+    int B = o->lookahead > 0 ? o->lookahead : 256;
+    const size_t budget = (size_t)48 << 30;
     while (B > 1 && (size_t)B * per_slot > budget) B >>= 1;
     h->B = B;
     h->hmap = dalloc<int32_t>(h, (size_t)B * h->m);
     h->members = dalloc<int32_t>(h, (size_t)B * h->nsel);
     h->offs = dalloc<int32_t>(h, (size_t)B * (h->tau + 1));
     h->keys = dalloc<uint64_t>(h, (size_t)B * h->m);
-    h->AS = dalloc<double>(h, (size_t)B * h->m * h->tau);
+    h->AS = dalloc<double>(h, (size_t)B * h->m * h->ldas);
+    // the padding columns of AS are read (times a zero delta) by the update: keep them zero
+    check_hip(hipMemsetAsync(h->AS, 0, sizeof(double) * (size_t)B * h->m * h->ldas, s), "memset");
+    h->rho = dalloc<double>(h, h->ldg);
+    if (h->sparse) h->tbuf = dalloc<char>(h, (size_t)B * sparse_t_bytes(h->vals_f32, h->nnz));
     h->G = dalloc<double>(h, (size_t)B * h->ldg * h->ldg);
     h->W = dalloc<double>(h, (size_t)B * h->ldg * h->ldg);
     h->status = dalloc<int32_t>(h, B);
     h->delta = dalloc<double>(h, h->ldg);
-    h->npart = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (h->m + 255) / 256));
+    h->npart = update_partials(h->m, h->tau);
     h->partials = dalloc<double>(h, h->npart);
     h->hist_len = h->opt.max_iter + 1;
     h->hist = dalloc<double>(h, h->hist_len);
@@ -442,6 +531,13 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
     for (int i = 0; i < 2; ++i) {
       h->xbuf[i] = dalloc<double>(h, h->m);
       h->rbuf[i] = dalloc<double>(h, h->m);
+    }
+    if (o->profile) {
+      const int pairs = 4 + 2 * B;  // sketch, AS, Cholesky, iteration sequence + 2 per iteration
+      h->ev.resize(2 * pairs);
+      h->ev_cls.resize(pairs);
+      h->ev_slots.resize(pairs);
+      for (auto& e : h->ev) check_hip(hipEventCreate(&e), "event create");
     }
     check_hip(hipMemsetAsync(h->status, 0, sizeof(int32_t) * B, s), "memset");
     check_hip(hipMemsetAsync(h->err, 0, sizeof(int32_t), s), "memset");
@@ -483,6 +579,41 @@ rs_status rs_step(rs_handle* h, int64_t iters, double* rel_res_out) {
   }
 }
 
+rs_status rs_reset(rs_handle* h, uint64_t seed) {
+  if (!h) return RS_EINVAL;
+  try {
+    h->opt.seed = seed;
+    h->k = 0;
+    h->done = false;
+    h->batch_k0 = -1;
+    h->batch_n = 0;
+    check_hip(hipMemsetAsync(h->status, 0, sizeof(int32_t) * h->B, h->stream), "memset");
+    check_hip(hipMemsetAsync(h->err, 0, sizeof(int32_t), h->stream), "memset");
+    check_hip(launch_init_state(h->b, h->xbuf[0], h->xbuf[1], h->rbuf[0], h->rbuf[1], h->m,
+                                h->partials, h->npart, h->flags, h->hist, h->stream),
+              "init");
+    DevFlags f{};
+    check_hip(hipMemcpyAsync(&f, h->flags, sizeof(DevFlags), hipMemcpyDeviceToHost, h->stream), "flags");
+    check_hip(hipStreamSynchronize(h->stream), "sync");
+    h->done = f.done != 0;
+    return RS_OK;
+  } catch (const Fail& f) {
+    h->last_error = f.msg;
+    return f.code;
+  }
+}
+
+rs_status rs_get_profile(rs_handle* h, rs_profile* out, int32_t clear) {
+  if (!h || !out) return RS_EINVAL;
+  if (!h->opt.profile) {
+    h->last_error = "profiling was not enabled in rs_options";
+    return RS_EINVAL;
+  }
+  *out = h->prof;
+  if (clear) h->prof = rs_profile{};
+  return RS_OK;
+}
+
 int64_t rs_iteration(const rs_handle* h) { return h ? h->k : -1; }
 int64_t rs_system_size(const rs_handle* h) { return h ? h->m : -1; }
 
@@ -495,7 +626,8 @@ rs_status rs_get_weights(rs_handle* h, double* w_out) {
     } else {
       double* wd = nullptr;
       check_hip(hipMalloc(&wd, sizeof(double) * h->d), "alloc");
-      hipError_t e = h->sparse ? launch_spmv_csr(h->zt_ptr, h->zt_col, h->zt_val, h->d, x, wd, h->stream)
+      hipError_t e = h->sparse ? launch_spmv_csr(h->zt_ptr, h->zt_col, h->zt_val, h->vals_f32, h->d, x, wd,
+                                                 h->stream)
                                : launch_gemv_cols(h->Z, h->ldz, h->m, h->K, x, wd, h->stream);
       if (e == hipSuccess)
         e = hipMemcpyAsync(w_out, wd, sizeof(double) * h->d, hipMemcpyDeviceToHost, h->stream);

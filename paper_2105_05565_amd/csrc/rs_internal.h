@@ -57,38 +57,51 @@ struct DevFlags {
 // ---------------------------------------------------------------------------
 hipError_t launch_sketch(const SketchArgs& a, hipStream_t s);
 
-// AS[slot][j][c] = sum_k Z[j][k] * Z[C_slot[c]][k] + lam * [j == C_slot[c]], FP64 MFMA.
+// AS[slot][j][c] (row stride ldas) = sum_k Z[j][k] * Z[C_slot[c]][k] + lam * [j == C_slot[c]],
+// FP64 MFMA.
 hipError_t launch_as_dense_f64(const double* Z, int64_t ldz, int64_t m, int64_t K,
-                               const int32_t* members, int32_t tau, int32_t nslots, double lam,
-                               double* AS, const int32_t* done, hipStream_t s);
+                               const int32_t* members, int32_t tau, int64_t ldas, int32_t nslots,
+                               double lam, double* AS, const int32_t* done, hipStream_t s);
 
-// Count / SubCount products from CSR(Z) (m rows) and CSR(Z^T) (K rows):
-// AS[slot] (m x tau) and, for member rows, G[slot][b][:] = sum_{j in b} sign_j AS[j][:].
-hipError_t launch_as_sparse_f64(const int64_t* zr_ptr, const int32_t* zr_col, const double* zr_val,
-                                const int64_t* zt_ptr, const int32_t* zt_col, const double* zt_val,
-                                int64_t m, int32_t tau, int32_t nslots, int32_t kind, double lam,
-                                const int32_t* hmap, const int32_t* members, const int32_t* offs,
-                                int64_t nsel, double* AS, double* G, int64_t ldg,
-                                const int32_t* done, hipStream_t s);
+// Count / SubCount products from CSR(Z) (m rows) and CSR(Z^T) (nnz entries), values FP32 or
+// FP64: AS[slot] (m x tau, row stride ldas) and, for member rows,
+// G[slot][b][:] = sum_{j in b} sign_j AS[j][:]. tbuf holds nslots * sparse_t_bytes(...) bytes.
+size_t sparse_t_bytes(int32_t vals_f32, int64_t nnz);
+// T[slot][q] = (bucket of column zt_col[q], signed value) for every entry q of CSR(Z^T).
+hipError_t launch_build_t(const int32_t* zt_col, const void* zt_val, int32_t vals_f32, int64_t nnz,
+                          const int32_t* hmap, int64_t m, int32_t nslots, void* tbuf,
+                          const int32_t* done, hipStream_t s);
+hipError_t launch_as_sparse(const int64_t* zr_ptr, const int32_t* zr_col, const void* zr_val,
+                            const int64_t* zt_ptr, const int32_t* zt_col, const void* zt_val,
+                            int32_t vals_f32, int64_t nnz, int64_t m, int32_t tau, int64_t ldas,
+                            int32_t nslots, int32_t kind, double lam, const int32_t* hmap,
+                            const int32_t* members, const int32_t* offs, int64_t nsel, void* tbuf,
+                            double* AS, double* G, int64_t ldg, const int32_t* done, hipStream_t s);
 
 // Ginv[slot] = (S^T A S)^{-1} (padded ldg x ldg, identity on empty buckets and padding).
 hipError_t launch_chol_inverse(double* G, double* W, int64_t ldg, int32_t tau, int32_t nslots,
-                               int32_t kind, const double* AS, int64_t m, const int32_t* members,
-                               const int32_t* offs, int32_t* status, const int32_t* done,
-                               hipStream_t s);
+                               int32_t kind, const double* AS, int64_t ldas, int64_t m,
+                               const int32_t* members, const int32_t* offs, int32_t* status,
+                               const int32_t* done, hipStream_t s);
 
 // Solve-state kernels.
+int32_t update_partials(int64_t m, int32_t tau);  // partial sums written by k_update
 hipError_t launch_init_state(const double* b, double* x0, double* x1, double* r0, double* r1,
                              int64_t m, double* partials, int32_t npart, DevFlags* flags,
                              double* hist, hipStream_t s);
-hipError_t launch_delta(const double* r, const int32_t* hmap, const int32_t* members,
-                        const int32_t* offs, int32_t tau, const double* Ginv, int64_t ldg,
+hipError_t launch_rho(const double* r, const int32_t* hmap, const int32_t* members,
+                      const int32_t* offs, int32_t tau, double* rho, const DevFlags* flags,
+                      hipStream_t s);
+hipError_t launch_delta(const double* rho, int32_t tau, const double* Ginv, int64_t ldg,
                         const double* partials, int32_t npart, DevFlags* flags, double* hist,
                         int64_t k, double tol, double* delta, hipStream_t s);
-hipError_t launch_update(const double* AS, int32_t tau, const double* delta, const int32_t* hmap,
-                         int64_t m, const double* x, double* x_prev_out, const double* r,
-                         double* r_prev_out, double gamma, double beta, double* partials,
-                         int32_t npart, const DevFlags* flags, hipStream_t s);
+hipError_t launch_update(const double* AS, int64_t ldas, int32_t tau, const double* delta,
+                         const int32_t* hmap, int64_t m, const double* x, double* x_prev_out,
+                         const double* r, double* r_prev_out, double gamma, double beta,
+                         double* partials, int32_t npart, const int32_t* hmap_next,
+                         const int32_t* members_next, const int32_t* offs_next,
+                         int32_t next_covers_all, double* rho_next, const DevFlags* flags,
+                         hipStream_t s);
 hipError_t launch_finalize(const double* partials, int32_t npart, DevFlags* flags, double* hist,
                            int64_t k, double tol, hipStream_t s);
 
@@ -101,14 +114,14 @@ hipError_t launch_gemv_rows(const double* Z, int64_t ldz, int64_t m, int64_t K, 
                             double* out, hipStream_t s);           // out = Z v
 hipError_t launch_gemv_cols(const double* Z, int64_t ldz, int64_t m, int64_t K, const double* v,
                             double* out, hipStream_t s);           // out = Z^T v
-hipError_t launch_spmv_csr(const int64_t* ptr, const int32_t* col, const double* val, int64_t rows,
-                           const double* v, double* out, hipStream_t s);
+hipError_t launch_spmv_csr(const int64_t* ptr, const int32_t* col, const void* val, int32_t vals_f32,
+                           int64_t rows, const double* v, double* out, hipStream_t s);
 hipError_t launch_vec_to_f64(const void* src, int32_t src_is_f32, int64_t n, double* dst,
                              hipStream_t s);
-// CSR (rows x cols) -> CSR of the transpose, FP64 values out. Stable: entries of each
-// output row appear in increasing source-row order.
-hipError_t csr_transpose(const int64_t* ptr, const int32_t* col, const void* val, int32_t val_is_f32,
+// CSR (rows x cols) -> CSR of the transpose, values kept in their precision. Stable:
+// entries of each output row appear in increasing source-row order.
+hipError_t csr_transpose(const int64_t* ptr, const int32_t* col, const void* val, int32_t vals_f32,
                          int64_t rows, int64_t cols, int64_t nnz, int64_t* tptr, int32_t* tcol,
-                         double* tval, hipStream_t s);
+                         void* tval, hipStream_t s);
 
 }  // namespace rs

@@ -42,7 +42,17 @@ class rs_options(ctypes.Structure):
                 ("eta", ctypes.c_double), ("beta_max", ctypes.c_double), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int64), ("seed", ctypes.c_uint64), ("problem_id", ctypes.c_uint64),
                 ("refresh_every", ctypes.c_int32), ("lookahead", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("profile", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+RS_PROF_SKETCH, RS_PROF_AS, RS_PROF_CHOL, RS_PROF_DELTA, RS_PROF_UPDATE, RS_PROF_REFRESH, RS_PROF_ITERS = range(7)
+RS_PROF_COUNT = 8
+PROF_NAMES = ["sketch", "as", "chol", "delta", "update", "refresh", "iters"]
+
+
+class rs_profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * RS_PROF_COUNT), ("launches", ctypes.c_int64 * RS_PROF_COUNT),
+                ("slots", ctypes.c_int64 * RS_PROF_COUNT)]
 
 
 class rs_report(ctypes.Structure):
@@ -66,6 +76,8 @@ SIGNATURES = {
                                    ctypes.POINTER(rs_options), ctypes.POINTER(_P)]),
     "rs_step": (ctypes.c_int32, [_P, ctypes.c_int64, _D]),
     "rs_solve": (ctypes.c_int32, [_P, _P, ctypes.POINTER(rs_report)]),
+    "rs_reset": (ctypes.c_int32, [_P, ctypes.c_uint64]),
+    "rs_get_profile": (ctypes.c_int32, [_P, ctypes.POINTER(rs_profile), ctypes.c_int32]),
     "rs_iteration": (ctypes.c_int64, [_P]),
     "rs_system_size": (ctypes.c_int64, [_P]),
     "rs_get_state": (ctypes.c_int32, [_P, _P, _P, _P, _P]),
@@ -154,6 +166,17 @@ def rs_solve(h, w_out=None):
     rep = rs_report()
     st = _check(load().rs_solve(h, _ptr(w_out), ctypes.byref(rep)), "rs_solve", h)
     return st, rep
+
+
+def rs_reset(h, seed):
+    _check(load().rs_reset(h, int(seed)), "rs_reset", h)
+
+
+def rs_get_profile(h, clear=False):
+    p = rs_profile()
+    _check(load().rs_get_profile(h, ctypes.byref(p), int(bool(clear))), "rs_get_profile", h)
+    return {name: {"ms": p.ms[i], "launches": p.launches[i], "slots": p.slots[i]}
+            for i, name in enumerate(PROF_NAMES)}
 
 
 def rs_iteration(h):
@@ -255,13 +278,13 @@ class Solver:
     def __init__(self, X, y, lam, *, tau, sketch="subsample", form="auto", momentum="heuristic",
                  precision="fp64", subcount_k=0, tol=1e-6, max_iter=100000, seed=1, problem_id=0,
                  eta=0.995, beta_max=0.5, gamma=1.0, beta=0.5, lookahead=0, refresh_every=20,
-                 stream=None):
+                 profile=False, stream=None):
         o = rs_options_default()
         o.form, o.sketch, o.tau = FORMS[form], SKETCHES[sketch], int(tau)
         o.subcount_k, o.momentum, o.precision = int(subcount_k), MOMENTA[momentum], PRECISIONS[precision]
         o.gamma, o.beta, o.eta, o.beta_max, o.tol = gamma, beta, eta, beta_max, tol
         o.max_iter, o.seed, o.problem_id = int(max_iter), int(seed), int(problem_id)
-        o.refresh_every, o.lookahead = int(refresh_every), int(lookahead)
+        o.refresh_every, o.lookahead, o.profile = int(refresh_every), int(lookahead), int(profile)
         o.stream = stream
         M, keep = make_matrix(X)
         if M.mem == RS_DEVICE:
@@ -272,6 +295,12 @@ class Solver:
         self.h = rs_create(M, yv, lam, o)
         self.m = rs_system_size(self.h)
         self.d = int(M.d)
+
+    def reset(self, seed):
+        rs_reset(self.h, seed)
+
+    def profile(self, clear=False):
+        return rs_get_profile(self.h, clear)
 
     def step(self, iters):
         return rs_step(self.h, iters)
