@@ -171,6 +171,13 @@ rs_status rs_get_weights(rs_handle* h, double* w_out);
 rs_status rs_get_last_sketch(const rs_handle* h, int32_t* rows, int32_t* cols, int8_t* signs,
                              int64_t* nnz_out);
 
+/* Products of the last iteration's sketch S_{k-1} (host buffers, may be NULL):
+ * as_out: m x tau row-major AS = Z (Z^T S) + lambda S as stored by the library (FP64,
+ * or FP32 widened to FP64 in mixed precision); ginv_out: tau x tau row-major
+ * (S^T A S)^{-1} as applied by the solve (identity rows/columns for empty buckets).
+ * For parity tests and inspection. */
+rs_status rs_get_products(const rs_handle* h, double* as_out, double* ginv_out);
+
 /* Relative residual history ||r^k|| / ||r^0||, k = 0..count-1 (host). */
 rs_status rs_get_history(const rs_handle* h, double* out, int64_t count);
 

@@ -85,10 +85,11 @@ __device__ __forceinline__ void acc_for_each(const Acc& c, F f) {
         f(wr + i * 16 + 4 * v + (lane >> 4), wc + j * 16 + (lane & 15), c.v[i][j][v]);
 }
 
+template <typename ASV>
 __global__ __launch_bounds__(kThreads) void k_chol_inverse(double* __restrict__ Gall,
                                                            double* __restrict__ Uall, int64_t ldg,
                                                            int32_t tau, int32_t kind,
-                                                           const double* __restrict__ ASall,
+                                                           const ASV* __restrict__ ASall,
                                                            int64_t ldas, int64_t m,
                                                            const int32_t* __restrict__ members_all,
                                                            const int32_t* __restrict__ offs_all,
@@ -112,10 +113,10 @@ __global__ __launch_bounds__(kThreads) void k_chol_inverse(double* __restrict__ 
   // Phase 0: assemble G (subsample: rows C of AS), padding and empty buckets.
   if (kind == kSubsample) {
     const int32_t* members = members_all + slot * tau;
-    const double* AS = ASall + slot * m * ldas;
+    const ASV* AS = ASall + slot * m * ldas;
     for (int64_t e = tid; e < (int64_t)tau * tau; e += kThreads) {
       const int64_t c = e / tau, cc = e % tau;
-      G[c * ldg + cc] = AS[(int64_t)members[c] * ldas + cc];
+      G[c * ldg + cc] = (double)AS[(int64_t)members[c] * ldas + cc];
     }
   }
   for (int64_t e = tid; e < ldg * ldg; e += kThreads) {
@@ -247,20 +248,31 @@ __global__ __launch_bounds__(kThreads) void k_chol_inverse(double* __restrict__ 
   if (tid == 0) status[slot] = bad;
 }
 
+template <typename ASV>
+hipError_t chol_launch(double* G, double* W, int64_t ldg, int32_t tau, int32_t nslots, int32_t kind,
+                       const ASV* AS, int64_t ldas, int64_t m, const int32_t* members,
+                       const int32_t* offs, int32_t* status, const int32_t* done, hipStream_t s) {
+  if (ldg % NB != 0) return hipErrorInvalidValue;
+  const size_t bytes = sizeof(double) * (3 * NB * LDT + NB);
+  hipError_t e = hipFuncSetAttribute((const void*)k_chol_inverse<ASV>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_chol_inverse<ASV>, dim3(nslots), dim3(kThreads), bytes, s, G, W, ldg, tau,
+                     kind, AS, ldas, m, members, offs, status, done);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_chol_inverse(double* G, double* W, int64_t ldg, int32_t tau, int32_t nslots,
-                               int32_t kind, const double* AS, int64_t ldas, int64_t m,
+                               int32_t kind, const void* AS, int32_t as_f32, int64_t ldas, int64_t m,
                                const int32_t* members, const int32_t* offs, int32_t* status,
                                const int32_t* done, hipStream_t s) {
-  if (ldg % NB != 0) return hipErrorInvalidValue;
-  const size_t bytes = sizeof(double) * (3 * NB * LDT + NB);
-  hipError_t e = hipFuncSetAttribute((const void*)k_chol_inverse,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_chol_inverse, dim3(nslots), dim3(kThreads), bytes, s, G, W, ldg, tau, kind, AS,
-                     ldas, m, members, offs, status, done);
-  return hipGetLastError();
+  if (as_f32)
+    return chol_launch<float>(G, W, ldg, tau, nslots, kind, (const float*)AS, ldas, m, members, offs,
+                              status, done, s);
+  return chol_launch<double>(G, W, ldg, tau, nslots, kind, (const double*)AS, ldas, m, members, offs,
+                             status, done, s);
 }
 
 }  // namespace rs

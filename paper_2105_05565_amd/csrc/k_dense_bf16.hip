@@ -1,0 +1,392 @@
+// Mixed-precision products for the subsample sketch (BF16 inputs, FP32 accumulation)
+// and the FP64 residual refresh.
+//
+// AS = Z Z[C,:]^T + lambda I_C is formed from a BF16 copy of Z on MFMA
+// (v_mfma_f32_32x32x16_bf16) with FP32 accumulation; several lookahead sketches share
+// the first operand, so one launch contracts Z against the gathered rows of every
+// slot (N = slots * tau columns). The tracked residual drifts with the BF16 rounding
+// of AS; every R iterations it is recomputed in FP64 from an FP32 copy of Z
+// (r = Z (Z^T x) + lambda x - b for x^k and x^{k-1}).
+//
+// GEMM tiling (gfx950): 256 x 256 output tile per workgroup, 8 waves each owning a
+// 64 x 128 sub-tile (2 x 4 MFMA blocks of 32 x 32), K staged 64 at a time through
+// double-buffered LDS (rows padded by 16 bytes against bank conflicts). Tiles are
+// ordered so that the workgroups one XCD runs together share row strips of Z and
+// gathered column strips (workgroups are dispatched to the 8 XCDs round-robin).
+#include "dev_common.h"
+#include "rs_internal.h"
+
+namespace rs {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kBM = 256, kBN = 256, kBK = 64;
+constexpr int kLdsRow = kBK + 8;  // bf16 elements per LDS row (64 + 8 padding)
+constexpr int kGemmThreads = 512;
+constexpr int kXcds = 8;
+constexpr int kGroupRows = 4;  // row tiles per tile group (XCD-local reuse of Z strips)
+
+__device__ __forceinline__ uint16_t bf16_bits_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (uint16_t)(u >> 16);
+}
+
+// dst (rows x ldd, BF16 bits, zero padded) and dst32 (FP32, ld ldd32) from src viewed
+// row-major (rows_s x cols_s, ld lds); trans: dst[c][r] = src[r][c].
+__global__ void k_cast_bf16(const void* __restrict__ src, int32_t is_f32, int64_t rows_s,
+                            int64_t cols_s, int64_t lds, int32_t trans, uint16_t* __restrict__ dst,
+                            int64_t ldd, float* __restrict__ dst32, int64_t ldd32) {
+  __shared__ float tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int64_t r = r0 + yy, c = c0 + tx;
+    float v = 0.0f;
+    if (r < rows_s && c < cols_s)
+      v = is_f32 ? ((const float*)src)[r * lds + c] : (float)((const double*)src)[r * lds + c];
+    tile[yy][tx] = v;
+  }
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8) {
+    int64_t orow, ocol;
+    float v;
+    if (trans) {
+      orow = c0 + yy;
+      ocol = r0 + tx;
+      v = tile[tx][yy];
+    } else {
+      orow = r0 + yy;
+      ocol = c0 + tx;
+      v = tile[yy][tx];
+    }
+    const int64_t out_rows = trans ? cols_s : rows_s;
+    if (orow < out_rows && ocol < ldd) {
+      dst[orow * ldd + ocol] = bf16_bits_rne(v);
+      if (ocol < ldd32) dst32[orow * ldd32 + ocol] = v;
+    }
+  }
+}
+
+struct GemmArgs {
+  const uint16_t* Z;   // m x ldz BF16 bits, zero padded to a multiple of kBK
+  int64_t ldz, m, kpad;
+  const int32_t* members;  // [slots][tau]
+  int32_t tau;
+  int64_t ntot;  // slots * tau
+  int64_t ldas;
+  double lam;
+  float* AS;  // [slot][m][ldas]
+  int32_t n_row_tiles, n_col_tiles;
+  const int32_t* done;
+};
+
+__device__ __forceinline__ void tile_of_block(const GemmArgs& a, int bid, int* rt, int* ct) {
+  const int ntiles = a.n_row_tiles * a.n_col_tiles;
+  const int per = (ntiles + kXcds - 1) / kXcds;
+  const int t = (bid % kXcds) * per + bid / kXcds;
+  if (t >= ntiles) {
+    *rt = -1;
+    return;
+  }
+  const int group = t / (kGroupRows * a.n_col_tiles);
+  const int rows_in_group = min(kGroupRows, a.n_row_tiles - group * kGroupRows);
+  const int idx = t - group * kGroupRows * a.n_col_tiles;
+  *rt = group * kGroupRows + idx % rows_in_group;
+  *ct = idx / rows_in_group;
+}
+
+__global__ __launch_bounds__(kGemmThreads) void k_as_dense_bf16(GemmArgs a) {
+  extern __shared__ __align__(16) uint16_t smem[];  // [2][kBM + kBN][kLdsRow]
+  __shared__ int64_t brow[kBN];
+  if (*a.done) return;
+  int rt, ct;
+  tile_of_block(a, blockIdx.x, &rt, &ct);
+  if (rt < 0) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t row0 = (int64_t)rt * kBM, n0 = (int64_t)ct * kBN;
+  if (tid < kBN) {
+    const int64_t n = n0 + tid;
+    brow[tid] = n < a.ntot ? (int64_t)a.members[n] : -1;
+  }
+  __syncthreads();
+
+  // global -> LDS staging: 512 rows (256 of Z, 256 gathered) x 64 BF16 = 8 x 16 B each;
+  // thread t loads rows (t >> 3) + 64 i, 16-byte segment (t & 7).
+  const int seg = tid & 7, rbase = tid >> 3;
+  const uint4* srcp[8];
+  bool valid[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int r = rbase + 64 * i;  // 0..511
+    int64_t grow;
+    if (r < kBM) {
+      grow = row0 + r;
+      valid[i] = grow < a.m;
+    } else {
+      grow = brow[r - kBM];
+      valid[i] = grow >= 0;
+    }
+    srcp[i] = reinterpret_cast<const uint4*>(a.Z + (valid[i] ? grow : 0) * a.ldz) + seg;
+  }
+  uint4 stage[8];
+  auto gload = [&](int64_t kk) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      stage[i] = valid[i] ? srcp[i][kk / 8] : make_uint4(0u, 0u, 0u, 0u);
+  };
+  auto lstore = [&](int buf) {
+    uint16_t* base = smem + (size_t)buf * (kBM + kBN) * kLdsRow;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      *reinterpret_cast<uint4*>(base + (rbase + 64 * i) * kLdsRow + seg * 8) = stage[i];
+  };
+
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 128;
+  f32x16 acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+
+  const int64_t nk = a.kpad / kBK;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  const int l32 = lane & 31, khalf = (lane >> 5) * 8;
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int buf = (int)(kt & 1);
+    if (kt + 1 < nk) gload((kt + 1) * kBK);
+    const uint16_t* As = smem + (size_t)buf * (kBM + kBN) * kLdsRow;
+    const uint16_t* Bs = As + kBM * kLdsRow;
+#pragma unroll
+    for (int ks = 0; ks < kBK; ks += 16) {
+      bf16x8 av[2], bv[4];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        av[i] = *reinterpret_cast<const bf16x8*>(As + (wr + i * 32 + l32) * kLdsRow + ks + khalf);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        bv[j] = *reinterpret_cast<const bf16x8*>(Bs + (wc + j * 32 + l32) * kLdsRow + ks + khalf);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // 32x32x16 result layout: lane l, element v -> row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = row0 + wr + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int col = wc + j * 32 + l32;
+        const int64_t n = n0 + col;
+        if (row < a.m && n < a.ntot) {
+          const int64_t slot = n / a.tau, c = n % a.tau;
+          float val = acc[i][j][v];
+          if (row == brow[col]) val = (float)((double)val + a.lam);
+          a.AS[(slot * a.m + row) * a.ldas + c] = val;
+        }
+      }
+}
+
+constexpr int kRefreshSplit = 32;  // row ranges of Z summed separately in Z^T x
+
+// upart[js][k][0..1] = sum_{j in range js} Z[j][k] * (x[j], xp[j]) in FP64 (FP32 data).
+__global__ void k_gemv_t_pair(const float* __restrict__ Z, int64_t ldz, int64_t m, int64_t K,
+                              const double* __restrict__ x, const double* __restrict__ xp,
+                              double* __restrict__ upart, const int32_t* __restrict__ done) {
+  if (*done) return;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const int64_t per = (m + kRefreshSplit - 1) / kRefreshSplit;
+  const int64_t j0 = min(m, (int64_t)blockIdx.y * per), j1 = min(m, j0 + per);
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t j = j0; j < j1; ++j) {
+    const double z = (double)Z[j * ldz + k];
+    s0 += z * x[j];
+    s1 += z * xp[j];
+  }
+  double* out = upart + ((int64_t)blockIdx.y * K + k) * 2;
+  out[0] = s0;
+  out[1] = s1;
+}
+
+// u[k] = sum over the row ranges in order.
+__global__ void k_sum_upart(const double* __restrict__ upart, int64_t K, double* __restrict__ u,
+                            const int32_t* __restrict__ done) {
+  if (*done) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * K) return;
+  double s = 0.0;
+  for (int js = 0; js < kRefreshSplit; ++js) s += upart[(int64_t)js * 2 * K + i];
+  u[i] = s;
+}
+
+// r[j] = sum_k Z[j][k] u[k][0] + lam x[j] - b[j] (and likewise rp from u[k][1], xp);
+// one wave per row; partial sums of ||r||^2 per workgroup.
+__global__ __launch_bounds__(256) void k_gemv_n_pair_residual(
+    const float* __restrict__ Z, int64_t ldz, int64_t m, int64_t K, const double* __restrict__ u,
+    const double* __restrict__ x, const double* __restrict__ xp, const double* __restrict__ b,
+    double lam, double* __restrict__ r, double* __restrict__ rp, double* __restrict__ partials,
+    const int32_t* __restrict__ done) {
+  __shared__ double scratch[16];
+  if (*done) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.x * 4 + wave;
+  double ss = 0.0;
+  if (j < m) {
+    const float* zr = Z + j * ldz;
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t k = lane; k < K; k += 64) {
+      const double z = (double)zr[k];
+      s0 += z * u[2 * k];
+      s1 += z * u[2 * k + 1];
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    if (lane == 0) {
+      const double rn = s0 + lam * x[j] - b[j];
+      r[j] = rn;
+      rp[j] = s1 + lam * xp[j] - b[j];
+      ss = rn * rn;
+    }
+  }
+  ss = block_sum(ss, scratch);
+  if (threadIdx.x == 0) partials[blockIdx.x] = ss;
+}
+
+__global__ void k_gemv_rows_f32(const float* __restrict__ Z, int64_t ldz, int64_t m, int64_t K,
+                                const double* __restrict__ v, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= m) return;
+  double s = 0.0;
+  for (int64_t k = lane; k < K; k += 64) s += (double)Z[row * ldz + k] * v[k];
+  s = wave_sum(s);
+  if (lane == 0) out[row] = s;
+}
+
+// out[k] = sum_j Z[j][k] v[j] in FP64 (FP32 data), one thread per column.
+__global__ void k_gemv_cols_f32(const float* __restrict__ Z, int64_t ldz, int64_t m, int64_t K,
+                                const double* __restrict__ v, double* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  double s = 0.0;
+  for (int64_t j = 0; j < m; ++j) s += (double)Z[j * ldz + k] * v[j];
+  out[k] = s;
+}
+
+// ||r||^2 from the refresh partials; records it and applies the stop test.
+__global__ __launch_bounds__(256) void k_refresh_norm(const double* __restrict__ partials, int32_t n,
+                                                      DevFlags* __restrict__ flags,
+                                                      double* __restrict__ hist,
+                                                      double* __restrict__ true_hist, int64_t k,
+                                                      double tol) {
+  __shared__ double scratch[16];
+  if (flags->done) return;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += partials[i];
+  s = block_sum(s, scratch);
+  if (threadIdx.x == 0) {
+    const double rel = sqrt(s) / flags->r0norm;
+    hist[k] = rel;
+    true_hist[k] = rel;
+    if (rel <= tol) {
+      flags->k_done = k;
+      flags->done = 1;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_cast_bf16(const void* src, int32_t src_is_f32, int64_t rows_s, int64_t cols_s,
+                            int64_t lds, int32_t trans, uint16_t* dst, int64_t ldd, float* dst32,
+                            int64_t ldd32, hipStream_t s) {
+  const int64_t out_rows = trans ? cols_s : rows_s;
+  // grid covers the padded output columns as well (zero fill)
+  const int64_t gx = trans ? (out_rows + 31) / 32 : (ldd + 31) / 32;
+  const int64_t gy = trans ? (ldd + 31) / 32 : (out_rows + 31) / 32;
+  dim3 grid((unsigned)gx, (unsigned)gy);
+  hipLaunchKernelGGL(k_cast_bf16, grid, dim3(256), 0, s, src, src_is_f32, rows_s, cols_s, lds, trans,
+                     dst, ldd, dst32, ldd32);
+  return hipGetLastError();
+}
+
+hipError_t launch_as_dense_bf16(const uint16_t* Zbf, int64_t ldz, int64_t m, int64_t kpad,
+                                const int32_t* members, int32_t tau, int64_t ldas, int32_t nslots,
+                                double lam, float* AS, const int32_t* done, hipStream_t s) {
+  if (kpad % kBK != 0 || ldz % 8 != 0) return hipErrorInvalidValue;
+  GemmArgs a;
+  a.Z = Zbf;
+  a.ldz = ldz;
+  a.m = m;
+  a.kpad = kpad;
+  a.members = members;
+  a.tau = tau;
+  a.ntot = (int64_t)nslots * tau;
+  a.ldas = ldas;
+  a.lam = lam;
+  a.AS = AS;
+  a.n_row_tiles = (int32_t)((m + kBM - 1) / kBM);
+  a.n_col_tiles = (int32_t)((a.ntot + kBN - 1) / kBN);
+  a.done = done;
+  const int ntiles = a.n_row_tiles * a.n_col_tiles;
+  const int per = (ntiles + kXcds - 1) / kXcds;
+  const size_t bytes = sizeof(uint16_t) * 2 * (kBM + kBN) * kLdsRow;
+  hipError_t e = hipFuncSetAttribute((const void*)k_as_dense_bf16,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_as_dense_bf16, dim3(per * kXcds), dim3(kGemmThreads), bytes, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_refresh(const float* Z32, int64_t ldz, int64_t m, int64_t K, const double* x,
+                          const double* xp, const double* b, double lam, double* r, double* rp,
+                          double* u, double* upart, double* partials, DevFlags* flags, double* hist,
+                          double* true_hist, int64_t k, double tol, const int32_t* done,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_gemv_t_pair, dim3((unsigned)((K + 255) / 256), kRefreshSplit), dim3(256), 0, s,
+                     Z32, ldz, m, K, x, xp, upart, done);
+  hipLaunchKernelGGL(k_sum_upart, dim3((unsigned)((2 * K + 255) / 256)), dim3(256), 0, s, upart, K, u,
+                     done);
+  const unsigned nb = (unsigned)((m + 3) / 4);
+  hipLaunchKernelGGL(k_gemv_n_pair_residual, dim3(nb), dim3(256), 0, s, Z32, ldz, m, K, u, x, xp, b,
+                     lam, r, rp, partials, done);
+  hipLaunchKernelGGL(k_refresh_norm, dim3(1), dim3(256), 0, s, partials, (int32_t)nb, flags, hist,
+                     true_hist, k, tol);
+  return hipGetLastError();
+}
+
+int64_t refresh_partials(int64_t m) { return (m + 3) / 4; }
+
+hipError_t launch_gemv_cols_f32(const float* Z, int64_t ldz, int64_t m, int64_t K, const double* v,
+                                double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_gemv_cols_f32, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, Z, ldz, m, K,
+                     v, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemv_rows_f32(const float* Z, int64_t ldz, int64_t m, int64_t K, const double* v,
+                                double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_gemv_rows_f32, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, Z, ldz, m, K, v,
+                     out);
+  return hipGetLastError();
+}
+int64_t refresh_upart_doubles(int64_t K) { return (int64_t)kRefreshSplit * 2 * K; }
+
+}  // namespace rs

@@ -134,8 +134,34 @@ __global__ __launch_bounds__(kThreads) void k_delta(const double* __restrict__ r
   }
 }
 
+__device__ __forceinline__ double row_dot(const double* __restrict__ AS, int64_t j, int64_t ldas,
+                                          const double* dl, int lane) {
+  const double2* row = reinterpret_cast<const double2*>(AS + j * ldas);
+  const int half = (int)(ldas >> 1);
+  double s = 0.0;
+  for (int c2 = lane; c2 < half; c2 += 64) {
+    const double2 a = row[c2];
+    s += a.x * dl[2 * c2] + a.y * dl[2 * c2 + 1];
+  }
+  return s;
+}
+
+__device__ __forceinline__ double row_dot(const float* __restrict__ AS, int64_t j, int64_t ldas,
+                                          const double* dl, int lane) {
+  const float4* row = reinterpret_cast<const float4*>(AS + j * ldas);
+  const int quarter = (int)(ldas >> 2);
+  double s = 0.0;
+  for (int c4 = lane; c4 < quarter; c4 += 64) {
+    const float4 a = row[c4];
+    s += (double)a.x * dl[4 * c4] + (double)a.y * dl[4 * c4 + 1] + (double)a.z * dl[4 * c4 + 2] +
+         (double)a.w * dl[4 * c4 + 3];
+  }
+  return s;
+}
+
 // One row of the update, computed by one wave; returns r^{k+1}_j in every lane.
-__device__ __forceinline__ double update_row(int64_t j, const double* __restrict__ AS, int64_t ldas,
+template <typename ASV>
+__device__ __forceinline__ double update_row(int64_t j, const ASV* __restrict__ AS, int64_t ldas,
                                              const double* dl, const int32_t* __restrict__ hmap,
                                              const double* __restrict__ x, double* __restrict__ xo,
                                              const double* __restrict__ r, double* __restrict__ ro,
@@ -149,14 +175,7 @@ __device__ __forceinline__ double update_row(int64_t j, const double* __restrict
     xj = x[j];
     xoj = xo[j];
   }
-  const double2* row = reinterpret_cast<const double2*>(AS + j * ldas);
-  const int half = (int)(ldas >> 1);
-  double s = 0.0;
-  for (int c2 = lane; c2 < half; c2 += 64) {
-    const double2 a = row[c2];
-    s += a.x * dl[2 * c2] + a.y * dl[2 * c2 + 1];
-  }
-  s = wave_sum(s);
+  double s = wave_sum(row_dot(AS, j, ldas, dl, lane));
   double rn = 0.0;
   if (lane == 0) {
     double sd = 0.0;
@@ -170,8 +189,9 @@ __device__ __forceinline__ double update_row(int64_t j, const double* __restrict
   return rn;
 }
 
+template <typename ASV>
 struct UpdateArgs {
-  const double* AS;
+  const ASV* AS;
   int64_t ldas;
   int32_t tau;
   const double* delta;
@@ -193,7 +213,8 @@ struct UpdateArgs {
   const DevFlags* flags;
 };
 
-__global__ __launch_bounds__(kUpdateThreads) void k_update(UpdateArgs a) {
+template <typename ASV>
+__global__ __launch_bounds__(kUpdateThreads) void k_update(UpdateArgs<ASV> a) {
   extern __shared__ __align__(16) double dl[];  // [ldas]
   __shared__ double scratch[16];
   __shared__ double part[kBucketWaves];
@@ -208,8 +229,8 @@ __global__ __launch_bounds__(kUpdateThreads) void k_update(UpdateArgs a) {
     double rs = 0.0;
     for (int p = a.offs_n[b] + wave; p < a.offs_n[b + 1]; p += kBucketWaves) {
       const int64_t j = a.members_n[p];
-      const double rn = update_row(j, a.AS, a.ldas, dl, a.hmap, a.x, a.xo, a.r, a.ro, a.gamma, a.beta,
-                                   lane);
+      const double rn = update_row<ASV>(j, a.AS, a.ldas, dl, a.hmap, a.x, a.xo, a.r, a.ro, a.gamma,
+                                        a.beta, lane);
       if (lane == 0) {
         ss += rn * rn;
         rs += (a.hmap_n[j] & 1) ? -rn : rn;
@@ -229,8 +250,8 @@ __global__ __launch_bounds__(kUpdateThreads) void k_update(UpdateArgs a) {
     const int64_t j0 = blk * rows_per_block, j1 = min(a.m, j0 + rows_per_block);
     for (int64_t j = j0 + wave; j < j1; j += (blockDim.x >> 6)) {
       if (a.hmap_n && a.hmap_n[j] >= 0) continue;
-      const double rn = update_row(j, a.AS, a.ldas, dl, a.hmap, a.x, a.xo, a.r, a.ro, a.gamma, a.beta,
-                                   lane);
+      const double rn = update_row<ASV>(j, a.AS, a.ldas, dl, a.hmap, a.x, a.xo, a.r, a.ro, a.gamma,
+                                        a.beta, lane);
       if (lane == 0) ss += rn * rn;
     }
   }
@@ -288,14 +309,15 @@ hipError_t launch_delta(const double* rho, int32_t tau, const double* Ginv, int6
   return hipGetLastError();
 }
 
-hipError_t launch_update(const double* AS, int64_t ldas, int32_t tau, const double* delta,
+template <typename ASV>
+hipError_t update_launch(const ASV* AS, int64_t ldas, int32_t tau, const double* delta,
                          const int32_t* hmap, int64_t m, const double* x, double* x_prev_out,
                          const double* r, double* r_prev_out, double gamma, double beta,
                          double* partials, int32_t npart, const int32_t* hmap_next,
                          const int32_t* members_next, const int32_t* offs_next,
                          int32_t next_covers_all, double* rho_next, const DevFlags* flags,
                          hipStream_t s) {
-  UpdateArgs a;
+  UpdateArgs<ASV> a;
   a.AS = AS;
   a.ldas = ldas;
   a.tau = tau;
@@ -321,8 +343,24 @@ hipError_t launch_update(const double* AS, int64_t ldas, int32_t tau, const doub
   const int32_t grid = tau + nrow_blocks;
   if (grid != npart) return hipErrorInvalidValue;
   // without a next sketch the bucket part is empty: its partial slots are written as zero
-  hipLaunchKernelGGL(k_update, dim3(grid), dim3(kUpdateThreads), sizeof(double) * ldas, s, a);
+  hipLaunchKernelGGL(k_update<ASV>, dim3(grid), dim3(kUpdateThreads), sizeof(double) * ldas, s, a);
   return hipGetLastError();
+}
+
+hipError_t launch_update(const void* AS, int32_t as_f32, int64_t ldas, int32_t tau, const double* delta,
+                         const int32_t* hmap, int64_t m, const double* x, double* x_prev_out,
+                         const double* r, double* r_prev_out, double gamma, double beta,
+                         double* partials, int32_t npart, const int32_t* hmap_next,
+                         const int32_t* members_next, const int32_t* offs_next,
+                         int32_t next_covers_all, double* rho_next, const DevFlags* flags,
+                         hipStream_t s) {
+  if (as_f32)
+    return update_launch<float>((const float*)AS, ldas, tau, delta, hmap, m, x, x_prev_out, r,
+                                r_prev_out, gamma, beta, partials, npart, hmap_next, members_next,
+                                offs_next, next_covers_all, rho_next, flags, s);
+  return update_launch<double>((const double*)AS, ldas, tau, delta, hmap, m, x, x_prev_out, r,
+                               r_prev_out, gamma, beta, partials, npart, hmap_next, members_next,
+                               offs_next, next_covers_all, rho_next, flags, s);
 }
 
 hipError_t launch_finalize(const double* partials, int32_t npart, DevFlags* flags, double* hist,

@@ -34,6 +34,15 @@ struct rs_handle {
   // Z (m x K): dense row-major, or CSR of Z and of Z^T.
   double* Z = nullptr;
   int64_t ldz = 0;
+  // mixed precision: BF16 copy (ld kpad, a multiple of 64) and FP32 copy (ld K)
+  bool mixed = false;
+  uint16_t* Zbf = nullptr;
+  int64_t kpad = 0;
+  float* Z32 = nullptr;
+  double* ref_u = nullptr;
+  double* ref_upart = nullptr;
+  double* ref_partials = nullptr;
+  double* true_hist = nullptr;
   int64_t* zr_ptr = nullptr;
   int32_t* zr_col = nullptr;
   void* zr_val = nullptr;
@@ -57,7 +66,7 @@ struct rs_handle {
   int32_t* members = nullptr;
   int32_t* offs = nullptr;
   uint64_t* keys = nullptr;
-  double* AS = nullptr;
+  void* AS = nullptr;  // FP64, or FP32 in mixed precision
   double* G = nullptr;
   double* W = nullptr;
   int32_t* status = nullptr;
@@ -183,6 +192,17 @@ void prof_collect(rs_handle* h) {
   h->ev_used = 0;
 }
 
+// Mixed precision: r^k and r^{k-1} recomputed in FP64 from x^k, x^{k-1}; stop test on it.
+void refresh(rs_handle* h, int64_t k) {
+  const int pe = prof_begin(h, RS_PROF_REFRESH, 1, 2);
+  check_hip(launch_refresh(h->Z32, h->K, h->m, h->K, h->xbuf[k & 1], h->xbuf[(k + 1) & 1], h->b,
+                           h->lam, h->rbuf[k & 1], h->rbuf[(k + 1) & 1], h->ref_u, h->ref_upart,
+                           h->ref_partials, h->flags, h->hist, h->true_hist, k, h->opt.tol,
+                           &h->flags->done, h->stream),
+            "refresh");
+  prof_end(h, pe);
+}
+
 void run_batch(rs_handle* h, int64_t k0, int nb) {
   hipStream_t s = h->stream;
   const int32_t* done = &h->flags->done;
@@ -213,18 +233,22 @@ void run_batch(rs_handle* h, int64_t k0, int nb) {
   if (h->sparse) {
     check_hip(launch_as_sparse(h->zr_ptr, h->zr_col, h->zr_val, h->zt_ptr, h->zt_col, h->zt_val,
                                h->vals_f32, h->nnz, h->m, h->tau, h->ldas, nb, h->kind, h->lam,
-                               h->hmap, h->members, h->offs, h->nsel, h->tbuf, h->AS, h->G, h->ldg,
-                               done, s),
+                               h->hmap, h->members, h->offs, h->nsel, h->tbuf, (double*)h->AS, h->G,
+                               h->ldg, done, s),
               "AS (sparse)");
+  } else if (h->mixed) {
+    check_hip(launch_as_dense_bf16(h->Zbf, h->kpad, h->m, h->kpad, h->members, h->tau, h->ldas, nb,
+                                   h->lam, (float*)h->AS, done, s),
+              "AS (dense, BF16)");
   } else {
     check_hip(launch_as_dense_f64(h->Z, h->ldz, h->m, h->K, h->members, h->tau, h->ldas, nb, h->lam,
-                                  h->AS, done, s),
+                                  (double*)h->AS, done, s),
               "AS (dense)");
   }
   prof_end(h, pe);
   pe = prof_begin(h, RS_PROF_CHOL, nb);
-  check_hip(launch_chol_inverse(h->G, h->W, h->ldg, h->tau, nb, h->kind, h->AS, h->ldas, h->m,
-                                h->members, h->offs, h->status, done, s),
+  check_hip(launch_chol_inverse(h->G, h->W, h->ldg, h->tau, nb, h->kind, h->AS, h->mixed ? 1 : 0,
+                                h->ldas, h->m, h->members, h->offs, h->status, done, s),
             "cholesky");
   prof_end(h, pe);
   // rho_{k0} = S_{k0}^T r^{k0}; later iterations get rho from the preceding update
@@ -238,13 +262,16 @@ void run_batch(rs_handle* h, int64_t k0, int nb) {
     const int cur = (int)(k & 1), nxt = 1 - cur;
     const int32_t* hm = h->hmap + (int64_t)i * h->m;
     pe = prof_begin(h, RS_PROF_DELTA, 1, 2);
+    // mixed precision: the tracked residual drifts, so only the refreshed one may stop
     check_hip(launch_delta(h->rho, h->tau, h->G + (int64_t)i * h->ldg * h->ldg, h->ldg, h->partials,
-                           h->npart, h->flags, h->hist, k, h->opt.tol, h->delta, s),
+                           h->npart, h->flags, h->hist, k, h->mixed ? -1.0 : h->opt.tol, h->delta, s),
               "delta");
     prof_end(h, pe);
     pe = prof_begin(h, RS_PROF_UPDATE, 1, 2);
     const bool has_next = i + 1 < nb;
-    check_hip(launch_update(h->AS + (int64_t)i * h->m * h->ldas, h->ldas, h->tau, h->delta, hm, h->m,
+    const size_t as_elt = h->mixed ? sizeof(float) : sizeof(double);
+    const void* as_i = (const char*)h->AS + (size_t)i * h->m * h->ldas * as_elt;
+    check_hip(launch_update(as_i, h->mixed ? 1 : 0, h->ldas, h->tau, h->delta, hm, h->m,
                             h->xbuf[cur], h->xbuf[nxt], h->rbuf[cur], h->rbuf[nxt], gamma, beta,
                             h->partials, h->npart,
                             has_next ? h->hmap + (int64_t)(i + 1) * h->m : nullptr,
@@ -253,6 +280,14 @@ void run_batch(rs_handle* h, int64_t k0, int nb) {
                             h->kind == kCount ? 1 : 0, h->rho, h->flags, s),
               "update");
     prof_end(h, pe);
+    if (h->mixed && (k + 1) % h->opt.refresh_every == 0) {
+      refresh(h, k + 1);
+      if (has_next)
+        check_hip(launch_rho(h->rbuf[(k + 1) & 1], h->hmap + (int64_t)(i + 1) * h->m,
+                             h->members + (int64_t)(i + 1) * h->nsel,
+                             h->offs + (int64_t)(i + 1) * (h->tau + 1), h->tau, h->rho, h->flags, s),
+                  "rho");
+    }
   }
   prof_end(h, pe_iters);
   h->batch_k0 = k0;
@@ -280,9 +315,15 @@ void advance(rs_handle* h, int64_t iters) {
     run_batch(h, k_enq, nb);
     k_enq += nb;
     left -= nb;
-    if (left == 0)
-      check_hip(launch_finalize(h->partials, h->npart, h->flags, h->hist, k_enq, h->opt.tol, h->stream),
-                "finalize");
+    if (left == 0) {
+      if (h->mixed) {
+        if (k_enq % h->opt.refresh_every != 0) refresh(h, k_enq);
+      } else {
+        check_hip(launch_finalize(h->partials, h->npart, h->flags, h->hist, k_enq, h->opt.tol,
+                                  h->stream),
+                  "finalize");
+      }
+    }
     DevFlags f{};
     int32_t err = 0;
     check_hip(hipMemcpyAsync(&f, h->flags, sizeof(DevFlags), hipMemcpyDeviceToHost, h->stream), "flags");
@@ -376,7 +417,13 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
     if (X->layout == RS_CSR && (!X->row_ptr || !X->col_idx || X->nnz < 0))
       throw Fail{RS_EINVAL, "CSR needs row_ptr, col_idx and nnz >= 0"};
     if (n > INT32_MAX || d > INT32_MAX) throw Fail{RS_EINVAL, "n and d must fit in int32"};
-    if (o->precision != RS_PREC_FP64) throw Fail{RS_EUNSUPPORTED, "only RS_PREC_FP64 is built"};
+    if (o->precision != RS_PREC_FP64 && o->precision != RS_PREC_MIXED_BF16)
+      throw Fail{RS_EINVAL, "unknown precision"};
+    if (o->precision == RS_PREC_MIXED_BF16 && X->layout == RS_CSR)
+      throw Fail{RS_EUNSUPPORTED, "mixed precision is built for dense data (subsample sketch)"};
+    if (o->precision == RS_PREC_MIXED_BF16 && o->refresh_every < 1)
+      throw Fail{RS_EINVAL, "refresh_every must be >= 1"};
+    h->mixed = o->precision == RS_PREC_MIXED_BF16;
     if (o->momentum < RS_MOMENTUM_NONE || o->momentum > RS_MOMENTUM_HEURISTIC)
       throw Fail{RS_EINVAL, "unknown momentum"};
     if (!(o->tol >= 0.0)) throw Fail{RS_EINVAL, "tol must be >= 0"};
@@ -438,11 +485,30 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
       check_hip(hipMemcpyAsync(xv, X->vals, total * esz,
                                X->mem == RS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s),
                 "X upload");
-      h->ldz = h->K;
-      h->Z = dalloc<double>(h, (size_t)h->m * h->ldz);
       // Z = X^T (primal) or X (dual), row-major m x K
       const bool rowmajor = X->layout == RS_DENSE_ROWMAJOR;
       const bool need_transpose = (h->form == RS_FORM_PRIMAL) == rowmajor;
+      if (h->mixed) {
+        h->kpad = (h->K + 63) / 64 * 64;
+        h->Zbf = dalloc<uint16_t>(h, (size_t)h->m * h->kpad);
+        h->Z32 = dalloc<float>(h, (size_t)h->m * h->K);
+        const int64_t rows = rowmajor ? n : d, cols = rowmajor ? d : n;
+        check_hip(launch_cast_bf16(xv, f32, rows, cols, cols, need_transpose ? 1 : 0, h->Zbf, h->kpad,
+                                   h->Z32, h->K, s),
+                  "BF16 copy");
+        if (h->form == RS_FORM_PRIMAL)
+          check_hip(launch_gemv_rows_f32(h->Z32, h->K, h->m, h->K, yd, h->b, s), "b = X^T y");
+        else
+          check_hip(hipMemcpyAsync(h->b, yd, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "b = y");
+        h->ref_u = dalloc<double>(h, 2 * h->K);
+        h->ref_upart = dalloc<double>(h, refresh_upart_doubles(h->K));
+        h->ref_partials = dalloc<double>(h, refresh_partials(h->m));
+        check_hip(hipStreamSynchronize(s), "sync");
+        (void)hipFree(xv);
+        h->allocs.erase(std::find(h->allocs.begin(), h->allocs.end(), xv));
+      } else {
+      h->ldz = h->K;
+      h->Z = dalloc<double>(h, (size_t)h->m * h->ldz);
       if (need_transpose) {
         // source viewed row-major: rowmajor -> n x d, colmajor -> d x n
         const int64_t rows = rowmajor ? n : d, cols = rowmajor ? d : n;
@@ -455,6 +521,7 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
         check_hip(launch_gemv_rows(h->Z, h->ldz, h->m, h->K, yd, h->b, s), "b = X^T y");
       else
         check_hip(hipMemcpyAsync(h->b, yd, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "b = y");
+      }
     } else {
       const int64_t nnz = X->nnz;
       if (nnz > INT32_MAX) throw Fail{RS_EINVAL, "nnz must fit in int32"};
@@ -502,7 +569,8 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
     h->ldg = ((int64_t)h->tau + 63) / 64 * 64;
     h->ldas = ((int64_t)h->tau + 7) / 8 * 8;
     const size_t per_slot = (h->sparse ? sparse_t_bytes(h->vals_f32, h->nnz) : 0) +
-                            sizeof(double) * ((size_t)h->m * h->ldas + 2 * (size_t)h->ldg * h->ldg) +
+                            (h->mixed ? sizeof(float) : sizeof(double)) * (size_t)h->m * h->ldas +
+                            sizeof(double) * 2 * (size_t)h->ldg * h->ldg +
                             sizeof(int32_t) * ((size_t)h->m + h->nsel + h->tau + 1) +
                             sizeof(uint64_t) * (size_t)h->m;
     int B = o->lookahead > 0 ? o->lookahead : 256;
@@ -513,9 +581,10 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
     h->members = dalloc<int32_t>(h, (size_t)B * h->nsel);
     h->offs = dalloc<int32_t>(h, (size_t)B * (h->tau + 1));
     h->keys = dalloc<uint64_t>(h, (size_t)B * h->m);
-    h->AS = dalloc<double>(h, (size_t)B * h->m * h->ldas);
+    const size_t as_bytes = (h->mixed ? sizeof(float) : sizeof(double)) * (size_t)B * h->m * h->ldas;
+    h->AS = dalloc<char>(h, as_bytes);
     // the padding columns of AS are read (times a zero delta) by the update: keep them zero
-    check_hip(hipMemsetAsync(h->AS, 0, sizeof(double) * (size_t)B * h->m * h->ldas, s), "memset");
+    check_hip(hipMemsetAsync(h->AS, 0, as_bytes, s), "memset");
     h->rho = dalloc<double>(h, h->ldg);
     if (h->sparse) h->tbuf = dalloc<char>(h, (size_t)B * sparse_t_bytes(h->vals_f32, h->nnz));
     h->G = dalloc<double>(h, (size_t)B * h->ldg * h->ldg);
@@ -526,6 +595,7 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
     h->partials = dalloc<double>(h, h->npart);
     h->hist_len = h->opt.max_iter + 1;
     h->hist = dalloc<double>(h, h->hist_len);
+    h->true_hist = dalloc<double>(h, h->hist_len);
     h->flags = dalloc<DevFlags>(h, 1);
     h->err = dalloc<int32_t>(h, 1);
     for (int i = 0; i < 2; ++i) {
@@ -569,7 +639,9 @@ rs_status rs_step(rs_handle* h, int64_t iters, double* rel_res_out) {
     if (iters > 0) advance(h, iters);
     if (rel_res_out) {
       double v = 1.0;
-      check_hip(hipMemcpy(&v, h->hist + h->k, sizeof(double), hipMemcpyDeviceToHost), "hist");
+      // mixed precision reports the FP64-refreshed residual (the tracked one drifts)
+      const double* src = (h->mixed && h->k > 0) ? h->true_hist : h->hist;
+      check_hip(hipMemcpy(&v, src + h->k, sizeof(double), hipMemcpyDeviceToHost), "hist");
       *rel_res_out = v;
     }
     return RS_OK;
@@ -628,7 +700,8 @@ rs_status rs_get_weights(rs_handle* h, double* w_out) {
       check_hip(hipMalloc(&wd, sizeof(double) * h->d), "alloc");
       hipError_t e = h->sparse ? launch_spmv_csr(h->zt_ptr, h->zt_col, h->zt_val, h->vals_f32, h->d, x, wd,
                                                  h->stream)
-                               : launch_gemv_cols(h->Z, h->ldz, h->m, h->K, x, wd, h->stream);
+                     : h->mixed ? launch_gemv_cols_f32(h->Z32, h->K, h->m, h->K, x, wd, h->stream)
+                                : launch_gemv_cols(h->Z, h->ldz, h->m, h->K, x, wd, h->stream);
       if (e == hipSuccess)
         e = hipMemcpyAsync(w_out, wd, sizeof(double) * h->d, hipMemcpyDeviceToHost, h->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -650,7 +723,8 @@ rs_status rs_solve(rs_handle* h, double* w_out, rs_report* rep) {
     advance(h, h->opt.max_iter - h->k);
     const auto t1 = std::chrono::steady_clock::now();
     double rel = 1.0;
-    check_hip(hipMemcpy(&rel, h->hist + h->k, sizeof(double), hipMemcpyDeviceToHost), "hist");
+    const double* src = (h->mixed && h->k > 0) ? h->true_hist : h->hist;
+    check_hip(hipMemcpy(&rel, src + h->k, sizeof(double), hipMemcpyDeviceToHost), "hist");
     if (rep) {
       rep->iters = h->k;
       rep->rel_res = rel;
@@ -699,6 +773,35 @@ rs_status rs_get_last_sketch(const rs_handle* h, int32_t* rows, int32_t* cols, i
       ++c;
     }
   *nnz_out = c;
+  return RS_OK;
+}
+
+rs_status rs_get_products(const rs_handle* h, double* as_out, double* ginv_out) {
+  if (!h) return RS_EINVAL;
+  const int64_t it = h->k - 1;
+  if (it < 0 || h->batch_k0 < 0 || it < h->batch_k0 || it >= h->batch_k0 + h->batch_n) return RS_EINVAL;
+  const int64_t slot = it - h->batch_k0;
+  if (as_out) {
+    const size_t elt = h->mixed ? sizeof(float) : sizeof(double);
+    std::vector<char> buf((size_t)h->m * h->ldas * elt);
+    if (hipMemcpy(buf.data(), (const char*)h->AS + (size_t)slot * h->m * h->ldas * elt, buf.size(),
+                  hipMemcpyDeviceToHost) != hipSuccess)
+      return RS_EDEVICE;
+    for (int64_t j = 0; j < h->m; ++j)
+      for (int64_t c = 0; c < h->tau; ++c) {
+        const size_t idx = (size_t)j * h->ldas + c;
+        as_out[j * h->tau + c] = h->mixed ? (double)((const float*)buf.data())[idx]
+                                          : ((const double*)buf.data())[idx];
+      }
+  }
+  if (ginv_out) {
+    std::vector<double> g((size_t)h->ldg * h->ldg);
+    if (hipMemcpy(g.data(), h->G + (size_t)slot * h->ldg * h->ldg, sizeof(double) * g.size(),
+                  hipMemcpyDeviceToHost) != hipSuccess)
+      return RS_EDEVICE;
+    for (int64_t r = 0; r < h->tau; ++r)
+      for (int64_t c = 0; c < h->tau; ++c) ginv_out[r * h->tau + c] = g[(size_t)r * h->ldg + c];
+  }
   return RS_OK;
 }
 

@@ -79,10 +79,34 @@ hipError_t launch_as_sparse(const int64_t* zr_ptr, const int32_t* zr_col, const 
                             double* AS, double* G, int64_t ldg, const int32_t* done, hipStream_t s);
 
 // Ginv[slot] = (S^T A S)^{-1} (padded ldg x ldg, identity on empty buckets and padding).
+// AS is FP64, or FP32 when as_f32 (mixed precision).
 hipError_t launch_chol_inverse(double* G, double* W, int64_t ldg, int32_t tau, int32_t nslots,
-                               int32_t kind, const double* AS, int64_t ldas, int64_t m,
+                               int32_t kind, const void* AS, int32_t as_f32, int64_t ldas, int64_t m,
                                const int32_t* members, const int32_t* offs, int32_t* status,
                                const int32_t* done, hipStream_t s);
+
+// Mixed precision (dense subsample): BF16 copy of Z (ld multiple of 64, zero padded)
+// and FP32 copy (ld = K), from src viewed row-major rows_s x cols_s (trans: Z = src^T).
+hipError_t launch_cast_bf16(const void* src, int32_t src_is_f32, int64_t rows_s, int64_t cols_s,
+                            int64_t lds, int32_t trans, uint16_t* dst, int64_t ldd, float* dst32,
+                            int64_t ldd32, hipStream_t s);
+// AS[slot] (FP32, row stride ldas) = Zbf Zbf[C_slot,:]^T + lambda I_C on BF16 MFMA.
+hipError_t launch_as_dense_bf16(const uint16_t* Zbf, int64_t ldz, int64_t m, int64_t kpad,
+                                const int32_t* members, int32_t tau, int64_t ldas, int32_t nslots,
+                                double lam, float* AS, const int32_t* done, hipStream_t s);
+// FP64 recomputation r = Z (Z^T x) + lambda x - b (and rp from xp) from the FP32 copy;
+// records ||r|| / ||r^0|| at k and applies the stop test.
+int64_t refresh_partials(int64_t m);
+int64_t refresh_upart_doubles(int64_t K);
+hipError_t launch_refresh(const float* Z32, int64_t ldz, int64_t m, int64_t K, const double* x,
+                          const double* xp, const double* b, double lam, double* r, double* rp,
+                          double* u, double* upart, double* partials, DevFlags* flags, double* hist,
+                          double* true_hist, int64_t k, double tol, const int32_t* done,
+                          hipStream_t s);
+hipError_t launch_gemv_rows_f32(const float* Z, int64_t ldz, int64_t m, int64_t K, const double* v,
+                                double* out, hipStream_t s);  // out = Z v, FP64 accumulation
+hipError_t launch_gemv_cols_f32(const float* Z, int64_t ldz, int64_t m, int64_t K, const double* v,
+                                double* out, hipStream_t s);  // out = Z^T v, FP64 accumulation
 
 // Solve-state kernels.
 int32_t update_partials(int64_t m, int32_t tau);  // partial sums written by k_update
@@ -95,7 +119,7 @@ hipError_t launch_rho(const double* r, const int32_t* hmap, const int32_t* membe
 hipError_t launch_delta(const double* rho, int32_t tau, const double* Ginv, int64_t ldg,
                         const double* partials, int32_t npart, DevFlags* flags, double* hist,
                         int64_t k, double tol, double* delta, hipStream_t s);
-hipError_t launch_update(const double* AS, int64_t ldas, int32_t tau, const double* delta,
+hipError_t launch_update(const void* AS, int32_t as_f32, int64_t ldas, int32_t tau, const double* delta,
                          const int32_t* hmap, int64_t m, const double* x, double* x_prev_out,
                          const double* r, double* r_prev_out, double gamma, double beta,
                          double* partials, int32_t npart, const int32_t* hmap_next,

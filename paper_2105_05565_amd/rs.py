@@ -84,6 +84,7 @@ SIGNATURES = {
     "rs_get_weights": (ctypes.c_int32, [_P, _P]),
     "rs_get_last_sketch": (ctypes.c_int32, [_P, _P, _P, _P, ctypes.POINTER(ctypes.c_int64)]),
     "rs_get_history": (ctypes.c_int32, [_P, _P, ctypes.c_int64]),
+    "rs_get_products": (ctypes.c_int32, [_P, _P, _P]),
     "rs_destroy": (ctypes.c_int32, [_P]),
     "rs_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "rs_last_error": (ctypes.c_char_p, [_P]),
@@ -202,6 +203,10 @@ def rs_get_last_sketch(h, rows, cols, signs):
     return nnz.value
 
 
+def rs_get_products(h, as_out=None, ginv_out=None):
+    _check(load().rs_get_products(h, _ptr(as_out), _ptr(ginv_out)), "rs_get_products", h)
+
+
 def rs_get_history(h, out, count):
     _check(load().rs_get_history(h, _ptr(out), int(count)), "rs_get_history", h)
 
@@ -295,6 +300,7 @@ class Solver:
         self.h = rs_create(M, yv, lam, o)
         self.m = rs_system_size(self.h)
         self.d = int(M.d)
+        self.tau = int(tau)
 
     def reset(self, seed):
         rs_reset(self.h, seed)
@@ -330,6 +336,14 @@ class Solver:
         signs = np.zeros(self.m, dtype=np.int8)
         n = rs_get_last_sketch(self.h, rows, cols, signs)
         return rows[:n].astype(np.int64), cols[:n].astype(np.int64), signs[:n].astype(np.float64)
+
+    def products(self):
+        """(AS, G^{-1}) of the last iteration's sketch, as FP64 arrays."""
+        tau = self.tau
+        AS = np.zeros((self.m, tau))
+        Gi = np.zeros((tau, tau))
+        rs_get_products(self.h, AS, Gi)
+        return AS, Gi
 
     def history(self):
         out = np.zeros(self.k + 1)
