@@ -27,12 +27,19 @@ FP64_PEAK_TFS = 78.6        # MI355X FP64 (vector and matrix)
 BF16_PEAK_TFS = 2500.0      # MI355X dense BF16 MFMA
 
 WORKLOADS = {
-    "sparse_count": dict(kind="csr", sketch="count", tau=500, sub_k=0,
+    "sparse_count": dict(kind="csr", gen="sparse_csr", sketch="count", tau=500, sub_k=0, precision="fp64",
                          name="csr_100000x20000_density0.001_count_tau500_primal"),
-    "sparse_subcount": dict(kind="csr", sketch="subcount", tau=500, sub_k=4,
+    "sparse_subcount": dict(kind="csr", gen="sparse_csr", sketch="subcount", tau=500, sub_k=4,
+                            precision="fp64",
                             name="csr_100000x20000_density0.001_subcount_s2000_tau500_primal"),
-    "dense_primal": dict(kind="dense", sketch="subsample", tau=50, sub_k=0,
-                         name="dense_2000x500_subsample_tau50_primal"),
+    "dense_primal": dict(kind="dense", gen="dense_primal", sketch="subsample", tau=50, sub_k=0,
+                         precision="fp64", name="dense_2000x500_subsample_tau50_primal"),
+    "dense_mixed": dict(kind="dense", gen="dense_mixed", sketch="subsample", tau=1024, sub_k=0,
+                        precision="mixed",
+                        name="dense_50000x8192_lognormal1_subsample_tau1024_primal_bf16_refresh20"),
+    "dense_mixed_fp64": dict(kind="dense", gen="dense_mixed", sketch="subsample", tau=1024, sub_k=0,
+                             precision="fp64",
+                             name="dense_50000x8192_lognormal1_subsample_tau1024_primal_fp64"),
 }
 
 
@@ -52,10 +59,11 @@ def algorithmic_bytes(cls, wl, n, d, nnz, m, K, tau, nsel):
             # bucket map, AS written once (FP64), G = S^T A S written once (FP64)
             return 2 * nnz * 8 + (m + 1) * 8 + (K + 1) * 8 + m * 4 + m * tau * 8 + tau * tau * 8
         # dense subsample: Z read once (m x K) + gathered rows (tau x K) + AS written
-        return m * K * 8 + tau * K * 8 + m * tau * 8
+        elt = 2 if wl["precision"] == "mixed" else 8
+        return m * K * elt + tau * K * elt + m * tau * (4 if wl["precision"] == "mixed" else 8)
     if cls == "update":
         # AS read, bucket map, x^k, x^{k-1}, r^k, r^{k-1} read, two vectors written, delta
-        return m * tau * 8 + m * 4 + 4 * m * 8 + 2 * m * 8 + tau * 8
+        return m * tau * (4 if wl["precision"] == "mixed" else 8) + m * 4 + 4 * m * 8 + 2 * m * 8 + tau * 8
     if cls == "delta":
         return tau * tau * 8 + nsel * (4 + 4 + 8) + tau * 4 + tau * 8
     if cls == "sketch":
@@ -70,9 +78,7 @@ def algorithmic_bytes(cls, wl, n, d, nnz, m, K, tau, nsel):
 
 def make_problem(wl):
     from paper_2105_05565_amd import inputs
-    if wl["kind"] == "csr":
-        return inputs.sparse_csr()
-    return inputs.dense_primal()
+    return getattr(inputs, wl["gen"])()
 
 
 def cpu_baseline(p, wl, gpu_iters_median, sample_s):
@@ -87,7 +93,7 @@ def cpu_baseline(p, wl, gpu_iters_median, sample_s):
         opts = Options(sketch=wl["sketch"], tau=wl["tau"], sum_size=wl["sub_k"], momentum="heuristic",
                        seed=1, tol=1e-6)
         t0 = time.perf_counter()
-        while time.perf_counter() - t0 < sample_s and st.history[-1] > 1e-6:
+        while (st.k == 0 or time.perf_counter() - t0 < sample_s) and st.history[-1] > 1e-6:
             step(system, st, opts)
         el = time.perf_counter() - t0
     per_iter = el / st.k
@@ -107,6 +113,8 @@ def main():
     ap.add_argument("--lookahead", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-s", type=float, default=15.0)
+    ap.add_argument("--max-iter", type=int, default=200000,
+                    help="iteration cap per solve (a capped run reports per-iteration throughput)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver is single-GPU.",
@@ -137,8 +145,8 @@ def main():
 
     t0 = time.perf_counter()
     S = rs.Solver(X, y, p.lam, tau=wl["tau"], sketch=wl["sketch"], form="primal", momentum="heuristic",
-                  subcount_k=wl["sub_k"], tol=1e-6, max_iter=200000, seed=1,
-                  lookahead=args.lookahead, profile=1, stream=stream)
+                  subcount_k=wl["sub_k"], tol=1e-6, max_iter=args.max_iter, seed=1,
+                  precision=wl["precision"], lookahead=args.lookahead, profile=1, stream=stream)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     m, K = d, n
@@ -170,8 +178,8 @@ def main():
 
     # one more solve, untimed, with every launch bracketed by events (per-launch breakdown)
     S2 = rs.Solver(X, y, p.lam, tau=wl["tau"], sketch=wl["sketch"], form="primal", momentum="heuristic",
-                   subcount_k=wl["sub_k"], tol=1e-6, max_iter=200000, seed=1,
-                   lookahead=args.lookahead, profile=2, stream=stream)
+                   subcount_k=wl["sub_k"], tol=1e-6, max_iter=args.max_iter, seed=1,
+                   precision=wl["precision"], lookahead=args.lookahead, profile=2, stream=stream)
     S2.solve()
     prof2 = S2.profile()
     S2.close()
@@ -189,7 +197,7 @@ def main():
                         "avg_ms": round(avg_ms, 5), "alg_bytes_per_launch": int(b),
                         "gbs": round(b / (avg_ms * 1e-3) / 1e9, 1) if avg_ms > 0 else None,
                         "share_of_timed": round(v["ms"] / (total * 1e3), 4)}
-    dom = max(kernels, key=lambda c: kernels[c]["total_ms"])
+    dom = max((c for c in kernels if c != "iters"), key=lambda c: kernels[c]["total_ms"])
     kd = kernels[dom]
     achieved = kd["gbs"]
     roofline = {"kernel": {"as": "k_as_sparse_bucket" if wl["kind"] == "csr" else "k_as_dense_f64",
@@ -199,6 +207,14 @@ def main():
                 "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None, "traffic": None,
                 "alg_bytes_per_launch": kd["alg_bytes_per_launch"], "avg_launch_ms": kd["avg_ms"]}
+    if wl["kind"] == "dense" and dom == "as":
+        flops = 2.0 * m * wl["tau"] * K * kd["slots_per_launch"]
+        tfs = flops / (kd["avg_ms"] * 1e-3) / 1e12
+        peak = BF16_PEAK_TFS if wl["precision"] == "mixed" else FP64_PEAK_TFS
+        roofline.update({"kernel": "k_as_dense_bf16" if wl["precision"] == "mixed" else "k_as_dense_f64",
+                         "bound": "mfma", "achieved": round(tfs, 1), "peak": peak, "unit": "TFLOP/s",
+                         "frac": round(tfs / peak, 4), "alg_flops_per_launch": flops,
+                         "hbm_gbs_algorithmic": kd["gbs"]})
     traffic_file = os.path.join(ROOT, "profiles", f"traffic_{roofline['kernel']}_{args.workload}.json")
     if os.path.exists(traffic_file):
         tf = json.load(open(traffic_file))
@@ -210,11 +226,13 @@ def main():
     out = {
         "metric": "time-to-rel-residual 1e-6", "value": round(T, 6), "unit": "s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(T * 1e3, 3),
-        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 products, f32 accumulate, f64 solve" if wl["precision"] == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": wl["name"], "n": n, "d": d, "nnz": nnz, "form": "primal",
                    "sketch": wl["sketch"], "tau": wl["tau"], "subcount_k": wl["sub_k"],
-                   "lambda": p.lam, "momentum": "heuristic", "tol": 1e-6, "precision": "fp64"},
+                   "lambda": p.lam, "momentum": "heuristic", "tol": 1e-6,
+                   "precision": wl["precision"], "max_iter": args.max_iter},
         "iters_per_s": round(tot_iters / total, 1),
         "iters_median": statistics.median(iters),
         "time_s_quartiles": [round(q, 6) for q in statistics.quantiles(times, n=4)] if len(times) > 1 else times,

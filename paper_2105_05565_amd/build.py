@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "librs.so")
-SOURCES = ["k_sketch.hip", "k_dense.hip", "k_dense_bf16.hip", "k_sparse.hip", "k_chol.hip",
+SOURCES = ["k_sketch.hip", "k_dense.hip", "k_dense_bf16.hip", "k_sparse.hip", "k_chol.hip", "k_chol_multi.hip",
            "k_update.hip", "rs_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

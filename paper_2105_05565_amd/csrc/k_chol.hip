@@ -18,72 +18,14 @@
 //      panel L_ik = G_ik U_kk, trailing update G_ij -= L_ik L_jk^T;
 //   2. U_ji = -(sum_{k=j}^{i-1} U_jk L_ik^T) U_ii for i > j  (U = (L^{-1})^T);
 //   3. G^{-1} = U U^T, tile (i, j) = sum_{k >= max(i,j)} U_ik U_jk^T, both triangles.
+#include "chol_tiles.h"
 #include "dev_common.h"
 #include "rs_internal.h"
 
 namespace rs {
 namespace {
 
-constexpr int NB = 64;
-constexpr int LDT = NB + 1;  // LDS row stride (odd: fewer bank conflicts)
-constexpr int kThreads = 256;
-
-typedef double d4v __attribute__((ext_vector_type(4)));
-
-struct Acc {
-  d4v v[2][2];
-};
-
-__device__ __forceinline__ void acc_zero(Acc& c) {
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) c.v[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
-}
-
-// dst[r][c] = src[r * ld + c]  (trans: src[c * ld + r]) for a 64 x 64 tile.
-__device__ __forceinline__ void load_tile(double* dst, const double* src, int64_t ld, bool trans) {
-  for (int e = threadIdx.x; e < NB * NB; e += kThreads) {
-    const int r = e >> 6, c = e & 63;
-    dst[r * LDT + c] = trans ? src[(int64_t)c * ld + r] : src[(int64_t)r * ld + c];
-  }
-}
-
-// C += A * B^T with A = a[r][k], B = b[c][k] (both 64 x 64 in LDS), K = 64.
-// Wave w owns rows 32 (w / 2) .. +32 and columns 32 (w % 2) .. +32 of C.
-__device__ __forceinline__ void tile_mma(Acc& c, const double* a, const double* b) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  const int l16 = lane & 15, lk = lane >> 4;
-#pragma unroll 4
-  for (int k4 = 0; k4 < NB; k4 += 4) {
-    double av[2], bv[2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) av[i] = a[(wr + i * 16 + l16) * LDT + k4 + lk];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) bv[j] = b[(wc + j * 16 + l16) * LDT + k4 + lk];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-        c.v[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], c.v[i][j], 0, 0, 0);
-  }
-}
-
-// Visit the accumulator elements: f(row, col, value) with (row, col) inside the tile.
-// 16x16x4 FP64 MFMA result layout: lane l, element v -> row 4 v + l / 16, column l % 16.
-template <class F>
-__device__ __forceinline__ void acc_for_each(const Acc& c, F f) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        f(wr + i * 16 + 4 * v + (lane >> 4), wc + j * 16 + (lane & 15), c.v[i][j][v]);
-}
+using namespace chol;
 
 template <typename ASV>
 __global__ __launch_bounds__(kThreads) void k_chol_inverse(double* __restrict__ Gall,

@@ -69,6 +69,7 @@ struct rs_handle {
   void* AS = nullptr;  // FP64, or FP32 in mixed precision
   double* G = nullptr;
   double* W = nullptr;
+  double* Xd = nullptr;  // inverted diagonal tiles (tiled factorisation scratch)
   int32_t* status = nullptr;
   double* delta = nullptr;
   double* partials = nullptr;
@@ -169,6 +170,7 @@ T* to_device(rs_handle* h, const void* src, size_t count, int mem) {
 // Event pair around one launch when profiling: returns the pair index or -1.
 int prof_begin(rs_handle* h, int cls, int slots, int level = 1) {
   if (h->opt.profile < level) return -1;
+  if (2 * (h->ev_used + 1) > (int)h->ev.size()) return -1;  // pool full: leave untimed
   const int i = h->ev_used++;
   h->ev_cls[i] = cls;
   h->ev_slots[i] = slots;
@@ -247,9 +249,16 @@ void run_batch(rs_handle* h, int64_t k0, int nb) {
   }
   prof_end(h, pe);
   pe = prof_begin(h, RS_PROF_CHOL, nb);
-  check_hip(launch_chol_inverse(h->G, h->W, h->ldg, h->tau, nb, h->kind, h->AS, h->mixed ? 1 : 0,
-                                h->ldas, h->m, h->members, h->offs, h->status, done, s),
-            "cholesky");
+  // One workgroup per sketch when the batch fills the chip; otherwise one per tile.
+  if (h->ldg >= 128 && nb < 128)
+    check_hip(launch_chol_multi(h->G, h->W, h->Xd, h->ldg, h->tau, nb, h->kind, h->AS,
+                                h->mixed ? 1 : 0, h->ldas, h->m, h->members, h->offs, h->status, done,
+                                s),
+              "cholesky (tiled)");
+  else
+    check_hip(launch_chol_inverse(h->G, h->W, h->ldg, h->tau, nb, h->kind, h->AS, h->mixed ? 1 : 0,
+                                  h->ldas, h->m, h->members, h->offs, h->status, done, s),
+              "cholesky");
   prof_end(h, pe);
   // rho_{k0} = S_{k0}^T r^{k0}; later iterations get rho from the preceding update
   check_hip(launch_rho(h->rbuf[k0 & 1], h->hmap, h->members, h->offs, h->tau, h->rho, h->flags, s),
@@ -573,7 +582,11 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
                             sizeof(double) * 2 * (size_t)h->ldg * h->ldg +
                             sizeof(int32_t) * ((size_t)h->m + h->nsel + h->tau + 1) +
                             sizeof(uint64_t) * (size_t)h->m;
-    int B = o->lookahead > 0 ? o->lookahead : 256;
+    // Default lookahead: 256 sketches, fewer when one sketch's contraction is large
+    // (the sketches formed past the stopping iteration are wasted work).
+    int B = 256;
+    if (!h->sparse && 2.0 * (double)h->m * (double)h->K * (double)h->tau > 1e11) B = 32;
+    if (o->lookahead > 0) B = o->lookahead;
     const size_t budget = (size_t)48 << 30;
     while (B > 1 && (size_t)B * per_slot > budget) B >>= 1;
     h->B = B;
@@ -589,6 +602,7 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
     if (h->sparse) h->tbuf = dalloc<char>(h, (size_t)B * sparse_t_bytes(h->vals_f32, h->nnz));
     h->G = dalloc<double>(h, (size_t)B * h->ldg * h->ldg);
     h->W = dalloc<double>(h, (size_t)B * h->ldg * h->ldg);
+    h->Xd = reinterpret_cast<double*>(dalloc<char>(h, (size_t)B * chol_multi_x_bytes(h->ldg)));
     h->status = dalloc<int32_t>(h, B);
     h->delta = dalloc<double>(h, h->ldg);
     h->npart = update_partials(h->m, h->tau);
@@ -603,7 +617,8 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
       h->rbuf[i] = dalloc<double>(h, h->m);
     }
     if (o->profile) {
-      const int pairs = 4 + 2 * B;  // sketch, AS, Cholesky, iteration sequence + 2 per iteration
+      // sketch, AS, Cholesky, iteration sequence; delta, update and refresh per iteration
+      const int pairs = 4 + 3 * B + 2;
       h->ev.resize(2 * pairs);
       h->ev_cls.resize(pairs);
       h->ev_slots.resize(pairs);

@@ -85,6 +85,15 @@ hipError_t launch_chol_inverse(double* G, double* W, int64_t ldg, int32_t tau, i
                                const int32_t* members, const int32_t* offs, int32_t* status,
                                const int32_t* done, hipStream_t s);
 
+// Same result computed by a sequence of launches in which every 64 x 64 tile of every
+// sketch is a workgroup (for batches with few sketches or large tau). X holds
+// nslots * chol_multi_x_bytes(ldg) bytes of scratch.
+size_t chol_multi_x_bytes(int64_t ldg);
+hipError_t launch_chol_multi(double* G, double* U, double* X, int64_t ldg, int32_t tau,
+                             int32_t nslots, int32_t kind, const void* AS, int32_t as_f32,
+                             int64_t ldas, int64_t m, const int32_t* members, const int32_t* offs,
+                             int32_t* status, const int32_t* done, hipStream_t s);
+
 // Mixed precision (dense subsample): BF16 copy of Z (ld multiple of 64, zero padded)
 // and FP32 copy (ld = K), from src viewed row-major rows_s x cols_s (trans: Z = src^T).
 hipError_t launch_cast_bf16(const void* src, int32_t src_is_f32, int64_t rows_s, int64_t cols_s,

@@ -134,3 +134,24 @@ def test_mixed_rejects_csr():
     with pytest.raises(rs.RsError) as e:
         rs.Solver(p.X, p.y, p.lam, tau=5, sketch="count", precision="mixed")
     assert e.value.status == rs.RS_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("tau,kind", [(130, "subsample"), (300, "subsample"), (700, "subsample"),
+                                      (257, "count")])
+def test_tiled_factorisation_inverse(tau, kind):
+    """G^{-1} from the device-wide tiled factorisation (tau > 64) inverts the oracle's G."""
+    if kind == "subsample":
+        p = inputs.make_dense(1500, 800, 0.5, seed=tau)
+    else:
+        p = inputs.make_csr(3000, 900, 0.01, 0.5, seed=tau)
+    S = rs.Solver(p.X, p.y, p.lam, tau=tau, sketch=kind, form="primal", tol=0.0, seed=5, lookahead=5)
+    S.step(5)
+    AS, Gi = S.products()
+    _, s, AS_or, G_or, active = _oracle_products(p, "primal", kind, 4, tau)
+    G = G_or.copy()
+    for b in np.flatnonzero(~active):
+        G[b, b] = 1.0
+    err = np.abs(Gi @ G - np.eye(tau)).max()
+    assert err <= 1e-9, err
+    assert np.allclose(Gi, Gi.T, rtol=0, atol=1e-12 * np.abs(Gi).max())
+    S.close()
