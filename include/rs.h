@@ -99,7 +99,10 @@ typedef struct rs_options {
   int32_t refresh_every;    /* mixed precision: FP64 recomputation of r every R iterations (default 20) */
   int32_t lookahead;        /* sketches drawn and factorised ahead per batch; 0 = library choice */
   int32_t profile;          /* 0: off; 1: batch-level HIP-event timing; 2: every launch (rs_get_profile) */
-  void* stream;             /* hipStream_t for all work; NULL = the default stream */
+  void* stream;             /* hipStream_t for all work; NULL = the default stream (a batch
+                               then creates its own stream, since graph capture needs one) */
+  int32_t graph_iters;      /* batch: iterations per captured HIP graph; 0 = 8, < 0 = no graph */
+  int32_t autotune;         /* batch: 1 = time candidate launch shapes at rs_batch_create */
 } rs_options;
 
 typedef struct rs_report {
@@ -182,6 +185,90 @@ rs_status rs_get_products(const rs_handle* h, double* as_out, double* ginv_out);
 rs_status rs_get_history(const rs_handle* h, double* out, int64_t count);
 
 rs_status rs_destroy(rs_handle* h);
+
+/* ------------------------------------------------------------------------
+ * Batched solves: many ridge problems, each with a grid of regularisers and
+ * several right-hand sides, in one lock-step iteration.
+ *
+ * Problem p has its own X_p (dense or CSR, any shape), nrhs_p right-hand sides and
+ * nlambda_p regularisers; its J_p = nlambda_p * nrhs_p solves (slot j = l * nrhs_p + q
+ * for lambda_l and right-hand side q) share one sketch sequence S_k drawn from the
+ * Philox key (seed, problem_id + p) -- the sequence a single solve created with
+ * rs_options.problem_id = problem_id + p draws -- so that B S_k = Z (Z^T S_k) is formed
+ * once per problem and iteration and A(lambda) S_k = B S_k + lambda S_k (eq:Axb with
+ * the lambda term split off; Alg. 2 otherwise unchanged). All problems advance in lock
+ * step; a solve stops at the first iteration whose ||r^k|| / ||r^0|| <= tol and keeps
+ * that iterate, a problem when all its solves stopped or at its iteration cap. Each
+ * iteration is a fixed sequence of device-wide launches over ragged work tables, and the
+ * sequence is captured once into a HIP graph (rs_options.graph_iters iterations per
+ * graph) and replayed; with rs_options.autotune the launch shapes of the
+ * iterate-independent kernels are timed on the batch's own tables and the fastest kept.
+ * Batched solves run in FP64 with the subsample sketch for dense X and the count
+ * sketch for CSR X. Options used: momentum parameters, tol, max_iter (upper bound of
+ * every cap), seed, problem_id, stream, graph_iters, autotune.
+ * ------------------------------------------------------------------------ */
+typedef struct rs_problem {
+  rs_matrix X;              /* as for rs_create; X.mem also applies to y */
+  const double* y;          /* n x nrhs, column-major, FP64 */
+  int32_t nrhs;             /* 1 .. 8 */
+  const double* lambdas;    /* host, nlambda values > 0 */
+  int32_t nlambda;          /* nlambda * nrhs <= 64 */
+  int32_t tau;              /* 0: a multiple of 64 nearest m^{2/3}, clamped to [64, 512] and to m */
+  int32_t sketch;           /* -1: subsample for dense X, count for CSR X (the only pairs built) */
+  int32_t form;             /* RS_FORM_* (AUTO: primal iff d <= n) */
+  int64_t max_iter;         /* iteration cap of this problem; 0: rs_options.max_iter */
+} rs_problem;
+
+typedef struct rs_batch_report {
+  int64_t iters;            /* lock-step iterations performed */
+  int32_t solves;           /* sum of J_p */
+  int32_t converged;        /* solves that met tol */
+  double seconds;           /* wall time of the solve */
+} rs_batch_report;
+
+typedef struct rs_batch_problem_info_t {
+  int64_t m, K;             /* system size and contraction length */
+  int32_t form, sketch, tau, slots;
+  int64_t max_iter;         /* the problem's cap */
+  int64_t iters;            /* iterations performed when it stopped (0 while running) */
+} rs_batch_problem_info_t;
+
+typedef struct rs_tuning {
+  int32_t tuned;            /* 1 when the shapes below were chosen by timing */
+  int32_t dense_tk;         /* K-panel depth of the dense product tiles (16 or 32) */
+  int32_t dense_wg_per_cu, sparse_wg_per_cu, chol_wg_per_cu;  /* persistent grid sizes */
+  int32_t graph_iters;      /* iterations per graph replay */
+  int32_t compute_units;
+  double dense_ms, sparse_ms, chol_ms;  /* best timed launch (ms), -1 if not timed */
+} rs_tuning;
+
+typedef struct rs_batch rs_batch;
+
+/* Build a batch of `count` problems (host array). Copies every X and y into library
+ * layouts, forms b, sets the initial states. Errors: RS_EINVAL (shapes, tau, lambdas,
+ * nrhs, non-finite y), RS_EUNSUPPORTED (precision other than FP64, sketch/layout pair),
+ * RS_ENOMEM, RS_EDEVICE. rs_batch_last_error(NULL) describes a failure. */
+rs_status rs_batch_create(int32_t count, const rs_problem* problems, const rs_options* o,
+                          rs_batch** out);
+/* Advance up to `iters` lock-step iterations (fewer once every problem stopped). */
+rs_status rs_batch_step(rs_batch* b, int64_t iters);
+/* Iterate until every problem stopped. RS_NOT_CONVERGED if some solve hit its cap. */
+rs_status rs_batch_solve(rs_batch* b, rs_batch_report* rep);
+/* Restart every solve from zero with a new sketch seed (layouts and tuning kept). */
+rs_status rs_batch_reset(rs_batch* b, uint64_t seed);
+int64_t rs_batch_iteration(const rs_batch* b);
+rs_status rs_batch_problem_info(const rs_batch* b, int32_t p, rs_batch_problem_info_t* info);
+/* Per slot of problem p (host arrays of J_p, either may be NULL): the iteration at which
+ * the solve met tol (-1 if it has not) and its last ||r^k|| / ||r^0||. */
+rs_status rs_batch_slot_report(const rs_batch* b, int32_t p, int64_t* stop_iter, double* rel_res);
+/* State of one solve (host buffers of m_p doubles, any may be NULL), as rs_get_state. */
+rs_status rs_batch_get_state(const rs_batch* b, int32_t p, int32_t slot, double* x, double* x_prev,
+                             double* r, double* r_prev);
+/* Ridge weights of problem p: d_p x J_p column-major (slot j in column j), host. */
+rs_status rs_batch_get_weights(rs_batch* b, int32_t p, double* w_out);
+rs_status rs_batch_get_tuning(const rs_batch* b, rs_tuning* out);
+rs_status rs_batch_destroy(rs_batch* b);
+const char* rs_batch_last_error(const rs_batch* b);
 
 const char* rs_status_string(rs_status s);
 /* Text of the last error on this handle (or of the last failed rs_create on

@@ -27,51 +27,14 @@ namespace {
 
 using namespace chol;
 
-template <typename ASV>
-__global__ __launch_bounds__(kThreads) void k_chol_inverse(double* __restrict__ Gall,
-                                                           double* __restrict__ Uall, int64_t ldg,
-                                                           int32_t tau, int32_t kind,
-                                                           const ASV* __restrict__ ASall,
-                                                           int64_t ldas, int64_t m,
-                                                           const int32_t* __restrict__ members_all,
-                                                           const int32_t* __restrict__ offs_all,
-                                                           int32_t* __restrict__ status,
-                                                           const int32_t* __restrict__ done) {
-  extern __shared__ __align__(16) double lds[];
-  double* ta = lds;                  // [64][65]
-  double* tb = lds + NB * LDT;       // [64][65]
-  double* td = lds + 2 * NB * LDT;   // [64][65]
-  double* col = lds + 3 * NB * LDT;  // [64]
-  __shared__ int bad;
-  if (*done) return;
+// Phases 1-3 on the assembled, padded ldg x ldg matrix G (lower triangle read):
+// G <- G^{-1} (both triangles), U <- L^{-T}. LDS: ta, tb, td (64 x LDT each), col (64).
+__device__ __forceinline__ void factor_invert(double* __restrict__ G, double* __restrict__ U,
+                                              int64_t ldg, double* ta, double* tb, double* td,
+                                              double* col, int* bad_flag) {
   const int tid = threadIdx.x;
-  const int64_t slot = blockIdx.x;
-  double* G = Gall + slot * ldg * ldg;
-  double* U = Uall + slot * ldg * ldg;
-  const int32_t* offs = offs_all + slot * (tau + 1);
   const int nt = (int)(ldg / NB);
-  if (tid == 0) bad = 0;
-
-  // Phase 0: assemble G (subsample: rows C of AS), padding and empty buckets.
-  if (kind == kSubsample) {
-    const int32_t* members = members_all + slot * tau;
-    const ASV* AS = ASall + slot * m * ldas;
-    for (int64_t e = tid; e < (int64_t)tau * tau; e += kThreads) {
-      const int64_t c = e / tau, cc = e % tau;
-      G[c * ldg + cc] = (double)AS[(int64_t)members[c] * ldas + cc];
-    }
-  }
-  for (int64_t e = tid; e < ldg * ldg; e += kThreads) {
-    const int64_t r = e / ldg, c = e % ldg;
-    if (r >= tau || c >= tau) G[e] = (r == c) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  if (kind != kSubsample) {
-    for (int bkt = tid; bkt < tau; bkt += kThreads)
-      if (offs[bkt + 1] == offs[bkt]) G[(int64_t)bkt * ldg + bkt] = 1.0;
-  }
-  __syncthreads();
-
+  int& bad = *bad_flag;
   // Phase 1: Cholesky (lower triangle of G in place) and U_kk = L_kk^{-T}.
   for (int kt = 0; kt < nt; ++kt) {
     double* Gkk = G + (int64_t)kt * NB * ldg + kt * NB;
@@ -187,7 +150,99 @@ __global__ __launch_bounds__(kThreads) void k_chol_inverse(double* __restrict__ 
       __syncthreads();
     }
   }
+}
+
+template <typename ASV>
+__global__ __launch_bounds__(kThreads) void k_chol_inverse(double* __restrict__ Gall,
+                                                           double* __restrict__ Uall, int64_t ldg,
+                                                           int32_t tau, int32_t kind,
+                                                           const ASV* __restrict__ ASall,
+                                                           int64_t ldas, int64_t m,
+                                                           const int32_t* __restrict__ members_all,
+                                                           const int32_t* __restrict__ offs_all,
+                                                           int32_t* __restrict__ status,
+                                                           const int32_t* __restrict__ done) {
+  extern __shared__ __align__(16) double lds[];
+  double* ta = lds;                  // [64][65]
+  double* tb = lds + NB * LDT;       // [64][65]
+  double* td = lds + 2 * NB * LDT;   // [64][65]
+  double* col = lds + 3 * NB * LDT;  // [64]
+  __shared__ int bad;
+  if (*done) return;
+  const int tid = threadIdx.x;
+  const int64_t slot = blockIdx.x;
+  double* G = Gall + slot * ldg * ldg;
+  double* U = Uall + slot * ldg * ldg;
+  const int32_t* offs = offs_all + slot * (tau + 1);
+  if (tid == 0) bad = 0;
+
+  // Phase 0: assemble G (subsample: rows C of AS), padding and empty buckets.
+  if (kind == kSubsample) {
+    const int32_t* members = members_all + slot * tau;
+    const ASV* AS = ASall + slot * m * ldas;
+    for (int64_t e = tid; e < (int64_t)tau * tau; e += kThreads) {
+      const int64_t c = e / tau, cc = e % tau;
+      G[c * ldg + cc] = (double)AS[(int64_t)members[c] * ldas + cc];
+    }
+  }
+  for (int64_t e = tid; e < ldg * ldg; e += kThreads) {
+    const int64_t r = e / ldg, c = e % ldg;
+    if (r >= tau || c >= tau) G[e] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (kind != kSubsample) {
+    for (int bkt = tid; bkt < tau; bkt += kThreads)
+      if (offs[bkt + 1] == offs[bkt]) G[(int64_t)bkt * ldg + bkt] = 1.0;
+  }
+  __syncthreads();
+
+  factor_invert(G, U, ldg, ta, tb, td, col, &bad);
   if (tid == 0) status[slot] = bad;
+}
+
+
+// Grouped form (batched solves): job = one (problem, lambda) pair sharing the
+// problem's product B S = Z (Z^T S) (no lambda term), so that
+// S^T A(lambda) S = S^T B S + lambda S^T S. Subsample: rows C of B S plus lambda I;
+// count: G0 = S^T B S plus lambda diag(bucket sizes) (S^T S for a count sketch), the
+// diagonal of an empty bucket set to 1. Persistent grid striding over the jobs.
+__global__ __launch_bounds__(kThreads) void k_chol_tab(const CholJob* __restrict__ jobs, int32_t njobs) {
+  extern __shared__ __align__(16) double lds[];
+  double* ta = lds;
+  double* tb = lds + NB * LDT;
+  double* td = lds + 2 * NB * LDT;
+  double* col = lds + 3 * NB * LDT;
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  for (int32_t t = blockIdx.x; t < njobs; t += gridDim.x) {
+    const CholJob& j = jobs[t];
+    if (*j.done) continue;  // uniform across the workgroup
+    double* G = j.G;
+    const int64_t ldg = j.ldg;
+    const int tau = j.tau;
+    if (tid == 0) bad = 0;
+    for (int64_t e = tid; e < ldg * ldg; e += kThreads) {
+      const int64_t r = e / ldg, c = e % ldg;
+      double v;
+      if (r >= tau || c >= tau) {
+        v = (r == c) ? 1.0 : 0.0;
+      } else if (j.kind == kSubsample) {
+        v = j.BS[(int64_t)j.members[r] * j.ldas + c];
+        if (r == c) v += j.lam;
+      } else {
+        v = j.G0[r * ldg + c];
+        if (r == c) {
+          const int cnt = j.offs[r + 1] - j.offs[r];
+          v = cnt == 0 ? 1.0 : v + j.lam * (double)cnt;
+        }
+      }
+      G[e] = v;
+    }
+    __syncthreads();
+    factor_invert(G, j.U, ldg, ta, tb, td, col, &bad);
+    if (tid == 0 && bad) *j.status = 1;  // sticky until the host clears it
+    __syncthreads();
+  }
 }
 
 template <typename ASV>
@@ -215,6 +270,17 @@ hipError_t launch_chol_inverse(double* G, double* W, int64_t ldg, int32_t tau, i
                               status, done, s);
   return chol_launch<double>(G, W, ldg, tau, nslots, kind, (const double*)AS, ldas, m, members, offs,
                              status, done, s);
+}
+
+hipError_t launch_chol_tab(const CholJob* jobs, int32_t njobs, int32_t grid, hipStream_t s) {
+  if (njobs <= 0) return hipSuccess;
+  grid = grid < 1 ? 1 : (grid > njobs ? njobs : grid);
+  const size_t bytes = sizeof(double) * (3 * NB * LDT + NB);
+  hipError_t e = hipFuncSetAttribute((const void*)k_chol_tab, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_chol_tab, dim3(grid), dim3(kThreads), bytes, s, jobs, njobs);
+  return hipGetLastError();
 }
 
 }  // namespace rs

@@ -78,8 +78,7 @@ __device__ void find_bin(SelHeader* H, int nbins, int need) {
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kSelThreads) void k_sketch_select(SketchArgs a) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
+__device__ __forceinline__ void select_body(const SketchArgs& a, int slot, unsigned char* lds_raw) {
   SelHeader* H = reinterpret_cast<SelHeader*>(lds_raw);
   const int sort_cap = (a.kind == kSubcount) ? max(kCandCap, next_pow2((int)a.nsel)) : kCandCap;
   uint64_t* skey = reinterpret_cast<uint64_t*>(lds_raw + sizeof(SelHeader));
@@ -87,9 +86,8 @@ __global__ __launch_bounds__(kSelThreads) void k_sketch_select(SketchArgs a) {
 
   if (*a.done) return;
   const int tid = threadIdx.x;
-  const int slot = blockIdx.x;
   const int64_t m = a.m;
-  const uint64_t k = (uint64_t)(a.k0 + slot);
+  const uint64_t k = (uint64_t)((a.kdev ? *a.kdev : a.k0) + slot);
   const uint64_t tag = (a.kind == kSubcount) ? kTagSubcount : kTagSubsample;
   uint64_t* keys = a.keys + (int64_t)slot * m;
   int32_t* hmap = a.hmap + (int64_t)slot * m;
@@ -224,16 +222,14 @@ __global__ __launch_bounds__(kSelThreads) void k_sketch_select(SketchArgs a) {
 
 // Count sketch: 16 waves; wave w owns a contiguous coordinate segment. Placement is
 // stable in the coordinate index, so the member order is deterministic.
-__global__ __launch_bounds__(kSelThreads) void k_sketch_count(SketchArgs a) {
-  extern __shared__ __align__(16) int cnt_lds[];
+__device__ __forceinline__ void count_body(const SketchArgs& a, int slot, int* cnt_lds) {
   int* cntw = cnt_lds;               // [16][tau]
   int* scan = cnt_lds + 16 * a.tau;  // 32 ints
   if (*a.done) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int slot = blockIdx.x;
   const int64_t m = a.m;
   const int tau = a.tau;
-  const uint64_t k = (uint64_t)(a.k0 + slot);
+  const uint64_t k = (uint64_t)((a.kdev ? *a.kdev : a.k0) + slot);
   int32_t* hmap = a.hmap + (int64_t)slot * m;
   int32_t* members = a.members + (int64_t)slot * a.nsel;
   int32_t* offs = a.offs + (int64_t)slot * (tau + 1);
@@ -296,6 +292,30 @@ __global__ __launch_bounds__(kSelThreads) void k_sketch_count(SketchArgs a) {
   }
 }
 
+
+__global__ __launch_bounds__(kSelThreads) void k_sketch_select(SketchArgs a) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  select_body(a, blockIdx.x, lds_raw);
+}
+
+__global__ __launch_bounds__(kSelThreads) void k_sketch_count(SketchArgs a) {
+  extern __shared__ __align__(16) int cnt_lds[];
+  count_body(a, blockIdx.x, cnt_lds);
+}
+
+// Grouped forms: blockIdx.y picks one problem's arguments from a device table.
+__global__ __launch_bounds__(kSelThreads) void k_sketch_select_tab(const SketchArgs* __restrict__ tab) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const SketchArgs a = tab[blockIdx.y];
+  select_body(a, blockIdx.x, lds_raw);
+}
+
+__global__ __launch_bounds__(kSelThreads) void k_sketch_count_tab(const SketchArgs* __restrict__ tab) {
+  extern __shared__ __align__(16) int cnt_lds[];
+  const SketchArgs a = tab[blockIdx.y];
+  count_body(a, blockIdx.x, cnt_lds);
+}
+
 }  // namespace
 
 hipError_t launch_sketch(const SketchArgs& a, hipStream_t s) {
@@ -319,6 +339,34 @@ hipError_t launch_sketch(const SketchArgs& a, hipStream_t s) {
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sketch_select, dim3(a.nslots), dim3(kSelThreads), bytes, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace rs
+
+namespace rs {
+
+size_t sketch_lds_bytes(int32_t kind, int32_t tau, int64_t nsel) {
+  if (kind == kCount) return sizeof(int) * (16 * (size_t)tau + 32);
+  int cap = kCandCap;
+  if (kind == kSubcount) {
+    int p = 1;
+    while (p < nsel) p <<= 1;
+    cap = p > cap ? p : cap;
+  }
+  return sizeof(SelHeader) + (size_t)cap * (sizeof(uint64_t) + sizeof(uint32_t));
+}
+
+hipError_t launch_sketch_tab(const SketchArgs* tab, int32_t count, int32_t kind, size_t lds_bytes,
+                             hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const void* fn = kind == kCount ? (const void*)k_sketch_count_tab : (const void*)k_sketch_select_tab;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  if (e != hipSuccess) return e;
+  if (kind == kCount)
+    hipLaunchKernelGGL(k_sketch_count_tab, dim3(1, count), dim3(kSelThreads), lds_bytes, s, tab);
+  else
+    hipLaunchKernelGGL(k_sketch_select_tab, dim3(1, count), dim3(kSelThreads), lds_bytes, s, tab);
   return hipGetLastError();
 }
 

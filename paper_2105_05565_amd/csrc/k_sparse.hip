@@ -122,19 +122,14 @@ __device__ __forceinline__ void scatter_row(int64_t j, const int64_t* __restrict
 // One workgroup per bucket b of a sketch: its member rows of AS and row b of G.
 // NCH = number of 64-column chunks of tau held per lane for the G partial sums.
 template <typename V, int NCH>
-__global__ __launch_bounds__(kWaves * 64) void k_as_sparse_bucket(
+__device__ __forceinline__ void bucket_body(
     const int64_t* __restrict__ zr_ptr, const int32_t* __restrict__ zr_col,
     const V* __restrict__ zr_val, const int64_t* __restrict__ zt_ptr,
     const TEntry<V>* __restrict__ T_all, int64_t nnz, int64_t m, int32_t tau, int64_t ldas,
     double lam, const int32_t* __restrict__ hmap_all, const int32_t* __restrict__ members_all,
     const int32_t* __restrict__ offs_all, int64_t nsel, double* __restrict__ AS,
-    double* __restrict__ G, int64_t ldg, const int32_t* __restrict__ done) {
-  extern __shared__ __align__(16) double lds[];  // acc [kWaves][tau]
-  __shared__ RowLds rls[kWaves];
-  if (*done) return;
+    double* __restrict__ G, int64_t ldg, int b, int64_t slot, double* lds, RowLds* rls) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int b = blockIdx.x;
-  const int64_t slot = blockIdx.y;
   const int32_t* hmap = hmap_all + slot * m;
   const int32_t* members = members_all + slot * nsel;
   const int32_t* offs = offs_all + slot * (tau + 1);
@@ -176,6 +171,55 @@ __global__ __launch_bounds__(kWaves * 64) void k_as_sparse_bucket(
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) v += lds[w * tau + c];
     grow[c] = v;
+  }
+  __syncthreads();  // lds is reused by the next bucket of a persistent workgroup
+}
+
+template <typename V, int NCH>
+__global__ __launch_bounds__(kWaves * 64) void k_as_sparse_bucket(
+    const int64_t* __restrict__ zr_ptr, const int32_t* __restrict__ zr_col,
+    const V* __restrict__ zr_val, const int64_t* __restrict__ zt_ptr,
+    const TEntry<V>* __restrict__ T_all, int64_t nnz, int64_t m, int32_t tau, int64_t ldas,
+    double lam, const int32_t* __restrict__ hmap_all, const int32_t* __restrict__ members_all,
+    const int32_t* __restrict__ offs_all, int64_t nsel, double* __restrict__ AS,
+    double* __restrict__ G, int64_t ldg, const int32_t* __restrict__ done) {
+  extern __shared__ __align__(16) double lds[];  // acc [kWaves][tau]
+  __shared__ RowLds rls[kWaves];
+  if (*done) return;
+  bucket_body<V, NCH>(zr_ptr, zr_col, zr_val, zt_ptr, T_all, nnz, m, tau, ldas, lam, hmap_all,
+                      members_all, offs_all, nsel, AS, G, ldg, blockIdx.x, blockIdx.y, lds, rls);
+}
+
+// Grouped forms (batched solves, FP64 values): T for every job (blockIdx.y = job), then
+// a persistent grid striding over the ragged table of (job, bucket) pairs.
+__global__ void k_build_t_tab(const SparseJob* __restrict__ jobs) {
+  const SparseJob& j = jobs[blockIdx.y];
+  if (*j.done) return;
+  TEntry<double>* t = static_cast<TEntry<double>*>(j.tbuf);
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < j.nnz;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int code = j.hmap[j.zt_col[q]];
+    const double v = j.zt_val[q];
+    TEntry<double> e;
+    e.code = code < 0 ? -1 : (code >> 1);
+    e.val = (code & 1) ? -v : v;
+    t[q] = e;
+  }
+}
+
+template <int NCH>
+__global__ __launch_bounds__(kWaves * 64) void k_as_sparse_bucket_tab(
+    const SparseJob* __restrict__ jobs, const int32_t* __restrict__ items, int32_t nitems) {
+  extern __shared__ __align__(16) double lds[];  // acc [kWaves][max tau]
+  __shared__ RowLds rls[kWaves];
+  for (int32_t t = blockIdx.x; t < nitems; t += gridDim.x) {
+    const int32_t job = items[2 * t], b = items[2 * t + 1];
+    const SparseJob& j = jobs[job];
+    if (*j.done) continue;  // uniform across the workgroup
+    bucket_body<double, NCH>(j.zr_ptr, j.zr_col, j.zr_val, j.zt_ptr,
+                             static_cast<const TEntry<double>*>(j.tbuf), j.nnz, j.m, j.tau, j.ldas,
+                             j.lam, j.hmap, j.members, j.offs, j.nsel, j.AS, j.G, j.ldg, b, 0, lds,
+                             rls);
   }
 }
 
@@ -397,5 +441,33 @@ hipError_t csr_transpose(const int64_t* ptr, const int32_t* col, const void* val
   return transpose_impl<double>(ptr, col, (const double*)val, rows, cols, nnz, tptr, tcol,
                                 (double*)tval, s);
 }
+
+hipError_t launch_sparse_tab(const SparseJob* jobs, int32_t njobs, const int32_t* items,
+                             int32_t nitems, int32_t max_tau, int32_t grid, hipStream_t s) {
+  if (njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_build_t_tab, dim3(256, njobs), dim3(256), 0, s, jobs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  grid = grid < 1 ? 1 : (grid > nitems ? nitems : grid);
+  const size_t bytes = sizeof(double) * kWaves * (size_t)max_tau;
+  if (max_tau <= 512) {
+    e = hipFuncSetAttribute((const void*)k_as_sparse_bucket_tab<8>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_as_sparse_bucket_tab<8>, dim3(grid), dim3(kWaves * 64), bytes, s, jobs,
+                       items, nitems);
+  } else if (max_tau <= 1024) {
+    e = hipFuncSetAttribute((const void*)k_as_sparse_bucket_tab<16>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_as_sparse_bucket_tab<16>, dim3(grid), dim3(kWaves * 64), bytes, s, jobs,
+                       items, nitems);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+size_t sparse_entry_bytes_f64() { return sizeof(TEntry<double>); }
 
 }  // namespace rs

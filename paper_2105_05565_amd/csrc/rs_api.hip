@@ -383,6 +383,8 @@ rs_status rs_options_default(rs_options* o) {
   o->refresh_every = 20;
   o->lookahead = 0;
   o->stream = nullptr;
+  o->graph_iters = 0;
+  o->autotune = 0;
   return RS_OK;
 }
 

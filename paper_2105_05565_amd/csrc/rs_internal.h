@@ -42,6 +42,7 @@ struct SketchArgs {
   uint64_t* keys;      // [nslots][m] scratch
   int32_t* err;        // device error word (set nonzero on an internal limit)
   const int32_t* done; // skip all work when *done != 0
+  const int64_t* kdev; // when set, slot 0 draws iteration *kdev (read on the device)
 };
 
 // Device-side solve state shared by the per-iteration kernels.
@@ -56,12 +57,36 @@ struct DevFlags {
 // Launchers (host functions defined in the .hip files).
 // ---------------------------------------------------------------------------
 hipError_t launch_sketch(const SketchArgs& a, hipStream_t s);
+// Grouped draw: one sketch per entry of a device table of arguments (all of one kind;
+// lds_bytes = the maximum of sketch_lds_bytes over the entries).
+size_t sketch_lds_bytes(int32_t kind, int32_t tau, int64_t nsel);
+hipError_t launch_sketch_tab(const SketchArgs* tab, int32_t count, int32_t kind, size_t lds_bytes,
+                             hipStream_t s);
 
 // AS[slot][j][c] (row stride ldas) = sum_k Z[j][k] * Z[C_slot[c]][k] + lam * [j == C_slot[c]],
 // FP64 MFMA.
 hipError_t launch_as_dense_f64(const double* Z, int64_t ldz, int64_t m, int64_t K,
                                const int32_t* members, int32_t tau, int64_t ldas, int32_t nslots,
                                double lam, double* AS, const int32_t* done, hipStream_t s);
+
+// Grouped dense products (batched solves): job = one sketch of one problem,
+// AS (m x tau, row stride ldas) = Z Z[C,:]^T + lam I_C; tiles = (job, row tile, column tile)
+// of 64 x 64. tk = 16 or 32 (K panel depth); grid = workgroups striding over the tiles.
+struct DenseJob {
+  const double* Z;
+  int64_t ldz, m, K;
+  const int32_t* members;
+  int32_t tau;
+  int64_t ldas;
+  double lam;
+  double* AS;
+  const int32_t* done;
+};
+struct DenseTile {
+  int32_t job, tm, tn;
+};
+hipError_t launch_as_dense_f64_tab(const DenseJob* jobs, const DenseTile* tiles, int32_t ntiles,
+                                   int32_t tk, int32_t grid, hipStream_t s);
 
 // Count / SubCount products from CSR(Z) (m rows) and CSR(Z^T) (nnz entries), values FP32 or
 // FP64: AS[slot] (m x tau, row stride ldas) and, for member rows,
@@ -78,12 +103,60 @@ hipError_t launch_as_sparse(const int64_t* zr_ptr, const int32_t* zr_col, const 
                             const int32_t* members, const int32_t* offs, int64_t nsel, void* tbuf,
                             double* AS, double* G, int64_t ldg, const int32_t* done, hipStream_t s);
 
+// Grouped count-sketch products (batched solves; CSR values held in FP64): per job,
+// T = Z^T S into tbuf (nnz * sparse_entry_bytes_f64() bytes), then AS (m x tau) and
+// G = S^T AS for the (job, bucket) pairs in items[2 * nitems].
+struct SparseJob {
+  const int64_t* zr_ptr;
+  const int32_t* zr_col;
+  const double* zr_val;
+  const int64_t* zt_ptr;
+  const int32_t* zt_col;
+  const double* zt_val;
+  int64_t nnz, m;
+  int32_t tau;
+  int64_t ldas;
+  double lam;
+  const int32_t* hmap;
+  const int32_t* members;
+  const int32_t* offs;
+  int64_t nsel;
+  void* tbuf;
+  double* AS;
+  double* G;
+  int64_t ldg;
+  const int32_t* done;
+};
+size_t sparse_entry_bytes_f64();
+hipError_t launch_sparse_tab(const SparseJob* jobs, int32_t njobs, const int32_t* items,
+                             int32_t nitems, int32_t max_tau, int32_t grid, hipStream_t s);
+
 // Ginv[slot] = (S^T A S)^{-1} (padded ldg x ldg, identity on empty buckets and padding).
 // AS is FP64, or FP32 when as_f32 (mixed precision).
 hipError_t launch_chol_inverse(double* G, double* W, int64_t ldg, int32_t tau, int32_t nslots,
                                int32_t kind, const void* AS, int32_t as_f32, int64_t ldas, int64_t m,
                                const int32_t* members, const int32_t* offs, int32_t* status,
                                const int32_t* done, hipStream_t s);
+
+// Grouped factorisation and inverse (batched solves): G (ldg x ldg) <- (S^T A(lam) S)^{-1}
+// assembled from the lambda-free product B S (subsample: rows C of BS, row stride ldas)
+// or from G0 = S^T B S (count), U: ldg x ldg scratch, *status <- 1 on a bad pivot.
+struct CholJob {
+  double* G;
+  double* U;
+  int64_t ldg;
+  int32_t tau;
+  int32_t kind;
+  const double* BS;
+  int64_t ldas;
+  const int32_t* members;
+  const int32_t* offs;
+  const double* G0;
+  double lam;
+  int32_t* status;
+  const int32_t* done;
+};
+hipError_t launch_chol_tab(const CholJob* jobs, int32_t njobs, int32_t grid, hipStream_t s);
 
 // Same result computed by a sequence of launches in which every 64 x 64 tile of every
 // sketch is a workgroup (for batches with few sketches or large tau). X holds
@@ -116,6 +189,49 @@ hipError_t launch_gemv_rows_f32(const float* Z, int64_t ldz, int64_t m, int64_t 
                                 double* out, hipStream_t s);  // out = Z v, FP64 accumulation
 hipError_t launch_gemv_cols_f32(const float* Z, int64_t ldz, int64_t m, int64_t K, const double* v,
                                 double* out, hipStream_t s);  // out = Z^T v, FP64 accumulation
+
+// ---------------------------------------------------------------------------
+// Batched solves: per-problem device state and the lock-step iteration kernels.
+// ---------------------------------------------------------------------------
+struct BState {
+  int64_t m;
+  int32_t J, nrhs, nlam, tau;
+  int64_t ldg, ldas;
+  const double* BS;       // m x ldas, lambda-free product Z (Z^T S), zero beyond tau
+  const double* Ginv;     // nlam x ldg x ldg inverses of S^T A(lambda_l) S
+  const int32_t* hmap;    // sketch (bucket-major, one slot)
+  const int32_t* members;
+  const int32_t* offs;
+  const double* lam;      // [nlam]
+  const double* b;        // m x nrhs row-major
+  double* x[2];           // m x J row-major; buffer (k & 1) holds iterate k
+  double* r[2];
+  double* rho;            // J x ldg
+  double* delta;          // J x ldg (zero beyond tau)
+  double* partials;       // ntiles x J
+  int32_t ntiles;         // 64-row tiles
+  double* r0n;            // [J] ||r^0||
+  int64_t* stop_k;        // [J] -1 while running, else the iteration whose iterate is kept
+  double* rel;            // [J] last ||r^k|| / ||r^0||
+  int32_t* inactive;      // problem finished (read as the `done` word of its launches)
+  int64_t cap;            // iteration cap
+  int64_t* iters;         // iterations performed when the problem finished
+};
+struct BGlobal {
+  int64_t k;     // shared iteration counter
+  int32_t done;  // every problem finished
+  int32_t pad;
+};
+hipError_t launch_binit(const BState* S, int32_t nprob, BGlobal* g, hipStream_t s);
+hipError_t launch_brho(const BState* S, const int32_t* items, int32_t nitems, const BGlobal* g,
+                       int32_t grid, hipStream_t s);
+hipError_t launch_bdelta(const BState* S, const int32_t* items, int32_t nitems, int32_t grid,
+                         hipStream_t s);
+hipError_t launch_bupdate(const BState* S, const int32_t* items, int32_t nitems, const BGlobal* g,
+                          const double* betas, const double* gammas, int32_t grid, hipStream_t s);
+hipError_t launch_bfinal(const BState* S, int32_t nprob, BGlobal* g, double tol, hipStream_t s);
+hipError_t launch_bcol(const double* src, int64_t m, int64_t src_ld, int64_t src_col, double* dst,
+                       int64_t dst_ld, int64_t dst_col, hipStream_t s);
 
 // Solve-state kernels.
 int32_t update_partials(int64_t m, int32_t tau);  // partial sums written by k_update

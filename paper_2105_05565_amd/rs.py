@@ -42,7 +42,33 @@ class rs_options(ctypes.Structure):
                 ("eta", ctypes.c_double), ("beta_max", ctypes.c_double), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int64), ("seed", ctypes.c_uint64), ("problem_id", ctypes.c_uint64),
                 ("refresh_every", ctypes.c_int32), ("lookahead", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("profile", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("graph_iters", ctypes.c_int32), ("autotune", ctypes.c_int32)]
+
+
+class rs_problem(ctypes.Structure):
+    _fields_ = [("X", rs_matrix), ("y", ctypes.c_void_p), ("nrhs", ctypes.c_int32),
+                ("lambdas", ctypes.c_void_p), ("nlambda", ctypes.c_int32), ("tau", ctypes.c_int32),
+                ("sketch", ctypes.c_int32), ("form", ctypes.c_int32), ("max_iter", ctypes.c_int64)]
+
+
+class rs_batch_report(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int64), ("solves", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("seconds", ctypes.c_double)]
+
+
+class rs_batch_problem_info_t(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("K", ctypes.c_int64), ("form", ctypes.c_int32),
+                ("sketch", ctypes.c_int32), ("tau", ctypes.c_int32), ("slots", ctypes.c_int32),
+                ("max_iter", ctypes.c_int64), ("iters", ctypes.c_int64)]
+
+
+class rs_tuning(ctypes.Structure):
+    _fields_ = [("tuned", ctypes.c_int32), ("dense_tk", ctypes.c_int32),
+                ("dense_wg_per_cu", ctypes.c_int32), ("sparse_wg_per_cu", ctypes.c_int32),
+                ("chol_wg_per_cu", ctypes.c_int32), ("graph_iters", ctypes.c_int32),
+                ("compute_units", ctypes.c_int32), ("dense_ms", ctypes.c_double),
+                ("sparse_ms", ctypes.c_double), ("chol_ms", ctypes.c_double)]
 
 
 RS_PROF_SKETCH, RS_PROF_AS, RS_PROF_CHOL, RS_PROF_DELTA, RS_PROF_UPDATE, RS_PROF_REFRESH, RS_PROF_ITERS = range(7)
@@ -88,6 +114,19 @@ SIGNATURES = {
     "rs_destroy": (ctypes.c_int32, [_P]),
     "rs_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "rs_last_error": (ctypes.c_char_p, [_P]),
+    "rs_batch_create": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(rs_problem),
+                                         ctypes.POINTER(rs_options), ctypes.POINTER(_P)]),
+    "rs_batch_step": (ctypes.c_int32, [_P, ctypes.c_int64]),
+    "rs_batch_solve": (ctypes.c_int32, [_P, ctypes.POINTER(rs_batch_report)]),
+    "rs_batch_reset": (ctypes.c_int32, [_P, ctypes.c_uint64]),
+    "rs_batch_iteration": (ctypes.c_int64, [_P]),
+    "rs_batch_problem_info": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.POINTER(rs_batch_problem_info_t)]),
+    "rs_batch_slot_report": (ctypes.c_int32, [_P, ctypes.c_int32, _P, _P]),
+    "rs_batch_get_state": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P]),
+    "rs_batch_get_weights": (ctypes.c_int32, [_P, ctypes.c_int32, _P]),
+    "rs_batch_get_tuning": (ctypes.c_int32, [_P, ctypes.POINTER(rs_tuning)]),
+    "rs_batch_destroy": (ctypes.c_int32, [_P]),
+    "rs_batch_last_error": (ctypes.c_char_p, [_P]),
 }
 
 
@@ -214,6 +253,72 @@ def rs_get_history(h, out, count):
 def rs_destroy(h):
     if h:
         load().rs_destroy(h)
+
+
+def batch_last_error(b=None):
+    return load().rs_batch_last_error(b).decode()
+
+
+def _bcheck(status, where, b=None):
+    if status < 0:
+        raise RsError(status, where, batch_last_error(b))
+    return status
+
+
+def rs_batch_create(problems, opts):
+    arr = (rs_problem * len(problems))(*problems)
+    b = _P()
+    _bcheck(load().rs_batch_create(len(problems), arr, ctypes.byref(opts), ctypes.byref(b)),
+            "rs_batch_create")
+    return b
+
+
+def rs_batch_step(b, iters):
+    _bcheck(load().rs_batch_step(b, int(iters)), "rs_batch_step", b)
+
+
+def rs_batch_solve(b):
+    rep = rs_batch_report()
+    st = _bcheck(load().rs_batch_solve(b, ctypes.byref(rep)), "rs_batch_solve", b)
+    return st, rep
+
+
+def rs_batch_reset(b, seed):
+    _bcheck(load().rs_batch_reset(b, int(seed)), "rs_batch_reset", b)
+
+
+def rs_batch_iteration(b):
+    return load().rs_batch_iteration(b)
+
+
+def rs_batch_problem_info(b, p):
+    info = rs_batch_problem_info_t()
+    _bcheck(load().rs_batch_problem_info(b, int(p), ctypes.byref(info)), "rs_batch_problem_info", b)
+    return info
+
+
+def rs_batch_slot_report(b, p, stop_iter=None, rel_res=None):
+    _bcheck(load().rs_batch_slot_report(b, int(p), _ptr(stop_iter), _ptr(rel_res)), "rs_batch_slot_report", b)
+
+
+def rs_batch_get_state(b, p, slot, x=None, x_prev=None, r=None, r_prev=None):
+    _bcheck(load().rs_batch_get_state(b, int(p), int(slot), _ptr(x), _ptr(x_prev), _ptr(r), _ptr(r_prev)),
+            "rs_batch_get_state", b)
+
+
+def rs_batch_get_weights(b, p, w_out):
+    _bcheck(load().rs_batch_get_weights(b, int(p), _ptr(w_out)), "rs_batch_get_weights", b)
+
+
+def rs_batch_get_tuning(b):
+    t = rs_tuning()
+    _bcheck(load().rs_batch_get_tuning(b, ctypes.byref(t)), "rs_batch_get_tuning", b)
+    return {name: getattr(t, name) for name, _ in rs_tuning._fields_}
+
+
+def rs_batch_destroy(b):
+    if b:
+        load().rs_batch_destroy(b)
 
 
 # ---------------------------------------------------------------- convenience wrapper
@@ -354,6 +459,96 @@ class Solver:
         if self.h:
             rs_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Owns one rs_batch. `problems` is a list of dicts with keys X (numpy array or scipy
+    CSR), y (n or n x nrhs), lambdas (sequence), and optionally tau, form, max_iter."""
+
+    def __init__(self, problems, *, momentum="heuristic", tol=1e-6, max_iter=100000, seed=1,
+                 problem_id=0, eta=0.995, beta_max=0.5, gamma=1.0, beta=0.5, graph_iters=0,
+                 autotune=False, stream=None):
+        o = rs_options_default()
+        o.momentum = MOMENTA[momentum] if isinstance(momentum, str) else int(momentum)
+        o.tol, o.max_iter = tol, int(max_iter)
+        o.seed, o.problem_id = int(seed), int(problem_id)
+        o.eta, o.beta_max, o.gamma, o.beta = eta, beta_max, gamma, beta
+        o.graph_iters, o.autotune, o.stream = int(graph_iters), int(bool(autotune)), stream
+        self._keep = []
+        structs = []
+        self.shapes = []
+        for pr in problems:
+            M, keep = make_matrix(pr["X"])
+            y = np.asarray(pr["y"], dtype=np.float64)
+            if y.ndim == 1:
+                y = y[:, None]
+            yv = np.asfortranarray(y)
+            lam = np.ascontiguousarray(np.asarray(pr["lambdas"], dtype=np.float64))
+            keep += [yv, lam]
+            self._keep.append(keep)
+            P = rs_problem()
+            P.X = M
+            P.y = yv.ctypes.data
+            P.nrhs = yv.shape[1]
+            P.lambdas = lam.ctypes.data
+            P.nlambda = lam.shape[0]
+            P.tau = int(pr.get("tau", 0))
+            P.sketch = -1
+            P.form = FORMS[pr.get("form", "auto")]
+            P.max_iter = int(pr.get("max_iter", 0))
+            structs.append(P)
+            self.shapes.append((int(M.n), int(M.d), yv.shape[1], lam.shape[0]))
+        self.b = rs_batch_create(structs, o)
+        self._keep = None  # the library copied X and y
+
+    def info(self, p):
+        return rs_batch_problem_info(self.b, p)
+
+    def step(self, iters):
+        rs_batch_step(self.b, iters)
+
+    def solve(self):
+        return rs_batch_solve(self.b)
+
+    def reset(self, seed):
+        rs_batch_reset(self.b, seed)
+
+    @property
+    def k(self):
+        return rs_batch_iteration(self.b)
+
+    def slots(self, p):
+        J = self.info(p).slots
+        stop = np.zeros(J, dtype=np.int64)
+        rel = np.zeros(J)
+        rs_batch_slot_report(self.b, p, stop, rel)
+        return stop, rel
+
+    def state(self, p, slot):
+        m = self.info(p).m
+        x, xp, r, rp = (np.zeros(m) for _ in range(4))
+        rs_batch_get_state(self.b, p, slot, x, xp, r, rp)
+        return x, xp, r, rp
+
+    def weights(self, p):
+        n, d, nrhs, nlam = self.shapes[p]
+        w = np.zeros((nrhs * nlam, d))
+        rs_batch_get_weights(self.b, p, w)
+        return w  # row j = slot j = l * nrhs + q
+
+    def tuning(self):
+        return rs_batch_get_tuning(self.b)
+
+    def close(self):
+        if self.b:
+            rs_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

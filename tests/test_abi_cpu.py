@@ -99,3 +99,51 @@ def test_binding_fails_loudly_without_library(tmp_path):
             rs.load(str(tmp_path / "nope.so"))
     finally:
         rs._lib = saved
+
+
+def _batch_problem(n=30, d=10, nrhs=1, lams=(1.0,), csr=False, **kw):
+    import scipy.sparse as sp
+    rng = np.random.default_rng(0)
+    X = rng.standard_normal((n, d))
+    if csr:
+        X = sp.csr_matrix(X * (rng.random((n, d)) < 0.3))
+    pr = dict(X=X, y=rng.standard_normal((n, nrhs)), lambdas=list(lams))
+    pr.update(kw)
+    return pr
+
+
+@pytest.mark.parametrize("pr,opt", [
+    (dict(nrhs=9), {}),                                  # nrhs > 8
+    (dict(nrhs=2, lams=[1.0] * 33), {}),                 # nlambda * nrhs > 64
+    (dict(lams=(0.0,)), {}),                             # lambda <= 0
+    (dict(lams=(math.nan,)), {}),
+    (dict(tau=11), {}),                                  # tau > m = 10
+    (dict(tau=-1 + 2000), {}),
+    (dict(), dict(tol=-1.0)),
+    (dict(), dict(momentum=9)),
+])
+def test_batch_rejects_bad_arguments_without_device(pr, opt):
+    kw = {k: v for k, v in pr.items() if k in ("nrhs", "lams", "csr")}
+    extra = {k: v for k, v in pr.items() if k not in kw}
+    problem = _batch_problem(**kw, **extra)
+    with pytest.raises(rs.RsError) as e:
+        rs.Batch([problem], **opt)
+    assert e.value.status == rs.RS_EINVAL, rs.batch_last_error()
+
+
+def test_batch_rejects_unbuilt_pairs_without_device():
+    o = rs.rs_options_default()
+    o.precision = rs.RS_PREC_MIXED_BF16
+    M, keep = rs.make_matrix(np.ones((20, 8)))
+    y = np.ones(20)
+    lam = np.ones(1)
+    P = rs.rs_problem()
+    P.X, P.y, P.nrhs, P.lambdas, P.nlambda, P.sketch = M, y.ctypes.data, 1, lam.ctypes.data, 1, -1
+    with pytest.raises(rs.RsError) as e:
+        rs.rs_batch_create([P], o)
+    assert e.value.status == rs.RS_EUNSUPPORTED
+    o.precision = rs.RS_PREC_FP64
+    P.sketch = rs.RS_SKETCH_COUNT  # count sketch on dense data
+    with pytest.raises(rs.RsError) as e:
+        rs.rs_batch_create([P], o)
+    assert e.value.status == rs.RS_EUNSUPPORTED

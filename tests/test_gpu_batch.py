@@ -1,0 +1,163 @@
+"""GPU: batched lock-step solves (problems of different shapes x lambda grid x right-hand sides).
+
+Slot (p, l, q) of a batch draws the sketch sequence of the single solve with
+problem_id = p (same Philox key), so its trajectory is the single solve's up to the
+rounding of forming A(lambda) S as B S + lambda S: checked to 1e-10 against the single
+GPU solve and against the oracle. Captured-graph replays equal direct launches bit
+for bit; converged weights match a direct solve; per-problem caps and resets behave.
+"""
+import numpy as np
+import pytest
+
+from oracle.problem import ridge_system
+from oracle.solver import Options, init_state, step
+from paper_2105_05565_amd import inputs, rs
+
+pytestmark = pytest.mark.gpu
+
+LAMS = [0.05, 0.5, 2.0]
+
+
+def _problems():
+    rng = np.random.default_rng(11)
+    out = []
+    specs = [("dense", 300, 130, 37, np.float64), ("dense", 110, 260, 0, np.float32),
+             ("csr", 400, 150, 23, np.float64), ("csr", 150, 400, 30, np.float32)]
+    for i, (kind, n, d, tau, dt) in enumerate(specs):
+        if kind == "dense":
+            X = inputs.make_dense(n, d, 0.1, seed=100 + i, dtype=dt).X
+        else:
+            X = inputs.make_csr(n, d, 0.04, 0.1, seed=100 + i, dtype=dt).X
+        y = rng.standard_normal((n, 2))
+        out.append(dict(X=X, y=y, lambdas=LAMS, tau=tau))
+    return out
+
+
+def _single(pr, p, l, q, iters, seed, tol=0.0):
+    tau = pr["tau"] if pr["tau"] else 64
+    sketch = "count" if hasattr(pr["X"], "tocsr") else "subsample"
+    S = rs.Solver(pr["X"], pr["y"][:, q], pr["lambdas"][l], tau=tau, sketch=sketch, tol=tol, seed=seed,
+                  problem_id=p, max_iter=100000)
+    return S
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def test_batch_matches_single_solves_and_oracle():
+    probs = _problems()
+    N = 25
+    B = rs.Batch(probs, tol=0.0, seed=4, graph_iters=4)
+    B.step(N)
+    assert B.k == N
+    for p, pr in enumerate(probs):
+        info = B.info(p)
+        assert info.slots == 6
+        for l in range(3):
+            for q in range(2):
+                j = l * 2 + q
+                x, xp, r, rp = B.state(p, j)
+                S = _single(pr, p, l, q, N, seed=4)
+                S.step(N)
+                xs, xps, rs_, rps = S.state()
+                S.close()
+                assert _rel(x, xs) <= 1e-10, (p, j, _rel(x, xs))
+                assert _rel(r, rs_) <= 1e-10, (p, j)
+                assert _rel(xp, xps) <= 1e-10 and _rel(rp, rps) <= 1e-10
+    # oracle, one slot per problem
+    for p, pr in enumerate(probs):
+        l, q = p % 3, (p + 1) % 2
+        system = ridge_system(pr["X"], pr["y"][:, q], pr["lambdas"][l])
+        sketch = "count" if hasattr(pr["X"], "tocsr") else "subsample"
+        tau = pr["tau"] if pr["tau"] else 64
+        opts = Options(sketch=sketch, tau=tau, momentum="heuristic", tol=0.0, max_iter=N, seed=4,
+                       problem_id=p)
+        st = init_state(system)
+        for _ in range(N):
+            step(system, st, opts)
+        x = B.state(p, l * 2 + q)[0]
+        assert _rel(x, st.w) <= 1e-10, (p, _rel(x, st.w))
+    B.close()
+
+
+def test_default_tau_rule():
+    probs = _problems()
+    B = rs.Batch(probs[:2], tol=0.0)
+    assert B.info(0).tau == 37
+    assert B.info(1).tau == 64  # m = 110: 64 round(110^(2/3) / 64) = 0 -> clamped to 64
+    B.close()
+
+
+def test_graph_replay_equals_direct_launches():
+    probs = _problems()
+    A = rs.Batch(probs, tol=0.0, seed=2, graph_iters=4)
+    D = rs.Batch(probs, tol=0.0, seed=2, graph_iters=-1)
+    A.step(10)
+    D.step(10)
+    for p in range(len(probs)):
+        for j in (0, 5):
+            for u, v in zip(A.state(p, j), D.state(p, j)):
+                assert np.array_equal(u, v), (p, j)
+    A.close()
+    D.close()
+
+
+def test_converged_batch_matches_direct_solution_and_single_stop_iterations():
+    probs = _problems()
+    tol = 1e-8
+    B = rs.Batch(probs, tol=tol, seed=3)
+    st, rep = B.solve()
+    assert st == rs.RS_OK and rep.converged == rep.solves == 24
+    for p, pr in enumerate(probs):
+        stop, rel = B.slots(p)
+        assert np.all(stop > 0) and np.all(rel <= tol)
+        W = B.weights(p)
+        for l in range(3):
+            for q in range(2):
+                j = l * 2 + q
+                system = ridge_system(pr["X"], pr["y"][:, q], pr["lambdas"][l])
+                A = system.dense_A()
+                w_direct = system.weights(np.linalg.solve(A, system.b))
+                kappa = np.linalg.cond(A)
+                assert _rel(W[j], w_direct) <= 2 * kappa * tol, (p, j)
+                S = _single(pr, p, l, q, 0, seed=3, tol=tol)
+                w1, st1, rep1 = S.solve()
+                S.close()
+                assert abs(rep1.iters - stop[j]) <= 1, (p, j, rep1.iters, stop[j])
+    B.close()
+
+
+def test_caps_and_not_converged():
+    probs = _problems()
+    probs[1]["max_iter"] = 5
+    B = rs.Batch(probs, tol=1e-10, seed=1)
+    st, rep = B.solve()
+    assert st == rs.RS_NOT_CONVERGED
+    assert B.info(1).iters == 5
+    stop, rel = B.slots(1)
+    assert np.all(stop == -1) and np.all(rel > 1e-10)
+    for p in (0, 2, 3):
+        assert np.all(B.slots(p)[0] > 0)
+    B.close()
+
+
+def test_reset_and_autotune():
+    probs = _problems()
+    B = rs.Batch(probs, tol=0.0, seed=5, autotune=True)
+    t = B.tuning()
+    assert t["tuned"] == 1 and t["dense_tk"] in (16, 32) and t["dense_ms"] > 0
+    B.step(8)
+    first = [B.state(p, 3)[0] for p in range(4)]
+    B.reset(6)
+    B.step(8)
+    C = rs.Batch(probs, tol=0.0, seed=6)
+    C.step(8)
+    for p in range(4):
+        assert _rel(B.state(p, 3)[0], C.state(p, 3)[0]) <= 1e-12
+    B.reset(5)
+    B.step(8)
+    for p in range(4):
+        assert _rel(B.state(p, 3)[0], first[p]) <= 1e-14
+    B.close()
+    C.close()
