@@ -40,6 +40,8 @@ WORKLOADS = {
     "dense_mixed_fp64": dict(kind="dense", gen="dense_mixed", sketch="subsample", tau=1024, sub_k=0,
                              precision="fp64",
                              name="dense_50000x8192_lognormal1_subsample_tau1024_primal_fp64"),
+    "batched": dict(kind="batch", precision="fp64",
+                    name="batched_64problems_n2000-40000_d500-8000_half_csr0.005_16lambda_4rhs"),
 }
 
 
@@ -104,6 +106,141 @@ def cpu_baseline(p, wl, gpu_iters_median, sample_s):
             "s_per_iter": per_iter}
 
 
+def batch_weights(pr):
+    """Relative per-iteration work of one batched problem (for extrapolating samples)."""
+    m, K = min(pr["n"], pr["d"]), max(pr["n"], pr["d"])
+    if pr["kind"] == "dense":
+        return 2.0 * m * K * pr["tau"]
+    return float(pr["X"].nnz) * pr["tau"] + m * pr["tau"]
+
+
+def main_batched(args):
+    import numpy as np
+    import torch
+
+    from paper_2105_05565_amd import inputs, rs
+
+    wl = WORKLOADS["batched"]
+    torch.cuda.set_device(0)
+    print(f"[bench] generating {wl['name']}", file=sys.stderr, flush=True)
+    probs = inputs.batched(scale=args.scale)
+    stream = torch.cuda.current_stream().cuda_stream
+    t0 = time.perf_counter()
+    B = rs.Batch(probs, tol=1e-6, seed=1, autotune=True, stream=stream, max_iter=args.max_iter)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    tune = B.tuning()
+    print(f"[bench] batch built in {setup_s:.1f} s, tuning {tune}", file=sys.stderr, flush=True)
+    for w in range(args.warmup):
+        B.reset(10000 + w)
+        B.solve()
+        print(f"[bench] warmup {w} done: {B.k} lock-step iterations", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    times, conv, steps_k = [], [], []
+    for i in range(args.steps):
+        ti = time.perf_counter()
+        B.reset(i + 1)
+        st, rep = B.solve()
+        times.append(time.perf_counter() - ti)
+        conv.append(rep.converged / rep.solves)
+        steps_k.append(rep.iters)
+        print(f"[bench] step {i}: {rep.iters} lock-step iterations, {rep.converged}/{rep.solves} "
+              f"converged, {times[-1]:.2f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    # iterations per slot of the last solve (cap for slots that did not converge)
+    slot_iters = []
+    for p, pr in enumerate(probs):
+        stop, _ = B.slots(p)
+        slot_iters.append(np.where(stop >= 0, stop, pr["max_iter"]))
+    n_solves = sum(len(v) for v in slot_iters)
+    solve_iters = int(sum(int(v.sum()) for v in slot_iters))
+    dense_flops = sum(batch_weights(pr) for pr in probs if pr["kind"] == "dense")
+    T = total / args.steps
+    roofline = {"kernel": "k_as_dense_f64_tab", "bound": "mfma", "achieved": None, "peak": FP64_PEAK_TFS,
+                "unit": "TFLOP/s", "frac": None, "traffic": None,
+                "alg_flops_per_launch": dense_flops, "avg_launch_ms": tune["dense_ms"],
+                "note": "launch duration timed with HIP events by the tuner on the first iteration "
+                        "(every problem active)"}
+    if tune["dense_ms"] > 0:
+        tfs = dense_flops / (tune["dense_ms"] * 1e-3) / 1e12
+        roofline.update({"achieved": round(tfs, 2), "frac": round(tfs / FP64_PEAK_TFS, 4)})
+
+    # the plain single-solve path on samples (one dense, one CSR problem), extrapolated
+    samples = {}
+    for p in (0, len(probs) // 2):
+        pr = probs[p]
+        S = rs.Solver(pr["X"], pr["y"][:, 0], float(pr["lambdas"][8]), tau=pr["tau"],
+                      sketch="subsample" if pr["kind"] == "dense" else "count", tol=0.0, seed=1,
+                      problem_id=p, max_iter=1000000, stream=stream)
+        S.step(8)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        S.step(64)
+        torch.cuda.synchronize()
+        samples[pr["kind"]] = ((time.perf_counter() - ts) / 64, batch_weights(pr))
+        S.close()
+    plain = 0.0
+    for pr, it in zip(probs, slot_iters):
+        t_it, w0 = samples[pr["kind"]]
+        plain += float(it.sum()) * t_it * batch_weights(pr) / w0
+    B.close()
+
+    out = {
+        "metric": "time-to-rel-residual 1e-6", "value": round(T, 4), "unit": "s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(T * 1e3, 1),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl["name"], "problems": len(probs), "lambdas": 16, "rhs": 4,
+                   "solves": n_solves, "dense": sum(pr["kind"] == "dense" for pr in probs),
+                   "tau_rule": "64 round(m^(2/3) / 64) clamped to [64, 512]", "cap": "50 m / tau",
+                   "tol": 1e-6, "momentum": "heuristic", "graph_iters": tune["graph_iters"]},
+        "converged_fraction": round(statistics.median(conv), 4),
+        "lock_step_iters_median": statistics.median(steps_k),
+        "solve_iterations": solve_iters,
+        "solve_iterations_per_s": round(solve_iters / T, 1),
+        "time_s_all": [round(t, 4) for t in times],
+        "setup_s": round(setup_s, 2),
+        "tuning": tune,
+        "roofline": roofline,
+        "plain_fp64_single_solves": {
+            "value": round(plain, 1), "unit": "s",
+            "sample": "64 iterations of one solve of problem 0 (dense) and of problem 32 (CSR) with the "
+                      "single-solve path, scaled by per-problem work and by the iterations each of the "
+                      f"{n_solves} solves took in the batch"},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        from threadpoolctl import threadpool_limits
+
+        from oracle.problem import ridge_system
+        from oracle.solver import Options, init_state, step
+        per = {}
+        with threadpool_limits(limits=1):
+            for p in (0, len(probs) // 2):
+                pr = probs[p]
+                system = ridge_system(pr["X"], pr["y"][:, 0], float(pr["lambdas"][8]))
+                st = init_state(system)
+                opts = Options(sketch="subsample" if pr["kind"] == "dense" else "count", tau=pr["tau"],
+                               momentum="heuristic", seed=1, problem_id=p, tol=0.0)
+                ts = time.perf_counter()
+                while st.k == 0 or (time.perf_counter() - ts < args.cpu_sample_s / 2 and st.k < 50):
+                    step(system, st, opts)
+                per[pr["kind"]] = ((time.perf_counter() - ts) / st.k, batch_weights(pr), st.k)
+        est = 0.0
+        for pr, it in zip(probs, slot_iters):
+            t_it, w0, _ = per[pr["kind"]]
+            est += float(it.sum()) * t_it * batch_weights(pr) / w0
+        out["cpu_baseline"] = {
+            "value": round(est, 1), "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": (f"{per['dense'][2]} iterations of one solve of problem 0 (dense, "
+                       f"{per['dense'][0]:.3f} s/iteration) and {per['csr'][2]} of problem 32 (CSR, "
+                       f"{per['csr'][0]:.4f} s/iteration), 1 thread, scaled by per-problem work to the "
+                       f"{solve_iters} solve-iterations of the batch")}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +250,8 @@ def main():
     ap.add_argument("--lookahead", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-s", type=float, default=15.0)
+    ap.add_argument("--scale", type=float, default=1.0,
+                    help="batched workload only: shrink n and d (shape-alike smaller batch)")
     ap.add_argument("--max-iter", type=int, default=200000,
                     help="iteration cap per solve (a capped run reports per-iteration throughput)")
     args = ap.parse_args()
@@ -120,6 +259,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver is single-GPU.",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batched":
+        return main_batched(args)
 
     import numpy as np
     import torch

@@ -653,6 +653,11 @@ rs_status rs_batch_create(int32_t count, const rs_problem* problems, const rs_op
       sig += (q.sparse ? "c" : "d") + std::to_string(m) + "x" + std::to_string(q.K) + "t" +
              std::to_string(q.tau) + "l" + std::to_string(q.nlam) + ";";
     }
+    // product tiles in decreasing contraction length (a tile costs ~K): with the
+    // workgroups striding over the table this keeps the per-workgroup loads even
+    std::stable_sort(dt.begin(), dt.end(), [&](const DenseTile& a, const DenseTile& b) {
+      return dj[a.job].K > dj[b.job].K;
+    });
     // factorisations in decreasing size, so the largest start first
     std::stable_sort(chol_order.begin(), chol_order.end(),
                      [](const auto& a, const auto& b) { return a.first > b.first; });

@@ -113,3 +113,52 @@ def dense_learned(scale=1.0, seed=DATA_SEED_BASE + 4):
     n, d = int(200000 * scale), int(4096 * scale)
     return make_dense(n, d, 1e-2, seed, np.float32, col_log_sigma=2.0, corr_frac=0.05,
                       name=f"dense_learned_{n}x{d}")
+
+
+def batched_tau(m):
+    """Sketch size of a batched problem: a multiple of 64 near m^(2/3), clamped to [64, 512]
+    and to m (the per-problem rule of the batched workload)."""
+    t = 64.0 * np.floor(m ** (2.0 / 3.0) / 64.0 + 0.5)
+    return int(min(min(512.0, max(64.0, t)), m))
+
+
+def _batched_one(p, n, d, dense, nrhs, seed, density):
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, p])))
+    if dense:
+        X = rng.standard_normal((n, d), dtype=np.float32)
+    else:
+        X = csr_matrix(n, d, int(round(density * n * d)), rng, np.float32)
+    W = rng.standard_normal((d, nrhs))
+    if dense:
+        Y = np.empty((n, nrhs))
+        for r0 in range(0, n, 4096):  # FP64 products without an FP64 copy of X
+            Y[r0:r0 + 4096] = X[r0:r0 + 4096].astype(np.float64) @ W
+    else:
+        Y = np.asarray(X @ W)
+    Y += 0.01 * rng.standard_normal((n, nrhs))
+    return X, Y
+
+
+def batched(count=64, scale=1.0, seed=DATA_SEED_BASE + 3, nrhs=4, nlambda=16, density=0.005,
+            workers=8, cap_factor=50):
+    """Ragged batch: n ~ U{2000..40000}, d ~ U{500..8000} (times `scale`); the first half dense
+    N(0,1) FP32, the second half CSR at 0.5% density with N(0,1) values; lambda grid
+    10^(-4 + 5 i / (nlambda - 1)); nrhs right-hand sides Y = X W* + 0.01 N(0,1), W* ~ N(0,1);
+    per-problem iteration cap cap_factor * m / tau (m = min(n, d), tau = batched_tau(m)).
+    Returns a list of dicts (X, y, lambdas, max_iter, kind)."""
+    import concurrent.futures
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ns = rng.integers(2000, 40001, size=count)
+    ds = rng.integers(500, 8001, size=count)
+    lams = 10.0 ** (-4.0 + 5.0 * np.arange(nlambda) / max(1, nlambda - 1))
+    shapes = [(p, max(8, int(ns[p] * scale)), max(8, int(ds[p] * scale)), p < count // 2)
+              for p in range(count)]
+    with concurrent.futures.ThreadPoolExecutor(max(1, workers)) as ex:
+        data = list(ex.map(lambda s: _batched_one(s[0], s[1], s[2], s[3], nrhs, seed, density), shapes))
+    out = []
+    for (p, n, d, dense), (X, Y) in zip(shapes, data):
+        m = min(n, d)
+        tau = batched_tau(m)
+        out.append(dict(X=X, y=Y, lambdas=lams, max_iter=max(1, int(cap_factor * m / tau)),
+                        kind="dense" if dense else "csr", n=n, d=d, tau=tau))
+    return out
