@@ -103,7 +103,23 @@ typedef struct rs_options {
                                then creates its own stream, since graph capture needs one) */
   int32_t graph_iters;      /* batch: iterations per captured HIP graph; 0 = 8, < 0 = no graph */
   int32_t autotune;         /* batch: 1 = time candidate launch shapes at rs_batch_create */
+  int32_t sampler;          /* RS_SAMPLER_* coordinate proposal of the subsample sketch */
+  int32_t trace_every;      /* > 0: record (features, credits) every that many iterations */
+  int32_t trace_capacity;   /* records kept (0 = 1024); later ones are dropped */
 } rs_options;
+
+/* Coordinate proposals for the subsample sketch (dense X). UNIFORM: every tau-subset
+ * equally likely (Def. 4.2). DIAG: q_j = A_jj / Tr A (the importance sampling of Sec. 7).
+ * LEARNED: q = (1 - 0.1) softmax(s) + 0.1 / m with scores s from an MLP of per-coordinate
+ * features (rs_set_sampler_params). A weighted sketch keeps the tau coordinates with the
+ * smallest u_j / q_j (u_j uniform from the Philox stream tag 4). Every coordinate keeps a
+ * positive probability, so the expected projection stays positive definite (Thm 5.1);
+ * a non-finite q falls back to a uniform draw. The learned proposal is recomputed from
+ * r^k, r^{k-1} at the start of every lookahead batch. */
+enum { RS_SAMPLER_UNIFORM = 0, RS_SAMPLER_LEARNED = 1, RS_SAMPLER_DIAG = 2 };
+/* MLP: features (6) -> 128 -> 128 -> 1, ReLU, FP32; parameters packed W1 [6][128], b1,
+ * W2 [128][128], b2, w3 [128], b3. */
+enum { RS_MLP_FEATURES = 6, RS_MLP_HIDDEN = 128, RS_MLP_PARAMS = 17537 };
 
 typedef struct rs_report {
   int64_t iters;            /* iterations performed */
@@ -185,6 +201,71 @@ rs_status rs_get_products(const rs_handle* h, double* as_out, double* ginv_out);
 rs_status rs_get_history(const rs_handle* h, double* out, int64_t count);
 
 rs_status rs_destroy(rs_handle* h);
+
+/* tau of the handle's sketch. */
+int32_t rs_sketch_size(const rs_handle* h);
+
+/* ------------------------------------------------------------------------
+ * Learned proposal: parameters, traces, training, and single-kernel entry points.
+ *
+ * Features of coordinate j at iteration k (r = r^k, rp = r^{k-1}, a = diag A, last_j the
+ * latest earlier iteration whose sketch held j, or -1): f0 = standardised log a_j,
+ * f1 = clip(log|r_j| - log(a_j)/2 - log||r|| + log(sum a)/2, -30, 30),
+ * f2 = log(1 + k - last_j), f3 = clip(log|r_j - rp_j| - log||r|| + log(m)/2, -30, 30),
+ * f4 = log(k + 1), f5 = [last_j == k - 1]. A trace record of iteration k holds the
+ * features of the tau sketched coordinates and their credits c_b = delta_b rho_b, whose
+ * sum delta^T G delta is the decrease of the squared A-norm error (eq:gradeqf).
+ * Training minimises, per record, the cross-entropy between t = max(c, 0) / sum max(c, 0)
+ * and softmax(s) over the record's coordinates, with Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8) on mini-batches of records.
+ * ------------------------------------------------------------------------ */
+/* Parameters of the learned proposal (host, RS_MLP_PARAMS finite values). */
+rs_status rs_set_sampler_params(rs_handle* h, const float* params);
+/* Trace records held by the handle (rs_reset keeps them). */
+rs_status rs_trace_count(const rs_handle* h, int64_t* count);
+/* Records first .. first+count-1: F (count x tau x 6) and credits (count x tau), host. */
+rs_status rs_get_trace(const rs_handle* h, float* F, float* credits, int64_t first, int64_t count);
+/* The proposal q (m values, host) of the latest draw and its usable flag (may be NULL). */
+rs_status rs_get_proposal(const rs_handle* h, float* q, int32_t* ok);
+
+typedef struct rs_trainer rs_trainer;
+/* Trainer for sketches of size tau; parameters initialised from Philox4x64-10 with key
+ * (init_seed, 0), counter (index, 0, 5, 0): weights uniform on +-1/sqrt(fan_in), biases 0. */
+rs_status rs_trainer_create(int32_t tau, uint64_t init_seed, rs_trainer** out);
+/* Append a handle's trace records (same tau) or host records to the trainer's store. */
+rs_status rs_trainer_add_traces(rs_trainer* t, const rs_handle* h);
+rs_status rs_trainer_add_records(rs_trainer* t, const float* F, const float* credits, int64_t count);
+rs_status rs_trainer_records(const rs_trainer* t, int64_t* count);
+/* `epochs` passes over the records in an order shuffled per epoch from shuffle_seed;
+ * mini-batches of `batch` records (a remainder is skipped); epoch_loss (host, may be
+ * NULL) receives the mean loss of each epoch. */
+rs_status rs_trainer_fit(rs_trainer* t, int32_t epochs, int32_t batch, double lr, uint64_t shuffle_seed,
+                         double* epoch_loss);
+rs_status rs_trainer_get_params(const rs_trainer* t, float* out);
+rs_status rs_trainer_set_params(rs_trainer* t, const float* in);
+const char* rs_trainer_last_error(const rs_trainer* t);
+rs_status rs_trainer_destroy(rs_trainer* t);
+
+/* Single kernels of the proposal on host arrays (for checking each piece). */
+rs_status rs_mlp_init(uint64_t seed, float* params_out);
+/* s_out[rows] = MLP(F[rows][6]). */
+rs_status rs_mlp_forward(const float* params, const float* F, int64_t rows, float* s_out);
+/* Mean loss over nrec records (F: nrec x tau x 6, credits: nrec x tau) and its gradient. */
+rs_status rs_mlp_gradient(const float* params, const float* F, const float* credits, int32_t nrec,
+                          int32_t tau, float* grad_out, double* loss_out);
+/* One Adam step t >= 1 on host arrays of RS_MLP_PARAMS (updated in place). */
+rs_status rs_adam_update(float* params, float* m1, float* m2, const float* grad, int64_t t, double lr,
+                         double b1, double b2, double eps);
+/* q = (1 - eps) softmax(s) + eps / m; *ok_out = 0 if q is not finite. */
+rs_status rs_proposal(const float* s, int64_t m, double eps, float* q_out, int32_t* ok_out);
+/* Features F_out (m x 6) of iteration k from a = diag A (> 0), r, rp and last. */
+rs_status rs_features(const double* a, const double* r, const double* rp, const int32_t* last, int64_t m,
+                      int64_t k, float* F_out);
+/* The weighted sketch of iteration k: C_out (tau, ascending) = the tau smallest
+ * (u_j / q_j, j), u_j = ((W0 >> 12) + 0.5) 2^-52 of Philox block (j, k, 4, 0) under key
+ * (seed, problem_id); q > 0 and finite. */
+rs_status rs_draw_weighted(const float* q, int64_t m, int32_t tau, uint64_t seed, uint64_t problem_id,
+                           int64_t k, int32_t* C_out);
 
 /* ------------------------------------------------------------------------
  * Batched solves: many ridge problems, each with a grid of regularisers and

@@ -89,6 +89,8 @@ __device__ __forceinline__ void select_body(const SketchArgs& a, int slot, unsig
   const int64_t m = a.m;
   const uint64_t k = (uint64_t)((a.kdev ? *a.kdev : a.k0) + slot);
   const uint64_t tag = (a.kind == kSubcount) ? kTagSubcount : kTagSubsample;
+  const bool weighted = a.kind == kWeighted;
+  const bool q_ok = weighted && a.q_ok && *a.q_ok != 0;
   uint64_t* keys = a.keys + (int64_t)slot * m;
   int32_t* hmap = a.hmap + (int64_t)slot * m;
   int32_t* members = a.members + (int64_t)slot * a.nsel;
@@ -99,10 +101,21 @@ __device__ __forceinline__ void select_body(const SketchArgs& a, int slot, unsig
   if (tid == 0) H->ncand = 0;
   __syncthreads();
   for (int64_t j = tid; j < m; j += kSelThreads) {
-    const Philox4 r = philox4x64_10((uint64_t)j, k, tag, 0, a.seed, a.pid);
-    keys[j] = r.v0;
+    uint64_t key;
+    if (weighted) {
+      // u_j in (0, 1), exact in FP64; key_j = u_j / q_j (IEEE division). A positive
+      // double's bit pattern orders like its value, so the same 64-bit selection applies.
+      // Without a usable proposal the keys are u_j themselves: a uniform tau-subset.
+      const Philox4 r = philox4x64_10((uint64_t)j, k, kTagWeighted, 0, a.seed, a.pid);
+      const double u = ((double)(r.v0 >> 12) + 0.5) * 0x1p-52;
+      const double kv = q_ok ? u / (double)a.q[j] : u;
+      key = (uint64_t)__double_as_longlong(kv);
+    } else {
+      key = philox4x64_10((uint64_t)j, k, tag, 0, a.seed, a.pid).v0;
+    }
+    keys[j] = key;
     hmap[j] = -1;
-    atomicAdd(&H->hist[r.v0 >> 52], 1);
+    atomicAdd(&H->hist[key >> 52], 1);
   }
   __syncthreads();
 

@@ -86,6 +86,24 @@ struct rs_handle {
   int ev_used = 0;
   rs_profile prof{};
 
+  // learned / diagonal proposal and traces (dense subsample only)
+  int sampler = RS_SAMPLER_UNIFORM;
+  int trace_every = 0;
+  int trace_cap = 0;
+  double* adiag = nullptr;   // A_jj
+  double* lstats = nullptr;  // mean log a, std log a, sum a
+  double* log_rn = nullptr;
+  int32_t* last = nullptr;   // latest iteration before the current batch holding each coordinate
+  float* feat = nullptr;     // m x 6
+  float* score = nullptr;    // m
+  float* q = nullptr;        // m
+  int32_t* q_ok = nullptr;
+  float* params = nullptr;   // MLP parameters
+  bool params_set = false;
+  float* tr_F = nullptr;
+  float* tr_c = nullptr;
+  int32_t* tr_count = nullptr;
+
   int64_t k = 0;          // iterations performed
   int64_t batch_k0 = -1;  // iteration of slot 0 of the most recent batch
   int batch_n = 0;
@@ -225,6 +243,20 @@ void run_batch(rs_handle* h, int64_t k0, int nb) {
   a.err = h->err;
   a.done = done;
   int pe = prof_begin(h, RS_PROF_SKETCH, nb);
+  if (h->sampler != RS_SAMPLER_UNIFORM) {
+    // coordinates drawn from the proposal q (features of r^{k0}, r^{k0-1} for the
+    // learned one): the tau smallest u_j / q_j per sketch
+    if (h->sampler == RS_SAMPLER_LEARNED) {
+      check_hip(launch_features(h->adiag, h->lstats, h->rbuf[k0 & 1], h->rbuf[(k0 + 1) & 1], h->last, h->m,
+                                k0, h->log_rn, h->feat, done, s),
+                "features");
+      check_hip(launch_mlp_fwd(h->params, h->feat, nullptr, 0, h->m, h->score, done, s), "scores");
+      check_hip(launch_proposal(h->score, h->m, 0.1f, h->q, h->q_ok, done, s), "proposal");
+    }
+    a.kind = kWeighted;
+    a.q = h->q;
+    a.q_ok = h->q_ok;
+  }
   check_hip(launch_sketch(a, s), "sketch");
   if (h->sparse)
     check_hip(launch_build_t(h->zt_col, h->zt_val, h->vals_f32, h->nnz, h->hmap, h->m, nb, h->tbuf,
@@ -276,6 +308,29 @@ void run_batch(rs_handle* h, int64_t k0, int nb) {
                            h->npart, h->flags, h->hist, k, h->mixed ? -1.0 : h->opt.tol, h->delta, s),
               "delta");
     prof_end(h, pe);
+    if (h->trace_every > 0 && k % h->trace_every == 0) {
+      TraceArgs t{};
+      t.m = h->m;
+      t.tau = h->tau;
+      t.k = k;
+      t.k0 = k0;
+      t.slot = i;
+      t.members = h->members + (int64_t)i * h->nsel;
+      t.hmap_batch = h->hmap;
+      t.last = h->last;
+      t.a = h->adiag;
+      t.stats = h->lstats;
+      t.r = h->rbuf[cur];
+      t.rp = h->rbuf[nxt];
+      t.delta = h->delta;
+      t.rho = h->rho;
+      t.F = h->tr_F;
+      t.credits = h->tr_c;
+      t.count = h->tr_count;
+      t.capacity = h->trace_cap;
+      t.flags = h->flags;
+      check_hip(launch_trace(t, s), "trace");
+    }
     pe = prof_begin(h, RS_PROF_UPDATE, 1, 2);
     const bool has_next = i + 1 < nb;
     const size_t as_elt = h->mixed ? sizeof(float) : sizeof(double);
@@ -299,6 +354,8 @@ void run_batch(rs_handle* h, int64_t k0, int nb) {
     }
   }
   prof_end(h, pe_iters);
+  if (h->last)
+    check_hip(launch_mark_last(h->members, h->tau, nb, k0, h->last, s), "sketch history");
   h->batch_k0 = k0;
   h->batch_n = nb;
 }
@@ -306,6 +363,8 @@ void run_batch(rs_handle* h, int64_t k0, int nb) {
 // Advance up to `iters` iterations, one lookahead batch at a time. After each batch
 // the stop flag, the factorisation status and the error word are read back.
 void advance(rs_handle* h, int64_t iters) {
+  if (h->sampler == RS_SAMPLER_LEARNED && !h->params_set)
+    throw Fail{RS_EINVAL, "the learned sampler needs rs_set_sampler_params before iterating"};
   int64_t k_enq = h->k;
   int64_t left = std::min(iters, h->opt.max_iter - h->k);
   std::vector<int32_t> st(h->B);
@@ -319,7 +378,8 @@ void advance(rs_handle* h, int64_t iters) {
     if (k_a >= 0 && k_b > k_a && rel_b < rel_a && rel_b > 0.0 && h->opt.tol > 0.0) {
       const double rate = std::log(rel_b / rel_a) / (double)(k_b - k_a);
       const double need = std::log(h->opt.tol / rel_b) / rate - (double)(h->k - k_b);
-      if (need < nb) nb = (int)std::max<double>(16.0, std::min<double>(nb, need * 1.1 + 8.0));
+      // never above the lookahead buffers nor the iterations asked for
+      if (need < nb) nb = (int)std::min<double>(nb, std::max<double>(std::min(16, nb), need * 1.1 + 8.0));
     }
     run_batch(h, k_enq, nb);
     k_enq += nb;
@@ -385,6 +445,9 @@ rs_status rs_options_default(rs_options* o) {
   o->stream = nullptr;
   o->graph_iters = 0;
   o->autotune = 0;
+  o->sampler = RS_SAMPLER_UNIFORM;
+  o->trace_every = 0;
+  o->trace_capacity = 0;
   return RS_OK;
 }
 
@@ -435,6 +498,11 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
     if (o->precision == RS_PREC_MIXED_BF16 && o->refresh_every < 1)
       throw Fail{RS_EINVAL, "refresh_every must be >= 1"};
     h->mixed = o->precision == RS_PREC_MIXED_BF16;
+    if (o->sampler < RS_SAMPLER_UNIFORM || o->sampler > RS_SAMPLER_DIAG) throw Fail{RS_EINVAL, "unknown sampler"};
+    if (o->trace_every < 0 || o->trace_capacity < 0) throw Fail{RS_EINVAL, "trace settings must be >= 0"};
+    if ((o->sampler != RS_SAMPLER_UNIFORM || o->trace_every > 0) &&
+        (X->layout == RS_CSR || o->sketch != RS_SKETCH_SUBSAMPLE))
+      throw Fail{RS_EUNSUPPORTED, "proposals and traces are built for the subsample sketch on dense data"};
     if (o->momentum < RS_MOMENTUM_NONE || o->momentum > RS_MOMENTUM_HEURISTIC)
       throw Fail{RS_EINVAL, "unknown momentum"};
     if (!(o->tol >= 0.0)) throw Fail{RS_EINVAL, "tol must be >= 0"};
@@ -618,6 +686,38 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
       h->xbuf[i] = dalloc<double>(h, h->m);
       h->rbuf[i] = dalloc<double>(h, h->m);
     }
+    h->sampler = o->sampler;
+    h->trace_every = o->trace_every;
+    if (h->sampler != RS_SAMPLER_UNIFORM || h->trace_every > 0) {
+      h->adiag = dalloc<double>(h, h->m);
+      h->lstats = dalloc<double>(h, 3);
+      h->log_rn = dalloc<double>(h, 1);
+      h->last = dalloc<int32_t>(h, h->m);
+      h->q = dalloc<float>(h, h->m);
+      h->q_ok = dalloc<int32_t>(h, 1);
+      if (h->mixed)
+        check_hip(launch_adiag(h->Z32, 1, h->K, h->m, h->K, h->lam, h->adiag, h->lstats, s), "A_jj");
+      else
+        check_hip(launch_adiag(h->Z, 0, h->ldz, h->m, h->K, h->lam, h->adiag, h->lstats, s), "A_jj");
+      check_hip(hipMemsetAsync(h->last, 0xFF, sizeof(int32_t) * h->m, s), "memset");  // -1: never sampled
+      if (h->sampler == RS_SAMPLER_DIAG) {
+        check_hip(launch_diag_q(h->adiag, h->lstats, h->m, h->q, s), "A_jj / Tr A");
+        const int32_t one = 1;
+        check_hip(hipMemcpy(h->q_ok, &one, sizeof(int32_t), hipMemcpyHostToDevice), "flag");
+      }
+      if (h->sampler == RS_SAMPLER_LEARNED) {
+        h->feat = dalloc<float>(h, (size_t)h->m * kMlpFeatures);
+        h->score = dalloc<float>(h, h->m);
+        h->params = dalloc<float>(h, kMlpParams);
+      }
+      if (h->trace_every > 0) {
+        h->trace_cap = o->trace_capacity > 0 ? o->trace_capacity : 1024;
+        h->tr_F = dalloc<float>(h, (size_t)h->trace_cap * h->tau * kMlpFeatures);
+        h->tr_c = dalloc<float>(h, (size_t)h->trace_cap * h->tau);
+        h->tr_count = dalloc<int32_t>(h, 1);
+        check_hip(hipMemsetAsync(h->tr_count, 0, sizeof(int32_t), s), "memset");
+      }
+    }
     if (o->profile) {
       // sketch, AS, Cholesky, iteration sequence; delta, update and refresh per iteration
       const int pairs = 4 + 3 * B + 2;
@@ -678,6 +778,7 @@ rs_status rs_reset(rs_handle* h, uint64_t seed) {
     h->batch_n = 0;
     check_hip(hipMemsetAsync(h->status, 0, sizeof(int32_t) * h->B, h->stream), "memset");
     check_hip(hipMemsetAsync(h->err, 0, sizeof(int32_t), h->stream), "memset");
+    if (h->last) check_hip(hipMemsetAsync(h->last, 0xFF, sizeof(int32_t) * h->m, h->stream), "memset");
     check_hip(launch_init_state(h->b, h->xbuf[0], h->xbuf[1], h->rbuf[0], h->rbuf[1], h->m,
                                 h->partials, h->npart, h->flags, h->hist, h->stream),
               "init");
@@ -705,6 +806,7 @@ rs_status rs_get_profile(rs_handle* h, rs_profile* out, int32_t clear) {
 
 int64_t rs_iteration(const rs_handle* h) { return h ? h->k : -1; }
 int64_t rs_system_size(const rs_handle* h) { return h ? h->m : -1; }
+int32_t rs_sketch_size(const rs_handle* h) { return h ? h->tau : -1; }
 
 rs_status rs_get_weights(rs_handle* h, double* w_out) {
   if (!h || !w_out) return RS_EINVAL;
@@ -826,6 +928,57 @@ rs_status rs_get_history(const rs_handle* h, double* out, int64_t count) {
   if (!h || !out || count < 0 || count > h->k + 1) return RS_EINVAL;
   if (count && hipMemcpy(out, h->hist, sizeof(double) * count, hipMemcpyDeviceToHost) != hipSuccess)
     return RS_EDEVICE;
+  return RS_OK;
+}
+
+rs_status rs_set_sampler_params(rs_handle* h, const float* params) {
+  if (!h || !params) return RS_EINVAL;
+  if (h->sampler != RS_SAMPLER_LEARNED) {
+    h->last_error = "the handle was not created with the learned sampler";
+    return RS_EINVAL;
+  }
+  for (int i = 0; i < kMlpParams; ++i)
+    if (!std::isfinite(params[i])) {
+      h->last_error = "sampler parameters must be finite";
+      return RS_EINVAL;
+    }
+  if (hipMemcpy(h->params, params, sizeof(float) * kMlpParams, hipMemcpyHostToDevice) != hipSuccess)
+    return RS_EDEVICE;
+  h->params_set = true;
+  return RS_OK;
+}
+
+rs_status rs_trace_count(const rs_handle* h, int64_t* count) {
+  if (!h || !count) return RS_EINVAL;
+  if (!h->tr_count) {
+    *count = 0;
+    return RS_OK;
+  }
+  int32_t c = 0;
+  if (hipMemcpy(&c, h->tr_count, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) return RS_EDEVICE;
+  *count = std::min<int64_t>(c, h->trace_cap);
+  return RS_OK;
+}
+
+rs_status rs_get_trace(const rs_handle* h, float* F, float* credits, int64_t first, int64_t count) {
+  int64_t n = 0;
+  rs_status st = rs_trace_count(h, &n);
+  if (st != RS_OK) return st;
+  if (first < 0 || count < 0 || first + count > n) return RS_EINVAL;
+  const size_t rf = (size_t)h->tau * kMlpFeatures, rc = (size_t)h->tau;
+  if (F && count &&
+      hipMemcpy(F, h->tr_F + first * rf, sizeof(float) * rf * count, hipMemcpyDeviceToHost) != hipSuccess)
+    return RS_EDEVICE;
+  if (credits && count &&
+      hipMemcpy(credits, h->tr_c + first * rc, sizeof(float) * rc * count, hipMemcpyDeviceToHost) != hipSuccess)
+    return RS_EDEVICE;
+  return RS_OK;
+}
+
+rs_status rs_get_proposal(const rs_handle* h, float* q, int32_t* ok) {
+  if (!h || !q || !h->q) return RS_EINVAL;
+  if (hipMemcpy(q, h->q, sizeof(float) * h->m, hipMemcpyDeviceToHost) != hipSuccess) return RS_EDEVICE;
+  if (ok && hipMemcpy(ok, h->q_ok, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) return RS_EDEVICE;
   return RS_OK;
 }
 

@@ -22,7 +22,9 @@ namespace rs {
 // Count: every coordinate is a member; members ordered by (bucket, index).
 // SubCount: the s kept coordinates; bucket b holds ranks [b k, (b+1) k).
 // ---------------------------------------------------------------------------
-enum SketchKind : int32_t { kSubsample = 0, kCount = 1, kSubcount = 2 };
+enum SketchKind : int32_t { kSubsample = 0, kCount = 1, kSubcount = 2, kWeighted = 3 };
+// kWeighted: a subsample whose coordinates are the tau smallest (u_j / q_j, j) for a
+// proposal q (u_j uniform from the tag-4 stream); stored exactly like a subsample.
 
 // Philox4x64-10 stream tags (counter word 2).
 constexpr uint64_t kTagSubsample = 1, kTagCount = 2, kTagSubcount = 3, kTagWeighted = 4;
@@ -43,6 +45,8 @@ struct SketchArgs {
   int32_t* err;        // device error word (set nonzero on an internal limit)
   const int32_t* done; // skip all work when *done != 0
   const int64_t* kdev; // when set, slot 0 draws iteration *kdev (read on the device)
+  const float* q;      // kWeighted: proposal q[m] (> 0)
+  const int32_t* q_ok; // kWeighted: 0 -> q unusable, draw a uniform subset instead
 };
 
 // Device-side solve state shared by the per-iteration kernels.
@@ -232,6 +236,61 @@ hipError_t launch_bupdate(const BState* S, const int32_t* items, int32_t nitems,
 hipError_t launch_bfinal(const BState* S, int32_t nprob, BGlobal* g, double tol, hipStream_t s);
 hipError_t launch_bcol(const double* src, int64_t m, int64_t src_ld, int64_t src_col, double* dst,
                        int64_t dst_ld, int64_t dst_col, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Learned proposal (features, MLP, proposal, traces, training).
+// ---------------------------------------------------------------------------
+constexpr int kMlpFeatures = 6;
+constexpr int kMlpHidden = 128;
+constexpr int kMlpParams = kMlpFeatures * kMlpHidden + kMlpHidden + kMlpHidden * kMlpHidden +
+                           kMlpHidden + kMlpHidden + 1;
+constexpr uint64_t kTagMlpInit = 5;
+
+struct TraceArgs {
+  int64_t m;
+  int32_t tau;
+  int64_t k, k0;               // iteration recorded; iteration of slot 0 of its batch
+  int32_t slot;                // k - k0
+  const int32_t* members;      // sketch of iteration k (subsample: bucket b = coordinate C_b)
+  const int32_t* hmap_batch;   // [slots][m] sketches of the batch
+  const int32_t* last;         // latest iteration < k0 holding each coordinate (-1: none)
+  const double* a;             // A_jj
+  const double* stats;         // mean log a, std log a, sum a
+  const double* r;             // r^k
+  const double* rp;            // r^{k-1}
+  const double* delta;         // delta_k
+  const double* rho;           // rho_k = S_k^T r^k
+  float* F;                    // [capacity][tau][6]
+  float* credits;              // [capacity][tau]
+  int32_t* count;              // records written (may exceed capacity: extra ones dropped)
+  int32_t capacity;
+  const DevFlags* flags;
+};
+
+hipError_t launch_adiag(const void* Z, int32_t z_f32, int64_t ldz, int64_t m, int64_t K, double lam,
+                        double* a, double* stats, hipStream_t s);
+hipError_t launch_lstats(const double* a, int64_t m, double* stats, hipStream_t s);
+hipError_t launch_features(const double* a, const double* stats, const double* r, const double* rp,
+                           const int32_t* last, int64_t m, int64_t k, double* log_rn, float* F,
+                           const int32_t* done, hipStream_t s);
+hipError_t launch_trace(const TraceArgs& t, hipStream_t s);
+hipError_t launch_mark_last(const int32_t* members, int32_t tau, int32_t nslots, int64_t k0,
+                            int32_t* last, hipStream_t s);
+hipError_t launch_proposal(const float* s_in, int64_t m, float eps, float* q, int32_t* ok,
+                           const int32_t* done, hipStream_t s);
+hipError_t launch_diag_q(const double* a, const double* stats, int64_t m, float* q, hipStream_t s);
+hipError_t launch_mlp_init(float* p, uint64_t seed, hipStream_t s);
+hipError_t launch_mlp_fwd(const float* P, const float* F, const int32_t* rec, int32_t tau, int64_t rows,
+                          float* out, const int32_t* done, hipStream_t s);
+int32_t mlp_bwd_blocks(int64_t rows);
+// One training evaluation over nrec records (rows = nrec * tau): scores into s_buf, dL/ds
+// into ds_buf, per-record losses into loss[nrec], gradient (mean over records) into grad.
+// partial holds mlp_bwd_blocks(rows) * kMlpParams floats.
+hipError_t launch_mlp_step(const float* P, const float* F, const float* credits, const int32_t* rec,
+                           int32_t tau, int32_t nrec, float* s_buf, float* ds_buf, double* loss,
+                           float* partial, float* grad, hipStream_t s);
+hipError_t launch_adam(float* P, float* m1, float* m2, const float* g, int64_t t, double lr, double b1,
+                       double b2, double eps, hipStream_t s);
 
 // Solve-state kernels.
 int32_t update_partials(int64_t m, int32_t tau);  // partial sums written by k_update

@@ -43,7 +43,14 @@ class rs_options(ctypes.Structure):
                 ("max_iter", ctypes.c_int64), ("seed", ctypes.c_uint64), ("problem_id", ctypes.c_uint64),
                 ("refresh_every", ctypes.c_int32), ("lookahead", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("stream", ctypes.c_void_p),
-                ("graph_iters", ctypes.c_int32), ("autotune", ctypes.c_int32)]
+                ("graph_iters", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("sampler", ctypes.c_int32), ("trace_every", ctypes.c_int32),
+                ("trace_capacity", ctypes.c_int32)]
+
+
+RS_SAMPLER_UNIFORM, RS_SAMPLER_LEARNED, RS_SAMPLER_DIAG = 0, 1, 2
+SAMPLERS = {"uniform": RS_SAMPLER_UNIFORM, "learned": RS_SAMPLER_LEARNED, "diag": RS_SAMPLER_DIAG}
+RS_MLP_FEATURES, RS_MLP_HIDDEN, RS_MLP_PARAMS = 6, 128, 17537
 
 
 class rs_problem(ctypes.Structure):
@@ -114,6 +121,30 @@ SIGNATURES = {
     "rs_destroy": (ctypes.c_int32, [_P]),
     "rs_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "rs_last_error": (ctypes.c_char_p, [_P]),
+    "rs_sketch_size": (ctypes.c_int32, [_P]),
+    "rs_set_sampler_params": (ctypes.c_int32, [_P, _P]),
+    "rs_trace_count": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "rs_get_trace": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int64, ctypes.c_int64]),
+    "rs_get_proposal": (ctypes.c_int32, [_P, _P, _P]),
+    "rs_trainer_create": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(_P)]),
+    "rs_trainer_add_traces": (ctypes.c_int32, [_P, _P]),
+    "rs_trainer_add_records": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int64]),
+    "rs_trainer_records": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "rs_trainer_fit": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64,
+                                        _P]),
+    "rs_trainer_get_params": (ctypes.c_int32, [_P, _P]),
+    "rs_trainer_set_params": (ctypes.c_int32, [_P, _P]),
+    "rs_trainer_last_error": (ctypes.c_char_p, [_P]),
+    "rs_trainer_destroy": (ctypes.c_int32, [_P]),
+    "rs_mlp_init": (ctypes.c_int32, [ctypes.c_uint64, _P]),
+    "rs_mlp_forward": (ctypes.c_int32, [_P, _P, ctypes.c_int64, _P]),
+    "rs_mlp_gradient": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _D]),
+    "rs_adam_update": (ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_double]),
+    "rs_proposal": (ctypes.c_int32, [_P, ctypes.c_int64, ctypes.c_double, _P, _P]),
+    "rs_features": (ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_int64, _P]),
+    "rs_draw_weighted": (ctypes.c_int32, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
+                                          ctypes.c_uint64, ctypes.c_int64, _P]),
     "rs_batch_create": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(rs_problem),
                                          ctypes.POINTER(rs_options), ctypes.POINTER(_P)]),
     "rs_batch_step": (ctypes.c_int32, [_P, ctypes.c_int64]),
@@ -255,6 +286,139 @@ def rs_destroy(h):
         load().rs_destroy(h)
 
 
+def rs_sketch_size(h):
+    return load().rs_sketch_size(h)
+
+
+def rs_set_sampler_params(h, params):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    assert p.shape == (RS_MLP_PARAMS,)
+    _check(load().rs_set_sampler_params(h, _ptr(p)), "rs_set_sampler_params", h)
+
+
+def rs_trace_count(h):
+    n = ctypes.c_int64(0)
+    _check(load().rs_trace_count(h, ctypes.byref(n)), "rs_trace_count", h)
+    return n.value
+
+
+def rs_get_trace(h, F, credits, first, count):
+    _check(load().rs_get_trace(h, _ptr(F), _ptr(credits), int(first), int(count)), "rs_get_trace", h)
+
+
+def rs_get_proposal(h, q, ok=None):
+    _check(load().rs_get_proposal(h, _ptr(q), _ptr(ok)), "rs_get_proposal", h)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def rs_mlp_init(seed):
+    out = np.zeros(RS_MLP_PARAMS, dtype=np.float32)
+    _check(load().rs_mlp_init(int(seed), _ptr(out)), "rs_mlp_init")
+    return out
+
+
+def rs_mlp_forward(params, F):
+    P, Fm = _f32(params), _f32(F)
+    out = np.zeros(Fm.shape[0], dtype=np.float32)
+    _check(load().rs_mlp_forward(_ptr(P), _ptr(Fm), Fm.shape[0], _ptr(out)), "rs_mlp_forward")
+    return out
+
+
+def rs_mlp_gradient(params, Fs, credits):
+    P, Fm, C = _f32(params), _f32(Fs), _f32(credits)
+    nrec, tau = C.shape
+    g = np.zeros(RS_MLP_PARAMS, dtype=np.float32)
+    loss = ctypes.c_double(0.0)
+    _check(load().rs_mlp_gradient(_ptr(P), _ptr(Fm), _ptr(C), nrec, tau, _ptr(g), ctypes.byref(loss)),
+           "rs_mlp_gradient")
+    return loss.value, g
+
+
+def rs_adam_update(params, m1, m2, grad, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    P, a, v, g = _f32(params).copy(), _f32(m1).copy(), _f32(m2).copy(), _f32(grad)
+    _check(load().rs_adam_update(_ptr(P), _ptr(a), _ptr(v), _ptr(g), int(t), lr, b1, b2, eps), "rs_adam_update")
+    return P, a, v
+
+
+def rs_proposal(s, eps=0.1):
+    sv = _f32(s)
+    q = np.zeros(sv.shape[0], dtype=np.float32)
+    ok = np.zeros(1, dtype=np.int32)
+    _check(load().rs_proposal(_ptr(sv), sv.shape[0], eps, _ptr(q), _ptr(ok)), "rs_proposal")
+    return q, bool(ok[0])
+
+
+def rs_features(a, r, rp, last, k):
+    a, r, rp = (np.ascontiguousarray(v, dtype=np.float64) for v in (a, r, rp))
+    last = np.ascontiguousarray(last, dtype=np.int32)
+    F = np.zeros((a.shape[0], RS_MLP_FEATURES), dtype=np.float32)
+    _check(load().rs_features(_ptr(a), _ptr(r), _ptr(rp), _ptr(last), a.shape[0], int(k), _ptr(F)), "rs_features")
+    return F
+
+
+def rs_draw_weighted(q, tau, seed, problem_id, k):
+    qv = _f32(q)
+    C = np.zeros(int(tau), dtype=np.int32)
+    _check(load().rs_draw_weighted(_ptr(qv), qv.shape[0], int(tau), int(seed), int(problem_id), int(k), _ptr(C)),
+           "rs_draw_weighted")
+    return C
+
+
+class Trainer:
+    """Owns one rs_trainer (MLP parameters, Adam state and a store of trace records)."""
+
+    def __init__(self, tau, init_seed=1):
+        self.t = _P()
+        _check(load().rs_trainer_create(int(tau), int(init_seed), ctypes.byref(self.t)), "rs_trainer_create")
+        self.tau = int(tau)
+
+    def _chk(self, st, where):
+        if st < 0:
+            raise RsError(st, where, load().rs_trainer_last_error(self.t).decode())
+
+    def add_traces(self, solver):
+        self._chk(load().rs_trainer_add_traces(self.t, solver.h), "rs_trainer_add_traces")
+
+    def add_records(self, F, credits):
+        Fm, C = _f32(F), _f32(credits)
+        self._chk(load().rs_trainer_add_records(self.t, _ptr(Fm), _ptr(C), C.shape[0]), "rs_trainer_add_records")
+
+    @property
+    def records(self):
+        n = ctypes.c_int64(0)
+        self._chk(load().rs_trainer_records(self.t, ctypes.byref(n)), "rs_trainer_records")
+        return n.value
+
+    def fit(self, epochs, batch=16, lr=1e-3, shuffle_seed=1):
+        out = np.zeros(max(1, epochs))
+        self._chk(load().rs_trainer_fit(self.t, int(epochs), int(batch), float(lr), int(shuffle_seed), _ptr(out)),
+                  "rs_trainer_fit")
+        return out[:epochs]
+
+    def params(self):
+        out = np.zeros(RS_MLP_PARAMS, dtype=np.float32)
+        self._chk(load().rs_trainer_get_params(self.t, _ptr(out)), "rs_trainer_get_params")
+        return out
+
+    def set_params(self, p):
+        pv = _f32(p)
+        self._chk(load().rs_trainer_set_params(self.t, _ptr(pv)), "rs_trainer_set_params")
+
+    def close(self):
+        if self.t:
+            load().rs_trainer_destroy(self.t)
+            self.t = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def batch_last_error(b=None):
     return load().rs_batch_last_error(b).decode()
 
@@ -388,7 +552,7 @@ class Solver:
     def __init__(self, X, y, lam, *, tau, sketch="subsample", form="auto", momentum="heuristic",
                  precision="fp64", subcount_k=0, tol=1e-6, max_iter=100000, seed=1, problem_id=0,
                  eta=0.995, beta_max=0.5, gamma=1.0, beta=0.5, lookahead=0, refresh_every=20,
-                 profile=False, stream=None):
+                 profile=False, stream=None, sampler="uniform", trace_every=0, trace_capacity=0):
         o = rs_options_default()
         o.form, o.sketch, o.tau = FORMS[form], SKETCHES[sketch], int(tau)
         o.subcount_k, o.momentum, o.precision = int(subcount_k), MOMENTA[momentum], PRECISIONS[precision]
@@ -396,6 +560,7 @@ class Solver:
         o.max_iter, o.seed, o.problem_id = int(max_iter), int(seed), int(problem_id)
         o.refresh_every, o.lookahead, o.profile = int(refresh_every), int(lookahead), int(profile)
         o.stream = stream
+        o.sampler, o.trace_every, o.trace_capacity = SAMPLERS[sampler], int(trace_every), int(trace_capacity)
         M, keep = make_matrix(X)
         if M.mem == RS_DEVICE:
             yv = y.double().contiguous()
@@ -449,6 +614,23 @@ class Solver:
         Gi = np.zeros((tau, tau))
         rs_get_products(self.h, AS, Gi)
         return AS, Gi
+
+    def set_sampler_params(self, params):
+        rs_set_sampler_params(self.h, params)
+
+    def trace(self):
+        n = rs_trace_count(self.h)
+        F = np.zeros((n, self.tau, RS_MLP_FEATURES), dtype=np.float32)
+        C = np.zeros((n, self.tau), dtype=np.float32)
+        if n:
+            rs_get_trace(self.h, F, C, 0, n)
+        return F, C
+
+    def proposal(self):
+        q = np.zeros(self.m, dtype=np.float32)
+        ok = np.zeros(1, dtype=np.int32)
+        rs_get_proposal(self.h, q, ok)
+        return q, bool(ok[0])
 
     def history(self):
         out = np.zeros(self.k + 1)

@@ -1,0 +1,197 @@
+"""GPU: the learned proposal's kernels against the oracle, and the samplers in the solver.
+
+* init: bit-exact (both round the same FP64 value to FP32);
+* features, scores, proposal, Adam: FP32 kernels against the FP64 oracle on the same
+  inputs, relative 1e-5 (1e-4 for gradients, whose sums run over thousands of rows);
+* weighted draw: bit-exact against the oracle for test-generated proposals;
+* traces: the records of a uniform solve against the oracle's own run of that solve;
+* samplers: DIAG and LEARNED solves converge to the direct solution; the draw in the
+  solver is the weighted-draw kernel applied to the solver's proposal.
+"""
+import numpy as np
+import pytest
+
+from oracle import mlp
+from oracle import sketch as osk
+from oracle.problem import ridge_system
+from oracle.solver import Options, init_state, step
+from paper_2105_05565_amd import inputs, rs
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return np.abs(np.asarray(a, np.float64) - b).max() / max(np.abs(b).max(), 1e-30)
+
+
+def test_init_bit_exact():
+    for seed in (1, 7, 123456789):
+        got = rs.rs_mlp_init(seed)
+        exp = mlp.init_params(seed).astype(np.float32)
+        assert np.array_equal(got, exp), seed
+
+
+def _rand_params(seed):
+    th = mlp.init_params(seed)
+    rng = np.random.default_rng(seed)
+    return (th + 0.05 * rng.standard_normal(th.shape)).astype(np.float32)
+
+
+@pytest.mark.parametrize("rows", [1, 31, 32, 1000, 4097])
+def test_forward_matches_oracle(rows):
+    rng = np.random.default_rng(rows)
+    P = _rand_params(2)
+    F = rng.standard_normal((rows, 6)).astype(np.float32)
+    got = rs.rs_mlp_forward(P, F)
+    exp, _ = mlp.forward(P.astype(np.float64), F.astype(np.float64))
+    assert _rel(got, exp) <= 1e-5
+
+
+@pytest.mark.parametrize("nrec,tau", [(1, 7), (3, 64), (16, 130)])
+def test_gradient_matches_oracle(nrec, tau):
+    rng = np.random.default_rng(nrec * 1000 + tau)
+    P = _rand_params(3)
+    Fs = rng.standard_normal((nrec, tau, 6)).astype(np.float32)
+    C = (rng.standard_normal((nrec, tau)) * (rng.random((nrec, tau)) < 0.6)).astype(np.float32)
+    C[0, :] = np.abs(C[0, :])
+    if nrec > 2:
+        C[2, :] = -np.abs(C[2, :])  # a record without positive credit: no loss
+    Lg, g = rs.rs_mlp_gradient(P, Fs, C)
+    Le, ge = mlp.batch_loss_grad(P.astype(np.float64), Fs.astype(np.float64), C.astype(np.float64))
+    assert abs(Lg - Le) <= 1e-5 * max(1.0, abs(Le))
+    assert _rel(g, ge) <= 1e-4
+
+
+def test_adam_matches_oracle():
+    rng = np.random.default_rng(4)
+    P = _rand_params(4)
+    g = rng.standard_normal(P.shape).astype(np.float32)
+    m1 = (0.1 * rng.standard_normal(P.shape)).astype(np.float32)
+    m2 = (0.01 * rng.random(P.shape)).astype(np.float32)
+    for t in (1, 5, 1000):
+        Pg, ag, vg = rs.rs_adam_update(P, m1, m2, g, t, lr=1e-3)
+        Pe, ae, ve = mlp.adam_step(P.astype(np.float64), g.astype(np.float64), m1.astype(np.float64),
+                                   m2.astype(np.float64), t, lr=1e-3)
+        assert _rel(ag, ae) <= 1e-6 and _rel(vg, ve) <= 1e-6
+        assert np.abs(Pg - Pe).max() <= 1e-5 * 1e-3 + 1e-7 * np.abs(Pe).max()
+
+
+def test_proposal_matches_oracle_and_flags_non_finite():
+    rng = np.random.default_rng(5)
+    s = (4 * rng.standard_normal(5000)).astype(np.float32)
+    q, ok = rs.rs_proposal(s)
+    assert ok and _rel(q, mlp.proposal(s.astype(np.float64))) <= 1e-5
+    s[17] = np.nan
+    q, ok = rs.rs_proposal(s)
+    assert not ok
+
+
+def test_features_match_oracle():
+    rng = np.random.default_rng(6)
+    m, k = 3000, 41
+    a = np.exp(2 * rng.standard_normal(m)) * 50
+    r = rng.standard_normal(m) * np.exp(rng.standard_normal(m))
+    rp = r + 0.1 * rng.standard_normal(m)
+    r[5] = 0.0
+    rp[9] = r[9]
+    last = rng.integers(-1, k, size=m).astype(np.int32)
+    got = rs.rs_features(a, r, rp, last, k)
+    exp = mlp.features(a, r, rp, last, k)
+    assert np.abs(got - exp).max() <= 1e-5 * np.maximum(1.0, np.abs(exp)).max()
+    assert got[5, 1] == -30.0 and got[9, 3] == -30.0
+
+
+@pytest.mark.parametrize("m,tau", [(1000, 37), (4096, 512), (300, 300), (5000, 1)])
+def test_weighted_draw_bit_exact(m, tau):
+    rng = np.random.default_rng(m + tau)
+    for trial in range(3):
+        q = np.exp(3 * rng.standard_normal(m)).astype(np.float32)
+        q /= q.sum()
+        if trial == 2:
+            q[:] = np.float32(1.0 / m)  # all keys u_j: a uniform subset
+        k = 11 + trial
+        got = rs.rs_draw_weighted(q, tau, seed=9, problem_id=2, k=k)
+        exp = osk.draw_weighted(9, 2, k, q, tau)
+        assert np.array_equal(got.astype(np.int64), exp.rows), (trial, got[:8], exp.rows[:8])
+
+
+def test_trace_records_match_oracle_run():
+    p = inputs.make_dense(900, 200, 0.05, seed=8, col_log_sigma=1.5)
+    tau, seed, N = 23, 5, 12
+    S = rs.Solver(p.X, p.y, p.lam, tau=tau, sketch="subsample", tol=0.0, seed=seed, trace_every=3,
+                  lookahead=5)
+    S.step(N)
+    F, C = S.trace()
+    S.close()
+    assert F.shape[0] == N // 3
+    system = ridge_system(p.X, p.y, p.lam, "primal")
+    a = np.einsum("ij,ij->i", system.Z, system.Z) + p.lam
+    st = init_state(system)
+    opts = Options(sketch="subsample", tau=tau, momentum="heuristic", tol=0.0, max_iter=N, seed=seed)
+    last = -np.ones(system.m, dtype=np.int64)
+    rec = 0
+    for k in range(N):
+        r_k, rp_k = st.r.copy(), st.r_prev.copy()
+        delta, sk, _ = step(system, st, opts)
+        if k % 3 == 0:
+            Fe = mlp.features(a, r_k, rp_k, last, k)[sk.rows]
+            ce = delta * r_k[sk.rows]
+            assert np.abs(F[rec] - Fe).max() <= 2e-5 * np.maximum(1.0, np.abs(Fe)).max(), k
+            assert _rel(C[rec], ce) <= 1e-5, k
+            rec += 1
+        last[sk.rows] = k
+
+
+def _direct(p):
+    system = ridge_system(p.X, p.y, p.lam, "primal")
+    A = system.dense_A()
+    return system, np.linalg.solve(A, system.b), np.linalg.cond(A)
+
+
+@pytest.mark.parametrize("sampler", ["diag", "learned"])
+def test_samplers_converge_and_use_the_weighted_draw(sampler):
+    # mild column scales: A_jj / Tr A sampling starves small columns when the scales spread
+    # widely (its rate is lambda_min(A) / Tr A for single coordinates, Sec. 7)
+    p = inputs.make_dense(1500, 300, 0.05, seed=9, col_log_sigma=0.5)
+    tau = 40
+    S = rs.Solver(p.X, p.y, p.lam, tau=tau, sketch="subsample", tol=1e-9, seed=3, sampler=sampler,
+                  lookahead=8, max_iter=200000)
+    if sampler == "learned":
+        with pytest.raises(rs.RsError):
+            S.step(1)  # parameters are required
+        S.set_sampler_params(_rand_params(1))
+    S.step(9)  # 9 iterations: the last sketch (k = 8) starts the second batch
+    q, ok = S.proposal()
+    assert ok and abs(q.astype(np.float64).sum() - 1.0) < 1e-4 and q.min() > 0
+    rows, _, _ = S.last_sketch()
+    assert np.array_equal(rows, np.sort(rs.rs_draw_weighted(q, tau, 3, 0, 8)).astype(np.int64))
+    if sampler == "diag":
+        system = ridge_system(p.X, p.y, p.lam, "primal")
+        a = np.einsum("ij,ij->i", system.Z, system.Z) + p.lam
+        assert _rel(q, a / a.sum()) <= 1e-6
+    w, st, rep = S.solve()
+    assert st == rs.RS_OK
+    system, x_direct, kappa = _direct(p)
+    assert np.linalg.norm(w - x_direct) / np.linalg.norm(x_direct) <= 2 * kappa * 1e-9
+    S.close()
+
+
+def test_trainer_fits_traces_and_loss_drops():
+    p = inputs.make_dense(2000, 256, 0.05, seed=10, col_log_sigma=2.0, corr_frac=0.05)
+    tau = 32
+    T = rs.Trainer(tau, init_seed=4)
+    S = rs.Solver(p.X, p.y, p.lam, tau=tau, sketch="subsample", tol=1e-8, seed=1, trace_every=2,
+                  trace_capacity=4096)
+    for seed in range(1, 6):
+        S.reset(seed)
+        S.solve()
+    n = rs.rs_trace_count(S.h)
+    assert n > 50
+    T.add_traces(S)
+    assert T.records == n
+    losses = T.fit(8, batch=16, lr=2e-3, shuffle_seed=3)
+    assert np.all(np.isfinite(losses)) and losses[-1] < losses[0]
+    params = T.params()
+    assert np.all(np.isfinite(params))
+    S.close()
+    T.close()
