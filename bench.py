@@ -40,6 +40,9 @@ WORKLOADS = {
     "dense_mixed_fp64": dict(kind="dense", gen="dense_mixed", sketch="subsample", tau=1024, sub_k=0,
                              precision="fp64",
                              name="dense_50000x8192_lognormal1_subsample_tau1024_primal_fp64"),
+    "dense_learned": dict(kind="dense", gen="dense_learned", sketch="subsample", tau=512, sub_k=0,
+                          precision="mixed",
+                          name="dense_200000x4096_lognormal2_corr0.05_subsample_tau512_primal_bf16_learned"),
     "batched": dict(kind="batch", precision="fp64",
                     name="batched_64problems_n2000-40000_d500-8000_half_csr0.005_16lambda_4rhs"),
 }
@@ -104,6 +107,49 @@ def cpu_baseline(p, wl, gpu_iters_median, sample_s):
                        f"({el:.1f} s, {per_iter:.3f} s/iteration, 1 thread), extrapolated to the "
                        f"GPU's median iteration count {gpu_iters_median:.0f}; sketches are bit-identical"),
             "s_per_iter": per_iter}
+
+
+def kernel_table(prof, wl, workload, n, d, nnz, m, K, nsel, total):
+    """Per-class timings (HIP events) with algorithmic bytes, and the roofline entry of the
+    class that dominates the timed solves."""
+    kernels = {}
+    for cls, v in prof.items():
+        if v["launches"] == 0:
+            continue
+        b = algorithmic_bytes(cls, wl, n, d, nnz, m, K, wl["tau"], nsel) * v["slots"] / v["launches"]
+        avg_ms = v["ms"] / v["launches"]
+        kernels[cls] = {"total_ms": round(v["ms"], 3), "launches": v["launches"],
+                        "slots_per_launch": round(v["slots"] / v["launches"], 2),
+                        "avg_ms": round(avg_ms, 5), "alg_bytes_per_launch": int(b),
+                        "gbs": round(b / (avg_ms * 1e-3) / 1e9, 1) if avg_ms > 0 else None,
+                        "share_of_timed": round(v["ms"] / (total * 1e3), 4)}
+    dom = max((c for c in kernels if c != "iters"), key=lambda c: kernels[c]["total_ms"])
+    kd = kernels[dom]
+    achieved = kd["gbs"]
+    roofline = {"kernel": {"as": "k_as_sparse_bucket" if wl["kind"] == "csr" else "k_as_dense_f64",
+                           "update": "k_update", "chol": "k_chol_inverse", "delta": "k_delta",
+                           "iters": "k_delta+k_update sequence",
+                           "sketch": "k_sketch_count" if wl["sketch"] == "count" else "k_sketch_select"}[dom],
+                "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None, "traffic": None,
+                "alg_bytes_per_launch": kd["alg_bytes_per_launch"], "avg_launch_ms": kd["avg_ms"]}
+    if wl["kind"] == "dense" and dom == "as":
+        flops = 2.0 * m * wl["tau"] * K * kd["slots_per_launch"]
+        tfs = flops / (kd["avg_ms"] * 1e-3) / 1e12
+        peak = BF16_PEAK_TFS if wl["precision"] == "mixed" else FP64_PEAK_TFS
+        roofline.update({"kernel": "k_as_dense_bf16" if wl["precision"] == "mixed" else "k_as_dense_f64",
+                         "bound": "mfma", "achieved": round(tfs, 1), "peak": peak, "unit": "TFLOP/s",
+                         "frac": round(tfs / peak, 4), "alg_flops_per_launch": flops,
+                         "hbm_gbs_algorithmic": kd["gbs"]})
+    traffic_file = os.path.join(ROOT, "profiles", f"traffic_{roofline['kernel']}_{workload}.json")
+    if os.path.exists(traffic_file):
+        tf = json.load(open(traffic_file))
+        src = {"k_as_sparse_bucket": ["k_sparse.hip"], "k_update": ["k_update.hip"],
+               "k_as_dense_f64": ["k_dense.hip"]}.get(roofline["kernel"], [])
+        if src and tf.get("source_sha") == kernel_source_sha(src):
+            roofline["traffic"] = tf["hbm_bytes_per_launch_scaled"] * kd["slots_per_launch"] / tf["slots_per_launch"]
+
+    return kernels, roofline
 
 
 def batch_weights(pr):
@@ -241,6 +287,129 @@ def main_batched(args):
     print(json.dumps(out))
 
 
+def main_learned(args):
+    """Learned proposal: train on traces of uniform solves (seeds 1..N), then time held-out
+    solves (seeds 201..) with the learned proposal; uniform, A_jj / Tr A and plain FP64
+    solves of the same held-out seeds are reported beside it."""
+    import numpy as np
+    import torch
+
+    from paper_2105_05565_amd import rs
+
+    wl = WORKLOADS["dense_learned"]
+    torch.cuda.set_device(0)
+    print(f"[bench] generating {wl['name']}", file=sys.stderr, flush=True)
+    p = make_problem(wl)
+    n, d = p.X.shape
+    X = torch.from_numpy(p.X).cuda()
+    y = torch.from_numpy(p.y).cuda()
+    stream = torch.cuda.current_stream().cuda_stream
+    tau = wl["tau"]
+    kw = dict(tau=tau, sketch="subsample", form="primal", momentum="heuristic", tol=1e-6, precision="mixed",
+              max_iter=args.max_iter, stream=stream)
+
+    t0 = time.perf_counter()
+    U = rs.Solver(X, y, p.lam, trace_every=2, trace_capacity=400000, lookahead=8, **kw)
+    tr_iters = []
+    for sd in range(1, args.train_solves + 1):
+        U.reset(sd)
+        _, _, rep = U.solve()
+        tr_iters.append(rep.iters)
+        if sd % 25 == 0:
+            print(f"[bench] trace solve {sd}/{args.train_solves}", file=sys.stderr, flush=True)
+    T = rs.Trainer(tau, init_seed=1)
+    T.add_traces(U)
+    records = T.records
+    U.close()
+    losses = T.fit(10, batch=16, lr=1e-3, shuffle_seed=7)
+    params = T.params()
+    T.close()
+    train_s = time.perf_counter() - t0
+    print(f"[bench] trained on {records} records from {args.train_solves} solves in {train_s:.1f} s; "
+          f"epoch losses {[round(v, 4) for v in losses]}", file=sys.stderr, flush=True)
+
+    def run(sampler, seeds, profile=0, **extra):
+        S = rs.Solver(X, y, p.lam, sampler=sampler, profile=profile, **{**kw, **extra})
+        if sampler == "learned":
+            S.set_sampler_params(params)
+        times, iters, rels, sts = [], [], [], []
+        for sd in seeds:
+            S.reset(sd)
+            torch.cuda.synchronize()
+            ti = time.perf_counter()
+            _, st, rep = S.solve()
+            times.append(time.perf_counter() - ti)
+            iters.append(rep.iters)
+            rels.append(rep.rel_res)
+            sts.append(st)
+        prof = S.profile() if profile else None
+        S.close()
+        return times, iters, rels, sts, prof
+
+    S = rs.Solver(X, y, p.lam, sampler="learned", profile=1, **kw)
+    S.set_sampler_params(params)
+    for w in range(args.warmup):
+        S.reset(10000 + w)
+        S.solve()
+    S.profile(clear=True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    times, iters = [], []
+    for i in range(args.steps):
+        ti = time.perf_counter()
+        S.reset(201 + i)
+        _, st, rep = S.solve()
+        times.append(time.perf_counter() - ti)
+        iters.append(rep.iters)
+        print(f"[bench] step {i}: {rep.iters} iterations, {times[-1]*1e3:.1f} ms, rel {rep.rel_res:.2e}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    prof = S.profile()
+    S.close()
+    T_step = total / args.steps
+    m, K = d, n
+    kernels, roofline = kernel_table(prof, wl, "dense_learned", n, d, n * d, m, K, tau, total)
+
+    seeds = list(range(201, 201 + args.steps))
+    ut, ui, ur, _, _ = run("uniform", seeds)
+    dt, di, dr, dst, _ = run("diag", seeds[:1], max_iter=min(args.max_iter, 3000))
+    pt, pi, pr_, _, _ = run("uniform", seeds[:1], precision="fp64")
+    out = {
+        "metric": "time-to-rel-residual 1e-6", "value": round(T_step, 6), "unit": "s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(T_step * 1e3, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 products, f32 accumulate, f64 solve; f32 MLP", "data": "synthetic",
+        "config": {"workload": wl["name"], "n": n, "d": d, "form": "primal", "sketch": "subsample (learned proposal)",
+                   "tau": tau, "lambda": p.lam, "momentum": "heuristic", "tol": 1e-6, "precision": "mixed",
+                   "lookahead": 8, "train_solves": args.train_solves, "held_out_seeds": seeds},
+        "iters_median": statistics.median(iters),
+        "time_s_all": [round(t, 4) for t in times],
+        "training": {"records": records, "seconds": round(train_s, 1),
+                     "trace_solve_iters_median": statistics.median(tr_iters),
+                     "epoch_loss": [round(v, 4) for v in losses]},
+        "compare_same_seeds": {
+            "uniform_mixed": {"time_s_median": round(statistics.median(ut), 4), "iters_median": statistics.median(ui)},
+            "diag_mixed": {"time_s": round(dt[0], 4), "iters": di[0], "rel_res": dr[0],
+                           "converged": dst[0] == 0, "cap": min(args.max_iter, 3000)},
+            "uniform_fp64_plain": {"time_s": round(pt[0], 4), "iters": pi[0], "rel_res": pr_[0]},
+        },
+        "speedup_vs_uniform_mixed": round(statistics.median(ut) / T_step, 3),
+        "speedup_vs_plain_fp64": round(pt[0] / T_step, 2),
+        "roofline": roofline,
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        cb = cpu_baseline(p, wl, statistics.median(iters), args.cpu_sample_s)
+        cb.pop("s_per_iter")
+        cb["sample"] = cb["sample"].replace("; sketches are bit-identical", "") + (
+            "; the oracle's per-iteration cost with uniform sketches (the proposal's MLP adds ~1e-4 of "
+            "an iteration's flops)")
+        out["cpu_baseline"] = cb
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -250,6 +419,8 @@ def main():
     ap.add_argument("--lookahead", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-s", type=float, default=15.0)
+    ap.add_argument("--train-solves", type=int, default=200,
+                    help="dense_learned only: seeded uniform solves whose traces train the proposal")
     ap.add_argument("--scale", type=float, default=1.0,
                     help="batched workload only: shrink n and d (shape-alike smaller batch)")
     ap.add_argument("--max-iter", type=int, default=200000,
@@ -262,6 +433,8 @@ def main():
 
     if args.workload == "batched":
         return main_batched(args)
+    if args.workload == "dense_learned":
+        return main_learned(args)
 
     import numpy as np
     import torch
@@ -328,42 +501,7 @@ def main():
 
     T = total / args.steps
     tot_iters = sum(iters)
-    kernels = {}
-    for cls, v in prof.items():
-        if v["launches"] == 0:
-            continue
-        b = algorithmic_bytes(cls, wl, n, d, nnz, m, K, wl["tau"], nsel) * v["slots"] / v["launches"]
-        avg_ms = v["ms"] / v["launches"]
-        kernels[cls] = {"total_ms": round(v["ms"], 3), "launches": v["launches"],
-                        "slots_per_launch": round(v["slots"] / v["launches"], 2),
-                        "avg_ms": round(avg_ms, 5), "alg_bytes_per_launch": int(b),
-                        "gbs": round(b / (avg_ms * 1e-3) / 1e9, 1) if avg_ms > 0 else None,
-                        "share_of_timed": round(v["ms"] / (total * 1e3), 4)}
-    dom = max((c for c in kernels if c != "iters"), key=lambda c: kernels[c]["total_ms"])
-    kd = kernels[dom]
-    achieved = kd["gbs"]
-    roofline = {"kernel": {"as": "k_as_sparse_bucket" if wl["kind"] == "csr" else "k_as_dense_f64",
-                           "update": "k_update", "chol": "k_chol_inverse", "delta": "k_delta",
-                           "iters": "k_delta+k_update sequence",
-                           "sketch": "k_sketch_count" if wl["sketch"] == "count" else "k_sketch_select"}[dom],
-                "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None, "traffic": None,
-                "alg_bytes_per_launch": kd["alg_bytes_per_launch"], "avg_launch_ms": kd["avg_ms"]}
-    if wl["kind"] == "dense" and dom == "as":
-        flops = 2.0 * m * wl["tau"] * K * kd["slots_per_launch"]
-        tfs = flops / (kd["avg_ms"] * 1e-3) / 1e12
-        peak = BF16_PEAK_TFS if wl["precision"] == "mixed" else FP64_PEAK_TFS
-        roofline.update({"kernel": "k_as_dense_bf16" if wl["precision"] == "mixed" else "k_as_dense_f64",
-                         "bound": "mfma", "achieved": round(tfs, 1), "peak": peak, "unit": "TFLOP/s",
-                         "frac": round(tfs / peak, 4), "alg_flops_per_launch": flops,
-                         "hbm_gbs_algorithmic": kd["gbs"]})
-    traffic_file = os.path.join(ROOT, "profiles", f"traffic_{roofline['kernel']}_{args.workload}.json")
-    if os.path.exists(traffic_file):
-        tf = json.load(open(traffic_file))
-        src = {"k_as_sparse_bucket": ["k_sparse.hip"], "k_update": ["k_update.hip"],
-               "k_as_dense_f64": ["k_dense.hip"]}.get(roofline["kernel"], [])
-        if src and tf.get("source_sha") == kernel_source_sha(src):
-            roofline["traffic"] = tf["hbm_bytes_per_launch_scaled"] * kd["slots_per_launch"] / tf["slots_per_launch"]
+    kernels, roofline = kernel_table(prof, wl, args.workload, n, d, nnz, m, K, nsel, total)
 
     out = {
         "metric": "time-to-rel-residual 1e-6", "value": round(T, 6), "unit": "s", "n_gpus": 1,

@@ -656,6 +656,8 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
     // (the sketches formed past the stopping iteration are wasted work).
     int B = 256;
     if (!h->sparse && 2.0 * (double)h->m * (double)h->K * (double)h->tau > 1e11) B = 32;
+    // the learned proposal is recomputed once per batch: short batches keep it fresh
+    if (o->sampler == RS_SAMPLER_LEARNED) B = 8;
     if (o->lookahead > 0) B = o->lookahead;
     const size_t budget = (size_t)48 << 30;
     while (B > 1 && (size_t)B * per_slot > budget) B >>= 1;

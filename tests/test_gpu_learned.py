@@ -195,3 +195,37 @@ def test_trainer_fits_traces_and_loss_drops():
     assert np.all(np.isfinite(params))
     S.close()
     T.close()
+
+
+def test_learned_proposal_gain_over_uniform():
+    """Shape-alike reduction of the learned-proposal workload (n = 20000, d = 409, log-normal(0,2)
+    column norms, 5% correlated columns, tau = 51, BF16 products): train on traces of 20 uniform
+    solves, then compare held-out solves. The true (FP64-refreshed) residual decides convergence."""
+    p = inputs.dense_learned(scale=0.1)
+    tau = 51
+    kw = dict(tau=tau, sketch="subsample", form="primal", tol=1e-6, precision="mixed", max_iter=20000)
+    U = rs.Solver(p.X, p.y, p.lam, trace_every=2, trace_capacity=100000, lookahead=8, **kw)
+    T = rs.Trainer(tau, init_seed=1)
+    for s in range(1, 21):
+        U.reset(s)
+        assert U.solve()[1] == rs.RS_OK
+    T.add_traces(U)
+    U.close()
+    T.fit(10, batch=16, lr=1e-3, shuffle_seed=7)
+    params = T.params()
+    T.close()
+    iters = {}
+    for sampler in ("uniform", "learned"):
+        S = rs.Solver(p.X, p.y, p.lam, sampler=sampler, **kw)
+        if sampler == "learned":
+            S.set_sampler_params(params)
+        its = []
+        for s in range(201, 206):
+            S.reset(s)
+            w, st, rep = S.solve()
+            assert st == rs.RS_OK and rep.rel_res <= 1e-6
+            its.append(rep.iters)
+        S.close()
+        iters[sampler] = float(np.median(its))
+    print("median iterations to true relative residual 1e-6:", iters)
+    assert iters["learned"] < 0.8 * iters["uniform"], iters
