@@ -425,7 +425,21 @@ def main():
                     help="batched workload only: shrink n and d (shape-alike smaller batch)")
     ap.add_argument("--max-iter", type=int, default=200000,
                     help="iteration cap per solve (a capped run reports per-iteration throughput)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device-to-device copy of 1 GiB five times (the known-size "
+                         "reference for HBM traffic counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "dispatches": 5}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver is single-GPU.",
               file=sys.stderr)
