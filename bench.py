@@ -56,9 +56,14 @@ def kernel_source_sha(files):
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(cls, wl, n, d, nnz, m, K, tau, nsel):
+def algorithmic_bytes(cls, wl, n, d, nnz, m, K, tau, nsel, a_nnz=0, slots=1):
     """Minimum HBM bytes one sketch (iteration) needs in each kernel class (FP64 layouts)."""
     if cls == "as":
+        if wl["kind"] == "csr" and a_nnz:
+            # rows of A0 = Z Z^T (int32 column + FP64 value) read once per launch and shared by
+            # its sketches; per sketch the bucket map, AS written, the member rows of AS read
+            # back for G, and G written
+            return (a_nnz * 12 + (m + 1) * 8) / slots + m * 4 + 2 * m * tau * 8 + tau * tau * 8
         if wl["kind"] == "csr":
             # CSR of Z and of Z^T (FP32 value + int32 column each) read once, row pointers,
             # bucket map, AS written once (FP64), G = S^T A S written once (FP64)
@@ -109,14 +114,15 @@ def cpu_baseline(p, wl, gpu_iters_median, sample_s):
             "s_per_iter": per_iter}
 
 
-def kernel_table(prof, wl, workload, n, d, nnz, m, K, nsel, total):
+def kernel_table(prof, wl, workload, n, d, nnz, m, K, nsel, total, a_nnz=0):
     """Per-class timings (HIP events) with algorithmic bytes, and the roofline entry of the
     class that dominates the timed solves."""
     kernels = {}
     for cls, v in prof.items():
         if v["launches"] == 0:
             continue
-        b = algorithmic_bytes(cls, wl, n, d, nnz, m, K, wl["tau"], nsel) * v["slots"] / v["launches"]
+        spl = v["slots"] / v["launches"]
+        b = algorithmic_bytes(cls, wl, n, d, nnz, m, K, wl["tau"], nsel, a_nnz, spl) * spl
         avg_ms = v["ms"] / v["launches"]
         kernels[cls] = {"total_ms": round(v["ms"], 3), "launches": v["launches"],
                         "slots_per_launch": round(v["slots"] / v["launches"], 2),
@@ -126,7 +132,9 @@ def kernel_table(prof, wl, workload, n, d, nnz, m, K, nsel, total):
     dom = max((c for c in kernels if c != "iters"), key=lambda c: kernels[c]["total_ms"])
     kd = kernels[dom]
     achieved = kd["gbs"]
-    roofline = {"kernel": {"as": "k_as_sparse_bucket" if wl["kind"] == "csr" else "k_as_dense_f64",
+    as_name = ("k_as_arows+k_g_from_as" if a_nnz else "k_as_sparse_bucket") if wl["kind"] == "csr" \
+        else "k_as_dense_f64"
+    roofline = {"kernel": {"as": as_name,
                            "update": "k_update", "chol": "k_chol_inverse", "delta": "k_delta",
                            "iters": "k_delta+k_update sequence",
                            "sketch": "k_sketch_count" if wl["sketch"] == "count" else "k_sketch_select"}[dom],
@@ -141,11 +149,13 @@ def kernel_table(prof, wl, workload, n, d, nnz, m, K, nsel, total):
                          "bound": "mfma", "achieved": round(tfs, 1), "peak": peak, "unit": "TFLOP/s",
                          "frac": round(tfs / peak, 4), "alg_flops_per_launch": flops,
                          "hbm_gbs_algorithmic": kd["gbs"]})
-    traffic_file = os.path.join(ROOT, "profiles", f"traffic_{roofline['kernel']}_{workload}.json")
+    traffic_file = os.path.join(ROOT, "profiles",
+                                f"traffic_{roofline['kernel'].replace('+', '_')}_{workload}.json")
     if os.path.exists(traffic_file):
         tf = json.load(open(traffic_file))
         src = {"k_as_sparse_bucket": ["k_sparse.hip"], "k_update": ["k_update.hip"],
-               "k_as_dense_f64": ["k_dense.hip"]}.get(roofline["kernel"], [])
+               "k_as_dense_f64": ["k_dense.hip"], "k_as_arows+k_g_from_as": ["k_sparse_a.hip"]
+               }.get(roofline["kernel"], [])
         if src and tf.get("source_sha") == kernel_source_sha(src):
             roofline["traffic"] = tf["hbm_bytes_per_launch_scaled"] * kd["slots_per_launch"] / tf["slots_per_launch"]
 
@@ -419,6 +429,8 @@ def main():
     ap.add_argument("--lookahead", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-s", type=float, default=15.0)
+    ap.add_argument("--sparse-route", default="auto", choices=["auto", "scatter", "arows"],
+                    help="CSR workloads: how AS is formed (auto picks the rows of Z Z^T when they fit)")
     ap.add_argument("--train-solves", type=int, default=200,
                     help="dense_learned only: seeded uniform solves whose traces train the proposal")
     ap.add_argument("--scale", type=float, default=1.0,
@@ -475,9 +487,11 @@ def main():
     t0 = time.perf_counter()
     S = rs.Solver(X, y, p.lam, tau=wl["tau"], sketch=wl["sketch"], form="primal", momentum="heuristic",
                   subcount_k=wl["sub_k"], tol=1e-6, max_iter=args.max_iter, seed=1,
-                  precision=wl["precision"], lookahead=args.lookahead, profile=1, stream=stream)
+                  precision=wl["precision"], lookahead=args.lookahead, profile=1, stream=stream,
+                  sparse_route=args.sparse_route)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
+    route, a_nnz = rs.rs_get_route(S.h)
     m, K = d, n
     nsel = {"count": m, "subcount": wl["tau"] * max(wl["sub_k"], 1), "subsample": wl["tau"]}[wl["sketch"]]
 
@@ -508,14 +522,15 @@ def main():
     # one more solve, untimed, with every launch bracketed by events (per-launch breakdown)
     S2 = rs.Solver(X, y, p.lam, tau=wl["tau"], sketch=wl["sketch"], form="primal", momentum="heuristic",
                    subcount_k=wl["sub_k"], tol=1e-6, max_iter=args.max_iter, seed=1,
-                   precision=wl["precision"], lookahead=args.lookahead, profile=2, stream=stream)
+                   precision=wl["precision"], lookahead=args.lookahead, profile=2, stream=stream,
+                   sparse_route=args.sparse_route)
     S2.solve()
     prof2 = S2.profile()
     S2.close()
 
     T = total / args.steps
     tot_iters = sum(iters)
-    kernels, roofline = kernel_table(prof, wl, args.workload, n, d, nnz, m, K, nsel, total)
+    kernels, roofline = kernel_table(prof, wl, args.workload, n, d, nnz, m, K, nsel, total, a_nnz)
 
     out = {
         "metric": "time-to-rel-residual 1e-6", "value": round(T, 6), "unit": "s", "n_gpus": 1,
@@ -526,7 +541,9 @@ def main():
         "config": {"workload": wl["name"], "n": n, "d": d, "nnz": nnz, "form": "primal",
                    "sketch": wl["sketch"], "tau": wl["tau"], "subcount_k": wl["sub_k"],
                    "lambda": p.lam, "momentum": "heuristic", "tol": 1e-6,
-                   "precision": wl["precision"], "max_iter": args.max_iter},
+                   "precision": wl["precision"], "max_iter": args.max_iter,
+                   "sparse_route": {0: None, 1: "scatter", 2: "arows"}[route],
+                   "a_nnz": a_nnz or None},
         "iters_per_s": round(tot_iters / total, 1),
         "iters_median": statistics.median(iters),
         "time_s_quartiles": [round(q, 6) for q in statistics.quantiles(times, n=4)] if len(times) > 1 else times,

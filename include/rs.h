@@ -106,7 +106,17 @@ typedef struct rs_options {
   int32_t sampler;          /* RS_SAMPLER_* coordinate proposal of the subsample sketch */
   int32_t trace_every;      /* > 0: record (features, credits) every that many iterations */
   int32_t trace_capacity;   /* records kept (0 = 1024); later ones are dropped */
+  int32_t sparse_route;     /* CSR count / SubCount products: RS_ROUTE_* */
 } rs_options;
+
+/* How AS is formed for the count and SubCount sketches on CSR data (same result up to
+ * rounding). SCATTER: per sketch, T = Z^T S (bucket, signed value) aligned with CSR(Z^T),
+ * then each row j of AS is the signed scatter-add of Z_ji T[i, :] into tau buckets.
+ * AROWS: A0 = Z Z^T is formed once (sparse, FP64); each row j of AS is the signed
+ * scatter-add of row j of A0 into tau buckets, with several sketches sharing each pass
+ * over A0, then G = S^T AS from the member rows. AUTO picks AROWS when the product
+ * Z Z^T has fewer than 2^31 pairs and fits in a quarter of the device memory. */
+enum { RS_ROUTE_AUTO = 0, RS_ROUTE_SCATTER = 1, RS_ROUTE_AROWS = 2 };
 
 /* Coordinate proposals for the subsample sketch (dense X). UNIFORM: every tau-subset
  * equally likely (Def. 4.2). DIAG: q_j = A_jj / Tr A (the importance sampling of Sec. 7).
@@ -204,6 +214,9 @@ rs_status rs_destroy(rs_handle* h);
 
 /* tau of the handle's sketch. */
 int32_t rs_sketch_size(const rs_handle* h);
+/* Route the handle forms sparse products with (RS_ROUTE_SCATTER or RS_ROUTE_AROWS; 0 for
+ * dense data) and, for RS_ROUTE_AROWS, the number of stored entries of Z Z^T (host). */
+rs_status rs_get_route(const rs_handle* h, int32_t* route, int64_t* a_nnz);
 
 /* ------------------------------------------------------------------------
  * Learned proposal: parameters, traces, training, and single-kernel entry points.

@@ -51,7 +51,12 @@ struct rs_handle {
   void* zt_val = nullptr;
   int32_t vals_f32 = 0;  // CSR values kept in the input precision
   int64_t nnz = 0;
-  void* tbuf = nullptr;  // per-sketch T = Z^T S entries (sparse path)
+  void* tbuf = nullptr;  // per-sketch T = Z^T S entries (sparse path, scatter route)
+  bool arows = false;    // sparse path through the rows of A0 = Z Z^T
+  int64_t* a_ptr = nullptr;
+  int32_t* a_col = nullptr;
+  double* a_val = nullptr;
+  int64_t a_nnz = 0;
 
   double* b = nullptr;
   double* xbuf[2] = {nullptr, nullptr};
@@ -258,13 +263,17 @@ void run_batch(rs_handle* h, int64_t k0, int nb) {
     a.q_ok = h->q_ok;
   }
   check_hip(launch_sketch(a, s), "sketch");
-  if (h->sparse)
+  if (h->sparse && !h->arows)
     check_hip(launch_build_t(h->zt_col, h->zt_val, h->vals_f32, h->nnz, h->hmap, h->m, nb, h->tbuf,
                              done, s),
               "T map");
   prof_end(h, pe);
   pe = prof_begin(h, RS_PROF_AS, nb);
-  if (h->sparse) {
+  if (h->arows) {
+    check_hip(launch_as_arows(h->a_ptr, h->a_col, h->a_val, h->m, h->tau, h->ldas, nb, h->lam, h->hmap,
+                              h->members, h->offs, h->nsel, (double*)h->AS, h->G, h->ldg, done, s),
+              "AS (rows of Z Z^T)");
+  } else if (h->sparse) {
     check_hip(launch_as_sparse(h->zr_ptr, h->zr_col, h->zr_val, h->zt_ptr, h->zt_col, h->zt_val,
                                h->vals_f32, h->nnz, h->m, h->tau, h->ldas, nb, h->kind, h->lam,
                                h->hmap, h->members, h->offs, h->nsel, h->tbuf, (double*)h->AS, h->G,
@@ -448,6 +457,7 @@ rs_status rs_options_default(rs_options* o) {
   o->sampler = RS_SAMPLER_UNIFORM;
   o->trace_every = 0;
   o->trace_capacity = 0;
+  o->sparse_route = RS_ROUTE_AUTO;
   return RS_OK;
 }
 
@@ -499,6 +509,8 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
       throw Fail{RS_EINVAL, "refresh_every must be >= 1"};
     h->mixed = o->precision == RS_PREC_MIXED_BF16;
     if (o->sampler < RS_SAMPLER_UNIFORM || o->sampler > RS_SAMPLER_DIAG) throw Fail{RS_EINVAL, "unknown sampler"};
+    if (o->sparse_route < RS_ROUTE_AUTO || o->sparse_route > RS_ROUTE_AROWS)
+      throw Fail{RS_EINVAL, "unknown sparse route"};
     if (o->trace_every < 0 || o->trace_capacity < 0) throw Fail{RS_EINVAL, "trace settings must be >= 0"};
     if ((o->sampler != RS_SAMPLER_UNIFORM || o->trace_every > 0) &&
         (X->layout == RS_CSR || o->sketch != RS_SKETCH_SUBSAMPLE))
@@ -644,10 +656,32 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
       }
     }
 
+    if (h->sparse && (o->sparse_route == RS_ROUTE_AROWS || o->sparse_route == RS_ROUTE_AUTO)) {
+      std::vector<int64_t> tp(h->K + 1);
+      check_hip(hipMemcpy(tp.data(), h->zt_ptr, sizeof(int64_t) * (h->K + 1), hipMemcpyDeviceToHost),
+                "row pointers");
+      const int64_t pairs = zzt_pairs(tp.data(), h->K);
+      size_t free_b = 0, total_b = 0;
+      check_hip(hipMemGetInfo(&free_b, &total_b), "memory info");
+      // sort and reduction buffers: 48 bytes per pair while A0 is formed
+      const bool fits = pairs > 0 && pairs < (int64_t)INT32_MAX && (double)pairs * 48.0 < 0.25 * (double)free_b;
+      if (o->sparse_route == RS_ROUTE_AROWS && !fits)
+        throw Fail{RS_EUNSUPPORTED, "the product Z Z^T is too large for the rows-of-A route"};
+      if (fits) {
+        check_hip(build_zzt(h->zt_ptr, h->zt_col, h->zt_val, h->vals_f32, h->K, h->m, pairs, &h->a_ptr,
+                            &h->a_col, &h->a_val, &h->a_nnz, s),
+                  "Z Z^T");
+        h->allocs.push_back(h->a_ptr);
+        h->allocs.push_back(h->a_col);
+        h->allocs.push_back(h->a_val);
+        h->arows = true;
+      }
+    }
+
     // batch buffers
     h->ldg = ((int64_t)h->tau + 63) / 64 * 64;
     h->ldas = ((int64_t)h->tau + 7) / 8 * 8;
-    const size_t per_slot = (h->sparse ? sparse_t_bytes(h->vals_f32, h->nnz) : 0) +
+    const size_t per_slot = (h->sparse && !h->arows ? sparse_t_bytes(h->vals_f32, h->nnz) : 0) +
                             (h->mixed ? sizeof(float) : sizeof(double)) * (size_t)h->m * h->ldas +
                             sizeof(double) * 2 * (size_t)h->ldg * h->ldg +
                             sizeof(int32_t) * ((size_t)h->m + h->nsel + h->tau + 1) +
@@ -671,7 +705,7 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
     // the padding columns of AS are read (times a zero delta) by the update: keep them zero
     check_hip(hipMemsetAsync(h->AS, 0, as_bytes, s), "memset");
     h->rho = dalloc<double>(h, h->ldg);
-    if (h->sparse) h->tbuf = dalloc<char>(h, (size_t)B * sparse_t_bytes(h->vals_f32, h->nnz));
+    if (h->sparse && !h->arows) h->tbuf = dalloc<char>(h, (size_t)B * sparse_t_bytes(h->vals_f32, h->nnz));
     h->G = dalloc<double>(h, (size_t)B * h->ldg * h->ldg);
     h->W = dalloc<double>(h, (size_t)B * h->ldg * h->ldg);
     h->Xd = reinterpret_cast<double*>(dalloc<char>(h, (size_t)B * chol_multi_x_bytes(h->ldg)));
@@ -809,6 +843,13 @@ rs_status rs_get_profile(rs_handle* h, rs_profile* out, int32_t clear) {
 int64_t rs_iteration(const rs_handle* h) { return h ? h->k : -1; }
 int64_t rs_system_size(const rs_handle* h) { return h ? h->m : -1; }
 int32_t rs_sketch_size(const rs_handle* h) { return h ? h->tau : -1; }
+
+rs_status rs_get_route(const rs_handle* h, int32_t* route, int64_t* a_nnz) {
+  if (!h) return RS_EINVAL;
+  if (route) *route = !h->sparse ? 0 : (h->arows ? RS_ROUTE_AROWS : RS_ROUTE_SCATTER);
+  if (a_nnz) *a_nnz = h->a_nnz;
+  return RS_OK;
+}
 
 rs_status rs_get_weights(rs_handle* h, double* w_out) {
   if (!h || !w_out) return RS_EINVAL;

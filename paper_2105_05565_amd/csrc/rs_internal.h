@@ -107,6 +107,18 @@ hipError_t launch_as_sparse(const int64_t* zr_ptr, const int32_t* zr_col, const 
                             const int32_t* members, const int32_t* offs, int64_t nsel, void* tbuf,
                             double* AS, double* G, int64_t ldg, const int32_t* done, hipStream_t s);
 
+// Count / SubCount products through the rows of A0 = Z Z^T (formed once): pairs of the
+// sparse product (host count from the row pointers of Z^T), A0 as CSR with FP64 values,
+// then per batch of sketches AS (row-major, several sketches per workgroup) and G.
+int64_t zzt_pairs(const int64_t* zt_ptr_host, int64_t K);
+hipError_t build_zzt(const int64_t* zt_ptr, const int32_t* zt_col, const void* zt_val, int32_t vals_f32,
+                     int64_t K, int64_t m, int64_t npairs, int64_t** a_ptr, int32_t** a_col, double** a_val,
+                     int64_t* a_nnz, hipStream_t s);
+hipError_t launch_as_arows(const int64_t* a_ptr, const int32_t* a_col, const double* a_val, int64_t m,
+                           int32_t tau, int64_t ldas, int32_t nslots, double lam, const int32_t* hmap,
+                           const int32_t* members, const int32_t* offs, int64_t nsel, double* AS, double* G,
+                           int64_t ldg, const int32_t* done, hipStream_t s);
+
 // Grouped count-sketch products (batched solves; CSR values held in FP64): per job,
 // T = Z^T S into tbuf (nnz * sparse_entry_bytes_f64() bytes), then AS (m x tau) and
 // G = S^T AS for the (job, bucket) pairs in items[2 * nitems].

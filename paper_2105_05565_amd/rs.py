@@ -45,12 +45,14 @@ class rs_options(ctypes.Structure):
                 ("profile", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("graph_iters", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("sampler", ctypes.c_int32), ("trace_every", ctypes.c_int32),
-                ("trace_capacity", ctypes.c_int32)]
+                ("trace_capacity", ctypes.c_int32), ("sparse_route", ctypes.c_int32)]
 
 
 RS_SAMPLER_UNIFORM, RS_SAMPLER_LEARNED, RS_SAMPLER_DIAG = 0, 1, 2
 SAMPLERS = {"uniform": RS_SAMPLER_UNIFORM, "learned": RS_SAMPLER_LEARNED, "diag": RS_SAMPLER_DIAG}
 RS_MLP_FEATURES, RS_MLP_HIDDEN, RS_MLP_PARAMS = 6, 128, 17537
+RS_ROUTE_AUTO, RS_ROUTE_SCATTER, RS_ROUTE_AROWS = 0, 1, 2
+ROUTES = {"auto": RS_ROUTE_AUTO, "scatter": RS_ROUTE_SCATTER, "arows": RS_ROUTE_AROWS}
 
 
 class rs_problem(ctypes.Structure):
@@ -122,6 +124,7 @@ SIGNATURES = {
     "rs_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "rs_last_error": (ctypes.c_char_p, [_P]),
     "rs_sketch_size": (ctypes.c_int32, [_P]),
+    "rs_get_route": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]),
     "rs_set_sampler_params": (ctypes.c_int32, [_P, _P]),
     "rs_trace_count": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int64)]),
     "rs_get_trace": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int64, ctypes.c_int64]),
@@ -288,6 +291,13 @@ def rs_destroy(h):
 
 def rs_sketch_size(h):
     return load().rs_sketch_size(h)
+
+
+def rs_get_route(h):
+    r = ctypes.c_int32(0)
+    n = ctypes.c_int64(0)
+    _check(load().rs_get_route(h, ctypes.byref(r), ctypes.byref(n)), "rs_get_route", h)
+    return r.value, n.value
 
 
 def rs_set_sampler_params(h, params):
@@ -552,7 +562,8 @@ class Solver:
     def __init__(self, X, y, lam, *, tau, sketch="subsample", form="auto", momentum="heuristic",
                  precision="fp64", subcount_k=0, tol=1e-6, max_iter=100000, seed=1, problem_id=0,
                  eta=0.995, beta_max=0.5, gamma=1.0, beta=0.5, lookahead=0, refresh_every=20,
-                 profile=False, stream=None, sampler="uniform", trace_every=0, trace_capacity=0):
+                 profile=False, stream=None, sampler="uniform", trace_every=0, trace_capacity=0,
+                 sparse_route="auto"):
         o = rs_options_default()
         o.form, o.sketch, o.tau = FORMS[form], SKETCHES[sketch], int(tau)
         o.subcount_k, o.momentum, o.precision = int(subcount_k), MOMENTA[momentum], PRECISIONS[precision]
@@ -561,6 +572,7 @@ class Solver:
         o.refresh_every, o.lookahead, o.profile = int(refresh_every), int(lookahead), int(profile)
         o.stream = stream
         o.sampler, o.trace_every, o.trace_capacity = SAMPLERS[sampler], int(trace_every), int(trace_capacity)
+        o.sparse_route = ROUTES[sparse_route]
         M, keep = make_matrix(X)
         if M.mem == RS_DEVICE:
             yv = y.double().contiguous()

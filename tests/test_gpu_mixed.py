@@ -27,16 +27,19 @@ def _oracle_products(p, form, kind, k, tau, sub_k=0, seed=5):
     return system, s, AS, G, active
 
 
-@pytest.mark.parametrize("kind,form", [("subsample", "primal"), ("subsample", "dual"),
-                                       ("count", "primal"), ("subcount", "dual")])
-def test_fp64_products_match_oracle(kind, form):
+@pytest.mark.parametrize("kind,form,route", [("subsample", "primal", "auto"), ("subsample", "dual", "auto"),
+                                             ("count", "primal", "scatter"), ("subcount", "dual", "scatter"),
+                                             ("count", "primal", "arows"), ("subcount", "dual", "arows"),
+                                             ("count", "dual", "arows")])
+def test_fp64_products_match_oracle(kind, form, route):
     if kind == "subsample":
         p = inputs.make_dense(300, 130, 0.05, seed=1) if form == "primal" else inputs.make_dense(110, 260, 0.05, seed=2)
         tau = 37
     else:
         p = inputs.make_csr(400, 150, 0.04, 0.05, seed=3) if form == "primal" else inputs.make_csr(150, 400, 0.04, 0.05, seed=4)
         tau = 23
-    S = rs.Solver(p.X, p.y, p.lam, tau=tau, sketch=kind, form=form, tol=0.0, seed=5, subcount_k=2)
+    S = rs.Solver(p.X, p.y, p.lam, tau=tau, sketch=kind, form=form, tol=0.0, seed=5, subcount_k=2,
+                  sparse_route=route)
     S.step(3)
     AS, Gi = S.products()
     _, s, AS_or, G_or, active = _oracle_products(p, form, kind, 2, tau, sub_k=2)

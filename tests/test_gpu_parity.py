@@ -85,13 +85,13 @@ def test_count_sketch_bit_exact_large_m():
 
 
 def _trajectory_check(X, y, lam, *, form, kind, tau, momentum, sub_k=0, iters=50, checkpoints=None,
-                      lookahead=0, seed=5):
+                      lookahead=0, seed=5, route="auto"):
     system = ridge_system(X, y, lam, form)
     opts = Options(sketch=kind, tau=tau, sum_size=sub_k if sub_k else 0, momentum=momentum, seed=seed,
                    tol=0.0)
     st = init_state(system)
     S = rs.Solver(X, y, lam, tau=tau, sketch=kind, form=form, momentum=momentum, tol=0.0, seed=seed,
-                  subcount_k=sub_k, lookahead=lookahead)
+                  subcount_k=sub_k, lookahead=lookahead, sparse_route=route)
     checkpoints = checkpoints or [1, 2, 3, 7, 20, iters]
     done = 0
     worst = 0.0
@@ -131,16 +131,34 @@ def test_dense_subsample_trajectory_f32_colmajor_input():
     _trajectory_check(Xf, p.y, p.lam, form="primal", kind="subsample", tau=20, momentum="heuristic")
 
 
+@pytest.mark.parametrize("route", ["scatter", "arows"])
 @pytest.mark.parametrize("kind,sub_k", [("count", 0), ("subcount", 2)])
 @pytest.mark.parametrize("form", ["primal", "dual"])
-def test_sparse_trajectory(kind, sub_k, form):
+def test_sparse_trajectory(kind, sub_k, form, route):
     if form == "primal":
         p = _csr(400, 150, 0.04, 0.05, seed=3)
         tau = 23
     else:
         p = _csr(150, 400, 0.04, 0.05, seed=4)
         tau = 29
-    _trajectory_check(p.X, p.y, p.lam, form=form, kind=kind, tau=tau, momentum="heuristic", sub_k=sub_k)
+    _trajectory_check(p.X, p.y, p.lam, form=form, kind=kind, tau=tau, momentum="heuristic", sub_k=sub_k,
+                      route=route)
+
+
+@pytest.mark.parametrize("route", ["scatter", "arows"])
+def test_sparse_ragged_rows_and_empty_columns(route):
+    """CSR rows of very different lengths (one dense row, empty rows and columns), tau larger than
+    one 64-column chunk, lookahead batches of 3."""
+    rng = np.random.default_rng(21)
+    n, d = 600, 230
+    X = sp.random(n, d, density=0.02, random_state=5, format="lil")
+    X[7, :] = rng.standard_normal(d)           # a dense row of X: a dense row of Z Z^T's pattern
+    X[:, 11] = 0.0                             # an empty column
+    X[40:45, :] = 0.0                          # empty rows
+    X = sp.csr_matrix(X)
+    y = rng.standard_normal(n)
+    _trajectory_check(X, y, 0.3, form="primal", kind="count", tau=70, momentum="heuristic", lookahead=3,
+                      route=route, checkpoints=[1, 4, 10])
 
 
 def test_lookahead_batches_do_not_change_results():
@@ -168,8 +186,9 @@ def test_sparse_full_size_first_iterations():
     iterations against the oracle, count and SubCount (s = 4 tau)."""
     p = inputs.sparse_csr()
     for kind, sub_k in (("count", 0), ("subcount", 4)):
-        _trajectory_check(p.X, p.y, p.lam, form="primal", kind=kind, tau=500, momentum="heuristic",
-                          sub_k=sub_k, checkpoints=[1, 3])
+        for route in ("scatter", "arows"):
+            _trajectory_check(p.X, p.y, p.lam, form="primal", kind=kind, tau=500, momentum="heuristic",
+                              sub_k=sub_k, checkpoints=[1, 3], route=route)
 
 
 def test_solve_converges_to_direct_solution():
