@@ -203,6 +203,130 @@ __global__ __launch_bounds__(kGemmThreads) void k_as_dense_bf16(GemmArgs a) {
       }
 }
 
+// Same product with the operand tiles moved from global memory straight into LDS
+// (global_load_lds_dwordx4, 16 bytes per lane, no register staging), 32 deep in K per
+// stage and four LDS stages, so three stages of loads stay in flight while one is
+// multiplied. A DMA instruction fills 1 KB of LDS: 16 rows of 64 bytes, lane L taking
+// row L / 4 and 16-byte slot L % 4. The slot of a row's logical segment t is
+// t ^ ((row / 4) % 4), which keeps the 16 rows read by a quarter wave on distinct banks.
+// Rows outside the matrix load row 0 (their results are not stored).
+constexpr int kDmaBK = 32;                    // K elements per stage
+constexpr int kDmaStages = 4;
+constexpr int kDmaRowBytes = kDmaBK * 2;      // 64
+constexpr int kDmaStageBytes = (kBM + kBN) * kDmaRowBytes;  // 32 KB
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+__device__ __forceinline__ void dma_wait_barrier() {
+  // every load of the stage about to be read has landed: at most two later stages
+  // (8 DMA instructions per wave) may still be in flight
+  __builtin_amdgcn_s_waitcnt(0x0F78);  // vmcnt(8), expcnt and lgkmcnt not waited on
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+__global__ __launch_bounds__(kGemmThreads) void k_as_dense_bf16_dma(GemmArgs a) {
+  extern __shared__ __align__(16) unsigned char dsm[];  // [kDmaStages][512 rows][64 B]
+  __shared__ int64_t brow[kBN];
+  if (*a.done) return;
+  int rt, ct;
+  tile_of_block(a, blockIdx.x, &rt, &ct);
+  if (rt < 0) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t row0 = (int64_t)rt * kBM, n0 = (int64_t)ct * kBN;
+  if (tid < kBN) {
+    const int64_t n = n0 + tid;
+    brow[tid] = n < a.ntot ? (int64_t)a.members[n] : -1;
+  }
+  __syncthreads();
+
+  // this lane's source rows for the wave's 4 DMA instructions of a stage
+  const unsigned char* src[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = (wave * 4 + q) * 16 + (lane >> 2);  // tile row 0..511
+    int64_t g;
+    if (r < kBM) {
+      g = row0 + r;
+      if (g >= a.m) g = 0;
+    } else {
+      g = brow[r - kBM];
+      if (g < 0) g = 0;
+    }
+    const int t = (lane & 3) ^ ((r >> 2) & 3);  // logical 16-byte segment stored in this slot
+    src[q] = reinterpret_cast<const unsigned char*>(a.Z + g * a.ldz) + t * 16;
+  }
+  const int64_t nk = a.kpad / kDmaBK;
+  auto issue = [&](int64_t kt) {
+    const int64_t ktl = kt < nk ? kt : nk - 1;  // past the end: reload the last stage
+    unsigned char* dst = dsm + (size_t)(kt & (kDmaStages - 1)) * kDmaStageBytes;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      __builtin_amdgcn_global_load_lds((const void*)(src[q] + ktl * kDmaRowBytes),
+                                       (lds_void_t*)(dst + (wave * 4 + q) * 16 * kDmaRowBytes), 16, 0, 0);
+  };
+
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 128;
+  f32x16 acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+  const int l32 = lane & 31, khi = lane >> 5;
+
+  issue(0);
+  issue(1);
+  issue(2);
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    dma_wait_barrier();
+    issue(kt + 3);  // into the stage every wave finished reading before the barrier
+    const unsigned char* st = dsm + (size_t)(kt & (kDmaStages - 1)) * kDmaStageBytes;
+#pragma unroll
+    for (int ks = 0; ks < kDmaBK; ks += 16) {
+      const int t = (ks >> 3) + khi;
+      bf16x8 av[2], bv[4];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int r = wr + i * 32 + l32;
+        av[i] = *reinterpret_cast<const bf16x8*>(st + r * kDmaRowBytes + ((t ^ ((r >> 2) & 3)) << 4));
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = kBM + wc + j * 32 + l32;
+        bv[j] = *reinterpret_cast<const bf16x8*>(st + r * kDmaRowBytes + ((t ^ ((r >> 2) & 3)) << 4));
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+  }
+  // no DMA may still be writing this workgroup's LDS when it exits
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+  __builtin_amdgcn_s_barrier();
+
+  // 32x32x16 result layout: lane l, element v -> row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = row0 + wr + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int col = wc + j * 32 + l32;
+        const int64_t n = n0 + col;
+        if (row < a.m && n < a.ntot) {
+          const int64_t slot = n / a.tau, c = n % a.tau;
+          float val = acc[i][j][v];
+          if (row == brow[col]) val = (float)((double)val + a.lam);
+          a.AS[(slot * a.m + row) * a.ldas + c] = val;
+        }
+      }
+}
+
 constexpr int kRefreshSplit = 32;  // row ranges of Z summed separately in Z^T x
 
 // upart[js][k][0..1] = sum_{j in range js} Z[j][k] * (x[j], xp[j]) in FP64 (FP32 data).
@@ -347,6 +471,14 @@ hipError_t launch_as_dense_bf16(const uint16_t* Zbf, int64_t ldz, int64_t m, int
   a.done = done;
   const int ntiles = a.n_row_tiles * a.n_col_tiles;
   const int per = (ntiles + kXcds - 1) / kXcds;
+  if (kpad % kDmaBK == 0) {
+    const size_t bytes = (size_t)kDmaStages * kDmaStageBytes;
+    hipError_t e = hipFuncSetAttribute((const void*)k_as_dense_bf16_dma,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_as_dense_bf16_dma, dim3(per * kXcds), dim3(kGemmThreads), bytes, s, a);
+    return hipGetLastError();
+  }
   const size_t bytes = sizeof(uint16_t) * 2 * (kBM + kBN) * kLdsRow;
   hipError_t e = hipFuncSetAttribute((const void*)k_as_dense_bf16,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);

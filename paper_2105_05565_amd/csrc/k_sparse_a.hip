@@ -128,30 +128,47 @@ __global__ __launch_bounds__(WAVES * 64) void k_as_arows(const int64_t* __restri
   }
 }
 
-// Rows of AS for one sketch per workgroup (blockIdx.x), with the sketch's bucket map staged
-// in LDS as 16-bit codes: the bucket lookups of the scatter-add become LDS reads instead of
-// vector-memory gathers. Consecutive workgroups take the same row chunk for different
-// sketches, so the XCD that runs them reads the chunk's rows of A0 into its L2 once.
+// Rows of AS for one sketch and one chunk of kLdsRows rows per workgroup, with the sketch's
+// bucket map staged in LDS as 16-bit codes: the bucket lookups of the scatter-add become LDS
+// reads instead of vector-memory gathers. Workgroups are dealt to the 8 XCDs in turn, so the
+// block index is mapped so that each XCD takes whole row chunks, every sketch of a chunk
+// before the next chunk: the chunk's rows of A0 are read into that XCD's L2 once and stay
+// there while its sketches pass.
 __global__ __launch_bounds__(512) void k_as_arows_lds(const int64_t* __restrict__ a_ptr,
                                                       const int32_t* __restrict__ a_col,
                                                       const double* __restrict__ a_val, int64_t m,
                                                       int32_t tau, int64_t ldas, double lam,
                                                       const int32_t* __restrict__ hmap_all,
-                                                      double* __restrict__ AS, int32_t rows_per_block,
-                                                      const int32_t* __restrict__ done) {
+                                                      double* __restrict__ AS, int32_t nslots,
+                                                      int64_t nchunks, const int32_t* __restrict__ done) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   int16_t* hm = reinterpret_cast<int16_t*>(lds_raw);                            // [m]
   double* acc_all = reinterpret_cast<double*>(lds_raw + ((2 * m + 15) & ~15ll));  // [8][tau]
   if (*done) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t slot = blockIdx.x;
+  const int64_t xcd = blockIdx.x & 7, i = blockIdx.x >> 3;
+  const int64_t chunk = 8 * (i / nslots) + xcd, slot = i % nslots;
+  if (chunk >= nchunks) return;  // the last round of chunks does not cover every XCD
   const int32_t* hmap = hmap_all + slot * m;
-  for (int64_t j = tid; j < m; j += 512) hm[j] = (int16_t)hmap[j];
+  // 8 loads in flight per thread while the map is staged
+  for (int64_t jb = tid; jb < m; jb += 512 * 8) {
+    int32_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t j = jb + u * 512;
+      v[u] = j < m ? hmap[j] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t j = jb + u * 512;
+      if (j < m) hm[j] = (int16_t)v[u];
+    }
+  }
   __syncthreads();
   double* acc = acc_all + (int64_t)wave * tau;
   double* out_base = AS + slot * m * ldas;
-  const int64_t j0 = (int64_t)blockIdx.y * rows_per_block;
-  const int64_t j1 = min(m, j0 + rows_per_block);
+  const int64_t j0 = chunk * kLdsRows;
+  const int64_t j1 = min(m, j0 + kLdsRows);
   for (int64_t j = j0 + wave; j < j1; j += 8) {
     for (int c = lane; c < tau; c += 64) acc[c] = 0.0;
     __builtin_amdgcn_wave_barrier();
@@ -321,9 +338,11 @@ hipError_t launch_as_arows(const int64_t* a_ptr, const int32_t* a_col, const dou
     // bucket map in LDS (16-bit codes): one sketch per workgroup
     e = hipFuncSetAttribute((const void*)k_as_arows_lds, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    const dim3 grid((unsigned)nslots, (unsigned)((m + kLdsRows - 1) / kLdsRows));
-    hipLaunchKernelGGL(k_as_arows_lds, grid, dim3(512), lds, s, a_ptr, a_col, a_val, m, tau, ldas, lam, hmap,
-                       AS, kLdsRows, done);
+    const int64_t nchunks = (m + kLdsRows - 1) / kLdsRows;
+    const int64_t nblocks = 8 * (int64_t)nslots * ((nchunks + 7) / 8);
+    if (nblocks > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_as_arows_lds, dim3((unsigned)nblocks), dim3(512), lds, s, a_ptr, a_col, a_val, m, tau,
+                       ldas, lam, hmap, AS, nslots, nchunks, done);
     e = hipGetLastError();
   } else if (tau <= 1024)
     e = arows_launch<16>(a_ptr, a_col, a_val, m, tau, ldas, nslots, lam, hmap, AS, done, s);
