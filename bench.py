@@ -427,6 +427,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sparse_count", choices=sorted(WORKLOADS))
     ap.add_argument("--lookahead", type=int, default=0)
+    ap.add_argument("--no-pipeline", action="store_true",
+                    help="prepare each lookahead batch on the solver's stream (no overlap with iterating)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-s", type=float, default=15.0)
     ap.add_argument("--sparse-route", default="auto", choices=["auto", "scatter", "arows"],
@@ -488,7 +490,7 @@ def main():
     S = rs.Solver(X, y, p.lam, tau=wl["tau"], sketch=wl["sketch"], form="primal", momentum="heuristic",
                   subcount_k=wl["sub_k"], tol=1e-6, max_iter=args.max_iter, seed=1,
                   precision=wl["precision"], lookahead=args.lookahead, profile=1, stream=stream,
-                  sparse_route=args.sparse_route)
+                  sparse_route=args.sparse_route, pipeline=not args.no_pipeline)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     route, a_nnz = rs.rs_get_route(S.h)
@@ -523,7 +525,7 @@ def main():
     S2 = rs.Solver(X, y, p.lam, tau=wl["tau"], sketch=wl["sketch"], form="primal", momentum="heuristic",
                    subcount_k=wl["sub_k"], tol=1e-6, max_iter=args.max_iter, seed=1,
                    precision=wl["precision"], lookahead=args.lookahead, profile=2, stream=stream,
-                   sparse_route=args.sparse_route)
+                   sparse_route=args.sparse_route, pipeline=not args.no_pipeline)
     S2.solve()
     prof2 = S2.profile()
     S2.close()
@@ -543,7 +545,8 @@ def main():
                    "lambda": p.lam, "momentum": "heuristic", "tol": 1e-6,
                    "precision": wl["precision"], "max_iter": args.max_iter,
                    "sparse_route": {0: None, 1: "scatter", 2: "arows"}[route],
-                   "a_nnz": a_nnz or None},
+                   "a_nnz": a_nnz or None,
+                   "pipeline": not args.no_pipeline and wl.get("sampler", "uniform") != "learned"},
         "iters_per_s": round(tot_iters / total, 1),
         "iters_median": statistics.median(iters),
         "time_s_quartiles": [round(q, 6) for q in statistics.quantiles(times, n=4)] if len(times) > 1 else times,

@@ -107,6 +107,11 @@ typedef struct rs_options {
   int32_t trace_every;      /* > 0: record (features, credits) every that many iterations */
   int32_t trace_capacity;   /* records kept (0 = 1024); later ones are dropped */
   int32_t sparse_route;     /* CSR count / SubCount products: RS_ROUTE_* */
+  int32_t pipeline;         /* 1 (default): prepare the next lookahead batch (sketches, AS,
+                               G^{-1}) on a second stream of default priority while the current
+                               batch iterates, in a second set of batch buffers (twice their
+                               memory); 0: one stream. Off for the learned sampler, whose
+                               proposal reads the iterate. */
 } rs_options;
 
 /* How AS is formed for the count and SubCount sketches on CSR data (same result up to

@@ -64,6 +64,25 @@ struct rs_handle {
 
   // lookahead batch
   int B = 1;
+  // Buffers a batch's preparation writes and its iterations read. With the pipeline on,
+  // the next batch is prepared into the other set on prep_stream while the current one
+  // iterates on `stream` (ev_ready[p]: set p prepared). hmap, members, offs, AS, G and
+  // status below point at the set of the latest batch.
+  struct BatchSet {
+    int32_t* hmap = nullptr;
+    int32_t* members = nullptr;
+    int32_t* offs = nullptr;
+    void* AS = nullptr;
+    double* G = nullptr;
+    int32_t* status = nullptr;
+  };
+  BatchSet sets[2];
+  int nsets = 1;
+  int cur_set = 0;
+  bool pipeline = false;
+  hipStream_t prep_stream = nullptr;
+  hipEvent_t ev_ready[2] = {nullptr, nullptr};
+  hipEvent_t ev_start = nullptr;
   int64_t ldg = 0;
   int64_t ldas = 0;  // row stride of AS (tau rounded up to 8)
   double* rho = nullptr;
@@ -148,6 +167,15 @@ void dfree_all(rs_handle* h) {
   h->allocs.clear();
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   h->ev.clear();
+  for (hipEvent_t* e : {&h->ev_ready[0], &h->ev_ready[1], &h->ev_start})
+    if (*e) {
+      (void)hipEventDestroy(*e);
+      *e = nullptr;
+    }
+  if (h->prep_stream) {
+    (void)hipStreamDestroy(h->prep_stream);
+    h->prep_stream = nullptr;
+  }
 }
 
 // Momentum schedule (Sec. 6, Sec. 9.1), evaluated in a fixed operation order.
@@ -191,18 +219,18 @@ T* to_device(rs_handle* h, const void* src, size_t count, int mem) {
 }
 
 // Event pair around one launch when profiling: returns the pair index or -1.
-int prof_begin(rs_handle* h, int cls, int slots, int level = 1) {
+int prof_begin(rs_handle* h, int cls, int slots, int level = 1, hipStream_t s = nullptr) {
   if (h->opt.profile < level) return -1;
   if (2 * (h->ev_used + 1) > (int)h->ev.size()) return -1;  // pool full: leave untimed
   const int i = h->ev_used++;
   h->ev_cls[i] = cls;
   h->ev_slots[i] = slots;
-  check_hip(hipEventRecord(h->ev[2 * i], h->stream), "event");
+  check_hip(hipEventRecord(h->ev[2 * i], s ? s : h->stream), "event");
   return i;
 }
 
-void prof_end(rs_handle* h, int i) {
-  if (i >= 0) check_hip(hipEventRecord(h->ev[2 * i + 1], h->stream), "event");
+void prof_end(rs_handle* h, int i, hipStream_t s = nullptr) {
+  if (i >= 0) check_hip(hipEventRecord(h->ev[2 * i + 1], s ? s : h->stream), "event");
 }
 
 // After a synchronisation: fold the recorded pairs into h->prof.
@@ -228,8 +256,11 @@ void refresh(rs_handle* h, int64_t k) {
   prof_end(h, pe);
 }
 
-void run_batch(rs_handle* h, int64_t k0, int nb) {
-  hipStream_t s = h->stream;
+// Sketches k0 .. k0 + nb - 1 of a batch, their products AS, G = S^T A S and its inverse,
+// written into buffer set p on stream s. Only the learned proposal reads the iterate
+// (and then s is the solver's stream).
+void prep_batch(rs_handle* h, int p, int64_t k0, int nb, hipStream_t s) {
+  rs_handle::BatchSet& bs = h->sets[p];
   const int32_t* done = &h->flags->done;
   SketchArgs a{};
   a.kind = h->kind;
@@ -241,13 +272,13 @@ void run_batch(rs_handle* h, int64_t k0, int nb) {
   a.pid = h->opt.problem_id;
   a.k0 = k0;
   a.nslots = nb;
-  a.hmap = h->hmap;
-  a.members = h->members;
-  a.offs = h->offs;
+  a.hmap = bs.hmap;
+  a.members = bs.members;
+  a.offs = bs.offs;
   a.keys = h->keys;
   a.err = h->err;
   a.done = done;
-  int pe = prof_begin(h, RS_PROF_SKETCH, nb);
+  int pe = prof_begin(h, RS_PROF_SKETCH, nb, 1, s);
   if (h->sampler != RS_SAMPLER_UNIFORM) {
     // coordinates drawn from the proposal q (features of r^{k0}, r^{k0-1} for the
     // learned one): the tau smallest u_j / q_j per sketch
@@ -264,43 +295,61 @@ void run_batch(rs_handle* h, int64_t k0, int nb) {
   }
   check_hip(launch_sketch(a, s), "sketch");
   if (h->sparse && !h->arows)
-    check_hip(launch_build_t(h->zt_col, h->zt_val, h->vals_f32, h->nnz, h->hmap, h->m, nb, h->tbuf,
+    check_hip(launch_build_t(h->zt_col, h->zt_val, h->vals_f32, h->nnz, bs.hmap, h->m, nb, h->tbuf,
                              done, s),
               "T map");
-  prof_end(h, pe);
-  pe = prof_begin(h, RS_PROF_AS, nb);
+  prof_end(h, pe, s);
+  pe = prof_begin(h, RS_PROF_AS, nb, 1, s);
   if (h->arows) {
-    check_hip(launch_as_arows(h->a_ptr, h->a_col, h->a_val, h->m, h->tau, h->ldas, nb, h->lam, h->hmap,
-                              h->members, h->offs, h->nsel, (double*)h->AS, h->G, h->ldg, done, s),
+    check_hip(launch_as_arows(h->a_ptr, h->a_col, h->a_val, h->m, h->tau, h->ldas, nb, h->lam, bs.hmap,
+                              bs.members, bs.offs, h->nsel, (double*)bs.AS, bs.G, h->ldg, done, s),
               "AS (rows of Z Z^T)");
   } else if (h->sparse) {
     check_hip(launch_as_sparse(h->zr_ptr, h->zr_col, h->zr_val, h->zt_ptr, h->zt_col, h->zt_val,
                                h->vals_f32, h->nnz, h->m, h->tau, h->ldas, nb, h->kind, h->lam,
-                               h->hmap, h->members, h->offs, h->nsel, h->tbuf, (double*)h->AS, h->G,
+                               bs.hmap, bs.members, bs.offs, h->nsel, h->tbuf, (double*)bs.AS, bs.G,
                                h->ldg, done, s),
               "AS (sparse)");
   } else if (h->mixed) {
-    check_hip(launch_as_dense_bf16(h->Zbf, h->kpad, h->m, h->kpad, h->members, h->tau, h->ldas, nb,
-                                   h->lam, (float*)h->AS, done, s),
+    check_hip(launch_as_dense_bf16(h->Zbf, h->kpad, h->m, h->kpad, bs.members, h->tau, h->ldas, nb,
+                                   h->lam, (float*)bs.AS, done, s),
               "AS (dense, BF16)");
   } else {
-    check_hip(launch_as_dense_f64(h->Z, h->ldz, h->m, h->K, h->members, h->tau, h->ldas, nb, h->lam,
-                                  (double*)h->AS, done, s),
+    check_hip(launch_as_dense_f64(h->Z, h->ldz, h->m, h->K, bs.members, h->tau, h->ldas, nb, h->lam,
+                                  (double*)bs.AS, done, s),
               "AS (dense)");
   }
-  prof_end(h, pe);
-  pe = prof_begin(h, RS_PROF_CHOL, nb);
+  prof_end(h, pe, s);
+  pe = prof_begin(h, RS_PROF_CHOL, nb, 1, s);
   // One workgroup per sketch when the batch fills the chip; otherwise one per tile.
   if (h->ldg >= 128 && nb < 128)
-    check_hip(launch_chol_multi(h->G, h->W, h->Xd, h->ldg, h->tau, nb, h->kind, h->AS,
-                                h->mixed ? 1 : 0, h->ldas, h->m, h->members, h->offs, h->status, done,
+    check_hip(launch_chol_multi(bs.G, h->W, h->Xd, h->ldg, h->tau, nb, h->kind, bs.AS,
+                                h->mixed ? 1 : 0, h->ldas, h->m, bs.members, bs.offs, bs.status, done,
                                 s),
               "cholesky (tiled)");
   else
-    check_hip(launch_chol_inverse(h->G, h->W, h->ldg, h->tau, nb, h->kind, h->AS, h->mixed ? 1 : 0,
-                                  h->ldas, h->m, h->members, h->offs, h->status, done, s),
+    check_hip(launch_chol_inverse(bs.G, h->W, h->ldg, h->tau, nb, h->kind, bs.AS, h->mixed ? 1 : 0,
+                                  h->ldas, h->m, bs.members, bs.offs, bs.status, done, s),
               "cholesky");
-  prof_end(h, pe);
+  prof_end(h, pe, s);
+}
+
+// Point the solver at buffer set p (the batch about to iterate; the accessors read it).
+void use_set(rs_handle* h, int p) {
+  h->cur_set = p;
+  h->hmap = h->sets[p].hmap;
+  h->members = h->sets[p].members;
+  h->offs = h->sets[p].offs;
+  h->AS = h->sets[p].AS;
+  h->G = h->sets[p].G;
+  h->status = h->sets[p].status;
+}
+
+// Iterations k0 .. k0 + nb - 1 on the solver's stream, from the batch prepared in set p.
+void iterate_batch(rs_handle* h, int p, int64_t k0, int nb) {
+  hipStream_t s = h->stream;
+  use_set(h, p);
+  int pe = -1;
   // rho_{k0} = S_{k0}^T r^{k0}; later iterations get rho from the preceding update
   check_hip(launch_rho(h->rbuf[k0 & 1], h->hmap, h->members, h->offs, h->tau, h->rho, h->flags, s),
             "rho");
@@ -369,8 +418,44 @@ void run_batch(rs_handle* h, int64_t k0, int nb) {
   h->batch_n = nb;
 }
 
+// Size of the batch starting at iteration k_from: the lookahead, or near the tolerance
+// fewer, from the contraction observed between the last two known residual norms, so
+// that few sketches are formed past the stopping iteration.
+// Iterations still needed after k_from to reach the tolerance, extrapolated from the
+// contraction between the last two known residual norms; +inf when unknown.
+double predicted_need(const rs_handle* h, int64_t k_from, int64_t k_a, double rel_a, int64_t k_b, double rel_b) {
+  if (k_a >= 0 && k_b > k_a && rel_b < rel_a && rel_b > 0.0 && h->opt.tol > 0.0) {
+    const double rate = std::log(rel_b / rel_a) / (double)(k_b - k_a);
+    return std::log(h->opt.tol / rel_b) / rate - (double)(k_from - k_b);
+  }
+  return INFINITY;
+}
+
+int batch_size(const rs_handle* h, int64_t left, int64_t k_from, int64_t k_a, double rel_a, int64_t k_b,
+               double rel_b) {
+  int nb = (int)std::min<int64_t>(h->B, left);
+  const double need = predicted_need(h, k_from, k_a, rel_a, k_b, rel_b);
+  // never above the lookahead buffers nor the iterations asked for
+  if (need < nb) nb = (int)std::min<double>(nb, std::max<double>(std::min(16, nb), need * 1.1 + 8.0));
+  return nb;
+}
+
+// Waits for the preparation stream when advance() leaves, also on an error.
+struct PrepDrain {
+  rs_handle* h;
+  ~PrepDrain() {
+    if (h->pipeline) (void)hipStreamSynchronize(h->prep_stream);
+  }
+};
+
 // Advance up to `iters` iterations, one lookahead batch at a time. After each batch
 // the stop flag, the factorisation status and the error word are read back.
+//
+// With the pipeline on, every batch is prepared on prep_stream (so preparations, which
+// share scratch buffers, run in order) and batch t + 1 is queued there before the host
+// waits for batch t: its sketches, products and factorisations run while batch t
+// iterates, in the other buffer set. The host waits for both streams after each batch,
+// so a set is never written while iterations read it.
 void advance(rs_handle* h, int64_t iters) {
   if (h->sampler == RS_SAMPLER_LEARNED && !h->params_set)
     throw Fail{RS_EINVAL, "the learned sampler needs rs_set_sampler_params before iterating"};
@@ -380,19 +465,40 @@ void advance(rs_handle* h, int64_t iters) {
   // last two known points (k, ||r^k|| / ||r^0||) of the residual history
   int64_t k_a = -1, k_b = -1;
   double rel_a = 0.0, rel_b = 0.0;
+  const bool pipe = h->pipeline;
+  PrepDrain drain{h};
+  int p = h->cur_set;
+  int nb = 0;
+  bool prepared = false;  // set p holds the batch that starts at k_enq (nb sketches)
+  if (pipe && left > 0 && !h->done) {
+    // the first preparation follows what the caller queued on the solver's stream
+    check_hip(hipEventRecord(h->ev_start, h->stream), "event");
+    check_hip(hipStreamWaitEvent(h->prep_stream, h->ev_start, 0), "wait");
+    nb = batch_size(h, left, k_enq, k_a, rel_a, k_b, rel_b);
+    prep_batch(h, p, k_enq, nb, h->prep_stream);
+    prepared = true;
+  }
   while (left > 0 && !h->done) {
-    int nb = (int)std::min<int64_t>(h->B, left);
-    // Near the tolerance, size the batch from the observed contraction so that few
-    // sketches are formed past the stopping iteration.
-    if (k_a >= 0 && k_b > k_a && rel_b < rel_a && rel_b > 0.0 && h->opt.tol > 0.0) {
-      const double rate = std::log(rel_b / rel_a) / (double)(k_b - k_a);
-      const double need = std::log(h->opt.tol / rel_b) / rate - (double)(h->k - k_b);
-      // never above the lookahead buffers nor the iterations asked for
-      if (need < nb) nb = (int)std::min<double>(nb, std::max<double>(std::min(16, nb), need * 1.1 + 8.0));
+    if (!prepared) {
+      nb = batch_size(h, left, k_enq, k_a, rel_a, k_b, rel_b);
+      prep_batch(h, p, k_enq, nb, h->stream);
+    } else {
+      check_hip(hipEventRecord(h->ev_ready[p], h->prep_stream), "event");
+      check_hip(hipStreamWaitEvent(h->stream, h->ev_ready[p], 0), "wait");
     }
-    run_batch(h, k_enq, nb);
+    iterate_batch(h, p, k_enq, nb);
     k_enq += nb;
     left -= nb;
+    prepared = false;
+    int nb_next = 0;
+    // Not when the tolerance is predicted within the batch just queued or early in the
+    // next: a batch prepared past the stopping iteration is only waited for, while a
+    // batch prepared after the wait is a short one.
+    if (pipe && left > 0 && predicted_need(h, k_enq, k_a, rel_a, k_b, rel_b) > 0.25 * nb) {
+      nb_next = batch_size(h, left, k_enq, k_a, rel_a, k_b, rel_b);
+      prep_batch(h, 1 - p, k_enq, nb_next, h->prep_stream);
+      prepared = true;
+    }
     if (left == 0) {
       if (h->mixed) {
         if (k_enq % h->opt.refresh_every != 0) refresh(h, k_enq);
@@ -407,8 +513,9 @@ void advance(rs_handle* h, int64_t iters) {
     check_hip(hipMemcpyAsync(&f, h->flags, sizeof(DevFlags), hipMemcpyDeviceToHost, h->stream), "flags");
     check_hip(hipMemcpyAsync(st.data(), h->status, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, h->stream),
               "status");
-    check_hip(hipMemcpyAsync(&err, h->err, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream), "err");
     check_hip(hipStreamSynchronize(h->stream), "sync");
+    if (pipe) check_hip(hipStreamSynchronize(h->prep_stream), "sync");
+    check_hip(hipMemcpy(&err, h->err, sizeof(int32_t), hipMemcpyDeviceToHost), "err");
     prof_collect(h);
     if (err) throw Fail{RS_EDEVICE, "internal sketch limit hit (code " + std::to_string(err) + ")"};
     const int64_t k_end = f.done ? f.k_done : k_enq;
@@ -425,6 +532,10 @@ void advance(rs_handle* h, int64_t iters) {
     }
     h->k = k_end;
     if (f.done) h->done = true;
+    if (prepared) {
+      p = 1 - p;
+      nb = nb_next;
+    }
   }
 }
 
@@ -458,6 +569,7 @@ rs_status rs_options_default(rs_options* o) {
   o->trace_every = 0;
   o->trace_capacity = 0;
   o->sparse_route = RS_ROUTE_AUTO;
+  o->pipeline = 1;
   return RS_OK;
 }
 
@@ -681,11 +793,15 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
     // batch buffers
     h->ldg = ((int64_t)h->tau + 63) / 64 * 64;
     h->ldas = ((int64_t)h->tau + 7) / 8 * 8;
-    const size_t per_slot = (h->sparse && !h->arows ? sparse_t_bytes(h->vals_f32, h->nnz) : 0) +
-                            (h->mixed ? sizeof(float) : sizeof(double)) * (size_t)h->m * h->ldas +
-                            sizeof(double) * 2 * (size_t)h->ldg * h->ldg +
-                            sizeof(int32_t) * ((size_t)h->m + h->nsel + h->tau + 1) +
-                            sizeof(uint64_t) * (size_t)h->m;
+    // The learned proposal reads the iterate, so its batches cannot be prepared ahead.
+    h->pipeline = o->pipeline != 0 && o->sampler != RS_SAMPLER_LEARNED;
+    h->nsets = h->pipeline ? 2 : 1;
+    const size_t per_slot_set = (h->mixed ? sizeof(float) : sizeof(double)) * (size_t)h->m * h->ldas +
+                                sizeof(double) * (size_t)h->ldg * h->ldg +
+                                sizeof(int32_t) * ((size_t)h->m + h->nsel + h->tau + 2);
+    const size_t per_slot = h->nsets * per_slot_set +
+                            (h->sparse && !h->arows ? sparse_t_bytes(h->vals_f32, h->nnz) : 0) +
+                            sizeof(double) * (size_t)h->ldg * h->ldg + sizeof(uint64_t) * (size_t)h->m;
     // Default lookahead: 256 sketches, fewer when one sketch's contraction is large
     // (the sketches formed past the stopping iteration are wasted work).
     int B = 256;
@@ -696,20 +812,31 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
     const size_t budget = (size_t)48 << 30;
     while (B > 1 && (size_t)B * per_slot > budget) B >>= 1;
     h->B = B;
-    h->hmap = dalloc<int32_t>(h, (size_t)B * h->m);
-    h->members = dalloc<int32_t>(h, (size_t)B * h->nsel);
-    h->offs = dalloc<int32_t>(h, (size_t)B * (h->tau + 1));
-    h->keys = dalloc<uint64_t>(h, (size_t)B * h->m);
     const size_t as_bytes = (h->mixed ? sizeof(float) : sizeof(double)) * (size_t)B * h->m * h->ldas;
-    h->AS = dalloc<char>(h, as_bytes);
-    // the padding columns of AS are read (times a zero delta) by the update: keep them zero
-    check_hip(hipMemsetAsync(h->AS, 0, as_bytes, s), "memset");
+    for (int p = 0; p < h->nsets; ++p) {
+      rs_handle::BatchSet& bs = h->sets[p];
+      bs.hmap = dalloc<int32_t>(h, (size_t)B * h->m);
+      bs.members = dalloc<int32_t>(h, (size_t)B * h->nsel);
+      bs.offs = dalloc<int32_t>(h, (size_t)B * (h->tau + 1));
+      bs.AS = dalloc<char>(h, as_bytes);
+      // the padding columns of AS are read (times a zero delta) by the update: keep them zero
+      check_hip(hipMemsetAsync(bs.AS, 0, as_bytes, s), "memset");
+      bs.G = dalloc<double>(h, (size_t)B * h->ldg * h->ldg);
+      bs.status = dalloc<int32_t>(h, B);
+      check_hip(hipMemsetAsync(bs.status, 0, sizeof(int32_t) * B, s), "memset");
+    }
+    use_set(h, 0);
+    h->keys = dalloc<uint64_t>(h, (size_t)B * h->m);
+    if (h->pipeline) {
+      // default priority, like the solver's stream
+      check_hip(hipStreamCreateWithFlags(&h->prep_stream, hipStreamNonBlocking), "stream create");
+      for (hipEvent_t* e : {&h->ev_ready[0], &h->ev_ready[1], &h->ev_start})
+        check_hip(hipEventCreateWithFlags(e, hipEventDisableTiming), "event create");
+    }
     h->rho = dalloc<double>(h, h->ldg);
     if (h->sparse && !h->arows) h->tbuf = dalloc<char>(h, (size_t)B * sparse_t_bytes(h->vals_f32, h->nnz));
-    h->G = dalloc<double>(h, (size_t)B * h->ldg * h->ldg);
     h->W = dalloc<double>(h, (size_t)B * h->ldg * h->ldg);
     h->Xd = reinterpret_cast<double*>(dalloc<char>(h, (size_t)B * chol_multi_x_bytes(h->ldg)));
-    h->status = dalloc<int32_t>(h, B);
     h->delta = dalloc<double>(h, h->ldg);
     h->npart = update_partials(h->m, h->tau);
     h->partials = dalloc<double>(h, h->npart);
@@ -755,14 +882,14 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
       }
     }
     if (o->profile) {
-      // sketch, AS, Cholesky, iteration sequence; delta, update and refresh per iteration
-      const int pairs = 4 + 3 * B + 2;
+      // sketch, AS, Cholesky of this batch and of the one prepared ahead, the iteration
+      // sequence; delta, update and refresh per iteration
+      const int pairs = 7 + 3 * B + 2;
       h->ev.resize(2 * pairs);
       h->ev_cls.resize(pairs);
       h->ev_slots.resize(pairs);
       for (auto& e : h->ev) check_hip(hipEventCreate(&e), "event create");
     }
-    check_hip(hipMemsetAsync(h->status, 0, sizeof(int32_t) * B, s), "memset");
     check_hip(hipMemsetAsync(h->err, 0, sizeof(int32_t), s), "memset");
     check_hip(launch_init_state(h->b, h->xbuf[0], h->xbuf[1], h->rbuf[0], h->rbuf[1], h->m,
                                 h->partials, h->npart, h->flags, h->hist, s),
@@ -812,7 +939,8 @@ rs_status rs_reset(rs_handle* h, uint64_t seed) {
     h->done = false;
     h->batch_k0 = -1;
     h->batch_n = 0;
-    check_hip(hipMemsetAsync(h->status, 0, sizeof(int32_t) * h->B, h->stream), "memset");
+    for (int p = 0; p < h->nsets; ++p)
+      check_hip(hipMemsetAsync(h->sets[p].status, 0, sizeof(int32_t) * h->B, h->stream), "memset");
     check_hip(hipMemsetAsync(h->err, 0, sizeof(int32_t), h->stream), "memset");
     if (h->last) check_hip(hipMemsetAsync(h->last, 0xFF, sizeof(int32_t) * h->m, h->stream), "memset");
     check_hip(launch_init_state(h->b, h->xbuf[0], h->xbuf[1], h->rbuf[0], h->rbuf[1], h->m,

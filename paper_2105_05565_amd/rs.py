@@ -45,7 +45,8 @@ class rs_options(ctypes.Structure):
                 ("profile", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("graph_iters", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("sampler", ctypes.c_int32), ("trace_every", ctypes.c_int32),
-                ("trace_capacity", ctypes.c_int32), ("sparse_route", ctypes.c_int32)]
+                ("trace_capacity", ctypes.c_int32), ("sparse_route", ctypes.c_int32),
+                ("pipeline", ctypes.c_int32)]
 
 
 RS_SAMPLER_UNIFORM, RS_SAMPLER_LEARNED, RS_SAMPLER_DIAG = 0, 1, 2
@@ -563,7 +564,7 @@ class Solver:
                  precision="fp64", subcount_k=0, tol=1e-6, max_iter=100000, seed=1, problem_id=0,
                  eta=0.995, beta_max=0.5, gamma=1.0, beta=0.5, lookahead=0, refresh_every=20,
                  profile=False, stream=None, sampler="uniform", trace_every=0, trace_capacity=0,
-                 sparse_route="auto"):
+                 sparse_route="auto", pipeline=True):
         o = rs_options_default()
         o.form, o.sketch, o.tau = FORMS[form], SKETCHES[sketch], int(tau)
         o.subcount_k, o.momentum, o.precision = int(subcount_k), MOMENTA[momentum], PRECISIONS[precision]
@@ -573,6 +574,7 @@ class Solver:
         o.stream = stream
         o.sampler, o.trace_every, o.trace_capacity = SAMPLERS[sampler], int(trace_every), int(trace_capacity)
         o.sparse_route = ROUTES[sparse_route]
+        o.pipeline = int(bool(pipeline))
         M, keep = make_matrix(X)
         if M.mem == RS_DEVICE:
             yv = y.double().contiguous()
