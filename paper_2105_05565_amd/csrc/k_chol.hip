@@ -13,9 +13,11 @@
 //
 // Blocked algorithm on 64 x 64 tiles (4 waves, FP64 MFMA 16x16x4 for tile products,
 // operands staged in LDS), with U = L^{-T} (upper triangular) kept instead of L^{-1}
-// so that every tile product reads its operands row-major:
-//   1. right-looking Cholesky: factor the diagonal tile and invert it in LDS,
-//      panel L_ik = G_ik U_kk, trailing update G_ij -= L_ik L_jk^T;
+// so that every tile product reads its operands row-major. Every phase is a sequence of
+// chains sum_k A_k B_k^T accumulated in MFMA registers, one chain per output tile, written
+// once; the operands of the next step load while the current step multiplies:
+//   1. left-looking Cholesky: C_ij = G_ij - sum_{k<j} L_ik L_jk^T, the diagonal tile
+//      factored and inverted in LDS (X_jj = L_jj^{-1}), panel L_ij = C_ij X_jj^T;
 //   2. U_ji = -(sum_{k=j}^{i-1} U_jk L_ik^T) U_ii for i > j  (U = (L^{-1})^T);
 //   3. G^{-1} = U U^T, tile (i, j) = sum_{k >= max(i,j)} U_ik U_jk^T, both triangles.
 #include "chol_tiles.h"
@@ -27,129 +29,209 @@ namespace {
 
 using namespace chol;
 
+// One 64 x 64 tile held in registers between its global load and its LDS store:
+// 16 doubles per thread as 8 double2 (element e = tid + 256 u: row e / 32, columns
+// 2 (e % 32) and 2 (e % 32) + 1), so that a tile row is one 512-byte coalesced read.
+struct TileRegs {
+  double2 v[8];
+};
+
+__device__ __forceinline__ void tile_gload(TileRegs& t, const double* __restrict__ src, int64_t ld) {
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int e = threadIdx.x + u * kThreads;
+    t.v[u] = *reinterpret_cast<const double2*>(src + (int64_t)(e >> 5) * ld + 2 * (e & 31));
+  }
+}
+
+__device__ __forceinline__ void tile_lstore(double* dst, const TileRegs& t) {
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int e = threadIdx.x + u * kThreads;
+    double* p = dst + (e >> 5) * LDT + 2 * (e & 31);
+    p[0] = t.v[u].x;
+    p[1] = t.v[u].y;
+  }
+}
+
+__device__ __forceinline__ double* gtile(double* base, int64_t ld, int i, int j) {
+  return base + (int64_t)i * NB * ld + (int64_t)j * NB;
+}
+
+// Chains of tile products C = sum_k A_k B_k^T, one chain per output tile, run back to
+// back: while the MFMAs of step s read the operands in LDS (ta, tb), the operands of
+// step s + 1 -- of the same chain or of the next one -- are already loading into
+// registers. At the last step of a chain, epi(it, C) consumes the accumulator; it may use
+// ta and tb as scratch and must end with a workgroup barrier. The operands of a chain's
+// first step never depend on the epilogue of the chain before it (checked for each
+// phase's order where the iterator is defined).
+template <class It, class Epi>
+__device__ __forceinline__ void chain_pipeline(It it, int64_t ld, double* ta, double* tb, Epi epi) {
+  if (!it.valid()) return;
+  TileRegs ra, rb;
+  tile_gload(ra, it.a(), ld);
+  tile_gload(rb, it.b(), ld);
+  tile_lstore(ta, ra);
+  tile_lstore(tb, rb);
+  __syncthreads();
+  Acc c;
+  acc_zero(c);
+  while (true) {
+    It nx = it;
+    nx.advance();
+    const bool more = nx.valid();
+    if (more) {
+      tile_gload(ra, nx.a(), ld);
+      tile_gload(rb, nx.b(), ld);
+    }
+    tile_mma(c, ta, tb);
+    __syncthreads();
+    if (it.last()) {
+      epi(it, c);
+      acc_zero(c);
+    }
+    if (!more) break;
+    tile_lstore(ta, ra);
+    tile_lstore(tb, rb);
+    __syncthreads();
+    it = nx;
+  }
+}
+
+// Phase 1, block columns j >= 1, left-looking: C_ij = sum_{k < j} L_ik L_jk^T for
+// i = j .. nt-1 (the diagonal tile first). The first step of a chain reads block column 0.
+struct ItChol {
+  double* G;
+  int64_t ld;
+  int nt, j, i, k;
+  __device__ bool valid() const { return j < nt; }
+  __device__ const double* a() const { return gtile(G, ld, i, k); }
+  __device__ const double* b() const { return gtile(G, ld, j, k); }
+  __device__ bool last() const { return k == j - 1; }
+  __device__ void advance() {
+    if (++k < j) return;
+    k = 0;
+    if (++i < nt) return;
+    ++j;
+    i = j;
+  }
+};
+
+// Phase 2: S_ji = sum_{k = j}^{i-1} U_jk L_ik^T for i > j, rows j in order, columns i
+// ascending. The chain of (j, i + 1) reads U_ji (the epilogue of (j, i)) only at its last
+// step; its first step reads U_jj.
+struct ItInv {
+  double* U;
+  double* G;
+  int64_t ld;
+  int nt, j, i, k;
+  __device__ bool valid() const { return j < nt - 1; }
+  __device__ const double* a() const { return gtile(U, ld, j, k); }
+  __device__ const double* b() const { return gtile(G, ld, i, k); }
+  __device__ bool last() const { return k == i - 1; }
+  __device__ void advance() {
+    if (++k < i) return;
+    if (++i == nt) {
+      ++j;
+      i = j + 1;
+    }
+    k = j;
+  }
+};
+
+// Phase 3: (G^{-1})_ij = sum_{k >= i} U_ik U_jk^T for j <= i; reads U only.
+struct ItLauum {
+  double* U;
+  int64_t ld;
+  int nt, i, j, k;
+  __device__ bool valid() const { return i < nt; }
+  __device__ const double* a() const { return gtile(U, ld, i, k); }
+  __device__ const double* b() const { return gtile(U, ld, j, k); }
+  __device__ bool last() const { return k == nt - 1; }
+  __device__ void advance() {
+    if (++k < nt) return;
+    if (++j > i) {
+      ++i;
+      j = 0;
+    }
+    k = i;
+  }
+};
+
 // Phases 1-3 on the assembled, padded ldg x ldg matrix G (lower triangle read):
-// G <- G^{-1} (both triangles), U <- L^{-T}. LDS: ta, tb, td (64 x LDT each), col (64).
+// G <- G^{-1} (both triangles), U <- L^{-T} (upper block triangle; the tile below each
+// diagonal tile, U_{i,i-1}, holds X_ii = L_ii^{-1} for phase 2).
+// LDS: ta, tb, td, tx (64 x LDT each), col (64).
 __device__ __forceinline__ void factor_invert(double* __restrict__ G, double* __restrict__ U,
                                               int64_t ldg, double* ta, double* tb, double* td,
-                                              double* col, int* bad_flag) {
-  const int tid = threadIdx.x;
+                                              double* tx, double* col, int* bad_flag) {
   const int nt = (int)(ldg / NB);
-  int& bad = *bad_flag;
-  // Phase 1: Cholesky (lower triangle of G in place) and U_kk = L_kk^{-T}.
-  for (int kt = 0; kt < nt; ++kt) {
-    double* Gkk = G + (int64_t)kt * NB * ldg + kt * NB;
-    load_tile(td, Gkk, ldg, false);
-    __syncthreads();
-    for (int c = 0; c < NB; ++c) {
-      if (tid < NB) {
-        double piv = td[c * LDT + c];
-        if (!(piv > 0.0) || !(piv < INFINITY)) {
-          if (tid == c) bad = 1;
-          piv = 1.0;
-        }
-        const double sq = sqrt(piv);
-        col[tid] = (tid == c) ? sq : (tid > c ? td[tid * LDT + c] / sq : 0.0);
-      }
-      __syncthreads();
-      for (int e = tid; e < NB * NB; e += kThreads) {
-        const int r = e >> 6, cc = e & 63;
-        if (cc == c && r >= c) td[r * LDT + c] = col[r];
-        else if (cc > c && r >= cc) td[r * LDT + cc] -= col[r] * col[cc];
-      }
-      __syncthreads();
-    }
-    // X = L_kk^{-1} row by row (row i needs rows < i): thread j owns column j, ta[i][j] = X[i][j]
-    if (tid < NB) {
-      const int j = tid;
-      for (int i = 0; i < NB; ++i) {
-        double s = (i == j) ? 1.0 : 0.0;
-        for (int t = j; t < i; ++t) s -= td[i * LDT + t] * ta[t * LDT + j];
-        ta[i * LDT + j] = (i >= j) ? s / td[i * LDT + i] : 0.0;
-      }
-    }
-    __syncthreads();
-    // write L_kk (upper part zero) and U_kk = X^T; tb[c][k] = U_kk[k][c] = X[c][k] for the panel
-    double* Ukk = U + (int64_t)kt * NB * ldg + kt * NB;
-    for (int e = tid; e < NB * NB; e += kThreads) {
+  // td holds C_jj: factor it, keep X_jj = L_jj^{-1} in tx, store L_jj, U_jj = X_jj^T and
+  // (j >= 1) the copy of X_jj read by phase 2
+  auto diag = [&](int j) {
+    factor_diag_tile(td, tx, col, bad_flag);
+    double* Gjj = gtile(G, ldg, j, j);
+    double* Ujj = gtile(U, ldg, j, j);
+    double* Xjj = j > 0 ? gtile(U, ldg, j, j - 1) : nullptr;
+    for (int e = threadIdx.x; e < NB * NB; e += kThreads) {
       const int r = e >> 6, c = e & 63;
-      Gkk[(int64_t)r * ldg + c] = (c <= r) ? td[r * LDT + c] : 0.0;
-      Ukk[(int64_t)r * ldg + c] = ta[c * LDT + r];
-      tb[r * LDT + c] = ta[r * LDT + c];
+      Gjj[(int64_t)r * ldg + c] = (c <= r) ? td[r * LDT + c] : 0.0;
+      Ujj[(int64_t)r * ldg + c] = tx[c * LDT + r];
+      if (Xjj) Xjj[(int64_t)r * ldg + c] = tx[r * LDT + c];
     }
     __syncthreads();
-    // panel: L_ik = G_ik U_kk
-    for (int it = kt + 1; it < nt; ++it) {
-      double* Gik = G + (int64_t)it * NB * ldg + kt * NB;
-      load_tile(ta, Gik, ldg, false);
-      __syncthreads();
-      Acc c;
-      acc_zero(c);
-      tile_mma(c, ta, tb);
-      __syncthreads();
-      acc_for_each(c, [&](int r, int cc, double v) { Gik[(int64_t)r * ldg + cc] = v; });
-      __syncthreads();
-    }
-    // trailing update: G_ij -= L_ik L_jk^T for kt < jt <= it
-    for (int jt = kt + 1; jt < nt; ++jt) {
-      load_tile(tb, G + (int64_t)jt * NB * ldg + kt * NB, ldg, false);  // tb[c][k] = L_jk[c][k]
-      for (int it = jt; it < nt; ++it) {
-        load_tile(ta, G + (int64_t)it * NB * ldg + kt * NB, ldg, false);
-        __syncthreads();
-        Acc c;
-        acc_zero(c);
-        tile_mma(c, ta, tb);
-        double* Gij = G + (int64_t)it * NB * ldg + jt * NB;
-        acc_for_each(c, [&](int r, int cc, double v) { Gij[(int64_t)r * ldg + cc] -= v; });
-        __syncthreads();
-      }
-    }
-  }
+  };
+  // ta holds C_ij (i > j): L_ij = C_ij L_jj^{-T} = C_ij X_jj^T
+  auto panel = [&](int i, int j) {
+    Acc o;
+    acc_zero(o);
+    tile_mma(o, ta, tx);
+    double* Gij = gtile(G, ldg, i, j);
+    acc_for_each(o, [&](int r, int c, double v) { Gij[(int64_t)r * ldg + c] = v; });
+    __syncthreads();
+  };
 
-  // Phase 2: U_ji = -(sum_{k=j}^{i-1} U_jk L_ik^T) U_ii for i > j.
-  for (int jt = 0; jt < nt; ++jt) {
-    for (int it = jt + 1; it < nt; ++it) {
-      Acc c;
-      acc_zero(c);
-      for (int kt = jt; kt < it; ++kt) {
-        load_tile(ta, U + (int64_t)jt * NB * ldg + kt * NB, ldg, false);  // ta = U_jk
-        load_tile(tb, G + (int64_t)it * NB * ldg + kt * NB, ldg, false);  // tb[c][k] = L_ik[c][k]
-        __syncthreads();
-        tile_mma(c, ta, tb);
-        __syncthreads();
-      }
-      acc_for_each(c, [&](int r, int cc, double v) { ta[r * LDT + cc] = v; });
-      load_tile(tb, U + (int64_t)it * NB * ldg + it * NB, ldg, true);  // tb[c][k] = U_ii[k][c]
-      __syncthreads();
-      Acc o;
-      acc_zero(o);
-      tile_mma(o, ta, tb);
-      double* Uji = U + (int64_t)jt * NB * ldg + it * NB;
-      acc_for_each(o, [&](int r, int cc, double v) { Uji[(int64_t)r * ldg + cc] = -v; });
-      __syncthreads();
-    }
+  // Phase 1, block column 0 (no updates)
+  load_tile(td, G, ldg, false);
+  __syncthreads();
+  diag(0);
+  for (int i = 1; i < nt; ++i) {
+    load_tile(ta, gtile(G, ldg, i, 0), ldg, false);
+    __syncthreads();
+    panel(i, 0);
   }
-
-  // Phase 3: G^{-1} = U U^T, tile (i, j) = sum_{k >= i} U_ik U_jk^T for i >= j.
-  for (int it = 0; it < nt; ++it) {
-    for (int jt = 0; jt <= it; ++jt) {
-      Acc c;
-      acc_zero(c);
-      for (int kt = it; kt < nt; ++kt) {
-        load_tile(ta, U + (int64_t)it * NB * ldg + kt * NB, ldg, false);  // ta = U_ik
-        load_tile(tb, U + (int64_t)jt * NB * ldg + kt * NB, ldg, false);  // tb[c][k] = U_jk[c][k]
-        __syncthreads();
-        tile_mma(c, ta, tb);
-        __syncthreads();
-      }
-      double* Gij = G + (int64_t)it * NB * ldg + jt * NB;
-      double* Gji = G + (int64_t)jt * NB * ldg + it * NB;
-      acc_for_each(c, [&](int r, int cc, double v) {
-        Gij[(int64_t)r * ldg + cc] = v;
-        if (jt != it) Gji[(int64_t)cc * ldg + r] = v;
-      });
-      __syncthreads();
-    }
-  }
+  // Phase 1, block columns 1 .. nt-1
+  chain_pipeline(ItChol{G, ldg, nt, 1, 1, 0}, ldg, ta, tb, [&](const ItChol& it, const Acc& c) {
+    const double* Gij = gtile(G, ldg, it.i, it.j);
+    double* dst = it.i == it.j ? td : ta;
+    acc_for_each(c, [&](int r, int cc, double v) { dst[r * LDT + cc] = Gij[(int64_t)r * ldg + cc] - v; });
+    __syncthreads();
+    if (it.i == it.j) diag(it.j);
+    else panel(it.i, it.j);
+  });
+  // Phase 2: U_ji = -S_ji U_ii = -S_ji X_ii^T
+  chain_pipeline(ItInv{U, G, ldg, nt, 0, 1, 0}, ldg, ta, tb, [&](const ItInv& it, const Acc& c) {
+    acc_for_each(c, [&](int r, int cc, double v) { ta[r * LDT + cc] = v; });
+    load_tile(tb, gtile(U, ldg, it.i, it.i - 1), ldg, false);
+    __syncthreads();
+    Acc o;
+    acc_zero(o);
+    tile_mma(o, ta, tb);
+    double* Uji = gtile(U, ldg, it.j, it.i);
+    acc_for_each(o, [&](int r, int cc, double v) { Uji[(int64_t)r * ldg + cc] = -v; });
+    __syncthreads();
+  });
+  // Phase 3: G^{-1} = U U^T, tile (i, j) and its transpose
+  chain_pipeline(ItLauum{U, ldg, nt, 0, 0, 0}, ldg, ta, tb, [&](const ItLauum& it, const Acc& c) {
+    double* Gij = gtile(G, ldg, it.i, it.j);
+    double* Gji = gtile(G, ldg, it.j, it.i);
+    const bool off = it.j != it.i;
+    acc_for_each(c, [&](int r, int cc, double v) {
+      Gij[(int64_t)r * ldg + cc] = v;
+      if (off) Gji[(int64_t)cc * ldg + r] = v;
+    });
+    __syncthreads();
+  });
 }
 
 template <typename ASV>
@@ -166,7 +248,8 @@ __global__ __launch_bounds__(kThreads) void k_chol_inverse(double* __restrict__ 
   double* ta = lds;                  // [64][65]
   double* tb = lds + NB * LDT;       // [64][65]
   double* td = lds + 2 * NB * LDT;   // [64][65]
-  double* col = lds + 3 * NB * LDT;  // [64]
+  double* tx = lds + 3 * NB * LDT;   // [64][65]
+  double* col = lds + 4 * NB * LDT;  // [64]
   __shared__ int bad;
   if (*done) return;
   const int tid = threadIdx.x;
@@ -196,7 +279,7 @@ __global__ __launch_bounds__(kThreads) void k_chol_inverse(double* __restrict__ 
   }
   __syncthreads();
 
-  factor_invert(G, U, ldg, ta, tb, td, col, &bad);
+  factor_invert(G, U, ldg, ta, tb, td, tx, col, &bad);
   if (tid == 0) status[slot] = bad;
 }
 
@@ -211,7 +294,8 @@ __global__ __launch_bounds__(kThreads) void k_chol_tab(const CholJob* __restrict
   double* ta = lds;
   double* tb = lds + NB * LDT;
   double* td = lds + 2 * NB * LDT;
-  double* col = lds + 3 * NB * LDT;
+  double* tx = lds + 3 * NB * LDT;
+  double* col = lds + 4 * NB * LDT;
   __shared__ int bad;
   const int tid = threadIdx.x;
   for (int32_t t = blockIdx.x; t < njobs; t += gridDim.x) {
@@ -239,7 +323,7 @@ __global__ __launch_bounds__(kThreads) void k_chol_tab(const CholJob* __restrict
       G[e] = v;
     }
     __syncthreads();
-    factor_invert(G, j.U, ldg, ta, tb, td, col, &bad);
+    factor_invert(G, j.U, ldg, ta, tb, td, tx, col, &bad);
     if (tid == 0 && bad) *j.status = 1;  // sticky until the host clears it
     __syncthreads();
   }
@@ -250,7 +334,7 @@ hipError_t chol_launch(double* G, double* W, int64_t ldg, int32_t tau, int32_t n
                        const ASV* AS, int64_t ldas, int64_t m, const int32_t* members,
                        const int32_t* offs, int32_t* status, const int32_t* done, hipStream_t s) {
   if (ldg % NB != 0) return hipErrorInvalidValue;
-  const size_t bytes = sizeof(double) * (3 * NB * LDT + NB);
+  const size_t bytes = sizeof(double) * (4 * NB * LDT + NB);
   hipError_t e = hipFuncSetAttribute((const void*)k_chol_inverse<ASV>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;
@@ -275,7 +359,7 @@ hipError_t launch_chol_inverse(double* G, double* W, int64_t ldg, int32_t tau, i
 hipError_t launch_chol_tab(const CholJob* jobs, int32_t njobs, int32_t grid, hipStream_t s) {
   if (njobs <= 0) return hipSuccess;
   grid = grid < 1 ? 1 : (grid > njobs ? njobs : grid);
-  const size_t bytes = sizeof(double) * (3 * NB * LDT + NB);
+  const size_t bytes = sizeof(double) * (4 * NB * LDT + NB);
   hipError_t e = hipFuncSetAttribute((const void*)k_chol_tab, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)bytes);
   if (e != hipSuccess) return e;
