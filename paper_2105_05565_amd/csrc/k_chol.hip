@@ -64,7 +64,9 @@ __device__ __forceinline__ double* gtile(double* base, int64_t ld, int i, int j)
 // registers. At the last step of a chain, epi(it, C) consumes the accumulator; it may use
 // ta and tb as scratch and must end with a workgroup barrier. The operands of a chain's
 // first step never depend on the epilogue of the chain before it (checked for each
-// phase's order where the iterator is defined).
+// phase's order where the iterator is defined). Before a long epilogue (it.long_epi(),
+// the diagonal factorisation) the next loads are issued after it instead: it is much
+// longer than their latency, and the staging registers stay free for it.
 template <class It, class Epi>
 __device__ __forceinline__ void chain_pipeline(It it, int64_t ld, double* ta, double* tb, Epi epi) {
   if (!it.valid()) return;
@@ -80,7 +82,8 @@ __device__ __forceinline__ void chain_pipeline(It it, int64_t ld, double* ta, do
     It nx = it;
     nx.advance();
     const bool more = nx.valid();
-    if (more) {
+    const bool early = more && !(it.last() && it.long_epi());
+    if (early) {
       tile_gload(ra, nx.a(), ld);
       tile_gload(rb, nx.b(), ld);
     }
@@ -91,6 +94,10 @@ __device__ __forceinline__ void chain_pipeline(It it, int64_t ld, double* ta, do
       acc_zero(c);
     }
     if (!more) break;
+    if (!early) {
+      tile_gload(ra, nx.a(), ld);
+      tile_gload(rb, nx.b(), ld);
+    }
     tile_lstore(ta, ra);
     tile_lstore(tb, rb);
     __syncthreads();
@@ -108,6 +115,7 @@ struct ItChol {
   __device__ const double* a() const { return gtile(G, ld, i, k); }
   __device__ const double* b() const { return gtile(G, ld, j, k); }
   __device__ bool last() const { return k == j - 1; }
+  __device__ bool long_epi() const { return i == j; }
   __device__ void advance() {
     if (++k < j) return;
     k = 0;
@@ -129,6 +137,7 @@ struct ItInv {
   __device__ const double* a() const { return gtile(U, ld, j, k); }
   __device__ const double* b() const { return gtile(G, ld, i, k); }
   __device__ bool last() const { return k == i - 1; }
+  __device__ bool long_epi() const { return false; }
   __device__ void advance() {
     if (++k < i) return;
     if (++i == nt) {
@@ -148,6 +157,7 @@ struct ItLauum {
   __device__ const double* a() const { return gtile(U, ld, i, k); }
   __device__ const double* b() const { return gtile(U, ld, j, k); }
   __device__ bool last() const { return k == nt - 1; }
+  __device__ bool long_epi() const { return false; }
   __device__ void advance() {
     if (++k < nt) return;
     if (++j > i) {

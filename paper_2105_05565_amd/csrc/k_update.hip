@@ -134,59 +134,101 @@ __global__ __launch_bounds__(kThreads) void k_delta(const double* __restrict__ r
   }
 }
 
-__device__ __forceinline__ double row_dot(const double* __restrict__ AS, int64_t j, int64_t ldas,
-                                          const double* dl, int lane) {
-  const double2* row = reinterpret_cast<const double2*>(AS + j * ldas);
-  const int half = (int)(ldas >> 1);
-  double s = 0.0;
-  for (int c2 = lane; c2 < half; c2 += 64) {
-    const double2 a = row[c2];
-    s += a.x * dl[2 * c2] + a.y * dl[2 * c2 + 1];
-  }
-  return s;
-}
-
-__device__ __forceinline__ double row_dot(const float* __restrict__ AS, int64_t j, int64_t ldas,
-                                          const double* dl, int lane) {
-  const float4* row = reinterpret_cast<const float4*>(AS + j * ldas);
-  const int quarter = (int)(ldas >> 2);
-  double s = 0.0;
-  for (int c4 = lane; c4 < quarter; c4 += 64) {
-    const float4 a = row[c4];
-    s += (double)a.x * dl[4 * c4] + (double)a.y * dl[4 * c4 + 1] + (double)a.z * dl[4 * c4 + 2] +
-         (double)a.w * dl[4 * c4 + 3];
-  }
-  return s;
-}
-
-// One row of the update, computed by one wave; returns r^{k+1}_j in every lane.
+// rows whose loads a wave issues before reducing any (FP64 rows: 2; FP32 rows: 1, within
+// the 64-VGPR budget of two workgroups per CU)
 template <typename ASV>
-__device__ __forceinline__ double update_row(int64_t j, const ASV* __restrict__ AS, int64_t ldas,
-                                             const double* dl, const int32_t* __restrict__ hmap,
-                                             const double* __restrict__ x, double* __restrict__ xo,
-                                             const double* __restrict__ r, double* __restrict__ ro,
-                                             double gamma, double beta, int lane) {
+struct RowsAtOnce {
+  static constexpr int value = sizeof(ASV) == 8 ? 2 : 1;
+};
+
+// sum_c AS[j_u][c] dl[c] for R rows (j_u < 0: none, 0 returned), partial per
+// lane: the loads of all rows are issued before the first product.
+template <int R>
+__device__ __forceinline__ void rows_dot(const double* __restrict__ AS, const int64_t (&j)[R], int64_t ldas,
+                                         const double* dl, int lane, double (&s)[R]) {
+  const int half = (int)(ldas >> 1);
+#pragma unroll
+  for (int u = 0; u < R; ++u) s[u] = 0.0;
+#pragma unroll 1
+  for (int c2 = lane; c2 < half; c2 += 64) {
+    double2 a[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+      a[u] = j[u] >= 0 ? reinterpret_cast<const double2*>(AS + j[u] * ldas)[c2] : make_double2(0.0, 0.0);
+    const double d0 = dl[2 * c2], d1 = dl[2 * c2 + 1];
+#pragma unroll
+    for (int u = 0; u < R; ++u) s[u] += a[u].x * d0 + a[u].y * d1;
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void rows_dot(const float* __restrict__ AS, const int64_t (&j)[R], int64_t ldas,
+                                         const double* dl, int lane, double (&s)[R]) {
+  const int quarter = (int)(ldas >> 2);
+#pragma unroll
+  for (int u = 0; u < R; ++u) s[u] = 0.0;
+#pragma unroll 1
+  for (int c4 = lane; c4 < quarter; c4 += 64) {
+    float4 a[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+      a[u] = j[u] >= 0 ? reinterpret_cast<const float4*>(AS + j[u] * ldas)[c4] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+      s[u] += (double)a[u].x * dl[4 * c4] + (double)a[u].y * dl[4 * c4 + 1] + (double)a[u].z * dl[4 * c4 + 2] +
+              (double)a[u].w * dl[4 * c4 + 3];
+  }
+}
+
+// Value of v in lane l (compile-time after unrolling), as a wave-uniform scalar.
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// Up to R rows of the update (j_u < 0: none), one wave: lane u loads and
+// updates row u, all rows' loads in flight together. Returns r^{k+1}_{j_u} (0 for none)
+// in every lane.
+template <typename ASV, int R>
+__device__ __forceinline__ void update_rows(const int64_t (&j)[R], const ASV* __restrict__ AS,
+                                            int64_t ldas, const double* dl, const int32_t* __restrict__ hmap,
+                                            const double* __restrict__ x, double* __restrict__ xo,
+                                            const double* __restrict__ r, double* __restrict__ ro,
+                                            double gamma, double beta, int lane, double (&rn)[R]) {
+  int64_t jl = -1;
+#pragma unroll
+  for (int u = 0; u < R; ++u)
+    if (lane == u) jl = j[u];
   int code = -1;
   double rj = 0.0, roj = 0.0, xj = 0.0, xoj = 0.0;
-  if (lane == 0) {  // issued ahead of the row so their latency overlaps the dot product
-    code = hmap[j];
-    rj = r[j];
-    roj = ro[j];
-    xj = x[j];
-    xoj = xo[j];
+  if (jl >= 0) {  // issued ahead of the products so their latency overlaps them
+    code = hmap[jl];
+    rj = r[jl];
+    roj = ro[jl];
+    xj = x[jl];
+    xoj = xo[jl];
   }
-  double s = wave_sum(row_dot(AS, j, ldas, dl, lane));
-  double rn = 0.0;
-  if (lane == 0) {
+  double s[R];
+  rows_dot(AS, j, ldas, dl, lane, s);
+  double sl = 0.0;
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const double t = wave_sum(s[u]);
+    if (lane == u) sl = t;
+  }
+  double rnl = 0.0;
+  if (jl >= 0) {
     double sd = 0.0;
     if (code >= 0) sd = (code & 1) ? -dl[code >> 1] : dl[code >> 1];
     const double onepb = 1.0 + beta;
-    rn = onepb * rj - beta * roj - gamma * s;
+    rnl = onepb * rj - beta * roj - gamma * sl;
     const double xn = onepb * xj - beta * xoj - gamma * sd;
-    ro[j] = rn;
-    xo[j] = xn;
+    ro[jl] = rnl;
+    xo[jl] = xn;
   }
-  return rn;
+#pragma unroll
+  for (int u = 0; u < R; ++u) rn[u] = lane_value(rnl, u);
 }
 
 template <typename ASV>
@@ -214,7 +256,10 @@ struct UpdateArgs {
 };
 
 template <typename ASV>
-__global__ __launch_bounds__(kUpdateThreads) void k_update(UpdateArgs<ASV> a) {
+// 8 waves per SIMD (at most 64 VGPRs): two workgroups per CU, also beside the
+// batch-preparation kernels of the next lookahead batch
+__global__ __launch_bounds__(kUpdateThreads, 8) void k_update(UpdateArgs<ASV> a) {
+  constexpr int R = RowsAtOnce<ASV>::value;
   extern __shared__ __align__(16) double dl[];  // [ldas]
   __shared__ double scratch[16];
   __shared__ double part[kBucketWaves];
@@ -226,14 +271,25 @@ __global__ __launch_bounds__(kUpdateThreads) void k_update(UpdateArgs<ASV> a) {
   if ((int)blockIdx.x < a.nbucket_blocks) {
     // bucket b of the next sketch: 8 waves share its members, in a fixed order
     const int b = blockIdx.x;
+    const int pe = a.offs_n[b + 1];
     double rs = 0.0;
-    for (int p = a.offs_n[b] + wave; p < a.offs_n[b + 1]; p += kBucketWaves) {
-      const int64_t j = a.members_n[p];
-      const double rn = update_row<ASV>(j, a.AS, a.ldas, dl, a.hmap, a.x, a.xo, a.r, a.ro, a.gamma,
-                                        a.beta, lane);
+    // members p = offs[b] + wave, + 16, ... in order, R of them per pass
+    for (int p0 = a.offs_n[b] + wave; p0 < pe; p0 += kBucketWaves * R) {
+      int64_t j[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const int p = p0 + u * kBucketWaves;
+        j[u] = p < pe ? (int64_t)a.members_n[p] : -1;
+      }
+      double rn[R];
+      update_rows<ASV, R>(j, a.AS, a.ldas, dl, a.hmap, a.x, a.xo, a.r, a.ro, a.gamma, a.beta, lane, rn);
       if (lane == 0) {
-        ss += rn * rn;
-        rs += (a.hmap_n[j] & 1) ? -rn : rn;
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+          if (j[u] >= 0) {
+            ss += rn[u] * rn[u];
+            rs += (a.hmap_n[j[u]] & 1) ? -rn[u] : rn[u];
+          }
       }
     }
     if (lane == 0) part[wave] = rs;
@@ -248,11 +304,20 @@ __global__ __launch_bounds__(kUpdateThreads) void k_update(UpdateArgs<ASV> a) {
     const int64_t blk = (int64_t)blockIdx.x - a.nbucket_blocks;
     const int64_t rows_per_block = (int64_t)(blockDim.x >> 6) * kRowsPerWave;
     const int64_t j0 = blk * rows_per_block, j1 = min(a.m, j0 + rows_per_block);
-    for (int64_t j = j0 + wave; j < j1; j += (blockDim.x >> 6)) {
-      if (a.hmap_n && a.hmap_n[j] >= 0) continue;
-      const double rn = update_row<ASV>(j, a.AS, a.ldas, dl, a.hmap, a.x, a.xo, a.r, a.ro, a.gamma,
-                                        a.beta, lane);
-      if (lane == 0) ss += rn * rn;
+    const int nw = blockDim.x >> 6;
+    for (int64_t jb = j0 + wave; jb < j1; jb += (int64_t)nw * R) {
+      int64_t j[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const int64_t jj = jb + (int64_t)u * nw;
+        j[u] = (jj < j1 && !(a.hmap_n && a.hmap_n[jj] >= 0)) ? jj : -1;
+      }
+      double rn[R];
+      update_rows<ASV, R>(j, a.AS, a.ldas, dl, a.hmap, a.x, a.xo, a.r, a.ro, a.gamma, a.beta, lane, rn);
+      if (lane == 0) {
+#pragma unroll
+        for (int u = 0; u < R; ++u) ss += rn[u] * rn[u];
+      }
     }
   }
   ss = block_sum(ss, scratch);
