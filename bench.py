@@ -61,9 +61,8 @@ def algorithmic_bytes(cls, wl, n, d, nnz, m, K, tau, nsel, a_nnz=0, slots=1):
     if cls == "as":
         if wl["kind"] == "csr" and a_nnz:
             # rows of A0 = Z Z^T (int32 column + FP64 value) read once per launch and shared by
-            # its sketches; per sketch the bucket map, AS written, the member rows of AS read
-            # back for G, and G written
-            return (a_nnz * 12 + (m + 1) * 8) / slots + m * 4 + 2 * m * tau * 8 + tau * tau * 8
+            # its sketches; per sketch the bucket map read and AS written (FP64)
+            return (a_nnz * 12 + (m + 1) * 8) / slots + m * 4 + m * tau * 8
         if wl["kind"] == "csr":
             # CSR of Z and of Z^T (FP32 value + int32 column each) read once, row pointers,
             # bucket map, AS written once (FP64), G = S^T A S written once (FP64)
@@ -71,6 +70,10 @@ def algorithmic_bytes(cls, wl, n, d, nnz, m, K, tau, nsel, a_nnz=0, slots=1):
         # dense subsample: Z read once (m x K) + gathered rows (tau x K) + AS written
         elt = 2 if wl["precision"] == "mixed" else 8
         return m * K * elt + tau * K * elt + m * tau * (4 if wl["precision"] == "mixed" else 8)
+    if cls == "g":
+        # G = S^T AS from the member rows of AS (FP64), their bucket codes and indices, the
+        # bucket offsets; G written
+        return nsel * tau * 8 + nsel * (4 + 4) + (tau + 1) * 4 + tau * tau * 8
     if cls == "update":
         # AS read, bucket map, x^k, x^{k-1}, r^k, r^{k-1} read, two vectors written, delta
         return m * tau * (4 if wl["precision"] == "mixed" else 8) + m * 4 + 4 * m * 8 + 2 * m * 8 + tau * 8
@@ -132,9 +135,9 @@ def kernel_table(prof, wl, workload, n, d, nnz, m, K, nsel, total, a_nnz=0):
     dom = max((c for c in kernels if c != "iters"), key=lambda c: kernels[c]["total_ms"])
     kd = kernels[dom]
     achieved = kd["gbs"]
-    as_name = ("k_as_arows+k_g_from_as" if a_nnz else "k_as_sparse_bucket") if wl["kind"] == "csr" \
+    as_name = ("k_as_arows_lds" if a_nnz else "k_as_sparse_bucket") if wl["kind"] == "csr" \
         else "k_as_dense_f64"
-    roofline = {"kernel": {"as": as_name,
+    roofline = {"kernel": {"as": as_name, "g": "k_g_from_as",
                            "update": "k_update", "chol": "k_chol_inverse", "delta": "k_delta",
                            "iters": "k_delta+k_update sequence",
                            "sketch": "k_sketch_count" if wl["sketch"] == "count" else "k_sketch_select"}[dom],
@@ -154,7 +157,8 @@ def kernel_table(prof, wl, workload, n, d, nnz, m, K, nsel, total, a_nnz=0):
     if os.path.exists(traffic_file):
         tf = json.load(open(traffic_file))
         src = {"k_as_sparse_bucket": ["k_sparse.hip"], "k_update": ["k_update.hip"],
-               "k_as_dense_f64": ["k_dense.hip"], "k_as_arows+k_g_from_as": ["k_sparse_a.hip"]
+               "k_as_dense_f64": ["k_dense.hip"], "k_as_arows_lds": ["k_sparse_a.hip"],
+               "k_g_from_as": ["k_sparse_a.hip"]
                }.get(roofline["kernel"], [])
         if src and tf.get("source_sha") == kernel_source_sha(src):
             roofline["traffic"] = tf["hbm_bytes_per_launch_scaled"] * kd["slots_per_launch"] / tf["slots_per_launch"]
@@ -325,8 +329,9 @@ def main_learned(args):
         U.reset(sd)
         _, _, rep = U.solve()
         tr_iters.append(rep.iters)
-        if sd % 25 == 0:
-            print(f"[bench] trace solve {sd}/{args.train_solves}", file=sys.stderr, flush=True)
+        if sd % max(1, args.train_solves // 20) == 0:
+            print(f"[bench] trace solve {sd}/{args.train_solves}: {rep.iters} iterations", file=sys.stderr,
+                  flush=True)
     T = rs.Trainer(tau, init_seed=1)
     T.add_traces(U)
     records = T.records

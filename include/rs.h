@@ -144,12 +144,13 @@ typedef struct rs_report {
 
 /* Per-kernel timing collected with HIP events on the solver's stream (indices
  * RS_PROF_*). rs_options.profile = 1 times each batch-level launch (sketch, AS,
- * Cholesky) and the whole per-iteration sequence of a batch (RS_PROF_ITERS);
+ * Cholesky; RS_PROF_G: the separate G = S^T AS pass of the CSR route through the rows
+ * of Z Z^T) and the whole per-iteration sequence of a batch (RS_PROF_ITERS);
  * profile = 2 also times every per-iteration launch (delta, update), which adds
  * event packets between them. `launches` counts timed launches (or sequences),
  * `slots` the sketches (iterations) they processed. */
 enum { RS_PROF_SKETCH = 0, RS_PROF_AS = 1, RS_PROF_CHOL = 2, RS_PROF_DELTA = 3, RS_PROF_UPDATE = 4,
-       RS_PROF_REFRESH = 5, RS_PROF_ITERS = 6, RS_PROF_COUNT = 8 };
+       RS_PROF_REFRESH = 5, RS_PROF_ITERS = 6, RS_PROF_G = 7, RS_PROF_COUNT = 8 };
 typedef struct rs_profile {
   double ms[RS_PROF_COUNT];
   int64_t launches[RS_PROF_COUNT];

@@ -9,9 +9,9 @@
 // (r = Z (Z^T x) + lambda x - b for x^k and x^{k-1}).
 //
 // GEMM tiling (gfx950): 256 x 256 output tile per workgroup, 8 waves each owning a
-// 64 x 128 sub-tile (2 x 4 MFMA blocks of 32 x 32), K staged 64 at a time through
-// double-buffered LDS (rows padded by 16 bytes against bank conflicts). Tiles are
-// ordered so that the workgroups one XCD runs together share row strips of Z and
+// 64 x 128 sub-tile (2 x 4 MFMA blocks of 32 x 32), K staged 32 at a time through a
+// four-stage LDS ring filled by direct-to-LDS loads (XOR-swizzled 64-byte rows). Tiles
+// are ordered so that the workgroups one XCD runs together share row strips of Z and
 // gathered column strips (workgroups are dispatched to the 8 XCDs round-robin).
 #include "dev_common.h"
 #include "rs_internal.h"
@@ -22,8 +22,7 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int kBM = 256, kBN = 256, kBK = 64;
-constexpr int kLdsRow = kBK + 8;  // bf16 elements per LDS row (64 + 8 padding)
+constexpr int kBM = 256, kBN = 256;
 constexpr int kGemmThreads = 512;
 constexpr int kXcds = 8;
 constexpr int kGroupRows = 4;  // row tiles per tile group (XCD-local reuse of Z strips)
@@ -73,7 +72,7 @@ __global__ void k_cast_bf16(const void* __restrict__ src, int32_t is_f32, int64_
 }
 
 struct GemmArgs {
-  const uint16_t* Z;   // m x ldz BF16 bits, zero padded to a multiple of kBK
+  const uint16_t* Z;   // m x ldz BF16 bits, zero padded to a multiple of 64
   int64_t ldz, m, kpad;
   const int32_t* members;  // [slots][tau]
   int32_t tau;
@@ -100,111 +99,8 @@ __device__ __forceinline__ void tile_of_block(const GemmArgs& a, int bid, int* r
   *ct = idx / rows_in_group;
 }
 
-__global__ __launch_bounds__(kGemmThreads) void k_as_dense_bf16(GemmArgs a) {
-  extern __shared__ __align__(16) uint16_t smem[];  // [2][kBM + kBN][kLdsRow]
-  __shared__ int64_t brow[kBN];
-  if (*a.done) return;
-  int rt, ct;
-  tile_of_block(a, blockIdx.x, &rt, &ct);
-  if (rt < 0) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t row0 = (int64_t)rt * kBM, n0 = (int64_t)ct * kBN;
-  if (tid < kBN) {
-    const int64_t n = n0 + tid;
-    brow[tid] = n < a.ntot ? (int64_t)a.members[n] : -1;
-  }
-  __syncthreads();
-
-  // global -> LDS staging: 512 rows (256 of Z, 256 gathered) x 64 BF16 = 8 x 16 B each;
-  // thread t loads rows (t >> 3) + 64 i, 16-byte segment (t & 7).
-  const int seg = tid & 7, rbase = tid >> 3;
-  const uint4* srcp[8];
-  bool valid[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int r = rbase + 64 * i;  // 0..511
-    int64_t grow;
-    if (r < kBM) {
-      grow = row0 + r;
-      valid[i] = grow < a.m;
-    } else {
-      grow = brow[r - kBM];
-      valid[i] = grow >= 0;
-    }
-    srcp[i] = reinterpret_cast<const uint4*>(a.Z + (valid[i] ? grow : 0) * a.ldz) + seg;
-  }
-  uint4 stage[8];
-  auto gload = [&](int64_t kk) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-      stage[i] = valid[i] ? srcp[i][kk / 8] : make_uint4(0u, 0u, 0u, 0u);
-  };
-  auto lstore = [&](int buf) {
-    uint16_t* base = smem + (size_t)buf * (kBM + kBN) * kLdsRow;
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-      *reinterpret_cast<uint4*>(base + (rbase + 64 * i) * kLdsRow + seg * 8) = stage[i];
-  };
-
-  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 128;
-  f32x16 acc[2][4];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
-
-  const int64_t nk = a.kpad / kBK;
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  const int l32 = lane & 31, khalf = (lane >> 5) * 8;
-  for (int64_t kt = 0; kt < nk; ++kt) {
-    const int buf = (int)(kt & 1);
-    if (kt + 1 < nk) gload((kt + 1) * kBK);
-    const uint16_t* As = smem + (size_t)buf * (kBM + kBN) * kLdsRow;
-    const uint16_t* Bs = As + kBM * kLdsRow;
-#pragma unroll
-    for (int ks = 0; ks < kBK; ks += 16) {
-      bf16x8 av[2], bv[4];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-        av[i] = *reinterpret_cast<const bf16x8*>(As + (wr + i * 32 + l32) * kLdsRow + ks + khalf);
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        bv[j] = *reinterpret_cast<const bf16x8*>(Bs + (wc + j * 32 + l32) * kLdsRow + ks + khalf);
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
-    }
-    if (kt + 1 < nk) lstore(buf ^ 1);
-    __syncthreads();
-  }
-
-  // 32x32x16 result layout: lane l, element v -> row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t row = row0 + wr + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        const int col = wc + j * 32 + l32;
-        const int64_t n = n0 + col;
-        if (row < a.m && n < a.ntot) {
-          const int64_t slot = n / a.tau, c = n % a.tau;
-          float val = acc[i][j][v];
-          if (row == brow[col]) val = (float)((double)val + a.lam);
-          a.AS[(slot * a.m + row) * a.ldas + c] = val;
-        }
-      }
-}
-
-// Same product with the operand tiles moved from global memory straight into LDS
-// (global_load_lds_dwordx4, 16 bytes per lane, no register staging), 32 deep in K per
+// AS for a batch of subsample sketches: operand tiles move from global memory straight into
+// LDS (global_load_lds_dwordx4, 16 bytes per lane, no register staging), 32 deep in K per
 // stage and four LDS stages, so three stages of loads stay in flight while one is
 // multiplied. A DMA instruction fills 1 KB of LDS: 16 rows of 64 bytes, lane L taking
 // row L / 4 and 16-byte slot L % 4. The slot of a row's logical segment t is
@@ -225,7 +121,7 @@ __device__ __forceinline__ void dma_wait_barrier() {
   __builtin_amdgcn_sched_barrier(0);
 }
 
-__global__ __launch_bounds__(kGemmThreads) void k_as_dense_bf16_dma(GemmArgs a) {
+__global__ __launch_bounds__(kGemmThreads) void k_as_dense_bf16(GemmArgs a) {
   extern __shared__ __align__(16) unsigned char dsm[];  // [kDmaStages][512 rows][64 B]
   __shared__ int64_t brow[kBN];
   if (*a.done) return;
@@ -454,7 +350,7 @@ hipError_t launch_cast_bf16(const void* src, int32_t src_is_f32, int64_t rows_s,
 hipError_t launch_as_dense_bf16(const uint16_t* Zbf, int64_t ldz, int64_t m, int64_t kpad,
                                 const int32_t* members, int32_t tau, int64_t ldas, int32_t nslots,
                                 double lam, float* AS, const int32_t* done, hipStream_t s) {
-  if (kpad % kBK != 0 || ldz % 8 != 0) return hipErrorInvalidValue;
+  if (kpad % kDmaBK != 0 || ldz % 8 != 0) return hipErrorInvalidValue;
   GemmArgs a;
   a.Z = Zbf;
   a.ldz = ldz;
@@ -471,17 +367,9 @@ hipError_t launch_as_dense_bf16(const uint16_t* Zbf, int64_t ldz, int64_t m, int
   a.done = done;
   const int ntiles = a.n_row_tiles * a.n_col_tiles;
   const int per = (ntiles + kXcds - 1) / kXcds;
-  if (kpad % kDmaBK == 0) {
-    const size_t bytes = (size_t)kDmaStages * kDmaStageBytes;
-    hipError_t e = hipFuncSetAttribute((const void*)k_as_dense_bf16_dma,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_as_dense_bf16_dma, dim3(per * kXcds), dim3(kGemmThreads), bytes, s, a);
-    return hipGetLastError();
-  }
-  const size_t bytes = sizeof(uint16_t) * 2 * (kBM + kBN) * kLdsRow;
-  hipError_t e = hipFuncSetAttribute((const void*)k_as_dense_bf16,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  const size_t bytes = (size_t)kDmaStages * kDmaStageBytes;
+  hipError_t e = hipFuncSetAttribute((const void*)k_as_dense_bf16, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)bytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_as_dense_bf16, dim3(per * kXcds), dim3(kGemmThreads), bytes, s, a);
   return hipGetLastError();

@@ -329,9 +329,8 @@ hipError_t build_zzt(const int64_t* zt_ptr, const int32_t* zt_col, const void* z
 }
 
 hipError_t launch_as_arows(const int64_t* a_ptr, const int32_t* a_col, const double* a_val, int64_t m,
-                           int32_t tau, int64_t ldas, int32_t nslots, double lam, const int32_t* hmap,
-                           const int32_t* members, const int32_t* offs, int64_t nsel, double* AS, double* G,
-                           int64_t ldg, const int32_t* done, hipStream_t s) {
+                           int32_t tau, int64_t ldas, int32_t nslots, double lam, const int32_t* hmap, double* AS,
+                           const int32_t* done, hipStream_t s) {
   hipError_t e;
   const size_t lds = arows_lds_bytes(m, tau);
   if (tau < 16383 && lds <= 96 * 1024) {
@@ -350,7 +349,12 @@ hipError_t launch_as_arows(const int64_t* a_ptr, const int32_t* a_col, const dou
     e = arows_launch<8>(a_ptr, a_col, a_val, m, tau, ldas, nslots, lam, hmap, AS, done, s);
   else
     return hipErrorInvalidValue;
-  if (e != hipSuccess) return e;
+  return e;
+}
+
+hipError_t launch_g_from_as(const double* AS, int64_t m, int32_t tau, int64_t ldas, int32_t nslots,
+                            const int32_t* hmap, const int32_t* members, const int32_t* offs, int64_t nsel,
+                            double* G, int64_t ldg, const int32_t* done, hipStream_t s) {
   hipLaunchKernelGGL(k_g_from_as, dim3(tau, nslots), dim3(256), 0, s, AS, m, tau, ldas, hmap, members, offs,
                      nsel, G, ldg, done);
   return hipGetLastError();

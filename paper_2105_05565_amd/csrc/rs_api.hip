@@ -302,8 +302,13 @@ void prep_batch(rs_handle* h, int p, int64_t k0, int nb, hipStream_t s) {
   pe = prof_begin(h, RS_PROF_AS, nb, 1, s);
   if (h->arows) {
     check_hip(launch_as_arows(h->a_ptr, h->a_col, h->a_val, h->m, h->tau, h->ldas, nb, h->lam, bs.hmap,
-                              bs.members, bs.offs, h->nsel, (double*)bs.AS, bs.G, h->ldg, done, s),
+                              (double*)bs.AS, done, s),
               "AS (rows of Z Z^T)");
+    prof_end(h, pe, s);
+    pe = prof_begin(h, RS_PROF_G, nb, 1, s);
+    check_hip(launch_g_from_as((const double*)bs.AS, h->m, h->tau, h->ldas, nb, bs.hmap, bs.members, bs.offs,
+                               h->nsel, bs.G, h->ldg, done, s),
+              "G = S^T AS");
   } else if (h->sparse) {
     check_hip(launch_as_sparse(h->zr_ptr, h->zr_col, h->zr_val, h->zt_ptr, h->zt_col, h->zt_val,
                                h->vals_f32, h->nnz, h->m, h->tau, h->ldas, nb, h->kind, h->lam,
@@ -470,19 +475,20 @@ void advance(rs_handle* h, int64_t iters) {
   int p = h->cur_set;
   int nb = 0;
   bool prepared = false;  // set p holds the batch that starts at k_enq (nb sketches)
+  // With the pipeline every preparation, also one that was not queued ahead, runs on
+  // prep_stream: preparations share scratch buffers and must not overlap each other.
+  hipStream_t ps = pipe ? h->prep_stream : h->stream;
   if (pipe && left > 0 && !h->done) {
     // the first preparation follows what the caller queued on the solver's stream
     check_hip(hipEventRecord(h->ev_start, h->stream), "event");
     check_hip(hipStreamWaitEvent(h->prep_stream, h->ev_start, 0), "wait");
-    nb = batch_size(h, left, k_enq, k_a, rel_a, k_b, rel_b);
-    prep_batch(h, p, k_enq, nb, h->prep_stream);
-    prepared = true;
   }
   while (left > 0 && !h->done) {
     if (!prepared) {
       nb = batch_size(h, left, k_enq, k_a, rel_a, k_b, rel_b);
-      prep_batch(h, p, k_enq, nb, h->stream);
-    } else {
+      prep_batch(h, p, k_enq, nb, ps);
+    }
+    if (pipe) {
       check_hip(hipEventRecord(h->ev_ready[p], h->prep_stream), "event");
       check_hip(hipStreamWaitEvent(h->stream, h->ev_ready[p], 0), "wait");
     }
@@ -496,7 +502,7 @@ void advance(rs_handle* h, int64_t iters) {
     // batch prepared after the wait is a short one.
     if (pipe && left > 0 && predicted_need(h, k_enq, k_a, rel_a, k_b, rel_b) > 0.25 * nb) {
       nb_next = batch_size(h, left, k_enq, k_a, rel_a, k_b, rel_b);
-      prep_batch(h, 1 - p, k_enq, nb_next, h->prep_stream);
+      prep_batch(h, 1 - p, k_enq, nb_next, ps);
       prepared = true;
     }
     if (left == 0) {
@@ -882,9 +888,9 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
       }
     }
     if (o->profile) {
-      // sketch, AS, Cholesky of this batch and of the one prepared ahead, the iteration
+      // sketch, AS, G, Cholesky of this batch and of the one prepared ahead, the iteration
       // sequence; delta, update and refresh per iteration
-      const int pairs = 7 + 3 * B + 2;
+      const int pairs = 9 + 3 * B + 2;
       h->ev.resize(2 * pairs);
       h->ev_cls.resize(pairs);
       h->ev_slots.resize(pairs);

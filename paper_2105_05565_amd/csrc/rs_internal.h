@@ -115,9 +115,11 @@ hipError_t build_zzt(const int64_t* zt_ptr, const int32_t* zt_col, const void* z
                      int64_t K, int64_t m, int64_t npairs, int64_t** a_ptr, int32_t** a_col, double** a_val,
                      int64_t* a_nnz, hipStream_t s);
 hipError_t launch_as_arows(const int64_t* a_ptr, const int32_t* a_col, const double* a_val, int64_t m,
-                           int32_t tau, int64_t ldas, int32_t nslots, double lam, const int32_t* hmap,
-                           const int32_t* members, const int32_t* offs, int64_t nsel, double* AS, double* G,
-                           int64_t ldg, const int32_t* done, hipStream_t s);
+                           int32_t tau, int64_t ldas, int32_t nslots, double lam, const int32_t* hmap, double* AS,
+                           const int32_t* done, hipStream_t s);
+hipError_t launch_g_from_as(const double* AS, int64_t m, int32_t tau, int64_t ldas, int32_t nslots,
+                            const int32_t* hmap, const int32_t* members, const int32_t* offs, int64_t nsel,
+                            double* G, int64_t ldg, const int32_t* done, hipStream_t s);
 
 // Grouped count-sketch products (batched solves; CSR values held in FP64): per job,
 // T = Z^T S into tbuf (nnz * sparse_entry_bytes_f64() bytes), then AS (m x tau) and

@@ -81,9 +81,10 @@ class rs_tuning(ctypes.Structure):
                 ("sparse_ms", ctypes.c_double), ("chol_ms", ctypes.c_double)]
 
 
-RS_PROF_SKETCH, RS_PROF_AS, RS_PROF_CHOL, RS_PROF_DELTA, RS_PROF_UPDATE, RS_PROF_REFRESH, RS_PROF_ITERS = range(7)
+RS_PROF_SKETCH, RS_PROF_AS, RS_PROF_CHOL, RS_PROF_DELTA, RS_PROF_UPDATE, RS_PROF_REFRESH, RS_PROF_ITERS, \
+    RS_PROF_G = range(8)
 RS_PROF_COUNT = 8
-PROF_NAMES = ["sketch", "as", "chol", "delta", "update", "refresh", "iters"]
+PROF_NAMES = ["sketch", "as", "chol", "delta", "update", "refresh", "iters", "g"]
 
 
 class rs_profile(ctypes.Structure):
