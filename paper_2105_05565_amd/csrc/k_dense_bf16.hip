@@ -172,33 +172,53 @@ __global__ __launch_bounds__(kGemmThreads) void k_as_dense_bf16(GemmArgs a) {
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
   const int l32 = lane & 31, khi = lane >> 5;
 
+  // fragments of one 16-deep K step: rows of the A strip (2) and of the gathered B strip (4)
+  auto read_frags = [&](const unsigned char* st, int ks, bf16x8 (&av)[2], bf16x8 (&bv)[4]) {
+    const int t = (ks >> 3) + khi;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int r = wr + i * 32 + l32;
+      av[i] = *reinterpret_cast<const bf16x8*>(st + r * kDmaRowBytes + ((t ^ ((r >> 2) & 3)) << 4));
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = kBM + wc + j * 32 + l32;
+      bv[j] = *reinterpret_cast<const bf16x8*>(st + r * kDmaRowBytes + ((t ^ ((r >> 2) & 3)) << 4));
+    }
+  };
+  auto mma = [&](const bf16x8 (&av)[2], const bf16x8 (&bv)[4]) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+  };
+  auto stage = [&](int64_t kt) { return dsm + (size_t)(kt & (kDmaStages - 1)) * kDmaStageBytes; };
+
+  // Stage kt holds K elements 32 kt .. 32 kt + 31 (two 16-deep steps). The fragments of a
+  // step are read while the MFMAs of the step before run; the barrier that hands over the
+  // next stage comes after this wave's reads of the current stage have landed, so that the
+  // refill issued right after it (into the current stage's buffer) cannot overtake them.
   issue(0);
   issue(1);
   issue(2);
+  dma_wait_barrier();  // stage 0 landed everywhere
+  issue(3);
+  bf16x8 a0[2], b0[4], a1[2], b1[4];
+  read_frags(stage(0), 0, a0, b0);
+  // The body is the same on the last pass (its refill reloads the last stage and its reads
+  // of stage nk go unused), so that no branch joins in-flight LDS reads of different ages.
   for (int64_t kt = 0; kt < nk; ++kt) {
-    dma_wait_barrier();
-    issue(kt + 3);  // into the stage every wave finished reading before the barrier
-    const unsigned char* st = dsm + (size_t)(kt & (kDmaStages - 1)) * kDmaStageBytes;
-#pragma unroll
-    for (int ks = 0; ks < kDmaBK; ks += 16) {
-      const int t = (ks >> 3) + khi;
-      bf16x8 av[2], bv[4];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int r = wr + i * 32 + l32;
-        av[i] = *reinterpret_cast<const bf16x8*>(st + r * kDmaRowBytes + ((t ^ ((r >> 2) & 3)) << 4));
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int r = kBM + wc + j * 32 + l32;
-        bv[j] = *reinterpret_cast<const bf16x8*>(st + r * kDmaRowBytes + ((t ^ ((r >> 2) & 3)) << 4));
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
-    }
+    read_frags(stage(kt), 16, a1, b1);
+    mma(a0, b0);
+    // this wave's reads of stage kt done, stage kt + 1 landed (at most two later stages, 8
+    // DMA instructions, in flight), then every wave
+    __builtin_amdgcn_s_waitcnt(0x0078);  // vmcnt(8), lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+    issue(kt + 4);  // into the buffer of stage kt, which no wave reads any more
+    read_frags(stage(kt + 1), 0, a0, b0);
+    mma(a1, b1);
   }
   // no DMA may still be writing this workgroup's LDS when it exits
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
