@@ -12,7 +12,9 @@
 // 64 x 128 sub-tile (2 x 4 MFMA blocks of 32 x 32), K staged 32 at a time through a
 // four-stage LDS ring filled by direct-to-LDS loads (XOR-swizzled 64-byte rows). Tiles
 // are ordered so that the workgroups one XCD runs together share row strips of Z and
-// gathered column strips (workgroups are dispatched to the 8 XCDs round-robin).
+// gathered column strips (workgroups are dispatched to the 8 XCDs round-robin). The
+// kernel is written for any even wave count; two 4-wave workgroups per CU (128 x 256
+// tiles, three stages each) measured 25-30% slower on the mixed workload.
 #include "dev_common.h"
 #include "rs_internal.h"
 
@@ -22,8 +24,7 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int kBM = 256, kBN = 256;
-constexpr int kGemmThreads = 512;
+constexpr int kBN = 256;  // gathered columns (sketch coordinates) per output tile
 constexpr int kXcds = 8;
 constexpr int kGroupRows = 4;  // row tiles per tile group (XCD-local reuse of Z strips)
 
@@ -107,59 +108,66 @@ __device__ __forceinline__ void tile_of_block(const GemmArgs& a, int bid, int* r
 // t ^ ((row / 4) % 4), which keeps the 16 rows read by a quarter wave on distinct banks.
 // Rows outside the matrix load row 0 (their results are not stored).
 constexpr int kDmaBK = 32;                    // K elements per stage
-constexpr int kDmaStages = 4;
 constexpr int kDmaRowBytes = kDmaBK * 2;      // 64
-constexpr int kDmaStageBytes = (kBM + kBN) * kDmaRowBytes;  // 32 KB
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 
-__device__ __forceinline__ void dma_wait_barrier() {
-  // every load of the stage about to be read has landed: at most two later stages
-  // (8 DMA instructions per wave) may still be in flight
-  __builtin_amdgcn_s_waitcnt(0x0F78);  // vmcnt(8), expcnt and lgkmcnt not waited on
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_sched_barrier(0);
-}
+// s_waitcnt immediate (gfx9 layout): vmcnt <= n, expcnt not waited on, lgkmcnt <= lgkm
+constexpr int waitcnt_imm(int n, int lgkm) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (lgkm << 8); }
 
-__global__ __launch_bounds__(kGemmThreads) void k_as_dense_bf16(GemmArgs a) {
-  extern __shared__ __align__(16) unsigned char dsm[];  // [kDmaStages][512 rows][64 B]
+// AS for a batch of subsample sketches, one BM x 256 output tile per workgroup of WAVES
+// waves (BM = 32 WAVES; each wave owns 64 x 128 as 2 x 4 MFMA blocks of 32 x 32). Operand
+// rows (BM of Z, 256 gathered) move from global memory straight into LDS
+// (global_load_lds_dwordx4, 16 bytes per lane), 32 deep in K per stage, STAGES stages, so
+// STAGES - 1 stages of loads are in flight while one is multiplied. A DMA instruction fills
+// 1 KB: 16 rows of 64 bytes, lane L taking row L / 4 and slot L % 4; the slot of a row's
+// logical segment t is t ^ ((row / 4) % 4), which keeps the 16 rows read by a quarter wave
+// on distinct banks. Rows outside the matrix load row 0 (their results are not stored).
+template <int WAVES, int STAGES>
+__global__ __launch_bounds__(WAVES * 64, 2) void k_as_dense_bf16(GemmArgs a) {
+  constexpr int BM = 32 * WAVES, ROWS = BM + kBN;
+  constexpr int NQ = ROWS / (16 * WAVES);             // DMA instructions per wave and stage
+  constexpr int STAGE_BYTES = ROWS * kDmaRowBytes;
+  constexpr int INFLIGHT = (STAGES - 2) * NQ;         // later stages' loads a wait leaves in flight
+  extern __shared__ __align__(16) unsigned char dsm[];  // [STAGES][ROWS][64 B]
   __shared__ int64_t brow[kBN];
   if (*a.done) return;
   int rt, ct;
   tile_of_block(a, blockIdx.x, &rt, &ct);
   if (rt < 0) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t row0 = (int64_t)rt * kBM, n0 = (int64_t)ct * kBN;
-  if (tid < kBN) {
-    const int64_t n = n0 + tid;
-    brow[tid] = n < a.ntot ? (int64_t)a.members[n] : -1;
+  const int64_t row0 = (int64_t)rt * BM, n0 = (int64_t)ct * kBN;
+  for (int c = tid; c < kBN; c += WAVES * 64) {
+    const int64_t n = n0 + c;
+    brow[c] = n < a.ntot ? (int64_t)a.members[n] : -1;
   }
   __syncthreads();
 
-  // this lane's source rows for the wave's 4 DMA instructions of a stage
-  const unsigned char* src[4];
+  // this lane's source rows for the wave's NQ DMA instructions of a stage
+  const unsigned char* src[NQ];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int r = (wave * 4 + q) * 16 + (lane >> 2);  // tile row 0..511
+  for (int q = 0; q < NQ; ++q) {
+    const int r = (wave * NQ + q) * 16 + (lane >> 2);  // tile row 0 .. ROWS - 1
     int64_t g;
-    if (r < kBM) {
+    if (r < BM) {
       g = row0 + r;
       if (g >= a.m) g = 0;
     } else {
-      g = brow[r - kBM];
+      g = brow[r - BM];
       if (g < 0) g = 0;
     }
     const int t = (lane & 3) ^ ((r >> 2) & 3);  // logical 16-byte segment stored in this slot
     src[q] = reinterpret_cast<const unsigned char*>(a.Z + g * a.ldz) + t * 16;
   }
   const int64_t nk = a.kpad / kDmaBK;
+  auto stage = [&](int64_t kt) { return dsm + (size_t)(kt % STAGES) * STAGE_BYTES; };
   auto issue = [&](int64_t kt) {
     const int64_t ktl = kt < nk ? kt : nk - 1;  // past the end: reload the last stage
-    unsigned char* dst = dsm + (size_t)(kt & (kDmaStages - 1)) * kDmaStageBytes;
+    unsigned char* dst = stage(kt);
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < NQ; ++q)
       __builtin_amdgcn_global_load_lds((const void*)(src[q] + ktl * kDmaRowBytes),
-                                       (lds_void_t*)(dst + (wave * 4 + q) * 16 * kDmaRowBytes), 16, 0, 0);
+                                       (lds_void_t*)(dst + (wave * NQ + q) * 16 * kDmaRowBytes), 16, 0, 0);
   };
 
   const int wr = (wave >> 1) * 64, wc = (wave & 1) * 128;
@@ -182,7 +190,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_as_dense_bf16(GemmArgs a) {
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int r = kBM + wc + j * 32 + l32;
+      const int r = BM + wc + j * 32 + l32;
       bv[j] = *reinterpret_cast<const bf16x8*>(st + r * kDmaRowBytes + ((t ^ ((r >> 2) & 3)) << 4));
     }
   };
@@ -193,17 +201,17 @@ __global__ __launch_bounds__(kGemmThreads) void k_as_dense_bf16(GemmArgs a) {
       for (int j = 0; j < 4; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
   };
-  auto stage = [&](int64_t kt) { return dsm + (size_t)(kt & (kDmaStages - 1)) * kDmaStageBytes; };
 
   // Stage kt holds K elements 32 kt .. 32 kt + 31 (two 16-deep steps). The fragments of a
   // step are read while the MFMAs of the step before run; the barrier that hands over the
   // next stage comes after this wave's reads of the current stage have landed, so that the
   // refill issued right after it (into the current stage's buffer) cannot overtake them.
-  issue(0);
-  issue(1);
-  issue(2);
-  dma_wait_barrier();  // stage 0 landed everywhere
-  issue(3);
+#pragma unroll
+  for (int q = 0; q + 1 < STAGES; ++q) issue(q);
+  __builtin_amdgcn_s_waitcnt(waitcnt_imm(INFLIGHT, 15));  // stage 0 landed
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_sched_barrier(0);
+  issue(STAGES - 1);
   bf16x8 a0[2], b0[4], a1[2], b1[4];
   read_frags(stage(0), 0, a0, b0);
   // The body is the same on the last pass (its refill reloads the last stage and its reads
@@ -211,17 +219,16 @@ __global__ __launch_bounds__(kGemmThreads) void k_as_dense_bf16(GemmArgs a) {
   for (int64_t kt = 0; kt < nk; ++kt) {
     read_frags(stage(kt), 16, a1, b1);
     mma(a0, b0);
-    // this wave's reads of stage kt done, stage kt + 1 landed (at most two later stages, 8
-    // DMA instructions, in flight), then every wave
-    __builtin_amdgcn_s_waitcnt(0x0078);  // vmcnt(8), lgkmcnt(0)
+    // this wave's reads of stage kt done, stage kt + 1 landed, then every wave
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(INFLIGHT, 0));
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_sched_barrier(0);
-    issue(kt + 4);  // into the buffer of stage kt, which no wave reads any more
+    issue(kt + STAGES);  // into the buffer of stage kt, which no wave reads any more
     read_frags(stage(kt + 1), 0, a0, b0);
     mma(a1, b1);
   }
   // no DMA may still be writing this workgroup's LDS when it exits
-  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+  __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));
   __builtin_amdgcn_s_barrier();
 
   // 32x32x16 result layout: lane l, element v -> row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32
@@ -242,6 +249,9 @@ __global__ __launch_bounds__(kGemmThreads) void k_as_dense_bf16(GemmArgs a) {
         }
       }
 }
+
+// Shape of the product launch: WAVES waves per workgroup, STAGES LDS stages.
+constexpr int kGemmWaves = 8, kGemmStages = 4;
 
 constexpr int kRefreshSplit = 32;  // row ranges of Z summed separately in Z^T x
 
@@ -382,16 +392,17 @@ hipError_t launch_as_dense_bf16(const uint16_t* Zbf, int64_t ldz, int64_t m, int
   a.ldas = ldas;
   a.lam = lam;
   a.AS = AS;
-  a.n_row_tiles = (int32_t)((m + kBM - 1) / kBM);
+  constexpr int BM = 32 * kGemmWaves;
+  a.n_row_tiles = (int32_t)((m + BM - 1) / BM);
   a.n_col_tiles = (int32_t)((a.ntot + kBN - 1) / kBN);
   a.done = done;
   const int ntiles = a.n_row_tiles * a.n_col_tiles;
   const int per = (ntiles + kXcds - 1) / kXcds;
-  const size_t bytes = (size_t)kDmaStages * kDmaStageBytes;
-  hipError_t e = hipFuncSetAttribute((const void*)k_as_dense_bf16, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)bytes);
+  const size_t bytes = (size_t)kGemmStages * (BM + kBN) * kDmaRowBytes;
+  auto kern = k_as_dense_bf16<kGemmWaves, kGemmStages>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_as_dense_bf16, dim3(per * kXcds), dim3(kGemmThreads), bytes, s, a);
+  hipLaunchKernelGGL(kern, dim3(per * kXcds), dim3(kGemmWaves * 64), bytes, s, a);
   return hipGetLastError();
 }
 
