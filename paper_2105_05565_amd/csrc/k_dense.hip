@@ -91,6 +91,132 @@ __device__ __forceinline__ void as_dense_tile(const double* __restrict__ Z, int6
   __syncthreads();  // brow is rewritten by the next tile of a persistent workgroup
 }
 
+// 128 x 128 tile of AS on 4 waves (each 64 x 64 as 4 x 4 FP64 MFMA blocks of 16 x 16):
+// twice the flops per staged byte of the 64 x 64 tile. The next 16-deep K panel of both
+// operands is loaded into registers (16-byte loads when rows are 16-byte aligned) while
+// the current one is multiplied from LDS.
+constexpr int kBT = 128, kBK = 16;
+struct DenseLds128 {
+  double As[kBT][kBK + 1];
+  double Bs[kBT][kBK + 1];
+  int64_t brow[kBT];
+};
+
+__device__ __forceinline__ void as_dense_tile128(const double* __restrict__ Z, int64_t ldz, int64_t m,
+                                                 int64_t K, const int32_t* __restrict__ members,
+                                                 int32_t tau, int64_t ntot, int64_t ldas, double lam,
+                                                 double* __restrict__ AS, int64_t row0, int64_t n0,
+                                                 DenseLds128& L) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+  if (tid < kBT) {
+    const int64_t n = n0 + tid;
+    L.brow[tid] = n < ntot ? (int64_t)members[n] : -1;  // members is [slot][tau]
+  }
+  __syncthreads();
+  d4v acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
+
+  // element pair e = tid + 256 u (u < 4) of a 128 x 16 panel: row e / 8, columns 2 (e % 8) + {0, 1}
+  const bool vec = (ldz & 1) == 0;
+  int64_t arow[4], brw[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int r = (tid + 256 * u) >> 3;
+    arow[u] = row0 + r < m ? row0 + r : -1;
+    brw[u] = L.brow[r];
+  }
+  const int kc = 2 * (tid & 7);
+  double2 ra[4], rb[4];
+  auto gload = [&](int64_t kk) {
+    const int64_t k = kk + kc;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
+      if (vec && k + 1 < K) {
+        if (arow[u] >= 0) va = *reinterpret_cast<const double2*>(Z + arow[u] * ldz + k);
+        if (brw[u] >= 0) vb = *reinterpret_cast<const double2*>(Z + brw[u] * ldz + k);
+      } else {
+        if (arow[u] >= 0 && k < K) va.x = Z[arow[u] * ldz + k];
+        if (arow[u] >= 0 && k + 1 < K) va.y = Z[arow[u] * ldz + k + 1];
+        if (brw[u] >= 0 && k < K) vb.x = Z[brw[u] * ldz + k];
+        if (brw[u] >= 0 && k + 1 < K) vb.y = Z[brw[u] * ldz + k + 1];
+      }
+      ra[u] = va;
+      rb[u] = vb;
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = (tid + 256 * u) >> 3;
+      L.As[r][kc] = ra[u].x;
+      L.As[r][kc + 1] = ra[u].y;
+      L.Bs[r][kc] = rb[u].x;
+      L.Bs[r][kc + 1] = rb[u].y;
+    }
+  };
+  gload(0);
+  lstore();
+  __syncthreads();
+  for (int64_t kk = 0; kk < K; kk += kBK) {
+    const bool more = kk + kBK < K;
+    if (more) gload(kk + kBK);
+#pragma unroll
+    for (int k4 = 0; k4 < kBK; k4 += 4) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = L.As[wr + i * 16 + (lane & 15)][k4 + (lane >> 4)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = L.Bs[wc + j * 16 + (lane & 15)][k4 + (lane >> 4)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+    if (more) {
+      lstore();
+      __syncthreads();
+    }
+  }
+
+  // D layout of the 16x16x4 FP64 MFMA: lane l, element v -> row 4 v + l / 16, column l % 16.
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = row0 + wr + i * 16 + v * 4 + (lane >> 4);
+        const int col = wc + j * 16 + (lane & 15);
+        const int64_t n = n0 + col;
+        if (row < m && n < ntot) {
+          const int64_t slot = n / tau, c = n % tau;
+          double val = acc[i][j][v];
+          if (row == L.brow[col]) val += lam;
+          AS[(slot * m + row) * ldas + c] = val;
+        }
+      }
+  __syncthreads();  // brow is rewritten by the next tile of a persistent workgroup
+}
+
+__global__ __launch_bounds__(256, 2) void k_as_dense_f64_128(const double* __restrict__ Z, int64_t ldz,
+                                                             int64_t m, int64_t K,
+                                                             const int32_t* __restrict__ members,
+                                                             int32_t tau, int64_t ldas, int32_t nslots,
+                                                             double lam, double* __restrict__ AS,
+                                                             const int32_t* __restrict__ done) {
+  __shared__ DenseLds128 L;
+  if (*done) return;
+  as_dense_tile128(Z, ldz, m, K, members, tau, (int64_t)nslots * tau, ldas, lam, AS,
+                   (int64_t)blockIdx.x * kBT, (int64_t)blockIdx.y * kBT, L);
+}
+
 __global__ __launch_bounds__(256) void k_as_dense_f64(const double* __restrict__ Z, int64_t ldz,
                                                       int64_t m, int64_t K,
                                                       const int32_t* __restrict__ members,
@@ -182,8 +308,8 @@ hipError_t launch_as_dense_f64(const double* Z, int64_t ldz, int64_t m, int64_t 
                                const int32_t* members, int32_t tau, int64_t ldas, int32_t nslots,
                                double lam, double* AS, const int32_t* done, hipStream_t s) {
   const int64_t ntot = (int64_t)nslots * tau;
-  dim3 grid((unsigned)((m + kTM - 1) / kTM), (unsigned)((ntot + kTN - 1) / kTN));
-  hipLaunchKernelGGL(k_as_dense_f64, grid, dim3(256), 0, s, Z, ldz, m, K, members, tau, ldas,
+  dim3 grid((unsigned)((m + kBT - 1) / kBT), (unsigned)((ntot + kBT - 1) / kBT));
+  hipLaunchKernelGGL(k_as_dense_f64_128, grid, dim3(256), 0, s, Z, ldz, m, K, members, tau, ldas,
                      nslots, lam, AS, done);
   return hipGetLastError();
 }
