@@ -335,7 +335,7 @@ typedef struct rs_batch_problem_info_t {
 
 typedef struct rs_tuning {
   int32_t tuned;            /* 1 when the shapes below were chosen by timing */
-  int32_t dense_tk;         /* K-panel depth of the dense product tiles (16 or 32) */
+  int32_t dense_tk;         /* K-panel depth of the dense product tiles (128 x 128 tiles; 16) */
   int32_t dense_wg_per_cu, sparse_wg_per_cu, chol_wg_per_cu;  /* persistent grid sizes */
   int32_t graph_iters;      /* iterations per graph replay */
   int32_t compute_units;

@@ -12,85 +12,6 @@ namespace {
 
 typedef double d4v __attribute__((ext_vector_type(4)));
 
-constexpr int kTM = 64, kTN = 64;
-
-// One 64 x 64 tile of AS (rows row0.., columns n0.. of the ntot = slots * tau columns).
-// TK: depth of the K panel staged in LDS per step.
-template <int TK>
-struct DenseLds {
-  double As[kTM][TK + 1];
-  double Bs[kTN][TK + 1];
-  int64_t brow[kTN];
-};
-
-template <int TK>
-__device__ __forceinline__ void as_dense_tile(const double* __restrict__ Z, int64_t ldz, int64_t m,
-                                              int64_t K, const int32_t* __restrict__ members,
-                                              int32_t tau, int64_t ntot, int64_t ldas, double lam,
-                                              double* __restrict__ AS, int64_t row0, int64_t n0,
-                                              DenseLds<TK>& L) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  if (tid < kTN) {
-    const int64_t n = n0 + tid;
-    L.brow[tid] = n < ntot ? (int64_t)members[n] : -1;  // members is [slot][tau]
-  }
-  __syncthreads();
-
-  d4v acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
-
-  constexpr int kPer = TK / 4;  // K elements loaded per thread and operand
-  const int lr = tid >> 2, lk = (tid & 3) * kPer;
-  const int64_t arow = row0 + lr;
-  const int64_t brw = L.brow[lr];
-  for (int64_t kk = 0; kk < K; kk += TK) {
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int64_t kidx = kk + lk + q;
-      L.As[lr][lk + q] = (arow < m && kidx < K) ? Z[arow * ldz + kidx] : 0.0;
-      L.Bs[lr][lk + q] = (brw >= 0 && kidx < K) ? Z[brw * ldz + kidx] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k4 = 0; k4 < TK; k4 += 4) {
-      double a[2], b[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = L.As[wr + i * 16 + (lane & 15)][k4 + (lane >> 4)];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = L.Bs[wc + j * 16 + (lane & 15)][k4 + (lane >> 4)];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
-    __syncthreads();
-  }
-
-  // D layout of the 16x16x4 FP64 MFMA: lane l, element v -> row 4 v + l / 16, column l % 16.
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t row = row0 + wr + i * 16 + v * 4 + (lane >> 4);
-        const int col = wc + j * 16 + (lane & 15);
-        const int64_t n = n0 + col;
-        if (row < m && n < ntot) {
-          const int64_t slot = n / tau, c = n % tau;
-          double val = acc[i][j][v];
-          if (row == L.brow[col]) val += lam;
-          AS[(slot * m + row) * ldas + c] = val;
-        }
-      }
-  __syncthreads();  // brow is rewritten by the next tile of a persistent workgroup
-}
-
 // 128 x 128 tile of AS on 4 waves (each 64 x 64 as 4 x 4 FP64 MFMA blocks of 16 x 16):
 // twice the flops per staged byte of the 64 x 64 tile. The next 16-deep K panel of both
 // operands is loaded into registers (16-byte loads when rows are 16-byte aligned) while
@@ -217,32 +138,18 @@ __global__ __launch_bounds__(256, 2) void k_as_dense_f64_128(const double* __res
                    (int64_t)blockIdx.x * kBT, (int64_t)blockIdx.y * kBT, L);
 }
 
-__global__ __launch_bounds__(256) void k_as_dense_f64(const double* __restrict__ Z, int64_t ldz,
-                                                      int64_t m, int64_t K,
-                                                      const int32_t* __restrict__ members,
-                                                      int32_t tau, int64_t ldas, int32_t nslots,
-                                                      double lam,
-                                                      double* __restrict__ AS,
-                                                      const int32_t* __restrict__ done) {
-  __shared__ DenseLds<16> L;
-  if (*done) return;
-  as_dense_tile<16>(Z, ldz, m, K, members, tau, (int64_t)nslots * tau, ldas, lam, AS,
-                    (int64_t)blockIdx.x * kTM, (int64_t)blockIdx.y * kTN, L);
-}
-
-// Grouped form over a ragged table of (job, row tile, column tile) entries; a fixed
-// grid of workgroups strides over the table (persistent launch).
-template <int TK>
-__global__ __launch_bounds__(256) void k_as_dense_f64_tab(const DenseJob* __restrict__ jobs,
-                                                          const DenseTile* __restrict__ tiles,
-                                                          int32_t ntiles) {
-  __shared__ DenseLds<TK> L;
+// Grouped form over a ragged table of (job, 128-row tile, 128-column tile) entries; a
+// fixed grid of workgroups strides over the table (persistent launch).
+__global__ __launch_bounds__(256, 2) void k_as_dense_f64_tab(const DenseJob* __restrict__ jobs,
+                                                             const DenseTile* __restrict__ tiles,
+                                                             int32_t ntiles) {
+  __shared__ DenseLds128 L;
   for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const DenseTile tl = tiles[t];
     const DenseJob& j = jobs[tl.job];
     if (*j.done) continue;  // uniform across the workgroup
-    as_dense_tile<TK>(j.Z, j.ldz, j.m, j.K, j.members, j.tau, j.tau, j.ldas, j.lam, j.AS,
-                      (int64_t)tl.tm * kTM, (int64_t)tl.tn * kTN, L);
+    as_dense_tile128(j.Z, j.ldz, j.m, j.K, j.members, j.tau, j.tau, j.ldas, j.lam, j.AS,
+                     (int64_t)tl.tm * kBT, (int64_t)tl.tn * kBT, L);
   }
 }
 
@@ -359,12 +266,8 @@ hipError_t launch_as_dense_f64_tab(const DenseJob* jobs, const DenseTile* tiles,
                                    int32_t tk, int32_t grid, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   grid = grid < 1 ? 1 : (grid > ntiles ? ntiles : grid);
-  if (tk == 32)
-    hipLaunchKernelGGL(k_as_dense_f64_tab<32>, dim3(grid), dim3(256), 0, s, jobs, tiles, ntiles);
-  else if (tk == 16)
-    hipLaunchKernelGGL(k_as_dense_f64_tab<16>, dim3(grid), dim3(256), 0, s, jobs, tiles, ntiles);
-  else
-    return hipErrorInvalidValue;
+  if (tk != kBK) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_as_dense_f64_tab, dim3(grid), dim3(256), 0, s, jobs, tiles, ntiles);
   return hipGetLastError();
 }
 

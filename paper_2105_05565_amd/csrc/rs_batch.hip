@@ -380,7 +380,7 @@ void autotune(rs_batch* B) {
   Tuning t = B->tune;
   if (B->n_dtiles) {
     float best = 1e30f;
-    for (int tk : {16, 32})
+    for (int tk : {16})  // the product's K-panel depth (fixed)
       for (int mult : {1, 2, 4, 8}) {
         const float ms = time_launch(B, [&] {
           check_hip(launch_as_dense_f64_tab(B->djobs, B->dtiles, B->n_dtiles, tk, mult * B->cus, s), "tune");
@@ -615,8 +615,9 @@ rs_status rs_batch_create(int32_t count, const rs_problem* problems, const rs_op
         DenseJob j{q.Z, q.K, m, q.K, members, q.tau, q.ldas, 0.0, BS, st.inactive};
         const int jid = (int)dj.size();
         dj.push_back(j);
-        for (int tn = 0; tn < (q.tau + 63) / 64; ++tn)
-          for (int tm = 0; tm < q.ntiles; ++tm) dt.push_back(DenseTile{jid, tm, tn});
+        // 128 x 128 product tiles (the kernel's unit)
+        for (int tn = 0; tn < (q.tau + 127) / 128; ++tn)
+          for (int tm = 0; tm < (int)((m + 127) / 128); ++tm) dt.push_back(DenseTile{jid, tm, tn});
       } else {
         cnt.push_back(a);
         B->lds_cnt = std::max(B->lds_cnt, sketch_lds_bytes(kCount, q.tau, nsel));
