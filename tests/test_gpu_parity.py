@@ -125,6 +125,14 @@ def test_dense_subsample_trajectory(momentum, form):
     _trajectory_check(p.X, p.y, p.lam, form=form, kind="subsample", tau=tau, momentum=momentum)
 
 
+@pytest.mark.parametrize("n,d,tau", [(301, 130, 37), (701, 300, 150)])
+def test_dense_subsample_trajectory_ragged_tiles(n, d, tau):
+    # K = n odd: rows of Z are not 16-byte aligned (element-wise panel loads); m = 300 and
+    # tau = 150 leave partial 128 x 128 product tiles in both directions
+    p = _dense(n, d, 0.05, seed=n)
+    _trajectory_check(p.X, p.y, p.lam, form="primal", kind="subsample", tau=tau, momentum="heuristic")
+
+
 def test_dense_subsample_trajectory_f32_colmajor_input():
     p = _dense(260, 70, 0.2, seed=9)
     Xf = np.asfortranarray(p.X.astype(np.float32))
