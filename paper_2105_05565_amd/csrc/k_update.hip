@@ -21,7 +21,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kDeltaRows = 4;       // rows of G^{-1} per k_delta workgroup (one per wave)
-constexpr int kBucketWaves = 16;    // waves per bucket in the bucket-major update
+constexpr int kBucketWaves = 8;     // waves per bucket in the bucket-major update (and in k_rho)
 constexpr int kUpdateThreads = 64 * kBucketWaves;
 constexpr int kRowsPerWave = 4;     // rows per wave in the row-range update
 
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kThreads) void k_norm0(const double* __restrict__ p
 }
 
 // rho[b] = sum_{p in bucket b} s_{members[p]} r[members[p]]: wave w of the bucket's
-// workgroup sums p = offs[b] + w, + 16, ... in order; waves are combined in order
+// workgroup sums p = offs[b] + w, + kBucketWaves, ... in order; waves are combined in order
 // (the bucket-major update uses the same order).
 __global__ __launch_bounds__(kBucketWaves * 64) void k_rho(const double* __restrict__ r,
                                                            const int32_t* __restrict__ hmap,
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(kUpdateThreads, 8) void k_update(UpdateArgs<ASV> a)
     const int b = blockIdx.x;
     const int pe = a.offs_n[b + 1];
     double rs = 0.0;
-    // members p = offs[b] + wave, + 16, ... in order, R of them per pass
+    // members p = offs[b] + wave, + kBucketWaves, ... in order, R of them per pass
     for (int p0 = a.offs_n[b] + wave; p0 < pe; p0 += kBucketWaves * R) {
       int64_t j[R];
 #pragma unroll
