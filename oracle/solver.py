@@ -25,6 +25,16 @@ Momentum schedules:
   capped at beta_max. eta = 0.995 and beta_max = 0.5 by default: the paper
   fixes neither for this rule, but says beta_k rises from 0 to about 0.5.
   The operations are evaluated in exactly this order in FP64.
+* "theory": the increasing-momentum rule of eq:parameterswitchtheory in the
+  iterate-averaging parameters of Thm 6.2: eta_k = eta (0.995) before the switch
+  and 1 from it on, zeta_k = (1 / eta_k) sum_{t<k} eta_t (1 - eta_t)
+  (eq:zeta_kaptheo, zeta_0 = 0), gamma_k = eta_k / (zeta_{k+1} + 1) and
+  beta_k = zeta_k / (zeta_{k+1} + 1) (eq:etalambdatogammbetagen). The paper
+  switches when beta_k reaches 0.5, but beta_k itself depends on eta_{k+1}; the
+  switch index K is read as the first k at which the constant-eta momentum of
+  Cor 6.3 (eq:cst_eta_lambda_to_gamma_beta_formula) reaches beta_max (0.5), so that
+  the schedule is a function of k alone. With eta = 0.995, K = 201 and gamma_k,
+  beta_k settle at 0.5 from there on. The sum is min(k, K) * (eta (1 - eta)).
 
 Part of the oracle: test infrastructure only.
 """
@@ -42,7 +52,7 @@ class Options:
     sketch: str = "subsample"       # subsample | count | subcount | weighted
     tau: int = 50
     sum_size: int = 0               # SubCount k; 0 = the paper's rule
-    momentum: str = "none"          # none | constant | heuristic
+    momentum: str = "none"          # none | constant | heuristic | theory
     eta: float = 0.995
     beta_max: float = 0.5
     gamma_const: float = 1.0
@@ -66,7 +76,39 @@ def schedule(opts, k):
         denom = denom + 1.0
         beta = 1.0 - (2.0 - eta) / denom
         return 1.0, min(float(opts.beta_max), beta)
+    if opts.momentum == "theory":
+        eta = float(opts.eta)
+        K = theory_switch(eta, float(opts.beta_max))
+        c = eta * (1.0 - eta)
+        eta_k = eta if k < K else 1.0
+        eta_k1 = eta if k + 1 < K else 1.0
+        zeta_k = float(min(k, K)) * c / eta_k
+        zeta_k1 = float(min(k + 1, K)) * c / eta_k1
+        return eta_k / (zeta_k1 + 1.0), zeta_k / (zeta_k1 + 1.0)
     raise ValueError(f"unknown momentum {opts.momentum!r}")
+
+
+SWITCH_NEVER = 1 << 40
+
+
+def theory_switch(eta, threshold):
+    """First k at which beta_k = 1 - (2 - eta) / ((k+1)(1 - eta) + 1), the constant-eta
+    momentum of Cor 6.3, reaches threshold; SWITCH_NEVER when it never does."""
+    if not (eta < 1.0) or not (threshold < 1.0):
+        return SWITCH_NEVER
+    def reached(k):
+        denom = float(k + 1) * (1.0 - eta)
+        denom = denom + 1.0
+        return 1.0 - (2.0 - eta) / denom >= threshold
+
+    # (k+1)(1 - eta) + 1 >= (2 - eta) / (1 - threshold) gives a start near K; beta_k
+    # increases with k, so step down while the threshold is already reached, then up
+    k = max(0, int(((2.0 - eta) / (1.0 - threshold) - 1.0) / (1.0 - eta)) - 3)
+    while k > 0 and reached(k - 1):
+        k -= 1
+    while not reached(k):
+        k += 1
+    return k
 
 
 @dataclass
