@@ -4,7 +4,8 @@
 A step is one full solve (x^0 = 0 until ||r^k|| / ||r^0|| <= 1e-6) of the sparse
 workload: CSR X 100000 x 20000 with 0.1% uniform nonzeros (FP32 values N(0,1)),
 y = X w* + 0.01 noise, lambda = 1e-3, primal form, count sketch tau = 500,
-heuristic momentum, FP64 arithmetic. Every step uses a new sketch seed
+heuristic momentum (--momentum theory: the increasing rule of Sec. 6), FP64
+arithmetic. Every step uses a new sketch seed
 (seed = step index + 1); the data and its device layouts stay resident in HBM.
 
 Prints one JSON line with the metric, a roofline entry for the kernel that
@@ -94,7 +95,7 @@ def make_problem(wl):
     return getattr(inputs, wl["gen"])()
 
 
-def cpu_baseline(p, wl, gpu_iters_median, sample_s):
+def cpu_baseline(p, wl, gpu_iters_median, sample_s, momentum="heuristic"):
     """The oracle, single-threaded, on the first iterations of the seed-1 solve."""
     from threadpoolctl import threadpool_limits
 
@@ -103,7 +104,7 @@ def cpu_baseline(p, wl, gpu_iters_median, sample_s):
     with threadpool_limits(limits=1):
         system = ridge_system(p.X, p.y, p.lam, "primal")
         st = init_state(system)
-        opts = Options(sketch=wl["sketch"], tau=wl["tau"], sum_size=wl["sub_k"], momentum="heuristic",
+        opts = Options(sketch=wl["sketch"], tau=wl["tau"], sum_size=wl["sub_k"], momentum=momentum,
                        seed=1, tol=1e-6)
         t0 = time.perf_counter()
         while (st.k == 0 or time.perf_counter() - t0 < sample_s) and st.history[-1] > 1e-6:
@@ -136,7 +137,7 @@ def kernel_table(prof, wl, workload, n, d, nnz, m, K, nsel, total, a_nnz=0):
     kd = kernels[dom]
     achieved = kd["gbs"]
     as_name = ("k_as_arows_lds" if a_nnz else "k_as_sparse_bucket") if wl["kind"] == "csr" \
-        else "k_as_dense_f64"
+        else "k_as_dense_f64_128"
     roofline = {"kernel": {"as": as_name, "g": "k_g_from_as",
                            "update": "k_update", "chol": "k_chol_inverse", "delta": "k_delta",
                            "iters": "k_delta+k_update sequence",
@@ -148,7 +149,7 @@ def kernel_table(prof, wl, workload, n, d, nnz, m, K, nsel, total, a_nnz=0):
         flops = 2.0 * m * wl["tau"] * K * kd["slots_per_launch"]
         tfs = flops / (kd["avg_ms"] * 1e-3) / 1e12
         peak = BF16_PEAK_TFS if wl["precision"] == "mixed" else FP64_PEAK_TFS
-        roofline.update({"kernel": "k_as_dense_bf16" if wl["precision"] == "mixed" else "k_as_dense_f64",
+        roofline.update({"kernel": "k_as_dense_bf16" if wl["precision"] == "mixed" else "k_as_dense_f64_128",
                          "bound": "mfma", "achieved": round(tfs, 1), "peak": peak, "unit": "TFLOP/s",
                          "frac": round(tfs / peak, 4), "alg_flops_per_launch": flops,
                          "hbm_gbs_algorithmic": kd["gbs"]})
@@ -157,7 +158,7 @@ def kernel_table(prof, wl, workload, n, d, nnz, m, K, nsel, total, a_nnz=0):
     if os.path.exists(traffic_file):
         tf = json.load(open(traffic_file))
         src = {"k_as_sparse_bucket": ["k_sparse.hip"], "k_update": ["k_update.hip"],
-               "k_as_dense_f64": ["k_dense.hip"], "k_as_arows_lds": ["k_sparse_a.hip"],
+               "k_as_dense_f64_128": ["k_dense.hip"], "k_as_arows_lds": ["k_sparse_a.hip"],
                "k_g_from_as": ["k_sparse_a.hip"]
                }.get(roofline["kernel"], [])
         if src and tf.get("source_sha") == kernel_source_sha(src):
@@ -186,7 +187,8 @@ def main_batched(args):
     probs = inputs.batched(scale=args.scale)
     stream = torch.cuda.current_stream().cuda_stream
     t0 = time.perf_counter()
-    B = rs.Batch(probs, tol=1e-6, seed=1, autotune=True, stream=stream, max_iter=args.max_iter)
+    B = rs.Batch(probs, tol=1e-6, seed=1, autotune=True, stream=stream, max_iter=args.max_iter,
+                 momentum=args.momentum)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     tune = B.tuning()
@@ -233,7 +235,7 @@ def main_batched(args):
         pr = probs[p]
         S = rs.Solver(pr["X"], pr["y"][:, 0], float(pr["lambdas"][8]), tau=pr["tau"],
                       sketch="subsample" if pr["kind"] == "dense" else "count", tol=0.0, seed=1,
-                      problem_id=p, max_iter=1000000, stream=stream)
+                      problem_id=p, max_iter=1000000, stream=stream, momentum=args.momentum)
         S.step(8)
         torch.cuda.synchronize()
         ts = time.perf_counter()
@@ -255,7 +257,7 @@ def main_batched(args):
         "config": {"workload": wl["name"], "problems": len(probs), "lambdas": 16, "rhs": 4,
                    "solves": n_solves, "dense": sum(pr["kind"] == "dense" for pr in probs),
                    "tau_rule": "64 round(m^(2/3) / 64) clamped to [64, 512]", "cap": "50 m / tau",
-                   "tol": 1e-6, "momentum": "heuristic", "graph_iters": tune["graph_iters"]},
+                   "tol": 1e-6, "momentum": args.momentum, "graph_iters": tune["graph_iters"]},
         "converged_fraction": round(statistics.median(conv), 4),
         "lock_step_iters_median": statistics.median(steps_k),
         "solve_iterations": solve_iters,
@@ -283,7 +285,7 @@ def main_batched(args):
                 system = ridge_system(pr["X"], pr["y"][:, 0], float(pr["lambdas"][8]))
                 st = init_state(system)
                 opts = Options(sketch="subsample" if pr["kind"] == "dense" else "count", tau=pr["tau"],
-                               momentum="heuristic", seed=1, problem_id=p, tol=0.0)
+                               momentum=args.momentum, seed=1, problem_id=p, tol=0.0)
                 ts = time.perf_counter()
                 while st.k == 0 or (time.perf_counter() - ts < args.cpu_sample_s / 2 and st.k < 50):
                     step(system, st, opts)
@@ -432,6 +434,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sparse_count", choices=sorted(WORKLOADS))
     ap.add_argument("--lookahead", type=int, default=0)
+    ap.add_argument("--momentum", default="heuristic", choices=["heuristic", "theory", "none"],
+                    help="momentum schedule (the learned-sampler workload keeps the heuristic one)")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="prepare each lookahead batch on the solver's stream (no overlap with iterating)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -492,7 +496,7 @@ def main():
     torch.cuda.synchronize()
 
     t0 = time.perf_counter()
-    S = rs.Solver(X, y, p.lam, tau=wl["tau"], sketch=wl["sketch"], form="primal", momentum="heuristic",
+    S = rs.Solver(X, y, p.lam, tau=wl["tau"], sketch=wl["sketch"], form="primal", momentum=args.momentum,
                   subcount_k=wl["sub_k"], tol=1e-6, max_iter=args.max_iter, seed=1,
                   precision=wl["precision"], lookahead=args.lookahead, profile=1, stream=stream,
                   sparse_route=args.sparse_route, pipeline=not args.no_pipeline)
@@ -527,7 +531,7 @@ def main():
     S.close()
 
     # one more solve, untimed, with every launch bracketed by events (per-launch breakdown)
-    S2 = rs.Solver(X, y, p.lam, tau=wl["tau"], sketch=wl["sketch"], form="primal", momentum="heuristic",
+    S2 = rs.Solver(X, y, p.lam, tau=wl["tau"], sketch=wl["sketch"], form="primal", momentum=args.momentum,
                    subcount_k=wl["sub_k"], tol=1e-6, max_iter=args.max_iter, seed=1,
                    precision=wl["precision"], lookahead=args.lookahead, profile=2, stream=stream,
                    sparse_route=args.sparse_route, pipeline=not args.no_pipeline)
@@ -547,7 +551,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["name"], "n": n, "d": d, "nnz": nnz, "form": "primal",
                    "sketch": wl["sketch"], "tau": wl["tau"], "subcount_k": wl["sub_k"],
-                   "lambda": p.lam, "momentum": "heuristic", "tol": 1e-6,
+                   "lambda": p.lam, "momentum": args.momentum, "tol": 1e-6,
                    "precision": wl["precision"], "max_iter": args.max_iter,
                    "sparse_route": {0: None, 1: "scatter", 2: "arows"}[route],
                    "a_nnz": a_nnz or None,
@@ -564,7 +568,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        cb = cpu_baseline(p, wl, statistics.median(iters), args.cpu_sample_s)
+        cb = cpu_baseline(p, wl, statistics.median(iters), args.cpu_sample_s, args.momentum)
         cb.pop("s_per_iter")
         out["cpu_baseline"] = cb
     print(json.dumps(out))

@@ -76,8 +76,16 @@ enum { RS_SKETCH_SUBSAMPLE = 0, RS_SKETCH_COUNT = 1, RS_SKETCH_SUBCOUNT = 2 };
  *  NONE      gamma = 1, beta = 0 (Alg. 1)
  *  CONSTANT  gamma = opts.gamma, beta = opts.beta (0.5 in the paper's comparison)
  *  HEURISTIC gamma = 1, beta_k = min(beta_max, 1 - (2 - eta) / ((k+1)(1 - eta) + 1))
- *            (eq:parametersheurististic) */
-enum { RS_MOMENTUM_NONE = 0, RS_MOMENTUM_CONSTANT = 1, RS_MOMENTUM_HEURISTIC = 2 };
+ *            (eq:parametersheurististic)
+ *  THEORY    increasing momentum of eq:parameterswitchtheory in the iterate-averaging
+ *            parameters of Thm 6.2: eta_k = opts.eta before the switch and 1 from it on,
+ *            zeta_k = (1 / eta_k) sum_{t<k} eta_t (1 - eta_t) (eq:zeta_kaptheo),
+ *            gamma_k = eta_k / (zeta_{k+1} + 1), beta_k = zeta_k / (zeta_{k+1} + 1)
+ *            (eq:etalambdatogammbetagen). The switch is the first k at which the
+ *            constant-eta momentum of Cor 6.3, 1 - (2 - eta) / ((k+1)(1 - eta) + 1),
+ *            reaches opts.beta_max (k = 201 for eta 0.995, beta_max 0.5); no switch when
+ *            eta >= 1 or beta_max >= 1. Needs 0 < eta <= 1 (RS_EINVAL otherwise). */
+enum { RS_MOMENTUM_NONE = 0, RS_MOMENTUM_CONSTANT = 1, RS_MOMENTUM_HEURISTIC = 2, RS_MOMENTUM_THEORY = 3 };
 /* Arithmetic of the AS products: FP64 throughout, or BF16 products with FP32
  * accumulation and an FP64 Cholesky plus a periodic FP64 residual refresh. */
 enum { RS_PREC_FP64 = 0, RS_PREC_MIXED_BF16 = 1 };
@@ -91,7 +99,7 @@ typedef struct rs_options {
   int32_t momentum;         /* RS_MOMENTUM_* */
   int32_t precision;        /* RS_PREC_* */
   double gamma, beta;       /* CONSTANT schedule */
-  double eta, beta_max;     /* HEURISTIC schedule (defaults 0.995, 0.5) */
+  double eta, beta_max;     /* HEURISTIC and THEORY schedules (defaults 0.995, 0.5) */
   double tol;               /* stop when ||r^k|| / ||r^0|| <= tol (default 1e-6) */
   int64_t max_iter;         /* iteration cap (default 100000) */
   uint64_t seed;            /* Philox key word 0 */
@@ -162,6 +170,12 @@ typedef struct rs_handle rs_handle;
 /* Fill *o with defaults: AUTO form, subsample, tau = 0 (must be set), heuristic
  * momentum, eta 0.995, beta_max 0.5, tol 1e-6, max_iter 100000, seed 1. */
 rs_status rs_options_default(rs_options* o);
+
+/* gamma_k and beta_k (host doubles) of iteration k >= 0 under the momentum settings of
+ * *o (o->momentum, gamma, beta, eta, beta_max), exactly as the solvers use them (Sec. 6,
+ * Sec. 9.1). Host-only, no device call. Errors: RS_EINVAL (unknown or unusable momentum
+ * settings, k < 0, a NULL pointer). */
+rs_status rs_momentum_schedule(const rs_options* o, int64_t k, double* gamma, double* beta);
 
 /* Build a solver for X, y (y: n values, FP64, in the memory X.mem names) and
  * lambda > 0. Uploads X into library-owned device layouts, forms b, sets

@@ -16,6 +16,7 @@
 #include <string>
 #include <vector>
 
+#include "momentum.h"
 #include "rs_internal.h"
 
 using namespace rs;
@@ -25,6 +26,7 @@ struct rs_handle {
   int form = RS_FORM_PRIMAL;
   int64_t n = 0, d = 0, m = 0, K = 0;
   double lam = 0.0;
+  int64_t mom_switch = 0;  // switch index of the theoretical momentum rule
   bool sparse = false;
   int kind = kSubsample;
   int tau = 0, sub_k = 0;
@@ -178,30 +180,8 @@ void dfree_all(rs_handle* h) {
   }
 }
 
-// Momentum schedule (Sec. 6, Sec. 9.1), evaluated in a fixed operation order.
+// Host arithmetic below in a fixed operation order (no contraction).
 #pragma clang fp contract(off)
-void schedule(const rs_options& o, int64_t k, double* gamma, double* beta) {
-  switch (o.momentum) {
-    case RS_MOMENTUM_NONE:
-      *gamma = 1.0;
-      *beta = 0.0;
-      return;
-    case RS_MOMENTUM_CONSTANT:
-      *gamma = o.gamma;
-      *beta = o.beta;
-      return;
-    default: {
-      const double eta = o.eta;
-      double denom = (double)(k + 1) * (1.0 - eta);
-      denom = denom + 1.0;
-      const double bt = 1.0 - (2.0 - eta) / denom;
-      *gamma = 1.0;
-      *beta = std::min(o.beta_max, bt);
-      return;
-    }
-  }
-}
-
 int subcount_rule(int64_t m, int tau) {
   if (10ll * tau <= m) return 10;
   return (int)(m / tau);
@@ -362,7 +342,7 @@ void iterate_batch(rs_handle* h, int p, int64_t k0, int nb) {
   for (int i = 0; i < nb; ++i) {
     const int64_t k = k0 + i;
     double gamma, beta;
-    schedule(h->opt, k, &gamma, &beta);
+    momentum_schedule(h->opt, h->mom_switch, k, &gamma, &beta);
     const int cur = (int)(k & 1), nxt = 1 - cur;
     const int32_t* hm = h->hmap + (int64_t)i * h->m;
     pe = prof_begin(h, RS_PROF_DELTA, 1, 2);
@@ -579,6 +559,12 @@ rs_status rs_options_default(rs_options* o) {
   return RS_OK;
 }
 
+rs_status rs_momentum_schedule(const rs_options* o, int64_t k, double* gamma, double* beta) {
+  if (!o || !gamma || !beta || k < 0 || momentum_invalid(*o)) return RS_EINVAL;
+  momentum_schedule(*o, momentum_switch(o->eta, o->beta_max), k, gamma, beta);
+  return RS_OK;
+}
+
 const char* rs_status_string(rs_status s) {
   switch (s) {
     case RS_OK: return "ok";
@@ -633,8 +619,8 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
     if ((o->sampler != RS_SAMPLER_UNIFORM || o->trace_every > 0) &&
         (X->layout == RS_CSR || o->sketch != RS_SKETCH_SUBSAMPLE))
       throw Fail{RS_EUNSUPPORTED, "proposals and traces are built for the subsample sketch on dense data"};
-    if (o->momentum < RS_MOMENTUM_NONE || o->momentum > RS_MOMENTUM_HEURISTIC)
-      throw Fail{RS_EINVAL, "unknown momentum"};
+    if (const char* why = momentum_invalid(*o)) throw Fail{RS_EINVAL, why};
+    h->mom_switch = momentum_switch(o->eta, o->beta_max);
     if (!(o->tol >= 0.0)) throw Fail{RS_EINVAL, "tol must be >= 0"};
     if (o->max_iter < 0 || o->max_iter > 100000000) throw Fail{RS_EINVAL, "max_iter out of range"};
     h->form = o->form == RS_FORM_AUTO ? (d <= n ? RS_FORM_PRIMAL : RS_FORM_DUAL) : o->form;

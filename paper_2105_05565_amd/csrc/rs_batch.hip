@@ -25,6 +25,7 @@
 #include <string>
 #include <vector>
 
+#include "momentum.h"
 #include "rs_internal.h"
 
 using namespace rs;
@@ -163,24 +164,8 @@ void free_all(rs_batch* b) {
   b->stream = nullptr;
 }
 
-// Momentum schedule (Sec. 6, Sec. 9.1) in a fixed operation order, as for one solve.
+// Host arithmetic below in a fixed operation order (no contraction).
 #pragma clang fp contract(off)
-void schedule(const rs_options& o, int64_t k, double* gamma, double* beta) {
-  if (o.momentum == RS_MOMENTUM_NONE) {
-    *gamma = 1.0;
-    *beta = 0.0;
-  } else if (o.momentum == RS_MOMENTUM_CONSTANT) {
-    *gamma = o.gamma;
-    *beta = o.beta;
-  } else {
-    const double eta = o.eta;
-    double denom = (double)(k + 1) * (1.0 - eta);
-    denom = denom + 1.0;
-    const double bt = 1.0 - (2.0 - eta) / denom;
-    *gamma = 1.0;
-    *beta = std::min(o.beta_max, bt);
-  }
-}
 
 // Default sketch size of a batched problem: a multiple of 64 near m^{2/3}, in [64, 512].
 int default_tau(int64_t m) {
@@ -466,8 +451,7 @@ rs_status rs_batch_create(int32_t count, const rs_problem* problems, const rs_op
   try {
     B->opt = *o;
     if (o->precision != RS_PREC_FP64) throw Fail{RS_EUNSUPPORTED, "batched solves run in FP64"};
-    if (o->momentum < RS_MOMENTUM_NONE || o->momentum > RS_MOMENTUM_HEURISTIC)
-      throw Fail{RS_EINVAL, "unknown momentum"};
+    if (const char* why = momentum_invalid(*o)) throw Fail{RS_EINVAL, why};
     if (!(o->tol >= 0.0)) throw Fail{RS_EINVAL, "tol must be >= 0"};
     if (o->max_iter < 0 || o->max_iter > 100000000) throw Fail{RS_EINVAL, "max_iter out of range"};
     B->graph_iters = o->graph_iters == 0 ? 8 : (o->graph_iters < 0 ? 0 : o->graph_iters);
@@ -670,7 +654,8 @@ rs_status rs_batch_create(int32_t count, const rs_problem* problems, const rs_op
     }
     // momentum schedule table, indexed by the device iteration counter
     std::vector<double> bt(max_cap + 1), gm(max_cap + 1);
-    for (int64_t kk = 0; kk <= max_cap; ++kk) schedule(*o, kk, &gm[kk], &bt[kk]);
+    const int64_t sw = momentum_switch(o->eta, o->beta_max);
+    for (int64_t kk = 0; kk <= max_cap; ++kk) momentum_schedule(*o, sw, kk, &gm[kk], &bt[kk]);
 
     B->S = upload(B, hs);
     B->betas = upload(B, bt);

@@ -20,12 +20,13 @@ RS_F64, RS_F32 = 0, 1
 RS_HOST, RS_DEVICE = 0, 1
 RS_FORM_AUTO, RS_FORM_PRIMAL, RS_FORM_DUAL = 0, 1, 2
 RS_SKETCH_SUBSAMPLE, RS_SKETCH_COUNT, RS_SKETCH_SUBCOUNT = 0, 1, 2
-RS_MOMENTUM_NONE, RS_MOMENTUM_CONSTANT, RS_MOMENTUM_HEURISTIC = 0, 1, 2
+RS_MOMENTUM_NONE, RS_MOMENTUM_CONSTANT, RS_MOMENTUM_HEURISTIC, RS_MOMENTUM_THEORY = 0, 1, 2, 3
 RS_PREC_FP64, RS_PREC_MIXED_BF16 = 0, 1
 
 FORMS = {"auto": RS_FORM_AUTO, "primal": RS_FORM_PRIMAL, "dual": RS_FORM_DUAL}
 SKETCHES = {"subsample": RS_SKETCH_SUBSAMPLE, "count": RS_SKETCH_COUNT, "subcount": RS_SKETCH_SUBCOUNT}
-MOMENTA = {"none": RS_MOMENTUM_NONE, "constant": RS_MOMENTUM_CONSTANT, "heuristic": RS_MOMENTUM_HEURISTIC}
+MOMENTA = {"none": RS_MOMENTUM_NONE, "constant": RS_MOMENTUM_CONSTANT, "heuristic": RS_MOMENTUM_HEURISTIC,
+           "theory": RS_MOMENTUM_THEORY}
 PRECISIONS = {"fp64": RS_PREC_FP64, "mixed": RS_PREC_MIXED_BF16}
 
 
@@ -124,6 +125,8 @@ SIGNATURES = {
     "rs_get_products": (ctypes.c_int32, [_P, _P, _P]),
     "rs_destroy": (ctypes.c_int32, [_P]),
     "rs_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
+    "rs_momentum_schedule": (ctypes.c_int32, [ctypes.POINTER(rs_options), ctypes.c_int64,
+                                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "rs_last_error": (ctypes.c_char_p, [_P]),
     "rs_sketch_size": (ctypes.c_int32, [_P]),
     "rs_get_route": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]),
@@ -223,6 +226,14 @@ def rs_options_default():
     o = rs_options()
     _check(load().rs_options_default(ctypes.byref(o)), "rs_options_default")
     return o
+
+
+def rs_momentum_schedule(opts, k):
+    """(gamma_k, beta_k) of iteration k under opts' momentum settings, from the library."""
+    g, b = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(load().rs_momentum_schedule(ctypes.byref(opts), int(k), ctypes.byref(g), ctypes.byref(b)),
+           "rs_momentum_schedule")
+    return g.value, b.value
 
 
 def rs_create(X, y, lam, opts):

@@ -147,3 +147,37 @@ def test_batch_rejects_unbuilt_pairs_without_device():
     with pytest.raises(rs.RsError) as e:
         rs.rs_batch_create([P], o)
     assert e.value.status == rs.RS_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("name,kw", [
+    ("none", {}), ("constant", dict(gamma=0.8, beta=0.4)), ("heuristic", {}),
+    ("heuristic", dict(eta=0.9, beta_max=0.3)), ("theory", {}), ("theory", dict(eta=0.9, beta_max=0.3)),
+    ("theory", dict(eta=0.5, beta_max=0.99)), ("theory", dict(eta=1.0)), ("theory", dict(beta_max=-0.5)),
+    ("theory", dict(eta=0.999, beta_max=0.999)),
+])
+def test_momentum_schedule_matches_oracle_bit_exact(name, kw):
+    from oracle.solver import Options, schedule
+
+    o = rs.rs_options_default()
+    o.momentum = rs.MOMENTA[name]
+    for f, v in kw.items():
+        setattr(o, f, v)
+    opts = Options(momentum=name, **{("gamma_const" if f == "gamma" else "beta_const" if f == "beta" else f): v
+                                     for f, v in kw.items()})
+    for k in list(range(0, 420)) + [999, 10**6, 2 * 10**6 + 1, 10**8]:
+        assert rs.rs_momentum_schedule(o, k) == schedule(opts, k), (name, kw, k)
+
+
+@pytest.mark.parametrize("kw", [dict(momentum=4), dict(momentum=-1), dict(momentum=3, eta=0.0),
+                                dict(momentum=3, eta=1.5), dict(momentum=3, eta=math.nan),
+                                dict(momentum=3, beta_max=math.nan)])
+def test_momentum_settings_rejected(kw):
+    o = rs.rs_options_default()
+    for f, v in kw.items():
+        setattr(o, f, v)
+    with pytest.raises(rs.RsError) as e:
+        rs.rs_momentum_schedule(o, 0)
+    assert e.value.status == rs.RS_EINVAL
+    with pytest.raises(rs.RsError) as e:
+        _create(np.ones((20, 8)), np.ones(20), 1.0, tau=3, **kw)
+    assert e.value.status == rs.RS_EINVAL

@@ -81,6 +81,27 @@ def test_batch_matches_single_solves_and_oracle():
     B.close()
 
 
+def test_batch_theory_momentum_across_switch_matches_oracle():
+    """The schedule table of a batch under the theoretical momentum rule: 230 iterations
+    cross its switch at k = 201; one slot per problem against the oracle."""
+    probs = _problems()
+    N = 230
+    B = rs.Batch(probs, momentum="theory", tol=0.0, seed=6, graph_iters=8)
+    B.step(N)
+    for p, pr in enumerate(probs):
+        l, q = (p + 2) % 3, p % 2
+        system = ridge_system(pr["X"], pr["y"][:, q], pr["lambdas"][l])
+        sketch = "count" if hasattr(pr["X"], "tocsr") else "subsample"
+        tau = pr["tau"] if pr["tau"] else 64
+        opts = Options(sketch=sketch, tau=tau, momentum="theory", tol=0.0, max_iter=N, seed=6, problem_id=p)
+        st = init_state(system)
+        for _ in range(N):
+            step(system, st, opts)
+        x = B.state(p, l * 2 + q)[0]
+        assert _rel(x, st.w) <= 1e-10, (p, _rel(x, st.w))
+    B.close()
+
+
 def test_default_tau_rule():
     probs = _problems()
     B = rs.Batch(probs[:2], tol=0.0)

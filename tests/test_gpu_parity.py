@@ -133,6 +133,25 @@ def test_dense_subsample_trajectory_ragged_tiles(n, d, tau):
     _trajectory_check(p.X, p.y, p.lam, form="primal", kind="subsample", tau=tau, momentum="heuristic")
 
 
+@pytest.mark.parametrize("case", ["dense-subsample", "csr-count-arows", "csr-subcount-scatter"])
+def test_theory_momentum_trajectory_across_switch(case):
+    """Theoretical momentum rule (eq:parameterswitchtheory): gamma_k falls and beta_k rises
+    until the switch at k = 201 (eta 0.995, threshold 0.5), then both stay at 0.5; the
+    checkpoints straddle the switch. The problems converge slowly enough that r stays far
+    above rounding level at k = 240."""
+    if case == "dense-subsample":
+        p = inputs.make_dense(600, 300, 0.05, seed=600, col_log_sigma=1.0)
+        kind, tau, route = "subsample", 10, "auto"
+    elif case == "csr-count-arows":
+        p = _csr(400, 150, 0.04, 0.05, seed=3)
+        kind, tau, route = "count", 23, "arows"
+    else:
+        p = _csr(600, 300, 0.02, 0.05, seed=7)
+        kind, tau, route = "subcount", 20, "scatter"
+    _trajectory_check(p.X, p.y, p.lam, form="primal", kind=kind, tau=tau, momentum="theory",
+                      checkpoints=[1, 7, 150, 200, 201, 202, 240], route=route)
+
+
 def test_dense_subsample_trajectory_f32_colmajor_input():
     p = _dense(260, 70, 0.2, seed=9)
     Xf = np.asfortranarray(p.X.astype(np.float32))
