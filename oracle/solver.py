@@ -4,7 +4,7 @@ One iteration k (Alg. 2, with Alg. 1 as the case beta_k = 0, gamma_k = 1):
 
 1. gamma_k, beta_k from the momentum schedule;
 2. draw S_k ~ D (see ``sketch``);
-3. AS_k = A S_k = Z (Z^T S_k) + lambda S_k;
+3. AS_k = A S_k = Z (Z^T S_k) + lambda S_k (kernel ridge: K (K S_k) + lambda K S_k);
 4. the sketched system G = S_k^T A S_k and sketched residual rho = S_k^T r^k;
 5. delta_k = least-norm solution of G delta = rho (eq:sketched_system);
 6. w^{k+1} = (1 + beta_k) w^k - beta_k w^{k-1} - gamma_k S_k delta_k;
@@ -138,9 +138,12 @@ def draw_sketch(system, opts, k, q=None):
 def sketched_products(system, sketch):
     """AS = Z (Z^T S) + lambda S (m x tau, dense), G = S^T AS, and the column mask."""
     S = sketch.matrix()
-    T = system.Z.T @ S                      # K x tau
-    AS = system.Z @ T                       # m x tau
-    AS = (AS.toarray() if sp.issparse(AS) else np.asarray(AS)) + system.lam * S.toarray()
+    if hasattr(system, "sketched_AS"):      # kernel ridge: A S = K (K S) + lambda K S
+        AS = system.sketched_AS(S)
+    else:
+        T = system.Z.T @ S                  # K x tau
+        AS = system.Z @ T                   # m x tau
+        AS = (AS.toarray() if sp.issparse(AS) else np.asarray(AS)) + system.lam * S.toarray()
     G = np.asarray(S.T @ AS)
     active = np.zeros(sketch.tau, dtype=bool)
     active[sketch.cols] = True

@@ -13,7 +13,10 @@ Recipes (numpy PCG64, ``data_seed`` fixed per workload):
 * csr:     exactly ``nnz`` distinct positions drawn uniformly over the n x d
            grid (row and column counts then follow Poisson-like laws),
            values N(0, 1);
-* targets: y = X w* + noise_scale * N(0, 1) with w* ~ N(0, 1).
+* targets: y = X w* + noise_scale * N(0, 1) with w* ~ N(0, 1);
+* kernel points: n points in d dimensions drawn around n / 10 cluster centres
+           (centres N(0, I), offsets spread * N(0, I)), each coordinate then
+           standardised; targets y = sin(P v) + 0.1 N(0, 1) with v ~ N(0, I / d).
 
 The paper's own datasets (Boston, California Housing, RCV1, YearPredictionMSD)
 are not used; these synthetic matrices stand in for them.
@@ -89,7 +92,28 @@ def make_csr(n, d, density, lam, seed, dtype=np.float32, name=None):
     return Problem(name or f"csr_{n}x{d}", X, y, lam, w_star)
 
 
-# The five workloads, with reduced shape-alike variants for fast tests.
+@dataclass
+class KernelProblem:
+    name: str
+    P: np.ndarray        # n x d points, FP64
+    y: np.ndarray        # FP64 [n]
+    lam: float
+    sigma: float         # Gaussian kernel width
+
+
+def make_points(n, d, lam, sigma, seed, clusters=None, spread=0.3, name=None):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nc = clusters if clusters else max(1, n // 10)
+    centres = rng.standard_normal((nc, d))
+    label = rng.integers(0, nc, size=n)
+    P = centres[label] + spread * rng.standard_normal((n, d))
+    P = (P - P.mean(axis=0)) / P.std(axis=0)
+    v = rng.standard_normal(d) / np.sqrt(d)
+    y = np.sin(P @ v) + 0.1 * rng.standard_normal(n)
+    return KernelProblem(name or f"points_{n}x{d}", np.ascontiguousarray(P), y, lam, sigma)
+
+
+# The workloads, with reduced shape-alike variants for fast tests.
 def dense_primal(scale=1.0, seed=DATA_SEED_BASE + 0):
     """X 2000 x 500 FP64 N(0,1), lambda = 1e-2 (subsample sketch, tau = 50)."""
     n, d = int(2000 * scale), int(500 * scale)
@@ -113,6 +137,20 @@ def dense_learned(scale=1.0, seed=DATA_SEED_BASE + 4):
     n, d = int(200000 * scale), int(4096 * scale)
     return make_dense(n, d, 1e-2, seed, np.float32, col_log_sigma=2.0, corr_frac=0.05,
                       name=f"dense_learned_{n}x{d}")
+
+
+def kernel_california(scale=1.0, seed=DATA_SEED_BASE + 5):
+    """20640 points in 8 dimensions (the shape of the California Housing kernel problem),
+    Gaussian kernel sigma = 0.5, lambda = 1e-6 (subsample sketch, tau = m / 4)."""
+    n = int(20640 * scale)
+    return make_points(n, 8, 1e-6, 0.5, seed, name=f"kernel_california_{n}x8")
+
+
+def kernel_boston(seed=DATA_SEED_BASE + 6):
+    """506 points in 13 dimensions (the shape of the Boston kernel problem), sigma = 0.5
+    sqrt(13 / 8) (the same typical kernel values as in 8 dimensions), lambda = 1e-6
+    (tau = floor(m / 4) = 126)."""
+    return make_points(506, 13, 1e-6, 0.5 * np.sqrt(13.0 / 8.0), seed, name="kernel_boston_506x13")
 
 
 def batched_tau(m):
