@@ -184,6 +184,19 @@ rs_status rs_momentum_schedule(const rs_options* o, int64_t k, double* gamma, do
 rs_status rs_create(const rs_matrix* X, const double* y, double lambda,
                     const rs_options* o, rs_handle** out);
 
+/* Kernel ridge regression (Sec. 2.2, eq:kernelridge): solve K (K + lambda I) alpha = K y
+ * for the Gaussian kernel K_ij = exp(-||p_i - p_j||^2 / (2 sigma^2)) (eq:Gausskernel) of
+ * the n points P (an rs_matrix of n rows and d coordinates, dense, FP32 or FP64, host or
+ * device; y: n values in the memory P.mem names). The library forms K (n x n, FP64) in
+ * device memory (8 n^2 bytes), b = K y, and then runs the same iteration as rs_create's
+ * dense path with m = n; the weights (rs_get_weights, rs_solve) are the n coefficients
+ * alpha, and predictions at the points are K alpha. Options: the subsample sketch, FP64,
+ * uniform sampling (RS_EUNSUPPORTED otherwise); o->form is ignored. Errors: RS_EINVAL
+ * (sigma or lambda not positive and finite, CSR points, shapes, non-finite y), RS_ENOMEM,
+ * RS_EDEVICE, RS_EUNSUPPORTED. */
+rs_status rs_create_kernel(const rs_matrix* P, const double* y, double sigma, double lambda,
+                           const rs_options* o, rs_handle** out);
+
 /* Advance up to `iters` iterations (fewer if ||r^k|| / ||r^0|| <= tol is met
  * first), then synchronise the stream. *rel_res_out (host, may be NULL)
  * receives ||r^k|| / ||r^0|| at the final k. */

@@ -4,6 +4,9 @@
 // contraction over K whose second operand is the gathered rows C of Z. Several
 // lookahead sketches share the first operand, so one launch contracts Z against
 // [Z[C_0,:]; Z[C_1,:]; ...] (N = slots * tau columns) on FP64 MFMA (16x16x4).
+// Kernel ridge (Sec. 2.2) stores the symmetric kernel matrix as Z (m = K): then
+// A S = K (K + lambda I) I_C = Z Z[C,:]^T + lambda Z[:,C], the same contraction with the
+// shift taken from the gathered columns.
 #include "dev_common.h"
 #include "rs_internal.h"
 
@@ -26,8 +29,8 @@ struct DenseLds128 {
 __device__ __forceinline__ void as_dense_tile128(const double* __restrict__ Z, int64_t ldz, int64_t m,
                                                  int64_t K, const int32_t* __restrict__ members,
                                                  int32_t tau, int64_t ntot, int64_t ldas, double lam,
-                                                 double* __restrict__ AS, int64_t row0, int64_t n0,
-                                                 DenseLds128& L) {
+                                                 int32_t lam_kernel, double* __restrict__ AS, int64_t row0,
+                                                 int64_t n0, DenseLds128& L) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
   if (tid < kBT) {
@@ -119,7 +122,10 @@ __device__ __forceinline__ void as_dense_tile128(const double* __restrict__ Z, i
         if (row < m && n < ntot) {
           const int64_t slot = n / tau, c = n % tau;
           double val = acc[i][j][v];
-          if (row == L.brow[col]) val += lam;
+          if (lam_kernel)
+            val += lam * Z[L.brow[col] * ldz + row];  // lambda K[row, C_c] (K symmetric)
+          else if (row == L.brow[col])
+            val += lam;
           AS[(slot * m + row) * ldas + c] = val;
         }
       }
@@ -130,11 +136,12 @@ __global__ __launch_bounds__(256, 2) void k_as_dense_f64_128(const double* __res
                                                              int64_t m, int64_t K,
                                                              const int32_t* __restrict__ members,
                                                              int32_t tau, int64_t ldas, int32_t nslots,
-                                                             double lam, double* __restrict__ AS,
+                                                             double lam, int32_t lam_kernel,
+                                                             double* __restrict__ AS,
                                                              const int32_t* __restrict__ done) {
   __shared__ DenseLds128 L;
   if (*done) return;
-  as_dense_tile128(Z, ldz, m, K, members, tau, (int64_t)nslots * tau, ldas, lam, AS,
+  as_dense_tile128(Z, ldz, m, K, members, tau, (int64_t)nslots * tau, ldas, lam, lam_kernel, AS,
                    (int64_t)blockIdx.x * kBT, (int64_t)blockIdx.y * kBT, L);
 }
 
@@ -148,7 +155,7 @@ __global__ __launch_bounds__(256, 2) void k_as_dense_f64_tab(const DenseJob* __r
     const DenseTile tl = tiles[t];
     const DenseJob& j = jobs[tl.job];
     if (*j.done) continue;  // uniform across the workgroup
-    as_dense_tile128(j.Z, j.ldz, j.m, j.K, j.members, j.tau, j.tau, j.ldas, j.lam, j.AS,
+    as_dense_tile128(j.Z, j.ldz, j.m, j.K, j.members, j.tau, j.tau, j.ldas, j.lam, 0, j.AS,
                      (int64_t)tl.tm * kBT, (int64_t)tl.tn * kBT, L);
   }
 }
@@ -203,6 +210,52 @@ __global__ void k_gemv_cols(const double* __restrict__ Z, int64_t ldz, int64_t m
   out[k] = s;
 }
 
+// Gaussian kernel matrix (eq:Gausskernel) of points P (n x d, row-major FP64):
+// Kout[i][j] = exp(-sum_t (P[i][t] - P[j][t])^2 / denom), denom = 2 sigma^2, one 64 x 64
+// tile per workgroup, 32 coordinates at a time staged in LDS; every thread owns a 4 x 4
+// block. The squares are summed in coordinate order, so Kout is exactly symmetric.
+constexpr int kRbfT = 64, kRbfD = 32;
+__global__ __launch_bounds__(256) void k_rbf_gram(const double* __restrict__ P, int64_t n, int64_t d,
+                                                  double denom, double* __restrict__ Kout, int64_t ldk) {
+  __shared__ double pi[kRbfT][kRbfD + 1];
+  __shared__ double pj[kRbfT][kRbfD + 1];
+  const int tid = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.y * kRbfT, j0 = (int64_t)blockIdx.x * kRbfT;
+  const int ti = (tid >> 4) * 4, tj = (tid & 15) * 4;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int64_t t0 = 0; t0 < d; t0 += kRbfD) {
+    for (int e = tid; e < kRbfT * kRbfD; e += 256) {
+      const int r = e / kRbfD, c = e % kRbfD;
+      const int64_t t = t0 + c;
+      pi[r][c] = (i0 + r < n && t < d) ? P[(i0 + r) * d + t] : 0.0;
+      pj[r][c] = (j0 + r < n && t < d) ? P[(j0 + r) * d + t] : 0.0;
+    }
+    __syncthreads();
+    const int tn = (int)(d - t0 < kRbfD ? d - t0 : kRbfD);
+    for (int c = 0; c < tn; ++c) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const double df = pi[ti + a][c] - pj[tj + b][c];
+          acc[a][b] += df * df;
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int64_t i = i0 + ti + a, j = j0 + tj + b;
+      if (i < n && j < n) Kout[i * ldk + j] = exp(-acc[a][b] / denom);
+    }
+}
+
 __global__ void k_vec_to_f64(const void* __restrict__ src, int32_t is_f32, int64_t n,
                              double* __restrict__ dst) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -213,11 +266,13 @@ __global__ void k_vec_to_f64(const void* __restrict__ src, int32_t is_f32, int64
 
 hipError_t launch_as_dense_f64(const double* Z, int64_t ldz, int64_t m, int64_t K,
                                const int32_t* members, int32_t tau, int64_t ldas, int32_t nslots,
-                               double lam, double* AS, const int32_t* done, hipStream_t s) {
+                               double lam, int32_t lam_kernel, double* AS, const int32_t* done,
+                               hipStream_t s) {
   const int64_t ntot = (int64_t)nslots * tau;
+  if (lam_kernel && K != m) return hipErrorInvalidValue;
   dim3 grid((unsigned)((m + kBT - 1) / kBT), (unsigned)((ntot + kBT - 1) / kBT));
   hipLaunchKernelGGL(k_as_dense_f64_128, grid, dim3(256), 0, s, Z, ldz, m, K, members, tau, ldas,
-                     nslots, lam, AS, done);
+                     nslots, lam, lam_kernel, AS, done);
   return hipGetLastError();
 }
 
@@ -259,6 +314,16 @@ hipError_t launch_vec_to_f64(const void* src, int32_t src_is_f32, int64_t n, dou
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_vec_to_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src,
                      src_is_f32, n, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_rbf_gram(const double* P, int64_t n, int64_t d, double sigma, double* Kout, int64_t ldk,
+                           hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (d < 1 || ldk < n || !(sigma > 0.0)) return hipErrorInvalidValue;
+  const unsigned t = (unsigned)((n + kRbfT - 1) / kRbfT);
+  if (t > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_rbf_gram, dim3(t, t), dim3(256), 0, s, P, n, d, 2.0 * sigma * sigma, Kout, ldk);
   return hipGetLastError();
 }
 

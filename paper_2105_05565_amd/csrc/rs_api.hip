@@ -27,6 +27,8 @@ struct rs_handle {
   int64_t n = 0, d = 0, m = 0, K = 0;
   double lam = 0.0;
   int64_t mom_switch = 0;  // switch index of the theoretical momentum rule
+  bool kern = false;        // kernel ridge: Z holds the symmetric kernel matrix (m = K = n)
+  int64_t pdim = 0;         // kernel ridge: dimension of the points
   bool sparse = false;
   int kind = kSubsample;
   int tau = 0, sub_k = 0;
@@ -301,7 +303,7 @@ void prep_batch(rs_handle* h, int p, int64_t k0, int nb, hipStream_t s) {
               "AS (dense, BF16)");
   } else {
     check_hip(launch_as_dense_f64(h->Z, h->ldz, h->m, h->K, bs.members, h->tau, h->ldas, nb, h->lam,
-                                  (double*)bs.AS, done, s),
+                                  h->kern ? 1 : 0, (double*)bs.AS, done, s),
               "AS (dense)");
   }
   prof_end(h, pe, s);
@@ -582,8 +584,13 @@ const char* rs_last_error(const rs_handle* h) {
   return h ? h->last_error.c_str() : g_create_error.c_str();
 }
 
-rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs_options* o,
-                    rs_handle** out) {
+}  // extern "C"
+
+namespace {
+
+// Shared by rs_create and rs_create_kernel: sigma > 0 selects kernel ridge with X the points.
+rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double sigma, const rs_options* o,
+                      rs_handle** out) {
   g_create_error.clear();
   if (!X || !y || !o || !out) {
     g_create_error = "null argument";
@@ -592,6 +599,15 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
   *out = nullptr;
   rs_handle* h = new rs_handle();
   try {
+    const bool kern = sigma > 0.0;
+    h->kern = kern;
+    if (kern && X->layout == RS_CSR) throw Fail{RS_EINVAL, "kernel ridge takes dense points"};
+    if (kern && o->precision != RS_PREC_FP64)
+      throw Fail{RS_EUNSUPPORTED, "kernel ridge runs in FP64"};
+    if (kern && o->sketch != RS_SKETCH_SUBSAMPLE)
+      throw Fail{RS_EUNSUPPORTED, "kernel ridge is built for the subsample sketch"};
+    if (kern && (o->sampler != RS_SAMPLER_UNIFORM || o->trace_every != 0))
+      throw Fail{RS_EUNSUPPORTED, "kernel ridge uses uniform sampling without traces"};
     h->opt = *o;
     h->stream = static_cast<hipStream_t>(o->stream);
     const int64_t n = X->n, d = X->d;
@@ -625,10 +641,12 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
     if (o->max_iter < 0 || o->max_iter > 100000000) throw Fail{RS_EINVAL, "max_iter out of range"};
     h->form = o->form == RS_FORM_AUTO ? (d <= n ? RS_FORM_PRIMAL : RS_FORM_DUAL) : o->form;
     if (h->form != RS_FORM_PRIMAL && h->form != RS_FORM_DUAL) throw Fail{RS_EINVAL, "unknown form"};
+    if (kern) h->form = RS_FORM_DUAL;  // n coefficients alpha; the weights are alpha itself
     h->n = n;
-    h->d = d;
+    h->d = kern ? n : d;
+    h->pdim = kern ? d : 0;
     h->m = h->form == RS_FORM_PRIMAL ? d : n;
-    h->K = h->form == RS_FORM_PRIMAL ? n : d;
+    h->K = h->form == RS_FORM_PRIMAL ? n : (kern ? n : d);
     h->lam = lambda;
     h->sparse = X->layout == RS_CSR;
     h->tau = o->tau;
@@ -683,7 +701,23 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
       // Z = X^T (primal) or X (dual), row-major m x K
       const bool rowmajor = X->layout == RS_DENSE_ROWMAJOR;
       const bool need_transpose = (h->form == RS_FORM_PRIMAL) == rowmajor;
-      if (h->mixed) {
+      if (kern) {
+        // points as FP64 row-major n x d, then Z = K (n x n, eq:Gausskernel) and b = K y
+        double* p64 = dalloc<double>(h, (size_t)n * d);
+        if (rowmajor)
+          check_hip(launch_copy_to_f64(xv, f32, n, d, d, p64, d, s), "points");
+        else
+          check_hip(launch_transpose_to_f64(xv, f32, d, n, n, p64, d, s), "points");
+        h->ldz = n;
+        h->Z = dalloc<double>(h, (size_t)n * h->ldz);
+        check_hip(launch_rbf_gram(p64, n, d, sigma, h->Z, h->ldz, s), "kernel matrix");
+        check_hip(launch_gemv_rows(h->Z, h->ldz, h->m, h->K, yd, h->b, s), "b = K y");
+        check_hip(hipStreamSynchronize(s), "sync");
+        for (void* p : {(void*)p64, xv}) {
+          (void)hipFree(p);
+          h->allocs.erase(std::find(h->allocs.begin(), h->allocs.end(), p));
+        }
+      } else if (h->mixed) {
         h->kpad = (h->K + 63) / 64 * 64;
         h->Zbf = dalloc<uint16_t>(h, (size_t)h->m * h->kpad);
         h->Z32 = dalloc<float>(h, (size_t)h->m * h->K);
@@ -905,6 +939,25 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs
   }
 }
 
+}  // namespace
+
+extern "C" {
+
+rs_status rs_create(const rs_matrix* X, const double* y, double lambda, const rs_options* o,
+                    rs_handle** out) {
+  return create_impl(X, y, lambda, 0.0, o, out);
+}
+
+rs_status rs_create_kernel(const rs_matrix* P, const double* y, double sigma, double lambda,
+                           const rs_options* o, rs_handle** out) {
+  if (!(sigma > 0.0) || !std::isfinite(sigma)) {
+    g_create_error = "sigma must be positive and finite";
+    if (out) *out = nullptr;
+    return RS_EINVAL;
+  }
+  return create_impl(P, y, lambda, sigma, o, out);
+}
+
 rs_status rs_step(rs_handle* h, int64_t iters, double* rel_res_out) {
   if (!h || iters < 0) return RS_EINVAL;
   try {
@@ -975,7 +1028,7 @@ rs_status rs_get_weights(rs_handle* h, double* w_out) {
   if (!h || !w_out) return RS_EINVAL;
   try {
     const double* x = h->xbuf[h->k & 1];
-    if (h->form == RS_FORM_PRIMAL) {
+    if (h->form == RS_FORM_PRIMAL || h->kern) {
       check_hip(hipMemcpyAsync(w_out, x, sizeof(double) * h->d, hipMemcpyDeviceToHost, h->stream), "w");
     } else {
       double* wd = nullptr;

@@ -69,9 +69,14 @@ hipError_t launch_sketch_tab(const SketchArgs* tab, int32_t count, int32_t kind,
 
 // AS[slot][j][c] (row stride ldas) = sum_k Z[j][k] * Z[C_slot[c]][k] + lam * [j == C_slot[c]],
 // FP64 MFMA.
+// lam_kernel != 0: Z is a symmetric kernel matrix (K == m) and the shift is lambda Z[:, C].
 hipError_t launch_as_dense_f64(const double* Z, int64_t ldz, int64_t m, int64_t K,
                                const int32_t* members, int32_t tau, int64_t ldas, int32_t nslots,
-                               double lam, double* AS, const int32_t* done, hipStream_t s);
+                               double lam, int32_t lam_kernel, double* AS, const int32_t* done,
+                               hipStream_t s);
+// Gaussian kernel matrix of n points (P: n x d row-major FP64) into Kout (n x n, row stride ldk).
+hipError_t launch_rbf_gram(const double* P, int64_t n, int64_t d, double sigma, double* Kout, int64_t ldk,
+                           hipStream_t s);
 
 // Grouped dense products (batched solves): job = one sketch of one problem,
 // AS (m x tau, row stride ldas) = Z Z[C,:]^T + lam I_C; tiles = (job, row tile, column tile)

@@ -112,6 +112,8 @@ SIGNATURES = {
     "rs_options_default": (ctypes.c_int32, [ctypes.POINTER(rs_options)]),
     "rs_create": (ctypes.c_int32, [ctypes.POINTER(rs_matrix), _P, ctypes.c_double,
                                    ctypes.POINTER(rs_options), ctypes.POINTER(_P)]),
+    "rs_create_kernel": (ctypes.c_int32, [ctypes.POINTER(rs_matrix), _P, ctypes.c_double, ctypes.c_double,
+                                          ctypes.POINTER(rs_options), ctypes.POINTER(_P)]),
     "rs_step": (ctypes.c_int32, [_P, ctypes.c_int64, _D]),
     "rs_solve": (ctypes.c_int32, [_P, _P, ctypes.POINTER(rs_report)]),
     "rs_reset": (ctypes.c_int32, [_P, ctypes.c_uint64]),
@@ -240,6 +242,13 @@ def rs_create(X, y, lam, opts):
     h = _P()
     _check(load().rs_create(ctypes.byref(X), _ptr(y), float(lam), ctypes.byref(opts), ctypes.byref(h)),
            "rs_create")
+    return h
+
+
+def rs_create_kernel(P, y, sigma, lam, opts):
+    h = _P()
+    _check(load().rs_create_kernel(ctypes.byref(P), _ptr(y), float(sigma), float(lam), ctypes.byref(opts),
+                                   ctypes.byref(h)), "rs_create_kernel")
     return h
 
 
@@ -570,13 +579,15 @@ def make_matrix(X):
 
 
 class Solver:
-    """Owns one rs_handle. `X` and `y` may live on the host (numpy) or the GPU (torch)."""
+    """Owns one rs_handle. `X` and `y` may live on the host (numpy) or the GPU (torch).
+    With kernel_sigma set, X holds the points of a kernel ridge problem (rs_create_kernel)
+    and the weights are its coefficients alpha."""
 
     def __init__(self, X, y, lam, *, tau, sketch="subsample", form="auto", momentum="heuristic",
                  precision="fp64", subcount_k=0, tol=1e-6, max_iter=100000, seed=1, problem_id=0,
                  eta=0.995, beta_max=0.5, gamma=1.0, beta=0.5, lookahead=0, refresh_every=20,
                  profile=False, stream=None, sampler="uniform", trace_every=0, trace_capacity=0,
-                 sparse_route="auto", pipeline=True):
+                 sparse_route="auto", pipeline=True, kernel_sigma=None):
         o = rs_options_default()
         o.form, o.sketch, o.tau = FORMS[form], SKETCHES[sketch], int(tau)
         o.subcount_k, o.momentum, o.precision = int(subcount_k), MOMENTA[momentum], PRECISIONS[precision]
@@ -593,9 +604,13 @@ class Solver:
         else:
             yv = np.ascontiguousarray(np.asarray(y, dtype=np.float64))
         keep.append(yv)
-        self.h = rs_create(M, yv, lam, o)
+        if kernel_sigma is None:
+            self.h = rs_create(M, yv, lam, o)
+            self.d = int(M.d)
+        else:
+            self.h = rs_create_kernel(M, yv, kernel_sigma, lam, o)
+            self.d = int(M.n)  # the coefficients alpha
         self.m = rs_system_size(self.h)
-        self.d = int(M.d)
         self.tau = int(tau)
 
     def reset(self, seed):

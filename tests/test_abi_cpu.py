@@ -181,3 +181,30 @@ def test_momentum_settings_rejected(kw):
     with pytest.raises(rs.RsError) as e:
         _create(np.ones((20, 8)), np.ones(20), 1.0, tau=3, **kw)
     assert e.value.status == rs.RS_EINVAL
+
+
+@pytest.mark.parametrize("sigma,kw,status", [
+    (0.0, {}, rs.RS_EINVAL), (-1.0, {}, rs.RS_EINVAL), (math.nan, {}, rs.RS_EINVAL), (math.inf, {}, rs.RS_EINVAL),
+    (0.5, dict(precision=rs.RS_PREC_MIXED_BF16), rs.RS_EUNSUPPORTED),
+    (0.5, dict(sketch=rs.RS_SKETCH_COUNT), rs.RS_EUNSUPPORTED),
+    (0.5, dict(sampler=rs.SAMPLERS["diag"]), rs.RS_EUNSUPPORTED),
+])
+def test_kernel_create_rejects_without_device(sigma, kw, status):
+    o = rs.rs_options_default()
+    o.tau = 3
+    for f, v in kw.items():
+        setattr(o, f, v)
+    M, keep = rs.make_matrix(np.ones((20, 4)))
+    with pytest.raises(rs.RsError) as e:
+        rs.rs_create_kernel(M, np.ones(20), sigma, 1.0, o)
+    assert e.value.status == status
+
+
+def test_kernel_create_rejects_csr_points():
+    import scipy.sparse as sp
+    o = rs.rs_options_default()
+    o.tau = 3
+    M, keep = rs.make_matrix(sp.random(20, 4, density=0.5, format="csr", random_state=1))
+    with pytest.raises(rs.RsError) as e:
+        rs.rs_create_kernel(M, np.ones(20), 0.5, 1.0, o)
+    assert e.value.status == rs.RS_EINVAL

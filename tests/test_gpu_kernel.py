@@ -1,0 +1,138 @@
+"""GPU: kernel ridge regression (Sec. 2.2, eq:kernelridge) through rs_create_kernel.
+
+The library forms the Gaussian kernel matrix (eq:Gausskernel) on the device and runs the
+dense subsample path on A = K (K + lambda I), b = K y. Checked against the oracle's kernel
+system: b (as -r^0), the sketched products, FP64 trajectories to 1e-10 over 50 iterations
+(odd and even m, ragged 128 x 128 product tiles, every momentum schedule), convergence to
+(K + lambda I)^{-1} y, and at the full 20640-point size on sampled rows (the kernel matrix
+is 3.4 GB there): b, the projection property of the first step and the tracked residual
+against A x - b formed by the oracle.
+"""
+import numpy as np
+import pytest
+
+from oracle import sketch as osk
+from oracle.problem import kernel_system, rbf_kernel
+from oracle.solver import Options, init_state, sketched_products, step
+from paper_2105_05565_amd import inputs, rs
+
+pytestmark = pytest.mark.gpu
+
+TRAJ_TOL = 1e-10
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _solver(p, tau, **kw):
+    return rs.Solver(p.P, p.y, p.lam, tau=tau, kernel_sigma=p.sigma, **kw)
+
+
+def test_kernel_rhs_and_products_match_oracle():
+    p = inputs.make_points(300, 8, 1e-3, 0.5, seed=31)
+    system = kernel_system(p.P, p.y, p.lam, p.sigma)
+    S = _solver(p, 37, tol=0.0, seed=4, momentum="none")
+    assert S.m == 300 and S.d == 300
+    x, _, r, _ = S.state()
+    assert not x.any()
+    assert _rel(-r, system.b) <= 1e-13
+    S.step(1)
+    rows, cols, signs = S.last_sketch()
+    sketch = osk.draw_subsample(4, 0, 0, 300, 37)
+    assert np.array_equal(rows, sketch.rows)
+    AS, _ = S.products()
+    _, AS_o, _, _ = sketched_products(system, sketch)
+    assert _rel(AS, AS_o) <= 1e-12
+    S.close()
+
+
+def _trajectory(p, tau, momentum, checkpoints, seed=5):
+    system = kernel_system(p.P, p.y, p.lam, p.sigma)
+    opts = Options(sketch="subsample", tau=tau, momentum=momentum, seed=seed, tol=0.0)
+    st = init_state(system)
+    S = _solver(p, tau, momentum=momentum, tol=0.0, seed=seed)
+    done = 0
+    for c in checkpoints:
+        while st.k < c:
+            step(system, st, opts)
+        S.step(c - done)
+        done = c
+        x, xp, r, rp = S.state()
+        ex, er = _rel(x, st.w), _rel(r, st.r)
+        assert ex <= TRAJ_TOL and er <= TRAJ_TOL, (c, ex, er)
+        if c > 1:
+            assert _rel(xp, st.w_prev) <= TRAJ_TOL
+    assert np.allclose(S.history(), st.history[:done + 1], rtol=1e-9, atol=0)
+    S.close()
+
+
+@pytest.mark.parametrize("momentum", ["none", "heuristic", "theory", "constant"])
+def test_kernel_trajectory(momentum):
+    p = inputs.make_points(400, 8, 1e-3, 0.5, seed=32)
+    _trajectory(p, 100, momentum, [1, 2, 7, 20, 50])
+
+
+@pytest.mark.parametrize("n,d,tau", [(301, 13, 75), (517, 5, 130)])
+def test_kernel_trajectory_ragged(n, d, tau):
+    # n odd: kernel rows not 16-byte aligned; tau = 130 leaves a partial product tile
+    p = inputs.make_points(n, d, 1e-2, 0.6, seed=n)
+    _trajectory(p, tau, "heuristic", [1, 3, 10, 50])
+
+
+def test_kernel_f32_colmajor_points():
+    p = inputs.make_points(250, 6, 1e-2, 0.5, seed=33)
+    q = inputs.KernelProblem(p.name, np.asfortranarray(p.P.astype(np.float32)), p.y, p.lam, p.sigma)
+    # the oracle sees the same FP32-rounded points
+    r = inputs.KernelProblem(p.name, q.P.astype(np.float64), p.y, p.lam, p.sigma)
+    system = kernel_system(r.P, r.y, r.lam, r.sigma)
+    S = _solver(q, 40, tol=0.0, seed=2)
+    st = init_state(system)
+    opts = Options(sketch="subsample", tau=40, momentum="heuristic", seed=2, tol=0.0)
+    for _ in range(20):
+        step(system, st, opts)
+    S.step(20)
+    assert _rel(S.state()[0], st.w) <= TRAJ_TOL
+    S.close()
+
+
+def test_kernel_solve_reaches_direct_solution():
+    p = inputs.make_points(500, 8, 1e-2, 0.4, seed=34)
+    S = _solver(p, 125, tol=1e-10, seed=3, max_iter=20000)
+    alpha, st, rep = S.solve()
+    assert st == rs.RS_OK
+    K = rbf_kernel(p.P, p.sigma)
+    A = K @ (K + p.lam * np.eye(500))
+    direct = np.linalg.solve(K + p.lam * np.eye(500), p.y)
+    kappa = np.linalg.cond(A)
+    assert _rel(alpha, direct) <= 2 * kappa * 1e-10
+    assert _rel(A @ alpha, K @ p.y) <= 2e-10
+    S.close()
+
+
+def test_kernel_full_size_first_step_sampled():
+    """20640 points in 8 dimensions, tau = m / 4 = 5160: sampled rows of b and of the first
+    iterate's residual against the oracle, and S^T r^1 = 0 (no momentum, gamma = 1)."""
+    p = inputs.kernel_california()
+    n = p.P.shape[0]
+    tau = n // 4
+    print(f"[kernel full size] n={n} tau={tau}", flush=True)
+    S = _solver(p, tau, tol=0.0, seed=1, momentum="none", lookahead=1)
+    rng = np.random.default_rng(0)
+    rows = rng.choice(n, size=64, replace=False)
+    Kr = rbf_kernel(p.P, p.sigma, rows=rows)
+    x, _, r, _ = S.state()
+    b_rows = Kr @ p.y
+    assert np.allclose(-r[rows], b_rows, rtol=1e-12, atol=1e-12 * np.abs(b_rows).max())
+    S.step(1)
+    x, _, r, _ = S.state()
+    sketch = osk.draw_subsample(1, 0, 0, n, tau)
+    assert np.array_equal(np.flatnonzero(x), np.intersect1d(np.flatnonzero(x), sketch.rows))
+    scale = np.abs(b_rows).max()
+    assert np.abs(r[sketch.rows]).max() <= 1e-9 * scale
+    # A x = K (K x + lambda x) on sampled rows; x is supported on C, so K x = K[C, :]^T x_C
+    supp = np.flatnonzero(x)
+    Kx = rbf_kernel(p.P, p.sigma, rows=supp).T @ x[supp]
+    direct = Kr @ (Kx + p.lam * x) - b_rows
+    assert np.allclose(r[rows], direct, rtol=0, atol=1e-9 * scale)
+    S.close()
