@@ -120,6 +120,14 @@ typedef struct rs_options {
                                batch iterates, in a second set of batch buffers (twice their
                                memory); 0: one stream. Off for the learned sampler, whose
                                proposal reads the iterate. */
+  int32_t accelerated;      /* 1: the accelerated method (Alg. 3) with parameters accel_mu,
+                               accel_nu instead of the momentum schedule; FP64, uniform
+                               sampling. 0 (default): Alg. 2 with the momentum schedule. */
+  double accel_mu, accel_nu; /* Alg. 3: 0 < mu <= 1 and 1 <= nu <= 1 / mu (defaults 1, 1: the
+                               iterates of Alg. 1); beta = 1 - sqrt(mu / nu), gamma =
+                               sqrt(1 / (mu nu)), alpha = 1 / (1 + sqrt(nu / mu)). The state
+                               (rs_get_state) is w, v, r_w, r_v; the weights are w; the stop
+                               test and the history use ||r_v^k|| / ||r_v^0||. */
 } rs_options;
 
 /* How AS is formed for the count and SubCount sketches on CSR data (same result up to
@@ -221,7 +229,8 @@ int64_t rs_iteration(const rs_handle* h);
 int64_t rs_system_size(const rs_handle* h);
 
 /* Copy the state to host buffers of m doubles each (any may be NULL):
- * x^k, x^{k-1}, r^k = A x^k - b (tracked), r^{k-1}. */
+ * x^k, x^{k-1}, r^k = A x^k - b (tracked), r^{k-1}. The accelerated method (Alg. 3)
+ * returns w^k, v^k, r_w^k, r_v^k in the same four places. */
 rs_status rs_get_state(const rs_handle* h, double* x, double* x_prev, double* r, double* r_prev);
 
 /* Ridge weights from the current iterate (host, d doubles). */

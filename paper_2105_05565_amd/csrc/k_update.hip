@@ -11,6 +11,9 @@
 //             sketched residual rho_{k+1} = S_{k+1}^T r^{k+1} is summed on the way;
 //   k_rho   : rho = S^T r on its own, with the same summation order, for iterations
 //             whose predecessor did not produce it.
+// The accelerated method (Alg. 3) uses the same kernels: k_update then also updates v and
+// r_v in place and writes r_z = alpha r_v + (1 - alpha) r_w, which is what the next
+// sketch is applied to, and the norm partials are those of r_v.
 // Once the stop test fires, a device flag turns every later kernel into a no-op, so
 // the state stays at the iteration that met the tolerance.
 #include "dev_common.h"
@@ -53,6 +56,18 @@ __global__ __launch_bounds__(kThreads) void k_init_state(const double* __restric
   }
   s = block_sum(s, scratch);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// v = 0, r_v = r_z = r^0 (Alg. 3 starts from w = v = 0)
+__global__ __launch_bounds__(kThreads) void k_init_accel(const double* __restrict__ r0, double* __restrict__ v,
+                                                         double* __restrict__ rv, double* __restrict__ rz,
+                                                         int64_t m) {
+  const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (j < m) {
+    v[j] = 0.0;
+    rv[j] = r0[j];
+    rz[j] = r0[j];
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_norm0(const double* __restrict__ partials, int32_t npart,
@@ -187,15 +202,25 @@ __device__ __forceinline__ double lane_value(double v, int l) {
   return __hiloint2double(hi, lo);
 }
 
+// Accelerated method (Alg. 3): v and r_v (updated in place), r_z (written), constants.
+struct AccelRows {
+  double* v;
+  double* rv;
+  double* rz;
+  double alpha, beta, gamma;
+};
+
 // Up to R rows of the update (j_u < 0: none), one wave: lane u loads and
-// updates row u, all rows' loads in flight together. Returns r^{k+1}_{j_u} (0 for none)
-// in every lane.
-template <typename ASV, int R>
+// updates row u, all rows' loads in flight together. Returns in every lane the new
+// residual entry whose norm is tracked (rn: r^{k+1}, or r_v^{k+1} for ACC) and the one
+// the next sketch is applied to (rq: r^{k+1}, or r_z^{k+1}), 0 for none.
+template <typename ASV, int R, bool ACC>
 __device__ __forceinline__ void update_rows(const int64_t (&j)[R], const ASV* __restrict__ AS,
                                             int64_t ldas, const double* dl, const int32_t* __restrict__ hmap,
                                             const double* __restrict__ x, double* __restrict__ xo,
                                             const double* __restrict__ r, double* __restrict__ ro,
-                                            double gamma, double beta, int lane, double (&rn)[R]) {
+                                            double gamma, double beta, const AccelRows& ac, int lane,
+                                            double (&rn)[R], double (&rq)[R]) {
   int64_t jl = -1;
 #pragma unroll
   for (int u = 0; u < R; ++u)
@@ -205,9 +230,14 @@ __device__ __forceinline__ void update_rows(const int64_t (&j)[R], const ASV* __
   if (jl >= 0) {  // issued ahead of the products so their latency overlaps them
     code = hmap[jl];
     rj = r[jl];
-    roj = ro[jl];
     xj = x[jl];
-    xoj = xo[jl];
+    if constexpr (ACC) {
+      roj = ac.rv[jl];  // r_v and v in place of r^{k-1} and x^{k-1}
+      xoj = ac.v[jl];
+    } else {
+      roj = ro[jl];
+      xoj = xo[jl];
+    }
   }
   double s[R];
   rows_dot(AS, j, ldas, dl, lane, s);
@@ -217,18 +247,43 @@ __device__ __forceinline__ void update_rows(const int64_t (&j)[R], const ASV* __
     const double t = wave_sum(s[u]);
     if (lane == u) sl = t;
   }
-  double rnl = 0.0;
+  double rnl = 0.0, rql = 0.0;
   if (jl >= 0) {
     double sd = 0.0;
     if (code >= 0) sd = (code & 1) ? -dl[code >> 1] : dl[code >> 1];
-    const double onepb = 1.0 + beta;
-    rnl = onepb * rj - beta * roj - gamma * sl;
-    const double xn = onepb * xj - beta * xoj - gamma * sd;
-    ro[jl] = rnl;
-    xo[jl] = xn;
+    if constexpr (ACC) {
+      // w = xj, v = xoj, r_w = rj, r_v = roj; g_j = sd, (A g)_j = sl
+      const double z = ac.alpha * xoj + (1.0 - ac.alpha) * xj;
+      const double rz = ac.alpha * roj + (1.0 - ac.alpha) * rj;
+      const double wn = z - sd;
+      const double vn = ac.beta * xoj + (1.0 - ac.beta) * z - ac.gamma * sd;
+      const double rwn = rz - sl;
+      const double rvn = ac.beta * roj + (1.0 - ac.beta) * rz - ac.gamma * sl;
+      const double rzn = ac.alpha * rvn + (1.0 - ac.alpha) * rwn;
+      xo[jl] = wn;
+      ro[jl] = rwn;
+      ac.v[jl] = vn;
+      ac.rv[jl] = rvn;
+      ac.rz[jl] = rzn;
+      rnl = rvn;
+      rql = rzn;
+    } else {
+      const double onepb = 1.0 + beta;
+      rnl = onepb * rj - beta * roj - gamma * sl;
+      const double xn = onepb * xj - beta * xoj - gamma * sd;
+      ro[jl] = rnl;
+      xo[jl] = xn;
+      rql = rnl;
+    }
   }
 #pragma unroll
-  for (int u = 0; u < R; ++u) rn[u] = lane_value(rnl, u);
+  for (int u = 0; u < R; ++u) {
+    rn[u] = lane_value(rnl, u);
+    if constexpr (ACC)
+      rq[u] = lane_value(rql, u);
+    else
+      rq[u] = rn[u];
+  }
 }
 
 template <typename ASV>
@@ -253,9 +308,10 @@ struct UpdateArgs {
   double* rho_n;
   int32_t nbucket_blocks;  // workgroups in the bucket-major part
   const DevFlags* flags;
+  AccelRows acc;           // accelerated method only
 };
 
-template <typename ASV>
+template <typename ASV, bool ACC>
 // 8 waves per SIMD (at most 64 VGPRs): two workgroups per CU, also beside the
 // batch-preparation kernels of the next lookahead batch
 __global__ __launch_bounds__(kUpdateThreads, 8) void k_update(UpdateArgs<ASV> a) {
@@ -281,14 +337,15 @@ __global__ __launch_bounds__(kUpdateThreads, 8) void k_update(UpdateArgs<ASV> a)
         const int p = p0 + u * kBucketWaves;
         j[u] = p < pe ? (int64_t)a.members_n[p] : -1;
       }
-      double rn[R];
-      update_rows<ASV, R>(j, a.AS, a.ldas, dl, a.hmap, a.x, a.xo, a.r, a.ro, a.gamma, a.beta, lane, rn);
+      double rn[R], rq[R];
+      update_rows<ASV, R, ACC>(j, a.AS, a.ldas, dl, a.hmap, a.x, a.xo, a.r, a.ro, a.gamma, a.beta, a.acc, lane,
+                               rn, rq);
       if (lane == 0) {
 #pragma unroll
         for (int u = 0; u < R; ++u)
           if (j[u] >= 0) {
             ss += rn[u] * rn[u];
-            rs += (a.hmap_n[j[u]] & 1) ? -rn[u] : rn[u];
+            rs += (a.hmap_n[j[u]] & 1) ? -rq[u] : rq[u];
           }
       }
     }
@@ -312,8 +369,9 @@ __global__ __launch_bounds__(kUpdateThreads, 8) void k_update(UpdateArgs<ASV> a)
         const int64_t jj = jb + (int64_t)u * nw;
         j[u] = (jj < j1 && !(a.hmap_n && a.hmap_n[jj] >= 0)) ? jj : -1;
       }
-      double rn[R];
-      update_rows<ASV, R>(j, a.AS, a.ldas, dl, a.hmap, a.x, a.xo, a.r, a.ro, a.gamma, a.beta, lane, rn);
+      double rn[R], rq[R];
+      update_rows<ASV, R, ACC>(j, a.AS, a.ldas, dl, a.hmap, a.x, a.xo, a.r, a.ro, a.gamma, a.beta, a.acc, lane,
+                               rn, rq);
       if (lane == 0) {
 #pragma unroll
         for (int u = 0; u < R; ++u) ss += rn[u] * rn[u];
@@ -357,6 +415,13 @@ hipError_t launch_init_state(const double* b, double* x0, double* x1, double* r0
   return hipGetLastError();
 }
 
+hipError_t launch_init_accel(const double* r0, double* v, double* rv, double* rz, int64_t m, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_init_accel, dim3((unsigned)((m + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, r0, v,
+                     rv, rz, m);
+  return hipGetLastError();
+}
+
 hipError_t launch_rho(const double* r, const int32_t* hmap, const int32_t* members,
                       const int32_t* offs, int32_t tau, double* rho, const DevFlags* flags,
                       hipStream_t s) {
@@ -381,7 +446,7 @@ hipError_t update_launch(const ASV* AS, int64_t ldas, int32_t tau, const double*
                          double* partials, int32_t npart, const int32_t* hmap_next,
                          const int32_t* members_next, const int32_t* offs_next,
                          int32_t next_covers_all, double* rho_next, const DevFlags* flags,
-                         hipStream_t s) {
+                         const AccelRows* acc, hipStream_t s) {
   UpdateArgs<ASV> a;
   a.AS = AS;
   a.ldas = ldas;
@@ -407,8 +472,12 @@ hipError_t update_launch(const ASV* AS, int64_t ldas, int32_t tau, const double*
   const int32_t nrow_blocks = (int32_t)((m + rows_per_block - 1) / rows_per_block);
   const int32_t grid = tau + nrow_blocks;
   if (grid != npart) return hipErrorInvalidValue;
+  a.acc = acc ? *acc : AccelRows{nullptr, nullptr, nullptr, 0.0, 0.0, 0.0};
   // without a next sketch the bucket part is empty: its partial slots are written as zero
-  hipLaunchKernelGGL(k_update<ASV>, dim3(grid), dim3(kUpdateThreads), sizeof(double) * ldas, s, a);
+  if (acc)
+    hipLaunchKernelGGL((k_update<ASV, true>), dim3(grid), dim3(kUpdateThreads), sizeof(double) * ldas, s, a);
+  else
+    hipLaunchKernelGGL((k_update<ASV, false>), dim3(grid), dim3(kUpdateThreads), sizeof(double) * ldas, s, a);
   return hipGetLastError();
 }
 
@@ -422,10 +491,21 @@ hipError_t launch_update(const void* AS, int32_t as_f32, int64_t ldas, int32_t t
   if (as_f32)
     return update_launch<float>((const float*)AS, ldas, tau, delta, hmap, m, x, x_prev_out, r,
                                 r_prev_out, gamma, beta, partials, npart, hmap_next, members_next,
-                                offs_next, next_covers_all, rho_next, flags, s);
+                                offs_next, next_covers_all, rho_next, flags, nullptr, s);
   return update_launch<double>((const double*)AS, ldas, tau, delta, hmap, m, x, x_prev_out, r,
                                r_prev_out, gamma, beta, partials, npart, hmap_next, members_next,
-                               offs_next, next_covers_all, rho_next, flags, s);
+                               offs_next, next_covers_all, rho_next, flags, nullptr, s);
+}
+
+hipError_t launch_update_accel(const double* AS, int64_t ldas, int32_t tau, const double* delta,
+                               const int32_t* hmap, int64_t m, const double* w, double* w_out, const double* rw,
+                               double* rw_out, double* v, double* rv, double* rz, double alpha, double beta,
+                               double gamma, double* partials, int32_t npart, const int32_t* hmap_next,
+                               const int32_t* members_next, const int32_t* offs_next, int32_t next_covers_all,
+                               double* rho_next, const DevFlags* flags, hipStream_t s) {
+  const AccelRows acc{v, rv, rz, alpha, beta, gamma};
+  return update_launch<double>(AS, ldas, tau, delta, hmap, m, w, w_out, rw, rw_out, 0.0, 0.0, partials, npart,
+                               hmap_next, members_next, offs_next, next_covers_all, rho_next, flags, &acc, s);
 }
 
 hipError_t launch_finalize(const double* partials, int32_t npart, DevFlags* flags, double* hist,

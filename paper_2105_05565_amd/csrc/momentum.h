@@ -3,6 +3,7 @@
 #pragma once
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 
 #include "../../include/rs.h"
@@ -69,6 +70,15 @@ inline void momentum_schedule(const rs_options& o, int64_t sw, int64_t k, double
       return;
     }
   }
+}
+
+// Constants of the accelerated method (Alg. 3) for 0 < mu <= 1 <= nu <= 1 / mu, in this
+// FP64 order: beta = 1 - sqrt(mu / nu), gamma = sqrt(1 / (mu nu)), alpha = 1 / (1 + sqrt(nu / mu)).
+inline void accel_constants(double mu, double nu, double* alpha, double* beta, double* gamma) {
+#pragma clang fp contract(off)
+  *beta = 1.0 - std::sqrt(mu / nu);
+  *gamma = std::sqrt(1.0 / (mu * nu));
+  *alpha = 1.0 / (1.0 + std::sqrt(nu / mu));
 }
 
 // Validation of the momentum settings; returns nullptr when they are usable.

@@ -28,6 +28,12 @@ struct rs_handle {
   double lam = 0.0;
   int64_t mom_switch = 0;  // switch index of the theoretical momentum rule
   bool kern = false;        // kernel ridge: Z holds the symmetric kernel matrix (m = K = n)
+  // accelerated method (Alg. 3): v, r_v, r_z and its constants
+  bool accel = false;
+  double* vbuf = nullptr;
+  double* rvbuf = nullptr;
+  double* rzbuf = nullptr;
+  double acc_alpha = 0.0, acc_beta = 0.0, acc_gamma = 0.0;
   int64_t pdim = 0;         // kernel ridge: dimension of the points
   bool sparse = false;
   int kind = kSubsample;
@@ -338,7 +344,9 @@ void iterate_batch(rs_handle* h, int p, int64_t k0, int nb) {
   use_set(h, p);
   int pe = -1;
   // rho_{k0} = S_{k0}^T r^{k0}; later iterations get rho from the preceding update
-  check_hip(launch_rho(h->rbuf[k0 & 1], h->hmap, h->members, h->offs, h->tau, h->rho, h->flags, s),
+  // (accelerated method: the sketch is applied to r_z)
+  check_hip(launch_rho(h->accel ? h->rzbuf : h->rbuf[k0 & 1], h->hmap, h->members, h->offs, h->tau, h->rho,
+                       h->flags, s),
             "rho");
   const int pe_iters = prof_begin(h, RS_PROF_ITERS, nb);
   for (int i = 0; i < nb; ++i) {
@@ -380,14 +388,21 @@ void iterate_batch(rs_handle* h, int p, int64_t k0, int nb) {
     const bool has_next = i + 1 < nb;
     const size_t as_elt = h->mixed ? sizeof(float) : sizeof(double);
     const void* as_i = (const char*)h->AS + (size_t)i * h->m * h->ldas * as_elt;
-    check_hip(launch_update(as_i, h->mixed ? 1 : 0, h->ldas, h->tau, h->delta, hm, h->m,
-                            h->xbuf[cur], h->xbuf[nxt], h->rbuf[cur], h->rbuf[nxt], gamma, beta,
-                            h->partials, h->npart,
-                            has_next ? h->hmap + (int64_t)(i + 1) * h->m : nullptr,
-                            has_next ? h->members + (int64_t)(i + 1) * h->nsel : nullptr,
-                            has_next ? h->offs + (int64_t)(i + 1) * (h->tau + 1) : nullptr,
-                            h->kind == kCount ? 1 : 0, h->rho, h->flags, s),
-              "update");
+    const int32_t* hm_n = has_next ? h->hmap + (int64_t)(i + 1) * h->m : nullptr;
+    const int32_t* mem_n = has_next ? h->members + (int64_t)(i + 1) * h->nsel : nullptr;
+    const int32_t* offs_n = has_next ? h->offs + (int64_t)(i + 1) * (h->tau + 1) : nullptr;
+    if (h->accel)
+      check_hip(launch_update_accel((const double*)as_i, h->ldas, h->tau, h->delta, hm, h->m, h->xbuf[cur],
+                                    h->xbuf[nxt], h->rbuf[cur], h->rbuf[nxt], h->vbuf, h->rvbuf, h->rzbuf,
+                                    h->acc_alpha, h->acc_beta, h->acc_gamma, h->partials, h->npart, hm_n,
+                                    mem_n, offs_n, h->kind == kCount ? 1 : 0, h->rho, h->flags, s),
+                "update (accelerated)");
+    else
+      check_hip(launch_update(as_i, h->mixed ? 1 : 0, h->ldas, h->tau, h->delta, hm, h->m,
+                              h->xbuf[cur], h->xbuf[nxt], h->rbuf[cur], h->rbuf[nxt], gamma, beta,
+                              h->partials, h->npart, hm_n, mem_n, offs_n,
+                              h->kind == kCount ? 1 : 0, h->rho, h->flags, s),
+                "update");
     prof_end(h, pe);
     if (h->mixed && (k + 1) % h->opt.refresh_every == 0) {
       refresh(h, k + 1);
@@ -558,6 +573,9 @@ rs_status rs_options_default(rs_options* o) {
   o->trace_capacity = 0;
   o->sparse_route = RS_ROUTE_AUTO;
   o->pipeline = 1;
+  o->accelerated = 0;
+  o->accel_mu = 1.0;
+  o->accel_nu = 1.0;
   return RS_OK;
 }
 
@@ -637,6 +655,15 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
       throw Fail{RS_EUNSUPPORTED, "proposals and traces are built for the subsample sketch on dense data"};
     if (const char* why = momentum_invalid(*o)) throw Fail{RS_EINVAL, why};
     h->mom_switch = momentum_switch(o->eta, o->beta_max);
+    if (o->accelerated != 0) {
+      const double mu = o->accel_mu, nu = o->accel_nu;
+      if (!(mu > 0.0 && mu <= 1.0) || !(nu >= 1.0 && nu <= 1.0 / mu))
+        throw Fail{RS_EINVAL, "the accelerated method needs 0 < mu <= 1 and 1 <= nu <= 1 / mu"};
+      if (o->precision != RS_PREC_FP64 || o->sampler != RS_SAMPLER_UNIFORM || o->trace_every != 0)
+        throw Fail{RS_EUNSUPPORTED, "the accelerated method runs in FP64 with uniform sampling"};
+      h->accel = true;
+      accel_constants(mu, nu, &h->acc_alpha, &h->acc_beta, &h->acc_gamma);
+    }
     if (!(o->tol >= 0.0)) throw Fail{RS_EINVAL, "tol must be >= 0"};
     if (o->max_iter < 0 || o->max_iter > 100000000) throw Fail{RS_EINVAL, "max_iter out of range"};
     h->form = o->form == RS_FORM_AUTO ? (d <= n ? RS_FORM_PRIMAL : RS_FORM_DUAL) : o->form;
@@ -875,6 +902,11 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
       h->xbuf[i] = dalloc<double>(h, h->m);
       h->rbuf[i] = dalloc<double>(h, h->m);
     }
+    if (h->accel) {
+      h->vbuf = dalloc<double>(h, h->m);
+      h->rvbuf = dalloc<double>(h, h->m);
+      h->rzbuf = dalloc<double>(h, h->m);
+    }
     h->sampler = o->sampler;
     h->trace_every = o->trace_every;
     if (h->sampler != RS_SAMPLER_UNIFORM || h->trace_every > 0) {
@@ -920,6 +952,7 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
     check_hip(launch_init_state(h->b, h->xbuf[0], h->xbuf[1], h->rbuf[0], h->rbuf[1], h->m,
                                 h->partials, h->npart, h->flags, h->hist, s),
               "init");
+    if (h->accel) check_hip(launch_init_accel(h->rbuf[0], h->vbuf, h->rvbuf, h->rzbuf, h->m, s), "init");
     DevFlags f{};
     check_hip(hipMemcpyAsync(&f, h->flags, sizeof(DevFlags), hipMemcpyDeviceToHost, s), "flags");
     check_hip(hipStreamSynchronize(s), "sync");
@@ -991,6 +1024,8 @@ rs_status rs_reset(rs_handle* h, uint64_t seed) {
     check_hip(launch_init_state(h->b, h->xbuf[0], h->xbuf[1], h->rbuf[0], h->rbuf[1], h->m,
                                 h->partials, h->npart, h->flags, h->hist, h->stream),
               "init");
+    if (h->accel)
+      check_hip(launch_init_accel(h->rbuf[0], h->vbuf, h->rvbuf, h->rzbuf, h->m, h->stream), "init");
     DevFlags f{};
     check_hip(hipMemcpyAsync(&f, h->flags, sizeof(DevFlags), hipMemcpyDeviceToHost, h->stream), "flags");
     check_hip(hipStreamSynchronize(h->stream), "sync");
@@ -1079,7 +1114,8 @@ rs_status rs_solve(rs_handle* h, double* w_out, rs_report* rep) {
 rs_status rs_get_state(const rs_handle* h, double* x, double* x_prev, double* r, double* r_prev) {
   if (!h) return RS_EINVAL;
   const int cur = (int)(h->k & 1), prv = 1 - cur;
-  const double* src[4] = {h->xbuf[cur], h->xbuf[prv], h->rbuf[cur], h->rbuf[prv]};
+  const double* src[4] = {h->xbuf[cur], h->accel ? h->vbuf : h->xbuf[prv], h->rbuf[cur],
+                          h->accel ? h->rvbuf : h->rbuf[prv]};
   double* dst[4] = {x, x_prev, r, r_prev};
   for (int i = 0; i < 4; ++i)
     if (dst[i] && hipMemcpy(dst[i], src[i], sizeof(double) * h->m, hipMemcpyDeviceToHost) != hipSuccess)

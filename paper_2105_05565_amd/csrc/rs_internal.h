@@ -329,6 +329,17 @@ hipError_t launch_update(const void* AS, int32_t as_f32, int64_t ldas, int32_t t
                          const int32_t* members_next, const int32_t* offs_next,
                          int32_t next_covers_all, double* rho_next, const DevFlags* flags,
                          hipStream_t s);
+// Accelerated method (Alg. 3), FP64 AS: w' = z - S delta and r_w' = r_z - AS delta into
+// w_out / rw_out; v, r_v updated in place; r_z = alpha r_v' + (1 - alpha) r_w' written;
+// the norm partials are those of r_v' and rho_next is taken from r_z'.
+hipError_t launch_update_accel(const double* AS, int64_t ldas, int32_t tau, const double* delta,
+                               const int32_t* hmap, int64_t m, const double* w, double* w_out, const double* rw,
+                               double* rw_out, double* v, double* rv, double* rz, double alpha, double beta,
+                               double gamma, double* partials, int32_t npart, const int32_t* hmap_next,
+                               const int32_t* members_next, const int32_t* offs_next, int32_t next_covers_all,
+                               double* rho_next, const DevFlags* flags, hipStream_t s);
+// v = 0, r_v = r_z = r0 (m entries).
+hipError_t launch_init_accel(const double* r0, double* v, double* rv, double* rz, int64_t m, hipStream_t s);
 hipError_t launch_finalize(const double* partials, int32_t npart, DevFlags* flags, double* hist,
                            int64_t k, double tol, hipStream_t s);
 

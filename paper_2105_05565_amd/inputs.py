@@ -153,6 +153,20 @@ def kernel_boston(seed=DATA_SEED_BASE + 6):
     return make_points(506, 13, 1e-6, 0.5 * np.sqrt(13.0 / 8.0), seed, name="kernel_boston_506x13")
 
 
+def accel_points(seed=DATA_SEED_BASE + 7):
+    """The acceleration experiment's problem: kernel ridge with sigma = 0.5 and lambda = 1/n on
+    the rows of a random sparse 2000 x 500 matrix of density 0.25 (values uniform on [0, 1),
+    exactly round(0.25 n d) distinct uniform positions), as dense points; subsample tau =
+    floor(m^(2/3)) = 158."""
+    n, d = 2000, 500
+    rng = np.random.Generator(np.random.PCG64(seed))
+    X = csr_matrix(n, d, int(round(0.25 * n * d)), rng, np.float64)
+    X.data = rng.random(X.nnz)
+    P = np.ascontiguousarray(X.toarray())
+    y = rng.standard_normal(n)
+    return KernelProblem("accel_sparse_2000x500", P, y, 1.0 / n, 0.5)
+
+
 def batched_tau(m):
     """Sketch size of a batched problem: a multiple of 64 near m^(2/3), clamped to [64, 512]
     and to m (the per-problem rule of the batched workload)."""

@@ -208,3 +208,22 @@ def test_kernel_create_rejects_csr_points():
     with pytest.raises(rs.RsError) as e:
         rs.rs_create_kernel(M, np.ones(20), 0.5, 1.0, o)
     assert e.value.status == rs.RS_EINVAL
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(accelerated=1, accel_mu=0.0, accel_nu=1.0), rs.RS_EINVAL),
+    (dict(accelerated=1, accel_mu=1.5, accel_nu=1.0), rs.RS_EINVAL),
+    (dict(accelerated=1, accel_mu=0.5, accel_nu=0.9), rs.RS_EINVAL),
+    (dict(accelerated=1, accel_mu=0.5, accel_nu=2.5), rs.RS_EINVAL),
+    (dict(accelerated=1, accel_mu=math.nan, accel_nu=1.0), rs.RS_EINVAL),
+    (dict(accelerated=1, precision=rs.RS_PREC_MIXED_BF16), rs.RS_EUNSUPPORTED),
+])
+def test_accelerated_settings_rejected_without_device(kw, status):
+    with pytest.raises(rs.RsError) as e:
+        _create(np.ones((20, 8)), np.ones(20), 1.0, tau=3, **kw)
+    assert e.value.status == status
+
+
+def test_accelerated_defaults():
+    o = rs.rs_options_default()
+    assert o.accelerated == 0 and o.accel_mu == 1.0 and o.accel_nu == 1.0
