@@ -26,6 +26,15 @@ Draws:
 * Weighted subsample (a distribution D other than uniform, Sec. 3 and the
   non-uniform sampling of Sec. 7): u_i = ((W0_i >> 12) + 0.5) * 2^-52 and
   key_i = u_i / q_i in IEEE FP64; the tau smallest (key_i, i) are kept.
+* Gaussian (Def. 4.1): S_ic ~ N(0, 1) i.i.d. Entry (i, c) comes from the block with
+  counter (i * G + c // 4, k, 6, slot), G = ceil(tau / 4): uniforms
+  u = ((W >> 11) + 0.5) * 2^-53 and the Box-Muller transform of the pairs (W0, W1)
+  (columns 4g, 4g + 1) and (W2, W3) (columns 4g + 2, 4g + 3):
+  sqrt(-2 ln u_a) cos(2 pi u_b), sqrt(-2 ln u_a) sin(2 pi u_b).
+* SRHT (Def. 4.4): S^T = I_C H_{m'} D / sqrt(tau m') with m' = 2^ceil(log2 m) and A
+  padded with zero rows, so S holds the first m rows of D H_{m'} I_C^T / sqrt(tau m'):
+  S_ic = d_i (-1)^popcount(i & C_c) / sqrt(tau m'). C: the tau smallest (W0_j, j) over
+  j < m' (tag 7), ascending; d_i = -1 if W1_i (same block) is odd, else +1.
 
 Part of the oracle: test infrastructure only.
 """
@@ -40,6 +49,8 @@ TAG_SUBSAMPLE = 1
 TAG_COUNT = 2
 TAG_SUBCOUNT = 3
 TAG_WEIGHTED = 4
+TAG_GAUSSIAN = 6
+TAG_SRHT = 7
 
 
 def _blocks(seed, problem_id, k, tag, slot, m):
@@ -65,7 +76,7 @@ def subcount_k(m, tau):
 
 @dataclass
 class Sketch:
-    kind: str            # "subsample" | "count" | "subcount" | "weighted"
+    kind: str            # "subsample" | "count" | "subcount" | "weighted" | "gaussian" | "srht"
     m: int
     tau: int
     rows: np.ndarray     # int64: coordinates carrying a nonzero of S
@@ -128,6 +139,66 @@ def draw_weighted(seed, problem_id, k, q, tau, slot=0):
     return Sketch("weighted", m, tau, C, np.arange(tau, dtype=np.int64), np.ones(tau))
 
 
+def _dense_sketch(kind, S):
+    m, tau = S.shape
+    rows = np.repeat(np.arange(m, dtype=np.int64), tau)
+    cols = np.tile(np.arange(tau, dtype=np.int64), m)
+    return Sketch(kind, m, tau, rows, cols, S.reshape(-1).copy())
+
+
+def gaussian_matrix(seed, problem_id, k, m, tau, slot=0):
+    """The m x tau Gaussian sketch (Def. 4.1) as a dense array."""
+    if tau < 1 or m < 1:
+        raise ValueError("Gaussian sketch needs m, tau >= 1")
+    G = (tau + 3) // 4
+    j = (np.arange(m, dtype=np.uint64)[:, None] * np.uint64(G) + np.arange(G, dtype=np.uint64)[None, :]).ravel()
+    w = philox4x64_10(j, np.uint64(k), np.uint64(TAG_GAUSSIAN), np.uint64(slot), np.uint64(seed),
+                      np.uint64(problem_id))
+    u = [((x >> np.uint64(11)).astype(np.float64) + 0.5) * 2.0 ** -53 for x in w]
+    r01, t01 = np.sqrt(-2.0 * np.log(u[0])), 2.0 * np.pi * u[1]
+    r23, t23 = np.sqrt(-2.0 * np.log(u[2])), 2.0 * np.pi * u[3]
+    z = np.stack([r01 * np.cos(t01), r01 * np.sin(t01), r23 * np.cos(t23), r23 * np.sin(t23)], axis=1)
+    return z.reshape(m, 4 * G)[:, :tau].copy()
+
+
+def draw_gaussian(seed, problem_id, k, m, tau, slot=0):
+    return _dense_sketch("gaussian", gaussian_matrix(seed, problem_id, k, m, tau, slot))
+
+
+def srht_padded_size(m):
+    """m' = 2^ceil(log2 m) (Sec. 4.3: A is padded with zero rows to a power of 2)."""
+    return 1 << max(0, int(m - 1).bit_length())
+
+
+def srht_parts(seed, problem_id, k, m, tau, slot=0):
+    """(C, d, m') of the SRHT sketch: C ascending in [0, m'), signs d for the first m rows."""
+    mp = srht_padded_size(m)
+    if not (1 <= tau <= mp):
+        raise ValueError("SRHT needs 1 <= tau <= m'")
+    w0, w1, _, _ = _blocks(seed, problem_id, k, TAG_SRHT, slot, mp)
+    C = np.sort(_smallest(w0, tau)).astype(np.int64)
+    d = np.where((w1[:m] & np.uint64(1)) == 1, -1.0, 1.0)
+    return C, d, mp
+
+
+def srht_matrix(seed, problem_id, k, m, tau, slot=0):
+    """The m x tau SRHT sketch (Def. 4.4) as a dense array, from the closed form of the
+    Sylvester Hadamard entries H_ij = (-1)^popcount(i & j)."""
+    C, d, mp = srht_parts(seed, problem_id, k, m, tau, slot)
+    i = np.arange(m, dtype=np.int64)[:, None]
+    bits = np.bitwise_and(i, C[None, :])
+    par = np.zeros(bits.shape, dtype=np.int64)
+    while np.any(bits):
+        par ^= bits & 1
+        bits >>= 1
+    H = 1.0 - 2.0 * par
+    return d[:, None] * H * (1.0 / np.sqrt(float(tau) * float(mp)))
+
+
+def draw_srht(seed, problem_id, k, m, tau, slot=0):
+    return _dense_sketch("srht", srht_matrix(seed, problem_id, k, m, tau, slot))
+
+
 def draw(kind, seed, problem_id, k, m, tau, sum_size=0, slot=0, q=None):
     if kind == "subsample":
         return draw_subsample(seed, problem_id, k, m, tau, slot)
@@ -137,4 +208,8 @@ def draw(kind, seed, problem_id, k, m, tau, sum_size=0, slot=0, q=None):
         return draw_subcount(seed, problem_id, k, m, tau, sum_size, slot)
     if kind == "weighted":
         return draw_weighted(seed, problem_id, k, q, tau, slot)
+    if kind == "gaussian":
+        return draw_gaussian(seed, problem_id, k, m, tau, slot)
+    if kind == "srht":
+        return draw_srht(seed, problem_id, k, m, tau, slot)
     raise ValueError(f"unknown sketch kind {kind!r}")
