@@ -49,6 +49,8 @@ WORKLOADS = {
                               name="kernel_rbf_20640x8_sigma0.5_lambda1e-6_subsample_tau5160"),
     "accel_grid": dict(kind="kernel", sketch="subsample", tau=158, sub_k=0, precision="fp64",
                        name="accel_grid_kernel_rbf_2000_sigma0.5_lambda1/n_tau158_tol1e-4"),
+    "sketch_compare": dict(kind="kernel", sketch="subsample", tau=126, sub_k=0, precision="fp64",
+                           name="sketches_kernel_boston_506x13_tau126_and_dense_2000x500_tau50"),
     "batched": dict(kind="batch", precision="fp64",
                     name="batched_64problems_n2000-40000_d500-8000_half_csr0.005_16lambda_4rhs"),
 }
@@ -157,7 +159,8 @@ def kernel_table(prof, wl, workload, n, d, nnz, m, K, nsel, total, a_nnz=0):
                 "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None, "traffic": None,
                 "alg_bytes_per_launch": kd["alg_bytes_per_launch"], "avg_launch_ms": kd["avg_ms"]}
     if wl["kind"] in ("dense", "kernel") and dom == "as":
-        flops = 2.0 * m * wl["tau"] * K * kd["slots_per_launch"]
+        # a dense sketch takes two products per sketch (T = Z^T S, then Z T)
+        flops = 2.0 * m * wl["tau"] * K * kd["slots_per_launch"] * wl.get("as_products", 1)
         tfs = flops / (kd["avg_ms"] * 1e-3) / 1e12
         peak = BF16_PEAK_TFS if wl["precision"] == "mixed" else FP64_PEAK_TFS
         roofline.update({"kernel": "k_as_dense_bf16" if wl["precision"] == "mixed" else "k_as_dense_f64_128",
@@ -438,6 +441,70 @@ def main_learned(args):
     print(json.dumps(out))
 
 
+def main_sketches(args):
+    """The sketch comparison (Sec. 9): subsample, count, SubCount, Gaussian and SRHT sketches with
+    the heuristic momentum on the kernel problem shaped like Boston (506 points, tau = 126,
+    lambda = 1e-6) and on the dense workload (2000 x 500, tau = 50); median time and iterations
+    to relative residual 1e-6 over seeded solves."""
+    import numpy as np
+    import torch
+
+    from paper_2105_05565_amd import inputs, rs
+
+    wl = WORKLOADS["sketch_compare"]
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    runs = max(1, args.steps)
+    kinds = ["subsample", "count", "subcount", "gaussian", "srht"]
+    pb = inputs.kernel_boston()
+    pd = inputs.dense_primal()
+    problems = [("kernel_boston_506x13", pb, 126), ("dense_2000x500", pd, 50)]
+    results = {}
+    prof_first = None
+    for pname, p, tau in problems:
+        kern = pname.startswith("kernel")
+        X = torch.from_numpy(p.P if kern else p.X).cuda()
+        y = torch.from_numpy(p.y).cuda()
+        res = {}
+        for kind in kinds:
+            kw = dict(kernel_sigma=p.sigma) if kern else dict(form="primal")
+            S = rs.Solver(X, y, p.lam, tau=tau, sketch=kind, tol=1e-6, max_iter=args.max_iter, seed=1,
+                          stream=stream, profile=1, **kw)
+            S.reset(1000)
+            S.solve()
+            S.profile(clear=True)
+            ts, its = [], []
+            for r in range(runs):
+                S.reset(r + 1)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, st, rep = S.solve()
+                ts.append(time.perf_counter() - t0)
+                its.append(rep.iters if st == rs.RS_OK else -1)
+            prof = S.profile()
+            S.close()
+            res[kind] = {"median_s": round(statistics.median(ts), 6), "median_iters": statistics.median(its),
+                         "all_converged": min(its) >= 0,
+                         "ms_per_iter": round(1e3 * sum(ts) / max(1, sum(i for i in its if i > 0)), 4)}
+            if prof_first is None and kind == "gaussian":
+                prof_first = (prof, sum(ts), p, tau, kern)
+            print(f"[bench] {pname} {kind}: {res[kind]}", file=sys.stderr, flush=True)
+        results[pname] = res
+    prof, total, p, tau, kern = prof_first
+    n = p.P.shape[0]
+    wl_k = dict(wl, tau=tau, as_products=2)
+    kernels, roofline = kernel_table(prof, wl_k, "sketch_compare", n, p.P.shape[1], n * p.P.shape[1], n, n, tau, total)
+    T = results["kernel_boston_506x13"]["subsample"]["median_s"]
+    out = {
+        "metric": "time-to-rel-residual 1e-6 by sketch (value: subsample on the Boston-shaped kernel problem)",
+        "value": T, "unit": "s", "n_gpus": 1, "steps": runs, "warmup": 1, "ms_per_step": round(T * 1e3, 4),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl["name"], "momentum": "heuristic", "tol": 1e-6, "runs": runs},
+        "results": results, "roofline_gaussian_kernel": roofline, "kernels_gaussian_kernel": kernels,
+    }
+    print(json.dumps(out))
+
+
 def main_accel(args):
     """Accelerated method (Alg. 3) over a (mu, nu) grid with 0 < mu <= 1/nu <= 1, on the
     acceleration experiment's kernel problem (rows of a random sparse 2000 x 500 matrix,
@@ -593,6 +660,8 @@ def main():
         return main_learned(args)
     if args.workload == "accel_grid":
         return main_accel(args)
+    if args.workload == "sketch_compare":
+        return main_sketches(args)
 
     import numpy as np
     import torch

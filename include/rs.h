@@ -70,8 +70,15 @@ typedef struct rs_matrix {
 
 /* Form of the linear system (Sec. 2.1): AUTO picks primal when d <= n. */
 enum { RS_FORM_AUTO = 0, RS_FORM_PRIMAL = 1, RS_FORM_DUAL = 2 };
-/* Sketch distribution D (Sec. 4). */
-enum { RS_SKETCH_SUBSAMPLE = 0, RS_SKETCH_COUNT = 1, RS_SKETCH_SUBCOUNT = 2 };
+/* Sketch distribution D (Sec. 4). GAUSSIAN (Def. 4.1): S_ic ~ N(0, 1) from Box-Muller on
+ * Philox uniforms. SRHT (Def. 4.4): S^T = I_C H D / sqrt(tau m') with m' = 2^ceil(log2 m) and
+ * A padded with zero rows, i.e. S_ic = d_i (-1)^popcount(i & C_c) / sqrt(tau m') for i < m, C a
+ * uniform tau-subset of [0, m'). Both are dense (m x tau per sketch; products on FP64 MFMA),
+ * for dense X or kernel ridge, FP64, uniform sampling, momentum schedules (not the
+ * accelerated method). A heavily padded SRHT (m well below m') can draw linearly dependent
+ * columns; the factorisation then reports RS_ESINGULAR. */
+enum { RS_SKETCH_SUBSAMPLE = 0, RS_SKETCH_COUNT = 1, RS_SKETCH_SUBCOUNT = 2, RS_SKETCH_GAUSSIAN = 3,
+       RS_SKETCH_SRHT = 4 };
 /* Momentum schedule (Sec. 6, Sec. 9.1):
  *  NONE      gamma = 1, beta = 0 (Alg. 1)
  *  CONSTANT  gamma = opts.gamma, beta = opts.beta (0.5 in the paper's comparison)

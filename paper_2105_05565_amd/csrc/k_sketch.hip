@@ -88,7 +88,7 @@ __device__ __forceinline__ void select_body(const SketchArgs& a, int slot, unsig
   const int tid = threadIdx.x;
   const int64_t m = a.m;
   const uint64_t k = (uint64_t)((a.kdev ? *a.kdev : a.k0) + slot);
-  const uint64_t tag = (a.kind == kSubcount) ? kTagSubcount : kTagSubsample;
+  const uint64_t tag = (a.kind == kSubcount) ? kTagSubcount : (a.kind == kSrht ? kTagSrht : kTagSubsample);
   const bool weighted = a.kind == kWeighted;
   const bool q_ok = weighted && a.q_ok && *a.q_ok != 0;
   uint64_t* keys = a.keys + (int64_t)slot * m;

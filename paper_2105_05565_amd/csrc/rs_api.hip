@@ -28,6 +28,12 @@ struct rs_handle {
   double lam = 0.0;
   int64_t mom_switch = 0;  // switch index of the theoretical momentum rule
   bool kern = false;        // kernel ridge: Z holds the symmetric kernel matrix (m = K = n)
+  // dense sketches (Gaussian, SRHT): padded size m' of the SRHT, S of the iterating set,
+  // scratch of S^T r
+  bool dense_s = false;
+  int64_t mpad = 0;
+  double* S = nullptr;
+  double* rho_part = nullptr;
   // accelerated method (Alg. 3): v, r_v, r_z and its constants
   bool accel = false;
   double* vbuf = nullptr;
@@ -85,6 +91,8 @@ struct rs_handle {
     void* AS = nullptr;
     double* G = nullptr;
     int32_t* status = nullptr;
+    double* S = nullptr;  // dense sketches: S (m x ldas per slot) and T = Z^T S (K x ldas per slot)
+    double* T = nullptr;
   };
   BatchSet sets[2];
   int nsets = 1;
@@ -281,14 +289,51 @@ void prep_batch(rs_handle* h, int p, int64_t k0, int nb, hipStream_t s) {
     a.q = h->q;
     a.q_ok = h->q_ok;
   }
-  check_hip(launch_sketch(a, s), "sketch");
+  if (h->kind == kGaussian) {
+    check_hip(launch_sketch_gauss(bs.S, h->m, h->tau, h->ldas, h->opt.seed, h->opt.problem_id, k0, nb, bs.offs,
+                                  done, s),
+              "sketch (Gaussian)");
+  } else if (h->kind == kSrht) {
+    a.m = h->mpad;  // C is drawn over the padded coordinates
+    check_hip(launch_sketch(a, s), "sketch (SRHT subset)");
+    check_hip(launch_srht_fill(bs.S, h->m, h->tau, h->ldas, bs.members, h->opt.seed, h->opt.problem_id, k0, h->mpad,
+                               nb, done, s),
+              "sketch (SRHT)");
+  } else {
+    check_hip(launch_sketch(a, s), "sketch");
+    if (h->dense_s) check_hip(launch_sketch_densify(bs.S, bs.hmap, h->m, h->ldas, nb, done, s), "dense S");
+  }
   if (h->sparse && !h->arows)
     check_hip(launch_build_t(h->zt_col, h->zt_val, h->vals_f32, h->nnz, bs.hmap, h->m, nb, h->tbuf,
                              done, s),
               "T map");
   prof_end(h, pe, s);
   pe = prof_begin(h, RS_PROF_AS, nb, 1, s);
-  if (h->arows) {
+  if (h->dense_s) {
+    // T = Z^T S, A S = Z T + lambda S (kernel ridge: + lambda T = lambda K S), G = S^T A S
+    GemmF64Args g{};
+    g.A = h->Z; g.lda = h->ldz; g.sA = 0;
+    g.B = bs.S; g.ldb = h->ldas; g.sB = h->m * h->ldas;
+    g.C = bs.T; g.ldc = h->ldas; g.sC = h->K * h->ldas;
+    g.M = h->K; g.N = h->tau; g.Kd = h->m; g.done = done;
+    check_hip(launch_gemm_f64(g, true, nb, s), "T = Z^T S");
+    GemmF64Args g2{};
+    g2.A = h->Z; g2.lda = h->ldz; g2.sA = 0;
+    g2.B = bs.T; g2.ldb = h->ldas; g2.sB = h->K * h->ldas;
+    g2.C = (double*)bs.AS; g2.ldc = h->ldas; g2.sC = h->m * h->ldas;
+    g2.E = h->kern ? bs.T : bs.S; g2.lde = h->ldas; g2.sE = h->kern ? h->K * h->ldas : h->m * h->ldas;
+    g2.lam = h->lam;
+    g2.M = h->m; g2.N = h->tau; g2.Kd = h->K; g2.done = done;
+    check_hip(launch_gemm_f64(g2, false, nb, s), "AS = Z T + lambda S");
+    prof_end(h, pe, s);
+    pe = prof_begin(h, RS_PROF_G, nb, 1, s);
+    GemmF64Args g3{};
+    g3.A = bs.S; g3.lda = h->ldas; g3.sA = h->m * h->ldas;
+    g3.B = (const double*)bs.AS; g3.ldb = h->ldas; g3.sB = h->m * h->ldas;
+    g3.C = bs.G; g3.ldc = h->ldg; g3.sC = h->ldg * h->ldg;
+    g3.M = h->tau; g3.N = h->tau; g3.Kd = h->m; g3.done = done;
+    check_hip(launch_gemm_f64(g3, true, nb, s), "G = S^T A S");
+  } else if (h->arows) {
     check_hip(launch_as_arows(h->a_ptr, h->a_col, h->a_val, h->m, h->tau, h->ldas, nb, h->lam, bs.hmap,
                               (double*)bs.AS, done, s),
               "AS (rows of Z Z^T)");
@@ -336,6 +381,7 @@ void use_set(rs_handle* h, int p) {
   h->AS = h->sets[p].AS;
   h->G = h->sets[p].G;
   h->status = h->sets[p].status;
+  h->S = h->sets[p].S;
 }
 
 // Iterations k0 .. k0 + nb - 1 on the solver's stream, from the batch prepared in set p.
@@ -345,9 +391,13 @@ void iterate_batch(rs_handle* h, int p, int64_t k0, int nb) {
   int pe = -1;
   // rho_{k0} = S_{k0}^T r^{k0}; later iterations get rho from the preceding update
   // (accelerated method: the sketch is applied to r_z)
-  check_hip(launch_rho(h->accel ? h->rzbuf : h->rbuf[k0 & 1], h->hmap, h->members, h->offs, h->tau, h->rho,
-                       h->flags, s),
-            "rho");
+  if (h->dense_s)
+    check_hip(launch_rho_dense(h->S, h->ldas, h->tau, h->m, h->rbuf[k0 & 1], h->rho_part, h->rho, h->flags, s),
+              "rho (dense S)");
+  else
+    check_hip(launch_rho(h->accel ? h->rzbuf : h->rbuf[k0 & 1], h->hmap, h->members, h->offs, h->tau, h->rho,
+                         h->flags, s),
+              "rho");
   const int pe_iters = prof_begin(h, RS_PROF_ITERS, nb);
   for (int i = 0; i < nb; ++i) {
     const int64_t k = k0 + i;
@@ -391,7 +441,17 @@ void iterate_batch(rs_handle* h, int p, int64_t k0, int nb) {
     const int32_t* hm_n = has_next ? h->hmap + (int64_t)(i + 1) * h->m : nullptr;
     const int32_t* mem_n = has_next ? h->members + (int64_t)(i + 1) * h->nsel : nullptr;
     const int32_t* offs_n = has_next ? h->offs + (int64_t)(i + 1) * (h->tau + 1) : nullptr;
-    if (h->accel)
+    if (h->dense_s) {
+      const double* S_i = h->S + (size_t)i * h->m * h->ldas;
+      check_hip(launch_update_dense((const double*)as_i, S_i, h->ldas, h->tau, h->delta, h->m, h->xbuf[cur],
+                                    h->xbuf[nxt], h->rbuf[cur], h->rbuf[nxt], gamma, beta, h->partials, h->npart,
+                                    h->flags, s),
+                "update (dense S)");
+      if (has_next)
+        check_hip(launch_rho_dense(S_i + (size_t)h->m * h->ldas, h->ldas, h->tau, h->m, h->rbuf[nxt], h->rho_part,
+                                   h->rho, h->flags, s),
+                  "rho (dense S)");
+    } else if (h->accel)
       check_hip(launch_update_accel((const double*)as_i, h->ldas, h->tau, h->delta, hm, h->m, h->xbuf[cur],
                                     h->xbuf[nxt], h->rbuf[cur], h->rbuf[nxt], h->vbuf, h->rvbuf, h->rzbuf,
                                     h->acc_alpha, h->acc_beta, h->acc_gamma, h->partials, h->npart, hm_n,
@@ -622,8 +682,6 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
     if (kern && X->layout == RS_CSR) throw Fail{RS_EINVAL, "kernel ridge takes dense points"};
     if (kern && o->precision != RS_PREC_FP64)
       throw Fail{RS_EUNSUPPORTED, "kernel ridge runs in FP64"};
-    if (kern && o->sketch != RS_SKETCH_SUBSAMPLE)
-      throw Fail{RS_EUNSUPPORTED, "kernel ridge is built for the subsample sketch"};
     if (kern && (o->sampler != RS_SAMPLER_UNIFORM || o->trace_every != 0))
       throw Fail{RS_EUNSUPPORTED, "kernel ridge uses uniform sampling without traces"};
     h->opt = *o;
@@ -696,11 +754,27 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
         if (h->nsel > 8192) throw Fail{RS_EUNSUPPORTED, "SubCount supports s = k * tau <= 8192"};
         if (h->tau > 2048) throw Fail{RS_EUNSUPPORTED, "SubCount supports tau <= 2048"};
         break;
+      case RS_SKETCH_GAUSSIAN:
+      case RS_SKETCH_SRHT:
+        h->kind = o->sketch == RS_SKETCH_GAUSSIAN ? kGaussian : kSrht;
+        h->nsel = h->tau;
+        h->dense_s = true;
+        h->mpad = 1;
+        while (h->mpad < h->m) h->mpad <<= 1;
+        if (h->sparse) throw Fail{RS_EUNSUPPORTED, "Gaussian and SRHT sketches are built for dense data"};
+        if (h->mixed || o->sampler != RS_SAMPLER_UNIFORM || o->trace_every != 0 || o->accelerated != 0)
+          throw Fail{RS_EUNSUPPORTED, "Gaussian and SRHT sketches run in FP64 with uniform sampling and momentum"};
+        break;
       default:
         throw Fail{RS_EINVAL, "unknown sketch"};
     }
-    if (h->kind != kSubsample && !h->sparse)
-      throw Fail{RS_EUNSUPPORTED, "count and SubCount sketches need CSR data"};
+    if ((h->kind == kCount || h->kind == kSubcount) && !h->sparse) {
+      // dense data: the drawn sketch is expanded to a dense S and takes the dense-S products
+      if (h->mixed || o->sampler != RS_SAMPLER_UNIFORM || o->trace_every != 0 || o->accelerated != 0)
+        throw Fail{RS_EUNSUPPORTED, "count and SubCount sketches on dense data run in FP64 with uniform sampling "
+                                    "and momentum"};
+      h->dense_s = true;
+    }
     if (h->kind == kSubsample && h->sparse)
       throw Fail{RS_EUNSUPPORTED, "the subsample sketch needs dense data"};
 
@@ -849,12 +923,14 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
     // The learned proposal reads the iterate, so its batches cannot be prepared ahead.
     h->pipeline = o->pipeline != 0 && o->sampler != RS_SAMPLER_LEARNED;
     h->nsets = h->pipeline ? 2 : 1;
+    const int64_t mkeys = h->kind == kSrht ? h->mpad : h->m;  // coordinates the selection keys span
     const size_t per_slot_set = (h->mixed ? sizeof(float) : sizeof(double)) * (size_t)h->m * h->ldas +
                                 sizeof(double) * (size_t)h->ldg * h->ldg +
-                                sizeof(int32_t) * ((size_t)h->m + h->nsel + h->tau + 2);
+                                sizeof(int32_t) * ((size_t)mkeys + h->nsel + h->tau + 2) +
+                                (h->dense_s ? sizeof(double) * (size_t)(h->m + h->K) * h->ldas : 0);
     const size_t per_slot = h->nsets * per_slot_set +
                             (h->sparse && !h->arows ? sparse_t_bytes(h->vals_f32, h->nnz) : 0) +
-                            sizeof(double) * (size_t)h->ldg * h->ldg + sizeof(uint64_t) * (size_t)h->m;
+                            sizeof(double) * (size_t)h->ldg * h->ldg + sizeof(uint64_t) * (size_t)mkeys;
     // Default lookahead: 256 sketches, fewer when one sketch's contraction is large
     // (the sketches formed past the stopping iteration are wasted work).
     int B = 256;
@@ -868,7 +944,7 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
     const size_t as_bytes = (h->mixed ? sizeof(float) : sizeof(double)) * (size_t)B * h->m * h->ldas;
     for (int p = 0; p < h->nsets; ++p) {
       rs_handle::BatchSet& bs = h->sets[p];
-      bs.hmap = dalloc<int32_t>(h, (size_t)B * h->m);
+      bs.hmap = dalloc<int32_t>(h, (size_t)B * mkeys);
       bs.members = dalloc<int32_t>(h, (size_t)B * h->nsel);
       bs.offs = dalloc<int32_t>(h, (size_t)B * (h->tau + 1));
       bs.AS = dalloc<char>(h, as_bytes);
@@ -877,9 +953,14 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
       bs.G = dalloc<double>(h, (size_t)B * h->ldg * h->ldg);
       bs.status = dalloc<int32_t>(h, B);
       check_hip(hipMemsetAsync(bs.status, 0, sizeof(int32_t) * B, s), "memset");
+      if (h->dense_s) {
+        bs.S = dalloc<double>(h, (size_t)B * h->m * h->ldas);
+        bs.T = dalloc<double>(h, (size_t)B * h->K * h->ldas);
+      }
     }
     use_set(h, 0);
-    h->keys = dalloc<uint64_t>(h, (size_t)B * h->m);
+    h->keys = dalloc<uint64_t>(h, (size_t)B * mkeys);
+    if (h->dense_s) h->rho_part = dalloc<double>(h, (size_t)rho_dense_blocks() * h->tau);
     if (h->pipeline) {
       // default priority, like the solver's stream
       check_hip(hipStreamCreateWithFlags(&h->prep_stream, hipStreamNonBlocking), "stream create");
@@ -1126,6 +1207,7 @@ rs_status rs_get_state(const rs_handle* h, double* x, double* x_prev, double* r,
 rs_status rs_get_last_sketch(const rs_handle* h, int32_t* rows, int32_t* cols, int8_t* signs,
                              int64_t* nnz_out) {
   if (!h || !rows || !cols || !signs || !nnz_out) return RS_EINVAL;
+  if (h->kind == kGaussian || h->kind == kSrht) return RS_EUNSUPPORTED;
   const int64_t it = h->k - 1;
   if (it < 0 || h->batch_k0 < 0 || it < h->batch_k0 || it >= h->batch_k0 + h->batch_n) return RS_EINVAL;
   const int64_t slot = it - h->batch_k0;

@@ -22,12 +22,15 @@ namespace rs {
 // Count: every coordinate is a member; members ordered by (bucket, index).
 // SubCount: the s kept coordinates; bucket b holds ranks [b k, (b+1) k).
 // ---------------------------------------------------------------------------
-enum SketchKind : int32_t { kSubsample = 0, kCount = 1, kSubcount = 2, kWeighted = 3 };
+enum SketchKind : int32_t { kSubsample = 0, kCount = 1, kSubcount = 2, kWeighted = 3, kGaussian = 4, kSrht = 5 };
+// kGaussian, kSrht: dense S (m x ldas per slot, row-major); for kSrht the selection of C runs
+// as a subsample over m' = 2^ceil(log2 m) coordinates (its hmap and keys are m' long per slot).
 // kWeighted: a subsample whose coordinates are the tau smallest (u_j / q_j, j) for a
 // proposal q (u_j uniform from the tag-4 stream); stored exactly like a subsample.
 
 // Philox4x64-10 stream tags (counter word 2).
-constexpr uint64_t kTagSubsample = 1, kTagCount = 2, kTagSubcount = 3, kTagWeighted = 4;
+constexpr uint64_t kTagSubsample = 1, kTagCount = 2, kTagSubcount = 3, kTagWeighted = 4, kTagGaussian = 6,
+                   kTagSrht = 7;
 
 struct SketchArgs {
   int32_t kind;
@@ -69,6 +72,38 @@ hipError_t launch_sketch_tab(const SketchArgs* tab, int32_t count, int32_t kind,
 
 // AS[slot][j][c] (row stride ldas) = sum_k Z[j][k] * Z[C_slot[c]][k] + lam * [j == C_slot[c]],
 // FP64 MFMA.
+// Dense sketches and general FP64 products (k_dense_sketch.hip).
+struct GemmF64Args {
+  const double* A;   // A(i, k) = a_trans ? A[k lda + i] : A[i lda + k]
+  int64_t lda, sA;   // row stride, slot stride
+  const double* B;   // B(k, j) = B[k ldb + j]
+  int64_t ldb, sB;
+  double* C;         // C[i ldc + j] = sum_k A(i, k) B(k, j) (+ lam E[i lde + j] when E)
+  int64_t ldc, sC;
+  const double* E;
+  int64_t lde, sE;
+  double lam;
+  int64_t M, N, Kd;
+  const int32_t* done;  // skip all work when *done != 0 (may be null)
+};
+hipError_t launch_gemm_f64(const GemmF64Args& g, bool a_trans, int32_t nslots, hipStream_t s);
+hipError_t launch_sketch_gauss(double* S, int64_t m, int32_t tau, int64_t ldas, uint64_t seed, uint64_t pid,
+                               int64_t k0, int32_t nslots, int32_t* offs, const int32_t* done, hipStream_t s);
+hipError_t launch_srht_fill(double* S, int64_t m, int32_t tau, int64_t ldas, const int32_t* members, uint64_t seed,
+                            uint64_t pid, int64_t k0, int64_t mpad, int32_t nslots, const int32_t* done,
+                            hipStream_t s);
+// S[slot] (m x ldas) from a sparse sketch's bucket codes (hmap, m per slot).
+hipError_t launch_sketch_densify(double* S, const int32_t* hmap, int64_t m, int64_t ldas, int32_t nslots,
+                                 const int32_t* done, hipStream_t s);
+int32_t rho_dense_blocks();
+// rho = S^T r with part (rho_dense_blocks() x tau doubles) as scratch.
+hipError_t launch_rho_dense(const double* S, int64_t ldas, int32_t tau, int64_t m, const double* r, double* part,
+                            double* rho, const DevFlags* flags, hipStream_t s);
+hipError_t launch_update_dense(const double* AS, const double* S, int64_t ldas, int32_t tau, const double* delta,
+                               int64_t m, const double* x, double* x_prev_out, const double* r, double* r_prev_out,
+                               double gamma, double beta, double* partials, int32_t npart, const DevFlags* flags,
+                               hipStream_t s);
+
 // lam_kernel != 0: Z is a symmetric kernel matrix (K == m) and the shift is lambda Z[:, C].
 hipError_t launch_as_dense_f64(const double* Z, int64_t ldz, int64_t m, int64_t K,
                                const int32_t* members, int32_t tau, int64_t ldas, int32_t nslots,

@@ -19,12 +19,13 @@ RS_DENSE_ROWMAJOR, RS_DENSE_COLMAJOR, RS_CSR = 0, 1, 2
 RS_F64, RS_F32 = 0, 1
 RS_HOST, RS_DEVICE = 0, 1
 RS_FORM_AUTO, RS_FORM_PRIMAL, RS_FORM_DUAL = 0, 1, 2
-RS_SKETCH_SUBSAMPLE, RS_SKETCH_COUNT, RS_SKETCH_SUBCOUNT = 0, 1, 2
+RS_SKETCH_SUBSAMPLE, RS_SKETCH_COUNT, RS_SKETCH_SUBCOUNT, RS_SKETCH_GAUSSIAN, RS_SKETCH_SRHT = 0, 1, 2, 3, 4
 RS_MOMENTUM_NONE, RS_MOMENTUM_CONSTANT, RS_MOMENTUM_HEURISTIC, RS_MOMENTUM_THEORY = 0, 1, 2, 3
 RS_PREC_FP64, RS_PREC_MIXED_BF16 = 0, 1
 
 FORMS = {"auto": RS_FORM_AUTO, "primal": RS_FORM_PRIMAL, "dual": RS_FORM_DUAL}
-SKETCHES = {"subsample": RS_SKETCH_SUBSAMPLE, "count": RS_SKETCH_COUNT, "subcount": RS_SKETCH_SUBCOUNT}
+SKETCHES = {"subsample": RS_SKETCH_SUBSAMPLE, "count": RS_SKETCH_COUNT, "subcount": RS_SKETCH_SUBCOUNT,
+            "gaussian": RS_SKETCH_GAUSSIAN, "srht": RS_SKETCH_SRHT}
 MOMENTA = {"none": RS_MOMENTUM_NONE, "constant": RS_MOMENTUM_CONSTANT, "heuristic": RS_MOMENTUM_HEURISTIC,
            "theory": RS_MOMENTUM_THEORY}
 PRECISIONS = {"fp64": RS_PREC_FP64, "mixed": RS_PREC_MIXED_BF16}

@@ -82,9 +82,19 @@ def test_rejects_nonfinite_targets():
 
 def test_rejects_unsupported_combinations():
     import scipy.sparse as sp
+    # count sketch on dense data: only FP64 (dense S products)
     with pytest.raises(rs.RsError) as e:
-        _create(np.ones((20, 8)), np.ones(20), 1.0, tau=3, sketch=rs.RS_SKETCH_COUNT)
+        _create(np.ones((20, 8)), np.ones(20), 1.0, tau=3, sketch=rs.RS_SKETCH_COUNT,
+                precision=rs.RS_PREC_MIXED_BF16)
     assert e.value.status == rs.RS_EUNSUPPORTED
+    for kind in (rs.RS_SKETCH_GAUSSIAN, rs.RS_SKETCH_SRHT):
+        with pytest.raises(rs.RsError) as e:  # dense sketches need dense data
+            _create(sp.random(20, 8, density=0.3, format="csr", random_state=0), np.ones(20), 1.0, tau=3,
+                    sketch=kind)
+        assert e.value.status == rs.RS_EUNSUPPORTED
+        with pytest.raises(rs.RsError) as e:  # and not the accelerated method
+            _create(np.ones((20, 8)), np.ones(20), 1.0, tau=3, sketch=kind, accelerated=1)
+        assert e.value.status == rs.RS_EUNSUPPORTED
     X = sp.random(20, 8, density=0.3, format="csr", random_state=0)
     with pytest.raises(rs.RsError) as e:
         _create(X, np.ones(20), 1.0, tau=3, sketch=rs.RS_SKETCH_SUBCOUNT, subcount_k=3)  # 9 > m
@@ -186,7 +196,7 @@ def test_momentum_settings_rejected(kw):
 @pytest.mark.parametrize("sigma,kw,status", [
     (0.0, {}, rs.RS_EINVAL), (-1.0, {}, rs.RS_EINVAL), (math.nan, {}, rs.RS_EINVAL), (math.inf, {}, rs.RS_EINVAL),
     (0.5, dict(precision=rs.RS_PREC_MIXED_BF16), rs.RS_EUNSUPPORTED),
-    (0.5, dict(sketch=rs.RS_SKETCH_COUNT), rs.RS_EUNSUPPORTED),
+    (0.5, dict(sketch=rs.RS_SKETCH_COUNT, precision=rs.RS_PREC_MIXED_BF16), rs.RS_EUNSUPPORTED),
     (0.5, dict(sampler=rs.SAMPLERS["diag"]), rs.RS_EUNSUPPORTED),
 ])
 def test_kernel_create_rejects_without_device(sigma, kw, status):
