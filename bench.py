@@ -150,7 +150,7 @@ def kernel_table(prof, wl, workload, n, d, nnz, m, K, nsel, total, a_nnz=0):
     kd = kernels[dom]
     achieved = kd["gbs"]
     as_name = ("k_as_arows_lds" if a_nnz else "k_as_sparse_bucket") if wl["kind"] == "csr" \
-        else "k_as_dense_f64_128"
+        else wl.get("as_kernel", "k_as_dense_f64_128")
     roofline = {"kernel": {"as": as_name, "g": "k_g_from_as",
                            "update": "k_update", "chol": "k_chol_inverse", "delta": "k_delta",
                            "iters": "k_delta+k_update sequence",
@@ -163,7 +163,7 @@ def kernel_table(prof, wl, workload, n, d, nnz, m, K, nsel, total, a_nnz=0):
         flops = 2.0 * m * wl["tau"] * K * kd["slots_per_launch"] * wl.get("as_products", 1)
         tfs = flops / (kd["avg_ms"] * 1e-3) / 1e12
         peak = BF16_PEAK_TFS if wl["precision"] == "mixed" else FP64_PEAK_TFS
-        roofline.update({"kernel": "k_as_dense_bf16" if wl["precision"] == "mixed" else "k_as_dense_f64_128",
+        roofline.update({"kernel": "k_as_dense_bf16" if wl["precision"] == "mixed" else as_name,
                          "bound": "mfma", "achieved": round(tfs, 1), "peak": peak, "unit": "TFLOP/s",
                          "frac": round(tfs / peak, 4), "alg_flops_per_launch": flops,
                          "hbm_gbs_algorithmic": kd["gbs"]})
@@ -492,7 +492,7 @@ def main_sketches(args):
         results[pname] = res
     prof, total, p, tau, kern = prof_first
     n = p.P.shape[0]
-    wl_k = dict(wl, tau=tau, as_products=2)
+    wl_k = dict(wl, tau=tau, as_products=2, as_kernel="k_gemm_f64")
     kernels, roofline = kernel_table(prof, wl_k, "sketch_compare", n, p.P.shape[1], n * p.P.shape[1], n, n, tau, total)
     T = results["kernel_boston_506x13"]["subsample"]["median_s"]
     out = {
