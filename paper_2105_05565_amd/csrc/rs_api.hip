@@ -125,6 +125,7 @@ struct rs_handle {
   std::vector<hipEvent_t> ev;  // pool: 2 events per timed launch of one batch
   std::vector<int> ev_cls;     // kernel class of each pair
   std::vector<int> ev_slots;   // sketches processed by each pair
+  std::vector<int64_t> ev_batch;  // first iteration of the batch a preparation pair belongs to (-1: none)
   int ev_used = 0;
   rs_profile prof{};
 
@@ -215,12 +216,13 @@ T* to_device(rs_handle* h, const void* src, size_t count, int mem) {
 }
 
 // Event pair around one launch when profiling: returns the pair index or -1.
-int prof_begin(rs_handle* h, int cls, int slots, int level = 1, hipStream_t s = nullptr) {
+int prof_begin(rs_handle* h, int cls, int slots, int level = 1, hipStream_t s = nullptr, int64_t batch = -1) {
   if (h->opt.profile < level) return -1;
   if (2 * (h->ev_used + 1) > (int)h->ev.size()) return -1;  // pool full: leave untimed
   const int i = h->ev_used++;
   h->ev_cls[i] = cls;
   h->ev_slots[i] = slots;
+  h->ev_batch[i] = batch;
   check_hip(hipEventRecord(h->ev[2 * i], s ? s : h->stream), "event");
   return i;
 }
@@ -229,9 +231,12 @@ void prof_end(rs_handle* h, int i, hipStream_t s = nullptr) {
   if (i >= 0) check_hip(hipEventRecord(h->ev[2 * i + 1], s ? s : h->stream), "event");
 }
 
-// After a synchronisation: fold the recorded pairs into h->prof.
-void prof_collect(rs_handle* h) {
+// After a synchronisation: fold the recorded pairs into h->prof. The preparation of a batch
+// that starts at or after drop_from (prepared ahead past the stopping iteration, so its
+// kernels returned at once) is left out.
+void prof_collect(rs_handle* h, int64_t drop_from = INT64_MAX) {
   for (int i = 0; i < h->ev_used; ++i) {
+    if (h->ev_batch[i] >= 0 && h->ev_batch[i] >= drop_from) continue;
     float ms = 0.0f;
     check_hip(hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]), "elapsed");
     h->prof.ms[h->ev_cls[i]] += ms;
@@ -274,7 +279,7 @@ void prep_batch(rs_handle* h, int p, int64_t k0, int nb, hipStream_t s) {
   a.keys = h->keys;
   a.err = h->err;
   a.done = done;
-  int pe = prof_begin(h, RS_PROF_SKETCH, nb, 1, s);
+  int pe = prof_begin(h, RS_PROF_SKETCH, nb, 1, s, k0);
   if (h->sampler != RS_SAMPLER_UNIFORM) {
     // coordinates drawn from the proposal q (features of r^{k0}, r^{k0-1} for the
     // learned one): the tau smallest u_j / q_j per sketch
@@ -308,7 +313,7 @@ void prep_batch(rs_handle* h, int p, int64_t k0, int nb, hipStream_t s) {
                              done, s),
               "T map");
   prof_end(h, pe, s);
-  pe = prof_begin(h, RS_PROF_AS, nb, 1, s);
+  pe = prof_begin(h, RS_PROF_AS, nb, 1, s, k0);
   if (h->dense_s) {
     // T = Z^T S, A S = Z T + lambda S (kernel ridge: + lambda T = lambda K S), G = S^T A S
     GemmF64Args g{};
@@ -326,7 +331,7 @@ void prep_batch(rs_handle* h, int p, int64_t k0, int nb, hipStream_t s) {
     g2.M = h->m; g2.N = h->tau; g2.Kd = h->K; g2.done = done;
     check_hip(launch_gemm_f64(g2, false, nb, s), "AS = Z T + lambda S");
     prof_end(h, pe, s);
-    pe = prof_begin(h, RS_PROF_G, nb, 1, s);
+    pe = prof_begin(h, RS_PROF_G, nb, 1, s, k0);
     GemmF64Args g3{};
     g3.A = bs.S; g3.lda = h->ldas; g3.sA = h->m * h->ldas;
     g3.B = (const double*)bs.AS; g3.ldb = h->ldas; g3.sB = h->m * h->ldas;
@@ -338,7 +343,7 @@ void prep_batch(rs_handle* h, int p, int64_t k0, int nb, hipStream_t s) {
                               (double*)bs.AS, done, s),
               "AS (rows of Z Z^T)");
     prof_end(h, pe, s);
-    pe = prof_begin(h, RS_PROF_G, nb, 1, s);
+    pe = prof_begin(h, RS_PROF_G, nb, 1, s, k0);
     check_hip(launch_g_from_as((const double*)bs.AS, h->m, h->tau, h->ldas, nb, bs.hmap, bs.members, bs.offs,
                                h->nsel, bs.G, h->ldg, done, s),
               "G = S^T AS");
@@ -358,7 +363,7 @@ void prep_batch(rs_handle* h, int p, int64_t k0, int nb, hipStream_t s) {
               "AS (dense)");
   }
   prof_end(h, pe, s);
-  pe = prof_begin(h, RS_PROF_CHOL, nb, 1, s);
+  pe = prof_begin(h, RS_PROF_CHOL, nb, 1, s, k0);
   // One workgroup per sketch when the batch fills the chip; otherwise one per tile.
   if (h->ldg >= 128 && nb < 128)
     check_hip(launch_chol_multi(bs.G, h->W, h->Xd, h->ldg, h->tau, nb, h->kind, bs.AS,
@@ -579,7 +584,7 @@ void advance(rs_handle* h, int64_t iters) {
     check_hip(hipStreamSynchronize(h->stream), "sync");
     if (pipe) check_hip(hipStreamSynchronize(h->prep_stream), "sync");
     check_hip(hipMemcpy(&err, h->err, sizeof(int32_t), hipMemcpyDeviceToHost), "err");
-    prof_collect(h);
+    prof_collect(h, f.done ? f.k_done : INT64_MAX);
     if (err) throw Fail{RS_EDEVICE, "internal sketch limit hit (code " + std::to_string(err) + ")"};
     const int64_t k_end = f.done ? f.k_done : k_enq;
     for (int i = 0; i < nb; ++i)
@@ -1027,6 +1032,7 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
       h->ev.resize(2 * pairs);
       h->ev_cls.resize(pairs);
       h->ev_slots.resize(pairs);
+      h->ev_batch.resize(pairs);
       for (auto& e : h->ev) check_hip(hipEventCreate(&e), "event create");
     }
     check_hip(hipMemsetAsync(h->err, 0, sizeof(int32_t), s), "memset");
