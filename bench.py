@@ -47,6 +47,9 @@ WORKLOADS = {
     "kernel_california": dict(kind="kernel", gen="kernel_california", sketch="subsample", tau=5160, sub_k=0,
                               precision="fp64",
                               name="kernel_rbf_20640x8_sigma0.5_lambda1e-6_subsample_tau5160"),
+    "kernel_california_mixed": dict(kind="kernel", gen="kernel_california", sketch="subsample", tau=5160, sub_k=0,
+                                    precision="mixed",
+                                    name="kernel_rbf_20640x8_sigma0.5_lambda1e-6_subsample_tau5160_bf16_refresh20"),
     "accel_grid": dict(kind="kernel", sketch="subsample", tau=158, sub_k=0, precision="fp64",
                        name="accel_grid_kernel_rbf_2000_sigma0.5_lambda1/n_tau158_tol1e-4"),
     "sketch_compare": dict(kind="kernel", sketch="subsample", tau=126, sub_k=0, precision="fp64",

@@ -80,6 +80,9 @@ struct GemmArgs {
   int64_t ntot;  // slots * tau
   int64_t ldas;
   double lam;
+  const double* Zk;    // kernel ridge (lam_kernel): the FP64 symmetric kernel matrix, row stride ldk
+  int64_t ldk;
+  int32_t lam_kernel;  // 1: the shift is lam K[C_c][row] (= lam K[row][C_c]) instead of lam I_C
   float* AS;  // [slot][m][ldas]
   int32_t n_row_tiles, n_col_tiles;
   const int32_t* done;
@@ -244,7 +247,10 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_as_dense_bf16(GemmArgs a) {
         if (row < a.m && n < a.ntot) {
           const int64_t slot = n / a.tau, c = n % a.tau;
           float val = acc[i][j][v];
-          if (row == brow[col]) val = (float)((double)val + a.lam);
+          if (a.lam_kernel)
+            val = (float)((double)val + a.lam * a.Zk[brow[col] * a.ldk + row]);
+          else if (row == brow[col])
+            val = (float)((double)val + a.lam);
           a.AS[(slot * a.m + row) * a.ldas + c] = val;
         }
       }
@@ -255,8 +261,9 @@ constexpr int kGemmWaves = 8, kGemmStages = 4;
 
 constexpr int kRefreshSplit = 32;  // row ranges of Z summed separately in Z^T x
 
-// upart[js][k][0..1] = sum_{j in range js} Z[j][k] * (x[j], xp[j]) in FP64 (FP32 data).
-__global__ void k_gemv_t_pair(const float* __restrict__ Z, int64_t ldz, int64_t m, int64_t K,
+// upart[js][k][0..1] = sum_{j in range js} Z[j][k] * (x[j], xp[j]) in FP64 (FP32 or FP64 data).
+template <typename T>
+__global__ void k_gemv_t_pair(const T* __restrict__ Z, int64_t ldz, int64_t m, int64_t K,
                               const double* __restrict__ x, const double* __restrict__ xp,
                               double* __restrict__ upart, const int32_t* __restrict__ done) {
   if (*done) return;
@@ -287,11 +294,13 @@ __global__ void k_sum_upart(const double* __restrict__ upart, int64_t K, double*
 }
 
 // r[j] = sum_k Z[j][k] u[k][0] + lam x[j] - b[j] (and likewise rp from u[k][1], xp);
-// one wave per row; partial sums of ||r||^2 per workgroup.
+// kernel ridge (lam_u): the shift is lam u[j] = lam (K x)[j] (K = Z symmetric, m = K).
+// One wave per row; partial sums of ||r||^2 per workgroup.
+template <typename T>
 __global__ __launch_bounds__(256) void k_gemv_n_pair_residual(
-    const float* __restrict__ Z, int64_t ldz, int64_t m, int64_t K, const double* __restrict__ u,
+    const T* __restrict__ Z, int64_t ldz, int64_t m, int64_t K, const double* __restrict__ u,
     const double* __restrict__ x, const double* __restrict__ xp, const double* __restrict__ b,
-    double lam, double* __restrict__ r, double* __restrict__ rp, double* __restrict__ partials,
+    double lam, int32_t lam_u, double* __restrict__ r, double* __restrict__ rp, double* __restrict__ partials,
     const int32_t* __restrict__ done) {
   __shared__ double scratch[16];
   if (*done) return;
@@ -299,7 +308,7 @@ __global__ __launch_bounds__(256) void k_gemv_n_pair_residual(
   const int64_t j = (int64_t)blockIdx.x * 4 + wave;
   double ss = 0.0;
   if (j < m) {
-    const float* zr = Z + j * ldz;
+    const T* zr = Z + j * ldz;
     double s0 = 0.0, s1 = 0.0;
     for (int64_t k = lane; k < K; k += 64) {
       const double z = (double)zr[k];
@@ -309,9 +318,10 @@ __global__ __launch_bounds__(256) void k_gemv_n_pair_residual(
     s0 = wave_sum(s0);
     s1 = wave_sum(s1);
     if (lane == 0) {
-      const double rn = s0 + lam * x[j] - b[j];
+      const double sx = lam_u ? u[2 * j] : x[j], sxp = lam_u ? u[2 * j + 1] : xp[j];
+      const double rn = s0 + lam * sx - b[j];
       r[j] = rn;
-      rp[j] = s1 + lam * xp[j] - b[j];
+      rp[j] = s1 + lam * sxp - b[j];
       ss = rn * rn;
     }
   }
@@ -379,8 +389,10 @@ hipError_t launch_cast_bf16(const void* src, int32_t src_is_f32, int64_t rows_s,
 
 hipError_t launch_as_dense_bf16(const uint16_t* Zbf, int64_t ldz, int64_t m, int64_t kpad,
                                 const int32_t* members, int32_t tau, int64_t ldas, int32_t nslots,
-                                double lam, float* AS, const int32_t* done, hipStream_t s) {
+                                double lam, const double* Zk, int64_t ldk, int32_t lam_kernel, float* AS,
+                                const int32_t* done, hipStream_t s) {
   if (kpad % kDmaBK != 0 || ldz % 8 != 0) return hipErrorInvalidValue;
+  if (lam_kernel && (!Zk || ldk < m)) return hipErrorInvalidValue;
   GemmArgs a;
   a.Z = Zbf;
   a.ldz = ldz;
@@ -391,6 +403,9 @@ hipError_t launch_as_dense_bf16(const uint16_t* Zbf, int64_t ldz, int64_t m, int
   a.ntot = (int64_t)nslots * tau;
   a.ldas = ldas;
   a.lam = lam;
+  a.Zk = Zk;
+  a.ldk = ldk;
+  a.lam_kernel = lam_kernel;
   a.AS = AS;
   constexpr int BM = 32 * kGemmWaves;
   a.n_row_tiles = (int32_t)((m + BM - 1) / BM);
@@ -406,18 +421,27 @@ hipError_t launch_as_dense_bf16(const uint16_t* Zbf, int64_t ldz, int64_t m, int
   return hipGetLastError();
 }
 
-hipError_t launch_refresh(const float* Z32, int64_t ldz, int64_t m, int64_t K, const double* x,
-                          const double* xp, const double* b, double lam, double* r, double* rp,
+hipError_t launch_refresh(const void* Zr, int32_t z_f32, int64_t ldz, int64_t m, int64_t K, const double* x,
+                          const double* xp, const double* b, double lam, int32_t lam_u, double* r, double* rp,
                           double* u, double* upart, double* partials, DevFlags* flags, double* hist,
                           double* true_hist, int64_t k, double tol, const int32_t* done,
                           hipStream_t s) {
-  hipLaunchKernelGGL(k_gemv_t_pair, dim3((unsigned)((K + 255) / 256), kRefreshSplit), dim3(256), 0, s,
-                     Z32, ldz, m, K, x, xp, upart, done);
+  if (lam_u && K != m) return hipErrorInvalidValue;
+  const dim3 gt((unsigned)((K + 255) / 256), kRefreshSplit);
+  if (z_f32)
+    hipLaunchKernelGGL(k_gemv_t_pair<float>, gt, dim3(256), 0, s, (const float*)Zr, ldz, m, K, x, xp, upart, done);
+  else
+    hipLaunchKernelGGL(k_gemv_t_pair<double>, gt, dim3(256), 0, s, (const double*)Zr, ldz, m, K, x, xp, upart,
+                       done);
   hipLaunchKernelGGL(k_sum_upart, dim3((unsigned)((2 * K + 255) / 256)), dim3(256), 0, s, upart, K, u,
                      done);
   const unsigned nb = (unsigned)((m + 3) / 4);
-  hipLaunchKernelGGL(k_gemv_n_pair_residual, dim3(nb), dim3(256), 0, s, Z32, ldz, m, K, u, x, xp, b,
-                     lam, r, rp, partials, done);
+  if (z_f32)
+    hipLaunchKernelGGL(k_gemv_n_pair_residual<float>, dim3(nb), dim3(256), 0, s, (const float*)Zr, ldz, m, K, u, x,
+                       xp, b, lam, lam_u, r, rp, partials, done);
+  else
+    hipLaunchKernelGGL(k_gemv_n_pair_residual<double>, dim3(nb), dim3(256), 0, s, (const double*)Zr, ldz, m, K, u,
+                       x, xp, b, lam, lam_u, r, rp, partials, done);
   hipLaunchKernelGGL(k_refresh_norm, dim3(1), dim3(256), 0, s, partials, (int32_t)nb, flags, hist,
                      true_hist, k, tol);
   return hipGetLastError();

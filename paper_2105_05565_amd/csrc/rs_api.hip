@@ -249,8 +249,11 @@ void prof_collect(rs_handle* h, int64_t drop_from = INT64_MAX) {
 // Mixed precision: r^k and r^{k-1} recomputed in FP64 from x^k, x^{k-1}; stop test on it.
 void refresh(rs_handle* h, int64_t k) {
   const int pe = prof_begin(h, RS_PROF_REFRESH, 1, 2);
-  check_hip(launch_refresh(h->Z32, h->K, h->m, h->K, h->xbuf[k & 1], h->xbuf[(k + 1) & 1], h->b,
-                           h->lam, h->rbuf[k & 1], h->rbuf[(k + 1) & 1], h->ref_u, h->ref_upart,
+  // kernel ridge refreshes from the FP64 kernel matrix, dense ridge from the FP32 copy of X
+  const void* Zr = h->kern ? (const void*)h->Z : (const void*)h->Z32;
+  const int64_t ldr = h->kern ? h->ldz : h->K;
+  check_hip(launch_refresh(Zr, h->kern ? 0 : 1, ldr, h->m, h->K, h->xbuf[k & 1], h->xbuf[(k + 1) & 1], h->b,
+                           h->lam, h->kern ? 1 : 0, h->rbuf[k & 1], h->rbuf[(k + 1) & 1], h->ref_u, h->ref_upart,
                            h->ref_partials, h->flags, h->hist, h->true_hist, k, h->opt.tol,
                            &h->flags->done, h->stream),
             "refresh");
@@ -355,7 +358,7 @@ void prep_batch(rs_handle* h, int p, int64_t k0, int nb, hipStream_t s) {
               "AS (sparse)");
   } else if (h->mixed) {
     check_hip(launch_as_dense_bf16(h->Zbf, h->kpad, h->m, h->kpad, bs.members, h->tau, h->ldas, nb,
-                                   h->lam, (float*)bs.AS, done, s),
+                                   h->lam, h->Z, h->ldz, h->kern ? 1 : 0, (float*)bs.AS, done, s),
               "AS (dense, BF16)");
   } else {
     check_hip(launch_as_dense_f64(h->Z, h->ldz, h->m, h->K, bs.members, h->tau, h->ldas, nb, h->lam,
@@ -685,8 +688,6 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
     const bool kern = sigma > 0.0;
     h->kern = kern;
     if (kern && X->layout == RS_CSR) throw Fail{RS_EINVAL, "kernel ridge takes dense points"};
-    if (kern && o->precision != RS_PREC_FP64)
-      throw Fail{RS_EUNSUPPORTED, "kernel ridge runs in FP64"};
     if (kern && (o->sampler != RS_SAMPLER_UNIFORM || o->trace_every != 0))
       throw Fail{RS_EUNSUPPORTED, "kernel ridge uses uniform sampling without traces"};
     h->opt = *o;
@@ -818,8 +819,19 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
         h->Z = dalloc<double>(h, (size_t)n * h->ldz);
         check_hip(launch_rbf_gram(p64, n, d, sigma, h->Z, h->ldz, s), "kernel matrix");
         check_hip(launch_gemv_rows(h->Z, h->ldz, h->m, h->K, yd, h->b, s), "b = K y");
+        std::vector<void*> tmp{(void*)p64, xv};
+        if (h->mixed) {
+          // BF16 copy for the products; K itself stays for the shift and the FP64 refresh (an
+          // FP32 copy would make the refreshed residual that of a rounded kernel matrix)
+          h->kpad = (h->K + 63) / 64 * 64;
+          h->Zbf = dalloc<uint16_t>(h, (size_t)h->m * h->kpad);
+          check_hip(launch_cast_bf16(h->Z, 0, n, n, n, 0, h->Zbf, h->kpad, nullptr, 0, s), "BF16 copy");
+          h->ref_u = dalloc<double>(h, 2 * h->K);
+          h->ref_upart = dalloc<double>(h, refresh_upart_doubles(h->K));
+          h->ref_partials = dalloc<double>(h, refresh_partials(h->m));
+        }
         check_hip(hipStreamSynchronize(s), "sync");
-        for (void* p : {(void*)p64, xv}) {
+        for (void* p : tmp) {
           (void)hipFree(p);
           h->allocs.erase(std::find(h->allocs.begin(), h->allocs.end(), p));
         }

@@ -231,15 +231,20 @@ hipError_t launch_cast_bf16(const void* src, int32_t src_is_f32, int64_t rows_s,
                             int64_t lds, int32_t trans, uint16_t* dst, int64_t ldd, float* dst32,
                             int64_t ldd32, hipStream_t s);
 // AS[slot] (FP32, row stride ldas) = Zbf Zbf[C_slot,:]^T + lambda I_C on BF16 MFMA.
+// lam_kernel != 0: kernel ridge, the shift is lam Zk[C_c][row] (the FP64 symmetric kernel matrix)
+// instead of lam I_C.
 hipError_t launch_as_dense_bf16(const uint16_t* Zbf, int64_t ldz, int64_t m, int64_t kpad,
                                 const int32_t* members, int32_t tau, int64_t ldas, int32_t nslots,
-                                double lam, float* AS, const int32_t* done, hipStream_t s);
+                                double lam, const double* Zk, int64_t ldk, int32_t lam_kernel, float* AS,
+                                const int32_t* done, hipStream_t s);
 // FP64 recomputation r = Z (Z^T x) + lambda x - b (and rp from xp) from the FP32 copy;
 // records ||r|| / ||r^0|| at k and applies the stop test.
 int64_t refresh_partials(int64_t m);
 int64_t refresh_upart_doubles(int64_t K);
-hipError_t launch_refresh(const float* Z32, int64_t ldz, int64_t m, int64_t K, const double* x,
-                          const double* xp, const double* b, double lam, double* r, double* rp,
+// FP64 residuals r = Z (Z^T x) + lam x - b from the FP32 (z_f32) or FP64 copy of Z; lam_u != 0:
+// kernel ridge, r = Z (Z^T x) + lam (Z^T x) - b.
+hipError_t launch_refresh(const void* Zr, int32_t z_f32, int64_t ldz, int64_t m, int64_t K, const double* x,
+                          const double* xp, const double* b, double lam, int32_t lam_u, double* r, double* rp,
                           double* u, double* upart, double* partials, DevFlags* flags, double* hist,
                           double* true_hist, int64_t k, double tol, const int32_t* done,
                           hipStream_t s);

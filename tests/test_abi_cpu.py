@@ -195,7 +195,6 @@ def test_momentum_settings_rejected(kw):
 
 @pytest.mark.parametrize("sigma,kw,status", [
     (0.0, {}, rs.RS_EINVAL), (-1.0, {}, rs.RS_EINVAL), (math.nan, {}, rs.RS_EINVAL), (math.inf, {}, rs.RS_EINVAL),
-    (0.5, dict(precision=rs.RS_PREC_MIXED_BF16), rs.RS_EUNSUPPORTED),
     (0.5, dict(sketch=rs.RS_SKETCH_COUNT, precision=rs.RS_PREC_MIXED_BF16), rs.RS_EUNSUPPORTED),
     (0.5, dict(sampler=rs.SAMPLERS["diag"]), rs.RS_EUNSUPPORTED),
 ])

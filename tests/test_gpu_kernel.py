@@ -136,3 +136,53 @@ def test_kernel_full_size_first_step_sampled():
     direct = Kr @ (Kx + p.lam * x) - b_rows
     assert np.allclose(r[rows], direct, rtol=0, atol=1e-9 * scale)
     S.close()
+
+
+U_BF16, U_FP32 = 2.0 ** -8, 2.0 ** -24
+
+
+def test_kernel_mixed_products_within_bound():
+    """BF16 products of the kernel matrix with FP32 accumulation, the shift lambda K[:, C] added
+    from the FP64 kernel matrix: within the dot-product bound of the FP64 product."""
+    p = inputs.make_points(700, 8, 1e-2, 0.5, seed=61)
+    system = kernel_system(p.P, p.y, p.lam, p.sigma)
+    S = _solver(p, 64, tol=0.0, seed=5, precision="mixed", lookahead=3)
+    S.step(3)
+    AS, Gi = S.products()
+    sketch = osk.draw_subsample(5, 0, 2, 700, 64)
+    _, AS_o, _, _ = sketched_products(system, sketch)
+    K = system.Kmat
+    C = sketch.rows
+    bound = (2 * U_BF16 + 700 * U_FP32) * (np.abs(K) @ np.abs(K[C]).T) + 2 * U_FP32 * np.abs(AS_o) + 1e-30
+    err = np.abs(AS - AS_o)
+    assert np.all(err <= bound), float((err / bound).max())
+    S.close()
+
+
+def test_kernel_mixed_refresh_uses_fp64_kernel_matrix():
+    p = inputs.make_points(600, 8, 1e-2, 0.5, seed=62)
+    system = kernel_system(p.P, p.y, p.lam, p.sigma)
+    S = _solver(p, 50, tol=0.0, seed=2, precision="mixed", refresh_every=10, lookahead=16)
+    for steps in (10, 20, 40):
+        S.step(steps - S.k)
+        x, xp, r, rp = S.state()
+        for xx, rr in ((x, r), (xp, rp)):
+            true = system.matvec(xx) - system.b
+            assert np.linalg.norm(rr - true) <= 1e-12 * np.linalg.norm(system.b)
+    S.close()
+
+
+def test_kernel_mixed_converges_to_direct_solution():
+    p = inputs.make_points(800, 8, 1e-2, 0.4, seed=63)
+    system = kernel_system(p.P, p.y, p.lam, p.sigma)
+    S = _solver(p, 200, tol=1e-8, seed=3, precision="mixed", max_iter=100000)
+    alpha, st, rep = S.solve()
+    assert st == rs.RS_OK
+    x = S.state()[0]
+    true_rel = np.linalg.norm(system.matvec(x) - system.b) / np.linalg.norm(system.b)
+    assert true_rel <= 1e-8 * 1.0001
+    A = system.dense_A()
+    direct = np.linalg.solve(A, system.b)
+    kappa = np.linalg.cond(A)
+    assert _rel(alpha, direct) <= 2 * kappa * 1e-8
+    S.close()
