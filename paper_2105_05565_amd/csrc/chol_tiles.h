@@ -55,6 +55,37 @@ __device__ __forceinline__ void tile_mma(Acc& c, const double* a, const double* 
   }
 }
 
+// C += A * B^T with A, B 64 x 64 tiles read straight from global memory (row stride ld, rows
+// 32-byte aligned), no LDS: wave w owns rows 32 (w / 2) .. +32 and columns 32 (w % 2) .. +32 of
+// C. A lane reads 4 consecutive k values of one row at once; the four 4-deep MFMA steps of a
+// 16-wide chunk q then take k = 16 q + 4 g + s in lane group g = lane / 16 at step s, the same
+// k for A and B, so every k term enters the sum once (in another order than tile_mma).
+__device__ __forceinline__ void tile_mma_global(Acc& c, const double* __restrict__ A, const double* __restrict__ B,
+                                                int64_t ld) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int l16 = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    double4 av[2], bv[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      av[i] = *reinterpret_cast<const double4*>(A + (int64_t)(wr + i * 16 + l16) * ld + 16 * q + 4 * g);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      bv[j] = *reinterpret_cast<const double4*>(B + (int64_t)(wc + j * 16 + l16) * ld + 16 * q + 4 * g);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        c.v[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].x, c.v[i][j], 0, 0, 0);
+        c.v[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].y, bv[j].y, c.v[i][j], 0, 0, 0);
+        c.v[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].z, bv[j].z, c.v[i][j], 0, 0, 0);
+        c.v[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].w, bv[j].w, c.v[i][j], 0, 0, 0);
+      }
+  }
+}
+
 // Visit the accumulator elements: f(row, col, value) with (row, col) inside the tile.
 // 16x16x4 FP64 MFMA result layout: lane l, element v -> row 4 v + l / 16, column l % 16.
 template <class F>

@@ -137,10 +137,9 @@ __device__ __forceinline__ void lower_pair(int idx, int lo, int* i, int* j) {
   *j = lo + idx;
 }
 
+// Operands are read straight from global memory (they are shared by many workgroups and stay
+// in L2); without LDS many workgroups fit on a compute unit to cover the load latency.
 __global__ __launch_bounds__(kThreads) void k_chol_trailing(MultiArgs a, int kt, int ntrail) {
-  extern __shared__ __align__(16) double lds[];
-  double* ta = lds;
-  double* tb = lds + NB * LDT;
   if (*a.done) return;
   const int64_t slot = blockIdx.y;
   double* G = a.G + slot * a.ldg * a.ldg;
@@ -152,10 +151,7 @@ __global__ __launch_bounds__(kThreads) void k_chol_trailing(MultiArgs a, int kt,
     // G_ij -= L_ik L_jk^T, kt < j <= i
     int i, j;
     lower_pair(idx, kt + 1, &i, &j);
-    load_tile(ta, tile(G, a.ldg, i, kt), a.ldg, false);
-    load_tile(tb, tile(G, a.ldg, j, kt), a.ldg, false);
-    __syncthreads();
-    tile_mma(c, ta, tb);
+    tile_mma_global(c, tile(G, a.ldg, i, kt), tile(G, a.ldg, j, kt), a.ldg);
     double* Gij = tile(G, a.ldg, i, j);
     acc_for_each(c, [&](int r, int cc, double v) { Gij[(int64_t)r * a.ldg + cc] -= v; });
     return;
@@ -165,17 +161,11 @@ __global__ __launch_bounds__(kThreads) void k_chol_trailing(MultiArgs a, int kt,
   idx -= ntrail;
   const int i = kt + 1 + idx / (kt + 1), j = idx % (kt + 1);
   double* Uji = tile(U, a.ldg, j, i);
-  load_tile(ta, tile(U, a.ldg, j, kt), a.ldg, false);  // U_jk
-  load_tile(tb, tile(G, a.ldg, i, kt), a.ldg, false);  // L_ik
-  __syncthreads();
-  tile_mma(c, ta, tb);
+  tile_mma_global(c, tile(U, a.ldg, j, kt), tile(G, a.ldg, i, kt), a.ldg);  // U_jk L_ik^T
   acc_for_each(c, [&](int r, int cc, double v) { Uji[(int64_t)r * a.ldg + cc] -= v; });
 }
 
 __global__ __launch_bounds__(kThreads) void k_chol_lauum(MultiArgs a) {
-  extern __shared__ __align__(16) double lds[];
-  double* ta = lds;
-  double* tb = lds + NB * LDT;
   if (*a.done) return;
   const int64_t slot = blockIdx.y;
   int i, j;
@@ -184,13 +174,7 @@ __global__ __launch_bounds__(kThreads) void k_chol_lauum(MultiArgs a) {
   double* U = a.U + slot * a.ldg * a.ldg;
   Acc c;
   acc_zero(c);
-  for (int kt = i; kt < a.nt; ++kt) {
-    load_tile(ta, tile(U, a.ldg, i, kt), a.ldg, false);
-    load_tile(tb, tile(U, a.ldg, j, kt), a.ldg, false);
-    __syncthreads();
-    tile_mma(c, ta, tb);
-    __syncthreads();
-  }
+  for (int kt = i; kt < a.nt; ++kt) tile_mma_global(c, tile(U, a.ldg, i, kt), tile(U, a.ldg, j, kt), a.ldg);
   double* Gij = tile(G, a.ldg, i, j);
   double* Gji = tile(G, a.ldg, j, i);
   acc_for_each(c, [&](int r, int cc, double v) {
@@ -212,15 +196,8 @@ hipError_t launch_chol_multi(double* G, double* U, double* X, int64_t ldg, int32
               status, done};
   const int nt = a.nt;
   const size_t diag_bytes = sizeof(double) * (3 * NB * LDT + NB);
-  const size_t pair_bytes = sizeof(double) * 2 * NB * LDT;
   hipError_t e = hipFuncSetAttribute((const void*)k_chol_diag_panel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)diag_bytes);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_chol_trailing, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)pair_bytes);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_chol_lauum, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)pair_bytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_chol_assemble, dim3(nt, nt, nslots), dim3(kThreads), 0, s, a);
   for (int kt = 0; kt < nt; ++kt) {
@@ -229,10 +206,9 @@ hipError_t launch_chol_multi(double* G, double* U, double* X, int64_t ldg, int32
     const int ntrail = rest * (rest + 1) / 2;
     const int ninv = rest * (kt + 1);
     if (ntrail + ninv > 0)
-      hipLaunchKernelGGL(k_chol_trailing, dim3(ntrail + ninv, nslots), dim3(kThreads), pair_bytes, s,
-                         a, kt, ntrail);
+      hipLaunchKernelGGL(k_chol_trailing, dim3(ntrail + ninv, nslots), dim3(kThreads), 0, s, a, kt, ntrail);
   }
-  hipLaunchKernelGGL(k_chol_lauum, dim3(nt * (nt + 1) / 2, nslots), dim3(kThreads), pair_bytes, s, a);
+  hipLaunchKernelGGL(k_chol_lauum, dim3(nt * (nt + 1) / 2, nslots), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
