@@ -170,6 +170,19 @@ def kernel_table(prof, wl, workload, n, d, nnz, m, K, nsel, total, a_nnz=0):
                          "bound": "mfma", "achieved": round(tfs, 1), "peak": peak, "unit": "TFLOP/s",
                          "frac": round(tfs / peak, 4), "alg_flops_per_launch": flops,
                          "hbm_gbs_algorithmic": kd["gbs"]})
+    if dom == "chol":
+        # explicit inverse of each tau x tau sketched system: factorisation tau^3 / 3, triangular
+        # inverse tau^3 / 3, U U^T tau^3 / 3 flop on FP64 MFMA; the device-wide tiled kernels serve
+        # tau >= 128 with fewer than 128 sketches per launch
+        tau = wl["tau"]
+        ldg = (tau + 63) // 64 * 64
+        flops = float(tau) ** 3 * kd["slots_per_launch"]
+        tfs = flops / (kd["avg_ms"] * 1e-3) / 1e12
+        tiled = ldg >= 128 and kd["slots_per_launch"] < 128
+        roofline.update({"kernel": "k_chol_assemble+diag_panel+trailing+lauum" if tiled else "k_chol_inverse",
+                         "bound": "mfma", "achieved": round(tfs, 1), "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                         "frac": round(tfs / FP64_PEAK_TFS, 4), "alg_flops_per_launch": flops,
+                         "hbm_gbs_algorithmic": kd["gbs"]})
     traffic_file = os.path.join(ROOT, "profiles",
                                 f"traffic_{roofline['kernel'].replace('+', '_')}_{workload}.json")
     if os.path.exists(traffic_file):
