@@ -179,7 +179,7 @@ def kernel_table(prof, wl, workload, n, d, nnz, m, K, nsel, total, a_nnz=0):
         flops = float(tau) ** 3 * kd["slots_per_launch"]
         tfs = flops / (kd["avg_ms"] * 1e-3) / 1e12
         tiled = ldg >= 128 and kd["slots_per_launch"] < 128
-        roofline.update({"kernel": "k_chol_assemble+diag_panel+trailing+lauum" if tiled else "k_chol_inverse",
+        roofline.update({"kernel": "k_chol_assemble+ll_diag+ll_panel+ll_inverse+lauum" if tiled else "k_chol_inverse",
                          "bound": "mfma", "achieved": round(tfs, 1), "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
                          "frac": round(tfs / FP64_PEAK_TFS, 4), "alg_flops_per_launch": flops,
                          "hbm_gbs_algorithmic": kd["gbs"]})

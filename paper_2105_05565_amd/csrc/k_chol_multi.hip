@@ -3,23 +3,24 @@
 //
 // The single-workgroup factorisation (k_chol.hip) runs one sketch per compute unit,
 // which leaves most of the chip idle when a batch holds few sketches. Here every
-// 64 x 64 tile of every sketch is a workgroup, and the sequential structure of the
-// right-looking algorithm is carried by kernel boundaries on the stream:
+// 64 x 64 tile of every sketch is a workgroup, and the sequential structure of a
+// left-looking algorithm is carried by kernel boundaries on the stream; every output tile is
+// accumulated in MFMA registers over its chain of tile products and written once (a
+// right-looking update would read and write the whole trailing matrix at every step):
 //
 //   assemble               G (gathered rows of AS for the subsample sketch), identity
 //                          padding and empty buckets; U <- 0
-//   for k = 0 .. nt-1:
-//     diag_panel(k)        each workgroup factors G_kk = L_kk L_kk^T in LDS (redundantly)
-//                          and forms X = L_kk^{-1}; workgroup k stores X and U_kk = X^T,
-//                          workgroup i > k stores the panel L_ik = G_ik X^T, and
-//                          workgroup j < k finishes U_jk <- U_jk X^T   (U = (L^{-1})^T)
-//     trailing(k)          G_ij -= L_ik L_jk^T for k < j <= i, and the inverse step
-//                          U_ji -= U_jk L_ik^T for i > k, j <= k
+//   for j = 0 .. nt-1:
+//     ll_diag(j)           D = G_jj - sum_{k<j} L_jk L_jk^T factored in LDS; X_jj = L_jj^{-1}
+//                          stored, and U_jj = X_jj^T
+//     ll_panel(j)          L_ij = (G_ij - sum_{k<j} L_ik L_jk^T) X_jj^T for i > j, over G_ij
+//   for d = 1 .. nt-1:
+//     ll_inverse(d)        W = L^{-1} by distance d = i - j: W_ij = -X_ii sum_{k=j}^{i-1} L_ik W_kj,
+//                          stored transposed as U_ji (U = L^{-T}, so W_kj = U_jk^T)
 //   lauum                  G^{-1} = U U^T: tile (i, j) = sum_{k >= i} U_ik U_jk^T
 //
-// The inverse step uses W = L^{-1} computed right-looking (W_k* <- L_kk^{-1} W_k*,
-// W_i* -= L_ik W_k* for i > k), stored transposed as U so that every tile product
-// reads both operands row-major.
+// Tile products read their operands straight from global memory (they are shared by many
+// workgroups and stay in L2), so that many workgroups fit on a compute unit.
 #include "chol_tiles.h"
 #include "dev_common.h"
 #include "rs_internal.h"
@@ -73,58 +74,6 @@ __global__ __launch_bounds__(kThreads) void k_chol_assemble(MultiArgs a) {
   if (ti == 0 && tj == 0 && threadIdx.x == 0) a.status[slot] = 0;
 }
 
-__global__ __launch_bounds__(kThreads) void k_chol_diag_panel(MultiArgs a, int kt) {
-  extern __shared__ __align__(16) double lds[];
-  double* ta = lds;
-  double* tb = lds + NB * LDT;
-  double* td = lds + 2 * NB * LDT;
-  double* col = lds + 3 * NB * LDT;
-  __shared__ int bad;
-  if (*a.done) return;
-  const int64_t slot = blockIdx.y;
-  double* G = a.G + slot * a.ldg * a.ldg;
-  double* U = a.U + slot * a.ldg * a.ldg;
-  if (threadIdx.x == 0) bad = 0;
-  // G_kk is only read in this launch (L_kk itself is not needed later), so every
-  // workgroup can factor it.
-  load_tile(td, tile(G, a.ldg, kt, kt), a.ldg, false);
-  __syncthreads();
-  factor_diag_tile(td, ta, col, &bad);
-  const int npanel = a.nt - kt;
-  if ((int)blockIdx.x >= npanel) {
-    // finish column kt of U: U_jk <- U_jk X^T for j < kt (all updates were applied)
-    const int j = (int)blockIdx.x - npanel;
-    double* Ujk = tile(U, a.ldg, j, kt);
-    load_tile(tb, Ujk, a.ldg, false);
-    __syncthreads();
-    Acc c;
-    acc_zero(c);
-    tile_mma(c, tb, ta);
-    acc_for_each(c, [&](int r, int cc, double v) { Ujk[(int64_t)r * a.ldg + cc] = v; });
-    return;
-  }
-  const int it = kt + (int)blockIdx.x;
-  if (it == kt) {
-    double* Ukk = tile(U, a.ldg, kt, kt);
-    double* Xk = a.X + (slot * a.nt + kt) * NB * NB;
-    for (int e = threadIdx.x; e < NB * NB; e += kThreads) {
-      const int r = e >> 6, c = e & 63;
-      Ukk[(int64_t)r * a.ldg + c] = ta[c * LDT + r];
-      Xk[e] = ta[r * LDT + c];
-    }
-    if (threadIdx.x == 0 && bad) a.status[slot] = 1;
-    return;
-  }
-  // panel: L_ik = G_ik X^T  (C = a b^T with a = G_ik, b = X)
-  double* Gik = tile(G, a.ldg, it, kt);
-  load_tile(tb, Gik, a.ldg, false);
-  __syncthreads();
-  Acc c;
-  acc_zero(c);
-  tile_mma(c, tb, ta);
-  acc_for_each(c, [&](int r, int cc, double v) { Gik[(int64_t)r * a.ldg + cc] = v; });
-}
-
 // Linear index -> (i, j) with lo <= j <= i < nt (row-major over i).
 __device__ __forceinline__ void lower_pair(int idx, int lo, int* i, int* j) {
   int row = lo, width = 1;
@@ -137,32 +86,79 @@ __device__ __forceinline__ void lower_pair(int idx, int lo, int* i, int* j) {
   *j = lo + idx;
 }
 
-// Operands are read straight from global memory (they are shared by many workgroups and stay
-// in L2); without LDS many workgroups fit on a compute unit to cover the load latency.
-__global__ __launch_bounds__(kThreads) void k_chol_trailing(MultiArgs a, int kt, int ntrail) {
+__global__ __launch_bounds__(kThreads) void k_chol_ll_diag(MultiArgs a, int j) {
+  extern __shared__ __align__(16) double lds[];
+  double* ta = lds;
+  double* td = lds + NB * LDT;
+  double* col = lds + 2 * NB * LDT;
+  __shared__ int bad;
   if (*a.done) return;
-  const int64_t slot = blockIdx.y;
+  const int64_t slot = blockIdx.x;
   double* G = a.G + slot * a.ldg * a.ldg;
   double* U = a.U + slot * a.ldg * a.ldg;
-  int idx = blockIdx.x;
+  if (threadIdx.x == 0) bad = 0;
   Acc c;
   acc_zero(c);
-  if (idx < ntrail) {
-    // G_ij -= L_ik L_jk^T, kt < j <= i
-    int i, j;
-    lower_pair(idx, kt + 1, &i, &j);
-    tile_mma_global(c, tile(G, a.ldg, i, kt), tile(G, a.ldg, j, kt), a.ldg);
-    double* Gij = tile(G, a.ldg, i, j);
-    acc_for_each(c, [&](int r, int cc, double v) { Gij[(int64_t)r * a.ldg + cc] -= v; });
-    return;
+  for (int k = 0; k < j; ++k) tile_mma_global(c, tile(G, a.ldg, j, k), tile(G, a.ldg, j, k), a.ldg);
+  load_tile(td, tile(G, a.ldg, j, j), a.ldg, false);
+  __syncthreads();
+  acc_for_each(c, [&](int r, int cc, double v) { td[r * LDT + cc] -= v; });
+  __syncthreads();
+  factor_diag_tile(td, ta, col, &bad);
+  double* Ujj = tile(U, a.ldg, j, j);
+  double* Xj = a.X + (slot * a.nt + j) * NB * NB;
+  for (int e = threadIdx.x; e < NB * NB; e += kThreads) {
+    const int r = e >> 6, cc = e & 63;
+    Ujj[(int64_t)r * a.ldg + cc] = ta[cc * LDT + r];
+    Xj[e] = ta[r * LDT + cc];
   }
-  // inverse step: U_ji -= U_jk L_ik^T for i > kt, j <= kt (column i is finished by
-  // diag_panel(i), which scales it by X_ii^T)
-  idx -= ntrail;
-  const int i = kt + 1 + idx / (kt + 1), j = idx % (kt + 1);
+  if (threadIdx.x == 0 && bad) a.status[slot] = 1;
+}
+
+__global__ __launch_bounds__(kThreads) void k_chol_ll_panel(MultiArgs a, int j) {
+  extern __shared__ __align__(16) double lds[];
+  double* tp = lds;
+  double* tx = lds + NB * LDT;
+  if (*a.done) return;
+  const int64_t slot = blockIdx.y;
+  const int i = j + 1 + (int)blockIdx.x;
+  double* G = a.G + slot * a.ldg * a.ldg;
+  Acc c;
+  acc_zero(c);
+  for (int k = 0; k < j; ++k) tile_mma_global(c, tile(G, a.ldg, i, k), tile(G, a.ldg, j, k), a.ldg);
+  double* Gij = tile(G, a.ldg, i, j);
+  load_tile(tp, Gij, a.ldg, false);
+  load_tile(tx, a.X + (slot * a.nt + j) * NB * NB, NB, false);
+  __syncthreads();
+  acc_for_each(c, [&](int r, int cc, double v) { tp[r * LDT + cc] -= v; });
+  __syncthreads();
+  Acc c2;
+  acc_zero(c2);
+  tile_mma(c2, tp, tx);  // P X_jj^T
+  acc_for_each(c2, [&](int r, int cc, double v) { Gij[(int64_t)r * a.ldg + cc] = v; });
+}
+
+__global__ __launch_bounds__(kThreads) void k_chol_ll_inverse(MultiArgs a, int d) {
+  extern __shared__ __align__(16) double lds[];
+  double* tt = lds;
+  double* tx = lds + NB * LDT;
+  if (*a.done) return;
+  const int64_t slot = blockIdx.y;
+  const int j = (int)blockIdx.x, i = j + d;
+  double* G = a.G + slot * a.ldg * a.ldg;
+  double* U = a.U + slot * a.ldg * a.ldg;
+  Acc c;
+  acc_zero(c);
+  for (int k = j; k < i; ++k) tile_mma_global(c, tile(G, a.ldg, i, k), tile(U, a.ldg, j, k), a.ldg);
+  // T = sum_k L_ik W_kj; U_ji = W_ij^T = -T^T X_ii^T
+  acc_for_each(c, [&](int r, int cc, double v) { tt[cc * LDT + r] = v; });
+  load_tile(tx, a.X + (slot * a.nt + i) * NB * NB, NB, false);
+  __syncthreads();
+  Acc c2;
+  acc_zero(c2);
+  tile_mma(c2, tt, tx);
   double* Uji = tile(U, a.ldg, j, i);
-  tile_mma_global(c, tile(U, a.ldg, j, kt), tile(G, a.ldg, i, kt), a.ldg);  // U_jk L_ik^T
-  acc_for_each(c, [&](int r, int cc, double v) { Uji[(int64_t)r * a.ldg + cc] -= v; });
+  acc_for_each(c2, [&](int r, int cc, double v) { Uji[(int64_t)r * a.ldg + cc] = -v; });
 }
 
 __global__ __launch_bounds__(kThreads) void k_chol_lauum(MultiArgs a) {
@@ -196,18 +192,24 @@ hipError_t launch_chol_multi(double* G, double* U, double* X, int64_t ldg, int32
               status, done};
   const int nt = a.nt;
   const size_t diag_bytes = sizeof(double) * (3 * NB * LDT + NB);
-  hipError_t e = hipFuncSetAttribute((const void*)k_chol_diag_panel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)diag_bytes);
+  const size_t pair_bytes = sizeof(double) * 2 * NB * LDT;
+  hipError_t e = hipFuncSetAttribute((const void*)k_chol_ll_diag, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)diag_bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_chol_ll_panel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)pair_bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_chol_ll_inverse, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)pair_bytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_chol_assemble, dim3(nt, nt, nslots), dim3(kThreads), 0, s, a);
-  for (int kt = 0; kt < nt; ++kt) {
-    hipLaunchKernelGGL(k_chol_diag_panel, dim3(nt, nslots), dim3(kThreads), diag_bytes, s, a, kt);
-    const int rest = nt - kt - 1;
-    const int ntrail = rest * (rest + 1) / 2;
-    const int ninv = rest * (kt + 1);
-    if (ntrail + ninv > 0)
-      hipLaunchKernelGGL(k_chol_trailing, dim3(ntrail + ninv, nslots), dim3(kThreads), 0, s, a, kt, ntrail);
+  for (int j = 0; j < nt; ++j) {
+    hipLaunchKernelGGL(k_chol_ll_diag, dim3(nslots), dim3(kThreads), diag_bytes, s, a, j);
+    if (nt - j - 1 > 0)
+      hipLaunchKernelGGL(k_chol_ll_panel, dim3(nt - j - 1, nslots), dim3(kThreads), pair_bytes, s, a, j);
   }
+  for (int d = 1; d < nt; ++d)
+    hipLaunchKernelGGL(k_chol_ll_inverse, dim3(nt - d, nslots), dim3(kThreads), pair_bytes, s, a, d);
   hipLaunchKernelGGL(k_chol_lauum, dim3(nt * (nt + 1) / 2, nslots), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
