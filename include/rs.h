@@ -205,10 +205,12 @@ rs_status rs_create(const rs_matrix* X, const double* y, double lambda,
  * device; y: n values in the memory P.mem names). The library forms K (n x n, FP64) in
  * device memory (8 n^2 bytes), b = K y, and then runs the same iteration as rs_create's
  * dense path with m = n; the weights (rs_get_weights, rs_solve) are the n coefficients
- * alpha, and predictions at the points are K alpha. Options: the subsample sketch, FP64,
- * uniform sampling (RS_EUNSUPPORTED otherwise); o->form is ignored. Errors: RS_EINVAL
- * (sigma or lambda not positive and finite, CSR points, shapes, non-finite y), RS_ENOMEM,
- * RS_EDEVICE, RS_EUNSUPPORTED. */
+ * alpha, and predictions at the points are K alpha. Options: every sketch (count and
+ * SubCount take the dense-S products); RS_PREC_MIXED_BF16 with the subsample sketch runs the
+ * products on a BF16 copy of K (another 2 n^2 bytes) and keeps K for the shift lambda K S and
+ * the FP64 refresh; uniform sampling (RS_EUNSUPPORTED otherwise); the accelerated method with
+ * the subsample sketch; o->form is ignored. Errors: RS_EINVAL (sigma or lambda not positive
+ * and finite, CSR points, shapes, non-finite y), RS_ENOMEM, RS_EDEVICE, RS_EUNSUPPORTED. */
 rs_status rs_create_kernel(const rs_matrix* P, const double* y, double sigma, double lambda,
                            const rs_options* o, rs_handle** out);
 
@@ -245,7 +247,8 @@ rs_status rs_get_weights(rs_handle* h, double* w_out);
 
 /* The sketch S_{k-1} used by the last iteration, as (rows, cols, signs)
  * triplets of its nonzeros (host buffers of capacity m). *nnz_out receives
- * the count. Bucket-major order: all nonzeros of column 0 first. */
+ * the count. Bucket-major order: all nonzeros of column 0 first. RS_EUNSUPPORTED for the
+ * Gaussian and SRHT sketches (dense S; rs_get_products gives A S). */
 rs_status rs_get_last_sketch(const rs_handle* h, int32_t* rows, int32_t* cols, int8_t* signs,
                              int64_t* nnz_out);
 
