@@ -754,6 +754,29 @@ def main():
         prof2 = S2.profile()
         S2.close()
 
+    # context, untimed for the metric: the theoretical momentum rule (eq:parameterswitchtheory)
+    # on the same workload and seeds, when a solve is short
+    alt = None
+    if args.momentum == "heuristic" and total / args.steps <= 5.0:
+        S3 = rs.Solver(X, y, p.lam, tau=wl["tau"], sketch=wl["sketch"], form="primal", momentum="theory",
+                       subcount_k=wl["sub_k"], tol=1e-6, max_iter=args.max_iter, seed=1,
+                       precision=wl["precision"], lookahead=args.lookahead, stream=stream,
+                       sparse_route=args.sparse_route, pipeline=not args.no_pipeline,
+                       kernel_sigma=p.sigma if kern else None)
+        S3.solve()
+        t3, i3 = [], []
+        for i in range(min(args.steps, 3)):
+            S3.reset(i + 1)
+            torch.cuda.synchronize()
+            ti = time.perf_counter()
+            _, st3, rep3 = S3.solve()
+            torch.cuda.synchronize()
+            t3.append(time.perf_counter() - ti)
+            i3.append(rep3.iters if st3 == rs.RS_OK else -1)
+        S3.close()
+        alt = {"momentum": "theory", "time_s_median": round(statistics.median(t3), 6),
+               "iters_median": statistics.median(i3), "solves": len(t3)}
+
     T = total / args.steps
     tot_iters = sum(iters)
     kernels, roofline = kernel_table(prof, wl, args.workload, n, d, nnz, m, K, nsel, total, a_nnz)
@@ -777,6 +800,7 @@ def main():
         "setup_s": round(setup_s, 4),
         "roofline": roofline,
         "kernels": kernels,
+        "other_momentum_untimed": alt,
         "kernels_per_launch_untimed": {c: {"avg_ms": round(v["ms"] / v["launches"], 5),
                                            "launches": v["launches"]}
                                        for c, v in prof2.items() if v["launches"]},
