@@ -30,6 +30,9 @@ BF16_PEAK_TFS = 2500.0      # MI355X dense BF16 MFMA
 WORKLOADS = {
     "sparse_count": dict(kind="csr", gen="sparse_csr", sketch="count", tau=500, sub_k=0, precision="fp64",
                          name="csr_100000x20000_density0.001_count_tau500_primal"),
+    "sparse_count_dual": dict(kind="csr", gen="sparse_csr", sketch="count", tau=500, sub_k=0, precision="fp64",
+                              form="dual", fixed_iters=200,
+                              name="csr_100000x20000_density0.001_count_tau500_dual_200iterations"),
     "sparse_subcount": dict(kind="csr", gen="sparse_csr", sketch="subcount", tau=500, sub_k=4,
                             precision="fp64",
                             name="csr_100000x20000_density0.001_subcount_s2000_tau500_primal"),
@@ -118,7 +121,7 @@ def cpu_baseline(p, wl, gpu_iters_median, sample_s, momentum="heuristic"):
             from oracle.problem import kernel_system
             system = kernel_system(p.P, p.y, p.lam, p.sigma)
         else:
-            system = ridge_system(p.X, p.y, p.lam, "primal")
+            system = ridge_system(p.X, p.y, p.lam, wl.get("form", "primal"))
         st = init_state(system)
         opts = Options(sketch=wl["sketch"], tau=wl["tau"], sum_size=wl["sub_k"], momentum=momentum,
                        seed=1, tol=1e-6)
@@ -705,16 +708,20 @@ def main():
     stream = torch.cuda.current_stream().cuda_stream
     torch.cuda.synchronize()
 
+    form = wl.get("form", "primal")
+    fixed = wl.get("fixed_iters", 0)  # throughput at a fixed iteration count instead of time to 1e-6
+    tol = 0.0 if fixed else 1e-6
+    max_iter = fixed if fixed else args.max_iter
     t0 = time.perf_counter()
-    S = rs.Solver(X, y, p.lam, tau=wl["tau"], sketch=wl["sketch"], form="primal", momentum=args.momentum,
-                  subcount_k=wl["sub_k"], tol=1e-6, max_iter=args.max_iter, seed=1,
+    S = rs.Solver(X, y, p.lam, tau=wl["tau"], sketch=wl["sketch"], form=form, momentum=args.momentum,
+                  subcount_k=wl["sub_k"], tol=tol, max_iter=max_iter, seed=1,
                   precision=wl["precision"], lookahead=args.lookahead, profile=1, stream=stream,
                   sparse_route=args.sparse_route, pipeline=not args.no_pipeline,
                   kernel_sigma=p.sigma if kern else None)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     route, a_nnz = rs.rs_get_route(S.h)
-    m, K = (n, n) if kern else (d, n)
+    m, K = (n, n) if kern else ((n, d) if form == "dual" else (d, n))
     nsel = {"count": m, "subcount": wl["tau"] * max(wl["sub_k"], 1), "subsample": wl["tau"]}[wl["sketch"]]
 
     for w in range(args.warmup):
@@ -732,7 +739,7 @@ def main():
         _, st, rep = S.solve()
         times.append(time.perf_counter() - ti)
         iters.append(rep.iters)
-        if st != rs.RS_OK:
+        if st != rs.RS_OK and not fixed:
             print(f"[bench] step {i} did not converge: {rep.rel_res:.3e}", file=sys.stderr, flush=True)
         print(f"[bench] step {i}: {rep.iters} iterations, {times[-1]*1e3:.1f} ms", file=sys.stderr,
               flush=True)
@@ -745,8 +752,8 @@ def main():
     # skipped when one solve takes more than 10 s
     prof2 = {}
     if total / args.steps <= 10.0:
-        S2 = rs.Solver(X, y, p.lam, tau=wl["tau"], sketch=wl["sketch"], form="primal", momentum=args.momentum,
-                       subcount_k=wl["sub_k"], tol=1e-6, max_iter=args.max_iter, seed=1,
+        S2 = rs.Solver(X, y, p.lam, tau=wl["tau"], sketch=wl["sketch"], form=form, momentum=args.momentum,
+                       subcount_k=wl["sub_k"], tol=tol, max_iter=max_iter, seed=1,
                        precision=wl["precision"], lookahead=args.lookahead, profile=2, stream=stream,
                        sparse_route=args.sparse_route, pipeline=not args.no_pipeline,
                        kernel_sigma=p.sigma if kern else None)
@@ -757,7 +764,7 @@ def main():
     # context, untimed for the metric: the theoretical momentum rule (eq:parameterswitchtheory)
     # on the same workload and seeds, when a solve is short
     alt = None
-    if args.momentum == "heuristic" and total / args.steps <= 5.0:
+    if args.momentum == "heuristic" and total / args.steps <= 5.0 and not fixed:
         S3 = rs.Solver(X, y, p.lam, tau=wl["tau"], sketch=wl["sketch"], form="primal", momentum="theory",
                        subcount_k=wl["sub_k"], tol=1e-6, max_iter=args.max_iter, seed=1,
                        precision=wl["precision"], lookahead=args.lookahead, stream=stream,
@@ -781,15 +788,18 @@ def main():
     tot_iters = sum(iters)
     kernels, roofline = kernel_table(prof, wl, args.workload, n, d, nnz, m, K, nsel, total, a_nnz)
 
+    metric, value, unit, hib = "time-to-rel-residual 1e-6", round(T, 6), "s", False
+    if fixed:
+        metric, value, unit, hib = f"iterations/s over {fixed} iterations", round(tot_iters / total, 1), "it/s", True
     out = {
-        "metric": "time-to-rel-residual 1e-6", "value": round(T, 6), "unit": "s", "n_gpus": 1,
+        "metric": metric, "value": value, "unit": unit, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(T * 1e3, 3),
-        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "higher_is_better": hib, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16 products, f32 accumulate, f64 solve" if wl["precision"] == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": wl["name"], "n": n, "d": d, "nnz": nnz, "form": "kernel" if kern else "primal",
+        "config": {"workload": wl["name"], "n": n, "d": d, "nnz": nnz, "form": "kernel" if kern else form,
                    "sketch": wl["sketch"], "tau": wl["tau"], "subcount_k": wl["sub_k"],
-                   "lambda": p.lam, "momentum": args.momentum, "tol": 1e-6,
+                   "lambda": p.lam, "momentum": args.momentum, "tol": tol,
                    "precision": wl["precision"], "max_iter": args.max_iter,
                    "sparse_route": {0: None, 1: "scatter", 2: "arows"}[route],
                    "a_nnz": a_nnz or None,
@@ -808,7 +818,9 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         cb = cpu_baseline(p, wl, statistics.median(iters), args.cpu_sample_s, args.momentum)
-        cb.pop("s_per_iter")
+        per_iter = cb.pop("s_per_iter")
+        if fixed:
+            cb["value"], cb["unit"] = round(1.0 / per_iter, 3), "it/s"
         out["cpu_baseline"] = cb
     print(json.dumps(out))
 

@@ -218,6 +218,17 @@ def test_sparse_full_size_first_iterations():
                               sub_k=sub_k, checkpoints=[1, 3], route=route)
 
 
+def test_sparse_dual_full_size_first_iterations():
+    """The sparse workload in the dual form at full size (m = n = 100000 coordinates, K = 20000,
+    count sketch tau = 500): the first iterations against the oracle on both routes (the rows
+    of X X^T hold about 2e8 entries, beyond the LDS bucket map: the global-map kernel)."""
+    p = inputs.sparse_csr()
+    for route in ("arows", "scatter"):
+        print(f"[dual full size] route={route}", flush=True)
+        _trajectory_check(p.X, p.y, p.lam, form="dual", kind="count", tau=500, momentum="heuristic",
+                          checkpoints=[1, 2], route=route)
+
+
 def test_solve_converges_to_direct_solution():
     p = _dense(400, 120, 0.1, seed=4)
     S = rs.Solver(p.X, p.y, p.lam, tau=30, sketch="subsample", momentum="heuristic", tol=1e-10,
