@@ -155,7 +155,14 @@ def kernel_table(prof, wl, workload, n, d, nnz, m, K, nsel, total, a_nnz=0):
     dom = max((c for c in kernels if c != "iters"), key=lambda c: kernels[c]["total_ms"])
     kd = kernels[dom]
     achieved = kd["gbs"]
-    as_name = ("k_as_arows_lds" if a_nnz else "k_as_sparse_bucket") if wl["kind"] == "csr" \
+    def arows_name():
+        # which A-rows kernel the library picks: 16-bit bucket map in LDS, packed 10-bit map, or global map
+        if 2 * m + 64 * wl["tau"] <= 96 * 1024 and wl["tau"] < 16383:
+            return "k_as_arows_lds"
+        if wl["tau"] <= 511 and (m + 2) // 3 * 4 + 32 * wl["tau"] <= 156 * 1024:
+            return "k_as_arows_packed"
+        return "k_as_arows"
+    as_name = (arows_name() if a_nnz else "k_as_sparse_bucket") if wl["kind"] == "csr" \
         else wl.get("as_kernel", "k_as_dense_f64_128")
     roofline = {"kernel": {"as": as_name, "g": "k_g_from_as",
                            "update": "k_update", "chol": "k_chol_inverse", "delta": "k_delta",

@@ -28,6 +28,14 @@ size_t arows_lds_bytes(int64_t m, int32_t tau) {
   return (size_t)((2 * m + 15) & ~15ll) + sizeof(double) * 8 * (size_t)tau;
 }
 
+// Packed bucket map for larger m: three 10-bit codes per 32-bit word (2 bucket + sign, 1023 = no
+// entry; tau <= 511), beside the accumulators of kPackedWaves waves.
+constexpr int kPackedWaves = 4;
+constexpr uint32_t kNoCode = 1023;
+size_t arows_packed_lds_bytes(int64_t m, int32_t tau) {
+  return (size_t)(((m + 2) / 3 * 4 + 15) & ~15ll) + sizeof(double) * kPackedWaves * (size_t)tau;
+}
+
 // cnt[i] = (row length of Z^T)^2: the products row i contributes to Z Z^T.
 __global__ void k_pair_counts(const int64_t* __restrict__ zt_ptr, int64_t K, int64_t* __restrict__ cnt) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -202,6 +210,79 @@ __global__ __launch_bounds__(512) void k_as_arows_lds(const int64_t* __restrict_
   }
 }
 
+// As k_as_arows_lds for a bucket map too large for 16-bit codes in LDS: the codes are packed
+// three to a 32-bit word, and 4 waves share a workgroup (one AS row each at a time).
+__global__ __launch_bounds__(64 * kPackedWaves) void k_as_arows_packed(const int64_t* __restrict__ a_ptr,
+                                                                      const int32_t* __restrict__ a_col,
+                                                                      const double* __restrict__ a_val, int64_t m,
+                                                                      int32_t tau, int64_t ldas, double lam,
+                                                                      const int32_t* __restrict__ hmap_all,
+                                                                      double* __restrict__ AS, int32_t nslots,
+                                                                      int64_t nchunks, const int32_t* __restrict__ done) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int64_t nwords = (m + 2) / 3;
+  uint32_t* pm = reinterpret_cast<uint32_t*>(lds_raw);                                      // [nwords]
+  double* acc_all = reinterpret_cast<double*>(lds_raw + ((nwords * 4 + 15) & ~15ll));     // [waves][tau]
+  if (*done) return;
+  constexpr int kT = 64 * kPackedWaves;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t xcd = blockIdx.x & 7, bi = blockIdx.x >> 3;
+  const int64_t chunk = 8 * (bi / nslots) + xcd, slot = bi % nslots;
+  if (chunk >= nchunks) return;
+  const int32_t* hmap = hmap_all + slot * m;
+  for (int64_t w = tid; w < nwords; w += kT) {
+    uint32_t word = 0;
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int64_t jj = 3 * w + u;
+      const int32_t code = jj < m ? hmap[jj] : -1;
+      word |= (code >= 0 ? (uint32_t)code : kNoCode) << (10 * u);
+    }
+    pm[w] = word;
+  }
+  __syncthreads();
+  double* acc = acc_all + (int64_t)wave * tau;
+  double* out_base = AS + slot * m * ldas;
+  const int64_t j0 = chunk * kLdsRows;
+  const int64_t j1 = min(m, j0 + kLdsRows);
+  auto code_of = [&](int64_t col) -> int {
+    const uint32_t q = (uint32_t)col / 3u, r = (uint32_t)col - 3u * q;
+    const uint32_t c = (pm[q] >> (10u * r)) & kNoCode;
+    return c == kNoCode ? -1 : (int)c;
+  };
+  for (int64_t j = j0 + wave; j < j1; j += kPackedWaves) {
+    for (int c = lane; c < tau; c += 64) acc[c] = 0.0;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    const int64_t p0 = a_ptr[j], p1 = a_ptr[j + 1];
+    for (int64_t pb = p0; pb < p1; pb += 64 * kLdsGroups) {
+      int32_t col[kLdsGroups];
+      double val[kLdsGroups];
+#pragma unroll
+      for (int u = 0; u < kLdsGroups; ++u) {
+        const int64_t p = pb + u * 64 + lane;
+        col[u] = p < p1 ? a_col[p] : -1;
+        val[u] = p < p1 ? a_val[p] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kLdsGroups; ++u) {
+        const int code = col[u] >= 0 ? code_of(col[u]) : -1;
+        if (code >= 0) atomicAdd(&acc[code >> 1], (code & 1) ? -val[u] : val[u]);
+      }
+    }
+    if (lane == 0) {
+      const int cj = code_of(j);
+      if (cj >= 0) atomicAdd(&acc[cj >> 1], (cj & 1) ? -lam : lam);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    double* out = out_base + j * ldas;
+    for (int c = lane; c < tau; c += 64) out[c] = acc[c];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  }
+}
+
 // G[slot][b][c] = sum over the members j of bucket b (in member order) of s_j AS[j][c].
 __global__ __launch_bounds__(256) void k_g_from_as(const double* __restrict__ AS_all, int64_t m,
                                                    int32_t tau, int64_t ldas,
@@ -342,6 +423,17 @@ hipError_t launch_as_arows(const int64_t* a_ptr, const int32_t* a_col, const dou
     if (nblocks > (int64_t)INT32_MAX) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_as_arows_lds, dim3((unsigned)nblocks), dim3(512), lds, s, a_ptr, a_col, a_val, m, tau,
                        ldas, lam, hmap, AS, nslots, nchunks, done);
+    e = hipGetLastError();
+  } else if (tau <= 511 && arows_packed_lds_bytes(m, tau) <= 156 * 1024) {
+    // packed map in LDS: one workgroup of 4 waves per CU
+    const size_t plds = arows_packed_lds_bytes(m, tau);
+    e = hipFuncSetAttribute((const void*)k_as_arows_packed, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plds);
+    if (e != hipSuccess) return e;
+    const int64_t nchunks = (m + kLdsRows - 1) / kLdsRows;
+    const int64_t nblocks = 8 * (int64_t)nslots * ((nchunks + 7) / 8);
+    if (nblocks > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_as_arows_packed, dim3((unsigned)nblocks), dim3(64 * kPackedWaves), plds, s, a_ptr, a_col,
+                       a_val, m, tau, ldas, lam, hmap, AS, nslots, nchunks, done);
     e = hipGetLastError();
   } else if (tau <= 1024)
     e = arows_launch<16>(a_ptr, a_col, a_val, m, tau, ldas, nslots, lam, hmap, AS, done, s);

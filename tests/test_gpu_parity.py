@@ -229,6 +229,15 @@ def test_sparse_dual_full_size_first_iterations():
                           checkpoints=[1, 2], route=route)
 
 
+def test_sparse_packed_bucket_map():
+    """m = 45000 coordinates (dual form): the 16-bit bucket map no longer fits LDS beside eight
+    accumulators, so the rows of X X^T take the kernel with three 10-bit codes per word."""
+    p = _csr(45000, 3000, 0.002, 0.05, seed=45)
+    for kind, sub_k in (("count", 0), ("subcount", 10)):
+        _trajectory_check(p.X, p.y, p.lam, form="dual", kind=kind, tau=100, momentum="heuristic", sub_k=sub_k,
+                          checkpoints=[1, 5, 20], route="arows")
+
+
 def test_solve_converges_to_direct_solution():
     p = _dense(400, 120, 0.1, seed=4)
     S = rs.Solver(p.X, p.y, p.lam, tau=30, sketch="subsample", momentum="heuristic", tol=1e-10,
