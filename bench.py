@@ -5,8 +5,9 @@ A step is one full solve (x^0 = 0 until ||r^k|| / ||r^0|| <= 1e-6) of the sparse
 workload: CSR X 100000 x 20000 with 0.1% uniform nonzeros (FP32 values N(0,1)),
 y = X w* + 0.01 noise, lambda = 1e-3, primal form, count sketch tau = 500,
 heuristic momentum (--momentum theory: the increasing rule of Sec. 6), FP64
-arithmetic. Every step uses a new sketch seed
-(seed = step index + 1); the data and its device layouts stay resident in HBM.
+arithmetic. Every step uses a new sketch seed (seed = step index + 1; 10 steps by default, the
+paper's 10 runs per setting, reported as median and quartiles); the data and its device
+layouts stay resident in HBM.
 
 Prints one JSON line with the metric, a roofline entry for the kernel that
 dominates the solve (algorithmic bytes per launch over its HIP-event duration),
@@ -640,7 +641,7 @@ def main_accel(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sparse_count", choices=sorted(WORKLOADS))
     ap.add_argument("--lookahead", type=int, default=0)
