@@ -158,3 +158,55 @@ def test_tiled_factorisation_inverse(tau, kind):
     assert err <= 1e-9, err
     assert np.allclose(Gi, Gi.T, rtol=0, atol=1e-12 * np.abs(Gi).max())
     S.close()
+
+
+@pytest.mark.parametrize("workload,tau", [("dense_mixed", 1024), ("dense_learned", 512)])
+def test_mixed_full_size_sampled(workload, tau):
+    """The BF16 workloads at full size, launched as the benchmark launches them (device inputs
+    on torch's current stream, default lookahead and preparation pipeline; uniform sampling):
+    X 50000 x 8192 with log-normal(0,1) column scales, tau = 1024, and X 200000 x 4096 with
+    log-normal(0,2) columns and 5% correlated ones, tau = 512, both primal. Checked: the
+    third sketch bit-exact; 96 sampled rows of its AS against the oracle's FP64 rows within
+    the BF16/FP32 bound; G^{-1} inverting the sketched matrix the GPU formed, within the
+    bound of an inverse through Cholesky (Higham, Sec. 14.3); and after 20 iterations the
+    refreshed residual and the previous one equal to A x - b from the oracle's FP64 system,
+    within the dot-product bound of the two summation orders (each side's error in
+    Z (Z^T x) + lambda x - Z y is within 2 gamma_n (|Z| (|Z^T| |x| + |y|) + lambda |x|), as
+    d < n)."""
+    import torch
+    p = getattr(inputs, workload)()
+    n, d = p.X.shape
+    print(f"[mixed full size] {workload} n={n} d={d} tau={tau}", flush=True)
+    X = torch.from_numpy(p.X).cuda()
+    y = torch.from_numpy(p.y).cuda()
+    stream = torch.cuda.current_stream().cuda_stream
+    S = rs.Solver(X, y, p.lam, tau=tau, sketch="subsample", form="primal", tol=0.0, seed=1,
+                  precision="mixed", stream=stream)
+    S.step(3)
+    rows, cols, _ = S.last_sketch()
+    exp = osk.draw_subsample(1, 0, 2, d, tau)
+    assert np.array_equal(rows, exp.rows) and np.array_equal(cols, exp.cols)
+    AS, Gi = S.products()
+    system = ridge_system(p.X, p.y, p.lam, "primal")
+    Z = system.Z  # d x n, FP64
+    C = exp.rows
+    rng = np.random.default_rng(11)
+    idx = np.unique(np.concatenate([rng.choice(d, 64, replace=False), C[:32]]))
+    ZC = Z[C]
+    AS_or = Z[idx] @ ZC.T
+    AS_or[idx[:, None] == C[None, :]] += p.lam
+    bound = (2 * U_BF16 + n * U_FP32) * (np.abs(Z[idx]) @ np.abs(ZC).T) + 1e-30
+    err = np.abs(AS[idx] - AS_or)
+    assert np.all(err <= bound), float((err / bound).max())
+    Gm = np.tril(AS[C]) + np.tril(AS[C], -1).T
+    kappa = np.linalg.cond(Gm)
+    assert np.abs(Gi @ Gm - np.eye(tau)).max() <= 4 * tau * 2.0 ** -53 * kappa, kappa
+    del ZC, AS, Gi, Gm
+    S.step(20 - S.k)
+    x, xp, r, rp = S.state()
+    gamma_n = n * 2.0 ** -53 / (1 - n * 2.0 ** -53)
+    for xx, rr in ((x, r), (xp, rp)):
+        true = system.matvec(xx) - system.b
+        mag = np.abs(Z) @ (np.abs(system.X) @ np.abs(xx) + np.abs(p.y)) + p.lam * np.abs(xx)
+        assert np.all(np.abs(rr - true) <= 4 * gamma_n * mag)
+    S.close()
