@@ -208,6 +208,17 @@ def test_dense_primal_full_size_trajectory():
                           checkpoints=[1, 10, 50])
 
 
+@pytest.mark.parametrize("workload,tau", [("dense_mixed", 1024), ("dense_learned", 512)])
+def test_dense_large_full_size_first_iterations_fp64(workload, tau):
+    """The large dense workloads at full size on the FP64 path (X 50000 x 8192 with log-normal(0,1)
+    column scales, tau = 1024; X 200000 x 4096 with log-normal(0,2) columns and 5% correlated
+    ones, tau = 512; primal, heuristic momentum): the first five iterations against the oracle."""
+    p = getattr(inputs, workload)()
+    print(f"[dense full size fp64] {workload} tau={tau}", flush=True)
+    _trajectory_check(p.X, p.y, p.lam, form="primal", kind="subsample", tau=tau, momentum="heuristic",
+                      checkpoints=[1, 3, 5])
+
+
 def test_sparse_full_size_first_iterations():
     """The sparse workload at full size (CSR 100000 x 20000, 0.1%, tau = 500): the first
     iterations against the oracle, count and SubCount (s = 4 tau)."""
