@@ -182,3 +182,42 @@ def test_reset_and_autotune():
         assert _rel(B.state(p, 3)[0], first[p]) <= 1e-14
     B.close()
     C.close()
+
+
+def test_batched_full_size_sampled_slots():
+    """The batched workload at full size, built as the benchmark builds it (64 problems,
+    n ~ U{2000..40000}, d ~ U{500..8000}, half dense and half CSR at 0.5%, 16 lambdas x 4
+    right-hand sides, autotuned launch shapes, torch's current stream): after three lock
+    steps, one slot of each of four problems (dense and CSR, primal and dual form where the
+    batch has one) against the oracle's solve to 1e-10."""
+    import torch
+    from oracle.problem import choose_form
+    probs = inputs.batched()
+    stream = torch.cuda.current_stream().cuda_stream
+    B = rs.Batch(probs, tol=0.0, seed=1, autotune=True, stream=stream)
+    N = 3
+    B.step(N)
+    assert B.k == N
+    picks = []
+    for kind in ("dense", "csr"):
+        for form in ("primal", "dual"):
+            cands = [p for p, pr in enumerate(probs)
+                     if pr["kind"] == kind and choose_form(pr["n"], pr["d"]) == form]
+            if cands:
+                picks.append(cands[len(cands) // 2])
+    assert len(picks) >= 2
+    for p in picks:
+        pr = probs[p]
+        l, q = p % len(pr["lambdas"]), p % pr["y"].shape[1]
+        print(f"[batched full size] problem {p} {pr['kind']} n={pr['n']} d={pr['d']} tau={pr['tau']}",
+              flush=True)
+        system = ridge_system(pr["X"], pr["y"][:, q], pr["lambdas"][l])
+        opts = Options(sketch="subsample" if pr["kind"] == "dense" else "count", tau=pr["tau"],
+                       momentum="heuristic", tol=0.0, max_iter=N, seed=1, problem_id=p)
+        st = init_state(system)
+        for _ in range(N):
+            step(system, st, opts)
+        x, xp, r, rp = B.state(p, l * pr["y"].shape[1] + q)
+        assert _rel(x, st.w) <= 1e-10 and _rel(r, st.r) <= 1e-10, (p, _rel(x, st.w), _rel(r, st.r))
+        assert _rel(xp, st.w_prev) <= 1e-10 and _rel(rp, st.r_prev) <= 1e-10, p
+    B.close()
