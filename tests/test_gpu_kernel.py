@@ -159,6 +159,36 @@ def test_kernel_mixed_products_within_bound():
     S.close()
 
 
+def test_kernel_mixed_full_size_products_sampled():
+    """The kernel workload at full size with BF16 products, launched as the benchmark launches
+    it (20640 points on the device, tau = 5160, default lookahead and pipeline, torch's current
+    stream): the third sketch bit-exact and 80 sampled rows of its AS = K (K S) + lambda K S
+    against the oracle's FP64 rows, within the bound of the small case."""
+    import torch
+    p = inputs.kernel_california()
+    n = p.P.shape[0]
+    tau = n // 4
+    print(f"[kernel mixed full size] n={n} tau={tau}", flush=True)
+    stream = torch.cuda.current_stream().cuda_stream
+    S = rs.Solver(torch.from_numpy(p.P).cuda(), torch.from_numpy(p.y).cuda(), p.lam, tau=tau,
+                  kernel_sigma=p.sigma, tol=0.0, seed=1, precision="mixed", stream=stream)
+    S.step(3)
+    rows, cols, _ = S.last_sketch()
+    sketch = osk.draw_subsample(1, 0, 2, n, tau)
+    assert np.array_equal(rows, sketch.rows) and np.array_equal(cols, sketch.cols)
+    AS, _ = S.products()
+    S.close()
+    C = sketch.rows
+    rng = np.random.default_rng(3)
+    idx = np.unique(np.concatenate([rng.choice(n, 64, replace=False), C[:16]]))
+    Kr = rbf_kernel(p.P, p.sigma, rows=idx)
+    KC = rbf_kernel(p.P, p.sigma, rows=C)
+    AS_o = Kr @ KC.T + p.lam * Kr[:, C]
+    bound = (2 * U_BF16 + n * U_FP32) * (np.abs(Kr) @ np.abs(KC).T) + 2 * U_FP32 * np.abs(AS_o) + 1e-30
+    err = np.abs(AS[idx] - AS_o)
+    assert np.all(err <= bound), float((err / bound).max())
+
+
 def test_kernel_mixed_refresh_uses_fp64_kernel_matrix():
     p = inputs.make_points(600, 8, 1e-2, 0.5, seed=62)
     system = kernel_system(p.P, p.y, p.lam, p.sigma)
