@@ -44,7 +44,7 @@ enum {
   RS_OK = 0,
   RS_NOT_CONVERGED = 1,   /* warning: max_iter reached before tol */
   RS_EINVAL = -1,         /* bad argument: shape, tau > m, lambda <= 0, NaN, ... */
-  RS_ENOMEM = -2,         /* device allocation failed */
+  RS_ENOMEM = -2,         /* allocation failed (device memory, or host buffers of a copy-out) */
   RS_EDEVICE = -3,        /* a HIP call failed */
   RS_ESINGULAR = -4,      /* non-positive Cholesky pivot on a nonzero sketch column */
   RS_EUNSUPPORTED = -5    /* option combination not built */

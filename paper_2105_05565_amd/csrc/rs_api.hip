@@ -1105,6 +1105,9 @@ rs_status rs_step(rs_handle* h, int64_t iters, double* rel_res_out) {
   } catch (const Fail& f) {
     h->last_error = f.msg;
     return f.code;
+  } catch (const std::exception& e) {
+    h->last_error = e.what();
+    return RS_EDEVICE;
   }
 }
 
@@ -1133,6 +1136,9 @@ rs_status rs_reset(rs_handle* h, uint64_t seed) {
   } catch (const Fail& f) {
     h->last_error = f.msg;
     return f.code;
+  } catch (const std::exception& e) {
+    h->last_error = e.what();
+    return RS_EDEVICE;
   }
 }
 
@@ -1182,6 +1188,9 @@ rs_status rs_get_weights(rs_handle* h, double* w_out) {
   } catch (const Fail& f) {
     h->last_error = f.msg;
     return f.code;
+  } catch (const std::exception& e) {
+    h->last_error = e.what();
+    return RS_EDEVICE;
   }
 }
 
@@ -1207,6 +1216,9 @@ rs_status rs_solve(rs_handle* h, double* w_out, rs_report* rep) {
   } catch (const Fail& f) {
     h->last_error = f.msg;
     return f.code;
+  } catch (const std::exception& e) {
+    h->last_error = e.what();
+    return RS_EDEVICE;
   }
 }
 
@@ -1229,22 +1241,26 @@ rs_status rs_get_last_sketch(const rs_handle* h, int32_t* rows, int32_t* cols, i
   const int64_t it = h->k - 1;
   if (it < 0 || h->batch_k0 < 0 || it < h->batch_k0 || it >= h->batch_k0 + h->batch_n) return RS_EINVAL;
   const int64_t slot = it - h->batch_k0;
-  std::vector<int32_t> mem(h->nsel), off(h->tau + 1), hm(h->m);
-  if (hipMemcpy(mem.data(), h->members + slot * h->nsel, sizeof(int32_t) * h->nsel, hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(off.data(), h->offs + slot * (h->tau + 1), sizeof(int32_t) * (h->tau + 1), hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(hm.data(), h->hmap + slot * h->m, sizeof(int32_t) * h->m, hipMemcpyDeviceToHost) != hipSuccess)
-    return RS_EDEVICE;
-  int64_t c = 0;
-  for (int b = 0; b < h->tau; ++b)
-    for (int p = off[b]; p < off[b + 1]; ++p) {
-      const int32_t j = mem[p];
-      rows[c] = j;
-      cols[c] = b;
-      signs[c] = (hm[j] & 1) ? -1 : 1;
-      ++c;
-    }
-  *nnz_out = c;
-  return RS_OK;
+  try {
+    std::vector<int32_t> mem(h->nsel), off(h->tau + 1), hm(h->m);
+    if (hipMemcpy(mem.data(), h->members + slot * h->nsel, sizeof(int32_t) * h->nsel, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(off.data(), h->offs + slot * (h->tau + 1), sizeof(int32_t) * (h->tau + 1), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(hm.data(), h->hmap + slot * h->m, sizeof(int32_t) * h->m, hipMemcpyDeviceToHost) != hipSuccess)
+      return RS_EDEVICE;
+    int64_t c = 0;
+    for (int b = 0; b < h->tau; ++b)
+      for (int p = off[b]; p < off[b + 1]; ++p) {
+        const int32_t j = mem[p];
+        rows[c] = j;
+        cols[c] = b;
+        signs[c] = (hm[j] & 1) ? -1 : 1;
+        ++c;
+      }
+    *nnz_out = c;
+    return RS_OK;
+  } catch (const std::exception&) {
+    return RS_ENOMEM;  // host buffers
+  }
 }
 
 rs_status rs_get_products(const rs_handle* h, double* as_out, double* ginv_out) {
@@ -1252,28 +1268,32 @@ rs_status rs_get_products(const rs_handle* h, double* as_out, double* ginv_out) 
   const int64_t it = h->k - 1;
   if (it < 0 || h->batch_k0 < 0 || it < h->batch_k0 || it >= h->batch_k0 + h->batch_n) return RS_EINVAL;
   const int64_t slot = it - h->batch_k0;
-  if (as_out) {
-    const size_t elt = h->mixed ? sizeof(float) : sizeof(double);
-    std::vector<char> buf((size_t)h->m * h->ldas * elt);
-    if (hipMemcpy(buf.data(), (const char*)h->AS + (size_t)slot * h->m * h->ldas * elt, buf.size(),
-                  hipMemcpyDeviceToHost) != hipSuccess)
-      return RS_EDEVICE;
-    for (int64_t j = 0; j < h->m; ++j)
-      for (int64_t c = 0; c < h->tau; ++c) {
-        const size_t idx = (size_t)j * h->ldas + c;
-        as_out[j * h->tau + c] = h->mixed ? (double)((const float*)buf.data())[idx]
-                                          : ((const double*)buf.data())[idx];
-      }
+  try {
+    if (as_out) {
+      const size_t elt = h->mixed ? sizeof(float) : sizeof(double);
+      std::vector<char> buf((size_t)h->m * h->ldas * elt);
+      if (hipMemcpy(buf.data(), (const char*)h->AS + (size_t)slot * h->m * h->ldas * elt, buf.size(),
+                    hipMemcpyDeviceToHost) != hipSuccess)
+        return RS_EDEVICE;
+      for (int64_t j = 0; j < h->m; ++j)
+        for (int64_t c = 0; c < h->tau; ++c) {
+          const size_t idx = (size_t)j * h->ldas + c;
+          as_out[j * h->tau + c] = h->mixed ? (double)((const float*)buf.data())[idx]
+                                            : ((const double*)buf.data())[idx];
+        }
+    }
+    if (ginv_out) {
+      std::vector<double> g((size_t)h->ldg * h->ldg);
+      if (hipMemcpy(g.data(), h->G + (size_t)slot * h->ldg * h->ldg, sizeof(double) * g.size(),
+                    hipMemcpyDeviceToHost) != hipSuccess)
+        return RS_EDEVICE;
+      for (int64_t r = 0; r < h->tau; ++r)
+        for (int64_t c = 0; c < h->tau; ++c) ginv_out[r * h->tau + c] = g[(size_t)r * h->ldg + c];
+    }
+    return RS_OK;
+  } catch (const std::exception&) {
+    return RS_ENOMEM;  // host buffers
   }
-  if (ginv_out) {
-    std::vector<double> g((size_t)h->ldg * h->ldg);
-    if (hipMemcpy(g.data(), h->G + (size_t)slot * h->ldg * h->ldg, sizeof(double) * g.size(),
-                  hipMemcpyDeviceToHost) != hipSuccess)
-      return RS_EDEVICE;
-    for (int64_t r = 0; r < h->tau; ++r)
-      for (int64_t c = 0; c < h->tau; ++c) ginv_out[r * h->tau + c] = g[(size_t)r * h->ldg + c];
-  }
-  return RS_OK;
 }
 
 rs_status rs_get_history(const rs_handle* h, double* out, int64_t count) {

@@ -720,6 +720,9 @@ rs_status rs_batch_step(rs_batch* B, int64_t iters) {
   } catch (const Fail& f) {
     B->last_error = f.msg;
     return f.code;
+  } catch (const std::exception& e) {
+    B->last_error = e.what();
+    return RS_EDEVICE;
   }
 }
 
@@ -757,6 +760,9 @@ rs_status rs_batch_solve(rs_batch* B, rs_batch_report* rep) {
   } catch (const Fail& f) {
     B->last_error = f.msg;
     return f.code;
+  } catch (const std::exception& e) {
+    B->last_error = e.what();
+    return RS_EDEVICE;
   }
 }
 
@@ -781,6 +787,9 @@ rs_status rs_batch_reset(rs_batch* B, uint64_t seed) {
   } catch (const Fail& f) {
     B->last_error = f.msg;
     return f.code;
+  } catch (const std::exception& e) {
+    B->last_error = e.what();
+    return RS_EDEVICE;
   }
 }
 
@@ -825,6 +834,8 @@ rs_status rs_batch_get_state(const rs_batch* B, int32_t p, int32_t slot, double*
     kp = problem_k(B, p);
   } catch (const Fail& f) {
     return f.code;
+  } catch (const std::exception&) {
+    return RS_EDEVICE;
   }
   const int cur = (int)(kp & 1), prv = 1 - cur;
   const double* src[4] = {st.x[cur], st.x[prv], st.r[cur], st.r[prv]};
@@ -870,6 +881,9 @@ rs_status rs_batch_get_weights(rs_batch* B, int32_t p, double* w_out) {
   } catch (const Fail& f) {
     B->last_error = f.msg;
     return f.code;
+  } catch (const std::exception& e) {
+    B->last_error = e.what();
+    return RS_EDEVICE;
   }
 }
 

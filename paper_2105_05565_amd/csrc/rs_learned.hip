@@ -130,6 +130,9 @@ rs_status rs_trainer_create(int32_t tau, uint64_t init_seed, rs_trainer** out) {
   } catch (const Fail& f) {
     rs_trainer_destroy(T);
     return f.code;
+  } catch (const std::exception&) {
+    rs_trainer_destroy(T);
+    return RS_EDEVICE;
   }
 }
 
@@ -148,6 +151,9 @@ rs_status rs_trainer_add_traces(rs_trainer* T, const rs_handle* h) {
   } catch (const Fail& f) {
     T->last_error = f.msg;
     return f.code;
+  } catch (const std::exception& e) {
+    T->last_error = e.what();
+    return RS_EDEVICE;
   }
 }
 
@@ -163,6 +169,9 @@ rs_status rs_trainer_add_records(rs_trainer* T, const float* F, const float* cre
   } catch (const Fail& f) {
     T->last_error = f.msg;
     return f.code;
+  } catch (const std::exception& e) {
+    T->last_error = e.what();
+    return RS_EDEVICE;
   }
 }
 
@@ -207,6 +216,9 @@ rs_status rs_trainer_fit(rs_trainer* T, int32_t epochs, int32_t batch, double lr
   } catch (const Fail& f) {
     T->last_error = f.msg;
     return f.code;
+  } catch (const std::exception& e) {
+    T->last_error = e.what();
+    return RS_EDEVICE;
   }
 }
 
@@ -244,6 +256,8 @@ rs_status rs_mlp_init(uint64_t seed, float* params_out) {
     return RS_OK;
   } catch (const Fail& f) {
     return f.code;
+  } catch (const std::exception&) {
+    return RS_EDEVICE;
   }
 }
 
@@ -259,6 +273,8 @@ rs_status rs_mlp_forward(const float* params, const float* F, int64_t rows, floa
     return RS_OK;
   } catch (const Fail& f) {
     return f.code;
+  } catch (const std::exception&) {
+    return RS_EDEVICE;
   }
 }
 
@@ -289,6 +305,8 @@ rs_status rs_mlp_gradient(const float* params, const float* F, const float* cred
     return RS_OK;
   } catch (const Fail& f) {
     return f.code;
+  } catch (const std::exception&) {
+    return RS_EDEVICE;
   }
 }
 
@@ -308,6 +326,8 @@ rs_status rs_adam_update(float* params, float* m1, float* m2, const float* grad,
     return RS_OK;
   } catch (const Fail& f) {
     return f.code;
+  } catch (const std::exception&) {
+    return RS_EDEVICE;
   }
 }
 
@@ -324,6 +344,8 @@ rs_status rs_proposal(const float* s, int64_t m, double eps, float* q_out, int32
     return RS_OK;
   } catch (const Fail& f) {
     return f.code;
+  } catch (const std::exception&) {
+    return RS_EDEVICE;
   }
 }
 
@@ -347,6 +369,8 @@ rs_status rs_features(const double* a, const double* r, const double* rp, const 
     return RS_OK;
   } catch (const Fail& f) {
     return f.code;
+  } catch (const std::exception&) {
+    return RS_EDEVICE;
   }
 }
 
@@ -387,6 +411,8 @@ rs_status rs_draw_weighted(const float* q, int64_t m, int32_t tau, uint64_t seed
     return err ? RS_EDEVICE : RS_OK;
   } catch (const Fail& f) {
     return f.code;
+  } catch (const std::exception&) {
+    return RS_EDEVICE;
   }
 }
 
