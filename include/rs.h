@@ -242,6 +242,23 @@ int64_t rs_system_size(const rs_handle* h);
  * returns w^k, v^k, r_w^k, r_v^k in the same four places. */
 rs_status rs_get_state(const rs_handle* h, double* x, double* x_prev, double* r, double* r_prev);
 
+/* Resume from a saved state (checkpoint): iteration k and x^k, x^{k-1}, r^k, r^{k-1}
+ * (host buffers of m doubles, none NULL, all finite; copied before the call returns), as
+ * rs_get_state returned them. Alg. 2's next iterate depends only on these and on S_k,
+ * which is drawn from (seed, problem_id, k), so the iterations that follow equal those
+ * of the uninterrupted solve (mixed precision recomputes r in FP64 when an rs_step or
+ * rs_solve call ends, so there the solve whose call ended at k); only the stop test at
+ * iteration k itself uses ||r^k||
+ * summed here on the host (in index order) rather than the update's partial sums. Any
+ * prepared lookahead batch is dropped; ||r^0|| stays the one of rs_create (= ||b||);
+ * history entries before k keep what the handle held. Not to be called while another
+ * call on the handle runs (handles are not thread-safe).
+ * RS_EINVAL for a NULL or non-finite vector or k outside [0, max_iter];
+ * RS_EUNSUPPORTED for the accelerated method and the learned sampler (their state holds
+ * more than these four vectors). */
+rs_status rs_set_state(rs_handle* h, int64_t k, const double* x, const double* x_prev, const double* r,
+                       const double* r_prev);
+
 /* Ridge weights from the current iterate (host, d doubles). */
 rs_status rs_get_weights(rs_handle* h, double* w_out);
 

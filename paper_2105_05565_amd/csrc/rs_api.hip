@@ -1234,6 +1234,64 @@ rs_status rs_get_state(const rs_handle* h, double* x, double* x_prev, double* r,
   return RS_OK;
 }
 
+rs_status rs_set_state(rs_handle* h, int64_t k, const double* x, const double* x_prev, const double* r,
+                       const double* r_prev) {
+  if (!h) return RS_EINVAL;
+  if (!x || !x_prev || !r || !r_prev || k < 0 || k > h->opt.max_iter) {
+    h->last_error = "rs_set_state: four host vectors and 0 <= k <= max_iter are required";
+    return RS_EINVAL;
+  }
+  if (h->accel || h->sampler == RS_SAMPLER_LEARNED) {
+    h->last_error = "rs_set_state: not available for the accelerated method or the learned sampler";
+    return RS_EUNSUPPORTED;
+  }
+  const double* src[4] = {x, x_prev, r, r_prev};
+  for (int i = 0; i < 4; ++i)
+    for (int64_t j = 0; j < h->m; ++j)
+      if (!std::isfinite(src[i][j])) {
+        h->last_error = "rs_set_state: non-finite entry";
+        return RS_EINVAL;
+      }
+  double ss = 0.0;
+  for (int64_t j = 0; j < h->m; ++j) ss += r[j] * r[j];
+  try {
+    check_hip(hipStreamSynchronize(h->stream), "sync");
+    if (h->pipeline) check_hip(hipStreamSynchronize(h->prep_stream), "sync");
+    DevFlags f{};
+    check_hip(hipMemcpy(&f, h->flags, sizeof(DevFlags), hipMemcpyDeviceToHost), "flags");
+    // x^k and r^k sit in buffer k & 1; the update overwrites the other (x^{k-1}, r^{k-1})
+    const int cur = (int)(k & 1), prv = 1 - cur;
+    double* dst[4] = {h->xbuf[cur], h->xbuf[prv], h->rbuf[cur], h->rbuf[prv]};
+    for (int i = 0; i < 4; ++i)
+      check_hip(hipMemcpy(dst[i], src[i], sizeof(double) * h->m, hipMemcpyHostToDevice), "state");
+    // the stop test at iteration k sums the partials: one slot holds ||r^k||^2
+    std::vector<double> part(h->npart, 0.0);
+    part[0] = ss;
+    check_hip(hipMemcpy(h->partials, part.data(), sizeof(double) * h->npart, hipMemcpyHostToDevice), "partials");
+    const double rel = f.r0norm > 0.0 ? std::sqrt(ss) / f.r0norm : 0.0;
+    check_hip(hipMemcpy(h->hist + k, &rel, sizeof(double), hipMemcpyHostToDevice), "history");
+    check_hip(hipMemcpy(h->true_hist + k, &rel, sizeof(double), hipMemcpyHostToDevice), "history");
+    f.done = (f.r0norm == 0.0) ? 1 : 0;  // as at creation: b = 0 leaves nothing to solve
+    f.err = 0;
+    f.k_done = 0;
+    check_hip(hipMemcpy(h->flags, &f, sizeof(DevFlags), hipMemcpyHostToDevice), "flags");
+    check_hip(hipMemset(h->err, 0, sizeof(int32_t)), "error word");
+    // sampling ages (trace features) restart: no coordinate sampled yet
+    if (h->last) check_hip(hipMemset(h->last, 0xFF, sizeof(int32_t) * h->m), "sketch history");
+    h->k = k;
+    h->done = f.done != 0;
+    h->batch_k0 = -1;
+    h->batch_n = 0;
+    return RS_OK;
+  } catch (const Fail& f) {
+    h->last_error = f.msg;
+    return f.code;
+  } catch (const std::exception& e) {
+    h->last_error = e.what();
+    return RS_EDEVICE;
+  }
+}
+
 rs_status rs_get_last_sketch(const rs_handle* h, int32_t* rows, int32_t* cols, int8_t* signs,
                              int64_t* nnz_out) {
   if (!h || !rows || !cols || !signs || !nnz_out) return RS_EINVAL;

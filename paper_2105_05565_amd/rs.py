@@ -123,6 +123,7 @@ SIGNATURES = {
     "rs_iteration": (ctypes.c_int64, [_P]),
     "rs_system_size": (ctypes.c_int64, [_P]),
     "rs_get_state": (ctypes.c_int32, [_P, _P, _P, _P, _P]),
+    "rs_set_state": (ctypes.c_int32, [_P, ctypes.c_int64, _P, _P, _P, _P]),
     "rs_get_weights": (ctypes.c_int32, [_P, _P]),
     "rs_get_last_sketch": (ctypes.c_int32, [_P, _P, _P, _P, ctypes.POINTER(ctypes.c_int64)]),
     "rs_get_history": (ctypes.c_int32, [_P, _P, ctypes.c_int64]),
@@ -287,6 +288,11 @@ def rs_system_size(h):
 
 def rs_get_state(h, x=None, x_prev=None, r=None, r_prev=None):
     _check(load().rs_get_state(h, _ptr(x), _ptr(x_prev), _ptr(r), _ptr(r_prev)), "rs_get_state", h)
+
+
+def rs_set_state(h, k, x, x_prev, r, r_prev):
+    vs = [np.ascontiguousarray(v, dtype=np.float64) for v in (x, x_prev, r, r_prev)]
+    _check(load().rs_set_state(h, int(k), *[_ptr(v) for v in vs]), "rs_set_state", h)
 
 
 def rs_get_weights(h, w_out):
@@ -639,6 +645,13 @@ class Solver:
         x, xp, r, rp = (np.zeros(self.m) for _ in range(4))
         rs_get_state(self.h, x, xp, r, rp)
         return x, xp, r, rp
+
+    def set_state(self, k, x, x_prev, r, r_prev):
+        """Resume at iteration k from a saved (x^k, x^{k-1}, r^k, r^{k-1})."""
+        for v in (x, x_prev, r, r_prev):
+            if np.shape(v) != (self.m,):
+                raise ValueError(f"state vectors must have {self.m} entries")
+        rs_set_state(self.h, k, x, x_prev, r, r_prev)
 
     def weights(self):
         w = np.zeros(self.d)

@@ -236,3 +236,11 @@ def test_accelerated_settings_rejected_without_device(kw, status):
 def test_accelerated_defaults():
     o = rs.rs_options_default()
     assert o.accelerated == 0 and o.accel_mu == 1.0 and o.accel_nu == 1.0
+
+
+def test_state_entry_points_reject_null_handle_without_device():
+    lib = rs.load()
+    z = np.zeros(4)
+    p = z.ctypes.data
+    assert lib.rs_set_state(None, 0, p, p, p, p) == rs.RS_EINVAL
+    assert lib.rs_get_state(None, p, p, p, p) == rs.RS_EINVAL

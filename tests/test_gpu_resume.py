@@ -1,0 +1,112 @@
+"""GPU: resuming a solve from a saved state (rs_set_state).
+
+The next iterate of Alg. 2 depends only on (x^k, x^{k-1}, r^k, r^{k-1}) and on S_k, which
+is drawn from (seed, problem_id, k); so a solve resumed at k from the state that
+rs_get_state returned must continue bit for bit like the uninterrupted one, in a fresh
+handle as in the same one, and a solve resumed from the oracle's state at k must follow
+the oracle's trajectory (1e-10, as the trajectory tests).
+"""
+import numpy as np
+import pytest
+
+from oracle.problem import ridge_system
+from oracle.solver import Options, init_state, step
+from paper_2105_05565_amd import inputs, rs
+
+pytestmark = pytest.mark.gpu
+
+TRAJ_TOL = 1e-10
+
+
+def _problem(kind):
+    if kind == "count":
+        return inputs.make_csr(600, 250, 0.03, 0.05, seed=71), "count"
+    return inputs.make_dense(500, 180, 0.05, seed=72), "subsample"
+
+
+@pytest.mark.parametrize("kind,precision", [("subsample", "fp64"), ("count", "fp64"), ("subsample", "mixed")])
+def test_resume_continues_bit_for_bit(kind, precision):
+    p, sketch = _problem(kind)
+    if precision == "mixed":
+        p = inputs.make_dense(500, 180, 0.05, seed=73, dtype=np.float32, col_log_sigma=1.0)
+    kw = dict(tau=23, sketch=sketch, form="primal", tol=0.0, seed=9, precision=precision, refresh_every=10,
+              lookahead=6)
+    # the mixed form recomputes r in FP64 at the end of every rs_step, so the
+    # uninterrupted solve stops at iteration 15 too
+    full = rs.Solver(p.X, p.y, p.lam, **kw)
+    full.step(15)
+    full.step(22)
+    want = full.state()
+    part = rs.Solver(p.X, p.y, p.lam, **kw)
+    part.step(15)
+    saved = part.state()
+    part.step(9)  # move on, then go back to iteration 15 in the same handle
+    part.set_state(15, *saved)
+    assert part.k == 15
+    part.step(22)
+    fresh = rs.Solver(p.X, p.y, p.lam, **kw)
+    fresh.set_state(15, *saved)
+    fresh.step(22)
+    for S in (part, fresh):
+        assert S.k == 37
+        for got, exp in zip(S.state(), want):
+            assert np.array_equal(got, exp)
+        S.close()
+    full.close()
+
+
+def test_resume_from_oracle_state_follows_oracle():
+    p, sketch = _problem("count")
+    system = ridge_system(p.X, p.y, p.lam, "primal")
+    opts = Options(sketch=sketch, tau=23, momentum="heuristic", seed=4, tol=0.0)
+    st = init_state(system)
+    for _ in range(10):
+        step(system, st, opts)
+    S = rs.Solver(p.X, p.y, p.lam, tau=23, sketch=sketch, form="primal", tol=0.0, seed=4)
+    S.set_state(10, st.w, st.w_prev, st.r, st.r_prev)
+    assert np.isclose(S.history()[10], np.linalg.norm(st.r) / np.linalg.norm(system.b), rtol=1e-14)
+    for _ in range(15):
+        step(system, st, opts)
+    S.step(15)
+    x, xp, r, rp = S.state()
+    for got, exp in ((x, st.w), (xp, st.w_prev), (r, st.r), (rp, st.r_prev)):
+        assert np.linalg.norm(got - exp) <= TRAJ_TOL * np.linalg.norm(exp)
+    S.close()
+
+
+def test_resume_stops_at_tolerance_like_the_full_solve():
+    p, sketch = _problem("subsample")
+    kw = dict(tau=23, sketch=sketch, form="primal", tol=1e-8, seed=5, max_iter=100000)
+    full = rs.Solver(p.X, p.y, p.lam, **kw)
+    _, st_full, rep_full = full.solve()
+    mid = rs.Solver(p.X, p.y, p.lam, **{**kw, "tol": 0.0})
+    mid.step(rep_full.iters // 2)
+    saved = mid.state()
+    mid.close()
+    res = rs.Solver(p.X, p.y, p.lam, **kw)
+    res.set_state(rep_full.iters // 2, *saved)
+    _, st_res, rep_res = res.solve()
+    assert st_res == st_full == rs.RS_OK
+    assert rep_res.iters == rep_full.iters
+    for got, exp in zip(res.state(), full.state()):
+        assert np.array_equal(got, exp)
+    full.close()
+    res.close()
+
+
+def test_set_state_rejections():
+    p, sketch = _problem("subsample")
+    S = rs.Solver(p.X, p.y, p.lam, tau=23, sketch=sketch, tol=0.0, seed=1, max_iter=50)
+    z = np.zeros(S.m)
+    bad = z.copy()
+    bad[3] = np.nan
+    for args in ((51, z, z, z, z), (-1, z, z, z, z), (0, z, z, bad, z)):
+        with pytest.raises(rs.RsError) as e:
+            S.set_state(*args)
+        assert e.value.status == rs.RS_EINVAL
+    S.close()
+    A = rs.Solver(p.X, p.y, p.lam, tau=23, sketch=sketch, tol=0.0, seed=1, accel=(0.1, 10.0))
+    with pytest.raises(rs.RsError) as e:
+        A.set_state(0, z, z, z, z)
+    assert e.value.status == rs.RS_EUNSUPPORTED
+    A.close()
