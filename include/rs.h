@@ -163,6 +163,8 @@ typedef struct rs_report {
   int64_t iters;            /* iterations performed */
   double rel_res;           /* ||r^iters|| / ||r^0|| of the tracked residual */
   double seconds;           /* wall time of the solve on the stream */
+  double rel_res_true;      /* ||A w - b|| / ||b|| recomputed in FP64 from the data (not the
+                               recursion) for the returned iterate, after the timed solve */
 } rs_report;
 
 /* Per-kernel timing collected with HIP events on the solver's stream (indices

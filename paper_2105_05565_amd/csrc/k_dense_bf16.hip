@@ -447,6 +447,26 @@ hipError_t launch_refresh(const void* Zr, int32_t z_f32, int64_t ldz, int64_t m,
   return hipGetLastError();
 }
 
+hipError_t launch_true_residual(const void* Zr, int32_t z_f32, int64_t ldz, int64_t m, int64_t K, const double* x,
+                                const double* b, double lam, int32_t lam_u, double* u, double* upart, double* r2,
+                                double* partials, const int32_t* zero, hipStream_t s) {
+  if (lam_u && K != m) return hipErrorInvalidValue;
+  const dim3 gt((unsigned)((K + 255) / 256), kRefreshSplit);
+  if (z_f32)
+    hipLaunchKernelGGL(k_gemv_t_pair<float>, gt, dim3(256), 0, s, (const float*)Zr, ldz, m, K, x, x, upart, zero);
+  else
+    hipLaunchKernelGGL(k_gemv_t_pair<double>, gt, dim3(256), 0, s, (const double*)Zr, ldz, m, K, x, x, upart, zero);
+  hipLaunchKernelGGL(k_sum_upart, dim3((unsigned)((2 * K + 255) / 256)), dim3(256), 0, s, upart, K, u, zero);
+  const unsigned nb = (unsigned)((m + 3) / 4);
+  if (z_f32)
+    hipLaunchKernelGGL(k_gemv_n_pair_residual<float>, dim3(nb), dim3(256), 0, s, (const float*)Zr, ldz, m, K, u, x,
+                       x, b, lam, lam_u, r2, r2 + m, partials, zero);
+  else
+    hipLaunchKernelGGL(k_gemv_n_pair_residual<double>, dim3(nb), dim3(256), 0, s, (const double*)Zr, ldz, m, K, u,
+                       x, x, b, lam, lam_u, r2, r2 + m, partials, zero);
+  return hipGetLastError();
+}
+
 int64_t refresh_partials(int64_t m) { return (m + 3) / 4; }
 
 hipError_t launch_gemv_cols_f32(const float* Z, int64_t ldz, int64_t m, int64_t K, const double* v,

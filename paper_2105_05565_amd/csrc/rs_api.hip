@@ -58,6 +58,12 @@ struct rs_handle {
   double* ref_u = nullptr;
   double* ref_upart = nullptr;
   double* ref_partials = nullptr;
+  // the FP64 residual of the returned iterate, recomputed from the data at the end of a solve
+  double* tr_u = nullptr;
+  double* tr_upart = nullptr;
+  double* tr_r = nullptr;
+  double* tr_part = nullptr;
+  int32_t* tr_zero = nullptr;  // a 'done' word that stays 0, so those kernels always run
   double* true_hist = nullptr;
   int64_t* zr_ptr = nullptr;
   int32_t* zr_col = nullptr;
@@ -258,6 +264,40 @@ void refresh(rs_handle* h, int64_t k) {
                            &h->flags->done, h->stream),
             "refresh");
   prof_end(h, pe);
+}
+
+// ||A x^k - b|| / ||b|| with A x^k formed from the data in FP64 (dense: Z (Z^T x) + lambda x,
+// from the FP32 copy for mixed precision; kernel ridge: K (K x) + lambda K x; CSR: two
+// sparse products, the last two terms added on the host), not from the recursion.
+double true_rel_res(rs_handle* h) {
+  const int64_t m = h->m;
+  const double* x = h->xbuf[h->k & 1];
+  hipStream_t s = h->stream;
+  std::vector<double> r(m);
+  if (h->sparse) {
+    check_hip(launch_spmv_csr(h->zt_ptr, h->zt_col, h->zt_val, h->vals_f32, h->K, x, h->tr_u, s), "Z^T x");
+    check_hip(launch_spmv_csr(h->zr_ptr, h->zr_col, h->zr_val, h->vals_f32, m, h->tr_u, h->tr_r, s), "Z Z^T x");
+    std::vector<double> hx(m), hb(m);
+    check_hip(hipMemcpyAsync(r.data(), h->tr_r, sizeof(double) * m, hipMemcpyDeviceToHost, s), "copy");
+    check_hip(hipMemcpyAsync(hx.data(), x, sizeof(double) * m, hipMemcpyDeviceToHost, s), "copy");
+    check_hip(hipMemcpyAsync(hb.data(), h->b, sizeof(double) * m, hipMemcpyDeviceToHost, s), "copy");
+    check_hip(hipStreamSynchronize(s), "sync");
+    for (int64_t j = 0; j < m; ++j) r[j] = r[j] + h->lam * hx[j] - hb[j];
+  } else {
+    const bool f32 = h->mixed && !h->kern;
+    const void* Zr = f32 ? (const void*)h->Z32 : (const void*)h->Z;
+    const int64_t ldr = f32 ? h->K : h->ldz;
+    check_hip(launch_true_residual(Zr, f32 ? 1 : 0, ldr, m, h->K, x, h->b, h->lam, h->kern ? 1 : 0, h->tr_u,
+                                   h->tr_upart, h->tr_r, h->tr_part, h->tr_zero, s),
+              "true residual");
+    check_hip(hipMemcpyAsync(r.data(), h->tr_r, sizeof(double) * m, hipMemcpyDeviceToHost, s), "copy");
+    check_hip(hipStreamSynchronize(s), "sync");
+  }
+  double ss = 0.0;
+  for (int64_t j = 0; j < m; ++j) ss += r[j] * r[j];
+  DevFlags f{};
+  check_hip(hipMemcpy(&f, h->flags, sizeof(DevFlags), hipMemcpyDeviceToHost), "flags");
+  return f.r0norm > 0.0 ? std::sqrt(ss) / f.r0norm : 0.0;
 }
 
 // Sketches k0 .. k0 + nb - 1 of a batch, their products AS, G = S^T A S and its inverse,
@@ -991,6 +1031,12 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
     h->delta = dalloc<double>(h, h->ldg);
     h->npart = update_partials(h->m, h->tau);
     h->partials = dalloc<double>(h, h->npart);
+    h->tr_u = dalloc<double>(h, 2 * h->K);
+    if (!h->sparse) h->tr_upart = dalloc<double>(h, refresh_upart_doubles(h->K));
+    h->tr_r = dalloc<double>(h, 2 * h->m);
+    h->tr_part = dalloc<double>(h, refresh_partials(h->m));
+    h->tr_zero = dalloc<int32_t>(h, 1);
+    check_hip(hipMemset(h->tr_zero, 0, sizeof(int32_t)), "memset");
     h->hist_len = h->opt.max_iter + 1;
     h->hist = dalloc<double>(h, h->hist_len);
     h->true_hist = dalloc<double>(h, h->hist_len);
@@ -1207,6 +1253,7 @@ rs_status rs_solve(rs_handle* h, double* w_out, rs_report* rep) {
       rep->iters = h->k;
       rep->rel_res = rel;
       rep->seconds = std::chrono::duration<double>(t1 - t0).count();
+      rep->rel_res_true = true_rel_res(h);
     }
     if (w_out) {
       rs_status st = rs_get_weights(h, w_out);

@@ -243,6 +243,11 @@ int64_t refresh_partials(int64_t m);
 int64_t refresh_upart_doubles(int64_t K);
 // FP64 residuals r = Z (Z^T x) + lam x - b from the FP32 (z_f32) or FP64 copy of Z; lam_u != 0:
 // kernel ridge, r = Z (Z^T x) + lam (Z^T x) - b.
+// r = Z (Z^T x) + lambda x - b in FP64 from FP32 or FP64 data (lam_u: lambda Z^T x, kernel
+// ridge with Z = K symmetric); r2 holds 2 m doubles (r twice), no state or flag is touched.
+hipError_t launch_true_residual(const void* Zr, int32_t z_f32, int64_t ldz, int64_t m, int64_t K, const double* x,
+                                const double* b, double lam, int32_t lam_u, double* u, double* upart, double* r2,
+                                double* partials, const int32_t* zero, hipStream_t s);
 hipError_t launch_refresh(const void* Zr, int32_t z_f32, int64_t ldz, int64_t m, int64_t K, const double* x,
                           const double* xp, const double* b, double lam, int32_t lam_u, double* r, double* rp,
                           double* u, double* upart, double* partials, DevFlags* flags, double* hist,

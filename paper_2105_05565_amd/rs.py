@@ -96,7 +96,8 @@ class rs_profile(ctypes.Structure):
 
 
 class rs_report(ctypes.Structure):
-    _fields_ = [("iters", ctypes.c_int64), ("rel_res", ctypes.c_double), ("seconds", ctypes.c_double)]
+    _fields_ = [("iters", ctypes.c_int64), ("rel_res", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("rel_res_true", ctypes.c_double)]
 
 
 class RsError(RuntimeError):

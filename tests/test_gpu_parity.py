@@ -294,3 +294,53 @@ def test_device_inputs_from_torch():
     assert np.array_equal(S1.state()[0], S2.state()[0])
     rowptr = torch.from_numpy(sp.csr_matrix(p.X).indptr.astype(np.int64)).cuda()
     assert rowptr.is_cuda
+
+
+@pytest.mark.parametrize("case", ["dense_primal", "dense_dual", "csr_count_arows", "csr_subcount_dual_scatter",
+                                  "kernel", "mixed", "gaussian"])
+def test_report_true_residual_matches_oracle(case):
+    """rs_report.rel_res_true, the FP64 residual of the returned iterate formed from the data,
+    against ||A x - b|| / ||b|| formed by the oracle for the same x: the two differ at most
+    by 4 gamma_n || |Z| (|Z^T| |x|) + lambda |x| + |b| || / ||b|| (two dot-product orders,
+    Higham Sec. 3.1; kernel ridge: |K| (|K| |x|) + lambda |K| |x| + |b|)."""
+    from oracle.problem import kernel_system
+    kw = dict(tol=1e-8, seed=3, max_iter=100000)
+    if case == "kernel":
+        p = inputs.make_points(300, 6, 1e-2, 0.5, seed=81)
+        system = kernel_system(p.P, p.y, p.lam, p.sigma)
+        S = rs.Solver(p.P, p.y, p.lam, tau=40, kernel_sigma=p.sigma, **kw)
+    else:
+        form = "dual" if "dual" in case else "primal"
+        if case.startswith("csr"):
+            p = _csr(500, 220, 0.03, 0.05, seed=82) if form == "primal" else _csr(220, 500, 0.03, 0.05, seed=83)
+            kind = "count" if "subcount" not in case else "subcount"
+            route = "arows" if "arows" in case else "scatter"
+            S = rs.Solver(p.X, p.y, p.lam, tau=25, sketch=kind, form=form, subcount_k=2, sparse_route=route, **kw)
+        else:
+            dt = np.float32 if case == "mixed" else np.float64
+            p = inputs.make_dense(400, 150, 0.05, seed=84, dtype=dt) if form == "primal" else \
+                inputs.make_dense(150, 400, 0.05, seed=85)
+            sketch = "gaussian" if case == "gaussian" else "subsample"
+            S = rs.Solver(p.X, p.y, p.lam, tau=30, sketch=sketch, form=form,
+                          precision="mixed" if case == "mixed" else "fp64", **kw)
+        system = ridge_system(p.X, p.y, p.lam, form)
+    _, st, rep = S.solve()
+    assert st == rs.RS_OK
+    x = S.state()[0]
+    S.close()
+    r = system.matvec(x) - system.b
+    nb = np.linalg.norm(system.b)
+    if case == "kernel":
+        K = np.abs(system.Kmat)
+        mag = K @ (K @ np.abs(x)) + p.lam * (K @ np.abs(x)) + np.abs(system.b)
+        n = K.shape[0]
+    else:
+        Z = system.Z.toarray() if hasattr(system.Z, "toarray") else np.asarray(system.Z)
+        Z = np.abs(Z)
+        mag = Z @ (Z.T @ np.abs(x)) + p.lam * np.abs(x) + np.abs(system.b)
+        n = max(Z.shape)
+    gamma = n * 2.0 ** -53 / (1 - n * 2.0 ** -53)
+    bound = 4 * gamma * np.linalg.norm(mag) / nb
+    assert abs(rep.rel_res_true - np.linalg.norm(r) / nb) <= bound, (rep.rel_res_true, np.linalg.norm(r) / nb, bound)
+    if case == "mixed":  # the stop test there uses the FP64-refreshed residual
+        assert rep.rel_res_true <= 1e-8 * 1.001
