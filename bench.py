@@ -417,13 +417,14 @@ def main_learned(args):
     S.profile(clear=True)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    times, iters = [], []
+    times, iters, rels_true = [], [], []
     for i in range(args.steps):
         ti = time.perf_counter()
         S.reset(201 + i)
         _, st, rep = S.solve()
         times.append(time.perf_counter() - ti)
         iters.append(rep.iters)
+        rels_true.append(rep.rel_res_true)
         print(f"[bench] step {i}: {rep.iters} iterations, {times[-1]*1e3:.1f} ms, rel {rep.rel_res:.2e}",
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -448,6 +449,8 @@ def main_learned(args):
                    "lookahead": 8, "train_solves": args.train_solves, "held_out_seeds": seeds},
         "iters_median": statistics.median(iters),
         "time_s_all": [round(t, 4) for t in times],
+        # per result: ||A w - b|| / ||b|| of each timed solve's iterate, recomputed in FP64 from the data
+        "final_rel_res_true_max": max(rels_true),
         "training": {"records": records, "seconds": round(train_s, 1),
                      "trace_solve_iters_median": statistics.median(tr_iters),
                      "epoch_loss": [round(v, 4) for v in losses]},
