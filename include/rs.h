@@ -253,7 +253,8 @@ rs_status rs_get_state(const rs_handle* h, double* x, double* x_prev, double* r,
  * iteration k itself uses ||r^k||
  * summed here on the host (in index order) rather than the update's partial sums. Any
  * prepared lookahead batch is dropped; ||r^0|| stays the one of rs_create (= ||b||);
- * history entries before k keep what the handle held. Not to be called while another
+ * history entries before k keep what the handle held (undefined in a handle that never
+ * iterated). Not to be called while another
  * call on the handle runs (handles are not thread-safe).
  * RS_EINVAL for a NULL or non-finite vector or k outside [0, max_iter];
  * RS_EUNSUPPORTED for the accelerated method and the learned sampler (their state holds
