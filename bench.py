@@ -205,6 +205,7 @@ def kernel_table(prof, wl, workload, n, d, nnz, m, K, nsel, total, a_nnz=0):
         tf = json.load(open(traffic_file))
         src = {"k_as_sparse_bucket": ["k_sparse.hip"], "k_update": ["k_update.hip"],
                "k_as_dense_f64_128": ["k_dense.hip"], "k_as_arows_lds": ["k_sparse_a.hip"],
+               "k_as_dense_bf16": ["k_dense_bf16.hip"],
                "k_g_from_as": ["k_sparse_a.hip"]
                }.get(roofline["kernel"], [])
         if src and tf.get("source_sha") == kernel_source_sha(src):
