@@ -82,6 +82,10 @@ def algorithmic_bytes(cls, wl, n, d, nnz, m, K, tau, nsel, a_nnz=0, slots=1):
             # CSR of Z and of Z^T (FP32 value + int32 column each) read once, row pointers,
             # bucket map, AS written once (FP64), G = S^T A S written once (FP64)
             return 2 * nnz * 8 + (m + 1) * 8 + (K + 1) * 8 + m * 4 + m * tau * 8 + tau * tau * 8
+        if wl.get("gram"):
+            # formed A: the tau gathered entries of each of its m rows read, AS written
+            elt = 4 if wl["precision"] == "mixed" else 8
+            return 2 * m * tau * elt + tau * 4
         # dense subsample: Z read once (m x K) + gathered rows (tau x K) + AS written; kernel
         # ridge also reads the gathered columns K[:, C] for the shift lambda K S
         elt = 2 if wl["precision"] == "mixed" else 8
@@ -169,7 +173,7 @@ def kernel_table(prof, wl, workload, n, d, nnz, m, K, nsel, total, a_nnz=0):
             return "k_as_arows_packed"
         return "k_as_arows"
     as_name = (arows_name() if a_nnz else "k_as_sparse_bucket") if wl["kind"] == "csr" \
-        else wl.get("as_kernel", "k_as_dense_f64_128")
+        else ("k_gram_gather" if wl.get("gram") else wl.get("as_kernel", "k_as_dense_f64_128"))
     roofline = {"kernel": {"as": as_name, "g": "k_g_from_as",
                            "update": "k_update", "chol": "k_chol_inverse", "delta": "k_delta",
                            "iters": "k_delta+k_update sequence",
@@ -177,7 +181,7 @@ def kernel_table(prof, wl, workload, n, d, nnz, m, K, nsel, total, a_nnz=0):
                 "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None, "traffic": None,
                 "alg_bytes_per_launch": kd["alg_bytes_per_launch"], "avg_launch_ms": kd["avg_ms"]}
-    if wl["kind"] in ("dense", "kernel") and dom == "as":
+    if wl["kind"] in ("dense", "kernel") and dom == "as" and not wl.get("gram"):
         # a dense sketch takes two products per sketch (T = Z^T S, then Z T)
         flops = 2.0 * m * wl["tau"] * K * kd["slots_per_launch"] * wl.get("as_products", 1)
         tfs = flops / (kd["avg_ms"] * 1e-3) / 1e12
@@ -670,6 +674,9 @@ def main():
                     help="batched workload only: shrink n and d (shape-alike smaller batch)")
     ap.add_argument("--max-iter", type=int, default=200000,
                     help="iteration cap per solve (a capped run reports per-iteration throughput)")
+    ap.add_argument("--dense-route", default="products", choices=["products", "gram"],
+                    help="subsample sketch on dense data: per-sketch MFMA products, or A formed once "
+                         "at creation and its columns gathered per sketch")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device-to-device copy of 1 GiB five times (the known-size "
                          "reference for HBM traffic counters)")
@@ -705,6 +712,10 @@ def main():
     from paper_2105_05565_amd import rs
 
     wl = WORKLOADS[args.workload]
+    if args.dense_route == "gram":
+        if wl["kind"] == "csr" or wl["sketch"] != "subsample":
+            raise SystemExit("--dense-route gram serves the subsample sketch on dense data or kernel ridge")
+        wl = {**wl, "gram": True, "name": wl["name"] + "_formedA"}
     torch.cuda.set_device(0)
     print(f"[bench] generating {wl['name']}", file=sys.stderr, flush=True)
     p = make_problem(wl)
@@ -734,7 +745,7 @@ def main():
                   subcount_k=wl["sub_k"], tol=tol, max_iter=max_iter, seed=1,
                   precision=wl["precision"], lookahead=args.lookahead, profile=1, stream=stream,
                   sparse_route=args.sparse_route, pipeline=not args.no_pipeline,
-                  kernel_sigma=p.sigma if kern else None)
+                  kernel_sigma=p.sigma if kern else None, dense_route=args.dense_route)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     route, a_nnz = rs.rs_get_route(S.h)
@@ -774,7 +785,7 @@ def main():
                        subcount_k=wl["sub_k"], tol=tol, max_iter=max_iter, seed=1,
                        precision=wl["precision"], lookahead=args.lookahead, profile=2, stream=stream,
                        sparse_route=args.sparse_route, pipeline=not args.no_pipeline,
-                       kernel_sigma=p.sigma if kern else None)
+                       kernel_sigma=p.sigma if kern else None, dense_route=args.dense_route)
         S2.solve()
         prof2 = S2.profile()
         S2.close()
@@ -787,7 +798,7 @@ def main():
                        subcount_k=wl["sub_k"], tol=1e-6, max_iter=args.max_iter, seed=1,
                        precision=wl["precision"], lookahead=args.lookahead, stream=stream,
                        sparse_route=args.sparse_route, pipeline=not args.no_pipeline,
-                       kernel_sigma=p.sigma if kern else None)
+                       kernel_sigma=p.sigma if kern else None, dense_route=args.dense_route)
         S3.solve()
         t3, i3 = [], []
         for i in range(min(args.steps, 3)):

@@ -135,6 +135,12 @@ typedef struct rs_options {
                                sqrt(1 / (mu nu)), alpha = 1 / (1 + sqrt(nu / mu)). The state
                                (rs_get_state) is w, v, r_w, r_v; the weights are w; the stop
                                test and the history use ||r_v^k|| / ||r_v^0||. */
+  int32_t dense_route;      /* subsample sketch on dense data or kernel ridge: 0 (default) forms
+                               each sketch's AS by the MFMA contraction Z Z[C,:]^T + lambda I_C;
+                               1 forms A = Z Z^T + lambda I (kernel ridge: K K + lambda K) once at
+                               creation with the same kernel (m x m, FP32 in mixed precision,
+                               else FP64) and gathers each sketch's tau columns from it. Pays when
+                               a solve takes more than about m / tau iterations and m^2 fits. */
 } rs_options;
 
 /* How AS is formed for the count and SubCount sketches on CSR data (same result up to

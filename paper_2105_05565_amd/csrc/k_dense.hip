@@ -264,6 +264,40 @@ __global__ void k_vec_to_f64(const void* __restrict__ src, int32_t is_f32, int64
 
 }  // namespace
 
+namespace {
+// One wave per row of AS: the row of the formed A is read at the sketch's coordinates
+// (ascending, so the reads of a wave fall in a few lines) and written contiguously.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram_gather(const T* __restrict__ A, int64_t lda, int64_t m,
+                                                     const int32_t* __restrict__ members, int64_t nsel,
+                                                     int32_t tau, int64_t ldas, T* __restrict__ AS,
+                                                     const int32_t* __restrict__ done) {
+  if (*done) return;
+  const int64_t slot = blockIdx.y;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= m) return;
+  const int lane = threadIdx.x & 63;
+  const int32_t* mem = members + slot * nsel;
+  const T* a = A + row * lda;
+  T* out = AS + (slot * m + row) * ldas;
+  for (int c = lane; c < tau; c += 64) out[c] = a[mem[c]];
+}
+}  // namespace
+
+hipError_t launch_gram_gather(const void* A, int32_t f32, int64_t lda, int64_t m, const int32_t* members,
+                              int64_t nsel, int32_t tau, int64_t ldas, int32_t nslots, void* AS,
+                              const int32_t* done, hipStream_t s) {
+  if (tau > nsel || tau > ldas || lda < m || nslots < 1) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((m + 3) / 4), (unsigned)nslots);
+  if (f32)
+    hipLaunchKernelGGL(k_gram_gather<float>, grid, dim3(256), 0, s, (const float*)A, lda, m, members, nsel, tau,
+                       ldas, (float*)AS, done);
+  else
+    hipLaunchKernelGGL(k_gram_gather<double>, grid, dim3(256), 0, s, (const double*)A, lda, m, members, nsel,
+                       tau, ldas, (double*)AS, done);
+  return hipGetLastError();
+}
+
 hipError_t launch_as_dense_f64(const double* Z, int64_t ldz, int64_t m, int64_t K,
                                const int32_t* members, int32_t tau, int64_t ldas, int32_t nslots,
                                double lam, int32_t lam_kernel, double* AS, const int32_t* done,

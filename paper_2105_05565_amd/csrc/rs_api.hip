@@ -64,6 +64,9 @@ struct rs_handle {
   double* tr_r = nullptr;
   double* tr_part = nullptr;
   int32_t* tr_zero = nullptr;  // a 'done' word that stays 0, so those kernels always run
+  // dense route 1: A = Z Z^T + lambda I formed once (m x ldgram, FP32 in mixed precision)
+  void* gram = nullptr;
+  int64_t ldgram = 0;
   double* true_hist = nullptr;
   int64_t* zr_ptr = nullptr;
   int32_t* zr_col = nullptr;
@@ -396,6 +399,10 @@ void prep_batch(rs_handle* h, int p, int64_t k0, int nb, hipStream_t s) {
                                bs.hmap, bs.members, bs.offs, h->nsel, h->tbuf, (double*)bs.AS, bs.G,
                                h->ldg, done, s),
               "AS (sparse)");
+  } else if (h->gram) {
+    check_hip(launch_gram_gather(h->gram, h->mixed ? 1 : 0, h->ldgram, h->m, bs.members, h->nsel, h->tau, h->ldas,
+                                 nb, bs.AS, done, s),
+              "AS (columns of the formed A)");
   } else if (h->mixed) {
     check_hip(launch_as_dense_bf16(h->Zbf, h->kpad, h->m, h->kpad, bs.members, h->tau, h->ldas, nb,
                                    h->lam, h->Z, h->ldz, h->kern ? 1 : 0, (float*)bs.AS, done, s),
@@ -823,6 +830,9 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
     }
     if (h->kind == kSubsample && h->sparse)
       throw Fail{RS_EUNSUPPORTED, "the subsample sketch needs dense data"};
+    if (o->dense_route != 0 && o->dense_route != 1) throw Fail{RS_EINVAL, "dense_route is 0 or 1"};
+    if (o->dense_route == 1 && (h->sparse || h->kind != kSubsample))
+      throw Fail{RS_EUNSUPPORTED, "the formed-A route serves the subsample sketch on dense data or kernel ridge"};
 
     // y: validate on the host
     std::vector<double> yh(n);
@@ -1037,6 +1047,25 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
     h->tr_part = dalloc<double>(h, refresh_partials(h->m));
     h->tr_zero = dalloc<int32_t>(h, 1);
     check_hip(hipMemset(h->tr_zero, 0, sizeof(int32_t)), "memset");
+    if (o->dense_route == 1) {
+      // the sketches' AS become gathers of tau columns of A, formed here by the product
+      // kernel itself with every coordinate as one sketch (C = 0 .. m-1)
+      h->ldgram = (h->m + 7) / 8 * 8;
+      h->gram = dalloc<char>(h, (size_t)h->m * h->ldgram * (h->mixed ? sizeof(float) : sizeof(double)));
+      std::vector<int32_t> all(h->m);
+      for (int64_t j = 0; j < h->m; ++j) all[j] = (int32_t)j;
+      int32_t* d_all = dalloc<int32_t>(h, h->m);
+      check_hip(hipMemcpy(d_all, all.data(), sizeof(int32_t) * h->m, hipMemcpyHostToDevice), "coordinates");
+      if (h->mixed)
+        check_hip(launch_as_dense_bf16(h->Zbf, h->kpad, h->m, h->kpad, d_all, (int32_t)h->m, h->ldgram, 1, h->lam,
+                                       h->Z, h->ldz, h->kern ? 1 : 0, (float*)h->gram, h->tr_zero, h->stream),
+                  "A = Z Z^T + lambda I (BF16)");
+      else
+        check_hip(launch_as_dense_f64(h->Z, h->ldz, h->m, h->K, d_all, (int32_t)h->m, h->ldgram, 1, h->lam,
+                                      h->kern ? 1 : 0, (double*)h->gram, h->tr_zero, h->stream),
+                  "A = Z Z^T + lambda I");
+      check_hip(hipStreamSynchronize(h->stream), "sync");
+    }
     h->hist_len = h->opt.max_iter + 1;
     h->hist = dalloc<double>(h, h->hist_len);
     h->true_hist = dalloc<double>(h, h->hist_len);

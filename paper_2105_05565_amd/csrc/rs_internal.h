@@ -243,6 +243,11 @@ int64_t refresh_partials(int64_t m);
 int64_t refresh_upart_doubles(int64_t K);
 // FP64 residuals r = Z (Z^T x) + lam x - b from the FP32 (z_f32) or FP64 copy of Z; lam_u != 0:
 // kernel ridge, r = Z (Z^T x) + lam (Z^T x) - b.
+// AS[slot][row][c] = A[row][members[slot][c]] from a formed A (m x m, row stride lda, FP32 when
+// f32 else FP64; AS in the same type), members with row stride nsel.
+hipError_t launch_gram_gather(const void* A, int32_t f32, int64_t lda, int64_t m, const int32_t* members,
+                              int64_t nsel, int32_t tau, int64_t ldas, int32_t nslots, void* AS,
+                              const int32_t* done, hipStream_t s);
 // r = Z (Z^T x) + lambda x - b in FP64 from FP32 or FP64 data (lam_u: lambda Z^T x, kernel
 // ridge with Z = K symmetric); r2 holds 2 m doubles (r twice), no state or flag is touched.
 hipError_t launch_true_residual(const void* Zr, int32_t z_f32, int64_t ldz, int64_t m, int64_t K, const double* x,
