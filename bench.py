@@ -482,7 +482,7 @@ def main_learned(args):
 
 
 def main_sketches(args):
-    """The sketch comparison (Sec. 9): subsample, count, SubCount, Gaussian and SRHT sketches with
+    """The sketch comparison (Sec. 8.2): subsample, count, SubCount, Gaussian and SRHT sketches with
     the heuristic momentum on the kernel problem shaped like Boston (506 points, tau = 126,
     lambda = 1e-6) and on the dense workload (2000 x 500, tau = 50); median time and iterations
     to relative residual 1e-6 over seeded solves."""

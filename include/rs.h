@@ -79,7 +79,7 @@ enum { RS_FORM_AUTO = 0, RS_FORM_PRIMAL = 1, RS_FORM_DUAL = 2 };
  * columns; the factorisation then reports RS_ESINGULAR. */
 enum { RS_SKETCH_SUBSAMPLE = 0, RS_SKETCH_COUNT = 1, RS_SKETCH_SUBCOUNT = 2, RS_SKETCH_GAUSSIAN = 3,
        RS_SKETCH_SRHT = 4 };
-/* Momentum schedule (Sec. 6, Sec. 9.1):
+/* Momentum schedule (Sec. 6, Sec. 8.1):
  *  NONE      gamma = 1, beta = 0 (Alg. 1)
  *  CONSTANT  gamma = opts.gamma, beta = opts.beta (0.5 in the paper's comparison)
  *  HEURISTIC gamma = 1, beta_k = min(beta_max, 1 - (2 - eta) / ((k+1)(1 - eta) + 1))
@@ -196,7 +196,7 @@ rs_status rs_options_default(rs_options* o);
 
 /* gamma_k and beta_k (host doubles) of iteration k >= 0 under the momentum settings of
  * *o (o->momentum, gamma, beta, eta, beta_max), exactly as the solvers use them (Sec. 6,
- * Sec. 9.1). Host-only, no device call. Errors: RS_EINVAL (unknown or unusable momentum
+ * Sec. 8.1). Host-only, no device call. Errors: RS_EINVAL (unknown or unusable momentum
  * settings, k < 0, a NULL pointer). */
 rs_status rs_momentum_schedule(const rs_options* o, int64_t k, double* gamma, double* beta);
 

@@ -18,7 +18,7 @@ What it computes, and where the paper defines it:
 * ``linalg``   -- Cholesky factorisation and triangular solves used as the
   least-norm solution of the sketched system (eq:sketched_system).
 * ``solver``   -- Alg. 1 / Alg. 2 (sketch-and-project with momentum,
-  eq:res_update_mom) and the momentum schedules of Sec. 6 and Sec. 9.1.
+  eq:res_update_mom) and the momentum schedules of Sec. 6 and Sec. 8.1.
 * ``mlp``      -- the small MLP (forward, backward, Adam) that scores
   coordinates for the learned proposal. The paper is silent on it; it is
   pinned by finite differences.

@@ -1,4 +1,4 @@
-"""Sketch-and-project with acceleration (Alg. 3, Sec. 10).
+"""Sketch-and-project with acceleration (Alg. 3, Sec. 9).
 
 Three iterate sequences w, z, v and their residuals r_w = A w - b, r_z = A z - b,
 r_v = A v - b. With mu in (0, 1] and nu in [1, 1/mu] (the parameters the paper sets

@@ -19,7 +19,7 @@ Momentum schedules:
 
 * "none":      gamma_k = 1, beta_k = 0 (Alg. 1);
 * "constant":  gamma_k = 1, beta_k = 0.5, the constant setting compared in
-  Sec. 9.1;
+  Sec. 8.1;
 * "heuristic": gamma_k = 1 and beta_k = 1 - (2 - eta) / ((k+1)(1 - eta) + 1)
   (eq:parametersheurististic, the beta of eq:cst_eta_lambda_to_gamma_beta_formula),
   capped at beta_max. eta = 0.995 and beta_max = 0.5 by default: the paper

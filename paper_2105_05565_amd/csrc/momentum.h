@@ -1,4 +1,4 @@
-// Momentum schedules (Sec. 6, Sec. 9.1) on the host, shared by the single and the batched
+// Momentum schedules (Sec. 6, Sec. 8.1) on the host, shared by the single and the batched
 // solver: gamma_k and beta_k of iteration k in a fixed FP64 operation order.
 #pragma once
 

@@ -998,14 +998,25 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
     const size_t per_slot = h->nsets * per_slot_set +
                             (h->sparse && !h->arows ? sparse_t_bytes(h->vals_f32, h->nnz) : 0) +
                             sizeof(double) * (size_t)h->ldg * h->ldg + sizeof(uint64_t) * (size_t)mkeys;
+    // The formed A of dense_route = 1 (m x m) is held beside the batch buffers: it comes out of
+    // the same budget, and a system whose A alone exceeds it is refused here, before any
+    // device allocation.
+    const size_t elt = h->mixed ? sizeof(float) : sizeof(double);
+    const size_t gram_bytes = o->dense_route == 1 ? (size_t)h->m * (size_t)((h->m + 7) / 8 * 8) * elt : 0;
+    const size_t budget_all = (size_t)48 << 30;
+    if (gram_bytes + per_slot > budget_all)
+      throw Fail{RS_ENOMEM, "dense_route = 1: the formed A (" + std::to_string(gram_bytes >> 20) +
+                                " MiB) and one lookahead slot exceed the 48 GiB the solver budgets"};
     // Default lookahead: 256 sketches, fewer when one sketch's contraction is large
-    // (the sketches formed past the stopping iteration are wasted work).
+    // (the sketches formed past the stopping iteration are wasted work). On the formed-A
+    // route a sketch's AS is a gather of tau columns, so the large batches stay: they also
+    // keep the factorisations on the one-workgroup-per-sketch kernel.
     int B = 256;
-    if (!h->sparse && 2.0 * (double)h->m * (double)h->K * (double)h->tau > 1e11) B = 32;
+    if (!h->sparse && o->dense_route != 1 && 2.0 * (double)h->m * (double)h->K * (double)h->tau > 1e11) B = 32;
     // the learned proposal is recomputed once per batch: short batches keep it fresh
     if (o->sampler == RS_SAMPLER_LEARNED) B = 8;
     if (o->lookahead > 0) B = o->lookahead;
-    const size_t budget = (size_t)48 << 30;
+    const size_t budget = budget_all - gram_bytes;
     while (B > 1 && (size_t)B * per_slot > budget) B >>= 1;
     h->B = B;
     const size_t as_bytes = (h->mixed ? sizeof(float) : sizeof(double)) * (size_t)B * h->m * h->ldas;
@@ -1051,7 +1062,7 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
       // the sketches' AS become gathers of tau columns of A, formed here by the product
       // kernel itself with every coordinate as one sketch (C = 0 .. m-1)
       h->ldgram = (h->m + 7) / 8 * 8;
-      h->gram = dalloc<char>(h, (size_t)h->m * h->ldgram * (h->mixed ? sizeof(float) : sizeof(double)));
+      h->gram = dalloc<char>(h, gram_bytes);
       std::vector<int32_t> all(h->m);
       for (int64_t j = 0; j < h->m; ++j) all[j] = (int32_t)j;
       int32_t* d_all = dalloc<int32_t>(h, h->m);

@@ -451,6 +451,8 @@ rs_status rs_batch_create(int32_t count, const rs_problem* problems, const rs_op
   try {
     B->opt = *o;
     if (o->precision != RS_PREC_FP64) throw Fail{RS_EUNSUPPORTED, "batched solves run in FP64"};
+    if (o->dense_route != 0)
+      throw Fail{RS_EUNSUPPORTED, "batched solves form B S per sketch (dense_route must be 0)"};
     if (const char* why = momentum_invalid(*o)) throw Fail{RS_EINVAL, why};
     if (!(o->tol >= 0.0)) throw Fail{RS_EINVAL, "tol must be >= 0"};
     if (o->max_iter < 0 || o->max_iter > 100000000) throw Fail{RS_EINVAL, "max_iter out of range"};

@@ -241,8 +241,6 @@ hipError_t launch_as_dense_bf16(const uint16_t* Zbf, int64_t ldz, int64_t m, int
 // records ||r|| / ||r^0|| at k and applies the stop test.
 int64_t refresh_partials(int64_t m);
 int64_t refresh_upart_doubles(int64_t K);
-// FP64 residuals r = Z (Z^T x) + lam x - b from the FP32 (z_f32) or FP64 copy of Z; lam_u != 0:
-// kernel ridge, r = Z (Z^T x) + lam (Z^T x) - b.
 // AS[slot][row][c] = A[row][members[slot][c]] from a formed A (m x m, row stride lda, FP32 when
 // f32 else FP64; AS in the same type), members with row stride nsel.
 hipError_t launch_gram_gather(const void* A, int32_t f32, int64_t lda, int64_t m, const int32_t* members,
@@ -253,6 +251,8 @@ hipError_t launch_gram_gather(const void* A, int32_t f32, int64_t lda, int64_t m
 hipError_t launch_true_residual(const void* Zr, int32_t z_f32, int64_t ldz, int64_t m, int64_t K, const double* x,
                                 const double* b, double lam, int32_t lam_u, double* u, double* upart, double* r2,
                                 double* partials, const int32_t* zero, hipStream_t s);
+// FP64 residuals r = Z (Z^T x) + lam x - b from the FP32 (z_f32) or FP64 copy of Z; lam_u != 0:
+// kernel ridge, r = Z (Z^T x) + lam (Z^T x) - b.
 hipError_t launch_refresh(const void* Zr, int32_t z_f32, int64_t ldz, int64_t m, int64_t K, const double* x,
                           const double* xp, const double* b, double lam, int32_t lam_u, double* r, double* rp,
                           double* u, double* upart, double* partials, DevFlags* flags, double* hist,

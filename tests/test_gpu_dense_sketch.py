@@ -6,7 +6,8 @@ dense data, which all take the dense-S products T = Z^T S, A S = Z T + lambda S 
   oracle's draw (SRHT and count to rounding of the solve, Gaussian also within the last
   bits of the transcendental functions);
 * A S against the oracle's sketched product;
-* FP64 trajectories to 1e-10 over 50 iterations: primal, dual, kernel ridge, ragged tiles;
+* FP64 trajectories to 1e-10 over 50 iterations, entry by entry (x, x_prev, r, r_prev): primal,
+  dual, kernel ridge, ragged tiles;
 * a converged solve reaches the direct solution.
 SRHT problems use m close below a power of 2 (m' / m < 1.1), where the truncated Hadamard
 columns stay independent.
@@ -18,6 +19,7 @@ from oracle import sketch as osk
 from oracle.problem import kernel_system, ridge_system
 from oracle.solver import Options, init_state, sketched_products, step
 from paper_2105_05565_amd import inputs, rs
+from parity_util import assert_state_close, assert_vec_close
 
 pytestmark = pytest.mark.gpu
 
@@ -39,7 +41,7 @@ def test_dense_sketch_products_and_draw(kind):
     AS, Ginv = S.products()
     sk = osk.draw(kind, 9, 0, 0, 120, tau, sum_size=3 if kind == "subcount" else 0)
     _, AS_o, G_o, _ = sketched_products(system, sk)
-    assert _rel(AS, AS_o) <= 1e-12
+    assert_vec_close(AS.ravel(), AS_o.ravel(), 1e-12, f"{kind} AS")
     S_gpu = np.linalg.solve(system.dense_A(), AS)
     assert np.abs(S_gpu - sk.matrix().toarray()).max() <= 1e-9 * np.abs(sk.signs).max()
     active = np.abs(sk.matrix().toarray()).sum(axis=0) > 0
@@ -70,9 +72,9 @@ def test_dense_sketch_trajectory(case, kind):
             step(system, st, opts)
         S.step(ck - done)
         done = ck
-        x, xp, r, rp = S.state()
-        assert max(_rel(x, st.w), _rel(r, st.r)) <= TRAJ_TOL, (ck, _rel(x, st.w), _rel(r, st.r))
-    assert np.allclose(S.history(), st.history[:done + 1], rtol=1e-9, atol=0)
+        assert_state_close(S.state(), [("x", st.w), ("x_prev", st.w_prev), ("r", st.r), ("r_prev", st.r_prev)],
+                           TRAJ_TOL, f"{kind}/{case} k={ck}")
+    np.testing.assert_allclose(S.history(), st.history[:done + 1], rtol=1e-9, atol=0)
     S.close()
 
 
@@ -86,8 +88,8 @@ def test_kernel_dense_sketch_trajectory(kind):
     for _ in range(50):
         step(system, st, opts)
     S.step(50)
-    x, _, r, _ = S.state()
-    assert max(_rel(x, st.w), _rel(r, st.r)) <= TRAJ_TOL
+    assert_state_close(S.state(), [("x", st.w), ("x_prev", st.w_prev), ("r", st.r), ("r_prev", st.r_prev)],
+                       TRAJ_TOL, f"kernel {kind} k=50")
     S.close()
 
 
@@ -100,4 +102,38 @@ def test_dense_sketch_solve_reaches_direct_solution(kind):
     assert st == rs.RS_OK
     wstar = np.linalg.solve(system.dense_A(), system.b)
     assert _rel(w, wstar) <= 1e-7
+    S.close()
+
+
+@pytest.mark.parametrize("call", ["step", "solve"])
+def test_singular_sketched_system_reports_status(call):
+    """A sketched system that is singular reaches the non-positive-pivot path. An SRHT draw over
+    m = 300 coordinates (padded to m' = 512, Def. 4.4) with tau = 250 keeps about 60 column pairs
+    (j, j + 256) whose truncated Hadamard columns agree on the first 256 rows and can only be told
+    apart on the 44 rows beyond: S has rank 223 < tau, so S^T A S is singular although A is
+    positive definite. The oracle's Cholesky meets a non-positive pivot on this draw; the library
+    returns RS_ESINGULAR through the C ABI (rs_step and rs_solve), its kernels end normally,
+    rs_last_error names the pivot, and the handle can still be reset and destroyed."""
+    from oracle.linalg import NotPositiveDefinite, cholesky_lower
+    m, tau, seed = 300, 250, 1
+    p = inputs.make_dense(400, m, 0.05, seed=7)
+    system = ridge_system(p.X, p.y, p.lam, "primal")
+    sk = osk.draw("srht", seed, 0, 0, m, tau)
+    assert np.linalg.matrix_rank(sk.matrix().toarray()) < tau
+    _, _, G_o, _ = sketched_products(system, sk)
+    with pytest.raises(NotPositiveDefinite):
+        cholesky_lower(G_o)
+    S = rs.Solver(p.X, p.y, p.lam, tau=tau, sketch="srht", form="primal", tol=1e-6, seed=seed,
+                  momentum="none", max_iter=50)
+    lib = rs.load()
+    if call == "step":
+        rel = rs.ctypes.c_double(0.0)
+        st = lib.rs_step(S.h, 1, rs.ctypes.byref(rel))
+    else:
+        rep = rs.rs_report()
+        st = lib.rs_solve(S.h, None, rs.ctypes.byref(rep))
+    assert st == rs.RS_ESINGULAR, (st, rs.status_string(st))
+    assert "pivot" in rs.last_error(S.h)
+    assert rs.status_string(st) == "sketched system not positive definite"
+    S.reset(seed + 1)
     S.close()

@@ -2,9 +2,10 @@
 
 A = Z Z^T + lambda I (kernel ridge: K K + lambda K) is formed once by the product kernel
 with every coordinate as one sketch, and each sketch's AS is gathered from its columns.
-Checked as the product route is: FP64 products and trajectories against the oracle
-(1e-12, 1e-10), BF16 products within the dot-product bound, kernel ridge against the
-product route, and the combinations it does not serve are rejected.
+Checked as the product route is: FP64 products and 50-iteration trajectories against the
+oracle entry by entry (1e-12, 1e-10), BF16 products within the dot-product bound (plain and
+kernel ridge), kernel ridge against the product route, and the combinations it does not
+serve are rejected.
 """
 import numpy as np
 import pytest
@@ -13,6 +14,7 @@ from oracle import sketch as osk
 from oracle.problem import kernel_system, ridge_system
 from oracle.solver import Options, init_state, sketched_products, step
 from paper_2105_05565_amd import inputs, rs
+from parity_util import assert_state_close, assert_vec_close
 
 pytestmark = pytest.mark.gpu
 
@@ -28,17 +30,16 @@ def test_gram_route_fp64_products_and_trajectory(form, n, d):
                   dense_route="gram")
     opts = Options(sketch="subsample", tau=tau, momentum="heuristic", seed=6, tol=0.0)
     st = init_state(system)
-    for c in (1, 7, 30):
+    for c in (1, 7, 30, 50):
         while st.k < c:
             step(system, st, opts)
         S.step(c - S.k)
-        x, xp, r, rp = S.state()
-        for got, exp in ((x, st.w), (xp, st.w_prev), (r, st.r), (rp, st.r_prev)):
-            assert np.linalg.norm(got - exp) <= 1e-10 * np.linalg.norm(exp), c
+        assert_state_close(S.state(), [("x", st.w), ("x_prev", st.w_prev), ("r", st.r), ("r_prev", st.r_prev)],
+                           1e-10, f"formed A {form} k={c}")
     AS, _ = S.products()
-    s = osk.draw_subsample(6, 0, 29, system.m, tau)
+    s = osk.draw_subsample(6, 0, 49, system.m, tau)
     _, AS_or, _, _ = sketched_products(system, s)
-    assert np.allclose(AS, AS_or, rtol=1e-12, atol=1e-12 * np.abs(AS_or).max())
+    assert_vec_close(AS.ravel(), AS_or.ravel(), 1e-12, "formed A: AS")
     S.close()
 
 
@@ -73,10 +74,47 @@ def test_gram_route_kernel_ridge_matches_product_route():
     B = rs.Solver(p.P, p.y, p.lam, **kw)
     A.step(25)
     B.step(25)
-    for got, exp in zip(A.state(), B.state()):
-        assert np.linalg.norm(got - exp) <= 1e-10 * np.linalg.norm(exp)
+    assert_state_close(A.state(), list(zip(("x", "x_prev", "r", "r_prev"), B.state())), 1e-10,
+                       "formed A vs products, kernel ridge")
     A.close()
     B.close()
+
+
+def test_gram_route_kernel_ridge_mixed_products_within_bound():
+    """Kernel ridge with BF16 products on the formed-A route: A = K K + lambda K formed once
+    from the BF16 kernel matrix (FP32 accumulation), each sketch's AS gathered from it. Its
+    entries against the oracle's FP64 K (K S) + lambda K S within the dot-product bound
+    (2 u_bf16 + n u_fp32) (|K| |K_C|^T) plus the FP32 rounding of the stored entries, and
+    against the product route's AS of the same sketch within twice that bound; a mixed solve
+    stops on the FP64-refreshed residual."""
+    p = inputs.make_points(700, 8, 1e-2, 0.5, seed=96)
+    system = kernel_system(p.P, p.y, p.lam, p.sigma)
+    tau = 64
+    kw = dict(tau=tau, kernel_sigma=p.sigma, tol=0.0, seed=5, precision="mixed", lookahead=3)
+    A = rs.Solver(p.P, p.y, p.lam, dense_route="gram", **kw)
+    B = rs.Solver(p.P, p.y, p.lam, **kw)
+    A.step(3)
+    B.step(3)
+    AS_a, Gi = A.products()
+    AS_b, _ = B.products()
+    A.close()
+    B.close()
+    sketch = osk.draw_subsample(5, 0, 2, 700, tau)
+    _, AS_o, _, _ = sketched_products(system, sketch)
+    K = system.Kmat
+    C = sketch.rows
+    bound = (2 * U_BF16 + 700 * U_FP32) * (np.abs(K) @ np.abs(K[C]).T) + 2 * U_FP32 * np.abs(AS_o) + 1e-30
+    err = np.abs(AS_a - AS_o)
+    assert np.all(err <= bound), float((err / bound).max())
+    assert np.all(np.abs(AS_a - AS_b) <= 2 * bound)
+    Gm = np.tril(AS_a[C]) + np.tril(AS_a[C], -1).T
+    kappa = np.linalg.cond(Gm)
+    assert np.abs(Gi @ Gm - np.eye(tau)).max() <= 4 * tau * 2.0 ** -53 * kappa
+    T = rs.Solver(p.P, p.y, p.lam, tau=tau, kernel_sigma=p.sigma, tol=1e-8, seed=5, precision="mixed",
+                  dense_route="gram", max_iter=100000)
+    _, st, rep = T.solve()
+    assert st == rs.RS_OK and rep.rel_res_true <= 1e-8 * 1.001
+    T.close()
 
 
 def test_gram_route_rejections():

@@ -1,7 +1,8 @@
 """GPU parity: the HIP library (through the C ABI) against the CPU FP64 oracle.
 
 * sketches: bit-exact (coordinates, buckets, signs) for every kind;
-* trajectories: ||x_gpu^k - x_oracle^k|| / ||x_oracle^k|| <= 1e-10 for k <= 50, FP64;
+* trajectories: x^k, x^{k-1}, r^k, r^{k-1} entry by entry within 1e-10 relative (plus 1e-10
+  times the vector's largest entry) for k <= 50, FP64;
 * converged weights against a direct solve; primal/dual agreement.
 Shapes are chosen to span several tiles with ragged tails (m, tau not multiples of
 the 64 x 64 product tiles or of the 32 x 32 factorisation tiles).
@@ -16,6 +17,7 @@ from oracle import sketch as osk
 from oracle.problem import ridge_system
 from oracle.solver import Options, init_state, step
 from paper_2105_05565_amd import inputs, rs
+from parity_util import assert_state_close, assert_vec_close
 
 pytestmark = pytest.mark.gpu
 
@@ -84,31 +86,44 @@ def test_count_sketch_bit_exact_large_m():
     S.close()
 
 
-def _trajectory_check(X, y, lam, *, form, kind, tau, momentum, sub_k=0, iters=50, checkpoints=None,
-                      lookahead=0, seed=5, route="auto"):
-    system = ridge_system(X, y, lam, form)
-    opts = Options(sketch=kind, tau=tau, sum_size=sub_k if sub_k else 0, momentum=momentum, seed=seed,
-                   tol=0.0)
+def _oracle_trajectory(system, opts, checkpoints):
+    """The oracle's (x, x_prev, r, r_prev) at each checkpoint, and its residual history."""
     st = init_state(system)
-    S = rs.Solver(X, y, lam, tau=tau, sketch=kind, form=form, momentum=momentum, tol=0.0, seed=seed,
-                  subcount_k=sub_k, lookahead=lookahead, sparse_route=route)
-    checkpoints = checkpoints or [1, 2, 3, 7, 20, iters]
-    done = 0
-    worst = 0.0
+    out = {}
     for c in checkpoints:
         while st.k < c:
             step(system, st, opts)
+        out[c] = (st.w.copy(), st.w_prev.copy(), st.r.copy(), st.r_prev.copy())
+    return out, list(st.history)
+
+
+def _trajectory_check(X, y, lam, *, form, kind, tau, momentum, sub_k=0, iters=50, checkpoints=None,
+                      lookahead=0, seed=5, route="auto", oracle=None):
+    """Advance the GPU solve and the oracle to each checkpoint and compare x^k, x^{k-1}, r^k and
+    r^{k-1} entry by entry (relative TRAJ_TOL, absolute TRAJ_TOL times the vector's largest
+    entry), then the residual history. oracle: a precomputed _oracle_trajectory result for the
+    same problem, options and checkpoints (shared by several routes)."""
+    checkpoints = checkpoints or [1, 2, 3, 7, 20, iters]
+    if oracle is None:
+        system = ridge_system(X, y, lam, form)
+        opts = Options(sketch=kind, tau=tau, sum_size=sub_k if sub_k else 0, momentum=momentum, seed=seed,
+                       tol=0.0)
+        oracle = _oracle_trajectory(system, opts, checkpoints)
+    ref, ref_hist = oracle
+    S = rs.Solver(X, y, lam, tau=tau, sketch=kind, form=form, momentum=momentum, tol=0.0, seed=seed,
+                  subcount_k=sub_k, lookahead=lookahead, sparse_route=route)
+    done = 0
+    worst = 0.0
+    for c in checkpoints:
         S.step(c - done)
         done = c
-        x, xp, r, rp = S.state()
         assert S.k == c
-        ex = np.linalg.norm(x - st.w) / np.linalg.norm(st.w)
-        er = np.linalg.norm(r - st.r) / np.linalg.norm(st.r)
-        exp_ = np.linalg.norm(xp - st.w_prev) / max(np.linalg.norm(st.w_prev), 1e-300)
-        worst = max(worst, ex, er)
-        assert ex <= TRAJ_TOL and er <= TRAJ_TOL and (c == 1 or exp_ <= TRAJ_TOL), (c, ex, er, exp_)
+        w, wp, r, rp = ref[c]
+        worst = max(worst, assert_state_close(
+            S.state(), [("x", w), ("x_prev", wp), ("r", r), ("r_prev", rp)], TRAJ_TOL,
+            f"{kind}/{form}/{route} k={c}"))
     hist = S.history()
-    assert np.allclose(hist, st.history[:len(hist)], rtol=1e-9, atol=0)
+    np.testing.assert_allclose(hist, ref_hist[:len(hist)], rtol=1e-9, atol=0)
     S.close()
     return worst
 
@@ -208,36 +223,52 @@ def test_dense_primal_full_size_trajectory():
                           checkpoints=[1, 10, 50])
 
 
+@pytest.mark.timeout(900)
 @pytest.mark.parametrize("workload,tau", [("dense_mixed", 1024), ("dense_learned", 512)])
 def test_dense_large_full_size_first_iterations_fp64(workload, tau):
     """The large dense workloads at full size on the FP64 path (X 50000 x 8192 with log-normal(0,1)
     column scales, tau = 1024; X 200000 x 4096 with log-normal(0,2) columns and 5% correlated
-    ones, tau = 512; primal, heuristic momentum): the first five iterations against the oracle."""
+    ones, tau = 512; primal, heuristic momentum): the first ten iterations against the oracle,
+    entry by entry."""
     p = getattr(inputs, workload)()
     print(f"[dense full size fp64] {workload} tau={tau}", flush=True)
     _trajectory_check(p.X, p.y, p.lam, form="primal", kind="subsample", tau=tau, momentum="heuristic",
-                      checkpoints=[1, 3, 5])
+                      checkpoints=[1, 3, 10])
 
 
-def test_sparse_full_size_first_iterations():
-    """The sparse workload at full size (CSR 100000 x 20000, 0.1%, tau = 500): the first
-    iterations against the oracle, count and SubCount (s = 4 tau)."""
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("kind,sub_k", [("count", 0), ("subcount", 4)])
+def test_sparse_full_size_trajectory(kind, sub_k):
+    """The sparse workload at full size (CSR 100000 x 20000, 0.1%, tau = 500, primal, heuristic
+    momentum): 50 iterations against the oracle, entry by entry, on both routes (the rows of
+    Z Z^T and the scatter of CSR columns), count and SubCount (s = 4 tau)."""
     p = inputs.sparse_csr()
-    for kind, sub_k in (("count", 0), ("subcount", 4)):
-        for route in ("scatter", "arows"):
-            _trajectory_check(p.X, p.y, p.lam, form="primal", kind=kind, tau=500, momentum="heuristic",
-                              sub_k=sub_k, checkpoints=[1, 3], route=route)
+    checkpoints = [1, 3, 10, 25, 50]
+    system = ridge_system(p.X, p.y, p.lam, "primal")
+    opts = Options(sketch=kind, tau=500, sum_size=sub_k, momentum="heuristic", seed=5, tol=0.0)
+    print(f"[sparse full size] {kind}: oracle, 50 iterations", flush=True)
+    ref = _oracle_trajectory(system, opts, checkpoints)
+    for route in ("arows", "scatter"):
+        print(f"[sparse full size] {kind} route={route}", flush=True)
+        _trajectory_check(p.X, p.y, p.lam, form="primal", kind=kind, tau=500, momentum="heuristic",
+                          sub_k=sub_k, checkpoints=checkpoints, route=route, oracle=ref)
 
 
-def test_sparse_dual_full_size_first_iterations():
+@pytest.mark.timeout(900)
+def test_sparse_dual_full_size_trajectory():
     """The sparse workload in the dual form at full size (m = n = 100000 coordinates, K = 20000,
-    count sketch tau = 500): the first iterations against the oracle on both routes (the rows
-    of X X^T hold about 2e8 entries, beyond the LDS bucket map: the global-map kernel)."""
+    count sketch tau = 500): ten iterations against the oracle, entry by entry, on both routes
+    (the rows of X X^T hold about 2e8 entries, beyond the LDS bucket map: the packed-map kernel)."""
     p = inputs.sparse_csr()
+    checkpoints = [1, 2, 5, 10]
+    system = ridge_system(p.X, p.y, p.lam, "dual")
+    opts = Options(sketch="count", tau=500, momentum="heuristic", seed=5, tol=0.0)
+    print("[dual full size] oracle, 10 iterations", flush=True)
+    ref = _oracle_trajectory(system, opts, checkpoints)
     for route in ("arows", "scatter"):
         print(f"[dual full size] route={route}", flush=True)
         _trajectory_check(p.X, p.y, p.lam, form="dual", kind="count", tau=500, momentum="heuristic",
-                          checkpoints=[1, 2], route=route)
+                          checkpoints=checkpoints, route=route, oracle=ref)
 
 
 def test_sparse_packed_bucket_map():

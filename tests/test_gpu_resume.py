@@ -12,6 +12,7 @@ import pytest
 from oracle.problem import ridge_system
 from oracle.solver import Options, init_state, step
 from paper_2105_05565_amd import inputs, rs
+from parity_util import assert_state_close, assert_vec_close
 
 pytestmark = pytest.mark.gpu
 
@@ -68,9 +69,8 @@ def test_resume_from_oracle_state_follows_oracle():
     for _ in range(15):
         step(system, st, opts)
     S.step(15)
-    x, xp, r, rp = S.state()
-    for got, exp in ((x, st.w), (xp, st.w_prev), (r, st.r), (rp, st.r_prev)):
-        assert np.linalg.norm(got - exp) <= TRAJ_TOL * np.linalg.norm(exp)
+    assert_state_close(S.state(), [("x", st.w), ("x_prev", st.w_prev), ("r", st.r), ("r_prev", st.r_prev)],
+                       TRAJ_TOL, f"resumed from the oracle's state ({sketch}) k=25")
     S.close()
 
 

@@ -69,6 +69,25 @@ def test_adam_first_step_closed_form():
     assert np.allclose(m1, 0.1 * g) and np.allclose(m2, 0.001 * g * g)
 
 
+def test_adam_constant_gradient_closed_form_every_step():
+    """Under a constant gradient g the moments have closed forms m1_t = (1 - b1^t) g and
+    m2_t = (1 - b2^t) g^2, so the bias-corrected moments equal g and g^2 at every t and every
+    update is -lr g / (|g| + eps). Checked at t = 1, 2, 50 and 1000: an exponent slip in the
+    bias correction (b1 instead of b1^t, t - 1 for t) or b1 and b2 swapped fails it at t >= 2."""
+    g = np.array([0.5, -2.0, 1e-3, 3.0e-6, -7.25])
+    lr, b1, b2, eps = 0.01, 0.9, 0.999, 1e-8
+    th = np.linspace(-1.0, 1.0, g.size)
+    m1 = np.zeros_like(g)
+    m2 = np.zeros_like(g)
+    for t in range(1, 1001):
+        new, m1, m2 = mlp.adam_step(th, g, m1, m2, t=t, lr=lr, b1=b1, b2=b2, eps=eps)
+        if t in (1, 2, 50, 1000):
+            np.testing.assert_allclose(m1, (1.0 - b1 ** t) * g, rtol=1e-12, atol=0)
+            np.testing.assert_allclose(m2, (1.0 - b2 ** t) * g * g, rtol=1e-12, atol=0)
+            np.testing.assert_allclose(new - th, -lr * g / (np.abs(g) + eps), rtol=1e-10, atol=0)
+        th = new
+
+
 def test_proposal_is_a_mixed_distribution():
     rng = np.random.default_rng(1)
     s = 5 * rng.standard_normal(1000)
