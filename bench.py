@@ -1,16 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark: time to relative residual 1e-6 of sketch-and-project on one MI355X.
 
-A step is one full solve (x^0 = 0 until ||r^k|| / ||r^0|| <= 1e-6) of the sparse
-workload: CSR X 100000 x 20000 with 0.1% uniform nonzeros (FP32 values N(0,1)),
-y = X w* + 0.01 noise, lambda = 1e-3, primal form, count sketch tau = 500,
-heuristic momentum (--momentum theory: the increasing rule of Sec. 6), FP64
-arithmetic. Every step uses a new sketch seed (seed = step index + 1; 10 steps by default, the
-paper's 10 runs per setting, reported as median and quartiles); the data and its device
-layouts stay resident in HBM.
+A step is one full solve (x^0 = 0 until ||r^k|| / ||r^0|| <= 1e-6). The default workload is the
+largest one that fits one GPU: dense X 200000 x 4096 (FP32, log-normal(0,2) column scales, 5% of
+the columns correlated at 0.9 with a random partner), lambda = 1e-2, primal form, subsample
+sketch tau = 512 whose coordinates come from the learned proposal (an MLP trained on traces of
+200 seeded uniform solves before the timed region), BF16 products with FP32 accumulation, FP64
+factorisations and an FP64 residual refresh every 20 iterations, heuristic momentum. The timed
+steps are the held-out seeds 201, 202, ...; the same seeds are also solved with uniform sampling
+(BF16) and by the plain FP64 solver (uniform sampling, FP64 products), the tuned-vs-plain
+comparison. --workload selects the other workloads (the sparse count-sketch workload, CSR
+100000 x 20000 at 0.1%, tau = 500: sparse_count). The data and its device layouts stay resident
+in HBM.
 
-Prints one JSON line with the metric, a roofline entry for the kernel that
-dominates the solve (algorithmic bytes per launch over its HIP-event duration),
+Prints one JSON line with the metric, a roofline entry for the kernel that dominates the solve
+(algorithmic flops or bytes per launch over its HIP-event duration, on the stream it runs on),
 a per-kernel breakdown and the CPU oracle's time on a bounded sample.
 """
 import argparse
@@ -74,10 +78,6 @@ def kernel_source_sha(files):
 def algorithmic_bytes(cls, wl, n, d, nnz, m, K, tau, nsel, a_nnz=0, slots=1):
     """Minimum HBM bytes one sketch (iteration) needs in each kernel class (FP64 layouts)."""
     if cls == "as":
-        if wl["kind"] == "csr" and a_nnz:
-            # rows of A0 = Z Z^T (int32 column + FP64 value) read once per launch and shared by
-            # its sketches; per sketch the bucket map read and AS written (FP64)
-            return (a_nnz * 12 + (m + 1) * 8) / slots + m * 4 + m * tau * 8
         if wl["kind"] == "csr":
             # CSR of Z and of Z^T (FP32 value + int32 column each) read once, row pointers,
             # bucket map, AS written once (FP64), G = S^T A S written once (FP64)
@@ -135,15 +135,16 @@ def cpu_baseline(p, wl, gpu_iters_median, sample_s, momentum="heuristic", thread
         while (st.k == 0 or time.perf_counter() - t0 < sample_s) and st.history[-1] > 1e-6:
             step(system, st, opts)
         el = time.perf_counter() - t0
-    per_iter = el / st.k
-    cores = 1
-    if threads != 1:
         from threadpoolctl import threadpool_info
-        cores = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
+        blas = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
+    per_iter = el / st.k
+    # the dense oracle's products are BLAS GEMMs (all the threads the limit allows); the CSR
+    # oracle's products are scipy sparse products, which run on one thread whatever the limit
+    cores = 1 if wl["kind"] == "csr" else blas
     return {"value": per_iter * gpu_iters_median, "unit": "s", "cores": cores, "kind": "oracle",
-            "sample": (f"first {st.k} iterations of the seed-1 solve on the full workload "
-                       f"({el:.1f} s, {per_iter:.3f} s/iteration, {cores} thread(s)), extrapolated to the "
-                       f"GPU's median iteration count {gpu_iters_median:.0f}; sketches are bit-identical"),
+            "sample": (f"extrapolated: first {st.k} iterations of the seed-1 solve on the full workload "
+                       f"({el:.1f} s, {per_iter:.3f} s/iteration, {cores} thread(s)) times the GPU's median "
+                       f"iteration count {gpu_iters_median:.0f}; sketches are bit-identical"),
             "s_per_iter": per_iter}
 
 
@@ -441,14 +442,19 @@ def main_learned(args):
     kernels, roofline = kernel_table(prof, wl, "dense_learned", n, d, n * d, m, K, tau, total)
 
     seeds = list(range(201, 201 + args.steps))
+    print("[bench] uniform sampling, BF16 products, same seeds", file=sys.stderr, flush=True)
     ut, ui, ur, _, _ = run("uniform", seeds)
+    print("[bench] A_jj / Tr A sampling, one seed", file=sys.stderr, flush=True)
     dt, di, dr, dst, _ = run("diag", seeds[:1], max_iter=min(args.max_iter, 3000))
-    pt, pi, pr_, _, _ = run("uniform", seeds[:1], precision="fp64")
+    nf = max(1, min(args.fp64_solves, len(seeds)))
+    print(f"[bench] plain FP64 solver (uniform sampling, FP64 products), {nf} seeds", file=sys.stderr,
+          flush=True)
+    pt, pi, pr_, pst, _ = run("uniform", seeds[:nf], precision="fp64")
     out = {
         "metric": "time-to-rel-residual 1e-6", "value": round(T_step, 6), "unit": "s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(T_step * 1e3, 3),
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16 products, f32 accumulate, f64 solve; f32 MLP", "data": "synthetic",
+        "dtype": "bf16", "data": "synthetic",
         "config": {"workload": wl["name"], "n": n, "d": d, "form": "primal", "sketch": "subsample (learned proposal)",
                    "tau": tau, "lambda": p.lam, "momentum": "heuristic", "tol": 1e-6, "precision": "mixed",
                    "lookahead": 8, "train_solves": args.train_solves, "held_out_seeds": seeds},
@@ -460,19 +466,23 @@ def main_learned(args):
                      "trace_solve_iters_median": statistics.median(tr_iters),
                      "epoch_loss": [round(v, 4) for v in losses]},
         "compare_same_seeds": {
-            "uniform_mixed": {"time_s_median": round(statistics.median(ut), 4), "iters_median": statistics.median(ui)},
-            "diag_mixed": {"time_s": round(dt[0], 4), "iters": di[0], "rel_res": dr[0],
+            "uniform_mixed": {"seeds": len(seeds), "time_s_median": round(statistics.median(ut), 4),
+                              "iters_median": statistics.median(ui)},
+            "diag_mixed": {"seeds": 1, "time_s": round(dt[0], 4), "iters": di[0], "rel_res": dr[0],
                            "converged": dst[0] == 0, "cap": min(args.max_iter, 3000)},
-            "uniform_fp64_plain": {"time_s": round(pt[0], 4), "iters": pi[0], "rel_res": pr_[0]},
+            "uniform_fp64_plain": {"seeds": nf, "time_s_median": round(statistics.median(pt), 4),
+                                   "iters_median": statistics.median(pi), "rel_res_max": max(pr_),
+                                   "all_converged": all(s == 0 for s in pst),
+                                   "learned_time_s_median_same_seeds": round(statistics.median(times[:nf]), 4)},
         },
-        "speedup_vs_uniform_mixed": round(statistics.median(ut) / T_step, 3),
-        "speedup_vs_plain_fp64": round(pt[0] / T_step, 2),
+        "speedup_vs_uniform_mixed": round(statistics.median(ut) / statistics.median(times), 3),
+        "speedup_vs_plain_fp64": round(statistics.median(pt) / statistics.median(times[:nf]), 2),
         "roofline": roofline,
         "kernels": kernels,
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        cb = cpu_baseline(p, wl, statistics.median(iters), args.cpu_sample_s)
+        cb = cpu_baseline(p, wl, statistics.median(iters), args.cpu_sample_s, threads=None)
         cb.pop("s_per_iter")
         cb["sample"] = cb["sample"].replace("; sketches are bit-identical", "") + (
             "; the oracle's per-iteration cost with uniform sketches (the proposal's MLP adds ~1e-4 of "
@@ -656,7 +666,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="sparse_count", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="dense_learned", choices=sorted(WORKLOADS))
     ap.add_argument("--lookahead", type=int, default=0)
     ap.add_argument("--momentum", default="heuristic", choices=["heuristic", "theory", "none"],
                     help="momentum schedule (the learned-sampler workload keeps the heuristic one)")
@@ -670,6 +680,8 @@ def main():
                     help="accel_grid: seeded solves per (mu, nu) cell")
     ap.add_argument("--train-solves", type=int, default=200,
                     help="dense_learned only: seeded uniform solves whose traces train the proposal")
+    ap.add_argument("--fp64-solves", type=int, default=5,
+                    help="dense_learned only: held-out seeds also solved by the plain FP64 solver")
     ap.add_argument("--scale", type=float, default=1.0,
                     help="batched workload only: shrink n and d (shape-alike smaller batch)")
     ap.add_argument("--max-iter", type=int, default=200000,
@@ -816,6 +828,17 @@ def main():
     T = total / args.steps
     tot_iters = sum(iters)
     kernels, roofline = kernel_table(prof, wl, args.workload, n, d, nnz, m, K, nsel, total, a_nnz)
+    solve_level = None
+    if wl["kind"] == "csr":
+        # the whole iteration's algorithmic bytes: CSR(Z) and CSR(Z^T) read (value + column),
+        # AS written and read back by the update, G written, six iterate/residual vectors
+        elt = 4 if wl["precision"] == "mixed" else 8
+        per_it = 2 * nnz * 8 + 2 * m * wl["tau"] * elt + wl["tau"] ** 2 * 8 + 6 * m * 8
+        gbs = per_it * tot_iters / total / 1e9
+        solve_level = {"bytes_per_iteration": per_it, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                       "us_per_iteration": round(total / tot_iters * 1e6, 2),
+                       "floor_us_per_iteration": round(per_it / (HBM_PEAK_GBS * 1e9) * 1e6, 2)}
 
     metric, value, unit, hib = "time-to-rel-residual 1e-6", round(T, 6), "s", False
     if fixed:
@@ -824,7 +847,7 @@ def main():
         "metric": metric, "value": value, "unit": unit, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(T * 1e3, 3),
         "higher_is_better": hib, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16 products, f32 accumulate, f64 solve" if wl["precision"] == "mixed" else "f64",
+        "dtype": "bf16" if wl["precision"] == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": wl["name"], "n": n, "d": d, "nnz": nnz, "form": "kernel" if kern else form,
                    "sketch": wl["sketch"], "tau": wl["tau"], "subcount_k": wl["sub_k"],
@@ -840,6 +863,7 @@ def main():
         "final_rel_res_true_max": max(rels_true),
         "setup_s": round(setup_s, 4),
         "roofline": roofline,
+        "solve_level_hbm": solve_level,
         "kernels": kernels,
         "other_momentum_untimed": alt,
         "kernels_per_launch_untimed": {c: {"avg_ms": round(v["ms"] / v["launches"], 5),
@@ -848,17 +872,12 @@ def main():
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        cb = cpu_baseline(p, wl, statistics.median(iters), args.cpu_sample_s, args.momentum)
+        cb = cpu_baseline(p, wl, statistics.median(iters), args.cpu_sample_s, args.momentum,
+                          threads=1 if wl["kind"] == "csr" else None)
         per_iter = cb.pop("s_per_iter")
         if fixed:
             cb["value"], cb["unit"] = round(1.0 / per_iter, 3), "it/s"
         out["cpu_baseline"] = cb
-        # the same oracle with every host thread for its BLAS calls (its sparse products stay serial)
-        cba = cpu_baseline(p, wl, statistics.median(iters), args.cpu_sample_s / 2, args.momentum, threads=None)
-        per_all = cba.pop("s_per_iter")
-        if fixed:
-            cba["value"], cba["unit"] = round(1.0 / per_all, 3), "it/s"
-        out["cpu_baseline_all_threads"] = cba
     print(json.dumps(out))
 
 

@@ -217,18 +217,30 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_as_dense_bf16(GemmArgs a) {
   issue(STAGES - 1);
   bf16x8 a0[2], b0[4], a1[2], b1[4];
   read_frags(stage(0), 0, a0, b0);
+  // Enter the loop with no LDS or scalar-memory result pending (DMA loads stay in flight), so
+  // that the only LDS results pending at the loop head are those of the fragment reads and
+  // each wait for a fragment can leave the six newer reads in flight.
+  __builtin_amdgcn_s_waitcnt(waitcnt_imm(63, 0));
+  __builtin_amdgcn_sched_barrier(0);
   // The body is the same on the last pass (its refill reloads the last stage and its reads
   // of stage nk go unused), so that no branch joins in-flight LDS reads of different ages.
   for (int64_t kt = 0; kt < nk; ++kt) {
     read_frags(stage(kt), 16, a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
     mma(a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
     // this wave's reads of stage kt done, stage kt + 1 landed, then every wave
     __builtin_amdgcn_s_waitcnt(waitcnt_imm(INFLIGHT, 0));
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_sched_barrier(0);
     issue(kt + STAGES);  // into the buffer of stage kt, which no wave reads any more
     read_frags(stage(kt + 1), 0, a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
     mma(a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
+    // the reads of a0, b0 were issued before these eight MFMAs: waiting for them here (and not
+    // at the loop head, after the next reads are issued) keeps the next reads in flight
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(63, 0));
   }
   // no DMA may still be writing this workgroup's LDS when it exits
   __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));

@@ -7,7 +7,8 @@
 // into registers while the current one is multiplied), batched over lookahead slots.
 // The iteration needs rho = S^T r (k_rho_dense_*: per row block partial sums, then a
 // fixed-order sum over the blocks) and x -= gamma S delta next to r -= gamma AS delta
-// (k_update_dense).
+// (k_update_dense). The SRHT skips the explicit-S products where it can: T = Z^T S and
+// G = S^T (AS) come from the fast Walsh-Hadamard transform of Z and of AS (k_srht_apply).
 #include <algorithm>
 
 #include "dev_common.h"
@@ -265,6 +266,81 @@ __global__ __launch_bounds__(kThreads) void k_update_dense(const double* __restr
   if (tid == 0) partials[blockIdx.x] = ss;
 }
 
+// The SRHT applied by its fast transform (Def. 4.4): for every column j of Y (m x ncols, row
+// stride ldy) and every sketch column c, OUT(j, c) = sum_{i < m} S_ic Y_ij with
+// S_ic = scale d_i (-1)^popcount(i & C_c), i.e. the entries C_c of H_{m'} (D Y_j) where the column
+// D Y_j is zero-padded to m' = 2^lg rows. A workgroup loads JB consecutive columns (times the
+// signs d_i) into LDS, runs the in-place Walsh-Hadamard butterflies on all of them (two stages
+// per pass: quads (b, b + h, b + 2h, b + 3h)), and writes the tau selected rows. Reading Y once
+// replaces the 2 m ncols tau flop of multiplying it by an explicit S. The signs are read back
+// from the slot's explicit S (column 0: d_i = sign(S_i0) (-1)^popcount(i & C_0)), so both forms
+// use the same draw. OUT(j, c) is stored at OUT[j ldo + c] (trans_out = 0) or OUT[c ldo + j].
+__global__ __launch_bounds__(kThreads) void k_srht_apply(
+    const double* __restrict__ Y, int64_t ldy, int64_t sY, int64_t m, int64_t ncols, int32_t lg, int32_t jbl,
+    const double* __restrict__ S, int64_t lds, int64_t sS, const int32_t* __restrict__ members, int32_t tau,
+    double scale, double* __restrict__ OUT, int64_t ldo, int64_t sO, int32_t trans_out,
+    const int32_t* __restrict__ done) {
+  extern __shared__ __align__(16) double buf[];  // [m'][JB], then m' sign bytes
+  if (*done) return;
+  const int64_t slot = blockIdx.y;
+  const int64_t mp = (int64_t)1 << lg;
+  const int JB = 1 << jbl;
+  const int64_t j0 = (int64_t)blockIdx.x * JB;
+  signed char* sgn = reinterpret_cast<signed char*>(buf + mp * JB);
+  const double* Ys = Y + slot * sY;
+  const double* Ss = S + slot * sS;
+  const int32_t* Cs = members + slot * (int64_t)tau;
+  const int64_t c0 = Cs[0];
+  for (int64_t i = threadIdx.x; i < m; i += kThreads) {
+    const bool hneg = __popcll((unsigned long long)(i & c0)) & 1;
+    sgn[i] = ((Ss[i * lds] < 0.0) != hneg) ? -1 : 1;
+  }
+  __syncthreads();
+  for (int64_t e = threadIdx.x; e < mp * JB; e += kThreads) {
+    const int64_t i = e >> jbl, j = j0 + (e & (JB - 1));
+    buf[e] = (i < m && j < ncols) ? (double)sgn[i] * Ys[i * ldy + j] : 0.0;
+  }
+  __syncthreads();
+  int64_t h = 1;
+  int rem = lg;
+  for (; rem >= 2; rem -= 2, h <<= 2) {
+    for (int64_t q = threadIdx.x; q < (mp >> 2) * JB; q += kThreads) {
+      const int64_t t = q >> jbl, j = q & (JB - 1);
+      const int64_t b = (t / h) * 4 * h + t % h;
+      double* p0 = buf + b * JB + j;
+      const int64_t hs = h * JB;
+      const double a0 = p0[0], a1 = p0[hs], a2 = p0[2 * hs], a3 = p0[3 * hs];
+      const double s01 = a0 + a1, d01 = a0 - a1, s23 = a2 + a3, d23 = a2 - a3;
+      p0[0] = s01 + s23;
+      p0[2 * hs] = s01 - s23;
+      p0[hs] = d01 + d23;
+      p0[3 * hs] = d01 - d23;
+    }
+    __syncthreads();
+  }
+  if (rem == 1) {
+    for (int64_t q = threadIdx.x; q < (mp >> 1) * JB; q += kThreads) {
+      const int64_t t = q >> jbl, j = q & (JB - 1);
+      const int64_t b = (t / h) * 2 * h + t % h;
+      double* p0 = buf + b * JB + j;
+      const double a0 = p0[0], a1 = p0[h * JB];
+      p0[0] = a0 + a1;
+      p0[h * JB] = a0 - a1;
+    }
+    __syncthreads();
+  }
+  double* Os = OUT + slot * sO;
+  for (int64_t e = threadIdx.x; e < (int64_t)JB * tau; e += kThreads) {
+    const int64_t jj = e / tau, c = e % tau, j = j0 + jj;
+    if (j >= ncols) continue;
+    const double v = scale * buf[(int64_t)Cs[c] * JB + jj];
+    if (trans_out)
+      Os[c * ldo + j] = v;
+    else
+      Os[j * ldo + c] = v;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_sketch_gauss(double* S, int64_t m, int32_t tau, int64_t ldas, uint64_t seed, uint64_t pid,
@@ -330,6 +406,38 @@ hipError_t launch_update_dense(const double* AS, const double* S, int64_t ldas, 
   if (ldas % 2 != 0 || npart <= 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_update_dense, dim3((unsigned)npart), dim3(kThreads), sizeof(double) * ldas, s, AS, S, ldas, tau,
                      delta, m, x, x_prev_out, r, r_prev_out, gamma, beta, partials, npart, flags);
+  return hipGetLastError();
+}
+
+int64_t srht_fast_max_mpad() { return 16384; }
+
+hipError_t launch_srht_apply(const double* Y, int64_t ldy, int64_t sY, int64_t m, int64_t ncols, int64_t mpad,
+                             const double* S, int64_t lds, int64_t sS, const int32_t* members, int32_t tau,
+                             double* OUT, int64_t ldo, int64_t sO, int32_t trans_out, int32_t nslots,
+                             const int32_t* done, hipStream_t s) {
+  if (nslots <= 0 || ncols <= 0) return hipSuccess;
+  int lg = 0;
+  while (((int64_t)1 << lg) < mpad) ++lg;
+  if (((int64_t)1 << lg) != mpad || mpad < m || mpad > srht_fast_max_mpad() || tau < 1 || tau > mpad ||
+      nslots > 65535)
+    return hipErrorInvalidValue;
+  // JB columns per workgroup: at most 16, and at most 16384 / m' so that the LDS image stays <= 128 KB
+  int jbl = 0;
+  while (jbl < 4 && ((int64_t)2 << jbl) * mpad <= 16384) ++jbl;
+  const int64_t JB = (int64_t)1 << jbl;
+  const size_t bytes = sizeof(double) * (size_t)mpad * JB + (size_t)mpad;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_srht_apply, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(sizeof(double) * 16384 + 16384));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const int64_t gx = (ncols + JB - 1) / JB;
+  if (gx > 0x7fffffff) return hipErrorInvalidValue;
+  const double scale = 1.0 / sqrt((double)tau * (double)mpad);
+  hipLaunchKernelGGL(k_srht_apply, dim3((unsigned)gx, (unsigned)nslots), dim3(kThreads), bytes, s, Y, ldy, sY, m,
+                     ncols, (int32_t)lg, (int32_t)jbl, S, lds, sS, members, tau, scale, OUT, ldo, sO, trans_out, done);
   return hipGetLastError();
 }
 

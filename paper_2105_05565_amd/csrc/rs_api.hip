@@ -361,13 +361,21 @@ void prep_batch(rs_handle* h, int p, int64_t k0, int nb, hipStream_t s) {
   prof_end(h, pe, s);
   pe = prof_begin(h, RS_PROF_AS, nb, 1, s, k0);
   if (h->dense_s) {
-    // T = Z^T S, A S = Z T + lambda S (kernel ridge: + lambda T = lambda K S), G = S^T A S
-    GemmF64Args g{};
-    g.A = h->Z; g.lda = h->ldz; g.sA = 0;
-    g.B = bs.S; g.ldb = h->ldas; g.sB = h->m * h->ldas;
-    g.C = bs.T; g.ldc = h->ldas; g.sC = h->K * h->ldas;
-    g.M = h->K; g.N = h->tau; g.Kd = h->m; g.done = done;
-    check_hip(launch_gemm_f64(g, true, nb, s), "T = Z^T S");
+    // T = Z^T S, A S = Z T + lambda S (kernel ridge: + lambda T = lambda K S), G = S^T A S. The SRHT
+    // forms T and G by its fast transform (Z and AS each read once) when m' fits the LDS butterflies.
+    const bool fast = h->kind == kSrht && h->mpad <= srht_fast_max_mpad();
+    if (fast) {
+      check_hip(launch_srht_apply(h->Z, h->ldz, 0, h->m, h->K, h->mpad, bs.S, h->ldas, h->m * h->ldas, bs.members,
+                                  h->tau, bs.T, h->ldas, h->K * h->ldas, 0, nb, done, s),
+                "T = Z^T S (fast Walsh-Hadamard transform)");
+    } else {
+      GemmF64Args g{};
+      g.A = h->Z; g.lda = h->ldz; g.sA = 0;
+      g.B = bs.S; g.ldb = h->ldas; g.sB = h->m * h->ldas;
+      g.C = bs.T; g.ldc = h->ldas; g.sC = h->K * h->ldas;
+      g.M = h->K; g.N = h->tau; g.Kd = h->m; g.done = done;
+      check_hip(launch_gemm_f64(g, true, nb, s), "T = Z^T S");
+    }
     GemmF64Args g2{};
     g2.A = h->Z; g2.lda = h->ldz; g2.sA = 0;
     g2.B = bs.T; g2.ldb = h->ldas; g2.sB = h->K * h->ldas;
@@ -378,12 +386,19 @@ void prep_batch(rs_handle* h, int p, int64_t k0, int nb, hipStream_t s) {
     check_hip(launch_gemm_f64(g2, false, nb, s), "AS = Z T + lambda S");
     prof_end(h, pe, s);
     pe = prof_begin(h, RS_PROF_G, nb, 1, s, k0);
-    GemmF64Args g3{};
-    g3.A = bs.S; g3.lda = h->ldas; g3.sA = h->m * h->ldas;
-    g3.B = (const double*)bs.AS; g3.ldb = h->ldas; g3.sB = h->m * h->ldas;
-    g3.C = bs.G; g3.ldc = h->ldg; g3.sC = h->ldg * h->ldg;
-    g3.M = h->tau; g3.N = h->tau; g3.Kd = h->m; g3.done = done;
-    check_hip(launch_gemm_f64(g3, true, nb, s), "G = S^T A S");
+    if (fast) {
+      check_hip(launch_srht_apply((const double*)bs.AS, h->ldas, h->m * h->ldas, h->m, h->tau, h->mpad, bs.S,
+                                  h->ldas, h->m * h->ldas, bs.members, h->tau, bs.G, h->ldg, h->ldg * h->ldg, 1, nb,
+                                  done, s),
+                "G = S^T A S (fast Walsh-Hadamard transform)");
+    } else {
+      GemmF64Args g3{};
+      g3.A = bs.S; g3.lda = h->ldas; g3.sA = h->m * h->ldas;
+      g3.B = (const double*)bs.AS; g3.ldb = h->ldas; g3.sB = h->m * h->ldas;
+      g3.C = bs.G; g3.ldc = h->ldg; g3.sC = h->ldg * h->ldg;
+      g3.M = h->tau; g3.N = h->tau; g3.Kd = h->m; g3.done = done;
+      check_hip(launch_gemm_f64(g3, true, nb, s), "G = S^T A S");
+    }
   } else if (h->arows) {
     check_hip(launch_as_arows(h->a_ptr, h->a_col, h->a_val, h->m, h->tau, h->ldas, nb, h->lam, bs.hmap,
                               (double*)bs.AS, done, s),

@@ -92,6 +92,16 @@ hipError_t launch_sketch_gauss(double* S, int64_t m, int32_t tau, int64_t ldas, 
 hipError_t launch_srht_fill(double* S, int64_t m, int32_t tau, int64_t ldas, const int32_t* members, uint64_t seed,
                             uint64_t pid, int64_t k0, int64_t mpad, int32_t nslots, const int32_t* done,
                             hipStream_t s);
+// The SRHT by its fast transform, for m' = mpad <= srht_fast_max_mpad() (LDS-resident butterflies):
+// OUT(j, c) = sum_{i < m} S_ic Y[i][j] for j < ncols, c < tau, where S_ic = d_i (-1)^popcount(i & C_c)
+// / sqrt(tau m'), C = members[slot] (ascending in [0, m')) and the signs d_i are read back from the
+// slot's explicit S (S[slot] m x lds, slot stride sS). Stored at OUT[j ldo + c] (trans_out 0) or
+// OUT[c ldo + j]; Y and OUT have slot strides sY and sO.
+int64_t srht_fast_max_mpad();
+hipError_t launch_srht_apply(const double* Y, int64_t ldy, int64_t sY, int64_t m, int64_t ncols, int64_t mpad,
+                             const double* S, int64_t lds, int64_t sS, const int32_t* members, int32_t tau,
+                             double* OUT, int64_t ldo, int64_t sO, int32_t trans_out, int32_t nslots,
+                             const int32_t* done, hipStream_t s);
 // S[slot] (m x ldas) from a sparse sketch's bucket codes (hmap, m per slot).
 hipError_t launch_sketch_densify(double* S, const int32_t* hmap, int64_t m, int64_t ldas, int32_t nslots,
                                  const int32_t* done, hipStream_t s);

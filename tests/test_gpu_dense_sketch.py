@@ -10,7 +10,8 @@ dense data, which all take the dense-S products T = Z^T S, A S = Z T + lambda S 
   dual, kernel ridge, ragged tiles;
 * a converged solve reaches the direct solution.
 SRHT problems use m close below a power of 2 (m' / m < 1.1), where the truncated Hadamard
-columns stay independent.
+columns stay independent. The SRHT's T = Z^T S and G = S^T AS come from its fast Walsh-Hadamard
+transform (m' <= 16384), the other sketches' from FP64 MFMA products with the explicit S.
 """
 import numpy as np
 import pytest
@@ -91,6 +92,26 @@ def test_kernel_dense_sketch_trajectory(kind):
     assert_state_close(S.state(), [("x", st.w), ("x_prev", st.w_prev), ("r", st.r), ("r_prev", st.r_prev)],
                        TRAJ_TOL, f"kernel {kind} k=50")
     S.close()
+
+
+def test_srht_fast_transform_largest_padding():
+    """The SRHT's fast transform at its largest LDS-resident padding: 9000 kernel-ridge points
+    (m' = 16384, one column of Z per workgroup, 144 KB of LDS). T = Z^T S and G = S^T AS come from
+    the Walsh-Hadamard butterflies; AS and G^{-1} against the oracle's products of the explicit
+    SRHT matrix, entry by entry."""
+    p = inputs.make_points(9000, 8, 1e-3, 0.5, seed=57)
+    system = kernel_system(p.P, p.y, p.lam, p.sigma)
+    tau = 60
+    S = rs.Solver(p.P, p.y, p.lam, tau=tau, sketch="srht", tol=0.0, seed=4, momentum="none",
+                  kernel_sigma=p.sigma)
+    S.step(1)
+    AS, Ginv = S.products()
+    S.close()
+    sk = osk.draw("srht", 4, 0, 0, 9000, tau)
+    _, AS_o, G_o, _ = sketched_products(system, sk)
+    assert_vec_close(AS.ravel(), AS_o.ravel(), 1e-11, "SRHT m'=16384 AS")
+    err = np.abs(Ginv[:tau, :tau] @ G_o - np.eye(tau)).max()
+    assert err <= 4 * tau * 2.0 ** -53 * np.linalg.cond(G_o), err
 
 
 @pytest.mark.parametrize("kind", ["gaussian", "srht"])
