@@ -41,6 +41,11 @@ WORKLOADS = {
     "sparse_subcount": dict(kind="csr", gen="sparse_csr", sketch="subcount", tau=500, sub_k=4,
                             precision="fp64",
                             name="csr_100000x20000_density0.001_subcount_s2000_tau500_primal"),
+    "sparse_count_mixed": dict(kind="csr", gen="sparse_csr", sketch="count", tau=500, sub_k=0, precision="mixed",
+                               name="csr_100000x20000_density0.001_count_tau500_primal_fp32AS_refresh20"),
+    "sparse_subcount_mixed": dict(kind="csr", gen="sparse_csr", sketch="subcount", tau=500, sub_k=4,
+                                  precision="mixed",
+                                  name="csr_100000x20000_density0.001_subcount_s2000_tau500_primal_fp32AS_refresh20"),
     "dense_primal": dict(kind="dense", gen="dense_primal", sketch="subsample", tau=50, sub_k=0,
                          precision="fp64", name="dense_2000x500_subsample_tau50_primal"),
     "dense_mixed": dict(kind="dense", gen="dense_mixed", sketch="subsample", tau=1024, sub_k=0,
@@ -80,8 +85,10 @@ def algorithmic_bytes(cls, wl, n, d, nnz, m, K, tau, nsel, a_nnz=0, slots=1):
     if cls == "as":
         if wl["kind"] == "csr":
             # CSR of Z and of Z^T (FP32 value + int32 column each) read once, row pointers,
-            # bucket map, AS written once (FP64), G = S^T A S written once (FP64)
-            return 2 * nnz * 8 + (m + 1) * 8 + (K + 1) * 8 + m * 4 + m * tau * 8 + tau * tau * 8
+            # bucket map, AS written once (FP64, or FP32 in mixed precision), G = S^T A S written
+            # once (FP64)
+            elt = 4 if wl["precision"] == "mixed" else 8
+            return 2 * nnz * 8 + (m + 1) * 8 + (K + 1) * 8 + m * 4 + m * tau * elt + tau * tau * 8
         if wl.get("gram"):
             # formed A: the tau gathered entries of each of its m rows read, AS written
             elt = 4 if wl["precision"] == "mixed" else 8
@@ -92,9 +99,10 @@ def algorithmic_bytes(cls, wl, n, d, nnz, m, K, tau, nsel, a_nnz=0, slots=1):
         shift = m * tau * 8 if wl["kind"] == "kernel" else 0
         return m * K * elt + tau * K * elt + m * tau * (4 if wl["precision"] == "mixed" else 8) + shift
     if cls == "g":
-        # G = S^T AS from the member rows of AS (FP64), their bucket codes and indices, the
-        # bucket offsets; G written
-        return nsel * tau * 8 + nsel * (4 + 4) + (tau + 1) * 4 + tau * tau * 8
+        # G = S^T AS from the member rows of AS (FP64, or FP32 in mixed precision), their bucket
+        # codes and indices, the bucket offsets; G written
+        elt = 4 if wl["precision"] == "mixed" else 8
+        return nsel * tau * elt + nsel * (4 + 4) + (tau + 1) * 4 + tau * tau * 8
     if cls == "update":
         # AS read, bucket map, x^k, x^{k-1}, r^k, r^{k-1} read, two vectors written, delta
         return m * tau * (4 if wl["precision"] == "mixed" else 8) + m * 4 + 4 * m * 8 + 2 * m * 8 + tau * 8
@@ -236,7 +244,7 @@ def main_batched(args):
     wl = WORKLOADS["batched"]
     torch.cuda.set_device(0)
     print(f"[bench] generating {wl['name']}", file=sys.stderr, flush=True)
-    probs = inputs.batched(scale=args.scale)
+    probs = inputs.batched(scale=args.scale, cap_factor=args.cap_factor)
     stream = torch.cuda.current_stream().cuda_stream
     t0 = time.perf_counter()
     B = rs.Batch(probs, tol=1e-6, seed=1, autotune=True, stream=stream, max_iter=args.max_iter,
@@ -281,25 +289,47 @@ def main_batched(args):
         tfs = dense_flops / (tune["dense_ms"] * 1e-3) / 1e12
         roofline.update({"achieved": round(tfs, 2), "frac": round(tfs / FP64_PEAK_TFS, 4)})
 
-    # the plain single-solve path on samples (one dense, one CSR problem), extrapolated
-    samples = {}
-    for p in (0, len(probs) // 2):
+    # converged fraction and median stop iteration per lambda (slot j = l * nrhs + q)
+    nl = len(probs[0]["lambdas"])
+    nrhs = probs[0]["y"].shape[1]
+    per_lambda = []
+    for l in range(nl):
+        stops = np.concatenate([B.slots(p)[0][l * nrhs:(l + 1) * nrhs] for p in range(len(probs))])
+        conv_l = stops >= 0
+        per_lambda.append({"lambda": float(probs[0]["lambdas"][l]), "converged_fraction": round(float(conv_l.mean()), 4),
+                           "median_stop_iteration": float(np.median(stops[conv_l])) if conv_l.any() else None})
+    B.close()
+
+    # the plain FP64 single-solve path: full solves (to 1e-6 or the problem's cap) of a stratified
+    # subset -- 8 problems spread over the per-iteration work (4 dense, 4 CSR), 4 lambdas each,
+    # right-hand side 0 -- timed one by one; the seconds per unit of work and iteration of each kind
+    # scale to every slot of the batch with the iterations that slot took there
+    order = sorted(range(len(probs)), key=lambda p: batch_weights(probs[p]))
+    subset = [p for kind in ("dense", "csr") for p in
+              [q for q in order if probs[q]["kind"] == kind][::8][:4]]
+    lam_idx = [0, nl // 3, (2 * nl) // 3, nl - 1]
+    rate = {"dense": [0.0, 0.0], "csr": [0.0, 0.0]}  # seconds, work * iterations
+    full = []
+    for p in subset:
         pr = probs[p]
-        S = rs.Solver(pr["X"], pr["y"][:, 0], float(pr["lambdas"][8]), tau=pr["tau"],
-                      sketch="subsample" if pr["kind"] == "dense" else "count", tol=0.0, seed=1,
-                      problem_id=p, max_iter=1000000, stream=stream, momentum=args.momentum)
-        S.step(8)
-        torch.cuda.synchronize()
-        ts = time.perf_counter()
-        S.step(64)
-        torch.cuda.synchronize()
-        samples[pr["kind"]] = ((time.perf_counter() - ts) / 64, batch_weights(pr))
-        S.close()
+        for l in lam_idx:
+            S = rs.Solver(pr["X"], pr["y"][:, 0], float(pr["lambdas"][l]), tau=pr["tau"],
+                          sketch="subsample" if pr["kind"] == "dense" else "count", tol=1e-6, seed=1,
+                          problem_id=p, max_iter=pr["max_iter"], stream=stream, momentum=args.momentum)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            _, st1, rep1 = S.solve()
+            torch.cuda.synchronize()
+            el = time.perf_counter() - ts
+            S.close()
+            rate[pr["kind"]][0] += el
+            rate[pr["kind"]][1] += batch_weights(pr) * rep1.iters
+            full.append({"problem": p, "kind": pr["kind"], "lambda": float(pr["lambdas"][l]), "seconds": round(el, 4),
+                         "iterations": rep1.iters, "converged": st1 == rs.RS_OK})
     plain = 0.0
     for pr, it in zip(probs, slot_iters):
-        t_it, w0 = samples[pr["kind"]]
-        plain += float(it.sum()) * t_it * batch_weights(pr) / w0
-    B.close()
+        sec, work = rate[pr["kind"]]
+        plain += float(it.sum()) * batch_weights(pr) * sec / work
 
     out = {
         "metric": "time-to-rel-residual 1e-6", "value": round(T, 4), "unit": "s", "n_gpus": 1,
@@ -308,7 +338,7 @@ def main_batched(args):
         "data": "synthetic",
         "config": {"workload": wl["name"], "problems": len(probs), "lambdas": 16, "rhs": 4,
                    "solves": n_solves, "dense": sum(pr["kind"] == "dense" for pr in probs),
-                   "tau_rule": "64 round(m^(2/3) / 64) clamped to [64, 512]", "cap": "50 m / tau",
+                   "tau_rule": "64 round(m^(2/3) / 64) clamped to [64, 512]", "cap": f"{args.cap_factor:g} m / tau",
                    "tol": 1e-6, "momentum": args.momentum, "graph_iters": tune["graph_iters"]},
         "converged_fraction": round(statistics.median(conv), 4),
         "lock_step_iters_median": statistics.median(steps_k),
@@ -318,11 +348,15 @@ def main_batched(args):
         "setup_s": round(setup_s, 2),
         "tuning": tune,
         "roofline": roofline,
+        "per_lambda": per_lambda,
         "plain_fp64_single_solves": {
             "value": round(plain, 1), "unit": "s",
-            "sample": "64 iterations of one solve of problem 0 (dense) and of problem 32 (CSR) with the "
-                      "single-solve path, scaled by per-problem work and by the iterations each of the "
-                      f"{n_solves} solves took in the batch"},
+            "sample": (f"{len(full)} full single solves (to 1e-6 or the cap) of a stratified subset: problems "
+                       f"{subset} (4 dense, 4 CSR, spread over the per-iteration work) x lambdas "
+                       f"{[float(probs[0]['lambdas'][l]) for l in lam_idx]} x right-hand side 0; their seconds per "
+                       "unit of work and iteration, per kind, scaled by every slot's work and the iterations it "
+                       "took in the batch"),
+            "full_solves": full},
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
@@ -684,6 +718,8 @@ def main():
                     help="dense_learned only: held-out seeds also solved by the plain FP64 solver")
     ap.add_argument("--scale", type=float, default=1.0,
                     help="batched workload only: shrink n and d (shape-alike smaller batch)")
+    ap.add_argument("--cap-factor", type=float, default=100.0,
+                    help="batched workload only: per-problem iteration cap cap_factor * m / tau")
     ap.add_argument("--max-iter", type=int, default=200000,
                     help="iteration cap per solve (a capped run reports per-iteration throughput)")
     ap.add_argument("--dense-route", default="products", choices=["products", "gram"],
@@ -847,7 +883,8 @@ def main():
         "metric": metric, "value": value, "unit": unit, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(T * 1e3, 3),
         "higher_is_better": hib, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16" if wl["precision"] == "mixed" else "f64",
+        # CSR mixed precision sums in FP64 and stores AS in FP32; dense mixed multiplies BF16 on MFMA
+        "dtype": "bf16" if wl["precision"] == "mixed" and wl["kind"] != "csr" else "f64",
         "data": "synthetic",
         "config": {"workload": wl["name"], "n": n, "d": d, "nnz": nnz, "form": "kernel" if kern else form,
                    "sketch": wl["sketch"], "tau": wl["tau"], "subcount_k": wl["sub_k"],

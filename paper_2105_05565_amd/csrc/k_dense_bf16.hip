@@ -459,6 +459,12 @@ hipError_t launch_refresh(const void* Zr, int32_t z_f32, int64_t ldz, int64_t m,
   return hipGetLastError();
 }
 
+hipError_t launch_refresh_norm(const double* partials, int32_t n, DevFlags* flags, double* hist, double* true_hist,
+                               int64_t k, double tol, hipStream_t s) {
+  hipLaunchKernelGGL(k_refresh_norm, dim3(1), dim3(256), 0, s, partials, n, flags, hist, true_hist, k, tol);
+  return hipGetLastError();
+}
+
 hipError_t launch_true_residual(const void* Zr, int32_t z_f32, int64_t ldz, int64_t m, int64_t K, const double* x,
                                 const double* b, double lam, int32_t lam_u, double* u, double* upart, double* r2,
                                 double* partials, const int32_t* zero, hipStream_t s) {

@@ -261,6 +261,55 @@ __global__ void k_spmv_csr(const int64_t* __restrict__ ptr, const int32_t* __res
   if (lane == 0) out[r] = s;
 }
 
+// Two sparse products sharing each row's pass: o0 = M v0, o1 = M v1 (FP64 accumulation), one
+// wave per row; skipped once the solve has stopped.
+template <typename V>
+__global__ void k_spmv_pair(const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                            const V* __restrict__ val, int64_t rows, const double* __restrict__ v0,
+                            const double* __restrict__ v1, double* __restrict__ o0, double* __restrict__ o1,
+                            const DevFlags* __restrict__ flags) {
+  if (flags->done) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (r >= rows) return;
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t p = ptr[r] + lane; p < ptr[r + 1]; p += 64) {
+    const double a = (double)val[p];
+    const int32_t c = col[p];
+    s0 += a * v0[c];
+    s1 += a * v1[c];
+  }
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  if (lane == 0) {
+    o0[r] = s0;
+    o1[r] = s1;
+  }
+}
+
+constexpr int kRefreshRows = 1024;  // rows per workgroup of the residual kernel
+
+// r = t0 + lambda x - b, rp = t1 + lambda xp - b; partial sums of ||r||^2 per workgroup.
+__global__ __launch_bounds__(256) void k_resid_pair(const double* __restrict__ t0, const double* __restrict__ t1,
+                                                    const double* __restrict__ x, const double* __restrict__ xp,
+                                                    const double* __restrict__ b, double lam, int64_t m,
+                                                    double* __restrict__ r, double* __restrict__ rp,
+                                                    double* __restrict__ partials,
+                                                    const DevFlags* __restrict__ flags) {
+  __shared__ double scratch[16];
+  if (flags->done) return;
+  const int64_t j0 = (int64_t)blockIdx.x * kRefreshRows, j1 = min(m, j0 + kRefreshRows);
+  double ss = 0.0;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+    const double rn = t0[j] + lam * x[j] - b[j];
+    r[j] = rn;
+    rp[j] = t1[j] + lam * xp[j] - b[j];
+    ss += rn * rn;
+  }
+  ss = block_sum(ss, scratch);
+  if (threadIdx.x == 0) partials[blockIdx.x] = ss;
+}
+
 // ---- CSR transpose (setup) ----
 __global__ void k_expand_rows(const int64_t* __restrict__ ptr, int64_t rows, int32_t* __restrict__ row_of) {
   const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -429,6 +478,34 @@ hipError_t launch_spmv_csr(const int64_t* ptr, const int32_t* col, const void* v
     hipLaunchKernelGGL(k_spmv_csr<double>, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, ptr,
                        col, (const double*)val, rows, v, out);
   return hipGetLastError();
+}
+
+int64_t refresh_csr_partials(int64_t m) { return (m + kRefreshRows - 1) / kRefreshRows; }
+
+hipError_t launch_refresh_csr(const int64_t* zr_ptr, const int32_t* zr_col, const void* zr_val,
+                              const int64_t* zt_ptr, const int32_t* zt_col, const void* zt_val, int32_t vals_f32,
+                              int64_t m, int64_t K, const double* x, const double* xp, const double* b, double lam,
+                              double* r, double* rp, double* u, double* t, double* partials, DevFlags* flags,
+                              double* hist, double* true_hist, int64_t k, double tol, hipStream_t s) {
+  if (m <= 0 || K <= 0) return hipErrorInvalidValue;
+  // u = Z^T [x, xp] (K rows of CSR(Z^T)), then t = Z u (m rows of CSR(Z))
+  if (vals_f32) {
+    hipLaunchKernelGGL(k_spmv_pair<float>, dim3((unsigned)((K + 3) / 4)), dim3(256), 0, s, zt_ptr, zt_col,
+                       (const float*)zt_val, K, x, xp, u, u + K, flags);
+    hipLaunchKernelGGL(k_spmv_pair<float>, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, zr_ptr, zr_col,
+                       (const float*)zr_val, m, u, u + K, t, t + m, flags);
+  } else {
+    hipLaunchKernelGGL(k_spmv_pair<double>, dim3((unsigned)((K + 3) / 4)), dim3(256), 0, s, zt_ptr, zt_col,
+                       (const double*)zt_val, K, x, xp, u, u + K, flags);
+    hipLaunchKernelGGL(k_spmv_pair<double>, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, zr_ptr, zr_col,
+                       (const double*)zr_val, m, u, u + K, t, t + m, flags);
+  }
+  const int64_t np = refresh_csr_partials(m);
+  hipLaunchKernelGGL(k_resid_pair, dim3((unsigned)np), dim3(256), 0, s, t, t + m, x, xp, b, lam, m, r, rp, partials,
+                     flags);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_refresh_norm(partials, (int32_t)np, flags, hist, true_hist, k, tol, s);
 }
 
 hipError_t csr_transpose(const int64_t* ptr, const int32_t* col, const void* val, int32_t vals_f32,

@@ -80,14 +80,15 @@ __global__ void k_a_structure(const uint64_t* __restrict__ ukeys, int64_t nu, in
   }
 }
 
-// Rows j0 .. j1 of AS for WAVES sketches (wave w: sketch blockIdx.y * WAVES + w).
-template <int WAVES>
+// Rows j0 .. j1 of AS for WAVES sketches (wave w: sketch blockIdx.y * WAVES + w). The bucket
+// sums are FP64; OutT is the stored type of AS (FP64, or FP32 in mixed precision).
+template <int WAVES, typename OutT>
 __global__ __launch_bounds__(WAVES * 64) void k_as_arows(const int64_t* __restrict__ a_ptr,
                                                           const int32_t* __restrict__ a_col,
                                                           const double* __restrict__ a_val, int64_t m,
                                                           int32_t tau, int64_t ldas, int32_t nslots,
                                                           double lam, const int32_t* __restrict__ hmap_all,
-                                                          double* __restrict__ AS, int32_t rows_per_block,
+                                                          OutT* __restrict__ AS, int32_t rows_per_block,
                                                           const int32_t* __restrict__ done) {
   extern __shared__ __align__(16) double lds[];  // [WAVES][tau]
   if (*done) return;
@@ -96,7 +97,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_as_arows(const int64_t* __restri
   if (slot >= nslots) return;  // waves are independent: no workgroup barrier below
   const int32_t* hmap = hmap_all + slot * m;
   double* acc = lds + (int64_t)wave * tau;
-  double* out_base = AS + slot * m * ldas;
+  OutT* out_base = AS + slot * m * ldas;
   const int64_t j0 = (int64_t)blockIdx.x * rows_per_block;
   const int64_t j1 = min(m, j0 + rows_per_block);
   for (int64_t j = j0; j < j1; ++j) {
@@ -129,8 +130,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_as_arows(const int64_t* __restri
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    double* out = out_base + j * ldas;
-    for (int c = lane; c < tau; c += 64) out[c] = acc[c];
+    OutT* out = out_base + j * ldas;
+    for (int c = lane; c < tau; c += 64) out[c] = (OutT)acc[c];
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   }
@@ -142,12 +143,13 @@ __global__ __launch_bounds__(WAVES * 64) void k_as_arows(const int64_t* __restri
 // block index is mapped so that each XCD takes whole row chunks, every sketch of a chunk
 // before the next chunk: the chunk's rows of A0 are read into that XCD's L2 once and stay
 // there while its sketches pass.
+template <typename OutT>
 __global__ __launch_bounds__(512) void k_as_arows_lds(const int64_t* __restrict__ a_ptr,
                                                       const int32_t* __restrict__ a_col,
                                                       const double* __restrict__ a_val, int64_t m,
                                                       int32_t tau, int64_t ldas, double lam,
                                                       const int32_t* __restrict__ hmap_all,
-                                                      double* __restrict__ AS, int32_t nslots,
+                                                      OutT* __restrict__ AS, int32_t nslots,
                                                       int64_t nchunks, const int32_t* __restrict__ done) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   int16_t* hm = reinterpret_cast<int16_t*>(lds_raw);                            // [m]
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(512) void k_as_arows_lds(const int64_t* __restrict_
   }
   __syncthreads();
   double* acc = acc_all + (int64_t)wave * tau;
-  double* out_base = AS + slot * m * ldas;
+  OutT* out_base = AS + slot * m * ldas;
   const int64_t j0 = chunk * kLdsRows;
   const int64_t j1 = min(m, j0 + kLdsRows);
   for (int64_t j = j0 + wave; j < j1; j += 8) {
@@ -203,8 +205,8 @@ __global__ __launch_bounds__(512) void k_as_arows_lds(const int64_t* __restrict_
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    double* out = out_base + j * ldas;
-    for (int c = lane; c < tau; c += 64) out[c] = acc[c];
+    OutT* out = out_base + j * ldas;
+    for (int c = lane; c < tau; c += 64) out[c] = (OutT)acc[c];
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   }
@@ -212,12 +214,13 @@ __global__ __launch_bounds__(512) void k_as_arows_lds(const int64_t* __restrict_
 
 // As k_as_arows_lds for a bucket map too large for 16-bit codes in LDS: the codes are packed
 // three to a 32-bit word, and 4 waves share a workgroup (one AS row each at a time).
+template <typename OutT>
 __global__ __launch_bounds__(64 * kPackedWaves) void k_as_arows_packed(const int64_t* __restrict__ a_ptr,
                                                                       const int32_t* __restrict__ a_col,
                                                                       const double* __restrict__ a_val, int64_t m,
                                                                       int32_t tau, int64_t ldas, double lam,
                                                                       const int32_t* __restrict__ hmap_all,
-                                                                      double* __restrict__ AS, int32_t nslots,
+                                                                      OutT* __restrict__ AS, int32_t nslots,
                                                                       int64_t nchunks, const int32_t* __restrict__ done) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int64_t nwords = (m + 2) / 3;
@@ -242,7 +245,7 @@ __global__ __launch_bounds__(64 * kPackedWaves) void k_as_arows_packed(const int
   }
   __syncthreads();
   double* acc = acc_all + (int64_t)wave * tau;
-  double* out_base = AS + slot * m * ldas;
+  OutT* out_base = AS + slot * m * ldas;
   const int64_t j0 = chunk * kLdsRows;
   const int64_t j1 = min(m, j0 + kLdsRows);
   auto code_of = [&](int64_t col) -> int {
@@ -276,15 +279,17 @@ __global__ __launch_bounds__(64 * kPackedWaves) void k_as_arows_packed(const int
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    double* out = out_base + j * ldas;
-    for (int c = lane; c < tau; c += 64) out[c] = acc[c];
+    OutT* out = out_base + j * ldas;
+    for (int c = lane; c < tau; c += 64) out[c] = (OutT)acc[c];
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   }
 }
 
-// G[slot][b][c] = sum over the members j of bucket b (in member order) of s_j AS[j][c].
-__global__ __launch_bounds__(256) void k_g_from_as(const double* __restrict__ AS_all, int64_t m,
+// G[slot][b][c] = sum over the members j of bucket b (in member order) of s_j AS[j][c], in FP64
+// (AS stored as InT: FP64, or FP32 in mixed precision).
+template <typename InT>
+__global__ __launch_bounds__(256) void k_g_from_as(const InT* __restrict__ AS_all, int64_t m,
                                                    int32_t tau, int64_t ldas,
                                                    const int32_t* __restrict__ hmap_all,
                                                    const int32_t* __restrict__ members_all,
@@ -294,7 +299,7 @@ __global__ __launch_bounds__(256) void k_g_from_as(const double* __restrict__ AS
   if (*done) return;
   const int b = blockIdx.x;
   const int64_t slot = blockIdx.y;
-  const double* AS = AS_all + slot * m * ldas;
+  const InT* AS = AS_all + slot * m * ldas;
   const int32_t* hmap = hmap_all + slot * m;
   const int32_t* members = members_all + slot * nsel;
   const int32_t* offs = offs_all + slot * (tau + 1);
@@ -305,7 +310,7 @@ __global__ __launch_bounds__(256) void k_g_from_as(const double* __restrict__ AS
 #pragma unroll 4
     for (int p = p0; p < p1; ++p) {
       const int64_t j = members[p];
-      const double v = AS[j * ldas + c];
+      const double v = (double)AS[j * ldas + c];
       s += (hmap[j] & 1) ? -v : v;
     }
     grow[c] = s;
@@ -374,19 +379,57 @@ hipError_t zzt_impl(const int64_t* zt_ptr, const int32_t* zt_col, const V* zt_va
   return e;
 }
 
-template <int W>
+template <int W, typename OutT>
 hipError_t arows_launch(const int64_t* a_ptr, const int32_t* a_col, const double* a_val, int64_t m,
                         int32_t tau, int64_t ldas, int32_t nslots, double lam, const int32_t* hmap,
-                        double* AS, const int32_t* done, hipStream_t s) {
+                        OutT* AS, const int32_t* done, hipStream_t s) {
   const size_t bytes = sizeof(double) * W * (size_t)tau;
-  hipError_t e = hipFuncSetAttribute((const void*)k_as_arows<W>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  hipError_t e = hipFuncSetAttribute((const void*)k_as_arows<W, OutT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)bytes);
   if (e != hipSuccess) return e;
   const int rows = 16;
   const dim3 grid((unsigned)((m + rows - 1) / rows), (unsigned)((nslots + W - 1) / W));
-  hipLaunchKernelGGL(k_as_arows<W>, grid, dim3(W * 64), bytes, s, a_ptr, a_col, a_val, m, tau, ldas, nslots,
-                     lam, hmap, AS, rows, done);
+  hipLaunchKernelGGL((k_as_arows<W, OutT>), grid, dim3(W * 64), bytes, s, a_ptr, a_col, a_val, m, tau, ldas,
+                     nslots, lam, hmap, AS, rows, done);
   return hipGetLastError();
+}
+
+template <typename OutT>
+hipError_t as_arows_impl(const int64_t* a_ptr, const int32_t* a_col, const double* a_val, int64_t m,
+                         int32_t tau, int64_t ldas, int32_t nslots, double lam, const int32_t* hmap, OutT* AS,
+                         const int32_t* done, hipStream_t s) {
+  hipError_t e;
+  const size_t lds = arows_lds_bytes(m, tau);
+  if (tau < 16383 && lds <= 96 * 1024) {
+    // bucket map in LDS (16-bit codes): one sketch per workgroup
+    e = hipFuncSetAttribute((const void*)k_as_arows_lds<OutT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+    if (e != hipSuccess) return e;
+    const int64_t nchunks = (m + kLdsRows - 1) / kLdsRows;
+    const int64_t nblocks = 8 * (int64_t)nslots * ((nchunks + 7) / 8);
+    if (nblocks > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_as_arows_lds<OutT>, dim3((unsigned)nblocks), dim3(512), lds, s, a_ptr, a_col, a_val, m,
+                       tau, ldas, lam, hmap, AS, nslots, nchunks, done);
+    e = hipGetLastError();
+  } else if (tau <= 511 && arows_packed_lds_bytes(m, tau) <= 156 * 1024) {
+    // packed map in LDS: one workgroup of 4 waves per CU
+    const size_t plds = arows_packed_lds_bytes(m, tau);
+    e = hipFuncSetAttribute((const void*)k_as_arows_packed<OutT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)plds);
+    if (e != hipSuccess) return e;
+    const int64_t nchunks = (m + kLdsRows - 1) / kLdsRows;
+    const int64_t nblocks = 8 * (int64_t)nslots * ((nchunks + 7) / 8);
+    if (nblocks > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_as_arows_packed<OutT>, dim3((unsigned)nblocks), dim3(64 * kPackedWaves), plds, s, a_ptr,
+                       a_col, a_val, m, tau, ldas, lam, hmap, AS, nslots, nchunks, done);
+    e = hipGetLastError();
+  } else if (tau <= 1024)
+    e = arows_launch<16, OutT>(a_ptr, a_col, a_val, m, tau, ldas, nslots, lam, hmap, AS, done, s);
+  else if (tau <= 2048)
+    e = arows_launch<8, OutT>(a_ptr, a_col, a_val, m, tau, ldas, nslots, lam, hmap, AS, done, s);
+  else
+    return hipErrorInvalidValue;
+  return e;
 }
 
 }  // namespace
@@ -410,45 +453,22 @@ hipError_t build_zzt(const int64_t* zt_ptr, const int32_t* zt_col, const void* z
 }
 
 hipError_t launch_as_arows(const int64_t* a_ptr, const int32_t* a_col, const double* a_val, int64_t m,
-                           int32_t tau, int64_t ldas, int32_t nslots, double lam, const int32_t* hmap, double* AS,
-                           const int32_t* done, hipStream_t s) {
-  hipError_t e;
-  const size_t lds = arows_lds_bytes(m, tau);
-  if (tau < 16383 && lds <= 96 * 1024) {
-    // bucket map in LDS (16-bit codes): one sketch per workgroup
-    e = hipFuncSetAttribute((const void*)k_as_arows_lds, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    const int64_t nchunks = (m + kLdsRows - 1) / kLdsRows;
-    const int64_t nblocks = 8 * (int64_t)nslots * ((nchunks + 7) / 8);
-    if (nblocks > (int64_t)INT32_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_as_arows_lds, dim3((unsigned)nblocks), dim3(512), lds, s, a_ptr, a_col, a_val, m, tau,
-                       ldas, lam, hmap, AS, nslots, nchunks, done);
-    e = hipGetLastError();
-  } else if (tau <= 511 && arows_packed_lds_bytes(m, tau) <= 156 * 1024) {
-    // packed map in LDS: one workgroup of 4 waves per CU
-    const size_t plds = arows_packed_lds_bytes(m, tau);
-    e = hipFuncSetAttribute((const void*)k_as_arows_packed, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plds);
-    if (e != hipSuccess) return e;
-    const int64_t nchunks = (m + kLdsRows - 1) / kLdsRows;
-    const int64_t nblocks = 8 * (int64_t)nslots * ((nchunks + 7) / 8);
-    if (nblocks > (int64_t)INT32_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_as_arows_packed, dim3((unsigned)nblocks), dim3(64 * kPackedWaves), plds, s, a_ptr, a_col,
-                       a_val, m, tau, ldas, lam, hmap, AS, nslots, nchunks, done);
-    e = hipGetLastError();
-  } else if (tau <= 1024)
-    e = arows_launch<16>(a_ptr, a_col, a_val, m, tau, ldas, nslots, lam, hmap, AS, done, s);
-  else if (tau <= 2048)
-    e = arows_launch<8>(a_ptr, a_col, a_val, m, tau, ldas, nslots, lam, hmap, AS, done, s);
-  else
-    return hipErrorInvalidValue;
-  return e;
+                           int32_t tau, int64_t ldas, int32_t nslots, double lam, const int32_t* hmap, void* AS,
+                           int32_t as_f32, const int32_t* done, hipStream_t s) {
+  if (as_f32)
+    return as_arows_impl<float>(a_ptr, a_col, a_val, m, tau, ldas, nslots, lam, hmap, (float*)AS, done, s);
+  return as_arows_impl<double>(a_ptr, a_col, a_val, m, tau, ldas, nslots, lam, hmap, (double*)AS, done, s);
 }
 
-hipError_t launch_g_from_as(const double* AS, int64_t m, int32_t tau, int64_t ldas, int32_t nslots,
+hipError_t launch_g_from_as(const void* AS, int32_t as_f32, int64_t m, int32_t tau, int64_t ldas, int32_t nslots,
                             const int32_t* hmap, const int32_t* members, const int32_t* offs, int64_t nsel,
                             double* G, int64_t ldg, const int32_t* done, hipStream_t s) {
-  hipLaunchKernelGGL(k_g_from_as, dim3(tau, nslots), dim3(256), 0, s, AS, m, tau, ldas, hmap, members, offs,
-                     nsel, G, ldg, done);
+  if (as_f32)
+    hipLaunchKernelGGL(k_g_from_as<float>, dim3(tau, nslots), dim3(256), 0, s, (const float*)AS, m, tau, ldas, hmap,
+                       members, offs, nsel, G, ldg, done);
+  else
+    hipLaunchKernelGGL(k_g_from_as<double>, dim3(tau, nslots), dim3(256), 0, s, (const double*)AS, m, tau, ldas,
+                       hmap, members, offs, nsel, G, ldg, done);
   return hipGetLastError();
 }
 

@@ -58,6 +58,7 @@ struct rs_handle {
   double* ref_u = nullptr;
   double* ref_upart = nullptr;
   double* ref_partials = nullptr;
+  double* ref_t = nullptr;  // mixed precision on CSR data: Z (Z^T x) for x^k and x^{k-1} (2 m)
   // the FP64 residual of the returned iterate, recomputed from the data at the end of a solve
   double* tr_u = nullptr;
   double* tr_upart = nullptr;
@@ -258,6 +259,16 @@ void prof_collect(rs_handle* h, int64_t drop_from = INT64_MAX) {
 // Mixed precision: r^k and r^{k-1} recomputed in FP64 from x^k, x^{k-1}; stop test on it.
 void refresh(rs_handle* h, int64_t k) {
   const int pe = prof_begin(h, RS_PROF_REFRESH, 1, 2);
+  if (h->sparse) {
+    // CSR: two sparse products over the data per vector (Z^T x, then Z (Z^T x)), FP64
+    check_hip(launch_refresh_csr(h->zr_ptr, h->zr_col, h->zr_val, h->zt_ptr, h->zt_col, h->zt_val, h->vals_f32,
+                                 h->m, h->K, h->xbuf[k & 1], h->xbuf[(k + 1) & 1], h->b, h->lam, h->rbuf[k & 1],
+                                 h->rbuf[(k + 1) & 1], h->ref_u, h->ref_t, h->ref_partials, h->flags, h->hist,
+                                 h->true_hist, k, h->opt.tol, h->stream),
+              "refresh (CSR)");
+    prof_end(h, pe);
+    return;
+  }
   // kernel ridge refreshes from the FP64 kernel matrix, dense ridge from the FP32 copy of X
   const void* Zr = h->kern ? (const void*)h->Z : (const void*)h->Z32;
   const int64_t ldr = h->kern ? h->ldz : h->K;
@@ -400,12 +411,12 @@ void prep_batch(rs_handle* h, int p, int64_t k0, int nb, hipStream_t s) {
       check_hip(launch_gemm_f64(g3, true, nb, s), "G = S^T A S");
     }
   } else if (h->arows) {
-    check_hip(launch_as_arows(h->a_ptr, h->a_col, h->a_val, h->m, h->tau, h->ldas, nb, h->lam, bs.hmap,
-                              (double*)bs.AS, done, s),
+    check_hip(launch_as_arows(h->a_ptr, h->a_col, h->a_val, h->m, h->tau, h->ldas, nb, h->lam, bs.hmap, bs.AS,
+                              h->mixed ? 1 : 0, done, s),
               "AS (rows of Z Z^T)");
     prof_end(h, pe, s);
     pe = prof_begin(h, RS_PROF_G, nb, 1, s, k0);
-    check_hip(launch_g_from_as((const double*)bs.AS, h->m, h->tau, h->ldas, nb, bs.hmap, bs.members, bs.offs,
+    check_hip(launch_g_from_as(bs.AS, h->mixed ? 1 : 0, h->m, h->tau, h->ldas, nb, bs.hmap, bs.members, bs.offs,
                                h->nsel, bs.G, h->ldg, done, s),
               "G = S^T AS");
   } else if (h->sparse) {
@@ -767,8 +778,13 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
     if (n > INT32_MAX || d > INT32_MAX) throw Fail{RS_EINVAL, "n and d must fit in int32"};
     if (o->precision != RS_PREC_FP64 && o->precision != RS_PREC_MIXED_BF16)
       throw Fail{RS_EINVAL, "unknown precision"};
-    if (o->precision == RS_PREC_MIXED_BF16 && X->layout == RS_CSR)
-      throw Fail{RS_EUNSUPPORTED, "mixed precision is built for dense data (subsample sketch)"};
+    if (o->precision == RS_PREC_MIXED_BF16 && X->layout == RS_CSR &&
+        (o->sketch != RS_SKETCH_COUNT && o->sketch != RS_SKETCH_SUBCOUNT))
+      throw Fail{RS_EUNSUPPORTED, "mixed precision on CSR data is built for the count and SubCount sketches"};
+    if (o->precision == RS_PREC_MIXED_BF16 && X->layout == RS_CSR &&
+        (o->sparse_route == RS_ROUTE_SCATTER || o->accelerated != 0))
+      throw Fail{RS_EUNSUPPORTED, "mixed precision on CSR data runs on the rows of Z Z^T (sparse_route AUTO or "
+                                  "AROWS) with the momentum schedules"};
     if (o->precision == RS_PREC_MIXED_BF16 && o->refresh_every < 1)
       throw Fail{RS_EINVAL, "refresh_every must be >= 1"};
     h->mixed = o->precision == RS_PREC_MIXED_BF16;
@@ -975,6 +991,12 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
         h->zt_ptr = tptr; h->zt_col = tcol; h->zt_val = tval;
         check_hip(hipMemcpyAsync(h->b, yd, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "b = y");
       }
+      if (h->mixed) {
+        // FP64 refresh from the CSR data: Z^T [x, xp], Z (Z^T [x, xp]), partial norms
+        h->ref_u = dalloc<double>(h, 2 * h->K);
+        h->ref_t = dalloc<double>(h, 2 * h->m);
+        h->ref_partials = dalloc<double>(h, refresh_csr_partials(h->m));
+      }
     }
 
     if (h->sparse && (o->sparse_route == RS_ROUTE_AROWS || o->sparse_route == RS_ROUTE_AUTO)) {
@@ -986,7 +1008,7 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
       check_hip(hipMemGetInfo(&free_b, &total_b), "memory info");
       // sort and reduction buffers: 48 bytes per pair while A0 is formed
       const bool fits = pairs > 0 && pairs < (int64_t)INT32_MAX && (double)pairs * 48.0 < 0.25 * (double)free_b;
-      if (o->sparse_route == RS_ROUTE_AROWS && !fits)
+      if ((o->sparse_route == RS_ROUTE_AROWS || h->mixed) && !fits)
         throw Fail{RS_EUNSUPPORTED, "the product Z Z^T is too large for the rows-of-A route"};
       if (fits) {
         check_hip(build_zzt(h->zt_ptr, h->zt_col, h->zt_val, h->vals_f32, h->K, h->m, pairs, &h->a_ptr,

@@ -164,12 +164,29 @@ int64_t zzt_pairs(const int64_t* zt_ptr_host, int64_t K);
 hipError_t build_zzt(const int64_t* zt_ptr, const int32_t* zt_col, const void* zt_val, int32_t vals_f32,
                      int64_t K, int64_t m, int64_t npairs, int64_t** a_ptr, int32_t** a_col, double** a_val,
                      int64_t* a_nnz, hipStream_t s);
+// AS (m x ldas per slot) from the rows of A0 = Z Z^T; bucket sums in FP64, stored as FP64 or,
+// when as_f32, rounded to FP32 (mixed precision).
 hipError_t launch_as_arows(const int64_t* a_ptr, const int32_t* a_col, const double* a_val, int64_t m,
-                           int32_t tau, int64_t ldas, int32_t nslots, double lam, const int32_t* hmap, double* AS,
-                           const int32_t* done, hipStream_t s);
-hipError_t launch_g_from_as(const double* AS, int64_t m, int32_t tau, int64_t ldas, int32_t nslots,
+                           int32_t tau, int64_t ldas, int32_t nslots, double lam, const int32_t* hmap, void* AS,
+                           int32_t as_f32, const int32_t* done, hipStream_t s);
+// G = S^T AS from the member rows of AS (FP64 or FP32 when as_f32), summed in FP64.
+hipError_t launch_g_from_as(const void* AS, int32_t as_f32, int64_t m, int32_t tau, int64_t ldas, int32_t nslots,
                             const int32_t* hmap, const int32_t* members, const int32_t* offs, int64_t nsel,
                             double* G, int64_t ldg, const int32_t* done, hipStream_t s);
+// Mixed precision on CSR data: r = Z (Z^T x) + lambda x - b and rp from xp, in FP64 from CSR(Z)
+// (m rows) and CSR(Z^T) (K rows); u holds 2 K doubles, t 2 m doubles, partials
+// refresh_csr_partials(m) doubles; ||r|| / ||r^0|| is recorded at k in hist and true_hist and
+// the stop test applied (flags->done).
+int64_t refresh_csr_partials(int64_t m);
+hipError_t launch_refresh_csr(const int64_t* zr_ptr, const int32_t* zr_col, const void* zr_val,
+                              const int64_t* zt_ptr, const int32_t* zt_col, const void* zt_val, int32_t vals_f32,
+                              int64_t m, int64_t K, const double* x, const double* xp, const double* b, double lam,
+                              double* r, double* rp, double* u, double* t, double* partials, DevFlags* flags,
+                              double* hist, double* true_hist, int64_t k, double tol, hipStream_t s);
+// ||r|| / ||r^0|| from partial sums of squares (n of them, summed in order) into hist[k] and
+// true_hist[k], with the stop test.
+hipError_t launch_refresh_norm(const double* partials, int32_t n, DevFlags* flags, double* hist, double* true_hist,
+                               int64_t k, double tol, hipStream_t s);
 
 // Grouped count-sketch products (batched solves; CSR values held in FP64): per job,
 // T = Z^T S into tbuf (nnz * sparse_entry_bytes_f64() bytes), then AS (m x tau) and

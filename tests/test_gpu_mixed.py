@@ -1,5 +1,6 @@
 """GPU: sketched products against the oracle (FP64) and the mixed-precision path
-(BF16 products with FP32 accumulation, FP64 Cholesky, periodic FP64 refresh).
+(BF16 products with FP32 accumulation on dense data, FP32-stored AS on CSR data, FP64
+Cholesky, periodic FP64 refresh).
 
 The BF16 products are bounded by the standard dot-product error bound (Higham,
 Accuracy and Stability, Sec. 3.1) applied to BF16-rounded inputs accumulated in
@@ -132,11 +133,112 @@ def test_mixed_converges_to_fp64_solution(form):
     S.close()
 
 
-def test_mixed_rejects_csr():
+@pytest.mark.parametrize("kind,sub_k", [("count", 0), ("subcount", 3)])
+@pytest.mark.parametrize("form", ["primal", "dual"])
+def test_csr_mixed_products_within_fp32_bound(kind, sub_k, form):
+    """CSR data in mixed precision: the bucket sums of AS are formed in FP64 from the rows of
+    Z Z^T and stored in FP32, so each entry is within u_fp32 |AS| of the exact product (plus
+    FP64 summation error); G = S^T AS is summed in FP64 from the stored entries, so
+    G_gpu = G + E with |E| <= |S|^T (u_fp32 |AS|), and the returned G^{-1} inverts G to
+    ||G^{-1}|| ||E|| (plus FP64 rounding)."""
+    p = inputs.make_csr(500, 220, 0.03, 0.05, seed=61) if form == "primal" else \
+        inputs.make_csr(220, 500, 0.03, 0.05, seed=62)
+    tau = 25
+    S = rs.Solver(p.X, p.y, p.lam, tau=tau, sketch=kind, form=form, subcount_k=sub_k, tol=0.0, seed=5,
+                  precision="mixed", lookahead=3)
+    S.step(3)
+    AS, Gi = S.products()
+    S.close()
+    system, s, AS_or, G_or, active = _oracle_products(p, form, kind, 2, tau, sub_k)
+    bound = U_FP32 * np.abs(AS_or) + 1e-13 * np.abs(AS_or).max()
+    err = np.abs(AS - AS_or)
+    assert np.all(err <= bound), float((err / bound).max())
+    Sabs = np.abs(s.matrix().toarray())
+    Eb = Sabs.T @ (U_FP32 * np.abs(AS_or))
+    G = G_or.copy()
+    for b in np.flatnonzero(~active):
+        G[b, b] = 1.0
+    resid = np.linalg.norm(Gi @ G - np.eye(tau), 2)
+    assert resid <= 1.01 * np.linalg.norm(Gi, 2) * np.linalg.norm(Eb) + 1e-10, resid
+
+
+@pytest.mark.parametrize("kind", ["count", "subcount"])
+def test_csr_mixed_refresh_recomputes_true_residual(kind):
+    """Every refresh_every iterations r^k and r^{k-1} are recomputed in FP64 from the CSR data
+    (Z^T x, then Z (Z^T x)): they equal A x - b formed by the oracle for the GPU's iterates."""
+    p = inputs.make_csr(900, 300, 0.02, 0.05, seed=63, dtype=np.float32)
+    system = ridge_system(p.X, p.y, p.lam, "primal")
+    S = rs.Solver(p.X, p.y, p.lam, tau=30, sketch=kind, subcount_k=2, tol=0.0, seed=2, precision="mixed",
+                  refresh_every=10, lookahead=16)
+    for steps in (10, 20, 40):
+        S.step(steps - S.k)
+        x, xp, r, rp = S.state()
+        for xx, rr in ((x, r), (xp, rp)):
+            true = system.matvec(xx) - system.b
+            assert np.linalg.norm(rr - true) <= 1e-12 * np.linalg.norm(system.b)
+    S.close()
+
+
+@pytest.mark.parametrize("kind", ["count", "subcount"])
+def test_csr_mixed_stops_only_on_refreshed_residual(kind):
+    """A mixed CSR solve stops at the first refresh whose FP64 residual is <= tol: the stop
+    iteration is a multiple of refresh_every, the reported and recomputed residuals are <= tol,
+    and the weights reach the direct solution within 2 kappa tol."""
+    p = inputs.make_csr(2000, 400, 0.02, 0.1, seed=64, dtype=np.float32)
+    system = ridge_system(p.X, p.y, p.lam, "primal")
+    tol = 1e-8
+    S = rs.Solver(p.X, p.y, p.lam, tau=40, sketch=kind, subcount_k=3, tol=tol, seed=3, precision="mixed",
+                  max_iter=200000, refresh_every=20)
+    w, st, rep = S.solve()
+    assert st == rs.RS_OK
+    assert rep.iters % 20 == 0 and rep.rel_res <= tol and rep.rel_res_true <= tol * 1.0001
+    hist = S.history()
+    assert hist[rep.iters] <= tol
+    A = system.dense_A()
+    w_direct = np.linalg.solve(A, system.b)
+    assert np.linalg.norm(w - w_direct) <= 2 * np.linalg.cond(A) * tol * np.linalg.norm(w_direct)
+    S.close()
+
+
+def test_csr_mixed_rejections():
     p = inputs.make_csr(100, 40, 0.1, 0.1, seed=1)
     with pytest.raises(rs.RsError) as e:
-        rs.Solver(p.X, p.y, p.lam, tau=5, sketch="count", precision="mixed")
+        rs.Solver(p.X, p.y, p.lam, tau=5, sketch="count", precision="mixed", sparse_route="scatter")
     assert e.value.status == rs.RS_EUNSUPPORTED
+    with pytest.raises(rs.RsError) as e:
+        rs.Solver(p.X, p.y, p.lam, tau=5, sketch="count", precision="mixed", accel=(0.5, 1.5))
+    assert e.value.status == rs.RS_EUNSUPPORTED
+
+
+@pytest.mark.timeout(600)
+def test_csr_mixed_full_size_sampled():
+    """The sparse workload at full size in mixed precision, launched as the benchmark launches it
+    (CSR 100000 x 20000, count sketch tau = 500, default lookahead and pipeline): 48 sampled rows
+    of the 20th sketch's AS within the FP32 bound against the oracle's FP64 rows, and the
+    refreshed r^20, r^19 against the oracle's A x - b for the GPU's iterates within
+    4 gamma_n (|Z| (|Z^T| |x|) + lambda |x| + |b|)."""
+    p = inputs.sparse_csr()
+    system = ridge_system(p.X, p.y, p.lam, "primal")
+    print("[csr mixed full size] count tau=500", flush=True)
+    S = rs.Solver(p.X, p.y, p.lam, tau=500, sketch="count", tol=0.0, seed=1, precision="mixed")
+    S.step(20)
+    AS, _ = S.products()
+    x, xp, r, rp = S.state()
+    S.close()
+    sk = osk.draw("count", 1, 0, 19, system.m, 500)
+    rng = np.random.default_rng(5)
+    rows = np.sort(rng.choice(system.m, 48, replace=False))
+    Zr = system.Z[rows]
+    AS_o = np.asarray((Zr @ (system.Z.T @ sk.matrix())).todense()) + system.lam * sk.matrix().toarray()[rows]
+    bound = U_FP32 * np.abs(AS_o) + 1e-13 * np.abs(AS_o).max()
+    assert np.all(np.abs(AS[rows] - AS_o) <= bound)
+    Za = abs(system.Z)
+    n = system.Z.shape[1]
+    gamma = n * 2.0 ** -53 / (1 - n * 2.0 ** -53)
+    for xx, rr in ((x, r), (xp, rp)):
+        true = system.matvec(xx) - system.b
+        mag = Za @ (Za.T @ np.abs(xx)) + system.lam * np.abs(xx) + np.abs(system.b)
+        assert np.all(np.abs(rr - true) <= 4 * gamma * mag)
 
 
 @pytest.mark.parametrize("tau,kind", [(130, "subsample"), (300, "subsample"), (700, "subsample"),
