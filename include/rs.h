@@ -358,6 +358,24 @@ rs_status rs_features(const double* a, const double* r, const double* rp, const 
 rs_status rs_draw_weighted(const float* q, int64_t m, int32_t tau, uint64_t seed, uint64_t problem_id,
                            int64_t k, int32_t* C_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): rs_draw_weighted on device buffers,
+ * enqueued on `stream` (hipStream_t; NULL = the default stream), allocating nothing.
+ * q: device, m floats, every entry positive and finite; C_out: device, tau int32 (the tau
+ * smallest (u_j / q_j, j), ascending, bit-identical to rs_draw_weighted); status_out:
+ * device, one int32 that receives RS_OK, RS_EINVAL (an entry of q not positive and
+ * finite: C_out is not written) or RS_EDEVICE (an internal selection limit) when the
+ * stream reaches the end of this call's work. The selection's working memory is a fixed
+ * array of about 16 MB in device memory that each device holds from the first call until
+ * the process ends; every call on a device shares it and it keeps the last call's
+ * contents, so calls whose work overlaps on one device (several streams or threads)
+ * race and must be serialised by the caller. Returns RS_OK once the work is enqueued;
+ * RS_EINVAL for NULL pointers, tau outside [1, m], k < 0 or m > 2^20 (nothing is
+ * enqueued); RS_EDEVICE if a launch fails. */
+rs_status rs_draw_weighted_noalloc(const float* q, int64_t m, int32_t tau, uint64_t seed,
+                                   uint64_t problem_id, int64_t k, int32_t* C_out,
+                                   int32_t* status_out, void* stream);
+
 /* ------------------------------------------------------------------------
  * Batched solves: many ridge problems, each with a grid of regularisers and
  * several right-hand sides, in one lock-step iteration.

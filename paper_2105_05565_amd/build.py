@@ -15,7 +15,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "librs.so")
 SOURCES = ["k_sketch.hip", "k_dense.hip", "k_dense_bf16.hip", "k_sparse.hip", "k_sparse_a.hip", "k_chol.hip", "k_chol_multi.hip",
            "k_update.hip", "k_dense_sketch.hip", "k_batch.hip", "k_learned.hip", "rs_api.hip", "rs_batch.hip",
-           "rs_learned.hip"]
+           "rs_learned.hip", "rs_noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -160,6 +160,8 @@ SIGNATURES = {
     "rs_features": (ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_int64, _P]),
     "rs_draw_weighted": (ctypes.c_int32, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
                                           ctypes.c_uint64, ctypes.c_int64, _P]),
+    "rs_draw_weighted_noalloc": (ctypes.c_int32, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
+                                                  ctypes.c_uint64, ctypes.c_int64, _P, _P, _P]),
     "rs_batch_create": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(rs_problem),
                                          ctypes.POINTER(rs_options), ctypes.POINTER(_P)]),
     "rs_batch_step": (ctypes.c_int32, [_P, ctypes.c_int64]),
@@ -407,6 +409,19 @@ def rs_draw_weighted(q, tau, seed, problem_id, k):
     _check(load().rs_draw_weighted(_ptr(qv), qv.shape[0], int(tau), int(seed), int(problem_id), int(k), _ptr(C)),
            "rs_draw_weighted")
     return C
+
+
+def rs_draw_weighted_noalloc(q, tau, seed, problem_id, k, C_out, status_out, stream=None):
+    """Enqueue the weighted draw on device tensors (q: m float32, C_out: >= tau int32,
+    status_out: one int32); returns the entry point's status. Nothing is allocated."""
+    for t, dt in ((q, "float32"), (C_out, "int32"), (status_out, "int32")):
+        if not _is_device(t) or str(t.dtype) != f"torch.{dt}" or not t.is_contiguous():
+            raise ValueError("q, C_out and status_out must be contiguous device tensors "
+                             "(float32, int32, int32)")
+    if C_out.numel() < int(tau) or status_out.numel() < 1:
+        raise ValueError("C_out needs tau entries and status_out one")
+    return load().rs_draw_weighted_noalloc(_ptr(q), q.numel(), int(tau), int(seed), int(problem_id), int(k),
+                                           _ptr(C_out), _ptr(status_out), stream)
 
 
 class Trainer:
