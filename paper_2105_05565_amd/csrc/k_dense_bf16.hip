@@ -9,12 +9,12 @@
 // (r = Z (Z^T x) + lambda x - b for x^k and x^{k-1}).
 //
 // GEMM tiling (gfx950): 256 x 256 output tile per workgroup, 8 waves each owning a
-// 64 x 128 sub-tile (2 x 4 MFMA blocks of 32 x 32), K staged 32 at a time through a
-// four-stage LDS ring filled by direct-to-LDS loads (XOR-swizzled 64-byte rows). Tiles
-// are ordered so that the workgroups one XCD runs together share row strips of Z and
-// gathered column strips (workgroups are dispatched to the 8 XCDs round-robin). The
-// kernel is written for any even wave count; two 4-wave workgroups per CU (128 x 256
-// tiles, three stages each) measured 25-30% slower on the mixed workload.
+// 64 x 128 sub-tile (2 x 4 MFMA blocks of 32 x 32), K staged 64 at a time through two
+// LDS stages filled by direct-to-LDS loads (XOR-swizzled 128-byte rows). Tiles are
+// ordered so that the workgroups one XCD runs together share row strips of Z and
+// gathered column strips (workgroups are dispatched to the 8 XCDs round-robin).
+#include <algorithm>
+
 #include "dev_common.h"
 #include "rs_internal.h"
 
@@ -104,14 +104,13 @@ __device__ __forceinline__ void tile_of_block(const GemmArgs& a, int bid, int* r
 }
 
 // AS for a batch of subsample sketches: operand tiles move from global memory straight into
-// LDS (global_load_lds_dwordx4, 16 bytes per lane, no register staging), 32 deep in K per
-// stage and four LDS stages, so three stages of loads stay in flight while one is
-// multiplied. A DMA instruction fills 1 KB of LDS: 16 rows of 64 bytes, lane L taking
-// row L / 4 and 16-byte slot L % 4. The slot of a row's logical segment t is
-// t ^ ((row / 4) % 4), which keeps the 16 rows read by a quarter wave on distinct banks.
-// Rows outside the matrix load row 0 (their results are not stored).
-constexpr int kDmaBK = 32;                    // K elements per stage
-constexpr int kDmaRowBytes = kDmaBK * 2;      // 64
+// LDS (global_load_lds_dwordx4, 16 bytes per lane, no register staging), 64 deep in K per
+// stage, so that every row of a stage is one whole 128-byte line: the load path into a CU
+// moves about a third more bytes per cycle with whole-line requests than with the half lines
+// of 32-deep stages, and that rate, not the LDS reads, is what feeds the matrix cores. Two
+// stages of 64 KB: one is multiplied while the next one loads.
+constexpr int kDmaBK = 64;                    // K elements per stage
+constexpr int kDmaRowBytes = kDmaBK * 2;      // 128
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 
@@ -119,58 +118,51 @@ typedef __attribute__((address_space(3))) void lds_void_t;
 constexpr int waitcnt_imm(int n, int lgkm) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (lgkm << 8); }
 
 // AS for a batch of subsample sketches, one BM x 256 output tile per workgroup of WAVES
-// waves (BM = 32 WAVES; each wave owns 64 x 128 as 2 x 4 MFMA blocks of 32 x 32). Operand
-// rows (BM of Z, 256 gathered) move from global memory straight into LDS
-// (global_load_lds_dwordx4, 16 bytes per lane), 32 deep in K per stage, STAGES stages, so
-// STAGES - 1 stages of loads are in flight while one is multiplied. A DMA instruction fills
-// 1 KB: 16 rows of 64 bytes, lane L taking row L / 4 and slot L % 4; the slot of a row's
-// logical segment t is t ^ ((row / 4) % 4), which keeps the 16 rows read by a quarter wave
-// on distinct banks. Rows outside the matrix load row 0 (their results are not stored).
-template <int WAVES, int STAGES>
-__global__ __launch_bounds__(WAVES * 64, 2) void k_as_dense_bf16(GemmArgs a) {
+// waves (BM = 32 WAVES; each wave owns 64 x 128 as 2 x 4 MFMA blocks of 32 x 32, fed by
+// v_mfma_f32_32x32x16_bf16 with FP32 accumulation). Operand rows (BM of Z, 256 gathered
+// rows Z[C, :]) are staged 64 deep in K. A DMA instruction fills 1 KB: 8 rows of 128 bytes,
+// lane L taking row L / 8 and 16-byte slot L % 8; the slot holding a row's logical 16-byte
+// segment t is t ^ ((row / 2) % 8), which puts the 16 rows read by a quarter wave on distinct
+// banks. Rows outside the matrix load row 0 (their results are not stored). The K steps are
+// accumulated in ascending order, 16 at a time.
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64, 1) void k_as_dense_bf16(GemmArgs a) {
   constexpr int BM = 32 * WAVES, ROWS = BM + kBN;
-  constexpr int NQ = ROWS / (16 * WAVES);             // DMA instructions per wave and stage
+  constexpr int NQ = ROWS / (8 * WAVES);             // DMA instructions per wave and stage
   constexpr int STAGE_BYTES = ROWS * kDmaRowBytes;
-  constexpr int INFLIGHT = (STAGES - 2) * NQ;         // later stages' loads a wait leaves in flight
-  extern __shared__ __align__(16) unsigned char dsm[];  // [STAGES][ROWS][64 B]
-  __shared__ int64_t brow[kBN];
+  extern __shared__ __align__(16) unsigned char dsm[];  // [2][ROWS][128 B]
   if (*a.done) return;
   int rt, ct;
   tile_of_block(a, blockIdx.x, &rt, &ct);
   if (rt < 0) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t row0 = (int64_t)rt * BM, n0 = (int64_t)ct * kBN;
-  for (int c = tid; c < kBN; c += WAVES * 64) {
-    const int64_t n = n0 + c;
-    brow[c] = n < a.ntot ? (int64_t)a.members[n] : -1;
-  }
-  __syncthreads();
 
   // this lane's source rows for the wave's NQ DMA instructions of a stage
   const unsigned char* src[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    const int r = (wave * NQ + q) * 16 + (lane >> 2);  // tile row 0 .. ROWS - 1
+    const int r = (wave * NQ + q) * 8 + (lane >> 3);  // tile row 0 .. ROWS - 1
     int64_t g;
     if (r < BM) {
       g = row0 + r;
       if (g >= a.m) g = 0;
     } else {
-      g = brow[r - BM];
-      if (g < 0) g = 0;
+      const int64_t n = n0 + r - BM;
+      g = n < a.ntot ? (int64_t)a.members[n] : 0;
     }
-    const int t = (lane & 3) ^ ((r >> 2) & 3);  // logical 16-byte segment stored in this slot
+    const int t = (lane & 7) ^ ((r >> 1) & 7);  // logical 16-byte segment stored in this slot
     src[q] = reinterpret_cast<const unsigned char*>(a.Z + g * a.ldz) + t * 16;
   }
   const int64_t nk = a.kpad / kDmaBK;
-  auto stage = [&](int64_t kt) { return dsm + (size_t)(kt % STAGES) * STAGE_BYTES; };
+  auto stage = [&](int64_t kt) { return dsm + (size_t)(kt & 1) * STAGE_BYTES; };
   auto issue = [&](int64_t kt) {
     const int64_t ktl = kt < nk ? kt : nk - 1;  // past the end: reload the last stage
     unsigned char* dst = stage(kt);
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
       __builtin_amdgcn_global_load_lds((const void*)(src[q] + ktl * kDmaRowBytes),
-                                       (lds_void_t*)(dst + (wave * NQ + q) * 16 * kDmaRowBytes), 16, 0, 0);
+                                       (lds_void_t*)(dst + (wave * NQ + q) * 1024), 16, 0, 0);
   };
 
   const int wr = (wave >> 1) * 64, wc = (wave & 1) * 128;
@@ -183,18 +175,19 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_as_dense_bf16(GemmArgs a) {
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
   const int l32 = lane & 31, khi = lane >> 5;
 
-  // fragments of one 16-deep K step: rows of the A strip (2) and of the gathered B strip (4)
-  auto read_frags = [&](const unsigned char* st, int ks, bf16x8 (&av)[2], bf16x8 (&bv)[4]) {
-    const int t = (ks >> 3) + khi;
+  // fragments of K step s (16 deep) of a stage: rows of the A strip (2) and of the gathered B
+  // strip (4); lanes 0-31 take K 16 s .. 16 s + 7 of their row, lanes 32-63 the next eight
+  auto read_frags = [&](const unsigned char* st, int s, bf16x8 (&av)[2], bf16x8 (&bv)[4]) {
+    const int t = 2 * s + khi;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int r = wr + i * 32 + l32;
-      av[i] = *reinterpret_cast<const bf16x8*>(st + r * kDmaRowBytes + ((t ^ ((r >> 2) & 3)) << 4));
+      av[i] = *reinterpret_cast<const bf16x8*>(st + r * kDmaRowBytes + ((t ^ ((r >> 1) & 7)) << 4));
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int r = BM + wc + j * 32 + l32;
-      bv[j] = *reinterpret_cast<const bf16x8*>(st + r * kDmaRowBytes + ((t ^ ((r >> 2) & 3)) << 4));
+      bv[j] = *reinterpret_cast<const bf16x8*>(st + r * kDmaRowBytes + ((t ^ ((r >> 1) & 7)) << 4));
     }
   };
   auto mma = [&](const bf16x8 (&av)[2], const bf16x8 (&bv)[4]) {
@@ -205,41 +198,46 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_as_dense_bf16(GemmArgs a) {
         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
   };
 
-  // Stage kt holds K elements 32 kt .. 32 kt + 31 (two 16-deep steps). The fragments of a
-  // step are read while the MFMAs of the step before run; the barrier that hands over the
-  // next stage comes after this wave's reads of the current stage have landed, so that the
-  // refill issued right after it (into the current stage's buffer) cannot overtake them.
-#pragma unroll
-  for (int q = 0; q + 1 < STAGES; ++q) issue(q);
-  __builtin_amdgcn_s_waitcnt(waitcnt_imm(INFLIGHT, 15));  // stage 0 landed
+  // The fragments of each step are read while the MFMAs of the step before run. Stage kt + 1
+  // loads while stage kt is multiplied; the barrier that hands it over comes after this
+  // wave's reads of stage kt have landed, so that the refill issued right after it (into
+  // stage kt's buffer) cannot overtake them.
+  issue(0);
+  __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));  // stage 0 landed (own share), then every wave
   __builtin_amdgcn_s_barrier();
   __builtin_amdgcn_sched_barrier(0);
-  issue(STAGES - 1);
+  issue(1);
   bf16x8 a0[2], b0[4], a1[2], b1[4];
   read_frags(stage(0), 0, a0, b0);
-  // Enter the loop with no LDS or scalar-memory result pending (DMA loads stay in flight), so
-  // that the only LDS results pending at the loop head are those of the fragment reads and
-  // each wait for a fragment can leave the six newer reads in flight.
   __builtin_amdgcn_s_waitcnt(waitcnt_imm(63, 0));
   __builtin_amdgcn_sched_barrier(0);
-  // The body is the same on the last pass (its refill reloads the last stage and its reads
-  // of stage nk go unused), so that no branch joins in-flight LDS reads of different ages.
+  // The body is the same on the last pass (its refill reloads the last stage and its reads of
+  // stage nk go unused), so that no branch joins in-flight LDS reads of different ages.
   for (int64_t kt = 0; kt < nk; ++kt) {
-    read_frags(stage(kt), 16, a1, b1);
+    const unsigned char* st = stage(kt);
+    read_frags(st, 1, a1, b1);
     __builtin_amdgcn_sched_barrier(0);
     mma(a0, b0);
     __builtin_amdgcn_sched_barrier(0);
-    // this wave's reads of stage kt done, stage kt + 1 landed, then every wave
-    __builtin_amdgcn_s_waitcnt(waitcnt_imm(INFLIGHT, 0));
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(63, 0));
+    read_frags(st, 2, a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(63, 0));
+    read_frags(st, 3, a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    // step 3's fragments read and stage kt + 1 landed (own share), then every wave
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 0));
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_sched_barrier(0);
-    issue(kt + STAGES);  // into the buffer of stage kt, which no wave reads any more
+    issue(kt + 2);  // into stage kt's buffer, which no wave reads any more
     read_frags(stage(kt + 1), 0, a0, b0);
     __builtin_amdgcn_sched_barrier(0);
     mma(a1, b1);
     __builtin_amdgcn_sched_barrier(0);
-    // the reads of a0, b0 were issued before these eight MFMAs: waiting for them here (and not
-    // at the loop head, after the next reads are issued) keeps the next reads in flight
     __builtin_amdgcn_s_waitcnt(waitcnt_imm(63, 0));
   }
   // no DMA may still be writing this workgroup's LDS when it exits
@@ -258,40 +256,91 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_as_dense_bf16(GemmArgs a) {
         const int64_t n = n0 + col;
         if (row < a.m && n < a.ntot) {
           const int64_t slot = n / a.tau, c = n % a.tau;
+          const int64_t cj = a.members[n];
           float val = acc[i][j][v];
           if (a.lam_kernel)
-            val = (float)((double)val + a.lam * a.Zk[brow[col] * a.ldk + row]);
-          else if (row == brow[col])
+            val = (float)((double)val + a.lam * a.Zk[cj * a.ldk + row]);
+          else if (row == cj)
             val = (float)((double)val + a.lam);
           a.AS[(slot * a.m + row) * a.ldas + c] = val;
         }
       }
 }
 
-// Shape of the product launch: WAVES waves per workgroup, STAGES LDS stages.
-constexpr int kGemmWaves = 8, kGemmStages = 4;
+// Shape of the product launch: waves per workgroup (two LDS stages).
+constexpr int kGemmWaves = 8;
 
 constexpr int kRefreshSplit = 32;  // row ranges of Z summed separately in Z^T x
 
-// upart[js][k][0..1] = sum_{j in range js} Z[j][k] * (x[j], xp[j]) in FP64 (FP32 or FP64 data).
-template <typename T>
-__global__ void k_gemv_t_pair(const T* __restrict__ Z, int64_t ldz, int64_t m, int64_t K,
-                              const double* __restrict__ x, const double* __restrict__ xp,
-                              double* __restrict__ upart, const int32_t* __restrict__ done) {
+// V consecutive entries of a row of Z as FP64 (V = 4 FP32 or 2 FP64 entries: one 16-byte load;
+// V = 1: one entry).
+template <typename T, int V>
+__device__ __forceinline__ void load_row_vec(const T* __restrict__ p, double (&out)[V]) {
+  if constexpr (V == 1) {
+    out[0] = (double)p[0];
+  } else if constexpr (sizeof(T) == 4) {
+    static_assert(V == 4, "FP32 rows load four entries");
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    out[0] = v.x;
+    out[1] = v.y;
+    out[2] = v.z;
+    out[3] = v.w;
+  } else {
+    static_assert(V == 2, "FP64 rows load two entries");
+    const double2 v = *reinterpret_cast<const double2*>(p);
+    out[0] = v.x;
+    out[1] = v.y;
+  }
+}
+
+// upart[js][k][0..1] = sum_{j in range js} Z[j][k] * (x[j], xp[j]) in FP64 (FP32 or FP64 data),
+// rows in ascending order. Each thread owns V consecutive columns (ldz a multiple of V, so
+// its loads stay inside the row) and keeps four rows of loads in flight.
+template <typename T, int V>
+__global__ __launch_bounds__(256) void k_gemv_t_pair(const T* __restrict__ Z, int64_t ldz, int64_t m, int64_t K,
+                                                     const double* __restrict__ x, const double* __restrict__ xp,
+                                                     double* __restrict__ upart, const int32_t* __restrict__ done) {
   if (*done) return;
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= K) return;
+  const int64_t k0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * V;
+  if (k0 >= K) return;
   const int64_t per = (m + kRefreshSplit - 1) / kRefreshSplit;
   const int64_t j0 = min(m, (int64_t)blockIdx.y * per), j1 = min(m, j0 + per);
-  double s0 = 0.0, s1 = 0.0;
-  for (int64_t j = j0; j < j1; ++j) {
-    const double z = (double)Z[j * ldz + k];
-    s0 += z * x[j];
-    s1 += z * xp[j];
+  double s0[V], s1[V];
+#pragma unroll
+  for (int e = 0; e < V; ++e) s0[e] = s1[e] = 0.0;
+  const T* zp = Z + k0;
+  int64_t j = j0;
+  for (; j + 4 <= j1; j += 4) {
+    double z[4][V];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) load_row_vec<T, V>(zp + (j + u) * ldz, z[u]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double xj = x[j + u], xpj = xp[j + u];
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        s0[e] += z[u][e] * xj;
+        s1[e] += z[u][e] * xpj;
+      }
+    }
   }
-  double* out = upart + ((int64_t)blockIdx.y * K + k) * 2;
-  out[0] = s0;
-  out[1] = s1;
+  for (; j < j1; ++j) {
+    double z[V];
+    load_row_vec<T, V>(zp + j * ldz, z);
+    const double xj = x[j], xpj = xp[j];
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      s0[e] += z[e] * xj;
+      s1[e] += z[e] * xpj;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < V; ++e)
+    if (k0 + e < K) {
+      double* out = upart + ((int64_t)blockIdx.y * K + k0 + e) * 2;
+      out[0] = s0[e];
+      out[1] = s1[e];
+    }
 }
 
 // u[k] = sum over the row ranges in order.
@@ -305,37 +354,89 @@ __global__ void k_sum_upart(const double* __restrict__ upart, int64_t K, double*
   u[i] = s;
 }
 
-// r[j] = sum_k Z[j][k] u[k][0] + lam x[j] - b[j] (and likewise rp from u[k][1], xp);
-// kernel ridge (lam_u): the shift is lam u[j] = lam (K x)[j] (K = Z symmetric, m = K).
-// One wave per row; partial sums of ||r||^2 per workgroup.
-template <typename T>
-__global__ __launch_bounds__(256) void k_gemv_n_pair_residual(
+// The product Z u of the refresh in column chunks: part[c][j][0..1] = sum over the columns k
+// of chunk c of Z[j][k] (u[k][0], u[k][1]). A workgroup (8 waves, 8 rows each) stages the
+// chunk of u in LDS once for its 64 rows; lane l takes columns l V, l V + 64 V, ... of the
+// chunk (ldz a multiple of V; columns past K meet zeros of the staged u).
+constexpr int kNChunk = 2048;          // columns per chunk
+constexpr int kNRowsPerWave = 8;
+constexpr int kNWaves = 8;
+constexpr int kNRows = kNRowsPerWave * kNWaves;  // rows per workgroup
+
+template <typename T, int V>
+__global__ __launch_bounds__(kNWaves * 64) void k_gemv_n_pair_part(
     const T* __restrict__ Z, int64_t ldz, int64_t m, int64_t K, const double* __restrict__ u,
-    const double* __restrict__ x, const double* __restrict__ xp, const double* __restrict__ b,
-    double lam, int32_t lam_u, double* __restrict__ r, double* __restrict__ rp, double* __restrict__ partials,
-    const int32_t* __restrict__ done) {
+    double* __restrict__ part, const int32_t* __restrict__ done) {
+  __shared__ double2 us[kNChunk];
+  if (*done) return;
+  const int64_t kc0 = (int64_t)blockIdx.y * kNChunk;
+  const int kn = (int)min((int64_t)kNChunk, K - kc0);
+  for (int i = threadIdx.x; i < kNChunk; i += kNWaves * 64)
+    us[i] = i < kn ? reinterpret_cast<const double2*>(u)[kc0 + i] : make_double2(0.0, 0.0);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * kNRows + wave * kNRowsPerWave;
+  const T* zr[kNRowsPerWave];
+#pragma unroll
+  for (int r = 0; r < kNRowsPerWave; ++r) zr[r] = Z + min(r0 + r, m - 1) * ldz + kc0;  // rows past m: discarded
+  double s0[kNRowsPerWave], s1[kNRowsPerWave];
+#pragma unroll
+  for (int r = 0; r < kNRowsPerWave; ++r) s0[r] = s1[r] = 0.0;
+  for (int kk = lane * V; kk < kn; kk += 64 * V) {
+    double u0[V], u1[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      const double2 w = us[kk + e];
+      u0[e] = w.x;
+      u1[e] = w.y;
+    }
+#pragma unroll
+    for (int r = 0; r < kNRowsPerWave; ++r) {
+      double z[V];
+      load_row_vec<T, V>(zr[r] + kk, z);
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        s0[r] += z[e] * u0[e];
+        s1[r] += z[e] * u1[e];
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kNRowsPerWave; ++r) {
+    const double t0 = wave_sum(s0[r]), t1 = wave_sum(s1[r]);
+    if (lane == 0 && r0 + r < m) {
+      double* out = part + ((int64_t)blockIdx.y * m + r0 + r) * 2;
+      out[0] = t0;
+      out[1] = t1;
+    }
+  }
+}
+
+// r[j] = sum_c part[c][j][0] + lam x[j] - b[j] and rp[j] = sum_c part[c][j][1] + lam xp[j] - b[j]
+// (chunks in order); kernel ridge (lam_u): the shift is lam u[j] = lam (K x)[j]. Partial sums
+// of ||r||^2 per workgroup.
+__global__ __launch_bounds__(256) void k_gemv_n_finish(const double* __restrict__ part, int32_t nchunk, int64_t m,
+                                                       const double* __restrict__ u, const double* __restrict__ x,
+                                                       const double* __restrict__ xp, const double* __restrict__ b,
+                                                       double lam, int32_t lam_u, double* __restrict__ r,
+                                                       double* __restrict__ rp, double* __restrict__ partials,
+                                                       const int32_t* __restrict__ done) {
   __shared__ double scratch[16];
   if (*done) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t j = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double ss = 0.0;
   if (j < m) {
-    const T* zr = Z + j * ldz;
     double s0 = 0.0, s1 = 0.0;
-    for (int64_t k = lane; k < K; k += 64) {
-      const double z = (double)zr[k];
-      s0 += z * u[2 * k];
-      s1 += z * u[2 * k + 1];
+    for (int c = 0; c < nchunk; ++c) {
+      const double2 w = reinterpret_cast<const double2*>(part)[(int64_t)c * m + j];
+      s0 += w.x;
+      s1 += w.y;
     }
-    s0 = wave_sum(s0);
-    s1 = wave_sum(s1);
-    if (lane == 0) {
-      const double sx = lam_u ? u[2 * j] : x[j], sxp = lam_u ? u[2 * j + 1] : xp[j];
-      const double rn = s0 + lam * sx - b[j];
-      r[j] = rn;
-      rp[j] = s1 + lam * sxp - b[j];
-      ss = rn * rn;
-    }
+    const double sx = lam_u ? u[2 * j] : x[j], sxp = lam_u ? u[2 * j + 1] : xp[j];
+    const double rn = s0 + lam * sx - b[j];
+    r[j] = rn;
+    rp[j] = s1 + lam * sxp - b[j];
+    ss = rn * rn;
   }
   ss = block_sum(ss, scratch);
   if (threadIdx.x == 0) partials[blockIdx.x] = ss;
@@ -425,37 +526,72 @@ hipError_t launch_as_dense_bf16(const uint16_t* Zbf, int64_t ldz, int64_t m, int
   a.done = done;
   const int ntiles = a.n_row_tiles * a.n_col_tiles;
   const int per = (ntiles + kXcds - 1) / kXcds;
-  const size_t bytes = (size_t)kGemmStages * (BM + kBN) * kDmaRowBytes;
-  auto kern = k_as_dense_bf16<kGemmWaves, kGemmStages>;
+  const size_t bytes = (size_t)2 * (BM + kBN) * kDmaRowBytes;
+  auto kern = k_as_dense_bf16<kGemmWaves>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(per * kXcds), dim3(kGemmWaves * 64), bytes, s, a);
   return hipGetLastError();
 }
 
+namespace {
+
+// The FP64 products of a refresh: u = Z^T (x, xp) (row ranges, then their sum in order), then
+// r, rp = Z u + lam (x, xp) - b (lam_u: + lam u) with ||r||^2 partial sums. Returns the number
+// of partial sums written.
+hipError_t refresh_products(const void* Zr, int32_t z_f32, int64_t ldz, int64_t m, int64_t K, const double* x,
+                            const double* xp, const double* b, double lam, int32_t lam_u, double* r, double* rp,
+                            double* u, double* upart, double* partials, const int32_t* done, int32_t* nparts,
+                            hipStream_t s) {
+  if (lam_u && K != m) return hipErrorInvalidValue;
+  const bool vec = z_f32 ? (ldz % 4 == 0) : (ldz % 2 == 0);
+  const bool aligned = (reinterpret_cast<uintptr_t>(Zr) & 15) == 0;
+  const int V = !(vec && aligned) ? 1 : (z_f32 ? 4 : 2);
+  const dim3 gt((unsigned)((K + 256 * V - 1) / (256 * V)), kRefreshSplit);
+  if (z_f32 && V == 4)
+    hipLaunchKernelGGL((k_gemv_t_pair<float, 4>), gt, dim3(256), 0, s, (const float*)Zr, ldz, m, K, x, xp, upart, done);
+  else if (z_f32)
+    hipLaunchKernelGGL((k_gemv_t_pair<float, 1>), gt, dim3(256), 0, s, (const float*)Zr, ldz, m, K, x, xp, upart, done);
+  else if (V == 2)
+    hipLaunchKernelGGL((k_gemv_t_pair<double, 2>), gt, dim3(256), 0, s, (const double*)Zr, ldz, m, K, x, xp, upart,
+                       done);
+  else
+    hipLaunchKernelGGL((k_gemv_t_pair<double, 1>), gt, dim3(256), 0, s, (const double*)Zr, ldz, m, K, x, xp, upart,
+                       done);
+  hipLaunchKernelGGL(k_sum_upart, dim3((unsigned)((2 * K + 255) / 256)), dim3(256), 0, s, upart, K, u, done);
+  // the row ranges of upart have been summed into u: upart now holds the column-chunk partials
+  const int64_t nchunk = (K + kNChunk - 1) / kNChunk;
+  const dim3 gn((unsigned)((m + kNRows - 1) / kNRows), (unsigned)nchunk);
+  if (z_f32 && V == 4)
+    hipLaunchKernelGGL((k_gemv_n_pair_part<float, 4>), gn, dim3(kNWaves * 64), 0, s, (const float*)Zr, ldz, m, K, u,
+                       upart, done);
+  else if (z_f32)
+    hipLaunchKernelGGL((k_gemv_n_pair_part<float, 1>), gn, dim3(kNWaves * 64), 0, s, (const float*)Zr, ldz, m, K, u,
+                       upart, done);
+  else if (V == 2)
+    hipLaunchKernelGGL((k_gemv_n_pair_part<double, 2>), gn, dim3(kNWaves * 64), 0, s, (const double*)Zr, ldz, m, K,
+                       u, upart, done);
+  else
+    hipLaunchKernelGGL((k_gemv_n_pair_part<double, 1>), gn, dim3(kNWaves * 64), 0, s, (const double*)Zr, ldz, m, K,
+                       u, upart, done);
+  const unsigned nb = (unsigned)((m + 255) / 256);
+  hipLaunchKernelGGL(k_gemv_n_finish, dim3(nb), dim3(256), 0, s, upart, (int32_t)nchunk, m, u, x, xp, b, lam, lam_u,
+                     r, rp, partials, done);
+  *nparts = (int32_t)nb;
+  return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_refresh(const void* Zr, int32_t z_f32, int64_t ldz, int64_t m, int64_t K, const double* x,
                           const double* xp, const double* b, double lam, int32_t lam_u, double* r, double* rp,
                           double* u, double* upart, double* partials, DevFlags* flags, double* hist,
                           double* true_hist, int64_t k, double tol, const int32_t* done,
                           hipStream_t s) {
-  if (lam_u && K != m) return hipErrorInvalidValue;
-  const dim3 gt((unsigned)((K + 255) / 256), kRefreshSplit);
-  if (z_f32)
-    hipLaunchKernelGGL(k_gemv_t_pair<float>, gt, dim3(256), 0, s, (const float*)Zr, ldz, m, K, x, xp, upart, done);
-  else
-    hipLaunchKernelGGL(k_gemv_t_pair<double>, gt, dim3(256), 0, s, (const double*)Zr, ldz, m, K, x, xp, upart,
-                       done);
-  hipLaunchKernelGGL(k_sum_upart, dim3((unsigned)((2 * K + 255) / 256)), dim3(256), 0, s, upart, K, u,
-                     done);
-  const unsigned nb = (unsigned)((m + 3) / 4);
-  if (z_f32)
-    hipLaunchKernelGGL(k_gemv_n_pair_residual<float>, dim3(nb), dim3(256), 0, s, (const float*)Zr, ldz, m, K, u, x,
-                       xp, b, lam, lam_u, r, rp, partials, done);
-  else
-    hipLaunchKernelGGL(k_gemv_n_pair_residual<double>, dim3(nb), dim3(256), 0, s, (const double*)Zr, ldz, m, K, u,
-                       x, xp, b, lam, lam_u, r, rp, partials, done);
-  hipLaunchKernelGGL(k_refresh_norm, dim3(1), dim3(256), 0, s, partials, (int32_t)nb, flags, hist,
-                     true_hist, k, tol);
+  int32_t np = 0;
+  hipError_t e = refresh_products(Zr, z_f32, ldz, m, K, x, xp, b, lam, lam_u, r, rp, u, upart, partials, done, &np, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_refresh_norm, dim3(1), dim3(256), 0, s, partials, np, flags, hist, true_hist, k, tol);
   return hipGetLastError();
 }
 
@@ -468,24 +604,12 @@ hipError_t launch_refresh_norm(const double* partials, int32_t n, DevFlags* flag
 hipError_t launch_true_residual(const void* Zr, int32_t z_f32, int64_t ldz, int64_t m, int64_t K, const double* x,
                                 const double* b, double lam, int32_t lam_u, double* u, double* upart, double* r2,
                                 double* partials, const int32_t* zero, hipStream_t s) {
-  if (lam_u && K != m) return hipErrorInvalidValue;
-  const dim3 gt((unsigned)((K + 255) / 256), kRefreshSplit);
-  if (z_f32)
-    hipLaunchKernelGGL(k_gemv_t_pair<float>, gt, dim3(256), 0, s, (const float*)Zr, ldz, m, K, x, x, upart, zero);
-  else
-    hipLaunchKernelGGL(k_gemv_t_pair<double>, gt, dim3(256), 0, s, (const double*)Zr, ldz, m, K, x, x, upart, zero);
-  hipLaunchKernelGGL(k_sum_upart, dim3((unsigned)((2 * K + 255) / 256)), dim3(256), 0, s, upart, K, u, zero);
-  const unsigned nb = (unsigned)((m + 3) / 4);
-  if (z_f32)
-    hipLaunchKernelGGL(k_gemv_n_pair_residual<float>, dim3(nb), dim3(256), 0, s, (const float*)Zr, ldz, m, K, u, x,
-                       x, b, lam, lam_u, r2, r2 + m, partials, zero);
-  else
-    hipLaunchKernelGGL(k_gemv_n_pair_residual<double>, dim3(nb), dim3(256), 0, s, (const double*)Zr, ldz, m, K, u,
-                       x, x, b, lam, lam_u, r2, r2 + m, partials, zero);
-  return hipGetLastError();
+  int32_t np = 0;
+  return refresh_products(Zr, z_f32, ldz, m, K, x, x, b, lam, lam_u, r2, r2 + m, u, upart, partials, zero, &np, s);
 }
 
-int64_t refresh_partials(int64_t m) { return (m + 3) / 4; }
+// partial sums written by a refresh (at most)
+int64_t refresh_partials(int64_t m) { return (m + 255) / 256; }
 
 hipError_t launch_gemv_cols_f32(const float* Z, int64_t ldz, int64_t m, int64_t K, const double* v,
                                 double* out, hipStream_t s) {
@@ -500,6 +624,9 @@ hipError_t launch_gemv_rows_f32(const float* Z, int64_t ldz, int64_t m, int64_t 
                      out);
   return hipGetLastError();
 }
-int64_t refresh_upart_doubles(int64_t K) { return (int64_t)kRefreshSplit * 2 * K; }
+// the row-range partials of Z^T x, then the column-chunk partials of Z u, in one buffer
+int64_t refresh_upart_doubles(int64_t m, int64_t K) {
+  return std::max<int64_t>((int64_t)kRefreshSplit * 2 * K, 2 * m * ((K + kNChunk - 1) / kNChunk));
+}
 
 }  // namespace rs

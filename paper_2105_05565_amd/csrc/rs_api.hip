@@ -55,6 +55,7 @@ struct rs_handle {
   uint16_t* Zbf = nullptr;
   int64_t kpad = 0;
   float* Z32 = nullptr;
+  int64_t ld32 = 0;           // row stride of Z32: K rounded up to 4 (zero padding), for 16-byte loads
   double* ref_u = nullptr;
   double* ref_upart = nullptr;
   double* ref_partials = nullptr;
@@ -271,7 +272,7 @@ void refresh(rs_handle* h, int64_t k) {
   }
   // kernel ridge refreshes from the FP64 kernel matrix, dense ridge from the FP32 copy of X
   const void* Zr = h->kern ? (const void*)h->Z : (const void*)h->Z32;
-  const int64_t ldr = h->kern ? h->ldz : h->K;
+  const int64_t ldr = h->kern ? h->ldz : h->ld32;
   check_hip(launch_refresh(Zr, h->kern ? 0 : 1, ldr, h->m, h->K, h->xbuf[k & 1], h->xbuf[(k + 1) & 1], h->b,
                            h->lam, h->kern ? 1 : 0, h->rbuf[k & 1], h->rbuf[(k + 1) & 1], h->ref_u, h->ref_upart,
                            h->ref_partials, h->flags, h->hist, h->true_hist, k, h->opt.tol,
@@ -300,7 +301,7 @@ double true_rel_res(rs_handle* h) {
   } else {
     const bool f32 = h->mixed && !h->kern;
     const void* Zr = f32 ? (const void*)h->Z32 : (const void*)h->Z;
-    const int64_t ldr = f32 ? h->K : h->ldz;
+    const int64_t ldr = f32 ? h->ld32 : h->ldz;
     check_hip(launch_true_residual(Zr, f32 ? 1 : 0, ldr, m, h->K, x, h->b, h->lam, h->kern ? 1 : 0, h->tr_u,
                                    h->tr_upart, h->tr_r, h->tr_part, h->tr_zero, s),
               "true residual");
@@ -908,7 +909,7 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
           h->Zbf = dalloc<uint16_t>(h, (size_t)h->m * h->kpad);
           check_hip(launch_cast_bf16(h->Z, 0, n, n, n, 0, h->Zbf, h->kpad, nullptr, 0, s), "BF16 copy");
           h->ref_u = dalloc<double>(h, 2 * h->K);
-          h->ref_upart = dalloc<double>(h, refresh_upart_doubles(h->K));
+          h->ref_upart = dalloc<double>(h, refresh_upart_doubles(h->m, h->K));
           h->ref_partials = dalloc<double>(h, refresh_partials(h->m));
         }
         check_hip(hipStreamSynchronize(s), "sync");
@@ -919,17 +920,18 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
       } else if (h->mixed) {
         h->kpad = (h->K + 63) / 64 * 64;
         h->Zbf = dalloc<uint16_t>(h, (size_t)h->m * h->kpad);
-        h->Z32 = dalloc<float>(h, (size_t)h->m * h->K);
+        h->ld32 = (h->K + 3) / 4 * 4;
+        h->Z32 = dalloc<float>(h, (size_t)h->m * h->ld32);
         const int64_t rows = rowmajor ? n : d, cols = rowmajor ? d : n;
         check_hip(launch_cast_bf16(xv, f32, rows, cols, cols, need_transpose ? 1 : 0, h->Zbf, h->kpad,
-                                   h->Z32, h->K, s),
+                                   h->Z32, h->ld32, s),
                   "BF16 copy");
         if (h->form == RS_FORM_PRIMAL)
-          check_hip(launch_gemv_rows_f32(h->Z32, h->K, h->m, h->K, yd, h->b, s), "b = X^T y");
+          check_hip(launch_gemv_rows_f32(h->Z32, h->ld32, h->m, h->K, yd, h->b, s), "b = X^T y");
         else
           check_hip(hipMemcpyAsync(h->b, yd, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "b = y");
         h->ref_u = dalloc<double>(h, 2 * h->K);
-        h->ref_upart = dalloc<double>(h, refresh_upart_doubles(h->K));
+        h->ref_upart = dalloc<double>(h, refresh_upart_doubles(h->m, h->K));
         h->ref_partials = dalloc<double>(h, refresh_partials(h->m));
         check_hip(hipStreamSynchronize(s), "sync");
         (void)hipFree(xv);
@@ -1090,7 +1092,7 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
     h->npart = update_partials(h->m, h->tau);
     h->partials = dalloc<double>(h, h->npart);
     h->tr_u = dalloc<double>(h, 2 * h->K);
-    if (!h->sparse) h->tr_upart = dalloc<double>(h, refresh_upart_doubles(h->K));
+    if (!h->sparse) h->tr_upart = dalloc<double>(h, refresh_upart_doubles(h->m, h->K));
     h->tr_r = dalloc<double>(h, 2 * h->m);
     h->tr_part = dalloc<double>(h, refresh_partials(h->m));
     h->tr_zero = dalloc<int32_t>(h, 1);
@@ -1138,7 +1140,7 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
       h->q = dalloc<float>(h, h->m);
       h->q_ok = dalloc<int32_t>(h, 1);
       if (h->mixed)
-        check_hip(launch_adiag(h->Z32, 1, h->K, h->m, h->K, h->lam, h->adiag, h->lstats, s), "A_jj");
+        check_hip(launch_adiag(h->Z32, 1, h->ld32, h->m, h->K, h->lam, h->adiag, h->lstats, s), "A_jj");
       else
         check_hip(launch_adiag(h->Z, 0, h->ldz, h->m, h->K, h->lam, h->adiag, h->lstats, s), "A_jj");
       check_hip(hipMemsetAsync(h->last, 0xFF, sizeof(int32_t) * h->m, s), "memset");  // -1: never sampled
@@ -1298,7 +1300,7 @@ rs_status rs_get_weights(rs_handle* h, double* w_out) {
       check_hip(hipMalloc(&wd, sizeof(double) * h->d), "alloc");
       hipError_t e = h->sparse ? launch_spmv_csr(h->zt_ptr, h->zt_col, h->zt_val, h->vals_f32, h->d, x, wd,
                                                  h->stream)
-                     : h->mixed ? launch_gemv_cols_f32(h->Z32, h->K, h->m, h->K, x, wd, h->stream)
+                     : h->mixed ? launch_gemv_cols_f32(h->Z32, h->ld32, h->m, h->K, x, wd, h->stream)
                                 : launch_gemv_cols(h->Z, h->ldz, h->m, h->K, x, wd, h->stream);
       if (e == hipSuccess)
         e = hipMemcpyAsync(w_out, wd, sizeof(double) * h->d, hipMemcpyDeviceToHost, h->stream);

@@ -267,7 +267,7 @@ hipError_t launch_as_dense_bf16(const uint16_t* Zbf, int64_t ldz, int64_t m, int
 // FP64 recomputation r = Z (Z^T x) + lambda x - b (and rp from xp) from the FP32 copy;
 // records ||r|| / ||r^0|| at k and applies the stop test.
 int64_t refresh_partials(int64_t m);
-int64_t refresh_upart_doubles(int64_t K);
+int64_t refresh_upart_doubles(int64_t m, int64_t K);
 // AS[slot][row][c] = A[row][members[slot][c]] from a formed A (m x m, row stride lda, FP32 when
 // f32 else FP64; AS in the same type), members with row stride nsel.
 hipError_t launch_gram_gather(const void* A, int32_t f32, int64_t lda, int64_t m, const int32_t* members,
