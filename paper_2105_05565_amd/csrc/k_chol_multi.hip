@@ -4,16 +4,18 @@
 // The single-workgroup factorisation (k_chol.hip) runs one sketch per compute unit,
 // which leaves most of the chip idle when a batch holds few sketches. Here every
 // 64 x 64 tile of every sketch is a workgroup, and the sequential structure of a
-// left-looking algorithm is carried by kernel boundaries on the stream; every output tile is
-// accumulated in MFMA registers over its chain of tile products and written once (a
-// right-looking update would read and write the whole trailing matrix at every step):
+// right-looking algorithm is carried by kernel boundaries on the stream: the diagonal
+// factorisation of step j never waits for a chain of tile products, because the trailing
+// update of step j - 1 (one tile product per workgroup, all tiles at once) has already
+// brought G_jj up to date:
 //
 //   assemble               G (gathered rows of AS for the subsample sketch), identity
 //                          padding and empty buckets; U <- 0
 //   for j = 0 .. nt-1:
-//     ll_diag(j)           D = G_jj - sum_{k<j} L_jk L_jk^T factored in LDS; X_jj = L_jj^{-1}
-//                          stored, and U_jj = X_jj^T
-//     ll_panel(j)          L_ij = (G_ij - sum_{k<j} L_ik L_jk^T) X_jj^T for i > j, over G_ij
+//     diag(j)              G_jj = L_jj L_jj^T factored in LDS; X_jj = L_jj^{-1} stored,
+//                          and U_jj = X_jj^T
+//     panel(j)             L_ij = G_ij X_jj^T for i > j, over G_ij
+//     trail(j)             G_il -= L_ij L_lj^T for j < l <= i
 //   for d = 1 .. nt-1:
 //     ll_inverse(d)        W = L^{-1} by distance d = i - j: W_ij = -X_ii sum_{k=j}^{i-1} L_ik W_kj,
 //                          stored transposed as U_ji (U = L^{-T}, so W_kj = U_jk^T)
@@ -86,7 +88,9 @@ __device__ __forceinline__ void lower_pair(int idx, int lo, int* i, int* j) {
   *j = lo + idx;
 }
 
-__global__ __launch_bounds__(kThreads) void k_chol_ll_diag(MultiArgs a, int j) {
+// Step j's diagonal tile (already updated by the trailing updates of steps < j) factored in
+// LDS: X_jj = L_jj^{-1} kept for the panel and the inverse, U_jj = X_jj^T.
+__global__ __launch_bounds__(kThreads) void k_chol_diag(MultiArgs a, int j) {
   extern __shared__ __align__(16) double lds[];
   double* ta = lds;
   double* td = lds + NB * LDT;
@@ -97,12 +101,7 @@ __global__ __launch_bounds__(kThreads) void k_chol_ll_diag(MultiArgs a, int j) {
   double* G = a.G + slot * a.ldg * a.ldg;
   double* U = a.U + slot * a.ldg * a.ldg;
   if (threadIdx.x == 0) bad = 0;
-  Acc c;
-  acc_zero(c);
-  for (int k = 0; k < j; ++k) tile_mma_global(c, tile(G, a.ldg, j, k), tile(G, a.ldg, j, k), a.ldg);
   load_tile(td, tile(G, a.ldg, j, j), a.ldg, false);
-  __syncthreads();
-  acc_for_each(c, [&](int r, int cc, double v) { td[r * LDT + cc] -= v; });
   __syncthreads();
   factor_diag_tile(td, ta, col, &bad);
   double* Ujj = tile(U, a.ldg, j, j);
@@ -115,7 +114,8 @@ __global__ __launch_bounds__(kThreads) void k_chol_ll_diag(MultiArgs a, int j) {
   if (threadIdx.x == 0 && bad) a.status[slot] = 1;
 }
 
-__global__ __launch_bounds__(kThreads) void k_chol_ll_panel(MultiArgs a, int j) {
+// L_ij = G_ij X_jj^T for the tiles i > j of column j (G_ij already updated), over G_ij.
+__global__ __launch_bounds__(kThreads) void k_chol_panel(MultiArgs a, int j) {
   extern __shared__ __align__(16) double lds[];
   double* tp = lds;
   double* tx = lds + NB * LDT;
@@ -123,19 +123,29 @@ __global__ __launch_bounds__(kThreads) void k_chol_ll_panel(MultiArgs a, int j) 
   const int64_t slot = blockIdx.y;
   const int i = j + 1 + (int)blockIdx.x;
   double* G = a.G + slot * a.ldg * a.ldg;
-  Acc c;
-  acc_zero(c);
-  for (int k = 0; k < j; ++k) tile_mma_global(c, tile(G, a.ldg, i, k), tile(G, a.ldg, j, k), a.ldg);
   double* Gij = tile(G, a.ldg, i, j);
   load_tile(tp, Gij, a.ldg, false);
   load_tile(tx, a.X + (slot * a.nt + j) * NB * NB, NB, false);
   __syncthreads();
-  acc_for_each(c, [&](int r, int cc, double v) { tp[r * LDT + cc] -= v; });
-  __syncthreads();
-  Acc c2;
-  acc_zero(c2);
-  tile_mma(c2, tp, tx);  // P X_jj^T
-  acc_for_each(c2, [&](int r, int cc, double v) { Gij[(int64_t)r * a.ldg + cc] = v; });
+  Acc c;
+  acc_zero(c);
+  tile_mma(c, tp, tx);  // G_ij X_jj^T
+  acc_for_each(c, [&](int r, int cc, double v) { Gij[(int64_t)r * a.ldg + cc] = v; });
+}
+
+// Trailing update of step j: G_il -= L_ij L_lj^T for every j < l <= i < nt, one tile per
+// workgroup (each element read and written by one lane).
+__global__ __launch_bounds__(kThreads) void k_chol_trail(MultiArgs a, int j) {
+  if (*a.done) return;
+  const int64_t slot = blockIdx.y;
+  int i, l;
+  lower_pair(blockIdx.x, j + 1, &i, &l);
+  double* G = a.G + slot * a.ldg * a.ldg;
+  Acc c;
+  acc_zero(c);
+  tile_mma_global(c, tile(G, a.ldg, i, j), tile(G, a.ldg, l, j), a.ldg);
+  double* Gil = tile(G, a.ldg, i, l);
+  acc_for_each(c, [&](int r, int cc, double v) { Gil[(int64_t)r * a.ldg + cc] -= v; });
 }
 
 __global__ __launch_bounds__(kThreads) void k_chol_ll_inverse(MultiArgs a, int d) {
@@ -193,10 +203,10 @@ hipError_t launch_chol_multi(double* G, double* U, double* X, int64_t ldg, int32
   const int nt = a.nt;
   const size_t diag_bytes = sizeof(double) * (3 * NB * LDT + NB);
   const size_t pair_bytes = sizeof(double) * 2 * NB * LDT;
-  hipError_t e = hipFuncSetAttribute((const void*)k_chol_ll_diag, hipFuncAttributeMaxDynamicSharedMemorySize,
+  hipError_t e = hipFuncSetAttribute((const void*)k_chol_diag, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)diag_bytes);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_chol_ll_panel, hipFuncAttributeMaxDynamicSharedMemorySize,
+    e = hipFuncSetAttribute((const void*)k_chol_panel, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)pair_bytes);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_chol_ll_inverse, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -204,9 +214,12 @@ hipError_t launch_chol_multi(double* G, double* U, double* X, int64_t ldg, int32
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_chol_assemble, dim3(nt, nt, nslots), dim3(kThreads), 0, s, a);
   for (int j = 0; j < nt; ++j) {
-    hipLaunchKernelGGL(k_chol_ll_diag, dim3(nslots), dim3(kThreads), diag_bytes, s, a, j);
-    if (nt - j - 1 > 0)
-      hipLaunchKernelGGL(k_chol_ll_panel, dim3(nt - j - 1, nslots), dim3(kThreads), pair_bytes, s, a, j);
+    hipLaunchKernelGGL(k_chol_diag, dim3(nslots), dim3(kThreads), diag_bytes, s, a, j);
+    const int below = nt - j - 1;
+    if (below > 0) {
+      hipLaunchKernelGGL(k_chol_panel, dim3(below, nslots), dim3(kThreads), pair_bytes, s, a, j);
+      hipLaunchKernelGGL(k_chol_trail, dim3(below * (below + 1) / 2, nslots), dim3(kThreads), 0, s, a, j);
+    }
   }
   for (int d = 1; d < nt; ++d)
     hipLaunchKernelGGL(k_chol_ll_inverse, dim3(nt - d, nslots), dim3(kThreads), pair_bytes, s, a, d);
