@@ -247,8 +247,9 @@ def main_batched(args):
     probs = inputs.batched(scale=args.scale, cap_factor=args.cap_factor)
     stream = torch.cuda.current_stream().cuda_stream
     t0 = time.perf_counter()
+    mixed = args.batch_precision == "mixed"
     B = rs.Batch(probs, tol=1e-6, seed=1, autotune=True, stream=stream, max_iter=args.max_iter,
-                 momentum=args.momentum)
+                 momentum=args.momentum, precision=args.batch_precision)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     tune = B.tuning()
@@ -280,14 +281,16 @@ def main_batched(args):
     solve_iters = int(sum(int(v.sum()) for v in slot_iters))
     dense_flops = sum(batch_weights(pr) for pr in probs if pr["kind"] == "dense")
     T = total / args.steps
-    roofline = {"kernel": "k_as_dense_f64_tab", "bound": "mfma", "achieved": None, "peak": FP64_PEAK_TFS,
+    peak = BF16_PEAK_TFS if mixed else FP64_PEAK_TFS
+    roofline = {"kernel": "k_as_dense_bf16_tab" if mixed else "k_as_dense_f64_tab", "bound": "mfma",
+                "achieved": None, "peak": peak,
                 "unit": "TFLOP/s", "frac": None, "traffic": None,
                 "alg_flops_per_launch": dense_flops, "avg_launch_ms": tune["dense_ms"],
                 "note": "launch duration timed with HIP events by the tuner on the first iteration "
                         "(every problem active)"}
     if tune["dense_ms"] > 0:
         tfs = dense_flops / (tune["dense_ms"] * 1e-3) / 1e12
-        roofline.update({"achieved": round(tfs, 2), "frac": round(tfs / FP64_PEAK_TFS, 4)})
+        roofline.update({"achieved": round(tfs, 2), "frac": round(tfs / peak, 4)})
 
     # converged fraction and median stop iteration per lambda (slot j = l * nrhs + q)
     nl = len(probs[0]["lambdas"])
@@ -299,6 +302,21 @@ def main_batched(args):
         per_lambda.append({"lambda": float(probs[0]["lambdas"][l]), "converged_fraction": round(float(conv_l.mean()), 4),
                            "median_stop_iteration": float(np.median(stops[conv_l])) if conv_l.any() else None})
     B.close()
+
+    fp64_batch = None
+    if mixed:
+        # the same batch with FP64 products (and no refresh), one solve of the first timed seed
+        print("[bench] the FP64 batch, one solve", file=sys.stderr, flush=True)
+        F = rs.Batch(probs, tol=1e-6, seed=1, autotune=True, stream=stream, max_iter=args.max_iter,
+                     momentum=args.momentum)
+        torch.cuda.synchronize()
+        ti = time.perf_counter()
+        st_f, rep_f = F.solve()
+        torch.cuda.synchronize()
+        fp64_batch = {"seconds": round(time.perf_counter() - ti, 3), "lock_step_iters": rep_f.iters,
+                      "converged_fraction": round(rep_f.converged / rep_f.solves, 4), "seed": 1,
+                      "mixed_seconds_same_seed": round(times[0], 3)}
+        F.close()
 
     # the plain FP64 single-solve path: full solves (to 1e-6 or the problem's cap) of a stratified
     # subset -- 8 problems spread over the per-iteration work (4 dense, 4 CSR), 4 lambdas each,
@@ -334,9 +352,10 @@ def main_batched(args):
     out = {
         "metric": "time-to-rel-residual 1e-6", "value": round(T, 4), "unit": "s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(T * 1e3, 1),
-        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "bf16" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": wl["name"], "problems": len(probs), "lambdas": 16, "rhs": 4,
+                   "precision": args.batch_precision, "refresh_every": 20 if mixed else None,
                    "solves": n_solves, "dense": sum(pr["kind"] == "dense" for pr in probs),
                    "tau_rule": "64 round(m^(2/3) / 64) clamped to [64, 512]", "cap": f"{args.cap_factor:g} m / tau",
                    "tol": 1e-6, "momentum": args.momentum, "graph_iters": tune["graph_iters"]},
@@ -349,6 +368,7 @@ def main_batched(args):
         "tuning": tune,
         "roofline": roofline,
         "per_lambda": per_lambda,
+        "fp64_batch": fp64_batch,
         "plain_fp64_single_solves": {
             "value": round(plain, 1), "unit": "s",
             "sample": (f"{len(full)} full single solves (to 1e-6 or the cap) of a stratified subset: problems "
@@ -725,6 +745,9 @@ def main():
     ap.add_argument("--dense-route", default="products", choices=["products", "gram"],
                     help="subsample sketch on dense data: per-sketch MFMA products, or A formed once "
                          "at creation and its columns gathered per sketch")
+    ap.add_argument("--batch-precision", default="mixed", choices=["mixed", "fp64"],
+                    help="batched workload: BF16 products for the dense problems with an FP64 refresh every "
+                         "20 iterations (then one FP64 batch solve is timed beside it), or FP64 throughout")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device-to-device copy of 1 GiB five times (the known-size "
                          "reference for HBM traffic counters)")

@@ -393,9 +393,14 @@ rs_status rs_draw_weighted_noalloc(const float* q, int64_t m, int32_t tau, uint6
  * sequence is captured once into a HIP graph (rs_options.graph_iters iterations per
  * graph) and replayed; with rs_options.autotune the launch shapes of the
  * iterate-independent kernels are timed on the batch's own tables and the fastest kept.
- * Batched solves run in FP64 with the subsample sketch for dense X and the count
- * sketch for CSR X. Options used: momentum parameters, tol, max_iter (upper bound of
- * every cap), seed, problem_id, stream, graph_iters, autotune.
+ * Batched solves use the subsample sketch for dense X and the count sketch for CSR X.
+ * precision RS_PREC_FP64: FP64 throughout. RS_PREC_MIXED_BF16: the dense problems' products
+ * B S come from a BF16 copy of Z with FP32 accumulation (stored FP64); after the update of
+ * every iteration k with (k + 1) % refresh_every == 0 (default 20) their R^{k+1} and R^k are
+ * recomputed in FP64 from the FP64 data (R = Z (Z^T X) + X diag(lambda) - B), and their slots
+ * may stop only at such an iteration; the CSR problems keep FP64 products (their stop test is
+ * unchanged). Options used: precision, refresh_every, momentum parameters, tol, max_iter
+ * (upper bound of every cap), seed, problem_id, stream, graph_iters, autotune.
  * ------------------------------------------------------------------------ */
 typedef struct rs_problem {
   rs_matrix X;              /* as for rs_create; X.mem also applies to y */
@@ -425,18 +430,19 @@ typedef struct rs_batch_problem_info_t {
 
 typedef struct rs_tuning {
   int32_t tuned;            /* 1 when the shapes below were chosen by timing */
-  int32_t dense_tk;         /* K-panel depth of the dense product tiles (128 x 128 tiles; 16) */
+  int32_t dense_tk;         /* K-panel depth of the FP64 dense product tiles (128 x 128 tiles; 16) */
   int32_t dense_wg_per_cu, sparse_wg_per_cu, chol_wg_per_cu;  /* persistent grid sizes */
   int32_t graph_iters;      /* iterations per graph replay */
   int32_t compute_units;
-  double dense_ms, sparse_ms, chol_ms;  /* best timed launch (ms), -1 if not timed */
+  double dense_ms, sparse_ms, chol_ms;  /* best timed launch (ms), -1 if not timed (mixed precision:
+                                          dense_ms times the BF16 product launch) */
 } rs_tuning;
 
 typedef struct rs_batch rs_batch;
 
 /* Build a batch of `count` problems (host array). Copies every X and y into library
  * layouts, forms b, sets the initial states. Errors: RS_EINVAL (shapes, tau, lambdas,
- * nrhs, non-finite y), RS_EUNSUPPORTED (precision other than FP64, sketch/layout pair),
+ * nrhs, non-finite y, unknown precision), RS_EUNSUPPORTED (sketch/layout pair, dense_route),
  * RS_ENOMEM, RS_EDEVICE. rs_batch_last_error(NULL) describes a failure. */
 rs_status rs_batch_create(int32_t count, const rs_problem* problems, const rs_options* o,
                           rs_batch** out);

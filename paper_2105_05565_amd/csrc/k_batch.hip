@@ -225,13 +225,119 @@ __global__ __launch_bounds__(64) void k_bfinal(const BState* __restrict__ S,
     for (int t = 0; t < st.ntiles; ++t) s += st.partials[(int64_t)t * st.J + j];
     const double rel = sqrt(s) / st.r0n[j];
     st.rel[j] = rel;
-    if (rel <= tol) st.stop_k[j] = k + 1;
+    // mixed precision: only a refreshed (FP64) residual may stop a slot
+    const bool may_stop = st.refresh == 0 || (k + 1) % st.refresh == 0;
+    if (rel <= tol && may_stop) st.stop_k[j] = k + 1;
     else running = 1;
   }
   const int any = __syncthreads_or(running);
   if (j == 0 && (!any || k + 1 >= st.cap)) {
     *st.iters = k + 1;
     *st.inactive = 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 refresh of a mixed-precision problem's residuals after the update of iteration k when
+// (k + 1) is a multiple of its refresh interval: for the iterates X^{k+1} (h = 0) and X^k
+// (h = 1), U_h = Z^T X_h (K x J), then R_h = Z U_h + X_h diag(lambda_j) - B. Both are FP64
+// MFMA tile products over 64 x 64 tiles staged in LDS (contraction in ascending order); the
+// squares of the refreshed R^{k+1} are summed per 64-row tile for the stop test. Slots that
+// have stopped keep their carried residual.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool refresh_due(const BState& st, int64_t k) {
+  return st.refresh > 0 && (k + 1) % st.refresh == 0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_bref_u(const BState* __restrict__ S, const int32_t* __restrict__ items,
+                                                     int32_t nitems, const BGlobal* __restrict__ g) {
+  extern __shared__ __align__(16) double lds[];
+  double* ta = lds;             // Z^T tile [64 columns of K][64 rows of Z]
+  double* tb = lds + NB * LDT;  // X^T tile [64 slots][64 rows of Z]
+  if (g->done) return;
+  const int64_t k = g->k;
+  const int tid = threadIdx.x;
+  for (int32_t t = blockIdx.x; t < nitems; t += gridDim.x) {
+    const BState& st = S[items[3 * t]];
+    if (*st.inactive || !refresh_due(st, k)) continue;  // uniform across the workgroup
+    const int64_t kk0 = (int64_t)items[3 * t + 1] * NB;
+    const int h = items[3 * t + 2];
+    const int nxt = (int)((k + 1) & 1);
+    const double* X = st.x[h == 0 ? nxt : (nxt ^ 1)];
+    const int64_t m = st.m, K = st.K, ldz = st.ldz;
+    const int J = st.J;
+    Acc c;
+    chol::acc_zero(c);
+    for (int64_t i0 = 0; i0 < m; i0 += NB) {
+      for (int e = tid; e < NB * NB; e += kThreads) {
+        const int ii = e >> 6, cc = e & 63;
+        const int64_t i = i0 + ii;
+        ta[cc * LDT + ii] = (i < m && kk0 + cc < K) ? st.Z[i * ldz + kk0 + cc] : 0.0;
+        tb[cc * LDT + ii] = (i < m && cc < J) ? X[i * J + cc] : 0.0;
+      }
+      __syncthreads();
+      chol::tile_mma(c, ta, tb);
+      __syncthreads();
+    }
+    double* U = st.Uref + (int64_t)h * K * J;
+    chol::acc_for_each(c, [&](int r, int j, double v) {
+      if (kk0 + r < K && j < J) U[(kk0 + r) * J + j] = v;
+    });
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_bref_r(const BState* __restrict__ S, const int32_t* __restrict__ items,
+                                                     int32_t nitems, const BGlobal* __restrict__ g) {
+  extern __shared__ __align__(16) double lds[];
+  double* ta = lds;             // Z tile [64 rows][64 columns of K]
+  double* tb = lds + NB * LDT;  // U^T tile [64 slots][64 columns of K]
+  if (g->done) return;
+  const int64_t k = g->k;
+  const int tid = threadIdx.x;
+  for (int32_t t = blockIdx.x; t < nitems; t += gridDim.x) {
+    const BState& st = S[items[3 * t]];
+    if (*st.inactive || !refresh_due(st, k)) continue;  // uniform across the workgroup
+    const int tile = items[3 * t + 1];
+    const int h = items[3 * t + 2];
+    const int64_t i0 = (int64_t)tile * NB;
+    const int nxt = (int)((k + 1) & 1);
+    const int buf = h == 0 ? nxt : (nxt ^ 1);
+    const double* X = st.x[buf];
+    double* R = st.r[buf];
+    const double* U = st.Uref + (int64_t)h * st.K * st.J;
+    const int64_t m = st.m, K = st.K, ldz = st.ldz;
+    const int J = st.J;
+    Acc c;
+    chol::acc_zero(c);
+    for (int64_t kk0 = 0; kk0 < K; kk0 += NB) {
+      for (int e = tid; e < NB * NB; e += kThreads) {
+        const int rr = e >> 6, cc = e & 63;
+        const int64_t i = i0 + rr;
+        ta[rr * LDT + cc] = (i < m && kk0 + cc < K) ? st.Z[i * ldz + kk0 + cc] : 0.0;
+        tb[cc * LDT + rr] = (kk0 + rr < K && cc < J) ? U[(kk0 + rr) * J + cc] : 0.0;
+      }
+      __syncthreads();
+      chol::tile_mma(c, ta, tb);
+      __syncthreads();
+    }
+    chol::acc_for_each(c, [&](int row, int j, double v) {
+      const int64_t i = i0 + row;
+      double sq = 0.0;
+      if (i < m && j < J && st.stop_k[j] < 0) {
+        const int64_t idx = i * J + j;
+        const double rn = v + st.lam[j / st.nrhs] * X[idx] - st.b[i * st.nrhs + (j % st.nrhs)];
+        R[idx] = rn;
+        sq = rn * rn;
+      }
+      ta[row * LDT + j] = sq;
+    });
+    __syncthreads();
+    if (h == 0 && tid < J) {
+      double s = 0.0;
+      for (int rr = 0; rr < NB; ++rr) s += ta[rr * LDT + tid];
+      st.partials[(int64_t)tile * J + tid] = s;
+    }
+    __syncthreads();
   }
 }
 
@@ -297,6 +403,21 @@ hipError_t launch_bfinal(const BState* S, int32_t nprob, BGlobal* g, double tol,
   if (nprob <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_bfinal, dim3(nprob), dim3(64), 0, s, S, g, tol);
   hipLaunchKernelGGL(k_badvance, dim3(1), dim3(kThreads), 0, s, S, nprob, g, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_brefresh(const BState* S, const int32_t* uitems, int32_t nu, const int32_t* ritems, int32_t nr,
+                           const BGlobal* g, int32_t grid, hipStream_t s) {
+  if (nu <= 0 || nr <= 0) return hipSuccess;
+  const size_t bytes = sizeof(double) * 2 * NB * LDT;
+  hipError_t e = hipFuncSetAttribute((const void*)k_bref_u, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_bref_r, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  const int gu = grid < 1 ? 1 : (grid > nu ? nu : grid);
+  const int gr = grid < 1 ? 1 : (grid > nr ? nr : grid);
+  hipLaunchKernelGGL(k_bref_u, dim3(gu), dim3(kThreads), bytes, s, S, uitems, nu, g);
+  hipLaunchKernelGGL(k_bref_r, dim3(gr), dim3(kThreads), bytes, s, S, ritems, nr, g);
   return hipGetLastError();
 }
 

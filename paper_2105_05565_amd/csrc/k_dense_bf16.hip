@@ -117,26 +117,23 @@ typedef __attribute__((address_space(3))) void lds_void_t;
 // s_waitcnt immediate (gfx9 layout): vmcnt <= n, expcnt not waited on, lgkmcnt <= lgkm
 constexpr int waitcnt_imm(int n, int lgkm) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (lgkm << 8); }
 
-// AS for a batch of subsample sketches, one BM x 256 output tile per workgroup of WAVES
-// waves (BM = 32 WAVES; each wave owns 64 x 128 as 2 x 4 MFMA blocks of 32 x 32, fed by
-// v_mfma_f32_32x32x16_bf16 with FP32 accumulation). Operand rows (BM of Z, 256 gathered
-// rows Z[C, :]) are staged 64 deep in K. A DMA instruction fills 1 KB: 8 rows of 128 bytes,
-// lane L taking row L / 8 and 16-byte slot L % 8; the slot holding a row's logical 16-byte
-// segment t is t ^ ((row / 2) % 8), which puts the 16 rows read by a quarter wave on distinct
-// banks. Rows outside the matrix load row 0 (their results are not stored). The K steps are
-// accumulated in ascending order, 16 at a time.
+// One BM x 256 output tile of Z Z[C, :]^T (BM = 32 WAVES) accumulated in FP32 by a workgroup
+// of WAVES waves; each wave owns 64 x 128 as 2 x 4 MFMA blocks of 32 x 32, fed by
+// v_mfma_f32_32x32x16_bf16. Output rows row0 .. row0 + BM - 1 of Z (rows >= m load row 0), output
+// columns n0 .. n0 + 255 (column n takes row members[n] of Z; n >= ntot loads row 0). Operand rows
+// are staged 64 deep in K through two LDS stages of ROWS x 128 bytes (dsm). A DMA instruction
+// fills 1 KB: 8 rows of 128 bytes, lane L taking row L / 8 and 16-byte slot L % 8; the slot
+// holding a row's logical 16-byte segment t is t ^ ((row / 2) % 8), which puts the 16 rows read
+// by a quarter wave on distinct banks. The K steps are accumulated in ascending order, 16 at a
+// time. Ends with every DMA of the workgroup landed and a barrier (dsm may be reused).
 template <int WAVES>
-__global__ __launch_bounds__(WAVES * 64, 1) void k_as_dense_bf16(GemmArgs a) {
+__device__ __forceinline__ void bf16_tile(const uint16_t* __restrict__ Z, int64_t ldz, int64_t m, int64_t kpad,
+                                          const int32_t* __restrict__ members, int64_t ntot, int64_t row0,
+                                          int64_t n0, unsigned char* dsm, f32x16 (&acc)[2][4]) {
   constexpr int BM = 32 * WAVES, ROWS = BM + kBN;
   constexpr int NQ = ROWS / (8 * WAVES);             // DMA instructions per wave and stage
   constexpr int STAGE_BYTES = ROWS * kDmaRowBytes;
-  extern __shared__ __align__(16) unsigned char dsm[];  // [2][ROWS][128 B]
-  if (*a.done) return;
-  int rt, ct;
-  tile_of_block(a, blockIdx.x, &rt, &ct);
-  if (rt < 0) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t row0 = (int64_t)rt * BM, n0 = (int64_t)ct * kBN;
 
   // this lane's source rows for the wave's NQ DMA instructions of a stage
   const unsigned char* src[NQ];
@@ -146,15 +143,15 @@ __global__ __launch_bounds__(WAVES * 64, 1) void k_as_dense_bf16(GemmArgs a) {
     int64_t g;
     if (r < BM) {
       g = row0 + r;
-      if (g >= a.m) g = 0;
+      if (g >= m) g = 0;
     } else {
       const int64_t n = n0 + r - BM;
-      g = n < a.ntot ? (int64_t)a.members[n] : 0;
+      g = n < ntot ? (int64_t)members[n] : 0;
     }
     const int t = (lane & 7) ^ ((r >> 1) & 7);  // logical 16-byte segment stored in this slot
-    src[q] = reinterpret_cast<const unsigned char*>(a.Z + g * a.ldz) + t * 16;
+    src[q] = reinterpret_cast<const unsigned char*>(Z + g * ldz) + t * 16;
   }
-  const int64_t nk = a.kpad / kDmaBK;
+  const int64_t nk = kpad / kDmaBK;
   auto stage = [&](int64_t kt) { return dsm + (size_t)(kt & 1) * STAGE_BYTES; };
   auto issue = [&](int64_t kt) {
     const int64_t ktl = kt < nk ? kt : nk - 1;  // past the end: reload the last stage
@@ -166,7 +163,6 @@ __global__ __launch_bounds__(WAVES * 64, 1) void k_as_dense_bf16(GemmArgs a) {
   };
 
   const int wr = (wave >> 1) * 64, wc = (wave & 1) * 128;
-  f32x16 acc[2][4];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -240,31 +236,76 @@ __global__ __launch_bounds__(WAVES * 64, 1) void k_as_dense_bf16(GemmArgs a) {
     __builtin_amdgcn_sched_barrier(0);
     __builtin_amdgcn_s_waitcnt(waitcnt_imm(63, 0));
   }
-  // no DMA may still be writing this workgroup's LDS when it exits
+  // no DMA may still be writing this workgroup's LDS when the tile ends
   __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));
   __builtin_amdgcn_s_barrier();
+}
 
-  // 32x32x16 result layout: lane l, element v -> row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32
+// Visit the tile's results: f(row in tile, column in tile, value), the 32x32x16 result layout
+// (lane l, element v -> row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32) under the wave's block.
+template <class F>
+__device__ __forceinline__ void bf16_tile_for_each(const f32x16 (&acc)[2][4], F f) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 128;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t row = row0 + wr + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        const int col = wc + j * 32 + l32;
-        const int64_t n = n0 + col;
-        if (row < a.m && n < a.ntot) {
-          const int64_t slot = n / a.tau, c = n % a.tau;
-          const int64_t cj = a.members[n];
-          float val = acc[i][j][v];
-          if (a.lam_kernel)
-            val = (float)((double)val + a.lam * a.Zk[cj * a.ldk + row]);
-          else if (row == cj)
-            val = (float)((double)val + a.lam);
-          a.AS[(slot * a.m + row) * a.ldas + c] = val;
-        }
-      }
+      for (int v = 0; v < 16; ++v)
+        f(wr + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3), wc + j * 32 + (lane & 31), acc[i][j][v]);
+}
+
+// AS for a batch of subsample sketches: one BM x 256 output tile per workgroup (bf16_tile),
+// AS[slot][row][c] = (Z Z[C_slot, :]^T)[row][c] + lam I_C (or lam K[row][C_c] for kernel ridge),
+// stored in FP32.
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64, 1) void k_as_dense_bf16(GemmArgs a) {
+  constexpr int BM = 32 * WAVES;
+  extern __shared__ __align__(16) unsigned char dsm[];  // [2][BM + 256][128 B]
+  if (*a.done) return;
+  int rt, ct;
+  tile_of_block(a, blockIdx.x, &rt, &ct);
+  if (rt < 0) return;
+  const int64_t row0 = (int64_t)rt * BM, n0 = (int64_t)ct * kBN;
+  f32x16 acc[2][4];
+  bf16_tile<WAVES>(a.Z, a.ldz, a.m, a.kpad, a.members, a.ntot, row0, n0, dsm, acc);
+  bf16_tile_for_each(acc, [&](int tr, int tc, float v) {
+    const int64_t row = row0 + tr, n = n0 + tc;
+    if (row < a.m && n < a.ntot) {
+      const int64_t slot = n / a.tau, c = n % a.tau;
+      const int64_t cj = a.members[n];
+      float val = v;
+      if (a.lam_kernel)
+        val = (float)((double)val + a.lam * a.Zk[cj * a.ldk + row]);
+      else if (row == cj)
+        val = (float)((double)val + a.lam);
+      a.AS[(slot * a.m + row) * a.ldas + c] = val;
+    }
+  });
+}
+
+// Grouped form for the batched solver: one workgroup per entry of a ragged table of (job,
+// 256-row tile, 256-column tile) entries, ordered by decreasing contraction length so that the
+// dispatcher hands the longest tiles out first; job p's lambda-free product BS = Z Z[C, :]^T
+// (m x tau, row stride ldas) is stored in FP64 from the FP32 accumulators.
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64, 1) void k_as_dense_bf16_tab(const DenseBf16Job* __restrict__ jobs,
+                                                                     const DenseTile* __restrict__ tiles) {
+  constexpr int BM = 32 * WAVES;
+  extern __shared__ __align__(16) unsigned char dsm[];
+  const DenseTile tl = tiles[blockIdx.x];
+  const DenseBf16Job j = jobs[tl.job];
+  if (*j.done) return;  // uniform across the workgroup
+  const int64_t row0 = (int64_t)tl.tm * BM, n0 = (int64_t)tl.tn * kBN;
+  f32x16 acc[2][4];
+  bf16_tile<WAVES>(j.Z, j.ldz, j.m, j.kpad, j.members, j.tau, row0, n0, dsm, acc);
+  const int64_t m = j.m, tau = j.tau, ldas = j.ldas;
+  double* BS = j.BS;
+  bf16_tile_for_each(acc, [&](int tr, int tc, float v) {
+    const int64_t row = row0 + tr, c = n0 + tc;
+    if (row < m && c < tau) BS[row * ldas + c] = (double)v;
+  });
 }
 
 // Shape of the product launch: waves per workgroup (two LDS stages).
@@ -582,6 +623,21 @@ hipError_t refresh_products(const void* Zr, int32_t z_f32, int64_t ldz, int64_t 
 }
 
 }  // namespace
+
+hipError_t launch_as_dense_bf16_tab(const DenseBf16Job* jobs, const DenseTile* tiles, int32_t ntiles,
+                                    hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  constexpr int BM = 32 * kGemmWaves;
+  const size_t bytes = (size_t)2 * (BM + kBN) * kDmaRowBytes;
+  auto kern = k_as_dense_bf16_tab<kGemmWaves>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3((unsigned)ntiles), dim3(kGemmWaves * 64), bytes, s, jobs, tiles);
+  return hipGetLastError();
+}
+
+int32_t bf16_tile_rows() { return 32 * kGemmWaves; }
+int32_t bf16_tile_cols() { return kBN; }
 
 hipError_t launch_refresh(const void* Zr, int32_t z_f32, int64_t ldz, int64_t m, int64_t K, const double* x,
                           const double* xp, const double* b, double lam, int32_t lam_u, double* r, double* rp,

@@ -52,6 +52,8 @@ struct BProb {
   int ntiles = 0;
   // device data
   double* Z = nullptr;  // dense m x K
+  uint16_t* Zbf = nullptr;  // mixed precision: BF16 copy (m x kpad, zero padded)
+  int64_t kpad = 0;
   int64_t* zr_ptr = nullptr;
   int32_t* zr_col = nullptr;
   double* zr_val = nullptr;
@@ -105,6 +107,14 @@ struct rs_batch {
   DenseJob* djobs = nullptr;
   DenseTile* dtiles = nullptr;
   int n_dtiles = 0;
+  bool mixed = false;          // BF16 products for the dense problems, FP64 refresh
+  DenseBf16Job* bjobs = nullptr;
+  DenseTile* btiles = nullptr;
+  int n_btiles = 0;
+  int32_t* ref_u = nullptr;    // refresh work items (p, K tile, h)
+  int n_ref_u = 0;
+  int32_t* ref_r = nullptr;    // (p, row tile, h)
+  int n_ref_r = 0;
   SparseJob* sjobs = nullptr;
   int n_sjobs = 0;
   int32_t* sitems = nullptr;
@@ -282,13 +292,18 @@ void enqueue_iteration(rs_batch* B) {
   check_hip(launch_sparse_tab(B->sjobs, B->n_sjobs, B->sitems, B->n_sitems, B->max_sparse_tau,
                               t.sparse_mult * B->cus, s),
             "B S (count)");
-  check_hip(launch_as_dense_f64_tab(B->djobs, B->dtiles, B->n_dtiles, t.dense_tk, t.dense_mult * B->cus, s),
-            "B S (dense)");
+  if (B->mixed)
+    check_hip(launch_as_dense_bf16_tab(B->bjobs, B->btiles, B->n_btiles, s), "B S (dense, BF16)");
+  else
+    check_hip(launch_as_dense_f64_tab(B->djobs, B->dtiles, B->n_dtiles, t.dense_tk, t.dense_mult * B->cus, s),
+              "B S (dense)");
   check_hip(launch_chol_tab(B->cjobs, B->n_cjobs, t.chol_mult * B->cus, s), "cholesky");
   check_hip(launch_brho(B->S, B->rho_items, B->n_rho, B->g, 8 * B->cus, s), "rho");
   check_hip(launch_bdelta(B->S, B->delta_items, B->n_delta, 8 * B->cus, s), "delta");
   check_hip(launch_bupdate(B->S, B->upd_items, B->n_upd, B->g, B->betas, B->gammas, 2 * B->cus, s),
             "update");
+  if (B->mixed)
+    check_hip(launch_brefresh(B->S, B->ref_u, B->n_ref_u, B->ref_r, B->n_ref_r, B->g, 4 * B->cus, s), "refresh");
   check_hip(launch_bfinal(B->S, (int)B->P.size(), B->g, B->opt.tol, s), "stop test");
 }
 
@@ -363,7 +378,13 @@ void autotune(rs_batch* B) {
   check_hip(launch_sketch_tab(B->sk_sub, B->n_sub, kSubsample, B->lds_sub, s), "sketch");
   check_hip(launch_sketch_tab(B->sk_cnt, B->n_cnt, kCount, B->lds_cnt, s), "sketch");
   Tuning t = B->tune;
-  if (B->n_dtiles) {
+  if (B->mixed && B->n_btiles) {
+    // one workgroup per tile: nothing to choose, the launch is timed for the report
+    t.dense_ms = time_launch(B, [&] {
+      check_hip(launch_as_dense_bf16_tab(B->bjobs, B->btiles, B->n_btiles, s), "tune");
+    });
+  }
+  if (B->n_dtiles && !B->mixed) {
     float best = 1e30f;
     for (int tk : {16})  // the product's K-panel depth (fixed)
       for (int mult : {1, 2, 4, 8}) {
@@ -450,7 +471,10 @@ rs_status rs_batch_create(int32_t count, const rs_problem* problems, const rs_op
   rs_batch* B = new rs_batch();
   try {
     B->opt = *o;
-    if (o->precision != RS_PREC_FP64) throw Fail{RS_EUNSUPPORTED, "batched solves run in FP64"};
+    if (o->precision != RS_PREC_FP64 && o->precision != RS_PREC_MIXED_BF16)
+      throw Fail{RS_EINVAL, "unknown precision"};
+    B->mixed = o->precision == RS_PREC_MIXED_BF16;
+    const int32_t refresh_every = o->refresh_every > 0 ? o->refresh_every : 20;
     if (o->dense_route != 0)
       throw Fail{RS_EUNSUPPORTED, "batched solves form B S per sketch (dense_route must be 0)"};
     if (const char* why = momentum_invalid(*o)) throw Fail{RS_EINVAL, why};
@@ -522,6 +546,9 @@ rs_status rs_batch_create(int32_t count, const rs_problem* problems, const rs_op
     std::vector<SketchArgs> sub, cnt;
     std::vector<DenseJob> dj;
     std::vector<DenseTile> dt;
+    std::vector<DenseBf16Job> bj;
+    std::vector<DenseTile> bft;
+    std::vector<int32_t> ru, rr;
     std::vector<SparseJob> sj;
     std::vector<int32_t> si, rho_it, del_it, upd_it;
     std::vector<CholJob> cj;
@@ -598,12 +625,42 @@ rs_status rs_batch_create(int32_t count, const rs_problem* problems, const rs_op
       if (q.kind == kSubsample) {
         sub.push_back(a);
         B->lds_sub = std::max(B->lds_sub, sketch_lds_bytes(kSubsample, q.tau, nsel));
-        DenseJob j{q.Z, q.K, m, q.K, members, q.tau, q.ldas, 0.0, BS, st.inactive};
-        const int jid = (int)dj.size();
-        dj.push_back(j);
-        // 128 x 128 product tiles (the kernel's unit)
-        for (int tn = 0; tn < (q.tau + 127) / 128; ++tn)
-          for (int tm = 0; tm < (int)((m + 127) / 128); ++tm) dt.push_back(DenseTile{jid, tm, tn});
+        if (B->mixed) {
+          // BF16 copy for the products; the FP64 Z stays for the refresh
+          q.kpad = (q.K + 63) / 64 * 64;
+          q.Zbf = dalloc<uint16_t>(B, (size_t)m * q.kpad);
+          check_hip(launch_cast_bf16(q.Z, 0, m, q.K, q.K, 0, q.Zbf, q.kpad, nullptr, 0, s), "BF16 copy");
+          DenseBf16Job j{q.Zbf, q.kpad, m, q.kpad, members, q.tau, q.ldas, BS, st.inactive};
+          const int jid = (int)bj.size();
+          bj.push_back(j);
+          const int tr = bf16_tile_rows(), tc = bf16_tile_cols();
+          for (int tn = 0; tn < (q.tau + tc - 1) / tc; ++tn)
+            for (int tm = 0; tm < (int)((m + tr - 1) / tr); ++tm) bft.push_back(DenseTile{jid, tm, tn});
+          st.refresh = refresh_every;
+          st.Z = q.Z;
+          st.ldz = q.K;
+          st.K = q.K;
+          st.Uref = dalloc<double>(B, (size_t)2 * q.K * q.J);
+          for (int h = 0; h < 2; ++h) {
+            for (int kt = 0; kt < (int)((q.K + 63) / 64); ++kt) {
+              ru.push_back(p);
+              ru.push_back(kt);
+              ru.push_back(h);
+            }
+            for (int rt = 0; rt < q.ntiles; ++rt) {
+              rr.push_back(p);
+              rr.push_back(rt);
+              rr.push_back(h);
+            }
+          }
+        } else {
+          DenseJob j{q.Z, q.K, m, q.K, members, q.tau, q.ldas, 0.0, BS, st.inactive};
+          const int jid = (int)dj.size();
+          dj.push_back(j);
+          // 128 x 128 product tiles (the kernel's unit)
+          for (int tn = 0; tn < (q.tau + 127) / 128; ++tn)
+            for (int tm = 0; tm < (int)((m + 127) / 128); ++tm) dt.push_back(DenseTile{jid, tm, tn});
+        }
       } else {
         cnt.push_back(a);
         B->lds_cnt = std::max(B->lds_cnt, sketch_lds_bytes(kCount, q.tau, nsel));
@@ -637,13 +694,16 @@ rs_status rs_batch_create(int32_t count, const rs_problem* problems, const rs_op
         upd_it.push_back(p);
         upd_it.push_back(tl);
       }
-      sig += (q.sparse ? "c" : "d") + std::to_string(m) + "x" + std::to_string(q.K) + "t" +
+      sig += (q.sparse ? "c" : (B->mixed ? "b" : "d")) + std::to_string(m) + "x" + std::to_string(q.K) + "t" +
              std::to_string(q.tau) + "l" + std::to_string(q.nlam) + ";";
     }
     // product tiles in decreasing contraction length (a tile costs ~K): with the
     // workgroups striding over the table this keeps the per-workgroup loads even
     std::stable_sort(dt.begin(), dt.end(), [&](const DenseTile& a, const DenseTile& b) {
       return dj[a.job].K > dj[b.job].K;
+    });
+    std::stable_sort(bft.begin(), bft.end(), [&](const DenseTile& a, const DenseTile& b) {
+      return bj[a.job].kpad > bj[b.job].kpad;
     });
     // factorisations in decreasing size, so the largest start first
     std::stable_sort(chol_order.begin(), chol_order.end(),
@@ -669,6 +729,13 @@ rs_status rs_batch_create(int32_t count, const rs_problem* problems, const rs_op
     B->djobs = upload(B, dj);
     B->dtiles = upload(B, dt);
     B->n_dtiles = (int)dt.size();
+    B->bjobs = upload(B, bj);
+    B->btiles = upload(B, bft);
+    B->n_btiles = (int)bft.size();
+    B->ref_u = upload(B, ru);
+    B->n_ref_u = (int)ru.size() / 3;
+    B->ref_r = upload(B, rr);
+    B->n_ref_r = (int)rr.size() / 3;
     B->sjobs = upload(B, sj);
     B->n_sjobs = (int)sj.size();
     B->sitems = upload(B, si);

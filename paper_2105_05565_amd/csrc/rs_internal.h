@@ -141,6 +141,22 @@ struct DenseTile {
 };
 hipError_t launch_as_dense_f64_tab(const DenseJob* jobs, const DenseTile* tiles, int32_t ntiles,
                                    int32_t tk, int32_t grid, hipStream_t s);
+// Batched mixed precision: BS = Z Z[C, :]^T from a BF16 copy of Z (m x kpad, row stride ldz,
+// zero padded; kpad a multiple of 64), FP32 accumulation, stored in FP64 (m x tau, row stride
+// ldas); tiles of bf16_tile_rows() x bf16_tile_cols().
+struct DenseBf16Job {
+  const uint16_t* Z;
+  int64_t ldz, m, kpad;
+  const int32_t* members;
+  int32_t tau;
+  int64_t ldas;
+  double* BS;
+  const int32_t* done;
+};
+hipError_t launch_as_dense_bf16_tab(const DenseBf16Job* jobs, const DenseTile* tiles, int32_t ntiles,
+                                    hipStream_t s);
+int32_t bf16_tile_rows();
+int32_t bf16_tile_cols();
 
 // Count / SubCount products from CSR(Z) (m rows) and CSR(Z^T) (nnz entries), values FP32 or
 // FP64: AS[slot] (m x tau, row stride ldas) and, for member rows,
@@ -316,6 +332,13 @@ struct BState {
   int32_t* inactive;      // problem finished (read as the `done` word of its launches)
   int64_t cap;            // iteration cap
   int64_t* iters;         // iterations performed when the problem finished
+  // mixed precision (dense problems with BF16 products): after the update of iteration k with
+  // (k + 1) % refresh == 0, R^{k+1} and R^k are recomputed in FP64 from Z (FP64, m x K, row
+  // stride ldz) through Uref (2 x K x J), and a slot may stop only at such an iteration
+  int32_t refresh;        // 0: FP64 products, tracked residuals only
+  const double* Z;
+  int64_t ldz, K;
+  double* Uref;
 };
 struct BGlobal {
   int64_t k;     // shared iteration counter
@@ -330,6 +353,11 @@ hipError_t launch_bdelta(const BState* S, const int32_t* items, int32_t nitems, 
 hipError_t launch_bupdate(const BState* S, const int32_t* items, int32_t nitems, const BGlobal* g,
                           const double* betas, const double* gammas, int32_t grid, hipStream_t s);
 hipError_t launch_bfinal(const BState* S, int32_t nprob, BGlobal* g, double tol, hipStream_t s);
+// FP64 refresh of the residuals of the mixed-precision problems (no-op at other iterations):
+// uitems (p, 64-column tile of K, h) for U_h = Z^T X_h, ritems (p, 64-row tile, h) for
+// R_h = Z U_h + X_h diag(lambda) - B, with h = 0 for X^{k+1} and 1 for X^k.
+hipError_t launch_brefresh(const BState* S, const int32_t* uitems, int32_t nu, const int32_t* ritems, int32_t nr,
+                           const BGlobal* g, int32_t grid, hipStream_t s);
 hipError_t launch_bcol(const double* src, int64_t m, int64_t src_ld, int64_t src_col, double* dst,
                        int64_t dst_ld, int64_t dst_col, hipStream_t s);
 

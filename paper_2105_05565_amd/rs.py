@@ -731,8 +731,10 @@ class Batch:
 
     def __init__(self, problems, *, momentum="heuristic", tol=1e-6, max_iter=100000, seed=1,
                  problem_id=0, eta=0.995, beta_max=0.5, gamma=1.0, beta=0.5, graph_iters=0,
-                 autotune=False, stream=None):
+                 autotune=False, stream=None, precision="fp64", refresh_every=20):
         o = rs_options_default()
+        o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        o.refresh_every = int(refresh_every)
         o.momentum = MOMENTA[momentum] if isinstance(momentum, str) else int(momentum)
         o.tol, o.max_iter = tol, int(max_iter)
         o.seed, o.problem_id = int(seed), int(problem_id)

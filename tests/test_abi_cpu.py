@@ -143,7 +143,7 @@ def test_batch_rejects_bad_arguments_without_device(pr, opt):
 
 def test_batch_rejects_unbuilt_pairs_without_device():
     o = rs.rs_options_default()
-    o.precision = rs.RS_PREC_MIXED_BF16
+    o.precision = 7  # neither FP64 nor mixed
     M, keep = rs.make_matrix(np.ones((20, 8)))
     y = np.ones(20)
     lam = np.ones(1)
@@ -151,7 +151,7 @@ def test_batch_rejects_unbuilt_pairs_without_device():
     P.X, P.y, P.nrhs, P.lambdas, P.nlambda, P.sketch = M, y.ctypes.data, 1, lam.ctypes.data, 1, -1
     with pytest.raises(rs.RsError) as e:
         rs.rs_batch_create([P], o)
-    assert e.value.status == rs.RS_EUNSUPPORTED
+    assert e.value.status == rs.RS_EINVAL
     o.precision = rs.RS_PREC_FP64
     P.sketch = rs.RS_SKETCH_COUNT  # count sketch on dense data
     with pytest.raises(rs.RsError) as e:

@@ -230,3 +230,89 @@ def test_batched_full_size_sampled_slots():
             assert_state_close(B.state(p, l * pr["y"].shape[1] + q), ref[p][c], 1e-10,
                                f"full-size batch problem {p} k={c}")
     B.close()
+
+
+# ---- mixed precision (BF16 products for the dense problems, FP64 refresh) ----
+
+def _refresh_bound(system, x):
+    """Dot-product bound of two FP64 summation orders of Z (Z^T x) + lambda x - b."""
+    Za = np.abs(np.asarray(system.Z.todense()) if hasattr(system.Z, "todense") else system.Z)
+    n = max(Za.shape)
+    gamma = n * 2.0 ** -53 / (1 - n * 2.0 ** -53)
+    return 4 * gamma * (Za @ (Za.T @ np.abs(x)) + system.lam * np.abs(x) + np.abs(system.b))
+
+
+def test_mixed_batch_refresh_recomputes_true_residual():
+    """After R lock steps (refresh interval R) a dense problem's r^R and r^{R-1} are the FP64
+    residuals A x - b of its iterates x^R and x^{R-1} (within the dot-product bound of the two
+    summation orders), for every slot; the CSR problems, whose products stay FP64, follow the
+    FP64 batch bit for bit."""
+    probs = _problems()
+    R = 5
+    M = rs.Batch(probs, tol=0.0, seed=4, precision="mixed", refresh_every=R, graph_iters=4)
+    F = rs.Batch(probs, tol=0.0, seed=4, graph_iters=4)
+    M.step(R)
+    F.step(R)
+    for p, pr in enumerate(probs):
+        for l in range(3):
+            for q in range(2):
+                j = l * 2 + q
+                x, xp, r, rp = M.state(p, j)
+                if hasattr(pr["X"], "tocsr"):
+                    for u, v in zip((x, xp, r, rp), F.state(p, j)):
+                        assert np.array_equal(u, v), (p, j)
+                    continue
+                system = ridge_system(pr["X"], pr["y"][:, q], pr["lambdas"][l])
+                for xx, rr, what in ((x, r, "r^R"), (xp, rp, "r^{R-1}")):
+                    true = system.matvec(xx) - system.b
+                    err = np.abs(rr - true)
+                    bound = _refresh_bound(system, xx)
+                    assert np.all(err <= bound), (p, j, what, float((err / bound).max()))
+    M.close()
+    F.close()
+
+
+def test_mixed_batch_converges_and_stops_only_at_refreshes():
+    """A mixed batch solved to tol: every slot converges; a dense problem's slots stop only at
+    refresh iterations (multiples of R) and reach the direct solution within 2 kappa tol; the
+    CSR problems stop where the FP64 batch stops."""
+    probs = _problems()
+    tol, R = 1e-8, 10
+    M = rs.Batch(probs, tol=tol, seed=3, precision="mixed", refresh_every=R)
+    F = rs.Batch(probs, tol=tol, seed=3)
+    st, rep = M.solve()
+    assert st == rs.RS_OK and rep.converged == rep.solves == 24
+    F.solve()
+    for p, pr in enumerate(probs):
+        stop, rel = M.slots(p)
+        assert np.all(stop > 0) and np.all(rel <= tol)
+        if hasattr(pr["X"], "tocsr"):
+            assert np.array_equal(stop, F.slots(p)[0]), p
+            continue
+        assert np.all(stop % R == 0), (p, stop)
+        W = M.weights(p)
+        for l in range(3):
+            for q in range(2):
+                j = l * 2 + q
+                system = ridge_system(pr["X"], pr["y"][:, q], pr["lambdas"][l])
+                A = system.dense_A()
+                w_direct = system.weights(np.linalg.solve(A, system.b))
+                assert _rel(W[j], w_direct) <= 2 * np.linalg.cond(A) * tol, (p, j)
+    M.close()
+    F.close()
+
+
+def test_mixed_batch_graph_replay_equals_direct_launches():
+    """Replays of the captured mixed sequence (the refresh kernels run every iteration and act
+    only at refresh iterations) equal direct launches bit for bit across two refreshes."""
+    probs = _problems()
+    A = rs.Batch(probs, tol=0.0, seed=2, precision="mixed", refresh_every=5, graph_iters=4)
+    D = rs.Batch(probs, tol=0.0, seed=2, precision="mixed", refresh_every=5, graph_iters=-1)
+    A.step(12)
+    D.step(12)
+    for p in range(len(probs)):
+        for j in (0, 5):
+            for u, v in zip(A.state(p, j), D.state(p, j)):
+                assert np.array_equal(u, v), (p, j)
+    A.close()
+    D.close()
