@@ -451,6 +451,8 @@ def main_learned(args):
     print(f"[bench] trained on {records} records from {args.train_solves} solves in {train_s:.1f} s; "
           f"epoch losses {[round(v, 4) for v in losses]}", file=sys.stderr, flush=True)
 
+    look = args.lookahead if args.lookahead > 0 else 2
+
     def run(sampler, seeds, profile=0, **extra):
         S = rs.Solver(X, y, p.lam, sampler=sampler, profile=profile, **{**kw, **extra})
         if sampler == "learned":
@@ -469,7 +471,7 @@ def main_learned(args):
         S.close()
         return times, iters, rels, sts, prof
 
-    S = rs.Solver(X, y, p.lam, sampler="learned", profile=1, **kw)
+    S = rs.Solver(X, y, p.lam, sampler="learned", profile=1, lookahead=look, **kw)
     S.set_sampler_params(params)
     for w in range(args.warmup):
         S.reset(10000 + w)
@@ -511,7 +513,7 @@ def main_learned(args):
         "dtype": "bf16", "data": "synthetic",
         "config": {"workload": wl["name"], "n": n, "d": d, "form": "primal", "sketch": "subsample (learned proposal)",
                    "tau": tau, "lambda": p.lam, "momentum": "heuristic", "tol": 1e-6, "precision": "mixed",
-                   "lookahead": 8, "train_solves": args.train_solves, "held_out_seeds": seeds},
+                   "lookahead": look, "train_solves": args.train_solves, "held_out_seeds": seeds},
         "iters_median": statistics.median(iters),
         "time_s_all": [round(t, 4) for t in times],
         # per result: ||A w - b|| / ||b|| of each timed solve's iterate, recomputed in FP64 from the data

@@ -285,6 +285,55 @@ __global__ __launch_bounds__(WAVES * 64, 1) void k_as_dense_bf16(GemmArgs a) {
   });
 }
 
+// The shift of AS's entry (row, column n of the launch): lam I_C, or lam K[C_c][row] for kernel ridge.
+__device__ __forceinline__ float shifted(const GemmArgs& a, int64_t row, int64_t n, float v) {
+  const int64_t cj = a.members[n];
+  if (a.lam_kernel) return (float)((double)v + a.lam * a.Zk[cj * a.ldk + row]);
+  if (row == cj) return (float)((double)v + a.lam);
+  return v;
+}
+
+// Split-K form for launches with fewer tiles than compute units: workgroup (s, tile) sums the
+// K stages [s q, (s + 1) q) of its tile (q stages per split) into ws[s][slot][row][c] (FP32, no
+// shift); k_splitk_reduce then adds the splits in order and the shift.
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64, 1) void k_as_dense_bf16_split(GemmArgs a, int64_t stages_per_split,
+                                                                       float* __restrict__ ws) {
+  constexpr int BM = 32 * WAVES;
+  extern __shared__ __align__(16) unsigned char dsm[];
+  if (*a.done) return;
+  const int ntiles = a.n_row_tiles * a.n_col_tiles;
+  const int span = (ntiles + kXcds - 1) / kXcds * kXcds;
+  const int sp = blockIdx.x / span;
+  int rt, ct;
+  tile_of_block(a, blockIdx.x % span, &rt, &ct);
+  if (rt < 0) return;
+  const int64_t nk = a.kpad / kDmaBK;
+  const int64_t k0 = (int64_t)sp * stages_per_split, k1 = min(nk, k0 + stages_per_split);  // k1 > k0 (host)
+  const int64_t row0 = (int64_t)rt * BM, n0 = (int64_t)ct * kBN;
+  f32x16 acc[2][4];
+  bf16_tile<WAVES>(a.Z + k0 * kDmaBK, a.ldz, a.m, (k1 - k0) * kDmaBK, a.members, a.ntot, row0, n0, dsm, acc);
+  const int64_t nslots = a.ntot / a.tau;
+  float* wsp = ws + (int64_t)sp * nslots * a.m * a.ldas;
+  bf16_tile_for_each(acc, [&](int tr, int tc, float v) {
+    const int64_t row = row0 + tr, n = n0 + tc;
+    if (row < a.m && n < a.ntot) wsp[((n / a.tau) * a.m + row) * a.ldas + n % a.tau] = v;
+  });
+}
+
+__global__ __launch_bounds__(256) void k_splitk_reduce(GemmArgs a, int32_t nsplit, const float* __restrict__ ws) {
+  if (*a.done) return;
+  const int64_t total = a.ntot * a.m;  // (slot, row, c) with c < tau
+  const int64_t plane = a.ntot / a.tau * a.m * a.ldas;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t c = e % a.tau, sr = e / a.tau, row = sr % a.m, slot = sr / a.m;
+    const int64_t idx = (slot * a.m + row) * a.ldas + c;
+    float v = 0.0f;
+    for (int sp = 0; sp < nsplit; ++sp) v += ws[sp * plane + idx];
+    a.AS[idx] = shifted(a, row, slot * a.tau + c, v);
+  }
+}
+
 // Grouped form for the batched solver: one workgroup per entry of a ragged table of (job,
 // 256-row tile, 256-column tile) entries, ordered by decreasing contraction length so that the
 // dispatcher hands the longest tiles out first; job p's lambda-free product BS = Z Z[C, :]^T
@@ -541,10 +590,35 @@ hipError_t launch_cast_bf16(const void* src, int32_t src_is_f32, int64_t rows_s,
   return hipGetLastError();
 }
 
+namespace {
+
+int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
+    (void)hipGetLastError();
+    return 256;
+  }
+  return cus;
+}
+
+}  // namespace
+
+int32_t bf16_split_factor(int64_t m, int64_t kpad, int32_t tau, int32_t nslots) {
+  constexpr int BM = 32 * kGemmWaves;
+  const int64_t ntiles = ((m + BM - 1) / BM) * (((int64_t)nslots * tau + kBN - 1) / kBN);
+  const int64_t nk = kpad / kDmaBK;
+  const int cus = device_cus();
+  int32_t split = 1;
+  // split while the tiles leave compute units idle and every split keeps >= 32 stages
+  while (ntiles * split * 2 <= cus && nk >= (int64_t)split * 2 * 32) split *= 2;
+  return split;
+}
+
 hipError_t launch_as_dense_bf16(const uint16_t* Zbf, int64_t ldz, int64_t m, int64_t kpad,
                                 const int32_t* members, int32_t tau, int64_t ldas, int32_t nslots,
                                 double lam, const double* Zk, int64_t ldk, int32_t lam_kernel, float* AS,
-                                const int32_t* done, hipStream_t s) {
+                                const int32_t* done, hipStream_t s, float* ws, int64_t ws_floats) {
   if (kpad % kDmaBK != 0 || ldz % 8 != 0) return hipErrorInvalidValue;
   if (lam_kernel && (!Zk || ldk < m)) return hipErrorInvalidValue;
   GemmArgs a;
@@ -568,6 +642,20 @@ hipError_t launch_as_dense_bf16(const uint16_t* Zbf, int64_t ldz, int64_t m, int
   const int ntiles = a.n_row_tiles * a.n_col_tiles;
   const int per = (ntiles + kXcds - 1) / kXcds;
   const size_t bytes = (size_t)2 * (BM + kBN) * kDmaRowBytes;
+  const int32_t split = ws ? bf16_split_factor(m, kpad, tau, nslots) : 1;
+  if (split > 1 && (int64_t)split * nslots * m * ldas <= ws_floats) {
+    const int64_t nk = kpad / kDmaBK;
+    const int64_t q = (nk + split - 1) / split;
+    if ((split - 1) * q >= nk) return hipErrorInvalidValue;  // every split gets >= 1 stage
+    auto kern = k_as_dense_bf16_split<kGemmWaves>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(per * kXcds * split), dim3(kGemmWaves * 64), bytes, s, a, q, ws);
+    const int64_t total = a.ntot * m;
+    const unsigned g = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_splitk_reduce, dim3(g), dim3(256), 0, s, a, split, ws);
+    return hipGetLastError();
+  }
   auto kern = k_as_dense_bf16<kGemmWaves>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;

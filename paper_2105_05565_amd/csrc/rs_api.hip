@@ -56,6 +56,8 @@ struct rs_handle {
   int64_t kpad = 0;
   float* Z32 = nullptr;
   int64_t ld32 = 0;           // row stride of Z32: K rounded up to 4 (zero padding), for 16-byte loads
+  float* splitk_ws = nullptr;  // BF16 products of small batches split over K: FP32 partial sums
+  int64_t splitk_floats = 0;
   double* ref_u = nullptr;
   double* ref_upart = nullptr;
   double* ref_partials = nullptr;
@@ -432,7 +434,8 @@ void prep_batch(rs_handle* h, int p, int64_t k0, int nb, hipStream_t s) {
               "AS (columns of the formed A)");
   } else if (h->mixed) {
     check_hip(launch_as_dense_bf16(h->Zbf, h->kpad, h->m, h->kpad, bs.members, h->tau, h->ldas, nb,
-                                   h->lam, h->Z, h->ldz, h->kern ? 1 : 0, (float*)bs.AS, done, s),
+                                   h->lam, h->Z, h->ldz, h->kern ? 1 : 0, (float*)bs.AS, done, s,
+                                   h->splitk_ws, h->splitk_floats),
               "AS (dense, BF16)");
   } else {
     check_hip(launch_as_dense_f64(h->Z, h->ldz, h->m, h->K, bs.members, h->tau, h->ldas, nb, h->lam,
@@ -1052,12 +1055,26 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
     // keep the factorisations on the one-workgroup-per-sketch kernel.
     int B = 256;
     if (!h->sparse && o->dense_route != 1 && 2.0 * (double)h->m * (double)h->K * (double)h->tau > 1e11) B = 32;
-    // the learned proposal is recomputed once per batch: short batches keep it fresh
-    if (o->sampler == RS_SAMPLER_LEARNED) B = 8;
+    // the learned proposal is recomputed once per batch: short batches keep it fresh (the BF16
+    // products of a short batch are split over K, so they still fill the chip)
+    if (o->sampler == RS_SAMPLER_LEARNED) B = 2;
     if (o->lookahead > 0) B = o->lookahead;
     const size_t budget = budget_all - gram_bytes;
     while (B > 1 && (size_t)B * per_slot > budget) B >>= 1;
     h->B = B;
+    if (h->mixed && !h->sparse && !h->dense_s && o->dense_route != 1) {
+      // batches whose product tiles leave compute units idle are split over K: room for the
+      // largest split any batch size up to B asks for
+      int64_t need = 0;
+      for (int nb = 1; nb <= B; ++nb) {
+        const int32_t sp = bf16_split_factor(h->m, h->kpad, h->tau, nb);
+        if (sp > 1) need = std::max<int64_t>(need, (int64_t)sp * nb * h->m * h->ldas);
+      }
+      if (need > 0) {
+        h->splitk_ws = dalloc<float>(h, (size_t)need);
+        h->splitk_floats = need;
+      }
+    }
     const size_t as_bytes = (h->mixed ? sizeof(float) : sizeof(double)) * (size_t)B * h->m * h->ldas;
     for (int p = 0; p < h->nsets; ++p) {
       rs_handle::BatchSet& bs = h->sets[p];

@@ -276,10 +276,14 @@ hipError_t launch_cast_bf16(const void* src, int32_t src_is_f32, int64_t rows_s,
 // AS[slot] (FP32, row stride ldas) = Zbf Zbf[C_slot,:]^T + lambda I_C on BF16 MFMA.
 // lam_kernel != 0: kernel ridge, the shift is lam Zk[C_c][row] (the FP64 symmetric kernel matrix)
 // instead of lam I_C.
+// ws (may be NULL): FP32 workspace of ws_floats; when the launch has fewer tiles than compute
+// units it is split over K (bf16_split_factor(...) splits, each summed into ws, then added in
+// order), which needs split * nslots * m * ldas floats.
 hipError_t launch_as_dense_bf16(const uint16_t* Zbf, int64_t ldz, int64_t m, int64_t kpad,
                                 const int32_t* members, int32_t tau, int64_t ldas, int32_t nslots,
                                 double lam, const double* Zk, int64_t ldk, int32_t lam_kernel, float* AS,
-                                const int32_t* done, hipStream_t s);
+                                const int32_t* done, hipStream_t s, float* ws = nullptr, int64_t ws_floats = 0);
+int32_t bf16_split_factor(int64_t m, int64_t kpad, int32_t tau, int32_t nslots);
 // FP64 recomputation r = Z (Z^T x) + lambda x - b (and rp from xp) from the FP32 copy;
 // records ||r|| / ||r^0|| at k and applies the stop test.
 int64_t refresh_partials(int64_t m);
