@@ -26,11 +26,26 @@ __device__ __forceinline__ void acc_zero(Acc& c) {
     for (int j = 0; j < 2; ++j) c.v[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
 }
 
-// dst[r][c] = src[r * ld + c]  (trans: src[c * ld + r]) for a 64 x 64 tile.
+// dst[r][c] = src[r * ld + c]  (trans: src[c * ld + r]) for a 64 x 64 tile (src and ld
+// even, so that a pair of neighbouring elements is one 16-byte load). Each thread issues
+// its 8 loads before the first LDS store, so the tile costs one memory latency.
 __device__ __forceinline__ void load_tile(double* dst, const double* src, int64_t ld, bool trans) {
-  for (int e = threadIdx.x; e < NB * NB; e += kThreads) {
-    const int r = e >> 6, c = e & 63;
-    dst[r * LDT + c] = trans ? src[(int64_t)c * ld + r] : src[(int64_t)r * ld + c];
+  double2 v[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int e = threadIdx.x + kThreads * q, r = e >> 5, c = 2 * (e & 31);
+    v[q] = *reinterpret_cast<const double2*>(src + (int64_t)r * ld + c);
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int e = threadIdx.x + kThreads * q, r = e >> 5, c = 2 * (e & 31);
+    if (trans) {
+      dst[c * LDT + r] = v[q].x;
+      dst[(c + 1) * LDT + r] = v[q].y;
+    } else {
+      dst[r * LDT + c] = v[q].x;
+      dst[r * LDT + c + 1] = v[q].y;
+    }
   }
 }
 
@@ -101,6 +116,19 @@ __device__ __forceinline__ void acc_for_each(const Acc& c, F f) {
         f(wr + i * 16 + 4 * v + (lane >> 4), wc + j * 16 + (lane & 15), c.v[i][j][v]);
 }
 
+// c <- the 64 x 64 tile at src (row stride ld) in the accumulator layout of acc_for_each.
+__device__ __forceinline__ void acc_load(Acc& c, const double* src, int64_t ld) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        c.v[i][j][v] = src[(int64_t)(wr + i * 16 + 4 * v + (lane >> 4)) * ld + wc + j * 16 + (lane & 15)];
+}
+
 // acc (16 x 16) += A B^T over K = 16 on FP64 MFMA, A(row, k) = pa[row * sar + k * sac],
 // B(col, k) = pb[col * sbr + k * sbc]. Result element v of lane l: row 4 v + l / 16,
 // column l % 16.
@@ -117,126 +145,158 @@ __device__ __forceinline__ void mma16(d4v& acc, const double* pa, int sar, int s
 
 __device__ __forceinline__ double* blk16(double* t, int i, int j) { return t + (i * 16) * LDT + j * 16; }
 
-// The value of v in lane l (a compile-time lane after unrolling), as a wave-uniform scalar.
-__device__ __forceinline__ double lane_value(double v, int l) {
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+// The value of v in lane l of this lane's 16-lane row (DPP row_newbcast), for a lane index
+// that is a constant once the caller's loops are unrolled.
+template <int L>
+__device__ __forceinline__ double row_bcast_c(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x150 + L, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x150 + L, 0xf, 0xf, true);
   return __hiloint2double(hi, lo);
 }
+__device__ __forceinline__ double row_bcast(double v, int l) {
+  switch (l) {
+    case 0: return row_bcast_c<0>(v);
+    case 1: return row_bcast_c<1>(v);
+    case 2: return row_bcast_c<2>(v);
+    case 3: return row_bcast_c<3>(v);
+    case 4: return row_bcast_c<4>(v);
+    case 5: return row_bcast_c<5>(v);
+    case 6: return row_bcast_c<6>(v);
+    case 7: return row_bcast_c<7>(v);
+    case 8: return row_bcast_c<8>(v);
+    case 9: return row_bcast_c<9>(v);
+    case 10: return row_bcast_c<10>(v);
+    case 11: return row_bcast_c<11>(v);
+    case 12: return row_bcast_c<12>(v);
+    case 13: return row_bcast_c<13>(v);
+    case 14: return row_bcast_c<14>(v);
+    default: return row_bcast_c<15>(v);
+  }
+}
 
-// Factor the 64 x 64 tile in td (LDS, lower triangle read) in place: td <- L (upper part
-// zeroed) with L L^T = td, and ta <- X = L^{-1} (lower, upper part zeroed). A pivot that
-// is not positive and finite is replaced by 1 and reported through *bad. col: LDS scratch
-// (unused). Called by all threads of the workgroup.
+// x^{-1/2}: the hardware estimate (relative error about 5e-8) refined by two Newton steps
+// y <- y + y (1/2 - x y^2 / 2), which brings it within an ulp or so.
+__device__ __forceinline__ double rsqrt_refined(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  double e = fma(-h * y, y, 0.5);
+  y = fma(y, e, y);
+  e = fma(-h * y, y, 0.5);
+  return fma(y, e, y);
+}
+
+// Factor the 64 x 64 tile in td (LDS, lower triangle read) in place: the lower triangle of
+// td <- L with L L^T = td (the part above the diagonal is left undefined), and ta <- X =
+// L^{-1} (lower triangular, zeros above the diagonal). A pivot that is not positive and
+// finite is replaced by 1 and reported through *bad. Called by all threads of the workgroup.
 //
-// Blocked on 16 x 16 sub-blocks, right-looking: wave 0 factors and inverts the diagonal
-// block in registers (lane r holds row r, column values read as scalars from their lane), the
-// panel L_ik = A_ik X_kk^T and the trailing update A_ij -= L_ik L_jk^T are FP64 MFMA
-// products spread over the waves. Then X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj by
-// distance i - j, the partial sums parked in the unused upper blocks of td.
-__device__ __forceinline__ void factor_diag_tile(double* td, double* ta, double* col, int* bad) {
-  (void)col;
+// Blocked on 16 x 16 sub-blocks, right-looking. Wave 0 factors a diagonal block in
+// registers: lane r holds row r (the four 16-lane rows of the wave hold the same block),
+// pivot c is L_cc = sqrt(a_cc) from one reciprocal square root, and the entries of column c
+// reach the other lanes by row broadcasts; in the same sweep lane j carries column j of the
+// block's inverse (x_c = s_c / L_cc, then s_i -= L_ic x_c). The waves then form, on FP64
+// MFMA, the panel L_ik = A_ik X_kk^T and the blocks X_kj = -X_kk T_kj of row k of X, and
+// then the trailing update A_ij -= L_ik L_jk^T together with the partial sums
+// T_ij = sum_{t=j}^{k} L_it X_tj (kept in the blocks of ta below the diagonal).
+__device__ __forceinline__ void factor_diag_tile(double* td, double* ta, int* bad) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int kNW = kThreads / 64;
   for (int kb = 0; kb < 4; ++kb) {
     if (wave == 0) {
-      // rows of the diagonal block in lanes 0-15 (lanes >= 16 carry copies, not stored)
       const int r = lane & 15;
       double* D = blk16(td, kb, kb);
-      double d[16];
+      double d[16], s[16];
 #pragma unroll
-      for (int c = 0; c < 16; ++c) d[c] = D[r * LDT + c];
+      for (int c = 0; c < 16; ++c) {
+        d[c] = D[r * LDT + c];
+        s[c] = c == r ? 1.0 : 0.0;
+      }
       int badl = 0;
 #pragma unroll
       for (int c = 0; c < 16; ++c) {
-        double piv = lane_value(d[c], c);
+        double piv = row_bcast(d[c], c);
         if (!(piv > 0.0) || !(piv < INFINITY)) {
           badl = 1;
           piv = 1.0;
         }
-        const double sq = sqrt(piv);
-        const double l = r > c ? d[c] / sq : (r == c ? sq : 0.0);
+        const double rs = rsqrt_refined(piv);
+        // lane c: sqrt(piv) (when the pivot was replaced, 1); lanes above c carry values
+        // of the upper triangle that are never read
+        const double l = r == c ? piv * rs : d[c] * rs;
         d[c] = l;
+        const double x = s[c] * rs;
+        s[c] = x;
 #pragma unroll
-        for (int cc = c + 1; cc < 16; ++cc) d[cc] -= l * lane_value(l, cc);
-      }
-      // X_kk = L_kk^{-1}: lane j solves for column j (rows i < j come out zero)
-      const int j = r;
-      double x[16];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        double s = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-        for (int t = 0; t < i; ++t) s -= lane_value(d[t], i) * x[t];
-        x[i] = s / lane_value(d[i], i);
+        for (int cc = c + 1; cc < 16; ++cc) {
+          const double lc = row_bcast(l, cc);
+          d[cc] -= l * lc;
+          s[cc] -= lc * x;
+        }
       }
       if (lane < 16) {
         double* X = blk16(ta, kb, kb);
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
-          D[r * LDT + c] = c <= r ? d[c] : 0.0;
-          X[c * LDT + j] = x[c];
+          if (c <= r) D[r * LDT + c] = d[c];
+          X[c * LDT + r] = s[c];
         }
         if (badl) *bad = 1;
       }
+    } else if (kb == 0) {
+      // the six blocks of ta above the diagonal blocks are zero in the result
+      for (int e = tid - 64; e < 6 * 256; e += kThreads - 64) {
+        const int b = e >> 8, w = e & 255;
+        const int bi = b < 3 ? 0 : (b < 5 ? 1 : 2);
+        const int bj = b < 3 ? b + 1 : (b < 5 ? b - 1 : 3);
+        ta[(16 * bi + (w >> 4)) * LDT + 16 * bj + (w & 15)] = 0.0;
+      }
     }
     __syncthreads();
-    // panel: L_ik = A_ik X_kk^T
-    for (int i = kb + 1 + wave; i < 4; i += kNW) {
+    // panel L_ik = A_ik X_kk^T (i > kb) and row kb of X: X_kj = -X_kk T_kj (j < kb)
+    if (wave < 3) {
       d4v acc = {0.0, 0.0, 0.0, 0.0};
-      double* Aik = blk16(td, i, kb);
-      mma16(acc, Aik, LDT, 1, blk16(ta, kb, kb), LDT, 1);
+      if (wave < 3 - kb) {
+        double* Aik = blk16(td, kb + 1 + wave, kb);
+        mma16(acc, Aik, LDT, 1, blk16(ta, kb, kb), LDT, 1);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) Aik[(4 * v + (lane >> 4)) * LDT + (lane & 15)] = acc[v];
+        for (int v = 0; v < 4; ++v) Aik[(4 * v + (lane >> 4)) * LDT + (lane & 15)] = acc[v];
+      } else {
+        double* Tkj = blk16(ta, kb, wave - (3 - kb));
+        mma16(acc, blk16(ta, kb, kb), LDT, 1, Tkj, 1, LDT);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Tkj[(4 * v + (lane >> 4)) * LDT + (lane & 15)] = -acc[v];
+      }
     }
     __syncthreads();
-    // trailing: A_ij -= L_ik L_jk^T for kb < j <= i
-    {
-      int q = 0;
-      for (int i = kb + 1; i < 4; ++i)
-        for (int j = kb + 1; j <= i; ++j, ++q) {
-          if (q % kNW != wave) continue;
-          d4v acc = {0.0, 0.0, 0.0, 0.0};
-          mma16(acc, blk16(td, i, kb), LDT, 1, blk16(td, j, kb), LDT, 1);
-          double* Aij = blk16(td, i, j);
-#pragma unroll
-          for (int v = 0; v < 4; ++v) Aij[(4 * v + (lane >> 4)) * LDT + (lane & 15)] -= acc[v];
+    if (kb == 3) break;
+    // A_ij -= L_ik L_jk^T (kb < j <= i) and T_ij (+)= L_ik X_kj (i > kb >= j)
+    const int nA = (3 - kb) * (4 - kb) / 2, nT = (3 - kb) * (kb + 1);
+    for (int it = wave; it < nA + nT; it += kNW) {
+      d4v acc = {0.0, 0.0, 0.0, 0.0};
+      if (it < nA) {
+        int i = kb + 1, j = it;
+        while (j >= i - kb) {
+          j -= i - kb;
+          ++i;
         }
-    }
-    __syncthreads();
-  }
-  // X below the diagonal blocks, by distance dd = i - j
-  for (int dd = 1; dd < 4; ++dd) {
-    // T_ij = sum_{k=j}^{i-1} L_ik X_kj, parked in td block (j, i)
-    for (int j = wave; j + dd < 4; j += kNW) {
-      const int i = j + dd;
-      d4v acc = {0.0, 0.0, 0.0, 0.0};
-      for (int k = j; k < i; ++k) mma16(acc, blk16(td, i, k), LDT, 1, blk16(ta, k, j), 1, LDT);
-      double* T = blk16(td, j, i);
+        j += kb + 1;
+        mma16(acc, blk16(td, i, kb), LDT, 1, blk16(td, j, kb), LDT, 1);
+        double* Aij = blk16(td, i, j);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) T[(4 * v + (lane >> 4)) * LDT + (lane & 15)] = acc[v];
-    }
-    __syncthreads();
-    // X_ij = -X_ii T_ij
-    for (int j = wave; j + dd < 4; j += kNW) {
-      const int i = j + dd;
-      d4v acc = {0.0, 0.0, 0.0, 0.0};
-      mma16(acc, blk16(ta, i, i), LDT, 1, blk16(td, j, i), 1, LDT);
-      double* X = blk16(ta, i, j);
+        for (int v = 0; v < 4; ++v) Aij[(4 * v + (lane >> 4)) * LDT + (lane & 15)] -= acc[v];
+      } else {
+        const int t = it - nA, i = kb + 1 + t / (kb + 1), j = t % (kb + 1);
+        mma16(acc, blk16(td, i, kb), LDT, 1, blk16(ta, kb, j), 1, LDT);
+        double* Tij = blk16(ta, i, j);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) X[(4 * v + (lane >> 4)) * LDT + (lane & 15)] = -acc[v];
+        for (int v = 0; v < 4; ++v) {
+          double* p = Tij + (4 * v + (lane >> 4)) * LDT + (lane & 15);
+          *p = j == kb ? acc[v] : *p + acc[v];
+        }
+      }
     }
     __syncthreads();
   }
-  // zero the blocks above the diagonal in both tiles
-  for (int e = tid; e < NB * NB; e += kThreads) {
-    const int r = e >> 6, c = e & 63;
-    if ((c >> 4) > (r >> 4)) {
-      td[r * LDT + c] = 0.0;
-      ta[r * LDT + c] = 0.0;
-    }
-  }
-  __syncthreads();
 }
 
 }  // namespace chol

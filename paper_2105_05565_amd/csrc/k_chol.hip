@@ -171,15 +171,15 @@ struct ItLauum {
 // Phases 1-3 on the assembled, padded ldg x ldg matrix G (lower triangle read):
 // G <- G^{-1} (both triangles), U <- L^{-T} (upper block triangle; the tile below each
 // diagonal tile, U_{i,i-1}, holds X_ii = L_ii^{-1} for phase 2).
-// LDS: ta, tb, td, tx (64 x LDT each), col (64).
+// LDS: ta, tb, td, tx (64 x LDT each).
 __device__ __forceinline__ void factor_invert(double* __restrict__ G, double* __restrict__ U,
                                               int64_t ldg, double* ta, double* tb, double* td,
-                                              double* tx, double* col, int* bad_flag) {
+                                              double* tx, int* bad_flag) {
   const int nt = (int)(ldg / NB);
   // td holds C_jj: factor it, keep X_jj = L_jj^{-1} in tx, store L_jj, U_jj = X_jj^T and
   // (j >= 1) the copy of X_jj read by phase 2
   auto diag = [&](int j) {
-    factor_diag_tile(td, tx, col, bad_flag);
+    factor_diag_tile(td, tx, bad_flag);
     double* Gjj = gtile(G, ldg, j, j);
     double* Ujj = gtile(U, ldg, j, j);
     double* Xjj = j > 0 ? gtile(U, ldg, j, j - 1) : nullptr;
@@ -259,7 +259,6 @@ __global__ __launch_bounds__(kThreads) void k_chol_inverse(double* __restrict__ 
   double* tb = lds + NB * LDT;       // [64][65]
   double* td = lds + 2 * NB * LDT;   // [64][65]
   double* tx = lds + 3 * NB * LDT;   // [64][65]
-  double* col = lds + 4 * NB * LDT;  // [64]
   __shared__ int bad;
   if (*done) return;
   const int tid = threadIdx.x;
@@ -289,7 +288,7 @@ __global__ __launch_bounds__(kThreads) void k_chol_inverse(double* __restrict__ 
   }
   __syncthreads();
 
-  factor_invert(G, U, ldg, ta, tb, td, tx, col, &bad);
+  factor_invert(G, U, ldg, ta, tb, td, tx, &bad);
   if (tid == 0) status[slot] = bad;
 }
 
@@ -305,7 +304,6 @@ __global__ __launch_bounds__(kThreads) void k_chol_tab(const CholJob* __restrict
   double* tb = lds + NB * LDT;
   double* td = lds + 2 * NB * LDT;
   double* tx = lds + 3 * NB * LDT;
-  double* col = lds + 4 * NB * LDT;
   __shared__ int bad;
   const int tid = threadIdx.x;
   for (int32_t t = blockIdx.x; t < njobs; t += gridDim.x) {
@@ -333,7 +331,7 @@ __global__ __launch_bounds__(kThreads) void k_chol_tab(const CholJob* __restrict
       G[e] = v;
     }
     __syncthreads();
-    factor_invert(G, j.U, ldg, ta, tb, td, tx, col, &bad);
+    factor_invert(G, j.U, ldg, ta, tb, td, tx, &bad);
     if (tid == 0 && bad) *j.status = 1;  // sticky until the host clears it
     __syncthreads();
   }
@@ -344,7 +342,7 @@ hipError_t chol_launch(double* G, double* W, int64_t ldg, int32_t tau, int32_t n
                        const ASV* AS, int64_t ldas, int64_t m, const int32_t* members,
                        const int32_t* offs, int32_t* status, const int32_t* done, hipStream_t s) {
   if (ldg % NB != 0) return hipErrorInvalidValue;
-  const size_t bytes = sizeof(double) * (4 * NB * LDT + NB);
+  const size_t bytes = sizeof(double) * 4 * NB * LDT;
   hipError_t e = hipFuncSetAttribute((const void*)k_chol_inverse<ASV>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;
@@ -369,7 +367,7 @@ hipError_t launch_chol_inverse(double* G, double* W, int64_t ldg, int32_t tau, i
 hipError_t launch_chol_tab(const CholJob* jobs, int32_t njobs, int32_t grid, hipStream_t s) {
   if (njobs <= 0) return hipSuccess;
   grid = grid < 1 ? 1 : (grid > njobs ? njobs : grid);
-  const size_t bytes = sizeof(double) * (4 * NB * LDT + NB);
+  const size_t bytes = sizeof(double) * 4 * NB * LDT;
   hipError_t e = hipFuncSetAttribute((const void*)k_chol_tab, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)bytes);
   if (e != hipSuccess) return e;

@@ -4,25 +4,26 @@
 // The single-workgroup factorisation (k_chol.hip) runs one sketch per compute unit,
 // which leaves most of the chip idle when a batch holds few sketches. Here every
 // 64 x 64 tile of every sketch is a workgroup, and the sequential structure of a
-// right-looking algorithm is carried by kernel boundaries on the stream: the diagonal
-// factorisation of step j never waits for a chain of tile products, because the trailing
-// update of step j - 1 (one tile product per workgroup, all tiles at once) has already
-// brought G_jj up to date:
+// right-looking algorithm is carried by kernel boundaries on the stream. With nt tiles
+// per side, the factorisation, the inverse W = L^{-1} and the product G^{-1} = W^T W all
+// advance together, one block column per launch, in nt + 1 launches:
 //
-//   assemble               G (gathered rows of AS for the subsample sketch), identity
-//                          padding and empty buckets; U <- 0
-//   for j = 0 .. nt-1:
-//     diag(j)              G_jj = L_jj L_jj^T factored in LDS; X_jj = L_jj^{-1} stored,
-//                          and U_jj = X_jj^T
-//     panel(j)             L_ij = G_ij X_jj^T for i > j, over G_ij
-//     trail(j)             G_il -= L_ij L_lj^T for j < l <= i
-//   for d = 1 .. nt-1:
-//     ll_inverse(d)        W = L^{-1} by distance d = i - j: W_ij = -X_ii sum_{k=j}^{i-1} L_ik W_kj,
-//                          stored transposed as U_ji (U = L^{-T}, so W_kj = U_jk^T)
-//   lauum                  G^{-1} = U U^T: tile (i, j) = sum_{k >= i} U_ik U_jk^T
+//   start                  G assembled (gathered rows of AS for the subsample sketch,
+//                          identity padding and empty buckets); tile (0, 0) factored in
+//                          LDS, X_0 = L_00^{-1} stored
+//   step s = 1 .. nt, k = s - 1, one workgroup per item:
+//     F  (s <= l <= i)     G_il -= L_ik L_lk^T with L_ik = G_ik X_k^T formed in the
+//                          workgroup; the item (s, s) then factors G_ss in LDS: X_s
+//     I  (i >= s, j <= k)  T_ij (+)= L_ik W_kj, where W_kj = -X_k T_kj (j < k) or X_k
+//                          (j = k); T_ij = sum_{t=j}^{i-1} L_it W_tj is what row i of
+//                          W = L^{-1} needs: W_ij = -X_i T_ij
+//     A  (j <= i <= k)     (G^{-1})_ij (+)= W_ki^T W_kj, both W blocks formed from T in
+//                          the workgroup; the last step also writes the upper triangle
 //
-// Tile products read their operands straight from global memory (they are shared by many
-// workgroups and stay in L2), so that many workgroups fit on a compute unit.
+// L itself is never stored: every item forms the L and W blocks it reads from G, X and T,
+// which are final by the time it runs (G_ik after step k - 1, X_k in step k, T_kj after
+// step k - 1). T lives in the tiles of U below the diagonal, G^{-1} over G: in step s the
+// tiles read by one item are written by none, each written tile by one item only.
 #include "chol_tiles.h"
 #include "dev_common.h"
 #include "rs_internal.h"
@@ -34,8 +35,8 @@ using namespace chol;
 
 struct MultiArgs {
   double* G;      // [slots][ldg][ldg]
-  double* U;      // [slots][ldg][ldg]
-  double* X;      // [slots][nt][64][64]  L_kk^{-1}
+  double* U;      // [slots][ldg][ldg]  T_ij in the tiles below the diagonal
+  double* X;      // [slots][nt][64][64]  X_k = L_kk^{-1}
   int64_t ldg;
   int32_t nt, tau, kind;
   const void* AS;
@@ -51,12 +52,24 @@ __device__ __forceinline__ double* tile(double* base, int64_t ld, int i, int j) 
   return base + (int64_t)i * NB * ld + (int64_t)j * NB;
 }
 
-__global__ __launch_bounds__(kThreads) void k_chol_assemble(MultiArgs a) {
+// X_s <- ta (64 x 64 from LDS), and its transpose into the diagonal tile U_ss (the form the
+// inverse by distance reads).
+__device__ __forceinline__ void store_x(double* X, double* Uss, int64_t ldg, const double* ta) {
+  for (int e = threadIdx.x; e < NB * NB; e += kThreads) {
+    const int r = e >> 6, c = e & 63;
+    X[e] = ta[r * LDT + c];
+    Uss[(int64_t)r * ldg + c] = ta[c * LDT + r];
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_chol_start(MultiArgs a) {
+  extern __shared__ __align__(16) double lds[];
+  __shared__ int bad;
   if (*a.done) return;
   const int64_t slot = blockIdx.z;
   const int ti = blockIdx.y, tj = blockIdx.x;
+  const bool first = ti == 0 && tj == 0;
   double* G = a.G + slot * a.ldg * a.ldg;
-  double* U = a.U + slot * a.ldg * a.ldg;
   const int32_t* offs = a.offs + slot * (a.tau + 1);
   const int32_t* members = a.members + slot * a.tau;  // subsample: nsel = tau
   for (int e = threadIdx.x; e < NB * NB; e += kThreads) {
@@ -71,12 +84,17 @@ __global__ __launch_bounds__(kThreads) void k_chol_assemble(MultiArgs a) {
     } else if (gr == gc && offs[gr + 1] == offs[gr]) {
       *g = 1.0;  // empty bucket: zero row and column of S^T A S
     }
-    U[gr * a.ldg + gc] = 0.0;
+    if (first) lds[r * LDT + c] = *g;
   }
-  if (ti == 0 && tj == 0 && threadIdx.x == 0) a.status[slot] = 0;
+  if (!first) return;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  factor_diag_tile(lds, lds + NB * LDT, &bad);
+  store_x(a.X + slot * a.nt * NB * NB, a.U + slot * a.ldg * a.ldg, a.ldg, lds + NB * LDT);
+  if (threadIdx.x == 0) a.status[slot] = bad;
 }
 
-// Linear index -> (i, j) with lo <= j <= i < nt (row-major over i).
+// Linear index -> (i, j) with lo <= j <= i (row-major over i).
 __device__ __forceinline__ void lower_pair(int idx, int lo, int* i, int* j) {
   int row = lo, width = 1;
   while (idx >= width) {
@@ -88,66 +106,281 @@ __device__ __forceinline__ void lower_pair(int idx, int lo, int* i, int* j) {
   *j = lo + idx;
 }
 
-// Step j's diagonal tile (already updated by the trailing updates of steps < j) factored in
-// LDS: X_jj = L_jj^{-1} kept for the panel and the inverse, U_jj = X_jj^T.
-__global__ __launch_bounds__(kThreads) void k_chol_diag(MultiArgs a, int j) {
+// Items of step s: F first (its item 0 is the diagonal tile (s, s), the longest), then I,
+// then A. LDS: tx, ta, tb (64 x LDT each).
+__global__ __launch_bounds__(kThreads) void k_chol_step(MultiArgs a, int s) {
   extern __shared__ __align__(16) double lds[];
-  double* ta = lds;
-  double* td = lds + NB * LDT;
-  double* col = lds + 2 * NB * LDT;
+  double* tx = lds;
+  double* ta = lds + NB * LDT;
+  double* tb = lds + 2 * NB * LDT;
   __shared__ int bad;
   if (*a.done) return;
-  const int64_t slot = blockIdx.x;
+  const int nt = a.nt, k = s - 1;
+  const int64_t slot = blockIdx.y;
   double* G = a.G + slot * a.ldg * a.ldg;
   double* U = a.U + slot * a.ldg * a.ldg;
-  if (threadIdx.x == 0) bad = 0;
-  load_tile(td, tile(G, a.ldg, j, j), a.ldg, false);
-  __syncthreads();
-  factor_diag_tile(td, ta, col, &bad);
-  double* Ujj = tile(U, a.ldg, j, j);
-  double* Xj = a.X + (slot * a.nt + j) * NB * NB;
-  for (int e = threadIdx.x; e < NB * NB; e += kThreads) {
-    const int r = e >> 6, cc = e & 63;
-    Ujj[(int64_t)r * a.ldg + cc] = ta[cc * LDT + r];
-    Xj[e] = ta[r * LDT + cc];
+  const double* Xk = a.X + (slot * nt + k) * NB * NB;
+  const int nF = (nt - s) * (nt - s + 1) / 2, nI = (nt - s) * s;
+  int item = blockIdx.x;
+  if (item < nF) {
+    // F: G_il -= L_ik L_lk^T
+    int i, l;
+    lower_pair(item, s, &i, &l);
+    double* Gil = tile(G, a.ldg, i, l);
+    Acc g;
+    acc_load(g, Gil, a.ldg);
+    load_tile(tx, Xk, NB, false);
+    load_tile(ta, tile(G, a.ldg, i, k), a.ldg, false);
+    if (l != i) load_tile(tb, tile(G, a.ldg, l, k), a.ldg, false);
+    __syncthreads();
+    Acc c1, c2;
+    acc_zero(c1);
+    tile_mma(c1, ta, tx);  // L_ik
+    if (l != i) {
+      acc_zero(c2);
+      tile_mma(c2, tb, tx);  // L_lk
+    }
+    __syncthreads();
+    acc_for_each(c1, [&](int r, int cc, double v) { ta[r * LDT + cc] = v; });
+    if (l != i) acc_for_each(c2, [&](int r, int cc, double v) { tb[r * LDT + cc] = v; });
+    __syncthreads();
+    Acc c3;
+    acc_zero(c3);
+    tile_mma(c3, ta, l != i ? tb : ta);
+    if (i == s && l == s) {
+      // the diagonal tile of step s is now final: factor it
+      if (threadIdx.x == 0) bad = 0;
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int w = 0; w < 2; ++w) g.v[u][w] -= c3.v[u][w];
+      acc_for_each(g, [&](int r, int cc, double v) { tx[r * LDT + cc] = v; });
+      __syncthreads();
+      factor_diag_tile(tx, ta, &bad);
+      store_x(a.X + (slot * nt + s) * NB * NB, tile(U, a.ldg, s, s), a.ldg, ta);
+      if (threadIdx.x == 0 && bad) a.status[slot] = 1;
+    } else {
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int w = 0; w < 2; ++w) g.v[u][w] -= c3.v[u][w];
+      acc_for_each(g, [&](int r, int cc, double v) { Gil[(int64_t)r * a.ldg + cc] = v; });
+    }
+    return;
   }
-  if (threadIdx.x == 0 && bad) a.status[slot] = 1;
+  item -= nF;
+  if (item < nI) {
+    // I: T_ij (+)= L_ik W_kj
+    const int i = s + item / s, j = item % s;
+    double* Tij = tile(U, a.ldg, i, j);
+    Acc g;
+    if (j < k) acc_load(g, Tij, a.ldg);
+    load_tile(tx, Xk, NB, false);
+    load_tile(ta, tile(G, a.ldg, i, k), a.ldg, false);
+    if (j < k)
+      load_tile(tb, tile(U, a.ldg, k, j), a.ldg, true);  // T_kj^T
+    else
+      load_tile(tb, Xk, NB, true);  // W_kk^T = X_k^T
+    __syncthreads();
+    Acc c1, c2;
+    acc_zero(c1);
+    tile_mma(c1, ta, tx);  // L_ik
+    if (j < k) {
+      acc_zero(c2);
+      tile_mma(c2, tx, tb);  // X_k T_kj = -W_kj
+    }
+    __syncthreads();
+    acc_for_each(c1, [&](int r, int cc, double v) { ta[r * LDT + cc] = v; });
+    if (j < k) acc_for_each(c2, [&](int r, int cc, double v) { tb[cc * LDT + r] = -v; });  // W_kj^T
+    __syncthreads();
+    Acc c3;
+    acc_zero(c3);
+    tile_mma(c3, ta, tb);  // L_ik W_kj
+    if (j < k) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int w = 0; w < 2; ++w) c3.v[u][w] += g.v[u][w];
+    }
+    acc_for_each(c3, [&](int r, int cc, double v) { Tij[(int64_t)r * a.ldg + cc] = v; });
+    return;
+  }
+  item -= nI;
+  {
+    // A: (G^{-1})_ij (+)= W_ki^T W_kj for j <= i <= k
+    int i, j;
+    lower_pair(item, 0, &i, &j);
+    double* Gij = tile(G, a.ldg, i, j);
+    Acc g;
+    if (i < k) acc_load(g, Gij, a.ldg);
+    load_tile(tx, Xk, NB, false);
+    if (i < k) load_tile(ta, tile(U, a.ldg, k, i), a.ldg, true);  // T_ki^T
+    if (j < k && j != i) load_tile(tb, tile(U, a.ldg, k, j), a.ldg, true);
+    __syncthreads();
+    Acc c1, c2;
+    if (i < k) {
+      acc_zero(c1);
+      tile_mma(c1, tx, ta);  // X_k T_ki = -W_ki
+    }
+    if (j < k && j != i) {
+      acc_zero(c2);
+      tile_mma(c2, tx, tb);  // -W_kj
+    }
+    __syncthreads();
+    // operands of W_ki^T W_kj: ta[r][t] = W_ki[t][r], tb[c][t] = W_kj[t][c]
+    if (i < k)
+      acc_for_each(c1, [&](int r, int cc, double v) { ta[cc * LDT + r] = -v; });
+    else
+      for (int e = threadIdx.x; e < NB * NB; e += kThreads)
+        ta[(e & 63) * LDT + (e >> 6)] = tx[(e >> 6) * LDT + (e & 63)];  // W_kk = X_k
+    if (j < k && j != i) acc_for_each(c2, [&](int r, int cc, double v) { tb[cc * LDT + r] = -v; });
+    __syncthreads();
+    Acc c3;
+    acc_zero(c3);
+    tile_mma(c3, ta, j != i ? tb : ta);
+    if (i < k) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int w = 0; w < 2; ++w) c3.v[u][w] += g.v[u][w];
+    }
+    double* Gji = tile(G, a.ldg, j, i);
+    const bool last = s == nt, mirror = last && i != j;
+    acc_for_each(c3, [&](int r, int cc, double v) {
+      Gij[(int64_t)r * a.ldg + cc] = v;
+      if (mirror) Gji[(int64_t)cc * a.ldg + r] = v;
+    });
+  }
 }
 
-// L_ij = G_ij X_jj^T for the tiles i > j of column j (G_ij already updated), over G_ij.
-__global__ __launch_bounds__(kThreads) void k_chol_panel(MultiArgs a, int j) {
+// Work-optimal form of the same steps, two launches per step (no block is formed twice).
+// Panel of step s (k = s - 1): L_ik = G_ik X_k^T stored over G_ik (i >= s), and row k of W,
+// W_kj = -X_k T_kj stored over T_kj (j < k). LDS: two tiles.
+__global__ __launch_bounds__(kThreads) void k_chol_panel(MultiArgs a, int s) {
   extern __shared__ __align__(16) double lds[];
-  double* tp = lds;
-  double* tx = lds + NB * LDT;
+  double* tx = lds;
+  double* ta = lds + NB * LDT;
   if (*a.done) return;
+  const int nt = a.nt, k = s - 1;
   const int64_t slot = blockIdx.y;
-  const int i = j + 1 + (int)blockIdx.x;
   double* G = a.G + slot * a.ldg * a.ldg;
-  double* Gij = tile(G, a.ldg, i, j);
-  load_tile(tp, Gij, a.ldg, false);
-  load_tile(tx, a.X + (slot * a.nt + j) * NB * NB, NB, false);
+  double* U = a.U + slot * a.ldg * a.ldg;
+  const double* Xk = a.X + (slot * nt + k) * NB * NB;
+  const int item = blockIdx.x;
+  const bool lpanel = item < nt - s;
+  double* dst = lpanel ? tile(G, a.ldg, s + item, k) : tile(U, a.ldg, k, item - (nt - s));
+  load_tile(tx, Xk, NB, false);
+  load_tile(ta, dst, a.ldg, !lpanel);  // G_ik, or T_kj^T
   __syncthreads();
   Acc c;
   acc_zero(c);
-  tile_mma(c, tp, tx);  // G_ij X_jj^T
-  acc_for_each(c, [&](int r, int cc, double v) { Gij[(int64_t)r * a.ldg + cc] = v; });
+  if (lpanel)
+    tile_mma(c, ta, tx);  // G_ik X_k^T
+  else
+    tile_mma(c, tx, ta);  // X_k T_kj
+  const double sign = lpanel ? 1.0 : -1.0;
+  acc_for_each(c, [&](int r, int cc, double v) { dst[(int64_t)r * a.ldg + cc] = sign * v; });
 }
 
-// Trailing update of step j: G_il -= L_ij L_lj^T for every j < l <= i < nt, one tile per
-// workgroup (each element read and written by one lane).
-__global__ __launch_bounds__(kThreads) void k_chol_trail(MultiArgs a, int j) {
+// Updates of step s from the stored panel: F (s <= l <= i): G_il -= L_ik L_lk^T, the item
+// (s, s) then factoring G_ss; I (i >= s, j <= k): T_ij (+)= L_ik W_kj; A (j <= i <= k):
+// (G^{-1})_ij (+)= W_ki^T W_kj. W_kk = X_k. LDS: two tiles.
+__global__ __launch_bounds__(kThreads) void k_chol_update(MultiArgs a, int s) {
+  extern __shared__ __align__(16) double lds[];
+  double* ta = lds;
+  double* tb = lds + NB * LDT;
+  __shared__ int bad;
   if (*a.done) return;
+  const int nt = a.nt, k = s - 1;
   const int64_t slot = blockIdx.y;
-  int i, l;
-  lower_pair(blockIdx.x, j + 1, &i, &l);
   double* G = a.G + slot * a.ldg * a.ldg;
-  Acc c;
+  double* U = a.U + slot * a.ldg * a.ldg;
+  const double* Xk = a.X + (slot * nt + k) * NB * NB;
+  const int nF = (nt - s) * (nt - s + 1) / 2, nI = (nt - s) * s;
+  int item = blockIdx.x;
+  // W_kj (j <= k) and its source: U_kj, or X_k for j = k
+  auto wsrc = [&](int j, int64_t* ld) -> const double* {
+    *ld = j < k ? a.ldg : NB;
+    return j < k ? tile(U, a.ldg, k, j) : Xk;
+  };
+  Acc g, c;
   acc_zero(c);
-  tile_mma_global(c, tile(G, a.ldg, i, j), tile(G, a.ldg, l, j), a.ldg);
-  double* Gil = tile(G, a.ldg, i, l);
-  acc_for_each(c, [&](int r, int cc, double v) { Gil[(int64_t)r * a.ldg + cc] -= v; });
+  if (item < nF) {
+    int i, l;
+    lower_pair(item, s, &i, &l);
+    double* Gil = tile(G, a.ldg, i, l);
+    acc_load(g, Gil, a.ldg);
+    load_tile(ta, tile(G, a.ldg, i, k), a.ldg, false);
+    if (l != i) load_tile(tb, tile(G, a.ldg, l, k), a.ldg, false);
+    __syncthreads();
+    tile_mma(c, ta, l != i ? tb : ta);
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int w = 0; w < 2; ++w) g.v[u][w] -= c.v[u][w];
+    if (i == s && l == s) {
+      if (threadIdx.x == 0) bad = 0;
+      __syncthreads();
+      acc_for_each(g, [&](int r, int cc, double v) { ta[r * LDT + cc] = v; });
+      __syncthreads();
+      factor_diag_tile(ta, tb, &bad);
+      store_x(a.X + (slot * nt + s) * NB * NB, tile(U, a.ldg, s, s), a.ldg, tb);
+      if (threadIdx.x == 0 && bad) a.status[slot] = 1;
+    } else {
+      acc_for_each(g, [&](int r, int cc, double v) { Gil[(int64_t)r * a.ldg + cc] = v; });
+    }
+    return;
+  }
+  item -= nF;
+  if (item < nI) {
+    const int i = s + item / s, j = item % s;
+    double* Tij = tile(U, a.ldg, i, j);
+    if (j < k) acc_load(g, Tij, a.ldg);
+    int64_t ldw;
+    const double* W = wsrc(j, &ldw);
+    load_tile(ta, tile(G, a.ldg, i, k), a.ldg, false);
+    load_tile(tb, W, ldw, true);
+    __syncthreads();
+    tile_mma(c, ta, tb);  // L_ik W_kj
+    if (j < k) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int w = 0; w < 2; ++w) c.v[u][w] += g.v[u][w];
+    }
+    acc_for_each(c, [&](int r, int cc, double v) { Tij[(int64_t)r * a.ldg + cc] = v; });
+    return;
+  }
+  item -= nI;
+  int i, j;
+  lower_pair(item, 0, &i, &j);
+  double* Gij = tile(G, a.ldg, i, j);
+  if (i < k) acc_load(g, Gij, a.ldg);
+  int64_t ldi, ldj;
+  const double* Wi = wsrc(i, &ldi);
+  const double* Wj = wsrc(j, &ldj);
+  load_tile(ta, Wi, ldi, true);
+  if (j != i) load_tile(tb, Wj, ldj, true);
+  __syncthreads();
+  tile_mma(c, ta, j != i ? tb : ta);  // W_ki^T W_kj
+  if (i < k) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int w = 0; w < 2; ++w) c.v[u][w] += g.v[u][w];
+  }
+  double* Gji = tile(G, a.ldg, j, i);
+  const bool mirror = s == nt && i != j;
+  acc_for_each(c, [&](int r, int cc, double v) {
+    Gij[(int64_t)r * a.ldg + cc] = v;
+    if (mirror) Gji[(int64_t)cc * a.ldg + r] = v;
+  });
 }
 
+// Inverse by distance d = i - j after the factorisation (mode 2): W_ij = -X_i sum_{k=j}^{i-1}
+// L_ik W_kj as one chain of tile products per workgroup, stored transposed as U_ji (U = W^T),
+// L_ik read from the tiles of G below the diagonal.
 __global__ __launch_bounds__(kThreads) void k_chol_ll_inverse(MultiArgs a, int d) {
   extern __shared__ __align__(16) double lds[];
   double* tt = lds;
@@ -160,7 +393,7 @@ __global__ __launch_bounds__(kThreads) void k_chol_ll_inverse(MultiArgs a, int d
   Acc c;
   acc_zero(c);
   for (int k = j; k < i; ++k) tile_mma_global(c, tile(G, a.ldg, i, k), tile(U, a.ldg, j, k), a.ldg);
-  // T = sum_k L_ik W_kj; U_ji = W_ij^T = -T^T X_ii^T
+  // T = sum_k L_ik W_kj; U_ji = W_ij^T = -T^T X_i^T
   acc_for_each(c, [&](int r, int cc, double v) { tt[cc * LDT + r] = v; });
   load_tile(tx, a.X + (slot * a.nt + i) * NB * NB, NB, false);
   __syncthreads();
@@ -171,6 +404,8 @@ __global__ __launch_bounds__(kThreads) void k_chol_ll_inverse(MultiArgs a, int d
   acc_for_each(c2, [&](int r, int cc, double v) { Uji[(int64_t)r * a.ldg + cc] = -v; });
 }
 
+// G^{-1} = U U^T (mode 2): tile (i, j) = sum_{k >= i} U_ik U_jk^T as one chain per
+// workgroup, written to both triangles.
 __global__ __launch_bounds__(kThreads) void k_chol_lauum(MultiArgs a) {
   if (*a.done) return;
   const int64_t slot = blockIdx.y;
@@ -193,38 +428,70 @@ __global__ __launch_bounds__(kThreads) void k_chol_lauum(MultiArgs a) {
 
 size_t chol_multi_x_bytes(int64_t ldg) { return sizeof(double) * (size_t)(ldg / NB) * NB * NB; }
 
-hipError_t launch_chol_multi(double* G, double* U, double* X, int64_t ldg, int32_t tau,
-                             int32_t nslots, int32_t kind, const void* AS, int32_t as_f32,
-                             int64_t ldas, int64_t m, const int32_t* members, const int32_t* offs,
-                             int32_t* status, const int32_t* done, hipStream_t s) {
+// mode 0: one launch per step, each workgroup forming the L and W blocks it reads (three
+// tile products per item, nt + 1 launches: the shortest chain); mode 1: panel and update
+// launches per step (one tile product per item, a third of the work, 2 nt + 1 launches);
+// mode 2: panel and update launches for the factorisation alone, then the inverse by
+// distance and U U^T as chains of products accumulated in registers (each output tile
+// written once: the least memory traffic, for large tau).
+hipError_t launch_chol_multi_mode(double* G, double* U, double* X, int64_t ldg, int32_t tau,
+                                  int32_t nslots, int32_t kind, const void* AS, int32_t as_f32,
+                                  int64_t ldas, int64_t m, const int32_t* members, const int32_t* offs,
+                                  int32_t* status, const int32_t* done, int mode, hipStream_t s) {
   if (ldg % NB != 0) return hipErrorInvalidValue;
   MultiArgs a{G, U, X, ldg, (int32_t)(ldg / NB), tau, kind, AS, as_f32, ldas, m, members, offs,
               status, done};
   const int nt = a.nt;
-  const size_t diag_bytes = sizeof(double) * (3 * NB * LDT + NB);
-  const size_t pair_bytes = sizeof(double) * 2 * NB * LDT;
-  hipError_t e = hipFuncSetAttribute((const void*)k_chol_diag, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)diag_bytes);
+  const size_t two = sizeof(double) * 2 * NB * LDT;
+  const size_t three = sizeof(double) * 3 * NB * LDT;
+  hipError_t e = hipFuncSetAttribute((const void*)k_chol_start, hipFuncAttributeMaxDynamicSharedMemorySize, (int)two);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_chol_panel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)pair_bytes);
+    e = hipFuncSetAttribute((const void*)k_chol_step, hipFuncAttributeMaxDynamicSharedMemorySize, (int)three);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_chol_ll_inverse, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)pair_bytes);
+    e = hipFuncSetAttribute((const void*)k_chol_panel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)two);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_chol_update, hipFuncAttributeMaxDynamicSharedMemorySize, (int)two);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_chol_ll_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)two);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_chol_assemble, dim3(nt, nt, nslots), dim3(kThreads), 0, s, a);
-  for (int j = 0; j < nt; ++j) {
-    hipLaunchKernelGGL(k_chol_diag, dim3(nslots), dim3(kThreads), diag_bytes, s, a, j);
-    const int below = nt - j - 1;
-    if (below > 0) {
-      hipLaunchKernelGGL(k_chol_panel, dim3(below, nslots), dim3(kThreads), pair_bytes, s, a, j);
-      hipLaunchKernelGGL(k_chol_trail, dim3(below * (below + 1) / 2, nslots), dim3(kThreads), 0, s, a, j);
+  hipLaunchKernelGGL(k_chol_start, dim3(nt, nt, nslots), dim3(kThreads), two, s, a);
+  for (int st = 1; st <= nt; ++st) {
+    const int nF = (nt - st) * (nt - st + 1) / 2;
+    const int items = nF + (nt - st) * st + st * (st + 1) / 2;
+    if (mode == 0) {
+      hipLaunchKernelGGL(k_chol_step, dim3(items, nslots), dim3(kThreads), three, s, a, st);
+    } else if (mode == 1) {
+      hipLaunchKernelGGL(k_chol_panel, dim3(nt - 1, nslots), dim3(kThreads), two, s, a, st);
+      hipLaunchKernelGGL(k_chol_update, dim3(items, nslots), dim3(kThreads), two, s, a, st);
+    } else if (st < nt) {
+      // the first nt - st panel items are the L blocks, the first nF update items the F ones
+      hipLaunchKernelGGL(k_chol_panel, dim3(nt - st, nslots), dim3(kThreads), two, s, a, st);
+      hipLaunchKernelGGL(k_chol_update, dim3(nF, nslots), dim3(kThreads), two, s, a, st);
     }
   }
-  for (int d = 1; d < nt; ++d)
-    hipLaunchKernelGGL(k_chol_ll_inverse, dim3(nt - d, nslots), dim3(kThreads), pair_bytes, s, a, d);
-  hipLaunchKernelGGL(k_chol_lauum, dim3(nt * (nt + 1) / 2, nslots), dim3(kThreads), 0, s, a);
+  if (mode == 2) {
+    for (int d = 1; d < nt; ++d)
+      hipLaunchKernelGGL(k_chol_ll_inverse, dim3(nt - d, nslots), dim3(kThreads), two, s, a, d);
+    hipLaunchKernelGGL(k_chol_lauum, dim3(nt * (nt + 1) / 2, nslots), dim3(kThreads), 0, s, a);
+  }
   return hipGetLastError();
+}
+
+// Measured on tau = 256 .. 5184 with 2 .. 31 sketches: the fused steps lead while a step's
+// items fit on the chip about twice (up to 2.0x over mode 1's chain at nt = 8), mode 1 in
+// between (tau = 2048, 4 sketches: 2.07 ms against 3.40 and 3.73), mode 2 once the tile
+// products outweigh every chain (tau = 5184, 31 sketches: 164 ms against 213 and 395).
+int chol_multi_mode(int64_t nt, int64_t nslots) {
+  if (nslots * nt * nt <= 512) return 0;
+  return nslots * nt * nt * nt > 2000000 ? 2 : 1;
+}
+
+hipError_t launch_chol_multi(double* G, double* U, double* X, int64_t ldg, int32_t tau,
+                             int32_t nslots, int32_t kind, const void* AS, int32_t as_f32,
+                             int64_t ldas, int64_t m, const int32_t* members, const int32_t* offs,
+                             int32_t* status, const int32_t* done, hipStream_t s) {
+  return launch_chol_multi_mode(G, U, X, ldg, tau, nslots, kind, AS, as_f32, ldas, m, members, offs, status,
+                                done, chol_multi_mode(ldg / NB, nslots), s);
 }
 
 }  // namespace rs
