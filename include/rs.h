@@ -141,6 +141,12 @@ typedef struct rs_options {
                                creation with the same kernel (m x m, FP32 in mixed precision,
                                else FP64) and gathers each sketch's tau columns from it. Pays when
                                a solve takes more than about m / tau iterations and m^2 fits. */
+  int32_t refresh_early;    /* mixed precision, single solves: 1 (default) also recomputes r in
+                               FP64 at the end of a lookahead batch whose last tracked estimate
+                               ||r^k|| / ||r^0|| has reached tol (at most once per 4 iterations),
+                               so that the stop, which only a refreshed residual may trigger, is
+                               not delayed to the next multiple of refresh_every; 0: refreshes only
+                               every refresh_every iterations. Ignored by the batched solver. */
 } rs_options;
 
 /* How AS is formed for the count and SubCount sketches on CSR data (same result up to

@@ -161,6 +161,7 @@ struct rs_handle {
   int32_t* tr_count = nullptr;
 
   int64_t k = 0;          // iterations performed
+  int64_t last_early = -1000000;  // iteration of the last refresh taken on the tracked estimate
   int64_t batch_k0 = -1;  // iteration of slot 0 of the most recent batch
   int batch_n = 0;
   bool done = false;
@@ -677,6 +678,19 @@ void advance(rs_handle* h, int64_t iters) {
       rel_a = rel_b;
       k_b = k_end - 1;
       rel_b = rel;
+      // Mixed precision stops only on a refreshed residual. Besides every refresh_every
+      // iterations, refresh at this batch boundary once the tracked estimate has reached
+      // tol, so that a solve is not carried to the next multiple of refresh_every; a refresh
+      // that does not meet tol resets the estimate to the FP64 residual, and the next such
+      // refresh waits at least 4 iterations.
+      if (h->mixed && h->opt.refresh_early && rel <= h->opt.tol && k_end % h->opt.refresh_every != 0 &&
+          k_end - h->last_early >= 4) {
+        h->last_early = k_end;
+        refresh(h, k_end);
+        check_hip(hipMemcpyAsync(&f, h->flags, sizeof(DevFlags), hipMemcpyDeviceToHost, h->stream), "flags");
+        check_hip(hipStreamSynchronize(h->stream), "sync");
+        prof_collect(h, f.done ? f.k_done : INT64_MAX);
+      }
     }
     h->k = k_end;
     if (f.done) h->done = true;
@@ -709,6 +723,7 @@ rs_status rs_options_default(rs_options* o) {
   o->seed = 1;
   o->problem_id = 0;
   o->refresh_every = 20;
+  o->refresh_early = 1;
   o->lookahead = 0;
   o->stream = nullptr;
   o->graph_iters = 0;
@@ -791,6 +806,7 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
                                   "AROWS) with the momentum schedules"};
     if (o->precision == RS_PREC_MIXED_BF16 && o->refresh_every < 1)
       throw Fail{RS_EINVAL, "refresh_every must be >= 1"};
+    if (o->refresh_early != 0 && o->refresh_early != 1) throw Fail{RS_EINVAL, "refresh_early is 0 or 1"};
     h->mixed = o->precision == RS_PREC_MIXED_BF16;
     if (o->sampler < RS_SAMPLER_UNIFORM || o->sampler > RS_SAMPLER_DIAG) throw Fail{RS_EINVAL, "unknown sampler"};
     if (o->sparse_route < RS_ROUTE_AUTO || o->sparse_route > RS_ROUTE_AROWS)
@@ -1258,6 +1274,7 @@ rs_status rs_reset(rs_handle* h, uint64_t seed) {
   try {
     h->opt.seed = seed;
     h->k = 0;
+    h->last_early = -1000000;
     h->done = false;
     h->batch_k0 = -1;
     h->batch_n = 0;

@@ -50,7 +50,7 @@ class rs_options(ctypes.Structure):
                 ("trace_capacity", ctypes.c_int32), ("sparse_route", ctypes.c_int32),
                 ("pipeline", ctypes.c_int32), ("accelerated", ctypes.c_int32),
                 ("accel_mu", ctypes.c_double), ("accel_nu", ctypes.c_double),
-                ("dense_route", ctypes.c_int32)]
+                ("dense_route", ctypes.c_int32), ("refresh_early", ctypes.c_int32)]
 
 
 RS_SAMPLER_UNIFORM, RS_SAMPLER_LEARNED, RS_SAMPLER_DIAG = 0, 1, 2
@@ -612,9 +612,11 @@ class Solver:
                  precision="fp64", subcount_k=0, tol=1e-6, max_iter=100000, seed=1, problem_id=0,
                  eta=0.995, beta_max=0.5, gamma=1.0, beta=0.5, lookahead=0, refresh_every=20,
                  profile=False, stream=None, sampler="uniform", trace_every=0, trace_capacity=0,
-                 sparse_route="auto", pipeline=True, kernel_sigma=None, accel=None, dense_route="products"):
+                 sparse_route="auto", pipeline=True, kernel_sigma=None, accel=None, dense_route="products",
+                 refresh_early=True):
         o = rs_options_default()
         o.dense_route = {"products": 0, "gram": 1}[dense_route]
+        o.refresh_early = int(bool(refresh_early))
         if accel is not None:  # (mu, nu) of the accelerated method (Alg. 3)
             o.accelerated, o.accel_mu, o.accel_nu = 1, float(accel[0]), float(accel[1])
         o.form, o.sketch, o.tau = FORMS[form], SKETCHES[sketch], int(tau)

@@ -183,23 +183,60 @@ def test_csr_mixed_refresh_recomputes_true_residual(kind):
 
 @pytest.mark.parametrize("kind", ["count", "subcount"])
 def test_csr_mixed_stops_only_on_refreshed_residual(kind):
-    """A mixed CSR solve stops at the first refresh whose FP64 residual is <= tol: the stop
-    iteration is a multiple of refresh_every, the reported and recomputed residuals are <= tol,
-    and the weights reach the direct solution within 2 kappa tol."""
+    """A mixed CSR solve stops at the first refresh whose FP64 residual is <= tol. With
+    refreshes only every refresh_every iterations the stop iteration is a multiple of it; with
+    the early refresh (the default) it is that or the end of a lookahead batch whose last
+    tracked estimate had reached tol, no later than the first. Either way the reported and
+    recomputed residuals are <= tol and the weights reach the direct solution within 2 kappa tol."""
     p = inputs.make_csr(2000, 400, 0.02, 0.1, seed=64, dtype=np.float32)
     system = ridge_system(p.X, p.y, p.lam, "primal")
     tol = 1e-8
-    S = rs.Solver(p.X, p.y, p.lam, tau=40, sketch=kind, subcount_k=3, tol=tol, seed=3, precision="mixed",
-                  max_iter=200000, refresh_every=20)
-    w, st, rep = S.solve()
-    assert st == rs.RS_OK
-    assert rep.iters % 20 == 0 and rep.rel_res <= tol and rep.rel_res_true <= tol * 1.0001
-    hist = S.history()
-    assert hist[rep.iters] <= tol
     A = system.dense_A()
     w_direct = np.linalg.solve(A, system.b)
-    assert np.linalg.norm(w - w_direct) <= 2 * np.linalg.cond(A) * tol * np.linalg.norm(w_direct)
-    S.close()
+    iters = {}
+    for early in (False, True):
+        S = rs.Solver(p.X, p.y, p.lam, tau=40, sketch=kind, subcount_k=3, tol=tol, seed=3, precision="mixed",
+                      max_iter=200000, refresh_every=20, refresh_early=early)
+        w, st, rep = S.solve()
+        assert st == rs.RS_OK
+        hist = S.history()
+        if early:
+            assert rep.iters % 20 == 0 or hist[rep.iters - 1] <= tol
+        else:
+            assert rep.iters % 20 == 0
+        assert rep.rel_res <= tol and rep.rel_res_true <= tol * 1.0001
+        assert hist[rep.iters] <= tol
+        assert np.linalg.norm(w - w_direct) <= 2 * np.linalg.cond(A) * tol * np.linalg.norm(w_direct)
+        iters[early] = rep.iters
+        S.close()
+    assert iters[True] <= iters[False]
+
+
+@pytest.mark.parametrize("lookahead", [2, 5])
+def test_dense_mixed_early_refresh(lookahead):
+    """Dense mixed solve with small lookahead batches: the early refresh stops at the first
+    batch end whose tracked estimate reached tol and whose FP64 residual meets it (never
+    later than the refresh_every schedule), at a true residual <= tol."""
+    p = inputs.make_dense(2000, 400, 0.1, seed=7, dtype=np.float32, col_log_sigma=1.0)
+    system = ridge_system(p.X, p.y, p.lam, "primal")
+    tol = 1e-8
+    iters = {}
+    for early in (False, True):
+        S = rs.Solver(p.X, p.y, p.lam, tau=64, sketch="subsample", tol=tol, seed=3, precision="mixed",
+                      max_iter=200000, lookahead=lookahead, refresh_early=early)
+        w, st, rep = S.solve()
+        assert st == rs.RS_OK
+        hist = S.history()
+        x = S.state()[0]
+        true_rel = np.linalg.norm(system.matvec(x) - system.b) / np.linalg.norm(system.b)
+        assert true_rel <= tol * 1.0001 and rep.rel_res <= tol and hist[rep.iters] <= tol
+        if early:
+            assert rep.iters % 20 == 0 or (rep.iters % lookahead == 0 and hist[rep.iters - 1] <= tol)
+        else:
+            assert rep.iters % 20 == 0
+        iters[early] = rep.iters
+        S.close()
+    assert iters[True] <= iters[False]
 
 
 def test_csr_mixed_rejections():
