@@ -195,7 +195,16 @@ def kernel_table(prof, wl, workload, n, d, nnz, m, K, nsel, total, a_nnz=0):
         flops = 2.0 * m * wl["tau"] * K * kd["slots_per_launch"] * wl.get("as_products", 1)
         tfs = flops / (kd["avg_ms"] * 1e-3) / 1e12
         peak = BF16_PEAK_TFS if wl["precision"] == "mixed" else FP64_PEAK_TFS
-        roofline.update({"kernel": "k_as_dense_bf16" if wl["precision"] == "mixed" else as_name,
+        if wl["precision"] == "mixed":
+            # the library's K split for launches with fewer 256 x 256 tiles than compute units
+            # (bf16_split_factor): doubling while tiles * split * 2 <= 256 and every K range
+            # keeps >= 32 stages of 64; the split form adds an in-order reduction launch
+            ntiles = -(-m // 256) * -(-int(kd["slots_per_launch"] * wl["tau"]) // 256)
+            nk, split = -(-K // 64), 1
+            while ntiles * split * 2 <= 256 and nk >= split * 2 * 32:
+                split *= 2
+            mixed_name = "k_as_dense_bf16_split+k_splitk_reduce" if split > 1 else "k_as_dense_bf16"
+        roofline.update({"kernel": mixed_name if wl["precision"] == "mixed" else as_name,
                          "bound": "mfma", "achieved": round(tfs, 1), "peak": peak, "unit": "TFLOP/s",
                          "frac": round(tfs / peak, 4), "alg_flops_per_launch": flops,
                          "hbm_gbs_algorithmic": kd["gbs"]})
@@ -208,7 +217,13 @@ def kernel_table(prof, wl, workload, n, d, nnz, m, K, nsel, total, a_nnz=0):
         flops = float(tau) ** 3 * kd["slots_per_launch"]
         tfs = flops / (kd["avg_ms"] * 1e-3) / 1e12
         tiled = ldg >= 128 and kd["slots_per_launch"] < 128
-        roofline.update({"kernel": "k_chol_assemble+ll_diag+ll_panel+ll_inverse+lauum" if tiled else "k_chol_inverse",
+        # the library's tiled form (chol_multi_mode): fused steps, panel + update, or the
+        # factor steps followed by the inverse-by-distance and U U^T chains
+        nt, ns = ldg // 64, kd["slots_per_launch"]
+        tiled_name = ("k_chol_start+k_chol_step" if ns * nt * nt <= 512 else
+                      "k_chol_start+k_chol_panel+k_chol_update" if ns * nt ** 3 <= 2e6 else
+                      "k_chol_start+k_chol_panel+k_chol_update+k_chol_ll_inverse+k_chol_lauum")
+        roofline.update({"kernel": tiled_name if tiled else "k_chol_inverse",
                          "bound": "mfma", "achieved": round(tfs, 1), "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
                          "frac": round(tfs / FP64_PEAK_TFS, 4), "alg_flops_per_launch": flops,
                          "hbm_gbs_algorithmic": kd["gbs"]})
@@ -219,6 +234,7 @@ def kernel_table(prof, wl, workload, n, d, nnz, m, K, nsel, total, a_nnz=0):
         src = {"k_as_sparse_bucket": ["k_sparse.hip"], "k_update": ["k_update.hip"],
                "k_as_dense_f64_128": ["k_dense.hip"], "k_as_arows_lds": ["k_sparse_a.hip"],
                "k_as_dense_bf16": ["k_dense_bf16.hip"],
+               "k_as_dense_bf16_split+k_splitk_reduce": ["k_dense_bf16.hip"],
                "k_g_from_as": ["k_sparse_a.hip"]
                }.get(roofline["kernel"], [])
         if src and tf.get("source_sha") == kernel_source_sha(src):
