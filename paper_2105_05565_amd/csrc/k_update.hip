@@ -399,6 +399,21 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const double* __restrict_
   }
 }
 
+// One launch gathers the host's view of a finished batch (out: mapped host memory).
+__global__ __launch_bounds__(256) void k_batch_report(const DevFlags* __restrict__ flags,
+                                                      const int32_t* __restrict__ err,
+                                                      const double* __restrict__ hist, int64_t k,
+                                                      const int32_t* __restrict__ status, int32_t nb,
+                                                      BatchReport* __restrict__ out) {
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) out->status[i] = status[i];
+  if (threadIdx.x == 0) {
+    out->flags = *flags;
+    out->err = *err;
+    out->nb = nb;
+    out->rel = k > 0 ? hist[k - 1] : 1.0;
+  }
+}
+
 }  // namespace
 
 int32_t update_partials(int64_t m, int32_t tau) {
@@ -511,6 +526,12 @@ hipError_t launch_update_accel(const double* AS, int64_t ldas, int32_t tau, cons
 hipError_t launch_finalize(const double* partials, int32_t npart, DevFlags* flags, double* hist,
                            int64_t k, double tol, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, partials, npart, flags, hist, k, tol);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_report(const DevFlags* flags, const int32_t* err, const double* hist, int64_t k,
+                               const int32_t* status, int32_t nb, BatchReport* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_report, dim3(1), dim3(256), 0, s, flags, err, hist, k, status, nb, out);
   return hipGetLastError();
 }
 

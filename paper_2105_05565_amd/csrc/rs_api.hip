@@ -114,6 +114,9 @@ struct rs_handle {
   hipStream_t prep_stream = nullptr;
   hipEvent_t ev_ready[2] = {nullptr, nullptr};
   hipEvent_t ev_start = nullptr;
+  hipEvent_t ev_prep_done = nullptr;  // recorded on prep_stream before a batch report
+  BatchReport* rep_host = nullptr;    // mapped pinned memory written by k_batch_report
+  BatchReport* rep_dev = nullptr;     // its device address
   int64_t ldg = 0;
   int64_t ldas = 0;  // row stride of AS (tau rounded up to 8)
   double* rho = nullptr;
@@ -200,11 +203,16 @@ void dfree_all(rs_handle* h) {
   h->allocs.clear();
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   h->ev.clear();
-  for (hipEvent_t* e : {&h->ev_ready[0], &h->ev_ready[1], &h->ev_start})
+  for (hipEvent_t* e : {&h->ev_ready[0], &h->ev_ready[1], &h->ev_start, &h->ev_prep_done})
     if (*e) {
       (void)hipEventDestroy(*e);
       *e = nullptr;
     }
+  if (h->rep_host) {
+    (void)hipHostFree(h->rep_host);
+    h->rep_host = nullptr;
+    h->rep_dev = nullptr;
+  }
   if (h->prep_stream) {
     (void)hipStreamDestroy(h->prep_stream);
     h->prep_stream = nullptr;
@@ -657,14 +665,18 @@ void advance(rs_handle* h, int64_t iters) {
                   "finalize");
       }
     }
-    DevFlags f{};
-    int32_t err = 0;
-    check_hip(hipMemcpyAsync(&f, h->flags, sizeof(DevFlags), hipMemcpyDeviceToHost, h->stream), "flags");
-    check_hip(hipMemcpyAsync(st.data(), h->status, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, h->stream),
-              "status");
+    // One report kernel after the batch (and after the preparation queued ahead, so that
+    // its errors are seen now) and one wait, instead of a round trip per value.
+    if (pipe) {
+      check_hip(hipEventRecord(h->ev_prep_done, h->prep_stream), "event");
+      check_hip(hipStreamWaitEvent(h->stream, h->ev_prep_done, 0), "wait");
+    }
+    check_hip(launch_batch_report(h->flags, h->err, h->hist, k_enq, h->status, nb, h->rep_dev, h->stream),
+              "report");
     check_hip(hipStreamSynchronize(h->stream), "sync");
-    if (pipe) check_hip(hipStreamSynchronize(h->prep_stream), "sync");
-    check_hip(hipMemcpy(&err, h->err, sizeof(int32_t), hipMemcpyDeviceToHost), "err");
+    DevFlags f = h->rep_host->flags;
+    const int32_t err = h->rep_host->err;
+    for (int i = 0; i < nb; ++i) st[i] = h->rep_host->status[i];
     prof_collect(h, f.done ? f.k_done : INT64_MAX);
     if (err) throw Fail{RS_EDEVICE, "internal sketch limit hit (code " + std::to_string(err) + ")"};
     const int64_t k_end = f.done ? f.k_done : k_enq;
@@ -672,8 +684,7 @@ void advance(rs_handle* h, int64_t iters) {
       if (st[i] != 0 && h->batch_k0 + i < k_end)
         throw Fail{RS_ESINGULAR, "non-positive pivot in the Cholesky factorisation of S^T A S"};
     if (!f.done && left > 0 && k_end > 0) {
-      double rel = 0.0;  // ||r^{k_end - 1}||, written by the batch's last delta launch
-      check_hip(hipMemcpy(&rel, h->hist + (k_end - 1), sizeof(double), hipMemcpyDeviceToHost), "hist");
+      const double rel = h->rep_host->rel;  // ||r^{k_end - 1}||, from the batch's last delta launch
       k_a = k_b;
       rel_a = rel_b;
       k_b = k_end - 1;
@@ -1114,9 +1125,12 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
     if (h->pipeline) {
       // default priority, like the solver's stream
       check_hip(hipStreamCreateWithFlags(&h->prep_stream, hipStreamNonBlocking), "stream create");
-      for (hipEvent_t* e : {&h->ev_ready[0], &h->ev_ready[1], &h->ev_start})
+      for (hipEvent_t* e : {&h->ev_ready[0], &h->ev_ready[1], &h->ev_start, &h->ev_prep_done})
         check_hip(hipEventCreateWithFlags(e, hipEventDisableTiming), "event create");
     }
+    check_hip(hipHostMalloc((void**)&h->rep_host, batch_report_bytes(B), hipHostMallocMapped | hipHostMallocCoherent),
+              "host alloc");
+    check_hip(hipHostGetDevicePointer((void**)&h->rep_dev, h->rep_host, 0), "host pointer");
     h->rho = dalloc<double>(h, h->ldg);
     if (h->sparse && !h->arows) h->tbuf = dalloc<char>(h, (size_t)B * sparse_t_bytes(h->vals_f32, h->nnz));
     h->W = dalloc<double>(h, (size_t)B * h->ldg * h->ldg);

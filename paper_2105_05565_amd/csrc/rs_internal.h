@@ -60,6 +60,20 @@ struct DevFlags {
   double r0norm;     // ||r^0||
 };
 
+// What the host reads after a lookahead batch, gathered by one kernel into host memory:
+// the flags, the error word, ||r^{k-1}|| / ||r^0|| of the tracked residual and the
+// factorisation status of the batch's sketches (status[nb], allocated with the report).
+struct BatchReport {
+  DevFlags flags;
+  int32_t err;
+  int32_t nb;
+  double rel;
+  int32_t status[1];
+};
+inline size_t batch_report_bytes(int32_t nmax) { return sizeof(BatchReport) + sizeof(int32_t) * nmax; }
+hipError_t launch_batch_report(const DevFlags* flags, const int32_t* err, const double* hist, int64_t k,
+                               const int32_t* status, int32_t nb, BatchReport* out, hipStream_t s);
+
 // ---------------------------------------------------------------------------
 // Launchers (host functions defined in the .hip files).
 // ---------------------------------------------------------------------------
