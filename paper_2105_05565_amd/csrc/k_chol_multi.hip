@@ -6,9 +6,9 @@
 // 64 x 64 tile of every sketch is a workgroup, and the sequential structure of a
 // right-looking algorithm is carried by kernel boundaries on the stream. With nt tiles
 // per side, the factorisation, the inverse W = L^{-1} and the product G^{-1} = W^T W all
-// advance together, one block column per launch, in nt + 1 launches:
+// advance together, one block column per launch, in nt + 2 launches:
 //
-//   start                  G assembled (gathered rows of AS for the subsample sketch,
+//   assemble, diag0        G assembled (gathered rows of AS for the subsample sketch,
 //                          identity padding and empty buckets); tile (0, 0) factored in
 //                          LDS, X_0 = L_00^{-1} stored
 //   step s = 1 .. nt, k = s - 1, one workgroup per item:
@@ -46,7 +46,26 @@ struct MultiArgs {
   const int32_t* offs;
   int32_t* status;
   const int32_t* done;
+  int32_t nslots;
+  int32_t xcd;  // 1: the items of a sketch on one XCD (see item_of_block)
 };
+
+// Sketch and item of this workgroup. Plain layout: grid (items, nslots). XCD layout (many
+// sketches): a 1-D grid of 8 * ceil(nslots / 8) * items workgroups; workgroup b runs on XCD
+// b % 8, sketches are dealt round-robin to the XCDs and each XCD takes its sketches' items
+// one sketch after the other, so the tiles a sketch's items share stay in that XCD's L2.
+// Returns false for the padding workgroups of the XCD layout.
+__device__ __forceinline__ bool item_of_block(const MultiArgs& a, int items, int64_t* slot, int* item) {
+  if (!a.xcd) {
+    *slot = blockIdx.y;
+    *item = blockIdx.x;
+    return true;
+  }
+  const int b = blockIdx.x, q = b >> 3;
+  *slot = (b & 7) + 8 * (q / items);
+  *item = q % items;
+  return *slot < a.nslots;
+}
 
 __device__ __forceinline__ double* tile(double* base, int64_t ld, int i, int j) {
   return base + (int64_t)i * NB * ld + (int64_t)j * NB;
@@ -62,13 +81,10 @@ __device__ __forceinline__ void store_x(double* X, double* Uss, int64_t ldg, con
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_chol_start(MultiArgs a) {
-  extern __shared__ __align__(16) double lds[];
-  __shared__ int bad;
+__global__ __launch_bounds__(kThreads) void k_chol_assemble(MultiArgs a) {
   if (*a.done) return;
   const int64_t slot = blockIdx.z;
   const int ti = blockIdx.y, tj = blockIdx.x;
-  const bool first = ti == 0 && tj == 0;
   double* G = a.G + slot * a.ldg * a.ldg;
   const int32_t* offs = a.offs + slot * (a.tau + 1);
   const int32_t* members = a.members + slot * a.tau;  // subsample: nsel = tau
@@ -84,10 +100,17 @@ __global__ __launch_bounds__(kThreads) void k_chol_start(MultiArgs a) {
     } else if (gr == gc && offs[gr + 1] == offs[gr]) {
       *g = 1.0;  // empty bucket: zero row and column of S^T A S
     }
-    if (first) lds[r * LDT + c] = *g;
   }
-  if (!first) return;
+}
+
+// Tile (0, 0) of every sketch factored in LDS: X_0 and U_00, and the sketch's status.
+__global__ __launch_bounds__(kThreads) void k_chol_diag0(MultiArgs a) {
+  extern __shared__ __align__(16) double lds[];
+  __shared__ int bad;
+  if (*a.done) return;
+  const int64_t slot = blockIdx.x;
   if (threadIdx.x == 0) bad = 0;
+  load_tile(lds, a.G + slot * a.ldg * a.ldg, a.ldg, false);
   __syncthreads();
   factor_diag_tile(lds, lds + NB * LDT, &bad);
   store_x(a.X + slot * a.nt * NB * NB, a.U + slot * a.ldg * a.ldg, a.ldg, lds + NB * LDT);
@@ -116,12 +139,13 @@ __global__ __launch_bounds__(kThreads) void k_chol_step(MultiArgs a, int s) {
   __shared__ int bad;
   if (*a.done) return;
   const int nt = a.nt, k = s - 1;
-  const int64_t slot = blockIdx.y;
+  const int nF = (nt - s) * (nt - s + 1) / 2, nI = (nt - s) * s;
+  int64_t slot;
+  int item;
+  if (!item_of_block(a, nF + nI + s * (s + 1) / 2, &slot, &item)) return;
   double* G = a.G + slot * a.ldg * a.ldg;
   double* U = a.U + slot * a.ldg * a.ldg;
   const double* Xk = a.X + (slot * nt + k) * NB * NB;
-  const int nF = (nt - s) * (nt - s + 1) / 2, nI = (nt - s) * s;
-  int item = blockIdx.x;
   if (item < nF) {
     // F: G_il -= L_ik L_lk^T
     int i, l;
@@ -257,17 +281,18 @@ __global__ __launch_bounds__(kThreads) void k_chol_step(MultiArgs a, int s) {
 // Work-optimal form of the same steps, two launches per step (no block is formed twice).
 // Panel of step s (k = s - 1): L_ik = G_ik X_k^T stored over G_ik (i >= s), and row k of W,
 // W_kj = -X_k T_kj stored over T_kj (j < k). LDS: two tiles.
-__global__ __launch_bounds__(kThreads) void k_chol_panel(MultiArgs a, int s) {
+__global__ __launch_bounds__(kThreads) void k_chol_panel(MultiArgs a, int s, int items) {
   extern __shared__ __align__(16) double lds[];
   double* tx = lds;
   double* ta = lds + NB * LDT;
   if (*a.done) return;
   const int nt = a.nt, k = s - 1;
-  const int64_t slot = blockIdx.y;
+  int64_t slot;
+  int item;
+  if (!item_of_block(a, items, &slot, &item)) return;
   double* G = a.G + slot * a.ldg * a.ldg;
   double* U = a.U + slot * a.ldg * a.ldg;
   const double* Xk = a.X + (slot * nt + k) * NB * NB;
-  const int item = blockIdx.x;
   const bool lpanel = item < nt - s;
   double* dst = lpanel ? tile(G, a.ldg, s + item, k) : tile(U, a.ldg, k, item - (nt - s));
   load_tile(tx, Xk, NB, false);
@@ -286,19 +311,20 @@ __global__ __launch_bounds__(kThreads) void k_chol_panel(MultiArgs a, int s) {
 // Updates of step s from the stored panel: F (s <= l <= i): G_il -= L_ik L_lk^T, the item
 // (s, s) then factoring G_ss; I (i >= s, j <= k): T_ij (+)= L_ik W_kj; A (j <= i <= k):
 // (G^{-1})_ij (+)= W_ki^T W_kj. W_kk = X_k. LDS: two tiles.
-__global__ __launch_bounds__(kThreads) void k_chol_update(MultiArgs a, int s) {
+__global__ __launch_bounds__(kThreads) void k_chol_update(MultiArgs a, int s, int items) {
   extern __shared__ __align__(16) double lds[];
   double* ta = lds;
   double* tb = lds + NB * LDT;
   __shared__ int bad;
   if (*a.done) return;
   const int nt = a.nt, k = s - 1;
-  const int64_t slot = blockIdx.y;
+  const int nF = (nt - s) * (nt - s + 1) / 2, nI = (nt - s) * s;
+  int64_t slot;
+  int item;
+  if (!item_of_block(a, items, &slot, &item)) return;
   double* G = a.G + slot * a.ldg * a.ldg;
   double* U = a.U + slot * a.ldg * a.ldg;
   const double* Xk = a.X + (slot * nt + k) * NB * NB;
-  const int nF = (nt - s) * (nt - s + 1) / 2, nI = (nt - s) * s;
-  int item = blockIdx.x;
   // W_kj (j <= k) and its source: U_kj, or X_k for j = k
   auto wsrc = [&](int j, int64_t* ld) -> const double* {
     *ld = j < k ? a.ldg : NB;
@@ -386,8 +412,10 @@ __global__ __launch_bounds__(kThreads) void k_chol_ll_inverse(MultiArgs a, int d
   double* tt = lds;
   double* tx = lds + NB * LDT;
   if (*a.done) return;
-  const int64_t slot = blockIdx.y;
-  const int j = (int)blockIdx.x, i = j + d;
+  int64_t slot;
+  int j;
+  if (!item_of_block(a, a.nt - d, &slot, &j)) return;
+  const int i = j + d;
   double* G = a.G + slot * a.ldg * a.ldg;
   double* U = a.U + slot * a.ldg * a.ldg;
   Acc c;
@@ -408,9 +436,10 @@ __global__ __launch_bounds__(kThreads) void k_chol_ll_inverse(MultiArgs a, int d
 // workgroup, written to both triangles.
 __global__ __launch_bounds__(kThreads) void k_chol_lauum(MultiArgs a) {
   if (*a.done) return;
-  const int64_t slot = blockIdx.y;
-  int i, j;
-  lower_pair(blockIdx.x, 0, &i, &j);
+  int64_t slot;
+  int item, i, j;
+  if (!item_of_block(a, a.nt * (a.nt + 1) / 2, &slot, &item)) return;
+  lower_pair(item, 0, &i, &j);
   double* G = a.G + slot * a.ldg * a.ldg;
   double* U = a.U + slot * a.ldg * a.ldg;
   Acc c;
@@ -428,23 +457,38 @@ __global__ __launch_bounds__(kThreads) void k_chol_lauum(MultiArgs a) {
 
 size_t chol_multi_x_bytes(int64_t ldg) { return sizeof(double) * (size_t)(ldg / NB) * NB * NB; }
 
+// Measured on tau = 256 .. 5184 with 2 .. 31 sketches: the fused steps lead while a step's
+// items fit on the chip about twice (up to 2.0x over mode 1's chain at nt = 8), mode 1 in
+// between (tau = 2048, 4 sketches: 2.06 ms against 3.38 and 3.72; tau = 1024, 31: 1.92 ms
+// against 3.25 and 1.97), mode 2 once the tile products outweigh every chain (tau = 2048,
+// 16 sketches: 6.54 ms against 7.06; tau = 5184, 31: 161 ms against 214 and 395).
+int chol_multi_mode(int64_t nt, int64_t nslots) {
+  if (nslots * nt * nt <= 512) return 0;
+  return nslots * nt * nt * nt > 300000 ? 2 : 1;
+}
+
+// The XCD layout keeps a sketch's tiles in one L2; it pays with 8 or more sketches whose
+// matrices are not far larger than the L2 (tau = 1024, 31 sketches: 1.92 ms against 2.15;
+// tau = 5184: 165 ms against 161).
+int chol_multi_xcd(int64_t nt, int64_t nslots) { return nslots >= 8 && nt <= 40 ? 1 : 0; }
+
 // mode 0: one launch per step, each workgroup forming the L and W blocks it reads (three
-// tile products per item, nt + 1 launches: the shortest chain); mode 1: panel and update
-// launches per step (one tile product per item, a third of the work, 2 nt + 1 launches);
+// tile products per item, nt + 2 launches: the shortest chain); mode 1: panel and update
+// launches per step (one tile product per item, a third of the work, 2 nt + 2 launches);
 // mode 2: panel and update launches for the factorisation alone, then the inverse by
 // distance and U U^T as chains of products accumulated in registers (each output tile
 // written once: the least memory traffic, for large tau).
 hipError_t launch_chol_multi_mode(double* G, double* U, double* X, int64_t ldg, int32_t tau,
                                   int32_t nslots, int32_t kind, const void* AS, int32_t as_f32,
                                   int64_t ldas, int64_t m, const int32_t* members, const int32_t* offs,
-                                  int32_t* status, const int32_t* done, int mode, hipStream_t s) {
+                                  int32_t* status, const int32_t* done, int mode, int xcd, hipStream_t s) {
   if (ldg % NB != 0) return hipErrorInvalidValue;
   MultiArgs a{G, U, X, ldg, (int32_t)(ldg / NB), tau, kind, AS, as_f32, ldas, m, members, offs,
-              status, done};
+              status, done, nslots, xcd >= 0 ? xcd : chol_multi_xcd(ldg / NB, nslots)};
   const int nt = a.nt;
   const size_t two = sizeof(double) * 2 * NB * LDT;
   const size_t three = sizeof(double) * 3 * NB * LDT;
-  hipError_t e = hipFuncSetAttribute((const void*)k_chol_start, hipFuncAttributeMaxDynamicSharedMemorySize, (int)two);
+  hipError_t e = hipFuncSetAttribute((const void*)k_chol_diag0, hipFuncAttributeMaxDynamicSharedMemorySize, (int)two);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_chol_step, hipFuncAttributeMaxDynamicSharedMemorySize, (int)three);
   if (e == hipSuccess)
@@ -454,36 +498,32 @@ hipError_t launch_chol_multi_mode(double* G, double* U, double* X, int64_t ldg, 
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_chol_ll_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)two);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_chol_start, dim3(nt, nt, nslots), dim3(kThreads), two, s, a);
+  hipLaunchKernelGGL(k_chol_assemble, dim3(nt, nt, nslots), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(k_chol_diag0, dim3(nslots), dim3(kThreads), two, s, a);
+  // grid of `items` work items per sketch in the layout item_of_block expects
+  auto grid = [&](int items) {
+    return a.xcd ? dim3((unsigned)(8 * ((nslots + 7) / 8) * items)) : dim3(items, nslots);
+  };
   for (int st = 1; st <= nt; ++st) {
     const int nF = (nt - st) * (nt - st + 1) / 2;
     const int items = nF + (nt - st) * st + st * (st + 1) / 2;
     if (mode == 0) {
-      hipLaunchKernelGGL(k_chol_step, dim3(items, nslots), dim3(kThreads), three, s, a, st);
+      hipLaunchKernelGGL(k_chol_step, grid(items), dim3(kThreads), three, s, a, st);
     } else if (mode == 1) {
-      hipLaunchKernelGGL(k_chol_panel, dim3(nt - 1, nslots), dim3(kThreads), two, s, a, st);
-      hipLaunchKernelGGL(k_chol_update, dim3(items, nslots), dim3(kThreads), two, s, a, st);
+      hipLaunchKernelGGL(k_chol_panel, grid(nt - 1), dim3(kThreads), two, s, a, st, nt - 1);
+      hipLaunchKernelGGL(k_chol_update, grid(items), dim3(kThreads), two, s, a, st, items);
     } else if (st < nt) {
       // the first nt - st panel items are the L blocks, the first nF update items the F ones
-      hipLaunchKernelGGL(k_chol_panel, dim3(nt - st, nslots), dim3(kThreads), two, s, a, st);
-      hipLaunchKernelGGL(k_chol_update, dim3(nF, nslots), dim3(kThreads), two, s, a, st);
+      hipLaunchKernelGGL(k_chol_panel, grid(nt - st), dim3(kThreads), two, s, a, st, nt - st);
+      hipLaunchKernelGGL(k_chol_update, grid(nF), dim3(kThreads), two, s, a, st, nF);
     }
   }
   if (mode == 2) {
     for (int d = 1; d < nt; ++d)
-      hipLaunchKernelGGL(k_chol_ll_inverse, dim3(nt - d, nslots), dim3(kThreads), two, s, a, d);
-    hipLaunchKernelGGL(k_chol_lauum, dim3(nt * (nt + 1) / 2, nslots), dim3(kThreads), 0, s, a);
+      hipLaunchKernelGGL(k_chol_ll_inverse, grid(nt - d), dim3(kThreads), two, s, a, d);
+    hipLaunchKernelGGL(k_chol_lauum, grid(nt * (nt + 1) / 2), dim3(kThreads), 0, s, a);
   }
   return hipGetLastError();
-}
-
-// Measured on tau = 256 .. 5184 with 2 .. 31 sketches: the fused steps lead while a step's
-// items fit on the chip about twice (up to 2.0x over mode 1's chain at nt = 8), mode 1 in
-// between (tau = 2048, 4 sketches: 2.07 ms against 3.40 and 3.73), mode 2 once the tile
-// products outweigh every chain (tau = 5184, 31 sketches: 164 ms against 213 and 395).
-int chol_multi_mode(int64_t nt, int64_t nslots) {
-  if (nslots * nt * nt <= 512) return 0;
-  return nslots * nt * nt * nt > 2000000 ? 2 : 1;
 }
 
 hipError_t launch_chol_multi(double* G, double* U, double* X, int64_t ldg, int32_t tau,
@@ -491,7 +531,7 @@ hipError_t launch_chol_multi(double* G, double* U, double* X, int64_t ldg, int32
                              int64_t ldas, int64_t m, const int32_t* members, const int32_t* offs,
                              int32_t* status, const int32_t* done, hipStream_t s) {
   return launch_chol_multi_mode(G, U, X, ldg, tau, nslots, kind, AS, as_f32, ldas, m, members, offs, status,
-                                done, chol_multi_mode(ldg / NB, nslots), s);
+                                done, chol_multi_mode(ldg / NB, nslots), -1, s);
 }
 
 }  // namespace rs

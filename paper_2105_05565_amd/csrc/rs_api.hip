@@ -1076,12 +1076,13 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
     if (gram_bytes + per_slot > budget_all)
       throw Fail{RS_ENOMEM, "dense_route = 1: the formed A (" + std::to_string(gram_bytes >> 20) +
                                 " MiB) and one lookahead slot exceed the 48 GiB the solver budgets"};
-    // Default lookahead: 256 sketches, fewer when one sketch's contraction is large
-    // (the sketches formed past the stopping iteration are wasted work). On the formed-A
-    // route a sketch's AS is a gather of tau columns, so the large batches stay: they also
-    // keep the factorisations on the one-workgroup-per-sketch kernel.
+    // Default lookahead: 256 sketches, fewer when one sketch's contraction is large (the
+    // sketches formed past the stopping iteration are wasted work, and the first batch's
+    // preparation is not overlapped). The formed-A route follows the same rule: its
+    // factorisations of 32 sketches run device-wide (C3 with A formed: 0.075 s at 32 against
+    // 0.108 s at 256).
     int B = 256;
-    if (!h->sparse && o->dense_route != 1 && 2.0 * (double)h->m * (double)h->K * (double)h->tau > 1e11) B = 32;
+    if (!h->sparse && 2.0 * (double)h->m * (double)h->K * (double)h->tau > 1e11) B = 32;
     // the learned proposal is recomputed once per batch: short batches keep it fresh (the BF16
     // products of a short batch are split over K, so they still fill the chip)
     if (o->sampler == RS_SAMPLER_LEARNED) B = 2;
