@@ -6,11 +6,12 @@
 // 64 x 64 tile of every sketch is a workgroup, and the sequential structure of a
 // right-looking algorithm is carried by kernel boundaries on the stream. With nt tiles
 // per side, the factorisation, the inverse W = L^{-1} and the product G^{-1} = W^T W all
-// advance together, one block column per launch, in nt + 2 launches:
+// advance together, one block column per launch, in nt + 1 launches:
 //
-//   assemble, diag0        G assembled (gathered rows of AS for the subsample sketch,
+//   assemble (+ diag0)     G assembled (gathered rows of AS for the subsample sketch,
 //                          identity padding and empty buckets); tile (0, 0) factored in
-//                          LDS, X_0 = L_00^{-1} stored
+//                          LDS, X_0 = L_00^{-1} stored (by the assembly's workgroup of that
+//                          tile, or in a launch of its own when many sketches are assembled)
 //   step s = 1 .. nt, k = s - 1, one workgroup per item:
 //     F  (s <= l <= i)     G_il -= L_ik L_lk^T with L_ik = G_ik X_k^T formed in the
 //                          workgroup; the item (s, s) then factors G_ss in LDS: X_s
@@ -81,10 +82,16 @@ __device__ __forceinline__ void store_x(double* X, double* Uss, int64_t ldg, con
   }
 }
 
+// FACTOR0: the workgroup of tile (0, 0) also factors it (dynamic LDS: two tiles for every
+// workgroup, so only with few sketches); otherwise k_chol_diag0 does, in a launch of its own.
+template <bool FACTOR0>
 __global__ __launch_bounds__(kThreads) void k_chol_assemble(MultiArgs a) {
+  extern __shared__ __align__(16) double lds[];
+  __shared__ int bad;
   if (*a.done) return;
   const int64_t slot = blockIdx.z;
   const int ti = blockIdx.y, tj = blockIdx.x;
+  const bool first = FACTOR0 && ti == 0 && tj == 0;
   double* G = a.G + slot * a.ldg * a.ldg;
   const int32_t* offs = a.offs + slot * (a.tau + 1);
   const int32_t* members = a.members + slot * a.tau;  // subsample: nsel = tau
@@ -100,7 +107,14 @@ __global__ __launch_bounds__(kThreads) void k_chol_assemble(MultiArgs a) {
     } else if (gr == gc && offs[gr + 1] == offs[gr]) {
       *g = 1.0;  // empty bucket: zero row and column of S^T A S
     }
+    if (first) lds[r * LDT + c] = *g;
   }
+  if (!first) return;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  factor_diag_tile(lds, lds + NB * LDT, &bad);
+  store_x(a.X + slot * a.nt * NB * NB, a.U + slot * a.ldg * a.ldg, a.ldg, lds + NB * LDT);
+  if (threadIdx.x == 0) a.status[slot] = bad;
 }
 
 // Tile (0, 0) of every sketch factored in LDS: X_0 and U_00, and the sketch's status.
@@ -473,7 +487,7 @@ int chol_multi_mode(int64_t nt, int64_t nslots) {
 int chol_multi_xcd(int64_t nt, int64_t nslots) { return nslots >= 8 && nt <= 40 ? 1 : 0; }
 
 // mode 0: one launch per step, each workgroup forming the L and W blocks it reads (three
-// tile products per item, nt + 2 launches: the shortest chain); mode 1: panel and update
+// tile products per item, nt + 1 launches: the shortest chain); mode 1: panel and update
 // launches per step (one tile product per item, a third of the work, 2 nt + 2 launches);
 // mode 2: panel and update launches for the factorisation alone, then the inverse by
 // distance and U U^T as chains of products accumulated in registers (each output tile
@@ -490,6 +504,9 @@ hipError_t launch_chol_multi_mode(double* G, double* U, double* X, int64_t ldg, 
   const size_t three = sizeof(double) * 3 * NB * LDT;
   hipError_t e = hipFuncSetAttribute((const void*)k_chol_diag0, hipFuncAttributeMaxDynamicSharedMemorySize, (int)two);
   if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_chol_assemble<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)two);
+  if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_chol_step, hipFuncAttributeMaxDynamicSharedMemorySize, (int)three);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_chol_panel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)two);
@@ -498,8 +515,12 @@ hipError_t launch_chol_multi_mode(double* G, double* U, double* X, int64_t ldg, 
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_chol_ll_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)two);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_chol_assemble, dim3(nt, nt, nslots), dim3(kThreads), 0, s, a);
-  hipLaunchKernelGGL(k_chol_diag0, dim3(nslots), dim3(kThreads), two, s, a);
+  if (mode == 0) {
+    hipLaunchKernelGGL(k_chol_assemble<true>, dim3(nt, nt, nslots), dim3(kThreads), two, s, a);
+  } else {
+    hipLaunchKernelGGL(k_chol_assemble<false>, dim3(nt, nt, nslots), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(k_chol_diag0, dim3(nslots), dim3(kThreads), two, s, a);
+  }
   // grid of `items` work items per sketch in the layout item_of_block expects
   auto grid = [&](int items) {
     return a.xcd ? dim3((unsigned)(8 * ((nslots + 7) / 8) * items)) : dim3(items, nslots);
