@@ -460,11 +460,16 @@ def main_learned(args):
     T.add_traces(U)
     records = T.records
     U.close()
+    # the listwise cross-entropy over all records before and after training, and its floor
+    # (the mean entropy of the records' targets, reached only if softmax(s) matched them)
+    loss_before, loss_floor = T.evaluate()
     losses = T.fit(10, batch=16, lr=1e-3, shuffle_seed=7)
+    loss_after, _ = T.evaluate()
     params = T.params()
     T.close()
     train_s = time.perf_counter() - t0
     print(f"[bench] trained on {records} records from {args.train_solves} solves in {train_s:.1f} s; "
+          f"loss {loss_before:.4f} -> {loss_after:.4f} (floor {loss_floor:.4f}); "
           f"epoch losses {[round(v, 4) for v in losses]}", file=sys.stderr, flush=True)
 
     look = args.lookahead if args.lookahead > 0 else 2
@@ -536,7 +541,9 @@ def main_learned(args):
         "final_rel_res_true_max": max(rels_true),
         "training": {"records": records, "seconds": round(train_s, 1),
                      "trace_solve_iters_median": statistics.median(tr_iters),
-                     "epoch_loss": [round(v, 4) for v in losses]},
+                     "epoch_loss": [round(v, 4) for v in losses],
+                     "loss_before": round(loss_before, 4), "loss_after": round(loss_after, 4),
+                     "loss_floor": round(loss_floor, 4)},
         "compare_same_seeds": {
             "uniform_mixed": {"seeds": len(seeds), "time_s_median": round(statistics.median(ut), 4),
                               "iters_median": statistics.median(ui)},

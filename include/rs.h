@@ -338,6 +338,10 @@ rs_status rs_trainer_records(const rs_trainer* t, int64_t* count);
  * NULL) receives the mean loss of each epoch. */
 rs_status rs_trainer_fit(rs_trainer* t, int32_t epochs, int32_t batch, double lr, uint64_t shuffle_seed,
                          double* epoch_loss);
+/* Mean loss over all stored records with the current parameters (no update), and, when
+ * floor_out is not NULL, the mean entropy of the records' targets t = max(c, 0) / sum: the
+ * least value the cross-entropy can take (reached when softmax(s) = t on every record). */
+rs_status rs_trainer_eval(rs_trainer* t, double* loss_out, double* floor_out);
 rs_status rs_trainer_get_params(const rs_trainer* t, float* out);
 rs_status rs_trainer_set_params(rs_trainer* t, const float* in);
 const char* rs_trainer_last_error(const rs_trainer* t);

@@ -222,6 +222,58 @@ rs_status rs_trainer_fit(rs_trainer* T, int32_t epochs, int32_t batch, double lr
   }
 }
 
+rs_status rs_trainer_eval(rs_trainer* T, double* loss_out, double* floor_out) {
+  if (!T || !loss_out) return RS_EINVAL;
+  if (T->n == 0) {
+    T->last_error = "no trace records";
+    return RS_EINVAL;
+  }
+  try {
+    // the mean loss over every record in index order, in batches of at most 256 (the gradient
+    // the step kernels also form is scratch here)
+    const int32_t nb = (int32_t)std::min<int64_t>(256, T->n);
+    ensure_batch(T, nb);
+    std::vector<int32_t> idx(nb);
+    std::vector<double> losses(nb);
+    double tot = 0.0;
+    for (int64_t off = 0; off < T->n; off += nb) {
+      const int32_t cnt = (int32_t)std::min<int64_t>(nb, T->n - off);
+      for (int32_t i = 0; i < cnt; ++i) idx[i] = (int32_t)(off + i);
+      ck(hipMemcpy(T->rec, idx.data(), sizeof(int32_t) * cnt, hipMemcpyHostToDevice), "records");
+      ck(launch_mlp_step(T->P, T->F, T->C, T->rec, T->tau, cnt, T->s, T->ds, T->loss, T->partial, T->grad,
+                         nullptr),
+         "loss");
+      ck(hipMemcpy(losses.data(), T->loss, sizeof(double) * cnt, hipMemcpyDeviceToHost), "loss");
+      for (int32_t i = 0; i < cnt; ++i) tot += losses[i];
+    }
+    *loss_out = tot / (double)T->n;
+    if (floor_out) {
+      // the cross-entropy against t is at least the entropy of t, reached when softmax(s) = t
+      std::vector<float> c((size_t)T->n * T->tau);
+      ck(hipMemcpy(c.data(), T->C, sizeof(float) * c.size(), hipMemcpyDeviceToHost), "credits");
+      double fl = 0.0;
+      for (int64_t r = 0; r < T->n; ++r) {
+        const float* cr = c.data() + (size_t)r * T->tau;
+        double sum = 0.0;
+        for (int32_t b = 0; b < T->tau; ++b) sum += std::max(0.0, (double)cr[b]);
+        if (!(sum > 0.0)) continue;
+        for (int32_t b = 0; b < T->tau; ++b) {
+          const double t = std::max(0.0, (double)cr[b]) / sum;
+          if (t > 0.0) fl -= t * std::log(t);
+        }
+      }
+      *floor_out = fl / (double)T->n;
+    }
+    return RS_OK;
+  } catch (const Fail& f) {
+    T->last_error = f.msg;
+    return f.code;
+  } catch (const std::exception& e) {
+    T->last_error = e.what();
+    return RS_EDEVICE;
+  }
+}
+
 rs_status rs_trainer_get_params(const rs_trainer* T, float* out) {
   if (!T || !out) return RS_EINVAL;
   return hipMemcpy(out, T->P, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost) == hipSuccess ? RS_OK

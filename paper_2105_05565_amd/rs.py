@@ -147,6 +147,7 @@ SIGNATURES = {
     "rs_trainer_records": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int64)]),
     "rs_trainer_fit": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64,
                                         _P]),
+    "rs_trainer_eval": (ctypes.c_int32, [_P, _P, _P]),
     "rs_trainer_get_params": (ctypes.c_int32, [_P, _P]),
     "rs_trainer_set_params": (ctypes.c_int32, [_P, _P]),
     "rs_trainer_last_error": (ctypes.c_char_p, [_P]),
@@ -454,6 +455,12 @@ class Trainer:
         self._chk(load().rs_trainer_fit(self.t, int(epochs), int(batch), float(lr), int(shuffle_seed), _ptr(out)),
                   "rs_trainer_fit")
         return out[:epochs]
+
+    def evaluate(self):
+        """(mean loss over the stored records, mean entropy of their targets: the loss floor)."""
+        loss, floor = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        self._chk(load().rs_trainer_eval(self.t, ctypes.byref(loss), ctypes.byref(floor)), "rs_trainer_eval")
+        return loss.value, floor.value
 
     def params(self):
         out = np.zeros(RS_MLP_PARAMS, dtype=np.float32)

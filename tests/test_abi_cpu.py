@@ -244,3 +244,9 @@ def test_state_entry_points_reject_null_handle_without_device():
     p = z.ctypes.data
     assert lib.rs_set_state(None, 0, p, p, p, p) == rs.RS_EINVAL
     assert lib.rs_get_state(None, p, p, p, p) == rs.RS_EINVAL
+
+
+def test_trainer_eval_rejects_null_without_device():
+    lib = rs.load()
+    d = np.zeros(2)
+    assert lib.rs_trainer_eval(None, d.ctypes.data, d.ctypes.data) == rs.RS_EINVAL
