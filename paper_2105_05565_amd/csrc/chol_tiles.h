@@ -185,70 +185,119 @@ __device__ __forceinline__ double rsqrt_refined(double x) {
   return fma(y, e, y);
 }
 
+// Wave 0 factors the 16 x 16 diagonal block kb of td in registers and inverts it in the same
+// sweep: lane r holds row r (the four 16-lane rows of the wave hold the same block), pivot c is
+// L_cc = sqrt(a_cc) from one reciprocal square root, the entries of column c reach the other
+// lanes by row broadcasts, and lane j carries column j of the inverse (x_c = s_c / L_cc, then
+// s_i -= L_ic x_c). L_kk goes back to td (lower triangle), X_kk = L_kk^{-1} to ta.
+__device__ __forceinline__ void factor_block16(double* td, double* ta, int kb, int* bad) {
+  const int lane = threadIdx.x & 63, r = lane & 15;
+  double* D = blk16(td, kb, kb);
+  double d[16], s[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    d[c] = D[r * LDT + c];
+    s[c] = c == r ? 1.0 : 0.0;
+  }
+  int badl = 0;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    double piv = row_bcast(d[c], c);
+    if (!(piv > 0.0) || !(piv < INFINITY)) {
+      badl = 1;
+      piv = 1.0;
+    }
+    const double rs = rsqrt_refined(piv);
+    // lane c: sqrt(piv) (when the pivot was replaced, 1); lanes above c carry values of the
+    // upper triangle that are never read
+    const double l = r == c ? piv * rs : d[c] * rs;
+    d[c] = l;
+    const double x = s[c] * rs;
+    s[c] = x;
+#pragma unroll
+    for (int cc = c + 1; cc < 16; ++cc) {
+      const double lc = row_bcast(l, cc);
+      d[cc] -= l * lc;
+      s[cc] -= lc * x;
+    }
+  }
+  if (lane < 16) {
+    double* X = blk16(ta, kb, kb);
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      if (c <= r) D[r * LDT + c] = d[c];
+      X[c * LDT + r] = s[c];
+    }
+    if (badl) *bad = 1;
+  }
+}
+
 // Factor the 64 x 64 tile in td (LDS, lower triangle read) in place: the lower triangle of
 // td <- L with L L^T = td (the part above the diagonal is left undefined), and ta <- X =
 // L^{-1} (lower triangular, zeros above the diagonal). A pivot that is not positive and
 // finite is replaced by 1 and reported through *bad. Called by all threads of the workgroup.
 //
-// Blocked on 16 x 16 sub-blocks, right-looking. Wave 0 factors a diagonal block in
-// registers: lane r holds row r (the four 16-lane rows of the wave hold the same block),
-// pivot c is L_cc = sqrt(a_cc) from one reciprocal square root, and the entries of column c
-// reach the other lanes by row broadcasts; in the same sweep lane j carries column j of the
-// block's inverse (x_c = s_c / L_cc, then s_i -= L_ic x_c). The waves then form, on FP64
-// MFMA, the panel L_ik = A_ik X_kk^T and the blocks X_kj = -X_kk T_kj of row k of X, and
-// then the trailing update A_ij -= L_ik L_jk^T together with the partial sums
-// T_ij = sum_{t=j}^{k} L_it X_tj (kept in the blocks of ta below the diagonal).
+// Blocked on 16 x 16 sub-blocks, right-looking, with the diagonal blocks on wave 0
+// (factor_block16). After block kb is factored the waves form, on FP64 MFMA, the panel
+// L_ik = A_ik X_kk^T and the blocks X_kj = -X_kk T_kj of row kb of X; then the trailing
+// update A_ij -= L_ik L_jk^T together with the partial sums T_ij = sum_{t=j}^{kb} L_it X_tj
+// (kept in the blocks of ta below the diagonal), during which wave 0 updates the next
+// diagonal block first and factors it while waves 1-3 update the rest.
 __device__ __forceinline__ void factor_diag_tile(double* td, double* ta, int* bad) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  constexpr int kNW = kThreads / 64;
   for (int kb = 0; kb < 4; ++kb) {
+    // Diagonal block kb on wave 0: its last update (by L_{kb,kb-1}, step kb - 1's item 0),
+    // then its factorisation. Waves 1-3 meanwhile take the rest of step kb - 1's trailing
+    // update, A_ij -= L_ik L_jk^T (k < j <= i) and T_ij (+)= L_ik X_kj (i > k >= j) with
+    // k = kb - 1; before the first block they clear the blocks of ta above the diagonal.
     if (wave == 0) {
-      const int r = lane & 15;
-      double* D = blk16(td, kb, kb);
-      double d[16], s[16];
+      if (kb > 0) {
+        d4v acc = {0.0, 0.0, 0.0, 0.0};
+        double* L1 = blk16(td, kb, kb - 1);
+        mma16(acc, L1, LDT, 1, L1, LDT, 1);
+        double* A11 = blk16(td, kb, kb);
 #pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        d[c] = D[r * LDT + c];
-        s[c] = c == r ? 1.0 : 0.0;
+        for (int v = 0; v < 4; ++v) A11[(4 * v + (lane >> 4)) * LDT + (lane & 15)] -= acc[v];
+        // the block's rows come back to other lanes of this wave through LDS
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
-      int badl = 0;
-#pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        double piv = row_bcast(d[c], c);
-        if (!(piv > 0.0) || !(piv < INFINITY)) {
-          badl = 1;
-          piv = 1.0;
-        }
-        const double rs = rsqrt_refined(piv);
-        // lane c: sqrt(piv) (when the pivot was replaced, 1); lanes above c carry values
-        // of the upper triangle that are never read
-        const double l = r == c ? piv * rs : d[c] * rs;
-        d[c] = l;
-        const double x = s[c] * rs;
-        s[c] = x;
-#pragma unroll
-        for (int cc = c + 1; cc < 16; ++cc) {
-          const double lc = row_bcast(l, cc);
-          d[cc] -= l * lc;
-          s[cc] -= lc * x;
-        }
-      }
-      if (lane < 16) {
-        double* X = blk16(ta, kb, kb);
-#pragma unroll
-        for (int c = 0; c < 16; ++c) {
-          if (c <= r) D[r * LDT + c] = d[c];
-          X[c * LDT + r] = s[c];
-        }
-        if (badl) *bad = 1;
-      }
+      factor_block16(td, ta, kb, bad);
     } else if (kb == 0) {
-      // the six blocks of ta above the diagonal blocks are zero in the result
       for (int e = tid - 64; e < 6 * 256; e += kThreads - 64) {
         const int b = e >> 8, w = e & 255;
         const int bi = b < 3 ? 0 : (b < 5 ? 1 : 2);
         const int bj = b < 3 ? b + 1 : (b < 5 ? b - 1 : 3);
         ta[(16 * bi + (w >> 4)) * LDT + 16 * bj + (w & 15)] = 0.0;
+      }
+    } else {
+      const int k = kb - 1;
+      const int nA = (3 - k) * (4 - k) / 2, nT = (3 - k) * (k + 1);
+      // item 0, the diagonal block (kb, kb), is wave 0's
+      for (int it = wave; it < nA + nT; it += kThreads / 64 - 1) {
+        d4v acc = {0.0, 0.0, 0.0, 0.0};
+        if (it < nA) {
+          int i = k + 1, j = it;
+          while (j >= i - k) {
+            j -= i - k;
+            ++i;
+          }
+          j += k + 1;
+          mma16(acc, blk16(td, i, k), LDT, 1, blk16(td, j, k), LDT, 1);
+          double* Aij = blk16(td, i, j);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Aij[(4 * v + (lane >> 4)) * LDT + (lane & 15)] -= acc[v];
+        } else {
+          const int t = it - nA, i = k + 1 + t / (k + 1), j = t % (k + 1);
+          mma16(acc, blk16(td, i, k), LDT, 1, blk16(ta, k, j), 1, LDT);
+          double* Tij = blk16(ta, i, j);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            double* p = Tij + (4 * v + (lane >> 4)) * LDT + (lane & 15);
+            *p = j == k ? acc[v] : *p + acc[v];
+          }
+        }
       }
     }
     __syncthreads();
@@ -265,34 +314,6 @@ __device__ __forceinline__ void factor_diag_tile(double* td, double* ta, int* ba
         mma16(acc, blk16(ta, kb, kb), LDT, 1, Tkj, 1, LDT);
 #pragma unroll
         for (int v = 0; v < 4; ++v) Tkj[(4 * v + (lane >> 4)) * LDT + (lane & 15)] = -acc[v];
-      }
-    }
-    __syncthreads();
-    if (kb == 3) break;
-    // A_ij -= L_ik L_jk^T (kb < j <= i) and T_ij (+)= L_ik X_kj (i > kb >= j)
-    const int nA = (3 - kb) * (4 - kb) / 2, nT = (3 - kb) * (kb + 1);
-    for (int it = wave; it < nA + nT; it += kNW) {
-      d4v acc = {0.0, 0.0, 0.0, 0.0};
-      if (it < nA) {
-        int i = kb + 1, j = it;
-        while (j >= i - kb) {
-          j -= i - kb;
-          ++i;
-        }
-        j += kb + 1;
-        mma16(acc, blk16(td, i, kb), LDT, 1, blk16(td, j, kb), LDT, 1);
-        double* Aij = blk16(td, i, j);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Aij[(4 * v + (lane >> 4)) * LDT + (lane & 15)] -= acc[v];
-      } else {
-        const int t = it - nA, i = kb + 1 + t / (kb + 1), j = t % (kb + 1);
-        mma16(acc, blk16(td, i, kb), LDT, 1, blk16(ta, kb, j), 1, LDT);
-        double* Tij = blk16(ta, i, j);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          double* p = Tij + (4 * v + (lane >> 4)) * LDT + (lane & 15);
-          *p = j == kb ? acc[v] : *p + acc[v];
-        }
       }
     }
     __syncthreads();

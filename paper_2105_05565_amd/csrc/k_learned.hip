@@ -235,7 +235,23 @@ __device__ __forceinline__ void mlp_front(MlpLds& L, const float* __restrict__ P
                                           const float* __restrict__ F, const int32_t* rec,
                                           int32_t tau, int64_t r0, int64_t rows, float* z2) {
   const int tid = threadIdx.x;
-  for (int e = tid; e < HID * HID; e += 256) L.W2[(e >> 7) * kW2Ld + (e & 127)] = P[OFF_W2 + e];
+  {
+    // W2 as 16 float4 loads per thread, all issued before the first LDS store
+    static_assert(HID * HID == 4 * 16 * 256 && OFF_W2 % 4 == 0, "W2 load layout");
+    const float4* W2g = reinterpret_cast<const float4*>(P + OFF_W2);
+    float4 v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = W2g[tid + 256 * q];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = 4 * (tid + 256 * q);
+      float* d = L.W2 + (e >> 7) * kW2Ld + (e & 127);
+      d[0] = v[q].x;
+      d[1] = v[q].y;
+      d[2] = v[q].z;
+      d[3] = v[q].w;
+    }
+  }
   for (int e = tid; e < NF * HID; e += 256) L.W1[e] = P[OFF_W1 + e];
   for (int e = tid; e < HID; e += 256) {
     L.b1[e] = P[OFF_B1 + e];
