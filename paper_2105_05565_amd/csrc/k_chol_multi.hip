@@ -293,12 +293,16 @@ __global__ __launch_bounds__(kThreads) void k_chol_step(MultiArgs a, int s) {
 }
 
 // Work-optimal form of the same steps, two launches per step (no block is formed twice).
-// Panel of step s (k = s - 1): L_ik = G_ik X_k^T stored over G_ik (i >= s), and row k of W,
-// W_kj = -X_k T_kj stored over T_kj (j < k). LDS: two tiles.
+// Panel of step s (k = s - 1): L_ik = G_ik X_k^T stored over G_ik (i >= s), and row k of W
+// (modes 1), stored transposed over T_kj: U_kj <- W_kj^T = -(X_k T_kj)^T (j < k). The item
+// of L_sk then brings the diagonal tile up to date, G_ss - L_sk L_sk^T (G_ss has every
+// earlier update: the update launch leaves it out), and factors it: X_s, U_ss = X_s^T.
+// LDS: two tiles.
 __global__ __launch_bounds__(kThreads) void k_chol_panel(MultiArgs a, int s, int items) {
   extern __shared__ __align__(16) double lds[];
   double* tx = lds;
   double* ta = lds + NB * LDT;
+  __shared__ int bad;
   if (*a.done) return;
   const int nt = a.nt, k = s - 1;
   int64_t slot;
@@ -309,112 +313,101 @@ __global__ __launch_bounds__(kThreads) void k_chol_panel(MultiArgs a, int s, int
   const double* Xk = a.X + (slot * nt + k) * NB * NB;
   const bool lpanel = item < nt - s;
   double* dst = lpanel ? tile(G, a.ldg, s + item, k) : tile(U, a.ldg, k, item - (nt - s));
+  const bool diag = lpanel && item == 0;
+  Acc g;
+  if (diag) acc_load(g, tile(G, a.ldg, s, s), a.ldg);
   load_tile(tx, Xk, NB, false);
   load_tile(ta, dst, a.ldg, !lpanel);  // G_ik, or T_kj^T
   __syncthreads();
   Acc c;
   acc_zero(c);
-  if (lpanel)
-    tile_mma(c, ta, tx);  // G_ik X_k^T
-  else
-    tile_mma(c, tx, ta);  // X_k T_kj
-  const double sign = lpanel ? 1.0 : -1.0;
-  acc_for_each(c, [&](int r, int cc, double v) { dst[(int64_t)r * a.ldg + cc] = sign * v; });
+  if (lpanel) {
+    tile_mma(c, ta, tx);  // L_ik = G_ik X_k^T
+    acc_for_each(c, [&](int r, int cc, double v) { dst[(int64_t)r * a.ldg + cc] = v; });
+  } else {
+    tile_mma(c, tx, ta);  // X_k T_kj = -W_kj, stored as W_kj^T
+    acc_for_each(c, [&](int r, int cc, double v) { dst[(int64_t)cc * a.ldg + r] = -v; });
+  }
+  if (!diag) return;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();  // ta, tx read by every wave
+  acc_for_each(c, [&](int r, int cc, double v) { ta[r * LDT + cc] = v; });
+  __syncthreads();
+  Acc c2;
+  acc_zero(c2);
+  tile_mma(c2, ta, ta);  // L_sk L_sk^T
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int w = 0; w < 2; ++w) g.v[u][w] -= c2.v[u][w];
+  acc_for_each(g, [&](int r, int cc, double v) { tx[r * LDT + cc] = v; });
+  __syncthreads();
+  factor_diag_tile(tx, ta, &bad);
+  store_x(a.X + (slot * nt + s) * NB * NB, tile(U, a.ldg, s, s), a.ldg, ta);
+  if (threadIdx.x == 0 && bad) a.status[slot] = 1;
 }
 
-// Updates of step s from the stored panel: F (s <= l <= i): G_il -= L_ik L_lk^T, the item
-// (s, s) then factoring G_ss; I (i >= s, j <= k): T_ij (+)= L_ik W_kj; A (j <= i <= k):
-// (G^{-1})_ij (+)= W_ki^T W_kj. W_kk = X_k. LDS: two tiles.
+// Updates of step s from the stored panel, one tile product per item straight from global
+// memory (no LDS, so that many items share a compute unit): F (s <= l <= i, (s, s) left to
+// the next panel): G_il -= L_ik L_lk^T; I (i >= s, j <= k): T_ij (+)= L_ik W_kj;
+// A (j <= i <= k): (G^{-1})_ij (+)= W_ki^T W_kj. W_kj^T is read from U_kj (U_kk = X_k^T).
 __global__ __launch_bounds__(kThreads) void k_chol_update(MultiArgs a, int s, int items) {
-  extern __shared__ __align__(16) double lds[];
-  double* ta = lds;
-  double* tb = lds + NB * LDT;
-  __shared__ int bad;
   if (*a.done) return;
   const int nt = a.nt, k = s - 1;
-  const int nF = (nt - s) * (nt - s + 1) / 2, nI = (nt - s) * s;
+  const int nF = (nt - s) * (nt - s + 1) / 2 - (s < nt ? 1 : 0), nI = (nt - s) * s;
   int64_t slot;
   int item;
   if (!item_of_block(a, items, &slot, &item)) return;
   double* G = a.G + slot * a.ldg * a.ldg;
   double* U = a.U + slot * a.ldg * a.ldg;
-  const double* Xk = a.X + (slot * nt + k) * NB * NB;
-  // W_kj (j <= k) and its source: U_kj, or X_k for j = k
-  auto wsrc = [&](int j, int64_t* ld) -> const double* {
-    *ld = j < k ? a.ldg : NB;
-    return j < k ? tile(U, a.ldg, k, j) : Xk;
-  };
+  const int64_t ld = a.ldg;
   Acc g, c;
   acc_zero(c);
   if (item < nF) {
     int i, l;
-    lower_pair(item, s, &i, &l);
-    double* Gil = tile(G, a.ldg, i, l);
-    acc_load(g, Gil, a.ldg);
-    load_tile(ta, tile(G, a.ldg, i, k), a.ldg, false);
-    if (l != i) load_tile(tb, tile(G, a.ldg, l, k), a.ldg, false);
-    __syncthreads();
-    tile_mma(c, ta, l != i ? tb : ta);
+    lower_pair(item + 1, s, &i, &l);  // pair 0 is (s, s)
+    double* Gil = tile(G, ld, i, l);
+    acc_load(g, Gil, ld);
+    tile_mma_global(c, tile(G, ld, i, k), tile(G, ld, l, k), ld);
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
       for (int w = 0; w < 2; ++w) g.v[u][w] -= c.v[u][w];
-    if (i == s && l == s) {
-      if (threadIdx.x == 0) bad = 0;
-      __syncthreads();
-      acc_for_each(g, [&](int r, int cc, double v) { ta[r * LDT + cc] = v; });
-      __syncthreads();
-      factor_diag_tile(ta, tb, &bad);
-      store_x(a.X + (slot * nt + s) * NB * NB, tile(U, a.ldg, s, s), a.ldg, tb);
-      if (threadIdx.x == 0 && bad) a.status[slot] = 1;
-    } else {
-      acc_for_each(g, [&](int r, int cc, double v) { Gil[(int64_t)r * a.ldg + cc] = v; });
-    }
+    acc_for_each(g, [&](int r, int cc, double v) { Gil[(int64_t)r * ld + cc] = v; });
     return;
   }
   item -= nF;
   if (item < nI) {
     const int i = s + item / s, j = item % s;
-    double* Tij = tile(U, a.ldg, i, j);
-    if (j < k) acc_load(g, Tij, a.ldg);
-    int64_t ldw;
-    const double* W = wsrc(j, &ldw);
-    load_tile(ta, tile(G, a.ldg, i, k), a.ldg, false);
-    load_tile(tb, W, ldw, true);
-    __syncthreads();
-    tile_mma(c, ta, tb);  // L_ik W_kj
+    double* Tij = tile(U, ld, i, j);
+    if (j < k) acc_load(g, Tij, ld);
+    tile_mma_global(c, tile(G, ld, i, k), tile(U, ld, k, j), ld);  // L_ik W_kj
     if (j < k) {
 #pragma unroll
       for (int u = 0; u < 2; ++u)
 #pragma unroll
         for (int w = 0; w < 2; ++w) c.v[u][w] += g.v[u][w];
     }
-    acc_for_each(c, [&](int r, int cc, double v) { Tij[(int64_t)r * a.ldg + cc] = v; });
+    acc_for_each(c, [&](int r, int cc, double v) { Tij[(int64_t)r * ld + cc] = v; });
     return;
   }
   item -= nI;
   int i, j;
   lower_pair(item, 0, &i, &j);
-  double* Gij = tile(G, a.ldg, i, j);
-  if (i < k) acc_load(g, Gij, a.ldg);
-  int64_t ldi, ldj;
-  const double* Wi = wsrc(i, &ldi);
-  const double* Wj = wsrc(j, &ldj);
-  load_tile(ta, Wi, ldi, true);
-  if (j != i) load_tile(tb, Wj, ldj, true);
-  __syncthreads();
-  tile_mma(c, ta, j != i ? tb : ta);  // W_ki^T W_kj
+  double* Gij = tile(G, ld, i, j);
+  if (i < k) acc_load(g, Gij, ld);
+  tile_mma_global(c, tile(U, ld, k, i), tile(U, ld, k, j), ld);  // W_ki^T W_kj
   if (i < k) {
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
       for (int w = 0; w < 2; ++w) c.v[u][w] += g.v[u][w];
   }
-  double* Gji = tile(G, a.ldg, j, i);
+  double* Gji = tile(G, ld, j, i);
   const bool mirror = s == nt && i != j;
   acc_for_each(c, [&](int r, int cc, double v) {
-    Gij[(int64_t)r * a.ldg + cc] = v;
-    if (mirror) Gji[(int64_t)cc * a.ldg + r] = v;
+    Gij[(int64_t)r * ld + cc] = v;
+    if (mirror) Gji[(int64_t)cc * ld + r] = v;
   });
 }
 
@@ -511,8 +504,6 @@ hipError_t launch_chol_multi_mode(double* G, double* U, double* X, int64_t ldg, 
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_chol_panel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)two);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_chol_update, hipFuncAttributeMaxDynamicSharedMemorySize, (int)two);
-  if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_chol_ll_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)two);
   if (e != hipSuccess) return e;
   if (mode == 0) {
@@ -531,12 +522,14 @@ hipError_t launch_chol_multi_mode(double* G, double* U, double* X, int64_t ldg, 
     if (mode == 0) {
       hipLaunchKernelGGL(k_chol_step, grid(items), dim3(kThreads), three, s, a, st);
     } else if (mode == 1) {
+      // the update leaves the diagonal tile (st, st) to the next panel
+      const int upd = items - (st < nt ? 1 : 0);
       hipLaunchKernelGGL(k_chol_panel, grid(nt - 1), dim3(kThreads), two, s, a, st, nt - 1);
-      hipLaunchKernelGGL(k_chol_update, grid(items), dim3(kThreads), two, s, a, st, items);
+      hipLaunchKernelGGL(k_chol_update, grid(upd), dim3(kThreads), 0, s, a, st, upd);
     } else if (st < nt) {
-      // the first nt - st panel items are the L blocks, the first nF update items the F ones
+      // the first nt - st panel items are the L blocks, the first nF - 1 update items the F ones
       hipLaunchKernelGGL(k_chol_panel, grid(nt - st), dim3(kThreads), two, s, a, st, nt - st);
-      hipLaunchKernelGGL(k_chol_update, grid(nF), dim3(kThreads), two, s, a, st, nF);
+      if (nF > 1) hipLaunchKernelGGL(k_chol_update, grid(nF - 1), dim3(kThreads), 0, s, a, st, nF - 1);
     }
   }
   if (mode == 2) {
