@@ -221,8 +221,8 @@ def kernel_table(prof, wl, workload, n, d, nnz, m, K, nsel, total, a_nnz=0):
         # factor steps followed by the inverse-by-distance and U U^T chains
         nt, ns = ldg // 64, kd["slots_per_launch"]
         tiled_name = ("k_chol_assemble+k_chol_diag0+k_chol_step" if ns * nt * nt <= 512 else
-                      "k_chol_assemble+k_chol_diag0+k_chol_panel+k_chol_update" if ns * nt ** 3 <= 3e5 else
-                      "k_chol_assemble+k_chol_diag0+k_chol_panel+k_chol_update+k_chol_ll_inverse+k_chol_lauum")
+                      "k_chol_assemble+k_chol_diag0+k_chol_panel+k_chol_narrow+k_chol_update" if ns * nt ** 3 <= 4e6 else
+                      "k_chol_assemble+k_chol_diag0+k_chol_panel+k_chol_narrow+k_chol_update+k_chol_ll_inverse+k_chol_lauum")
         roofline.update({"kernel": tiled_name if tiled else "k_chol_inverse",
                          "bound": "mfma", "achieved": round(tfs, 1), "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
                          "frac": round(tfs / FP64_PEAK_TFS, 4), "alg_flops_per_launch": flops,

@@ -294,11 +294,11 @@ __global__ __launch_bounds__(kThreads) void k_chol_step(MultiArgs a, int s) {
 
 // Work-optimal form of the same steps, two launches per step (no block is formed twice).
 // Panel of step s (k = s - 1): L_ik = G_ik X_k^T stored over G_ik (i >= s), and row k of W
-// (modes 1), stored transposed over T_kj: U_kj <- W_kj^T = -(X_k T_kj)^T (j < k). The item
-// of L_sk then brings the diagonal tile up to date, G_ss - L_sk L_sk^T (G_ss has every
-// earlier update: the update launch leaves it out), and factors it: X_s, U_ss = X_s^T.
-// LDS: two tiles.
-__global__ __launch_bounds__(kThreads) void k_chol_panel(MultiArgs a, int s, int items) {
+// (mode 1), stored transposed over T_kj: U_kj <- W_kj^T = -(X_k T_kj)^T (j < k). The item
+// of L_sk then brings the diagonal tile up to date, G_ss - L_sk L_sk^T (and - L_s,kx L_s,kx^T
+// for kx >= 0, the column whose update of G_ss was deferred to here: the update launches
+// leave the diagonal tile out), and factors it: X_s, U_ss = X_s^T. LDS: two tiles.
+__global__ __launch_bounds__(kThreads) void k_chol_panel(MultiArgs a, int s, int items, int kx) {
   extern __shared__ __align__(16) double lds[];
   double* tx = lds;
   double* ta = lds + NB * LDT;
@@ -336,6 +336,7 @@ __global__ __launch_bounds__(kThreads) void k_chol_panel(MultiArgs a, int s, int
   Acc c2;
   acc_zero(c2);
   tile_mma(c2, ta, ta);  // L_sk L_sk^T
+  if (kx >= 0) tile_mma_global(c2, tile(G, a.ldg, s, kx), tile(G, a.ldg, s, kx), a.ldg);  // + L_s,kx L_s,kx^T
 #pragma unroll
   for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -347,13 +348,16 @@ __global__ __launch_bounds__(kThreads) void k_chol_panel(MultiArgs a, int s, int
   if (threadIdx.x == 0 && bad) a.status[slot] = 1;
 }
 
-// Updates of step s from the stored panel, one tile product per item straight from global
-// memory (no LDS, so that many items share a compute unit): F (s <= l <= i, (s, s) left to
-// the next panel): G_il -= L_ik L_lk^T; I (i >= s, j <= k): T_ij (+)= L_ik W_kj;
-// A (j <= i <= k): (G^{-1})_ij (+)= W_ki^T W_kj. W_kj^T is read from U_kj (U_kk = X_k^T).
-__global__ __launch_bounds__(kThreads) void k_chol_update(MultiArgs a, int s, int items) {
+// Updates from the stored panels of columns k_lo .. s - 1 (one, or two when a pair of steps
+// shares the launch, so that each target is read and written once for both), the tile
+// products straight from global memory (no LDS, so that many items share a compute unit):
+// F (s <= l <= i, (s, s) left to the next panel): G_il -= sum_k L_ik L_lk^T;
+// I (i >= s, j < s): T_ij (+)= sum_{k >= max(k_lo, j)} L_ik W_kj (the k = j term is the first);
+// A (j <= i < s): (G^{-1})_ij (+)= sum_{k >= max(k_lo, i)} W_ki^T W_kj (the k = i term is the
+// first). W_kj^T is read from U_kj (U_kk = X_k^T).
+__global__ __launch_bounds__(kThreads) void k_chol_update(MultiArgs a, int s, int items, int k_lo) {
   if (*a.done) return;
-  const int nt = a.nt, k = s - 1;
+  const int nt = a.nt;
   const int nF = (nt - s) * (nt - s + 1) / 2 - (s < nt ? 1 : 0), nI = (nt - s) * s;
   int64_t slot;
   int item;
@@ -368,7 +372,7 @@ __global__ __launch_bounds__(kThreads) void k_chol_update(MultiArgs a, int s, in
     lower_pair(item + 1, s, &i, &l);  // pair 0 is (s, s)
     double* Gil = tile(G, ld, i, l);
     acc_load(g, Gil, ld);
-    tile_mma_global(c, tile(G, ld, i, k), tile(G, ld, l, k), ld);
+    for (int k = k_lo; k < s; ++k) tile_mma_global(c, tile(G, ld, i, k), tile(G, ld, l, k), ld);
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -379,10 +383,11 @@ __global__ __launch_bounds__(kThreads) void k_chol_update(MultiArgs a, int s, in
   item -= nF;
   if (item < nI) {
     const int i = s + item / s, j = item % s;
+    const bool first = j >= k_lo;
     double* Tij = tile(U, ld, i, j);
-    if (j < k) acc_load(g, Tij, ld);
-    tile_mma_global(c, tile(G, ld, i, k), tile(U, ld, k, j), ld);  // L_ik W_kj
-    if (j < k) {
+    if (!first) acc_load(g, Tij, ld);
+    for (int k = max(k_lo, j); k < s; ++k) tile_mma_global(c, tile(G, ld, i, k), tile(U, ld, k, j), ld);
+    if (!first) {
 #pragma unroll
       for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -394,10 +399,11 @@ __global__ __launch_bounds__(kThreads) void k_chol_update(MultiArgs a, int s, in
   item -= nI;
   int i, j;
   lower_pair(item, 0, &i, &j);
+  const bool first = i >= k_lo;
   double* Gij = tile(G, ld, i, j);
-  if (i < k) acc_load(g, Gij, ld);
-  tile_mma_global(c, tile(U, ld, k, i), tile(U, ld, k, j), ld);  // W_ki^T W_kj
-  if (i < k) {
+  if (!first) acc_load(g, Gij, ld);
+  for (int k = max(k_lo, i); k < s; ++k) tile_mma_global(c, tile(U, ld, k, i), tile(U, ld, k, j), ld);
+  if (!first) {
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -409,6 +415,45 @@ __global__ __launch_bounds__(kThreads) void k_chol_update(MultiArgs a, int s, in
     Gij[(int64_t)r * ld + cc] = v;
     if (mirror) Gji[(int64_t)cc * ld + r] = v;
   });
+}
+
+// The part of step s's update (k = s - 1) that the next panel needs before a paired update
+// applies the rest together with step s + 1's: column s of G, G_is -= L_ik L_sk^T (i > s),
+// and, with trow, row s of T, T_sj (+)= L_sk W_kj (j <= k; the j = k term is the first).
+__global__ __launch_bounds__(kThreads) void k_chol_narrow(MultiArgs a, int s, int items, int trow) {
+  if (*a.done) return;
+  const int nt = a.nt, k = s - 1, nFc = nt - s - 1;
+  int64_t slot;
+  int item;
+  if (!item_of_block(a, items, &slot, &item)) return;
+  double* G = a.G + slot * a.ldg * a.ldg;
+  double* U = a.U + slot * a.ldg * a.ldg;
+  const int64_t ld = a.ldg;
+  Acc g, c;
+  acc_zero(c);
+  if (item < nFc) {
+    double* Gis = tile(G, ld, s + 1 + item, s);
+    acc_load(g, Gis, ld);
+    tile_mma_global(c, tile(G, ld, s + 1 + item, k), tile(G, ld, s, k), ld);
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int w = 0; w < 2; ++w) g.v[u][w] -= c.v[u][w];
+    acc_for_each(g, [&](int r, int cc, double v) { Gis[(int64_t)r * ld + cc] = v; });
+    return;
+  }
+  if (!trow) return;
+  const int j = item - nFc;
+  double* Tsj = tile(U, ld, s, j);
+  if (j < k) acc_load(g, Tsj, ld);
+  tile_mma_global(c, tile(G, ld, s, k), tile(U, ld, k, j), ld);
+  if (j < k) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int w = 0; w < 2; ++w) c.v[u][w] += g.v[u][w];
+  }
+  acc_for_each(c, [&](int r, int cc, double v) { Tsj[(int64_t)r * ld + cc] = v; });
 }
 
 // Inverse by distance d = i - j after the factorisation (mode 2): W_ij = -X_i sum_{k=j}^{i-1}
@@ -465,13 +510,13 @@ __global__ __launch_bounds__(kThreads) void k_chol_lauum(MultiArgs a) {
 size_t chol_multi_x_bytes(int64_t ldg) { return sizeof(double) * (size_t)(ldg / NB) * NB * NB; }
 
 // Measured on tau = 256 .. 5184 with 2 .. 31 sketches: the fused steps lead while a step's
-// items fit on the chip about twice (up to 2.0x over mode 1's chain at nt = 8), mode 1 in
-// between (tau = 2048, 4 sketches: 2.06 ms against 3.38 and 3.72; tau = 1024, 31: 1.92 ms
-// against 3.25 and 1.97), mode 2 once the tile products outweigh every chain (tau = 2048,
-// 16 sketches: 6.54 ms against 7.06; tau = 5184, 31: 161 ms against 214 and 395).
+// items fit on the chip about twice (tau = 512, 2 sketches: 199 us against 276 and 422),
+// mode 1 in between (tau = 1024, 31 sketches: 1.76 ms against 3.38 and 2.00; tau = 2048, 16:
+// 5.56 ms against 12.9 and 6.43), mode 2 once the tile products outweigh every chain
+// (tau = 5184, 31 sketches: 138 ms against 146 and 397).
 int chol_multi_mode(int64_t nt, int64_t nslots) {
   if (nslots * nt * nt <= 512) return 0;
-  return nslots * nt * nt * nt > 300000 ? 2 : 1;
+  return nslots * nt * nt * nt > 4000000 ? 2 : 1;
 }
 
 // The XCD layout keeps a sketch's tiles in one L2; it pays with 8 or more sketches whose
@@ -516,20 +561,39 @@ hipError_t launch_chol_multi_mode(double* G, double* U, double* X, int64_t ldg, 
   auto grid = [&](int items) {
     return a.xcd ? dim3((unsigned)(8 * ((nslots + 7) / 8) * items)) : dim3(items, nslots);
   };
-  for (int st = 1; st <= nt; ++st) {
-    const int nF = (nt - st) * (nt - st + 1) / 2;
-    const int items = nF + (nt - st) * st + st * (st + 1) / 2;
-    if (mode == 0) {
+  if (mode == 0) {
+    for (int st = 1; st <= nt; ++st) {
+      const int items = (nt - st) * (nt - st + 1) / 2 + (nt - st) * st + st * (st + 1) / 2;
       hipLaunchKernelGGL(k_chol_step, grid(items), dim3(kThreads), three, s, a, st);
-    } else if (mode == 1) {
-      // the update leaves the diagonal tile (st, st) to the next panel
-      const int upd = items - (st < nt ? 1 : 0);
-      hipLaunchKernelGGL(k_chol_panel, grid(nt - 1), dim3(kThreads), two, s, a, st, nt - 1);
-      hipLaunchKernelGGL(k_chol_update, grid(upd), dim3(kThreads), 0, s, a, st, upd);
-    } else if (st < nt) {
-      // the first nt - st panel items are the L blocks, the first nF - 1 update items the F ones
-      hipLaunchKernelGGL(k_chol_panel, grid(nt - st), dim3(kThreads), two, s, a, st, nt - st);
-      if (nF > 1) hipLaunchKernelGGL(k_chol_update, grid(nF - 1), dim3(kThreads), 0, s, a, st, nF - 1);
+    }
+  } else {
+    // Steps in pairs (st, st + 1): panel st, the narrow part of update st, panel st + 1 (its
+    // diagonal tile also takes column st - 1's term), then one update for both columns; a
+    // last unpaired step takes its own update. Mode 2 stops before step nt (no W, no G^{-1}).
+    const int last = mode == 1 ? nt : nt - 1;
+    auto nupd = [&](int st) {  // update items of step st (the diagonal tile left out)
+      const int nF = (nt - st) * (nt - st + 1) / 2 - (st < nt ? 1 : 0);
+      return mode == 1 ? nF + (nt - st) * st + st * (st + 1) / 2 : nF;
+    };
+    auto npanel = [&](int st) { return mode == 1 ? nt - 1 : nt - st; };
+    int st = 1;
+    while (st <= last) {
+      if (st + 1 <= last) {
+        const int nnar = (nt - st - 1) + (mode == 1 ? st : 0);
+        hipLaunchKernelGGL(k_chol_panel, grid(npanel(st)), dim3(kThreads), two, s, a, st, npanel(st), -1);
+        if (nnar > 0)
+          hipLaunchKernelGGL(k_chol_narrow, grid(nnar), dim3(kThreads), 0, s, a, st, nnar, mode == 1 ? 1 : 0);
+        hipLaunchKernelGGL(k_chol_panel, grid(npanel(st + 1)), dim3(kThreads), two, s, a, st + 1, npanel(st + 1),
+                           st - 1);
+        const int nu = nupd(st + 1);
+        if (nu > 0) hipLaunchKernelGGL(k_chol_update, grid(nu), dim3(kThreads), 0, s, a, st + 1, nu, st - 1);
+        st += 2;
+      } else {
+        hipLaunchKernelGGL(k_chol_panel, grid(npanel(st)), dim3(kThreads), two, s, a, st, npanel(st), -1);
+        const int nu = nupd(st);
+        if (nu > 0) hipLaunchKernelGGL(k_chol_update, grid(nu), dim3(kThreads), 0, s, a, st, nu, st - 1);
+        st += 1;
+      }
     }
   }
   if (mode == 2) {
