@@ -113,7 +113,8 @@ typedef struct rs_options {
   uint64_t problem_id;      /* Philox key word 1 */
   int32_t refresh_every;    /* mixed precision: FP64 recomputation of r every R iterations (default 20) */
   int32_t lookahead;        /* sketches drawn and factorised ahead per batch; 0 = library choice */
-  int32_t profile;          /* 0: off; 1: batch-level HIP-event timing; 2: every launch (rs_get_profile) */
+  int32_t profile;          /* 0: off; 1: batch-level HIP-event timing; 2: every launch (rs_get_profile);
+                               3: the AS products of each batch only (the fewest events in the stream) */
   void* stream;             /* hipStream_t for all work; NULL = the default stream (a batch
                                then creates its own stream, since graph capture needs one) */
   int32_t graph_iters;      /* batch: iterations per captured HIP graph; 0 = 8, < 0 = no graph */

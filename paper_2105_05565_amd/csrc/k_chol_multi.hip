@@ -95,19 +95,32 @@ __global__ __launch_bounds__(kThreads) void k_chol_assemble(MultiArgs a) {
   double* G = a.G + slot * a.ldg * a.ldg;
   const int32_t* offs = a.offs + slot * (a.tau + 1);
   const int32_t* members = a.members + slot * a.tau;  // subsample: nsel = tau
-  for (int e = threadIdx.x; e < NB * NB; e += kThreads) {
-    const int r = e >> 6, c = e & 63;
+  // the 16 values of this thread first (their loads in flight together), then the stores
+  constexpr int kPer = NB * NB / kThreads;
+  double v[kPer];
+  bool wr[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int e = threadIdx.x + kThreads * q, r = e >> 6, c = e & 63;
     const int64_t gr = (int64_t)ti * NB + r, gc = (int64_t)tj * NB + c;
-    double* g = G + gr * a.ldg + gc;
+    wr[q] = true;
     if (gr >= a.tau || gc >= a.tau) {
-      *g = (gr == gc) ? 1.0 : 0.0;
+      v[q] = (gr == gc) ? 1.0 : 0.0;
     } else if (a.kind == kSubsample) {
       const int64_t src = (slot * a.m + members[gr]) * a.ldas + gc;
-      *g = a.as_f32 ? (double)((const float*)a.AS)[src] : ((const double*)a.AS)[src];
+      v[q] = a.as_f32 ? (double)((const float*)a.AS)[src] : ((const double*)a.AS)[src];
     } else if (gr == gc && offs[gr + 1] == offs[gr]) {
-      *g = 1.0;  // empty bucket: zero row and column of S^T A S
+      v[q] = 1.0;  // empty bucket: zero row and column of S^T A S
+    } else {
+      wr[q] = false;  // formed already (S^T A S summed from AS)
+      v[q] = first ? G[gr * a.ldg + gc] : 0.0;
     }
-    if (first) lds[r * LDT + c] = *g;
+  }
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int e = threadIdx.x + kThreads * q, r = e >> 6, c = e & 63;
+    if (wr[q]) G[((int64_t)ti * NB + r) * a.ldg + (int64_t)tj * NB + c] = v[q];
+    if (first) lds[r * LDT + c] = v[q];
   }
   if (!first) return;
   if (threadIdx.x == 0) bad = 0;

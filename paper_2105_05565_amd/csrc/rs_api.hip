@@ -239,7 +239,11 @@ T* to_device(rs_handle* h, const void* src, size_t count, int mem) {
 
 // Event pair around one launch when profiling: returns the pair index or -1.
 int prof_begin(rs_handle* h, int cls, int slots, int level = 1, hipStream_t s = nullptr, int64_t batch = -1) {
-  if (h->opt.profile < level) return -1;
+  if (h->opt.profile == 3) {
+    if (cls != RS_PROF_AS) return -1;  // products only
+  } else if (h->opt.profile < level) {
+    return -1;
+  }
   if (2 * (h->ev_used + 1) > (int)h->ev.size()) return -1;  // pool full: leave untimed
   const int i = h->ev_used++;
   h->ev_cls[i] = cls;
@@ -818,6 +822,7 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
     if (o->precision == RS_PREC_MIXED_BF16 && o->refresh_every < 1)
       throw Fail{RS_EINVAL, "refresh_every must be >= 1"};
     if (o->refresh_early != 0 && o->refresh_early != 1) throw Fail{RS_EINVAL, "refresh_early is 0 or 1"};
+    if (o->profile < 0 || o->profile > 3) throw Fail{RS_EINVAL, "profile is 0, 1, 2 or 3"};
     h->mixed = o->precision == RS_PREC_MIXED_BF16;
     if (o->sampler < RS_SAMPLER_UNIFORM || o->sampler > RS_SAMPLER_DIAG) throw Fail{RS_EINVAL, "unknown sampler"};
     if (o->sparse_route < RS_ROUTE_AUTO || o->sparse_route > RS_ROUTE_AROWS)
