@@ -88,6 +88,17 @@ struct GemmArgs {
   const int32_t* done;
 };
 
+// Tile t of the grouped order: groups of kGroupRows row tiles, column by column within a
+// group, so that a run of consecutive tiles covers a compact block of row and column strips.
+__device__ __forceinline__ void tile_of_index(const GemmArgs& a, int t, int* rt, int* ct) {
+  const int group = t / (kGroupRows * a.n_col_tiles);
+  const int rows_in_group = min(kGroupRows, a.n_row_tiles - group * kGroupRows);
+  const int idx = t - group * kGroupRows * a.n_col_tiles;
+  *rt = group * kGroupRows + idx % rows_in_group;
+  *ct = idx / rows_in_group;
+}
+
+// Workgroup bid (XCD bid % 8) -> its tile: each XCD takes a run of consecutive tiles.
 __device__ __forceinline__ void tile_of_block(const GemmArgs& a, int bid, int* rt, int* ct) {
   const int ntiles = a.n_row_tiles * a.n_col_tiles;
   const int per = (ntiles + kXcds - 1) / kXcds;
@@ -96,11 +107,7 @@ __device__ __forceinline__ void tile_of_block(const GemmArgs& a, int bid, int* r
     *rt = -1;
     return;
   }
-  const int group = t / (kGroupRows * a.n_col_tiles);
-  const int rows_in_group = min(kGroupRows, a.n_row_tiles - group * kGroupRows);
-  const int idx = t - group * kGroupRows * a.n_col_tiles;
-  *rt = group * kGroupRows + idx % rows_in_group;
-  *ct = idx / rows_in_group;
+  tile_of_index(a, t, rt, ct);
 }
 
 // AS for a batch of subsample sketches: operand tiles move from global memory straight into
@@ -302,13 +309,19 @@ __global__ __launch_bounds__(WAVES * 64, 1) void k_as_dense_bf16_split(GemmArgs 
   constexpr int BM = 32 * WAVES;
   extern __shared__ __align__(16) unsigned char dsm[];
   if (*a.done) return;
+  // XCD x (= blockIdx.x % 8) takes a run of consecutive (split, tile) pairs in split-major
+  // order: its workgroups share one K range and the strips of a compact block of tiles, so
+  // each XCD's L2 fetches every operand strip it needs once (a K range's tiles spread over
+  // all XCDs would have each XCD fetch every strip of that range for a few tiles)
   const int ntiles = a.n_row_tiles * a.n_col_tiles;
-  const int span = (ntiles + kXcds - 1) / kXcds * kXcds;
-  const int sp = blockIdx.x / span;
-  int rt, ct;
-  tile_of_block(a, blockIdx.x % span, &rt, &ct);
-  if (rt < 0) return;
   const int64_t nk = a.kpad / kDmaBK;
+  const int nsplit = (int)((nk + stages_per_split - 1) / stages_per_split);
+  const int total = ntiles * nsplit, per = (total + kXcds - 1) / kXcds;
+  const int pair = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+  if (pair >= total) return;
+  const int sp = pair / ntiles;
+  int rt, ct;
+  tile_of_index(a, pair % ntiles, &rt, &ct);
   const int64_t k0 = (int64_t)sp * stages_per_split, k1 = min(nk, k0 + stages_per_split);  // k1 > k0 (host)
   const int64_t row0 = (int64_t)rt * BM, n0 = (int64_t)ct * kBN;
   f32x16 acc[2][4];
@@ -650,7 +663,8 @@ hipError_t launch_as_dense_bf16(const uint16_t* Zbf, int64_t ldz, int64_t m, int
     auto kern = k_as_dense_bf16_split<kGemmWaves>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(per * kXcds * split), dim3(kGemmWaves * 64), bytes, s, a, q, ws);
+    const int64_t per_x = ((int64_t)ntiles * split + kXcds - 1) / kXcds;
+    hipLaunchKernelGGL(kern, dim3((unsigned)(per_x * kXcds)), dim3(kGemmWaves * 64), bytes, s, a, q, ws);
     const int64_t total = a.ntot * m;
     const unsigned g = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
     hipLaunchKernelGGL(k_splitk_reduce, dim3(g), dim3(256), 0, s, a, split, ws);

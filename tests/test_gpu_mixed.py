@@ -60,10 +60,12 @@ def _bf16(a):
 
 
 @pytest.mark.parametrize("n,d,tau,form", [(700, 300, 37, "primal"), (300, 700, 41, "dual"),
-                                          (1200, 513, 64, "primal"), (8192, 300, 37, "primal")])
+                                          (1200, 513, 64, "primal"), (8192, 300, 37, "primal"),
+                                          (8192, 600, 37, "primal")])
 def test_mixed_products_within_bound(n, d, tau, form):
-    """The last case (m = 300, K = 8192: two 256 x 256 tiles per launch) runs the launch split over
-    K, two halves summed into a workspace and added in order."""
+    """The last two cases (m = 300 and 600, K = 8192: two and three 256 x 256 tiles per launch) run
+    the launch split over K into 4 ranges summed into a workspace and added in order; with three
+    tiles the 12 (range, tile) pairs leave workgroups of the 8-XCD layout idle."""
     p = inputs.make_dense(n, d, 0.1, seed=n + d, dtype=np.float32, col_log_sigma=1.0)
     S = rs.Solver(p.X, p.y, p.lam, tau=tau, sketch="subsample", form=form, tol=0.0, seed=5,
                   precision="mixed", lookahead=3)
