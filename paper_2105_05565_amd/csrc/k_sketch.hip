@@ -119,7 +119,11 @@ __device__ __forceinline__ void select_body(const SketchArgs& a, int slot, unsig
   }
   __syncthreads();
 
-  // Radix select: narrow the digit containing the want-th smallest key.
+  // Radix select: narrow the digit containing the want-th smallest key. With few coordinates
+  // another pass over the keys costs less than sorting a crowded digit (keys u_j / q_j of a
+  // weighted draw share a binary exponent in large groups), so the narrowing goes on until at
+  // most 64 candidates are left; with many, it stops at the sort's capacity.
+  const int sort_max = m <= 16 * kSelThreads ? 64 : kCandCap;
   int need = want;
   uint64_t prefix = 0;  // value of (key >> shift) shared by the candidates
   int shift = 52, width = 12;
@@ -130,7 +134,7 @@ __device__ __forceinline__ void select_body(const SketchArgs& a, int slot, unsig
     prefix = (prefix << width) | (uint64_t)bin;
     const int binc = H->hist[bin];
     __syncthreads();
-    if (binc <= kCandCap || shift == 0) break;
+    if (binc <= sort_max || shift == 0) break;
     const int nshift = shift >= 12 ? shift - 12 : 0;
     width = shift - nshift;
     for (int i = tid; i < kBins; i += kSelThreads) H->hist[i] = 0;
