@@ -8,8 +8,8 @@
 // per side, the factorisation, the inverse W = L^{-1} and the product G^{-1} = W^T W all
 // advance together, one block column per launch, in nt + 1 launches:
 //
-//   assemble (+ diag0)     G assembled (gathered rows of AS for the subsample sketch,
-//                          identity padding and empty buckets); tile (0, 0) factored in
+//   assemble (+ diag0)     G assembled on and below the diagonal (gathered rows of AS for
+//                          the subsample sketch, identity padding and empty buckets); tile (0, 0) factored in
 //                          LDS, X_0 = L_00^{-1} stored (by the assembly's workgroup of that
 //                          tile, or in a launch of its own when many sketches are assembled)
 //   step s = 1 .. nt, k = s - 1, one workgroup per item:
@@ -72,6 +72,18 @@ __device__ __forceinline__ double* tile(double* base, int64_t ld, int i, int j) 
   return base + (int64_t)i * NB * ld + (int64_t)j * NB;
 }
 
+// Linear index -> (i, j) with lo <= j <= i (row-major over i).
+__device__ __forceinline__ void lower_pair(int idx, int lo, int* i, int* j) {
+  int row = lo, width = 1;
+  while (idx >= width) {
+    idx -= width;
+    ++row;
+    ++width;
+  }
+  *i = row;
+  *j = lo + idx;
+}
+
 // X_s <- ta (64 x 64 from LDS), and its transpose into the diagonal tile U_ss (the form the
 // inverse by distance reads).
 __device__ __forceinline__ void store_x(double* X, double* Uss, int64_t ldg, const double* ta) {
@@ -84,13 +96,16 @@ __device__ __forceinline__ void store_x(double* X, double* Uss, int64_t ldg, con
 
 // FACTOR0: the workgroup of tile (0, 0) also factors it (dynamic LDS: two tiles for every
 // workgroup, so only with few sketches); otherwise k_chol_diag0 does, in a launch of its own.
+// Only the tiles on and below the diagonal (grid: nt (nt + 1) / 2 x 1 x slots): the steps read
+// G below the diagonal and write G^{-1} over both triangles at the end.
 template <bool FACTOR0>
 __global__ __launch_bounds__(kThreads) void k_chol_assemble(MultiArgs a) {
   extern __shared__ __align__(16) double lds[];
   __shared__ int bad;
   if (*a.done) return;
   const int64_t slot = blockIdx.z;
-  const int ti = blockIdx.y, tj = blockIdx.x;
+  int ti, tj;
+  lower_pair(blockIdx.x, 0, &ti, &tj);
   const bool first = FACTOR0 && ti == 0 && tj == 0;
   double* G = a.G + slot * a.ldg * a.ldg;
   const int32_t* offs = a.offs + slot * (a.tau + 1);
@@ -142,18 +157,6 @@ __global__ __launch_bounds__(kThreads) void k_chol_diag0(MultiArgs a) {
   factor_diag_tile(lds, lds + NB * LDT, &bad);
   store_x(a.X + slot * a.nt * NB * NB, a.U + slot * a.ldg * a.ldg, a.ldg, lds + NB * LDT);
   if (threadIdx.x == 0) a.status[slot] = bad;
-}
-
-// Linear index -> (i, j) with lo <= j <= i (row-major over i).
-__device__ __forceinline__ void lower_pair(int idx, int lo, int* i, int* j) {
-  int row = lo, width = 1;
-  while (idx >= width) {
-    idx -= width;
-    ++row;
-    ++width;
-  }
-  *i = row;
-  *j = lo + idx;
 }
 
 // Items of step s: F first (its item 0 is the diagonal tile (s, s), the longest), then I,
@@ -565,9 +568,9 @@ hipError_t launch_chol_multi_mode(double* G, double* U, double* X, int64_t ldg, 
     e = hipFuncSetAttribute((const void*)k_chol_ll_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)two);
   if (e != hipSuccess) return e;
   if (mode == 0) {
-    hipLaunchKernelGGL(k_chol_assemble<true>, dim3(nt, nt, nslots), dim3(kThreads), two, s, a);
+    hipLaunchKernelGGL(k_chol_assemble<true>, dim3(nt * (nt + 1) / 2, 1, nslots), dim3(kThreads), two, s, a);
   } else {
-    hipLaunchKernelGGL(k_chol_assemble<false>, dim3(nt, nt, nslots), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(k_chol_assemble<false>, dim3(nt * (nt + 1) / 2, 1, nslots), dim3(kThreads), 0, s, a);
     hipLaunchKernelGGL(k_chol_diag0, dim3(nslots), dim3(kThreads), two, s, a);
   }
   // grid of `items` work items per sketch in the layout item_of_block expects

@@ -142,57 +142,103 @@ __global__ __launch_bounds__(kThreads) void k_delta(const double* __restrict__ r
   const int row_end = min(tau, (int)(blockIdx.x + 1) * kDeltaRows);
   for (int c = blockIdx.x * kDeltaRows + wave; c < row_end; c += kThreads / 64) {
     const double* g = Ginv + (int64_t)c * ldg;
+    // eight columns of the row per lane in flight together (clamped loads, selected terms:
+    // the same terms in the same order as a column-by-column loop)
     double s = 0.0;
-    for (int cc = lane; cc < tau; cc += 64) s += g[cc] * rho[cc];
+    for (int c0 = lane; c0 < tau; c0 += 512) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = g[min(c0 + 64 * q, tau - 1)];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int cc = min(c0 + 64 * q, tau - 1);
+        const double t = fma(v[q], rho[cc], s);
+        s = c0 + 64 * q < tau ? t : s;
+      }
+    }
     s = wave_sum(s);
     if (lane == 0) delta[c] = s;
   }
 }
 
-// rows whose loads a wave issues before reducing any (FP64 rows: 2; FP32 rows: 1, within
-// the 64-VGPR budget of two workgroups per CU)
+// rows whose loads a wave issues before reducing any (FP64 rows: 2; FP32 rows: 1)
 template <typename ASV>
 struct RowsAtOnce {
   static constexpr int value = sizeof(ASV) == 8 ? 2 : 1;
 };
 
-// sum_c AS[j_u][c] dl[c] for R rows (j_u < 0: none, 0 returned), partial per
-// lane: the loads of all rows are issued before the first product.
+// sum_c AS[j_u][c] dl[c] for R rows (j_u < 0: none, 0 returned), partial per lane, c ascending.
+// A lane's chunks c0, c0 + 64, c0 + 128, c0 + 192 load together, unconditionally (past the row's
+// end its last chunk is read again, and a missing row reads row 0; neither enters the sum), so a
+// row costs one memory latency per four chunks instead of one per chunk.
 template <int R>
 __device__ __forceinline__ void rows_dot(const double* __restrict__ AS, const int64_t (&j)[R], int64_t ldas,
                                          const double* dl, int lane, double (&s)[R]) {
   const int half = (int)(ldas >> 1);
+  const double2* row[R];
 #pragma unroll
-  for (int u = 0; u < R; ++u) s[u] = 0.0;
-#pragma unroll 1
-  for (int c2 = lane; c2 < half; c2 += 64) {
-    double2 a[R];
-#pragma unroll
-    for (int u = 0; u < R; ++u)
-      a[u] = j[u] >= 0 ? reinterpret_cast<const double2*>(AS + j[u] * ldas)[c2] : make_double2(0.0, 0.0);
-    const double d0 = dl[2 * c2], d1 = dl[2 * c2 + 1];
-#pragma unroll
-    for (int u = 0; u < R; ++u) s[u] += a[u].x * d0 + a[u].y * d1;
+  for (int u = 0; u < R; ++u) {
+    s[u] = 0.0;
+    row[u] = reinterpret_cast<const double2*>(AS + (j[u] >= 0 ? j[u] : 0) * ldas);
   }
+  for (int c0 = lane; c0 < half; c0 += 256) {
+    double2 a[4][R];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = min(c0 + 64 * q, half - 1);
+#pragma unroll
+      for (int u = 0; u < R; ++u) a[q][u] = row[u][c];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c2 = min(c0 + 64 * q, half - 1);
+      const bool in = c0 + 64 * q < half;
+      const double d0 = dl[2 * c2], d1 = dl[2 * c2 + 1];
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const double t = a[q][u].x * d0 + a[q][u].y * d1;
+        s[u] += in ? t : 0.0;  // a select, not a branch: the loads stay ahead of every use
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < R; ++u)
+    if (j[u] < 0) s[u] = 0.0;
 }
 
 template <int R>
 __device__ __forceinline__ void rows_dot(const float* __restrict__ AS, const int64_t (&j)[R], int64_t ldas,
                                          const double* dl, int lane, double (&s)[R]) {
   const int quarter = (int)(ldas >> 2);
+  const float4* row[R];
 #pragma unroll
-  for (int u = 0; u < R; ++u) s[u] = 0.0;
-#pragma unroll 1
-  for (int c4 = lane; c4 < quarter; c4 += 64) {
-    float4 a[R];
-#pragma unroll
-    for (int u = 0; u < R; ++u)
-      a[u] = j[u] >= 0 ? reinterpret_cast<const float4*>(AS + j[u] * ldas)[c4] : make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-    for (int u = 0; u < R; ++u)
-      s[u] += (double)a[u].x * dl[4 * c4] + (double)a[u].y * dl[4 * c4 + 1] + (double)a[u].z * dl[4 * c4 + 2] +
-              (double)a[u].w * dl[4 * c4 + 3];
+  for (int u = 0; u < R; ++u) {
+    s[u] = 0.0;
+    row[u] = reinterpret_cast<const float4*>(AS + (j[u] >= 0 ? j[u] : 0) * ldas);
   }
+  for (int c0 = lane; c0 < quarter; c0 += 256) {
+    float4 a[4][R];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = min(c0 + 64 * q, quarter - 1);
+#pragma unroll
+      for (int u = 0; u < R; ++u) a[q][u] = row[u][c];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c4 = min(c0 + 64 * q, quarter - 1);
+      const bool in = c0 + 64 * q < quarter;
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const double t = (double)a[q][u].x * dl[4 * c4] + (double)a[q][u].y * dl[4 * c4 + 1] +
+                         (double)a[q][u].z * dl[4 * c4 + 2] + (double)a[q][u].w * dl[4 * c4 + 3];
+        s[u] += in ? t : 0.0;  // a select, not a branch: the loads stay ahead of every use
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < R; ++u)
+    if (j[u] < 0) s[u] = 0.0;
 }
 
 // Value of v in lane l (compile-time after unrolling), as a wave-uniform scalar.
@@ -312,9 +358,8 @@ struct UpdateArgs {
 };
 
 template <typename ASV, bool ACC>
-// 8 waves per SIMD (at most 64 VGPRs): two workgroups per CU, also beside the
-// batch-preparation kernels of the next lookahead batch
-__global__ __launch_bounds__(kUpdateThreads, 8) void k_update(UpdateArgs<ASV> a) {
+// at least 4 waves per SIMD (at most 128 VGPRs: the four chunks of a row's loads in flight)
+__global__ __launch_bounds__(kUpdateThreads, 4) void k_update(UpdateArgs<ASV> a) {
   constexpr int R = RowsAtOnce<ASV>::value;
   extern __shared__ __align__(16) double dl[];  // [ldas]
   __shared__ double scratch[16];
