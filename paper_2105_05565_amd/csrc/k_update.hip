@@ -142,15 +142,15 @@ __global__ __launch_bounds__(kThreads) void k_delta(const double* __restrict__ r
   const int row_end = min(tau, (int)(blockIdx.x + 1) * kDeltaRows);
   for (int c = blockIdx.x * kDeltaRows + wave; c < row_end; c += kThreads / 64) {
     const double* g = Ginv + (int64_t)c * ldg;
-    // eight columns of the row per lane in flight together (clamped loads, selected terms:
+    // four columns of the row per lane in flight together (clamped loads, selected terms:
     // the same terms in the same order as a column-by-column loop)
     double s = 0.0;
-    for (int c0 = lane; c0 < tau; c0 += 512) {
-      double v[8];
+    for (int c0 = lane; c0 < tau; c0 += 256) {
+      double v[4];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = g[min(c0 + 64 * q, tau - 1)];
+      for (int q = 0; q < 4; ++q) v[q] = g[min(c0 + 64 * q, tau - 1)];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
+      for (int q = 0; q < 4; ++q) {
         const int cc = min(c0 + 64 * q, tau - 1);
         const double t = fma(v[q], rho[cc], s);
         s = c0 + 64 * q < tau ? t : s;
