@@ -63,6 +63,9 @@ def _create(X, y, lam, **kw):
     (dict(tau=3, momentum=7), 1.0),
     (dict(tau=3, form=9), 1.0),
     (dict(tau=3, sketch=9), 1.0),
+    (dict(tau=3, profile=4), 1.0),           # profiling levels 0 .. 3
+    (dict(tau=3, profile=-1), 1.0),
+    (dict(tau=3, refresh_early=2), 1.0),     # 0 or 1
 ])
 def test_rejects_bad_arguments_without_device(kw, lam):
     X = np.ones((20, 8))
