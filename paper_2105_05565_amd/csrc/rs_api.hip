@@ -1084,8 +1084,8 @@ rs_status create_impl(const rs_matrix* X, const double* y, double lambda, double
     // Default lookahead: 256 sketches, fewer when one sketch's contraction is large (the
     // sketches formed past the stopping iteration are wasted work, and the first batch's
     // preparation is not overlapped). The formed-A route follows the same rule: its
-    // factorisations of 32 sketches run device-wide (C3 with A formed: 0.075 s at 32 against
-    // 0.108 s at 256).
+    // factorisations of 32 sketches run device-wide (the 50000 x 8192, tau = 1024 mixed solve
+    // with A formed: 0.075 s at 32 against 0.108 s at 256).
     int B = 256;
     if (!h->sparse && 2.0 * (double)h->m * (double)h->K * (double)h->tau > 1e11) B = 32;
     // the learned proposal is recomputed once per batch: short batches keep it fresh (the BF16
